@@ -1,0 +1,210 @@
+"""ctypes binding of the plain FP64 CPU oracle (test infrastructure only).
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package; the partitioning library never does.
+``build()`` compiles ``oracle.cpp`` with g++ into ``liboracle.so`` next to it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "oracle.cpp")
+
+GRAPH = {"weighted": 0, "unit": 1, "face": 2}
+METHOD = {"lanczos": 0, "inverse_cg": 1}
+
+
+class Opts(C.Structure):
+    _fields_ = [("graph", C.c_int32), ("method", C.c_int32), ("lanczos_m", C.c_int32),
+                ("max_restarts", C.c_int32), ("tol", C.c_double), ("inv_max_outer", C.c_int32),
+                ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
+                ("cg_full_projection", C.c_int32), ("seed", C.c_uint64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("matvecs", C.c_int64),
+                ("theta", C.c_double), ("residual", C.c_double), ("ncomp", C.c_int32),
+                ("cg_iters", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIB):
+        cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-o", LIB + ".tmp", SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        P = C.POINTER
+        L.orc_opts_default.argtypes = [P(Opts)]
+        L.orc_start_value.argtypes = [C.c_uint64, C.c_int64]
+        L.orc_start_value.restype = C.c_double
+        L.orc_dual_graph.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, P(C.c_int64)]
+        L.orc_laplacian_apply.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p]
+        L.orc_tridiag_smallest.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
+                                           P(C.c_double), C.c_void_p]
+        L.orc_fiedler.argtypes = [C.c_int64, C.c_int32, C.c_void_p, P(Opts), C.c_void_p,
+                                  P(C.c_double), P(Info)]
+        L.orc_fiedler_csr.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      P(Opts), C.c_void_p, P(C.c_double), P(Info)]
+        L.orc_split.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.orc_partition.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, P(Opts),
+                                    C.c_void_p, P(Info)]
+        L.orc_metrics.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                  C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def opts(**kw) -> Opts:
+    o = Opts()
+    lib().orc_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if k == "graph" and isinstance(v, str):
+            v = GRAPH[v]
+        if k == "method" and isinstance(v, str):
+            v = METHOD[v]
+        setattr(o, k, v)
+    return o
+
+
+def start_value(seed: int, gid: int) -> float:
+    return lib().orc_start_value(seed, gid)
+
+
+def _ids(ids) -> np.ndarray:
+    a = np.ascontiguousarray(ids, dtype=np.int64)
+    if a.ndim != 2:
+        raise ValueError("ids must be [nelem, nv]")
+    return a
+
+
+def dual_graph(ids, graph="weighted"):
+    """(row_ptr int64[n+1], col int32[nnz], weight int32[nnz])."""
+    a = _ids(ids)
+    n, nv = a.shape
+    g = GRAPH[graph] if isinstance(graph, str) else graph
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    nnz = C.c_int64(0)
+    rc = lib().orc_dual_graph(n, nv, _ptr(a), g, _ptr(row_ptr), None, None, C.byref(nnz))
+    if rc != 0:
+        raise RuntimeError(f"orc_dual_graph: {rc}")
+    col = np.zeros(max(nnz.value, 1), dtype=np.int32)
+    w = np.zeros(max(nnz.value, 1), dtype=np.int32)
+    rc = lib().orc_dual_graph(n, nv, _ptr(a), g, _ptr(row_ptr), _ptr(col), _ptr(w), C.byref(nnz))
+    if rc != 0:
+        raise RuntimeError(f"orc_dual_graph: {rc}")
+    return row_ptr, col[: nnz.value], w[: nnz.value]
+
+
+def laplacian_apply(row_ptr, col, w, x) -> np.ndarray:
+    n = len(row_ptr) - 1
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.zeros(n, dtype=np.float64)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    ww = np.ascontiguousarray(w, dtype=np.int32)
+    lib().orc_laplacian_apply(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(x), _ptr(y))
+    return y
+
+
+def tridiag_smallest(a, b, thr=0.0):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    k = len(a)
+    t = np.zeros(k, dtype=np.float64)
+    th = C.c_double(0)
+    rc = lib().orc_tridiag_smallest(k, _ptr(a), _ptr(b), thr, C.byref(th), _ptr(t))
+    if rc != 0:
+        raise RuntimeError(f"orc_tridiag_smallest: {rc}")
+    return th.value, t
+
+
+def fiedler(ids, **kw):
+    """(status, lambda2, y, info) for the whole mesh."""
+    a = _ids(ids)
+    n, nv = a.shape
+    o = opts(**kw)
+    y = np.zeros(n, dtype=np.float64)
+    lam = C.c_double(0)
+    info = Info()
+    rc = lib().orc_fiedler(n, nv, _ptr(a), C.byref(o), _ptr(y), C.byref(lam), C.byref(info))
+    if rc < 0:
+        raise RuntimeError(f"orc_fiedler: {rc}")
+    return rc, lam.value, y, info.as_dict()
+
+
+def fiedler_csr(row_ptr, col, w, gid=None, **kw):
+    n = len(row_ptr) - 1
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    ww = np.ascontiguousarray(w, dtype=np.int32)
+    g = np.arange(n, dtype=np.int64) if gid is None else np.ascontiguousarray(gid, dtype=np.int64)
+    o = opts(**kw)
+    y = np.zeros(n, dtype=np.float64)
+    lam = C.c_double(0)
+    info = Info()
+    rc = lib().orc_fiedler_csr(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(g), C.byref(o), _ptr(y),
+                               C.byref(lam), C.byref(info))
+    if rc < 0:
+        raise RuntimeError(f"orc_fiedler_csr: {rc}")
+    return rc, lam.value, y, info.as_dict()
+
+
+def split(y, gid, n_low) -> np.ndarray:
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    g = np.ascontiguousarray(gid, dtype=np.int64)
+    side = np.zeros(len(y), dtype=np.uint8)
+    rc = lib().orc_split(len(y), _ptr(y), _ptr(g), int(n_low), _ptr(side))
+    if rc != 0:
+        raise RuntimeError(f"orc_split: {rc}")
+    return side
+
+
+def partition(ids, nparts, **kw):
+    """(status, part int32[n], info)."""
+    a = _ids(ids)
+    n, nv = a.shape
+    o = opts(**kw)
+    part = np.zeros(n, dtype=np.int32)
+    info = Info()
+    rc = lib().orc_partition(n, nv, _ptr(a), int(nparts), C.byref(o), _ptr(part), C.byref(info))
+    if rc < 0:
+        raise RuntimeError(f"orc_partition: {rc}")
+    return rc, part, info.as_dict()
+
+
+def metrics(ids, part, nparts) -> dict:
+    a = _ids(ids)
+    n, nv = a.shape
+    p = np.ascontiguousarray(part, dtype=np.int32)
+    out = np.zeros(6, dtype=np.float64)
+    rc = lib().orc_metrics(n, nv, _ptr(a), int(nparts), _ptr(p), _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_metrics: {rc}")
+    return {"weighted_cut": out[0], "cut_pairs": out[1], "max_neighbors": out[2],
+            "avg_neighbors": out[3], "min_size": out[4], "max_size": out[5]}

@@ -1,0 +1,756 @@
+// oracle.cpp -- plain FP64 CPU reference for recursive spectral bisection.
+//
+// TEST INFRASTRUCTURE ONLY: the GPU library never includes, links or calls
+// this file.  It is deliberately simple (maps, explicit loops, one thread)
+// so that each function can be checked against the paper by eye.
+//
+// Readings where the paper is silent (each is also stated where it is used):
+//  * a vertex id repeated inside one element counts once (set semantics);
+//  * "face connected" means sharing at least nv/2 vertex ids;
+//  * the start vector is r_i = U[-1, 1) from splitmix64(seed, gid_i);
+//  * the ones vector u0 = 1/sqrt(n) is kept in the reorthogonalisation basis;
+//  * two classical Gram-Schmidt passes per Lanczos step;
+//  * convergence when ||L y - theta y||_2 <= tol * theta; explicit restart
+//    from the Ritz vector; at most max_restarts restarts;
+//  * canonical sign: the first element (in global-id order) whose |y| is at
+//    least 1e-3 max|y| gets y <= 0;
+//  * ties in the sort broken by global id, -0.0 before +0.0;
+//  * low side gets P_L = floor(P/2) parts and floor(n P_L / P) elements;
+//  * disconnected subgraphs: components ordered by smallest global id go
+//    whole to one side; only the component that straddles the target count
+//    is cut, by its own Fiedler vector.
+#include "oracle.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <set>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+typedef std::vector<double> Vec;
+
+// ---------------------------------------------------------------------------
+// Graph held as adjacency lists (sorted by neighbour index).
+// ---------------------------------------------------------------------------
+struct Graph {
+  int64_t n = 0;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> adj;  // (neighbour, weight)
+};
+
+// Edge weight from the number s of vertex ids two elements share
+// (Sec. 2: weight = shared vertices, 1/2/4 for hexes; Sec. 4 unweighted
+// Laplacian: unit weight; face graph: sharing at least half of the vertices).
+int weight_of(int32_t graph, int s, int nv) {
+  if (graph == ORC_GRAPH_WEIGHTED) return s;
+  if (graph == ORC_GRAPH_UNIT) return 1;
+  return (s >= nv / 2) ? 1 : 0;
+}
+
+// Dual graph (Sec. 2): vertex = element, edge = elements sharing a mesh vertex.
+// Built by a vertex -> elements map and per-element neighbour counting.
+Graph build_dual_graph(int64_t nelem, int nv, const int64_t *ids, int32_t graph) {
+  std::unordered_map<int64_t, std::vector<int32_t>> elems_of_vertex;
+  std::vector<std::vector<int64_t>> distinct(nelem);
+  for (int64_t e = 0; e < nelem; ++e) {
+    std::set<int64_t> s(ids + e * nv, ids + (e + 1) * nv);
+    distinct[e].assign(s.begin(), s.end());
+    for (int64_t v : distinct[e]) elems_of_vertex[v].push_back((int32_t)e);
+  }
+  Graph g;
+  g.n = nelem;
+  g.adj.resize(nelem);
+  for (int64_t e = 0; e < nelem; ++e) {
+    std::map<int32_t, int> shared;  // neighbour -> number of shared vertex ids
+    for (int64_t v : distinct[e])
+      for (int32_t j : elems_of_vertex[v])
+        if (j != e) shared[j] += 1;
+    for (auto &kv : shared) {
+      int w = weight_of(graph, kv.second, nv);
+      if (w > 0) g.adj[e].push_back({kv.first, w});
+    }
+  }
+  return g;
+}
+
+// y = L x with L = D - A (Sec. 4): l_ii = sum_j w_ij, l_ij = -w_ij.
+void apply_laplacian(const Graph &g, const Vec &x, Vec &y) {
+  for (int64_t i = 0; i < g.n; ++i) {
+    double d = 0.0, ax = 0.0;
+    for (auto &nw : g.adj[i]) {
+      d += nw.second;
+      ax += nw.second * x[nw.first];
+    }
+    y[i] = d * x[i] - ax;
+  }
+}
+
+double dot(const Vec &a, const Vec &b) {
+  double s = 0.0;
+  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+  return s;
+}
+
+double norm2(const Vec &a) { return std::sqrt(dot(a, a)); }
+
+// splitmix64 (Steele, Lea, Flood 2014): output for counter c of the stream
+// started at seed is mix(seed + c * golden_gamma).
+uint64_t splitmix64_at(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + counter * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+double start_value(uint64_t seed, int64_t gid) {
+  uint64_t z = splitmix64_at(seed, (uint64_t)gid + 1);
+  return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Smallest eigenpair of a symmetric tridiagonal matrix: Sturm-sequence
+// bisection for the eigenvalue, inverse iteration for the eigenvector.
+// ---------------------------------------------------------------------------
+
+// Number of eigenvalues of T strictly below x (signs of the pivots of the
+// LDL^T factorisation of T - x I).
+int sturm_count(int k, const double *a, const double *b, double x) {
+  int count = 0;
+  double q = 1.0;
+  for (int i = 0; i < k; ++i) {
+    double off = (i == 0) ? 0.0 : b[i] * b[i] / q;
+    q = (a[i] - x) - off;
+    if (q == 0.0) q = -1e-300;  // a zero pivot is taken as a tiny negative
+    if (q < 0.0) ++count;
+  }
+  return count;
+}
+
+// Solve (T - s I) z = r for tridiagonal T by Gaussian elimination with
+// partial pivoting (the system is nearly singular in inverse iteration).
+void tridiag_shifted_solve(int k, const double *a, const double *b, double s, Vec &z) {
+  // Row i of the band: [l_i, d_i, u_i, u2_i] after pivoting.
+  Vec d(k), u(k, 0.0), u2(k, 0.0), l(k, 0.0), rhs = z;
+  for (int i = 0; i < k; ++i) {
+    d[i] = a[i] - s;
+    if (i + 1 < k) u[i] = b[i + 1];
+    if (i > 0) l[i] = b[i];
+  }
+  // a zero pivot is replaced by a perturbation of the size of rounding
+  double scale = 0.0;
+  for (int i = 0; i < k; ++i) scale = std::max(scale, std::fabs(a[i]) + (i ? std::fabs(b[i]) : 0.0));
+  double tiny = std::max(scale, 1e-300) * 2.220446049250313e-16;
+  for (int i = 0; i + 1 < k; ++i) {
+    // candidate pivot rows i (d[i], u[i], u2[i]) and i+1 (l[i+1], d[i+1], u[i+1])
+    if (std::fabs(l[i + 1]) > std::fabs(d[i])) {
+      std::swap(d[i], l[i + 1]);
+      std::swap(u[i], d[i + 1]);
+      std::swap(u2[i], u[i + 1]);
+      std::swap(rhs[i], rhs[i + 1]);
+    }
+    if (d[i] == 0.0) d[i] = tiny;
+    double f = l[i + 1] / d[i];
+    d[i + 1] -= f * u[i];
+    u[i + 1] -= f * u2[i];
+    rhs[i + 1] -= f * rhs[i];
+    l[i + 1] = 0.0;
+  }
+  if (d[k - 1] == 0.0) d[k - 1] = tiny;
+  for (int i = k - 1; i >= 0; --i) {
+    double v = rhs[i];
+    if (i + 1 < k) v -= u[i] * rhs[i + 1];
+    if (i + 2 < k) v -= u2[i] * rhs[i + 2];
+    rhs[i] = v / d[i];
+  }
+  z = rhs;
+}
+
+int tridiag_smallest(int k, const double *a, const double *b, double thr, double *theta, Vec &t) {
+  if (k <= 0) return -1;
+  // Gershgorin interval
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < k; ++i) {
+    double r = 0.0;
+    if (i > 0) r += std::fabs(b[i]);
+    if (i + 1 < k) r += std::fabs(b[i + 1]);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  // Eigenvalues below thr are spurious null modes and skipped: target the
+  // (c0+1)-th smallest eigenvalue, c0 = count below thr.
+  int c0 = sturm_count(k, a, b, thr);
+  if (c0 >= k) return -1;
+  int target = c0 + 1;
+  lo = std::max(lo, thr);
+  hi = hi + 1e-12 * std::fabs(hi) + 1e-300;
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(k, a, b, mid) >= target) hi = mid; else lo = mid;
+  }
+  double th = 0.5 * (lo + hi);
+  *theta = th;
+  // inverse iteration from a fixed vector
+  t.assign(k, 1.0);
+  for (int it = 0; it < 4; ++it) {
+    tridiag_shifted_solve(k, a, b, th, t);
+    double big = 0.0;
+    for (double v : t) big = std::max(big, std::fabs(v));
+    for (double &v : t) v /= big;
+    double nrm = 0.0;
+    for (double v : t) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    for (double &v : t) v /= nrm;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Fiedler pair on a connected graph (one component), Sec. 6 and Sec. 7.
+// gid[i]: global id of local vertex i (start vector, sign rule).
+// ---------------------------------------------------------------------------
+
+// Remove the ones-vector component: x <- x - (u0^T x) u0 with u0 = 1/sqrt(n).
+void deflate_ones(Vec &x) {
+  double mean = 0.0;
+  for (double v : x) mean += v;
+  mean /= (double)x.size();
+  for (double &v : x) v -= mean;
+}
+
+void normalize(Vec &x) {
+  double nr = norm2(x);
+  for (double &v : x) v /= nr;
+}
+
+// Canonical sign: the first element in global-id order whose magnitude is at
+// least 1e-3 of the largest gets a non-positive value.
+void canonical_sign(Vec &y, const std::vector<int64_t> &gid) {
+  double ymax = 0.0;
+  for (double v : y) ymax = std::max(ymax, std::fabs(v));
+  int64_t best = -1;
+  for (size_t i = 0; i < y.size(); ++i)
+    if (std::fabs(y[i]) >= 1e-3 * ymax && (best < 0 || gid[i] < gid[best])) best = (int64_t)i;
+  if (best >= 0 && y[best] > 0.0)
+    for (double &v : y) v = -v;
+}
+
+double residual_norm(const Graph &g, const Vec &y, double theta, int64_t &matvecs) {
+  Vec ly(g.n);
+  apply_laplacian(g, y, ly);
+  ++matvecs;
+  double s = 0.0;
+  for (int64_t i = 0; i < g.n; ++i) s += (ly[i] - theta * y[i]) * (ly[i] - theta * y[i]);
+  return std::sqrt(s);
+}
+
+double rayleigh(const Graph &g, const Vec &y, int64_t &matvecs) {
+  Vec ly(g.n);
+  apply_laplacian(g, y, ly);
+  ++matvecs;
+  return dot(y, ly) / dot(y, y);
+}
+
+// Restarted Lanczos with full reorthogonalisation (Sec. 6).
+int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_opts &o, Vec &y,
+                    double &lambda, orc_info &info) {
+  const int64_t n = g.n;
+  const double u0 = 1.0 / std::sqrt((double)n);
+  Vec q(n);
+  for (int64_t i = 0; i < n; ++i) q[i] = start_value(o.seed, gid[i]);
+  deflate_ones(q);
+  normalize(q);
+  int m = std::max(1, o.lanczos_m);
+  int converged = 0;
+  double theta = 0.0, res = 0.0;
+  y = q;
+  for (int cycle = 0; cycle <= o.max_restarts; ++cycle) {
+    std::vector<Vec> Q;
+    Q.push_back(q);
+    std::vector<double> alpha, beta(1, 0.0);  // beta[j] couples Q[j-1] and Q[j]
+    Vec w(n);
+    double tnorm = 0.0;
+    for (int j = 0; j < m; ++j) {
+      apply_laplacian(g, Q[j], w);
+      ++info.matvecs;
+      double a = dot(Q[j], w);
+      for (int64_t i = 0; i < n; ++i) {
+        w[i] -= a * Q[j][i];
+        if (j > 0) w[i] -= beta[j] * Q[j - 1][i];
+      }
+      // two classical Gram-Schmidt passes against [u0, Q[0..j]]
+      for (int pass = 0; pass < 2; ++pass) {
+        double h0 = 0.0;
+        for (int64_t i = 0; i < n; ++i) h0 += u0 * w[i];
+        std::vector<double> h(j + 1);
+        for (int k = 0; k <= j; ++k) h[k] = dot(Q[k], w);
+        for (int64_t i = 0; i < n; ++i) {
+          double s = h0 * u0;
+          for (int k = 0; k <= j; ++k) s += h[k] * Q[k][i];
+          w[i] -= s;
+        }
+        a += h[j];
+      }
+      alpha.push_back(a);
+      double b = norm2(w);
+      tnorm = std::max(tnorm, std::fabs(a) + b + beta[j]);
+      if (j == m - 1 || b <= 1e-12 * tnorm) break;
+      beta.push_back(b);
+      Vec qn(n);
+      for (int64_t i = 0; i < n; ++i) qn[i] = w[i] / b;
+      Q.push_back(qn);
+    }
+    int k = (int)alpha.size();
+    Vec t;
+    if (tridiag_smallest(k, alpha.data(), beta.data(), 1e-10 * tnorm, &theta, t) != 0) return -5;
+    // Ritz vector y = Q t, re-projected against the ones vector and normalised
+    y.assign(n, 0.0);
+    for (int c = 0; c < k; ++c)
+      for (int64_t i = 0; i < n; ++i) y[i] += t[c] * Q[c][i];
+    deflate_ones(y);
+    normalize(y);
+    res = residual_norm(g, y, theta, info.matvecs);
+    info.cycles = cycle + 1;
+    if (res <= o.tol * theta) {
+      converged = 1;
+      break;
+    }
+    q = y;
+  }
+  info.theta = theta;
+  info.residual = res;
+  info.converged = converged;
+  lambda = rayleigh(g, y, info.matvecs);
+  canonical_sign(y, gid);
+  return converged ? 0 : 1;
+}
+
+// Conjugate gradients for L x = b with b orthogonal to the ones vector
+// (Sec. 7): x0 = 0, first direction r0 (not preconditioned), Polak-Ribiere
+// beta (identity preconditioner), optional L-orthogonalisation of every new
+// direction against the kept ones ("full projection").  Returns iterations.
+int cg_solve(const Graph &g, const Vec &b, const orc_opts &o, Vec &x, int64_t &matvecs) {
+  const int64_t n = g.n;
+  x.assign(n, 0.0);
+  Vec r = b, p = b, lp(n);
+  deflate_ones(r);
+  p = r;
+  double rr = dot(r, r);
+  double bnorm = norm2(b);
+  std::vector<Vec> P, LP;
+  std::vector<double> pLp;
+  int it = 0;
+  if (std::sqrt(rr) <= o.cg_tol * bnorm) return 0;
+  for (it = 1; it <= o.cg_max_iter; ++it) {
+    apply_laplacian(g, p, lp);
+    ++matvecs;
+    double plp = dot(p, lp);
+    double alpha = rr / plp;
+    Vec rn(n);
+    for (int64_t i = 0; i < n; ++i) {
+      x[i] += alpha * p[i];
+      rn[i] = r[i] - alpha * lp[i];
+    }
+    deflate_ones(rn);
+    double rrn = dot(rn, rn);
+    if (std::sqrt(rrn) <= o.cg_tol * bnorm) break;
+    double diff = 0.0;
+    for (int64_t i = 0; i < n; ++i) diff += rn[i] * (rn[i] - r[i]);
+    double beta = diff / rr;
+    if (o.cg_full_projection > 0) {
+      P.push_back(p);
+      LP.push_back(lp);
+      pLp.push_back(plp);
+      if ((int)P.size() > o.cg_full_projection) {
+        P.erase(P.begin());
+        LP.erase(LP.begin());
+        pLp.erase(pLp.begin());
+      }
+    }
+    for (int64_t i = 0; i < n; ++i) p[i] = rn[i] + beta * p[i];
+    for (size_t k = 0; k < P.size(); ++k) {
+      double c = dot(LP[k], p) / pLp[k];
+      for (int64_t i = 0; i < n; ++i) p[i] -= c * P[k][i];
+    }
+    r = rn;
+    rr = rrn;
+  }
+  return std::min(it, o.cg_max_iter);
+}
+
+// Inverse iteration (Sec. 7, Alg. 2).
+int inverse_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_opts &o, Vec &y,
+                    double &lambda, orc_info &info) {
+  const int64_t n = g.n;
+  Vec b(n), x;
+  for (int64_t i = 0; i < n; ++i) b[i] = start_value(o.seed, gid[i]);
+  int converged = 0;
+  double rho = 0.0, res = 0.0;
+  for (int outer = 0; outer < o.inv_max_outer; ++outer) {
+    deflate_ones(b);
+    normalize(b);
+    int its = cg_solve(g, b, o, x, info.matvecs);
+    info.cg_iters += its;
+    b = x;
+    info.cycles = outer + 1;
+    // eigen-residual of the new iterate
+    Vec yy = b;
+    deflate_ones(yy);
+    normalize(yy);
+    rho = rayleigh(g, yy, info.matvecs);
+    res = residual_norm(g, yy, rho, info.matvecs);
+    if (its <= 1 || res <= o.tol * rho) {
+      converged = 1;
+      break;
+    }
+  }
+  deflate_ones(b);
+  normalize(b);
+  y = b;
+  info.theta = rho;
+  info.residual = res;
+  info.converged = converged;
+  lambda = rayleigh(g, y, info.matvecs);
+  canonical_sign(y, gid);
+  return converged ? 0 : 1;
+}
+
+// ---------------------------------------------------------------------------
+// Components, split rule, recursion (Sec. 4, Alg. 1)
+// ---------------------------------------------------------------------------
+
+// Component of every vertex, numbered in order of each component's smallest
+// global id.
+int components(const Graph &g, const std::vector<int64_t> &gid, std::vector<int32_t> &comp) {
+  comp.assign(g.n, -1);
+  int nc = 0;
+  std::vector<int32_t> stack;
+  for (int64_t s = 0; s < g.n; ++s) {
+    if (comp[s] >= 0) continue;
+    comp[s] = nc;
+    stack.push_back((int32_t)s);
+    while (!stack.empty()) {
+      int32_t u = stack.back();
+      stack.pop_back();
+      for (auto &nw : g.adj[u])
+        if (comp[nw.first] < 0) {
+          comp[nw.first] = nc;
+          stack.push_back(nw.first);
+        }
+    }
+    ++nc;
+  }
+  std::vector<int64_t> mingid(nc, INT64_MAX);
+  for (int64_t i = 0; i < g.n; ++i) mingid[comp[i]] = std::min(mingid[comp[i]], gid[i]);
+  std::vector<int32_t> order(nc), rank(nc);
+  for (int c = 0; c < nc; ++c) order[c] = c;
+  std::sort(order.begin(), order.end(),
+            [&](int32_t a, int32_t b) { return mingid[a] < mingid[b]; });
+  for (int c = 0; c < nc; ++c) rank[order[c]] = c;
+  for (auto &c : comp) c = rank[c];
+  return nc;
+}
+
+// Induced subgraph on the sorted local index list `keep`.
+Graph induced(const Graph &g, const std::vector<int64_t> &keep) {
+  std::unordered_map<int64_t, int32_t> local;
+  for (size_t i = 0; i < keep.size(); ++i) local[keep[i]] = (int32_t)i;
+  Graph s;
+  s.n = (int64_t)keep.size();
+  s.adj.resize(s.n);
+  for (size_t i = 0; i < keep.size(); ++i)
+    for (auto &nw : g.adj[keep[i]]) {
+      auto it = local.find(nw.first);
+      if (it != local.end()) s.adj[i].push_back({it->second, nw.second});
+    }
+  for (auto &a : s.adj) std::sort(a.begin(), a.end());
+  return s;
+}
+
+// Total order on doubles used for the split key: -0.0 before +0.0.
+uint64_t ordered_bits(double v) {
+  uint64_t u;
+  std::memcpy(&u, &v, 8);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ULL);
+}
+
+struct KeyLess {
+  const Vec &y;
+  const std::vector<int64_t> &gid;
+  bool operator()(int64_t a, int64_t b) const {
+    uint64_t ka = ordered_bits(y[a]), kb = ordered_bits(y[b]);
+    if (ka != kb) return ka < kb;
+    return gid[a] < gid[b];
+  }
+};
+
+// side[i] = 0 for the n_low smallest keys (y_i, gid_i).
+void split_by_keys(const Vec &y, const std::vector<int64_t> &gid, int64_t n_low,
+                   std::vector<uint8_t> &side) {
+  std::vector<int64_t> order(y.size());
+  for (size_t i = 0; i < y.size(); ++i) order[i] = (int64_t)i;
+  std::sort(order.begin(), order.end(), KeyLess{y, gid});
+  side.assign(y.size(), 1);
+  for (int64_t r = 0; r < n_low; ++r) side[order[r]] = 0;
+}
+
+struct SolveResult {
+  int status = 0;         // 0 ok, 1 not converged, 2 disconnected
+  double lambda = 0.0;
+};
+
+// One bisection of graph g (vertices in ascending gid order) into a low side
+// of n_low vertices and a high side.  y receives the vector used (zero
+// outside the component that was cut).  Returns the status of the solve.
+int bisect(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const orc_opts &o,
+           std::vector<uint8_t> &side, Vec &y, double &lambda, orc_info &info) {
+  std::vector<int32_t> comp;
+  int nc = components(g, gid, comp);
+  info.ncomp = nc;
+  std::vector<int64_t> size(nc, 0);
+  for (int32_t c : comp) size[c] += 1;
+  // components are numbered in order of their smallest global id
+  int64_t before = 0;
+  int strad = -1;
+  int64_t strad_before = 0;
+  for (int c = 0; c < nc; ++c) {
+    if (before < n_low && n_low < before + size[c]) {
+      strad = c;
+      strad_before = before;
+    }
+    before += size[c];
+  }
+  side.assign(g.n, 1);
+  y.assign(g.n, 0.0);
+  lambda = 0.0;
+  std::vector<int64_t> prefix(nc, 0);
+  for (int c = 1; c < nc; ++c) prefix[c] = prefix[c - 1] + size[c - 1];
+  for (int64_t i = 0; i < g.n; ++i) {
+    int c = comp[i];
+    if (prefix[c] + size[c] <= n_low) side[i] = 0;
+  }
+  int status = (nc > 1) ? 2 : 0;
+  if (strad < 0) return status;
+  std::vector<int64_t> members;
+  for (int64_t i = 0; i < g.n; ++i)
+    if (comp[i] == strad) members.push_back(i);
+  Graph sub = (nc > 1) ? induced(g, members) : g;
+  std::vector<int64_t> sub_gid(members.size());
+  for (size_t i = 0; i < members.size(); ++i) sub_gid[i] = gid[members[i]];
+  Vec ys;
+  int st;
+  if (o.method == ORC_INVERSE_CG)
+    st = inverse_fiedler(sub, sub_gid, o, ys, lambda, info);
+  else
+    st = lanczos_fiedler(sub, sub_gid, o, ys, lambda, info);
+  if (st < 0) return st;
+  std::vector<uint8_t> sub_side;
+  split_by_keys(ys, sub_gid, n_low - strad_before, sub_side);
+  for (size_t i = 0; i < members.size(); ++i) {
+    side[members[i]] = sub_side[i];
+    y[members[i]] = ys[i];
+  }
+  if (status == 0 && st == 1) status = 1;
+  return status;
+}
+
+void to_graph(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+              Graph &g) {
+  g.n = n;
+  g.adj.assign(n, {});
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) g.adj[i].push_back({col[p], weight[p]});
+}
+
+bool valid_mesh(int64_t nelem, int32_t nv, const int64_t *ids) {
+  if (nelem < 1 || nv < 1 || !ids) return false;
+  for (int64_t i = 0; i < nelem * nv; ++i)
+    if (ids[i] < 0) return false;
+  return true;
+}
+
+// Recursion of Alg. 1 on the vertex list `elems` (ascending global ids),
+// parts [p0, p0 + np).
+int rsb_recurse(const Graph &g, const std::vector<int64_t> &elems, int32_t p0, int32_t np,
+                const orc_opts &o, int32_t *part, orc_info &info, int &worst) {
+  if (np == 1) {
+    for (int64_t e : elems) part[e] = p0;
+    return 0;
+  }
+  Graph sub = induced(g, elems);
+  int32_t pl = np / 2;
+  int64_t n_low = (int64_t)((__int128)elems.size() * pl / np);
+  std::vector<uint8_t> side;
+  Vec y;
+  double lam;
+  orc_info li{};
+  int st = bisect(sub, elems, n_low, o, side, y, lam, li);
+  if (st < 0) return st;
+  worst = std::max(worst, st);
+  info.matvecs += li.matvecs;
+  info.cycles += li.cycles;
+  info.cg_iters += li.cg_iters;
+  std::vector<int64_t> lo, hi;
+  for (size_t i = 0; i < elems.size(); ++i) (side[i] ? hi : lo).push_back(elems[i]);
+  int r = rsb_recurse(g, lo, p0, pl, o, part, info, worst);
+  if (r < 0) return r;
+  return rsb_recurse(g, hi, p0 + pl, np - pl, o, part, info, worst);
+}
+
+}  // namespace
+
+extern "C" {
+
+void orc_opts_default(orc_opts *o) {
+  o->graph = ORC_GRAPH_WEIGHTED;
+  o->method = ORC_LANCZOS;
+  o->lanczos_m = 100;
+  o->max_restarts = 50;
+  o->tol = 1e-6;
+  o->inv_max_outer = 50;
+  o->cg_max_iter = 20000;
+  o->cg_tol = 1e-8;
+  o->cg_full_projection = 0;
+  o->seed = 20261203ULL;
+}
+
+double orc_start_value(uint64_t seed, int64_t gid) { return start_value(seed, gid); }
+
+int orc_dual_graph(int64_t nelem, int32_t nv, const int64_t *ids, int32_t graph, int64_t *row_ptr,
+                   int32_t *col, int32_t *weight, int64_t *nnz_inout) {
+  if (!valid_mesh(nelem, nv, ids) || !row_ptr || !nnz_inout) return -1;
+  Graph g = build_dual_graph(nelem, nv, ids, graph);
+  row_ptr[0] = 0;
+  for (int64_t i = 0; i < nelem; ++i) row_ptr[i + 1] = row_ptr[i] + (int64_t)g.adj[i].size();
+  int64_t nnz = row_ptr[nelem];
+  if (!col) {
+    *nnz_inout = nnz;
+    return 0;
+  }
+  if (*nnz_inout < nnz) {
+    *nnz_inout = nnz;
+    return -4;
+  }
+  for (int64_t i = 0; i < nelem; ++i)
+    for (size_t p = 0; p < g.adj[i].size(); ++p) {
+      col[row_ptr[i] + p] = g.adj[i][p].first;
+      if (weight) weight[row_ptr[i] + p] = g.adj[i][p].second;
+    }
+  *nnz_inout = nnz;
+  return 0;
+}
+
+void orc_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                         const int32_t *weight, const double *x, double *y) {
+  Graph g;
+  to_graph(n, row_ptr, col, weight, g);
+  Vec xv(x, x + n), yv(n);
+  apply_laplacian(g, xv, yv);
+  std::copy(yv.begin(), yv.end(), y);
+}
+
+int orc_tridiag_smallest(int32_t k, const double *a, const double *b, double spurious_thr,
+                         double *theta, double *t) {
+  Vec tv;
+  int r = tridiag_smallest(k, a, b, spurious_thr, theta, tv);
+  if (r == 0) std::copy(tv.begin(), tv.end(), t);
+  return r;
+}
+
+int orc_fiedler_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                    const int64_t *gid, const orc_opts *o, double *y, double *lambda,
+                    orc_info *info) {
+  if (n < 2 || !row_ptr || !col || !weight || !gid || !o || !y || !lambda) return -1;
+  Graph g;
+  to_graph(n, row_ptr, col, weight, g);
+  std::vector<int64_t> gv(gid, gid + n);
+  std::vector<uint8_t> side;
+  Vec yv;
+  orc_info li{};
+  int st = bisect(g, gv, n / 2, *o, side, yv, *lambda, li);
+  if (info) *info = li;
+  if (st < 0) return st;
+  std::copy(yv.begin(), yv.end(), y);
+  return st;
+}
+
+int orc_fiedler(int64_t nelem, int32_t nv, const int64_t *ids, const orc_opts *o, double *y,
+                double *lambda, orc_info *info) {
+  if (!valid_mesh(nelem, nv, ids) || nelem < 2 || !o || !y || !lambda) return -1;
+  Graph g = build_dual_graph(nelem, nv, ids, o->graph);
+  std::vector<int64_t> gv(nelem);
+  for (int64_t i = 0; i < nelem; ++i) gv[i] = i;
+  std::vector<uint8_t> side;
+  Vec yv;
+  orc_info li{};
+  int st = bisect(g, gv, nelem / 2, *o, side, yv, *lambda, li);
+  if (info) *info = li;
+  if (st < 0) return st;
+  std::copy(yv.begin(), yv.end(), y);
+  return st;
+}
+
+int orc_split(int64_t n, const double *y, const int64_t *gid, int64_t n_low, uint8_t *side) {
+  if (n < 0 || n_low < 0 || n_low > n || (n > 0 && (!y || !gid || !side))) return -1;
+  for (int64_t i = 0; i < n; ++i)
+    if (std::isnan(y[i])) return -1;
+  Vec yv(y, y + n);
+  std::vector<int64_t> gv(gid, gid + n);
+  std::vector<uint8_t> s;
+  split_by_keys(yv, gv, n_low, s);
+  std::copy(s.begin(), s.end(), side);
+  return 0;
+}
+
+int orc_partition(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts, const orc_opts *o,
+                  int32_t *part, orc_info *info) {
+  if (!valid_mesh(nelem, nv, ids) || nparts < 1 || nparts > nelem || !o || !part) return -1;
+  Graph g = build_dual_graph(nelem, nv, ids, o->graph);
+  std::vector<int64_t> all(nelem);
+  for (int64_t i = 0; i < nelem; ++i) all[i] = i;
+  orc_info li{};
+  int worst = 0;
+  int r = rsb_recurse(g, all, 0, nparts, *o, part, li, worst);
+  if (info) *info = li;
+  if (r < 0) return r;
+  return worst;
+}
+
+int orc_metrics(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts, const int32_t *part,
+                double *out) {
+  if (!valid_mesh(nelem, nv, ids) || nparts < 1 || !part || !out) return -1;
+  Graph g = build_dual_graph(nelem, nv, ids, ORC_GRAPH_WEIGHTED);
+  double wcut = 0.0, pairs = 0.0;
+  std::vector<std::set<int32_t>> nbr(nparts);
+  std::vector<int64_t> sizes(nparts, 0);
+  for (int64_t i = 0; i < nelem; ++i) {
+    if (part[i] < 0 || part[i] >= nparts) return -1;
+    sizes[part[i]] += 1;
+    for (auto &nw : g.adj[i])
+      if (part[nw.first] != part[i]) {
+        nbr[part[i]].insert(part[nw.first]);
+        if (nw.first > i) {
+          wcut += nw.second;
+          pairs += 1.0;
+        }
+      }
+  }
+  double mx = 0.0, sum = 0.0;
+  for (auto &s : nbr) {
+    mx = std::max(mx, (double)s.size());
+    sum += (double)s.size();
+  }
+  out[0] = wcut;
+  out[1] = pairs;
+  out[2] = mx;
+  out[3] = sum / nparts;
+  out[4] = (double)*std::min_element(sizes.begin(), sizes.end());
+  out[5] = (double)*std::max_element(sizes.begin(), sizes.end());
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+/*
+ * oracle.h -- plain FP64 CPU reference for recursive spectral bisection.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the partitioning library links,
+ * includes or calls this code; only the test-suite, the smoke check and the
+ * CPU baseline of the benchmark load it.  It shares no source with the GPU
+ * library.
+ *
+ * What it computes (paper sections in brackets):
+ *   - the element dual graph and its Laplacian [Sec. 2, Sec. 4 eqs. for the
+ *     unweighted and weighted Laplacian, Sec. 5 A_w = P^T Q Q^T P];
+ *   - the Fiedler pair by restarted Lanczos with full reorthogonalisation
+ *     [Sec. 6] or by inverse iteration with conjugate gradients [Sec. 7,
+ *     Alg. 2];
+ *   - the median split and the recursion into floor(P/2) / ceil(P/2) parts
+ *     [Sec. 4, Alg. 1].
+ *
+ * All arithmetic is IEEE double, round to nearest, single-threaded.
+ */
+#ifndef RSB_ORACLE_H
+#define RSB_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_GRAPH_WEIGHTED = 0, ORC_GRAPH_UNIT = 1, ORC_GRAPH_FACE = 2 };
+enum { ORC_LANCZOS = 0, ORC_INVERSE_CG = 1 };
+
+typedef struct orc_opts {
+  int32_t graph;             /* ORC_GRAPH_* */
+  int32_t method;            /* ORC_LANCZOS or ORC_INVERSE_CG */
+  int32_t lanczos_m;         /* Lanczos steps per cycle */
+  int32_t max_restarts;      /* cycles after the first one */
+  double tol;                /* stop when ||L y - theta y|| <= tol * theta */
+  int32_t inv_max_outer;     /* inverse iteration: outer cap */
+  int32_t cg_max_iter;       /* CG iteration cap per solve */
+  double cg_tol;             /* CG: ||r|| <= cg_tol * ||b|| */
+  int32_t cg_full_projection;/* 0: plain CG; k>0: L-orthogonalise each new
+                                direction against up to k kept directions */
+  uint64_t seed;             /* start-vector seed */
+} orc_opts;
+
+typedef struct orc_info {
+  int32_t cycles;      /* Lanczos cycles (or inverse-iteration outer steps) */
+  int32_t converged;   /* 1 if the tolerance was met */
+  int64_t matvecs;     /* Laplacian applications */
+  double theta;        /* last Ritz value (Lanczos) */
+  double residual;     /* ||L y - theta y|| of the returned vector */
+  int32_t ncomp;       /* connected components of the graph solved on */
+  int32_t cg_iters;    /* inverse iteration: CG steps summed over solves */
+} orc_info;
+
+void orc_opts_default(orc_opts *o);
+
+/* Start-vector entry for a global element id: uniform in [-1, 1) from the
+ * splitmix64 output for counter gid+1 of the stream started at seed. */
+double orc_start_value(uint64_t seed, int64_t gid);
+
+/* Dual graph: off-diagonal CSR, columns ascending.  Two-call protocol: with
+ * col == NULL only *nnz_inout is written.  Returns 0, or -1 on bad input,
+ * -4 if *nnz_inout is too small. */
+int orc_dual_graph(int64_t nelem, int32_t nv, const int64_t *ids, int32_t graph,
+                   int64_t *row_ptr, int32_t *col, int32_t *weight, int64_t *nnz_inout);
+
+/* y = L x with L = D - A from the CSR above. */
+void orc_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                         const int32_t *weight, const double *x, double *y);
+
+/* Smallest eigenpair of the symmetric tridiagonal matrix with diagonal
+ * a[0..k-1] and off-diagonal b[1..k-1] (b[0] ignored), skipping eigenvalues
+ * below spurious_thr.  Returns 0 on success. */
+int orc_tridiag_smallest(int32_t k, const double *a, const double *b, double spurious_thr,
+                         double *theta, double *t);
+
+/* Fiedler pair of the mesh's dual-graph Laplacian.  Returns 0, 2 if the graph
+ * is disconnected (then y is the Fiedler vector of the component straddling
+ * the median, zero elsewhere), 1 if the iteration did not converge, <0 on
+ * error.  y has unit norm and canonical sign. */
+int orc_fiedler(int64_t nelem, int32_t nv, const int64_t *ids, const orc_opts *o,
+                double *y, double *lambda, orc_info *info);
+
+/* Same on an explicit CSR graph (columns ascending, no diagonal), with
+ * global ids gid[i] used for the start vector and tie-breaks. */
+int orc_fiedler_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                    const int64_t *gid, const orc_opts *o, double *y, double *lambda,
+                    orc_info *info);
+
+/* The split rule on a given vector: side[i] = 0 for the n_low smallest keys
+ * (y_i, gid_i), 1 otherwise. */
+int orc_split(int64_t n, const double *y, const int64_t *gid, int64_t n_low, uint8_t *side);
+
+/* Recursive spectral bisection into nparts parts; part[i] in [0, nparts). */
+int orc_partition(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts,
+                  const orc_opts *o, int32_t *part, orc_info *info);
+
+/* Quality metrics of a partition on the weighted vertex-shared dual graph:
+ * out[0] weighted cut (sum of shared-vertex counts across parts),
+ * out[1] number of cut element pairs, out[2] max neighbour parts,
+ * out[3] mean neighbour parts, out[4] min part size, out[5] max part size. */
+int orc_metrics(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts,
+                const int32_t *part, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

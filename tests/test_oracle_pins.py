@@ -1,0 +1,405 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: values the
+paper prints, closed forms for box meshes, a dense eigen-decomposition
+(library routine) on small graphs, brute-force products, or invariants the
+paper states.  All CPU-only.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def dense_laplacian(rp, col, w):
+    n = len(rp) - 1
+    L = np.zeros((n, n))
+    for i in range(n):
+        for p in range(rp[i], rp[i + 1]):
+            L[i, col[p]] -= w[p]
+            L[i, i] += w[p]
+    return L
+
+
+def gs_adjacency(ids):
+    """A_w = P^T Q Q^T P built from explicit copy matrices (Sec. 5)."""
+    ids = np.asarray(ids)
+    m, v = ids.shape
+    mL = m * v
+    uniq = np.unique(ids)
+    mu = len(uniq)
+    P = np.zeros((mL, m))          # element value copied to its v local vertices
+    for e in range(m):
+        P[e * v:(e + 1) * v, e] = 1.0
+    Q = np.zeros((mL, mu))         # local vertex <- global vertex (one nonzero per row)
+    Q[np.arange(mL), np.searchsorted(uniq, ids.ravel())] = 1.0
+    return P.T @ Q @ Q.T @ P
+
+
+def small_meshes():
+    out = []
+    out.append(("box5x4x3", mg.box_hex(5, 4, 3)))
+    out.append(("box6x5x4-holes", mg.uniform_holes(mg.box_hex(6, 5, 4), 0.15, 7)))
+    out.append(("quad12x9-holes", mg.uniform_holes(mg.box_quad(12, 9), 0.1, 3)))
+    m = mg.uniform_holes(mg.box_hex(7, 6, 5), 0.1, 11)
+    out.append(("box7x6x5-renum-shuffle", mg.shuffle_elements(mg.renumber_vertices(m, 5), 9)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The paper's worked example (Sec. 5)
+# ---------------------------------------------------------------------------
+
+def test_paper_example_weights_and_product(orc):
+    g = load("paper_gs_example.json")
+    ids = np.array(g["elements"])
+    rp, col, w = orc.dual_graph(ids)
+    A = np.zeros((3, 3))
+    for i in range(3):
+        for p in range(rp[i], rp[i + 1]):
+            A[i, col[p]] = w[p]
+    assert A[0, 1] == g["derived"]["weights"]["1-2"]
+    assert A[0, 2] == g["derived"]["weights"]["1-3"]
+    assert A[1, 2] == g["derived"]["weights"]["2-3"]
+    # z = A_w x with x1 = 1, x2 = x3 = 0 gives z2 = 2 (printed in Sec. 5)
+    z = A @ np.array(g["printed"]["x"], dtype=float)
+    assert z[1] == g["printed"]["z2"]
+    # L x = D x - A x; the singleton vertex 1 leaves L untouched: removing it
+    # from element 1 (replacing it by another private vertex) changes nothing
+    L = dense_laplacian(rp, col, w)
+    assert np.array_equal(L, np.array(g["derived"]["laplacian"], dtype=float))
+    ids2 = ids.copy()
+    ids2[0, 0] = 99
+    rp2, col2, w2 = orc.dual_graph(ids2)
+    assert np.array_equal(dense_laplacian(rp2, col2, w2), L)
+    y = orc.laplacian_apply(rp, col, w, [1.0, 0.0, 0.0])
+    assert np.allclose(y, L @ np.array([1.0, 0.0, 0.0]))
+    # the rank-0 global-id list of the gs_setup example is elements 1 and 2
+    assert list(ids[:2].ravel()) == g["printed"]["rank0_global_id"]
+    assert list(ids[2].ravel()) == g["printed"]["rank1_global_id"]
+
+
+def test_paper_example_fiedler(orc):
+    g = load("paper_gs_example.json")
+    ids = np.array(g["elements"])
+    st, lam, y, info = orc.fiedler(ids, lanczos_m=10, tol=1e-12)
+    assert st == 0
+    assert abs(lam - 4.0) < 1e-12
+    ref = np.array(g["derived"]["fiedler_vector_up_to_sign"])
+    assert min(np.abs(y - ref).max(), np.abs(y + ref).max()) < 1e-12
+    ev = np.linalg.eigvalsh(np.array(g["derived"]["laplacian"], dtype=float))
+    assert np.allclose(ev, g["derived"]["eigenvalues"], atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Dual graph
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,mesh", small_meshes())
+def test_dual_graph_matches_gather_scatter_product(orc, name, mesh):
+    rp, col, w = orc.dual_graph(mesh.ids)
+    n = mesh.nelem
+    A = np.zeros((n, n))
+    for i in range(n):
+        cols = col[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(cols) > 0), "columns ascending, no duplicates"
+        A[i, cols] = w[rp[i]:rp[i + 1]]
+    Aw = gs_adjacency(mesh.ids)
+    np.fill_diagonal(Aw, 0.0)
+    assert np.array_equal(A, Aw)
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16), (9, 7, 5), (3, 1, 4)])
+def test_box_pair_counts_closed_form(orc, dims):
+    mesh = mg.box_hex(*dims)
+    rp, col, w = orc.dual_graph(mesh.ids)
+    cnt = mg.box_counts(*dims)
+    assert np.sum(w == 4) == 2 * cnt["face"]
+    assert np.sum(w == 2) == 2 * cnt["edge"]
+    assert np.sum(w == 1) == 2 * cnt["corner"]
+    assert set(np.unique(w)) <= {1, 2, 4}
+    # interior element: 26 neighbours, weighted degree 6*4 + 12*2 + 8*1 = 56
+    if min(dims) >= 3:
+        nx, ny, nz = dims
+        e = 1 + nx * (1 + ny * 1)
+        assert rp[e + 1] - rp[e] == 26
+        assert w[rp[e]:rp[e + 1]].sum() == 56
+    # face graph: the 7-point stencil
+    rpf, colf, wf = orc.dual_graph(mesh.ids, graph="face")
+    assert len(colf) == 2 * cnt["face"] and np.all(wf == 1)
+    rpu, colu, wu = orc.dual_graph(mesh.ids, graph="unit")
+    assert np.array_equal(colu, col) and np.all(wu == 1)
+
+
+def test_dual_graph_renumber_and_shuffle_invariance(orc):
+    base = mg.uniform_holes(mg.box_hex(8, 7, 6), 0.1, 21)
+    rp, col, w = orc.dual_graph(base.ids)
+    ren = mg.renumber_vertices(base, 4)
+    rp2, col2, w2 = orc.dual_graph(ren.ids)
+    assert np.array_equal(rp, rp2) and np.array_equal(col, col2) and np.array_equal(w, w2)
+    sh = mg.shuffle_elements(base, 8)
+    perm = sh.meta["perm"]                       # new element k = old element perm[k]
+    rp3, col3, w3 = orc.dual_graph(sh.ids)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    for k in range(0, sh.nelem, 7):
+        old = perm[k]
+        a = sorted(zip(inv[col[rp[old]:rp[old + 1]]], w[rp[old]:rp[old + 1]]))
+        b = list(zip(col3[rp3[k]:rp3[k + 1]], w3[rp3[k]:rp3[k + 1]]))
+        assert [tuple(map(int, x)) for x in a] == [tuple(map(int, x)) for x in b]
+
+
+def test_repeated_vertex_counts_once(orc):
+    # a collapsed element lists vertex 4 twice; shared ids are counted as a set
+    ids = np.array([[1, 2, 3, 4], [4, 4, 5, 6], [3, 4, 7, 8]])
+    rp, col, w = orc.dual_graph(ids)
+    A = np.zeros((3, 3), dtype=int)
+    for i in range(3):
+        A[i, col[rp[i]:rp[i + 1]]] = w[rp[i]:rp[i + 1]]
+    assert A[0, 1] == 1 and A[1, 2] == 1 and A[0, 2] == 2
+
+
+@pytest.mark.parametrize("name,mesh", small_meshes())
+def test_laplacian_invariants(orc, name, mesh):
+    for graph in ("weighted", "unit", "face"):
+        rp, col, w = orc.dual_graph(mesh.ids, graph=graph)
+        L = dense_laplacian(rp, col, w)
+        assert np.array_equal(L, L.T)
+        assert np.allclose(L.sum(axis=1), 0.0)           # zero row sums, L 1 = 0
+        ev = np.linalg.eigvalsh(L)
+        assert ev.min() > -1e-10 * max(1.0, ev.max())      # positive semi-definite
+        x = np.random.default_rng(0).standard_normal(mesh.nelem)
+        assert np.allclose(orc.laplacian_apply(rp, col, w, x), L @ x, rtol=1e-13, atol=1e-11)
+
+
+def test_zero_multiplicity_equals_components(orc):
+    a = mg.box_hex(4, 3, 3)
+    b = mg.box_hex(3, 3, 2)
+    ids = np.concatenate([a.ids, b.ids + 10_000])
+    rp, col, w = orc.dual_graph(ids)
+    ev = np.linalg.eigvalsh(dense_laplacian(rp, col, w))
+    assert np.sum(np.abs(ev) < 1e-9) == 2
+
+
+def test_cut_identity(orc):
+    mesh = mg.uniform_holes(mg.box_hex(6, 5, 4), 0.1, 2)
+    rng = np.random.default_rng(1)
+    for graph in ("unit", "weighted"):
+        rp, col, w = orc.dual_graph(mesh.ids, graph=graph)
+        for _ in range(3):
+            x = np.where(rng.random(mesh.nelem) < 0.5, -1.0, 1.0)
+            cut = 0
+            for i in range(mesh.nelem):
+                for p in range(rp[i], rp[i + 1]):
+                    if col[p] > i and x[i] != x[col[p]]:
+                        cut += w[p]
+            xLx = x @ orc.laplacian_apply(rp, col, w, x)
+            assert xLx == 4 * cut   # x^T L x = 4 delta(A, B) (Sec. 3)
+
+
+# ---------------------------------------------------------------------------
+# Tridiagonal eigen-solve and the start vector
+# ---------------------------------------------------------------------------
+
+def test_tridiag_smallest_matches_dense(orc):
+    rng = np.random.default_rng(3)
+    for k in (1, 2, 5, 40, 100):
+        a = rng.uniform(0, 10, k)
+        b = np.concatenate([[0.0], rng.uniform(0.1, 3, k - 1)])
+        T = np.diag(a) + np.diag(b[1:], 1) + np.diag(b[1:], -1)
+        ev, V = np.linalg.eigh(T)
+        th, t = orc.tridiag_smallest(a, b, thr=-1e300)
+        assert abs(th - ev[0]) <= 1e-12 * max(1.0, abs(ev).max())
+        assert abs(abs(t @ V[:, 0]) - 1.0) < 1e-10
+        if k >= 5:
+            thr = 0.5 * (ev[1] + ev[2])           # skip the two lowest
+            th2, _ = orc.tridiag_smallest(a, b, thr=thr)
+            assert abs(th2 - ev[2]) <= 1e-12 * abs(ev).max()
+
+
+def test_start_vector_is_splitmix64(orc):
+    g = load("splitmix64_seed0.json")
+    for gid, hx in enumerate(g["outputs_hex"]):
+        z = int(hx, 16)
+        ref = 2.0 * ((z >> 11) * 2.0 ** -53) - 1.0
+        assert orc.start_value(0, gid) == ref
+
+
+# ---------------------------------------------------------------------------
+# Fiedler pair
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(12, 7, 5), (20, 9, 8), (9, 4, 3)])
+def test_face_box_fiedler_closed_form(orc, dims):
+    mesh = mg.box_hex(*dims)
+    nmax = max(dims)
+    st, lam, y, info = orc.fiedler(mesh.ids, graph="face", tol=1e-10)
+    assert st == 0
+    exact = 2.0 - 2.0 * math.cos(math.pi / nmax)
+    assert abs(lam - exact) <= 1e-10 * exact
+    axis = int(np.argmax(dims))
+    idx = np.unravel_index(mesh.lex, dims[::-1])   # (k, j, i)
+    coord = idx[2 - axis]
+    ref = np.cos(math.pi * (coord + 0.5) / nmax)
+    ref /= np.linalg.norm(ref)
+    assert abs(abs(y @ ref) - 1.0) < 1e-9
+
+
+@pytest.mark.parametrize("name,mesh", small_meshes())
+def test_fiedler_matches_dense_eigh(orc, name, mesh):
+    for graph in ("weighted", "face"):
+        rp, col, w = orc.dual_graph(mesh.ids, graph=graph)
+        L = dense_laplacian(rp, col, w)
+        ev, V = np.linalg.eigh(L)
+        ncomp = int(np.sum(np.abs(ev) < 1e-9))
+        if ncomp != 1:
+            continue
+        st, lam, y, info = orc.fiedler(mesh.ids, graph=graph, tol=1e-10)
+        assert st == 0
+        assert abs(lam - ev[1]) <= 1e-10 * ev[1]
+        assert abs(y.sum()) < 1e-10
+        assert abs(np.linalg.norm(y) - 1.0) < 1e-12
+        if ev[2] - ev[1] > 1e-6 * ev[1]:
+            assert abs(abs(y @ V[:, 1]) - 1.0) < 1e-8
+
+
+def test_inverse_iteration_agrees_with_lanczos(orc):
+    mesh = mg.uniform_holes(mg.box_hex(14, 9, 7), 0.05, 5)
+    st1, lam1, y1, _ = orc.fiedler(mesh.ids, tol=1e-9)
+    st2, lam2, y2, info = orc.fiedler(mesh.ids, method="inverse_cg", tol=1e-9, inv_max_outer=300)
+    assert st1 == 0 and st2 == 0
+    assert abs(lam1 - lam2) <= 1e-9 * lam1
+    assert abs(abs(y1 @ y2) - 1.0) < 1e-6
+
+
+def test_cg_one_step_on_eigenvector(orc):
+    # With b an exact eigenvector, CG from x0 = 0 returns b / lambda in one
+    # step, so inverse iteration stops after its first outer pass (Sec. 7).
+    # a graph whose deflated start vector is an eigenvector: two elements
+    # sharing an edge, whose only nonzero eigenvector is (1, -1)/sqrt(2)
+    ids = np.array([[0, 1, 2, 3], [2, 3, 4, 5]])
+    st, lam, y, info = orc.fiedler(ids, method="inverse_cg")
+    assert st == 0 and info["cycles"] == 1 and info["cg_iters"] == 1
+    assert abs(lam - 4.0) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Split rule and recursion
+# ---------------------------------------------------------------------------
+
+def test_split_brute_force(orc):
+    rng = np.random.default_rng(7)
+    for trial in range(20):
+        n = int(rng.integers(1, 60))
+        y = rng.choice([-1.0, -0.0, 0.0, 0.5, 0.25, -0.25, 3.0], size=n)
+        gid = rng.permutation(1000)[:n].astype(np.int64)
+        n_low = int(rng.integers(0, n + 1))
+        side = orc.split(y, gid, n_low)
+        signbit = np.signbit(y)
+        # ascending (value, sign: -0 before +0, gid)
+        order = sorted(range(n), key=lambda i: (y[i], 0 if signbit[i] else 1, gid[i]))
+        ref = np.ones(n, dtype=np.uint8)
+        ref[order[:n_low]] = 0
+        assert np.array_equal(side, ref)
+
+
+def test_canonical_sign(orc):
+    mesh = mg.box_hex(9, 5, 4)
+    st, lam, y, _ = orc.fiedler(mesh.ids, tol=1e-10)
+    thr = 1e-3 * np.abs(y).max()
+    first = np.nonzero(np.abs(y) >= thr)[0][0]
+    assert y[first] <= 0
+
+
+@pytest.mark.parametrize("n,p", [(10, 3), (37, 5), (64, 7), (100, 16), (29, 29), (30, 1)])
+def test_balance_rule(orc, n, p):
+    mesh = mg.box_quad(n, 1)
+    st, part, info = orc.partition(mesh.ids, p)
+    sizes = np.bincount(part, minlength=p)
+    assert sizes.min() >= n // p and sizes.max() <= -(-n // p)
+    # floor/ceil recursion: the low side of every split gets floor(P/2) parts
+    # and floor(n P_L / P) elements
+    def expect(n, p):
+        if p == 1:
+            return [n]
+        pl = p // 2
+        nl = n * pl // p
+        return expect(nl, pl) + expect(n - nl, p - pl)
+    assert list(sizes) == expect(n, p)
+    if (n, p) == (10, 3):
+        assert list(sizes) == [3, 3, 4]
+
+
+def test_rsb_octants_face_graph(orc):
+    # 24x20x18 with a unique, even longest axis at every level: the RSB cut is
+    # the octant partition; face cut = 20*18 + 2*12*18 + 4*12*10 = 1272 and
+    # every part has 7 vertex neighbours (as in the P = 8 row of Table 4).
+    mesh = mg.box_hex(24, 20, 18)
+    st, part, info = orc.partition(mesh.ids, 8, graph="face", tol=1e-8)
+    assert st == 0
+    rp, col, w = orc.dual_graph(mesh.ids, graph="face")
+    rows = np.repeat(np.arange(mesh.nelem), np.diff(rp))
+    face_cut = int(np.sum(part[rows] != part[col])) // 2
+    assert face_cut == 1272
+    k, j, i = np.unravel_index(mesh.lex, (18, 20, 24))
+    octant = (i >= 12).astype(int) * 4 + (j >= 10).astype(int) * 2 + (k >= 9).astype(int)
+    # same partition up to renaming of the parts
+    pairs = set(zip(part.tolist(), octant.tolist()))
+    assert len(pairs) == 8
+    met = orc.metrics(mesh.ids, part, 8)
+    assert met["max_neighbors"] == 7 and met["avg_neighbors"] == 7.0
+    assert met["min_size"] == met["max_size"] == mesh.nelem // 8
+
+
+def test_weighted_half_box_cut(orc):
+    # Weighted vertex graph on a box with a unique longest (even) axis: by
+    # reflection symmetry the median split is the exact half box.  Weighted
+    # cut across the mid plane = 4 (2 ny - 1)(2 nz - 1); element pairs across
+    # it = (3 ny - 2)(3 nz - 2).
+    nx, ny, nz = 10, 6, 5
+    mesh = mg.box_hex(nx, ny, nz)
+    st, part, info = orc.partition(mesh.ids, 2, tol=1e-9)
+    assert st == 0
+    i = mesh.lex % nx
+    assert len(set(zip(part.tolist(), (i >= nx // 2).tolist()))) == 2
+    met = orc.metrics(mesh.ids, part, 2)
+    assert met["weighted_cut"] == 4 * (2 * ny - 1) * (2 * nz - 1)
+    assert met["cut_pairs"] == (3 * ny - 2) * (3 * nz - 2)
+
+
+def test_disconnected_components_rule(orc):
+    # two disjoint boxes of 36 and 18 elements, 3 parts: the low side
+    # (1 part, 18 elements) is exactly the second box... components are
+    # ordered by smallest global id: box A (ids 0..35) first.
+    a = mg.box_hex(4, 3, 3)                 # 36 elements, gids 0..35
+    b = mg.box_hex(3, 3, 2)                 # 18 elements, gids 36..53
+    ids = np.concatenate([a.ids, b.ids + 10_000])
+    # P = 2: n_low = 27, straddling component = box A (0 < 27 < 36)
+    st, part, info = orc.partition(ids, 2)
+    assert st == 2
+    assert np.all(part[36:] == 1)
+    assert np.sum(part[:36] == 0) == 27
+    # 3 parts of 18: n_low = 18 cuts box A; then box A's rest + box B
+    st, part, info = orc.partition(ids, 3)
+    assert np.bincount(part).tolist() == [18, 18, 18]
+    # P such that the boundary is exact: 36 / 54 = 2/3 -> nparts 3 with
+    # P_L = 1 gives 18; use a mesh where the component boundary matches n_low
+    ids2 = np.concatenate([b.ids, b.ids + 10_000])  # two 18-element boxes
+    st, part, info = orc.partition(ids2, 2)
+    assert st == 2
+    assert np.all(part[:18] == 0) and np.all(part[18:] == 1)
+    met = orc.metrics(ids2, part, 2)
+    assert met["weighted_cut"] == 0
+    st, lam, y, info = orc.fiedler(ids2)
+    assert st == 2 and lam == 0.0 and np.all(y == 0.0)
