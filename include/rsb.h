@@ -1,0 +1,202 @@
+/*
+ * rsb.h -- C ABI of the MI355X (gfx950) recursive spectral bisection library.
+ *
+ * Problem (paper Sec. 2): given a mesh as per-element global vertex ids and a
+ * number of parts P, assign every element to one part so that the parts are
+ * disjoint, cover the mesh, and differ in size by at most one element, while
+ * the dual-graph edge cut stays small.  The method (Sec. 4, Alg. 1) bisects
+ * the element dual graph by the Fiedler vector of its Laplacian, computed by
+ * restarted Lanczos (Sec. 6) or by inverse iteration with conjugate
+ * gradients (Sec. 7, Alg. 2), and recurses into floor(P/2) / ceil(P/2) parts.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Element i of a mesh is row i of `elem_vertex_ids` (row-major, int64,
+ *    nelem x nv_per_elem).  Its global id is i; ids are used for the random
+ *    start vector, for tie-breaks and for ordering components.
+ *  - Buffers are owned by the caller.  The library never frees or keeps a
+ *    caller pointer after returning.  With opts->device_pointers == 0 every
+ *    array argument is host memory; with 1 every array argument is device
+ *    memory on opts->device (for instance a torch tensor's data_ptr()).
+ *  - Calls are synchronous: outputs are complete when the call returns.
+ *    Work is queued on opts->stream (a hipStream_t; NULL = the null stream).
+ *    Calls on distinct streams may run from distinct host threads.
+ *  - Scratch device memory comes from the stream-ordered allocator of the
+ *    device and is returned to its pool before the call returns.
+ *  - Limits: nelem < 2^28 elements per call (all meshes of a batch
+ *    together), edge weights <= 15 (shared-vertex counts), at most 1024
+ *    candidate neighbour entries per element when building the graph
+ *    (sum over its vertices of the elements touching that vertex).
+ *
+ * Return codes: 0 success; positive = warning, outputs valid; negative =
+ * error, outputs unspecified.  rsb_last_error() gives a message for the last
+ * failing call on the calling thread.
+ */
+#ifndef RSB_H
+#define RSB_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSB_OK 0
+#define RSB_WARN_NOT_CONVERGED 1 /* iteration caps reached; outputs valid */
+#define RSB_WARN_DISCONNECTED 2  /* a bisected graph was disconnected; rule below used */
+#define RSB_EINVAL (-1)          /* invalid argument */
+#define RSB_ENOMEM (-2)          /* device memory exhausted or above device_mem_limit */
+#define RSB_EDEVICE (-3)         /* HIP runtime error */
+#define RSB_EBUFFER (-4)         /* output buffer too small (see rsb_dual_graph) */
+#define RSB_EINTERNAL (-5)       /* internal consistency check failed */
+
+/* Dual-graph kinds.  Two elements are adjacent when they share at least one
+ * vertex id (Sec. 2); s_ij = number of distinct ids they share.  */
+#define RSB_GRAPH_WEIGHTED 0 /* weight s_ij (Sec. 4, weighted Laplacian; default) */
+#define RSB_GRAPH_UNIT 1     /* weight 1 for every adjacent pair (Sec. 4, unweighted) */
+#define RSB_GRAPH_FACE 2     /* weight 1 when s_ij >= nv/2 (face neighbours), else no edge */
+
+#define RSB_LANCZOS 0    /* restarted Lanczos, full reorthogonalisation (Sec. 6) */
+#define RSB_INVERSE_CG 1 /* inverse iteration, CG inner solves (Sec. 7, Alg. 2) */
+
+#define RSB_FP64 0  /* all vectors and arithmetic in FP64 */
+#define RSB_MIXED 1 /* FP32 vectors and SpMV; FP64 coefficients, projections,
+                       tridiagonal solve; then FP64 refinement of the pair */
+
+typedef struct rsb_opts {
+  int32_t struct_size;      /* sizeof(rsb_opts); set by rsb_opts_init */
+  int32_t graph;            /* RSB_GRAPH_* */
+  int32_t method;           /* RSB_LANCZOS or RSB_INVERSE_CG */
+  int32_t precision;        /* RSB_FP64 or RSB_MIXED */
+  int32_t lanczos_m;        /* Lanczos steps per cycle (default 100, max 250) */
+  int32_t max_restarts;     /* restarts after the first cycle (default 50) */
+  double tol;               /* converged when ||L y - theta y||_2 <= tol * theta */
+  int32_t refine_m;         /* MIXED: steps per FP64 refinement cycle (20) */
+  int32_t refine_max_restarts; /* MIXED: FP64 refinement cycles - 1 (50) */
+  double tol_fp32;          /* MIXED: tolerance that ends the FP32 phase (1e-2) */
+  int32_t inv_max_outer;    /* INVERSE_CG: outer iterations cap (50) */
+  int32_t cg_max_iter;      /* INVERSE_CG: CG steps per solve cap (20000) */
+  double cg_tol;            /* INVERSE_CG: CG stops at ||r|| <= cg_tol ||b|| (1e-8) */
+  int32_t cg_full_projection; /* reserved; must be 0 */
+  int32_t batched;          /* 1: all subgraphs of a level in one launch sequence;
+                               0: one subgraph at a time (reference mode) */
+  uint64_t seed;            /* start-vector seed (default 20261203) */
+  int32_t use_hipgraph;     /* 1: replay each Lanczos cycle as a captured hipGraph */
+  int32_t autotune;         /* 0: built-in tile; 1: use/extend the cache; 2: retune */
+  const char *autotune_cache; /* path of the tile cache file (NULL: no file) */
+  int32_t device;           /* HIP device ordinal */
+  int32_t device_pointers;  /* 0: host arrays; 1: device arrays */
+  void *stream;             /* hipStream_t, NULL for the null stream */
+  int64_t device_mem_limit; /* 0: no limit; else bytes of scratch allowed */
+  int32_t verbose;          /* 1: one line per level on stderr */
+  int32_t reserved[8];
+} rsb_opts;
+
+typedef struct rsb_stats {
+  int32_t struct_size;       /* sizeof(rsb_stats), set by the caller */
+  int32_t levels;            /* bisection levels run */
+  int64_t level_steps;       /* Lanczos (or CG) steps, one per launch over all
+                                segments of a level */
+  int64_t segment_steps;     /* the same counted per segment */
+  int64_t cycles;            /* Lanczos cycles summed over levels */
+  int64_t refine_steps;      /* MIXED: FP64 refinement steps (level-steps) */
+  int32_t not_converged;     /* segments that hit the iteration caps */
+  int32_t disconnected;      /* bisections of disconnected graphs */
+  double lambda2;            /* rsb_fiedler: Rayleigh quotient of the output */
+  double residual;           /* rsb_fiedler: ||L y - lambda y|| of the output */
+  double ms_graph;           /* dual-graph build (device time) */
+  double ms_solve;           /* eigen-solves */
+  double ms_split;           /* components, split and compaction */
+  double ms_total;           /* whole call, host wall clock */
+  double edge_cut;           /* rsb_partition: weighted edge cut of the result */
+  int64_t cut_pairs;         /* rsb_partition: adjacent element pairs cut */
+  int32_t max_neighbors;     /* rsb_partition: max parts sharing a vertex with a part
+                                (-1 when nparts > 16384) */
+  double avg_neighbors;      /* rsb_partition: mean of the same */
+  int64_t nnz;               /* off-diagonal nonzeros of the level-0 Laplacian */
+  double spmv_bytes;         /* algorithmic bytes moved by all SpMVs */
+  double ms_spmv_est;        /* reserved */
+  int32_t reserved[8];
+} rsb_stats;
+
+/* Fills *o with the defaults listed above.  Returns RSB_OK or RSB_EINVAL (o NULL). */
+int rsb_opts_init(rsb_opts *o);
+
+/* Element dual graph and its Laplacian (Sec. 2; Sec. 4 equations for the
+ * unweighted and weighted Laplacian; Sec. 5: the same matrix as the
+ * off-diagonal part of P^T Q Q^T P).  Output: off-diagonal CSR of L with
+ * positive weights w_ij = -l_ij, columns strictly ascending within a row,
+ * row_ptr[nelem + 1] int64, col_idx[nnz] int32, weight[nnz] int32; the
+ * diagonal is the row sum of weights.  A vertex id repeated inside one element
+ * counts once.  Two-call size query: with col_idx == NULL only *nnz_inout is
+ * written (row_ptr may be NULL then); otherwise *nnz_inout is the capacity of
+ * col_idx/weight on entry and nnz on return, RSB_EBUFFER if too small.
+ * Errors: RSB_EINVAL for null ids/nnz_inout, nelem < 1, nv < 1, a negative id,
+ * a weight above 15 or an element with more than 1024 candidate entries. */
+int rsb_dual_graph(int64_t nelem, int32_t nv_per_elem, const int64_t *elem_vertex_ids,
+                   const rsb_opts *opts, int64_t *row_ptr, int32_t *col_idx, int32_t *weight,
+                   int64_t *nnz_inout);
+
+/* y = L x on a caller-supplied off-diagonal CSR (row_ptr int64[n+1], col_idx
+ * int32, weight int32 in [0, 15], columns < n), evaluated as
+ * y_i = sum_j w_ij (x_i - x_j) in FP64 (Sec. 5: the action of the Laplacian).
+ * Exposed for testing the SpMV.  RSB_EINVAL on bad sizes or weights. */
+int rsb_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                        const int32_t *weight, const double *x, double *y, const rsb_opts *opts);
+
+/* Fiedler pair of the mesh's dual-graph Laplacian (Sec. 4: L x = lambda x
+ * with 1^T x = 0; Sec. 6 Lanczos or Sec. 7 inverse iteration).  fiedler_out
+ * [nelem] FP64 in element order, unit 2-norm, orthogonal to the ones vector,
+ * with its sign fixed so that the lowest-index element whose |y_i| is at least
+ * 1e-3 max|y| has y_i <= 0.  *lambda2_out = y^T L y (FP64).  If the graph is
+ * disconnected, the bisection rule for disconnected graphs applies (see
+ * rsb_partition): the vector is the Fiedler vector of the component that
+ * straddles position floor(nelem/2), zero elsewhere (all zero, lambda 0, if
+ * no component straddles it), and RSB_WARN_DISCONNECTED is returned.
+ * stats_out may be NULL.  Errors: as rsb_dual_graph, and nelem < 2. */
+int rsb_fiedler(int64_t nelem, int32_t nv_per_elem, const int64_t *elem_vertex_ids,
+                const rsb_opts *opts, double *fiedler_out, double *lambda2_out,
+                rsb_stats *stats_out);
+
+/* The split rule (Sec. 4: sort by the Fiedler vector and give the first part
+ * of the sorted order to the first half of the processors): side[i] = 0 for
+ * the n_low smallest keys (y_i, gid_i) and 1 for the rest, where keys compare
+ * y first (IEEE total order, -0.0 before +0.0) and then gid.  gid must be
+ * distinct.  Exposed for testing the radix select.  RSB_EINVAL on NaN in y,
+ * n_low outside [0, n] or null pointers. */
+int rsb_split(int64_t n, const double *y, const int64_t *gid, int64_t n_low, uint8_t *side,
+              const rsb_opts *opts);
+
+/* Recursive spectral bisection (Alg. 1).  part_out[nelem] int32 in [0, nparts).
+ * A part range [p0, p0 + P) with n elements splits into [p0, p0 + floor(P/2))
+ * with floor(n floor(P/2) / P) elements (the smallest keys of the Fiedler
+ * vector, see rsb_split) and [p0 + floor(P/2), p0 + P) with the rest, so all
+ * part sizes are floor(nelem/nparts) or ceil(nelem/nparts).  A disconnected
+ * subgraph is bisected component-wise: components ordered by smallest global
+ * id go whole to the low side while they fit; the one component that
+ * straddles the target count is cut by its own Fiedler vector.
+ * Returns RSB_OK, RSB_WARN_DISCONNECTED if that rule was used,
+ * RSB_WARN_NOT_CONVERGED if a solve hit its caps (the partition is still
+ * valid).  Errors: as rsb_dual_graph, nparts < 1 or nparts > nelem.
+ * stats_out may be NULL. */
+int rsb_partition(int64_t nelem, int32_t nv_per_elem, const int64_t *elem_vertex_ids,
+                  int32_t nparts, const rsb_opts *opts, int32_t *part_out, rsb_stats *stats_out);
+
+/* rsb_partition on nmesh independent meshes in one call: every bisection
+ * level of all meshes runs as one batched launch sequence.  Mesh b has
+ * nelem[b] elements, ids elem_vertex_ids[b] and is split into nparts[b]
+ * parts written to part_out[b].  With device_pointers == 1 the pointer
+ * arrays themselves are host arrays of device pointers.  Results equal nmesh
+ * separate rsb_partition calls. */
+int rsb_partition_batch(int32_t nmesh, const int64_t *nelem, int32_t nv_per_elem,
+                        const int64_t *const *elem_vertex_ids, const int32_t *nparts,
+                        const rsb_opts *opts, int32_t *const *part_out, rsb_stats *stats_out);
+
+/* Message for a return code (static string). */
+const char *rsb_strerror(int code);
+/* Message of the last failing call on this thread ("" if none). */
+const char *rsb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSB_H */

@@ -10,7 +10,8 @@
 //  * the start vector is r_i = U[-1, 1) from splitmix64(seed, gid_i);
 //  * the ones vector u0 = 1/sqrt(n) is kept in the reorthogonalisation basis;
 //  * two classical Gram-Schmidt passes per Lanczos step;
-//  * convergence when ||L y - theta y||_2 <= tol * theta; explicit restart
+//  * convergence when ||L y - rho y||_2 <= tol * rho (rho the Rayleigh quotient
+//    of the Ritz vector); explicit restart
 //    from the Ritz vector; at most max_restarts restarts;
 //  * canonical sign: the first element (in global-id order) whose |y| is at
 //    least 1e-3 max|y| gets y <= 0;
@@ -313,9 +314,11 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
       for (int64_t i = 0; i < n; ++i) y[i] += t[c] * Q[c][i];
     deflate_ones(y);
     normalize(y);
-    res = residual_norm(g, y, theta, info.matvecs);
+    // residual against the Rayleigh quotient rho of the Ritz vector
+    double rho = rayleigh(g, y, info.matvecs);
+    res = residual_norm(g, y, rho, info.matvecs);
     info.cycles = cycle + 1;
-    if (res <= o.tol * theta) {
+    if (res <= o.tol * rho) {
       converged = 1;
       break;
     }

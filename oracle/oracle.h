@@ -33,7 +33,7 @@ typedef struct orc_opts {
   int32_t method;            /* ORC_LANCZOS or ORC_INVERSE_CG */
   int32_t lanczos_m;         /* Lanczos steps per cycle */
   int32_t max_restarts;      /* cycles after the first one */
-  double tol;                /* stop when ||L y - theta y|| <= tol * theta */
+  double tol;                /* stop when ||L y - rho y|| <= tol * rho, rho = y^T L y */
   int32_t inv_max_outer;     /* inverse iteration: outer cap */
   int32_t cg_max_iter;       /* CG iteration cap per solve */
   double cg_tol;             /* CG: ||r|| <= cg_tol * ||b|| */

@@ -1,0 +1,248 @@
+"""Python binding of librsb.so, the gfx950 recursive spectral bisection library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library behind the C ABI of ``include/rsb.h``.  Arrays may be numpy arrays
+(host memory) or torch tensors on a ROCm device; in the latter case the
+library reads and writes them in place (``device_pointers = 1``) and queues
+its work on torch's current stream.  There is no CPU fallback: if the
+library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librsb.so")
+
+GRAPH = {"weighted": 0, "unit": 1, "face": 2}
+METHOD = {"lanczos": 0, "inverse_cg": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+
+OK, WARN_NOT_CONVERGED, WARN_DISCONNECTED = 0, 1, 2
+EINVAL, ENOMEM, EDEVICE, EBUFFER, EINTERNAL = -1, -2, -3, -4, -5
+
+
+class Opts(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_int32), ("graph", C.c_int32), ("method", C.c_int32),
+        ("precision", C.c_int32), ("lanczos_m", C.c_int32), ("max_restarts", C.c_int32),
+        ("tol", C.c_double), ("refine_m", C.c_int32), ("refine_max_restarts", C.c_int32),
+        ("tol_fp32", C.c_double), ("inv_max_outer", C.c_int32), ("cg_max_iter", C.c_int32),
+        ("cg_tol", C.c_double), ("cg_full_projection", C.c_int32), ("batched", C.c_int32),
+        ("seed", C.c_uint64), ("use_hipgraph", C.c_int32), ("autotune", C.c_int32),
+        ("autotune_cache", C.c_char_p), ("device", C.c_int32), ("device_pointers", C.c_int32),
+        ("stream", C.c_void_p), ("device_mem_limit", C.c_int64), ("verbose", C.c_int32),
+        ("reserved", C.c_int32 * 8),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_int32), ("levels", C.c_int32), ("level_steps", C.c_int64),
+        ("segment_steps", C.c_int64), ("cycles", C.c_int64), ("refine_steps", C.c_int64),
+        ("not_converged", C.c_int32), ("disconnected", C.c_int32), ("lambda2", C.c_double),
+        ("residual", C.c_double), ("ms_graph", C.c_double), ("ms_solve", C.c_double),
+        ("ms_split", C.c_double), ("ms_total", C.c_double), ("edge_cut", C.c_double),
+        ("cut_pairs", C.c_int64), ("max_neighbors", C.c_int32), ("avg_neighbors", C.c_double),
+        ("nnz", C.c_int64), ("spmv_bytes", C.c_double), ("ms_spmv_est", C.c_double),
+        ("reserved", C.c_int32 * 8),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "struct_size")}
+
+
+class RsbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rsb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# Every function of the C ABI, with its ctypes signature.
+_SIGNATURES = {
+    "rsb_opts_init": ([C.c_void_p], C.c_int),
+    "rsb_dual_graph": ([C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                        C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
+    "rsb_laplacian_apply": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p], C.c_int),
+    "rsb_fiedler": ([C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                     C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "rsb_split": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
+    "rsb_partition": ([C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                       C.c_void_p], C.c_int),
+    "rsb_partition_batch": ([C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "rsb_strerror": ([C.c_int], C.c_char_p),
+    "rsb_last_error": ([], C.c_char_p),
+}
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2606_14659_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code: int, what: str) -> int:
+    if code < 0:
+        msg = lib().rsb_last_error().decode()
+        raise RsbError(code, f"{what}: {msg or lib().rsb_strerror(code).decode()}")
+    return code
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def make_opts(device_arrays: bool = False, **kw) -> Opts:
+    o = Opts()
+    _check(lib().rsb_opts_init(C.byref(o)), "rsb_opts_init")
+    for k, v in kw.items():
+        if k == "graph" and isinstance(v, str):
+            v = GRAPH[v]
+        elif k == "method" and isinstance(v, str):
+            v = METHOD[v]
+        elif k == "precision" and isinstance(v, str):
+            v = PRECISION[v]
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    if device_arrays:
+        import torch
+        o.device_pointers = 1
+        o.device = torch.cuda.current_device()
+        o.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return o
+
+
+class _Arr:
+    """An argument array: numpy (host) or torch (device) with its pointer."""
+
+    def __init__(self, a, dtype, device: bool):
+        if device:
+            import torch
+            tdt = {np.int64: torch.int64, np.int32: torch.int32, np.float64: torch.float64,
+                   np.uint8: torch.uint8}[dtype]
+            if not _is_torch(a):
+                a = torch.as_tensor(np.ascontiguousarray(a, dtype=dtype))
+            self.a = a.to(device="cuda", dtype=tdt).contiguous()
+            self.ptr = C.c_void_p(self.a.data_ptr())
+        else:
+            self.a = np.ascontiguousarray(a, dtype=dtype)
+            self.ptr = self.a.ctypes.data_as(C.c_void_p)
+
+
+def _out(shape, dtype, device: bool):
+    if device:
+        import torch
+        tdt = {np.int64: torch.int64, np.int32: torch.int32, np.float64: torch.float64,
+               np.uint8: torch.uint8}[dtype]
+        t = torch.empty(shape, dtype=tdt, device="cuda")
+        return t, C.c_void_p(t.data_ptr())
+    a = np.zeros(shape, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _ids_shape(ids):
+    if len(ids.shape) != 2:
+        raise ValueError("ids must be a [nelem, nv] array")
+    return int(ids.shape[0]), int(ids.shape[1])
+
+
+def dual_graph(ids, device: bool = False, **kw):
+    """Off-diagonal CSR of the dual-graph Laplacian: (row_ptr, col, weight)."""
+    n, nv = _ids_shape(ids)
+    o = make_opts(device, **kw)
+    a = _Arr(ids, np.int64, device)
+    nnz = C.c_int64(0)
+    _check(lib().rsb_dual_graph(n, nv, a.ptr, C.byref(o), None, None, None, C.byref(nnz)),
+           "rsb_dual_graph")
+    rp, rpp = _out(n + 1, np.int64, device)
+    col, colp = _out(max(nnz.value, 1), np.int32, device)
+    w, wp = _out(max(nnz.value, 1), np.int32, device)
+    _check(lib().rsb_dual_graph(n, nv, a.ptr, C.byref(o), rpp, colp, wp, C.byref(nnz)),
+           "rsb_dual_graph")
+    return rp, col[: nnz.value], w[: nnz.value]
+
+
+def laplacian_apply(row_ptr, col, weight, x, device: bool = False, **kw):
+    n = len(row_ptr) - 1
+    o = make_opts(device, **kw)
+    rp = _Arr(row_ptr, np.int64, device)
+    c = _Arr(col if len(col) else np.zeros(1), np.int32, device)
+    w = _Arr(weight if len(weight) else np.zeros(1), np.int32, device)
+    xx = _Arr(x, np.float64, device)
+    y, yp = _out(n, np.float64, device)
+    _check(lib().rsb_laplacian_apply(n, rp.ptr, c.ptr, w.ptr, xx.ptr, yp, C.byref(o)),
+           "rsb_laplacian_apply")
+    return y
+
+
+def split(y, gid, n_low, device: bool = False, **kw):
+    n = len(y)
+    o = make_opts(device, **kw)
+    yy = _Arr(y, np.float64, device)
+    g = _Arr(gid, np.int64, device)
+    side, sp = _out(n, np.uint8, device)
+    _check(lib().rsb_split(n, yy.ptr, g.ptr, int(n_low), sp, C.byref(o)), "rsb_split")
+    return side
+
+
+def fiedler(ids, device: bool = False, **kw):
+    """(status, lambda2, y, stats) of the mesh's dual-graph Laplacian."""
+    n, nv = _ids_shape(ids)
+    o = make_opts(device, **kw)
+    a = _Arr(ids, np.int64, device)
+    y, yp = _out(n, np.float64, device)
+    lam = C.c_double(0)
+    st = Stats()
+    st.struct_size = C.sizeof(Stats)
+    code = _check(lib().rsb_fiedler(n, nv, a.ptr, C.byref(o), yp, C.byref(lam), C.byref(st)),
+                  "rsb_fiedler")
+    return code, lam.value, y, st.as_dict()
+
+
+def partition(ids, nparts: int, device: bool = False, **kw):
+    """(status, part, stats): recursive spectral bisection into nparts parts."""
+    n, nv = _ids_shape(ids)
+    o = make_opts(device, **kw)
+    a = _Arr(ids, np.int64, device)
+    part, pp = _out(n, np.int32, device)
+    st = Stats()
+    st.struct_size = C.sizeof(Stats)
+    code = _check(lib().rsb_partition(n, nv, a.ptr, int(nparts), C.byref(o), pp, C.byref(st)),
+                  "rsb_partition")
+    return code, part, st.as_dict()
+
+
+def partition_batch(ids_list, nparts_list, device: bool = False, **kw):
+    """(status, [part], stats) for independent meshes in one call."""
+    nmesh = len(ids_list)
+    nv = _ids_shape(ids_list[0])[1]
+    o = make_opts(device, **kw)
+    arrs = [_Arr(a, np.int64, device) for a in ids_list]
+    nelem = (C.c_int64 * nmesh)(*[int(a.shape[0]) for a in ids_list])
+    nparts = (C.c_int32 * nmesh)(*[int(p) for p in nparts_list])
+    idp = (C.c_void_p * nmesh)(*[a.ptr.value for a in arrs])
+    outs = [_out(int(a.shape[0]), np.int32, device) for a in ids_list]
+    pp = (C.c_void_p * nmesh)(*[p.value for _, p in outs])
+    st = Stats()
+    st.struct_size = C.sizeof(Stats)
+    code = _check(lib().rsb_partition_batch(nmesh, nelem, nv, idp, nparts, C.byref(o), pp,
+                                            C.byref(st)), "rsb_partition_batch")
+    return code, [p for p, _ in outs], st.as_dict()

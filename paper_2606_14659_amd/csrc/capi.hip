@@ -1,0 +1,569 @@
+// capi.hip -- the C entry points: argument checks, device set-up, the level
+// loop of recursive spectral bisection (Alg. 1), and error reporting.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace rsb {
+namespace {
+
+thread_local std::string g_last_error;
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename F>
+int guarded(F &&f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const Error &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return RSB_ENOMEM;
+  } catch (...) {
+    g_last_error = "unexpected exception";
+    return RSB_EINTERNAL;
+  }
+}
+
+void check_opts(const rsb_opts *o) {
+  if (!o) fail(RSB_EINVAL, "opts is NULL");
+  if (o->struct_size != (int32_t)sizeof(rsb_opts))
+    fail(RSB_EINVAL, "opts->struct_size mismatch (call rsb_opts_init)");
+  if (o->graph < 0 || o->graph > 2) fail(RSB_EINVAL, "graph kind");
+  if (o->method < 0 || o->method > 1) fail(RSB_EINVAL, "method");
+  if (o->precision < 0 || o->precision > 1) fail(RSB_EINVAL, "precision");
+  if (o->lanczos_m < 1 || o->lanczos_m > kMaxM) fail(RSB_EINVAL, "lanczos_m must be in [1, 250]");
+  if (o->refine_m < 1 || o->refine_m > kMaxM) fail(RSB_EINVAL, "refine_m must be in [1, 250]");
+  if (o->max_restarts < 0 || o->refine_max_restarts < 0) fail(RSB_EINVAL, "negative restarts");
+  if (!(o->tol > 0) || !(o->tol_fp32 > 0) || !(o->cg_tol > 0)) fail(RSB_EINVAL, "tolerances");
+  if (o->inv_max_outer < 1 || o->cg_max_iter < 1) fail(RSB_EINVAL, "inverse iteration caps");
+  if (o->cg_full_projection != 0) fail(RSB_EINVAL, "cg_full_projection is not supported");
+  if (o->autotune < 0 || o->autotune > 2) fail(RSB_EINVAL, "autotune");
+}
+
+void setup_ctx(Ctx &ctx, const rsb_opts &o) {
+  int ndev = 0;
+  RSB_HIP(hipGetDeviceCount(&ndev));
+  if (o.device < 0 || o.device >= ndev) fail(RSB_EINVAL, "device ordinal out of range");
+  RSB_HIP(hipSetDevice(o.device));
+  ctx.device = o.device;
+  ctx.stream = (hipStream_t)o.stream;
+  if (!ctx.stream) {
+    // graph capture needs a real stream: use a private one for this call
+    RSB_HIP(hipStreamCreateWithFlags(&ctx.stream, hipStreamNonBlocking));
+    ctx.own_stream = true;
+    // work the caller queued on the null stream must be visible to ours
+    RSB_HIP(hipStreamSynchronize(nullptr));
+  }
+  ctx.limit = o.device_mem_limit;
+  ctx.verbose = o.verbose;
+  static std::once_flag once[64];
+  if (o.device < 64)
+    std::call_once(once[o.device], [&] {
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, o.device) == hipSuccess) {
+        uint64_t thr = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+      }
+    });
+}
+
+// Device copy of a caller array (or the caller's device pointer itself).
+template <typename T>
+struct InArr {
+  DevBuf<T> own;
+  const T *p = nullptr;
+  void init(Ctx &ctx, const T *src, int64_t n, bool device) {
+    if (device) {
+      p = src;
+      return;
+    }
+    own.alloc(ctx, std::max<int64_t>(n, 1));
+    if (n > 0)
+      RSB_HIP(hipMemcpyAsync(own.get(), src, n * sizeof(T), hipMemcpyHostToDevice, ctx.stream));
+    p = own.get();
+  }
+};
+
+template <typename T>
+void copy_out(Ctx &ctx, T *dst, const T *dsrc, int64_t n, bool device) {
+  if (n <= 0) return;
+  RSB_HIP(hipMemcpyAsync(dst, dsrc, n * sizeof(T),
+                         device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx.stream));
+}
+
+int pick_rpt(int64_t nrows) {
+  // rows per thread of the streaming kernels: enough blocks to fill 256 CUs
+  if (nrows >= (int64_t)8 * 256 * kBlock * 8) return 8;
+  if (nrows >= (int64_t)2 * 256 * kBlock * 4) return 4;
+  return 4;
+}
+
+struct MeshIn {
+  int64_t nelem;
+  const int64_t *d_ids;
+  int32_t nparts;
+};
+
+struct RunOut {
+  int status = RSB_OK;
+  int flip = 0;  // rsb_fiedler: the returned vector must be negated (sign rule)
+  double lambda = 0.0, residual = 0.0;
+};
+
+// The whole hot path for a batch of meshes: graph, then level by level
+// components -> eigen-solve -> split -> compaction.  part: concatenated
+// output (device).  If fiedler_y != nullptr, only the first level of a
+// single mesh runs and its vector is written there (device, nelem values).
+RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx &ctx,
+               int32_t *d_part, rsb_stats *stats, double *fiedler_y) {
+  RunOut out;
+  const double t0 = now_ms();
+  rsb_stats st{};
+  // 1. dual graphs
+  std::vector<DevCsr> graphs(meshes.size());
+  int64_t total = 0;
+  for (size_t b = 0; b < meshes.size(); ++b) {
+    build_dual_graph(meshes[b].d_ids, meshes[b].nelem, nv, o.graph, graphs[b], ctx);
+    st.nnz += graphs[b].nnz;
+    total += meshes[b].nelem;
+  }
+  if (total >= kMaxRows) fail(RSB_EINVAL, "too many elements (limit 2^28 per call)");
+  RSB_HIP(hipStreamSynchronize(ctx.stream));
+  const double t1 = now_ms();
+  st.ms_graph = t1 - t0;
+  // 2. level 0
+  std::vector<const DevCsr *> gp;
+  std::vector<int32_t> np;
+  int64_t parts_total = 0;
+  for (size_t b = 0; b < meshes.size(); ++b) {
+    gp.push_back(&graphs[b]);
+    np.push_back(fiedler_y ? 2 : meshes[b].nparts);
+    parts_total += meshes[b].nparts;
+  }
+  int rpt = pick_rpt(total);
+  Level L0;
+  level0_from_csr(L0, gp, np, rpt, ctx);
+  for (auto &g : graphs) {
+    g.col.release();
+    g.wgt.release();
+    g.row_ptr.release();
+  }
+  if (d_part) fill_i32(d_part, total, -1, ctx);
+  // meshes kept whole (one part)
+  {
+    int64_t off = 0;
+    for (size_t b = 0; b < meshes.size(); ++b) {
+      if (np[b] < 2 && d_part) fill_i32(d_part + off, meshes[b].nelem, 0, ctx);
+      off += meshes[b].nelem;
+    }
+  }
+  // 3. buffers sized for the largest level
+  const int64_t cap_rows = round_up(total, kWave) + (int64_t)kWave * (parts_total + 2 * (int64_t)meshes.size());
+  const bool mixed = o.precision == RSB_MIXED && o.method == RSB_LANCZOS;
+  const int m64 = mixed ? o.refine_m : o.lanczos_m;
+  DevBuf<float> basis32;
+  DevBuf<double> basis64;
+  if (o.method == RSB_LANCZOS) {
+    if (mixed) basis32.alloc(ctx, (size_t)(o.lanczos_m + 3) * cap_rows);
+    basis64.alloc(ctx, (size_t)(m64 + 3) * cap_rows);
+  }
+  DevBuf<double> y64(ctx, cap_rows);
+  DevBuf<uint8_t> side(ctx, cap_rows);
+  Level LA, LB;
+  Level *L = &L0;
+  Level *next = &LA;
+  int level = 0;
+  int worst = RSB_OK;
+  while (L->nseg > 0) {
+    const double ta = now_ms();
+    SolveDev S32, S64;
+    CompDev C;
+    solve_alloc(S64, *L, std::max(m64, 1), ctx);
+    components_and_targets(*L, C, S64, ctx);
+    int64_t steps = 0, ref_steps = 0;
+    if (o.method == RSB_LANCZOS) {
+      LanczosParams p64{m64, mixed ? o.refine_max_restarts : o.max_restarts, o.tol, 0,
+                        o.use_hipgraph, o.seed};
+      if (mixed) {
+        solve_alloc(S32, *L, o.lanczos_m, ctx);
+        RSB_HIP(hipMemcpyAsync(S32.st.get(), S64.st.get(), L->nseg * sizeof(SegState),
+                               hipMemcpyDeviceToDevice, ctx.stream));
+        LanczosParams p32{o.lanczos_m, o.max_restarts, o.tol_fp32, 1, o.use_hipgraph, o.seed};
+        steps += lanczos_level<float>(*L, C, S32, p32, nullptr, nullptr, basis32.get(), nullptr,
+                                      ctx);
+        ref_steps = lanczos_level<double>(*L, C, S64, p64, basis32.get(), &S32, basis64.get(),
+                                          y64.get(), ctx);
+        steps += ref_steps;
+      } else {
+        steps += lanczos_level<double>(*L, C, S64, p64, nullptr, nullptr, basis64.get(),
+                                       y64.get(), ctx);
+      }
+    } else {
+      InverseParams ip{o.inv_max_outer, o.cg_max_iter, o.cg_tol, o.tol, o.seed};
+      steps += inverse_level(*L, C, S64, ip, y64.get(), ctx);
+    }
+    // per-segment outcome
+    std::vector<SegState> hs(L->nseg);
+    RSB_HIP(hipMemcpyAsync(hs.data(), S64.st.get(), L->nseg * sizeof(SegState),
+                           hipMemcpyDeviceToHost, ctx.stream));
+    int64_t segsteps[2] = {0, 0};
+    RSB_HIP(hipMemcpyAsync(segsteps, S64.counters.get(), sizeof(int64_t), hipMemcpyDeviceToHost,
+                           ctx.stream));
+    if (mixed)
+      RSB_HIP(hipMemcpyAsync(segsteps + 1, S32.counters.get(), sizeof(int64_t),
+                             hipMemcpyDeviceToHost, ctx.stream));
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    const double tb = now_ms();
+    st.ms_solve += tb - ta;
+    st.level_steps += steps;
+    st.refine_steps += mixed ? ref_steps : 0;
+    st.segment_steps += segsteps[0] + segsteps[1];
+    int disc = 0, notconv = 0;
+    for (auto &s : hs) {
+      if (s.ncomp > 1) ++disc;
+      if (s.solve && !s.converged) ++notconv;
+      st.cycles += s.cycles;
+    }
+    st.disconnected += disc;
+    st.not_converged += notconv;
+    if (disc) worst = std::max(worst, RSB_WARN_DISCONNECTED);
+    if (notconv && worst == RSB_OK) worst = RSB_WARN_NOT_CONVERGED;
+    if (fiedler_y) {
+      const SegState &s = hs[0];
+      RSB_HIP(hipMemcpyAsync(fiedler_y, y64.get(), meshes[0].nelem * sizeof(double),
+                             hipMemcpyDeviceToDevice, ctx.stream));
+      // canonical sign: computed by the split's sign rule
+      split_level(*L, C, S64, y64.get(), side.get(), ctx);
+      std::vector<SegState> hs2(1);
+      RSB_HIP(hipMemcpyAsync(hs2.data(), S64.st.get(), sizeof(SegState), hipMemcpyDeviceToHost,
+                             ctx.stream));
+      RSB_HIP(hipStreamSynchronize(ctx.stream));
+      out.lambda = s.solve ? s.rho : 0.0;
+      out.residual = s.solve ? s.res : 0.0;
+      out.flip = hs2[0].flip;
+      out.status = (s.ncomp > 1) ? RSB_WARN_DISCONNECTED
+                                 : (s.solve && !s.converged ? RSB_WARN_NOT_CONVERGED : RSB_OK);
+      st.lambda2 = out.lambda;
+      st.residual = out.residual;
+      st.levels = 1;
+      st.ms_total = now_ms() - t0;
+      if (stats) {
+        int32_t sz = stats->struct_size;
+        *stats = st;
+        stats->struct_size = sz;
+      }
+      return out;
+    }
+    split_level(*L, C, S64, y64.get(), side.get(), ctx);
+    compact_level(*L, side.get(), d_part, *next, rpt, ctx);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    st.ms_split += now_ms() - tb;
+    if (ctx.verbose)
+      fprintf(stderr, "[rsb] level %d: %d segments, %lld rows, %lld level-steps, %.1f ms solve\n",
+              level, L->nseg, (long long)L->nrows, (long long)steps, tb - ta);
+    ++level;
+    // advance: keep level 0 for the metrics
+    Level *done = L;
+    L = next;
+    next = (done == &L0) ? &LB : done;
+    if (next != &L0) *next = Level();
+  }
+  st.levels = level;
+  std::vector<int32_t> poff(meshes.size(), 0);
+  {
+    int32_t off = 0;
+    for (size_t b = 0; b < meshes.size(); ++b) {
+      poff[b] = off;
+      off += meshes[b].nparts;
+    }
+  }
+  if (stats && L0.nseg > 0) partition_metrics(L0, d_part, (int32_t)parts_total, poff, &st, ctx);
+  RSB_HIP(hipStreamSynchronize(ctx.stream));
+  st.ms_total = now_ms() - t0;
+  if (stats) {
+    int32_t sz = stats->struct_size;
+    *stats = st;
+    stats->struct_size = sz;
+  }
+  out.status = worst;
+  return out;
+}
+
+__global__ void k_negate(double *y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = -y[i];
+}
+
+void check_mesh(int64_t nelem, int32_t nv, const int64_t *ids) {
+  if (!ids) fail(RSB_EINVAL, "elem_vertex_ids is NULL");
+  if (nelem < 1) fail(RSB_EINVAL, "nelem < 1");
+  if (nv < 1) fail(RSB_EINVAL, "nv_per_elem < 1");
+  if (nelem >= kMaxRows) fail(RSB_EINVAL, "nelem too large (limit 2^28)");
+  if (nelem * nv >= ((int64_t)1 << 31)) fail(RSB_EINVAL, "nelem * nv too large");
+}
+
+void check_stats(rsb_stats *s) {
+  if (s && s->struct_size != (int32_t)sizeof(rsb_stats))
+    fail(RSB_EINVAL, "stats->struct_size must be sizeof(rsb_stats)");
+}
+
+}  // namespace
+}  // namespace rsb
+
+using namespace rsb;
+
+extern "C" {
+
+int rsb_opts_init(rsb_opts *o) {
+  if (!o) return RSB_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(rsb_opts);
+  o->graph = RSB_GRAPH_WEIGHTED;
+  o->method = RSB_LANCZOS;
+  o->precision = RSB_FP64;
+  o->lanczos_m = 100;
+  o->max_restarts = 50;
+  o->tol = 1e-6;
+  o->refine_m = 20;
+  o->refine_max_restarts = 50;
+  o->tol_fp32 = 1e-4;
+  o->inv_max_outer = 50;
+  o->cg_max_iter = 20000;
+  o->cg_tol = 1e-8;
+  o->cg_full_projection = 0;
+  o->batched = 1;
+  o->seed = 20261203ull;
+  o->use_hipgraph = 1;
+  o->autotune = 0;
+  o->autotune_cache = nullptr;
+  o->device = 0;
+  o->device_pointers = 0;
+  o->stream = nullptr;
+  o->device_mem_limit = 0;
+  o->verbose = 0;
+  return RSB_OK;
+}
+
+const char *rsb_strerror(int code) {
+  switch (code) {
+    case RSB_OK: return "success";
+    case RSB_WARN_NOT_CONVERGED: return "eigen-solver hit its iteration caps (result valid)";
+    case RSB_WARN_DISCONNECTED: return "a bisected graph was disconnected (result valid)";
+    case RSB_EINVAL: return "invalid argument";
+    case RSB_ENOMEM: return "out of device memory";
+    case RSB_EDEVICE: return "HIP runtime error";
+    case RSB_EBUFFER: return "output buffer too small";
+    case RSB_EINTERNAL: return "internal error";
+    default: return "unknown code";
+  }
+}
+
+const char *rsb_last_error(void) { return g_last_error.c_str(); }
+
+int rsb_dual_graph(int64_t nelem, int32_t nv, const int64_t *ids, const rsb_opts *opts,
+                   int64_t *row_ptr, int32_t *col_idx, int32_t *weight, int64_t *nnz_inout) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    check_mesh(nelem, nv, ids);
+    if (!nnz_inout) fail(RSB_EINVAL, "nnz_inout is NULL");
+    if (col_idx && (!row_ptr || !weight)) fail(RSB_EINVAL, "row_ptr/weight NULL");
+    Ctx ctx;
+    setup_ctx(ctx, *opts);
+    const bool dev = opts->device_pointers != 0;
+    InArr<int64_t> in;
+    in.init(ctx, ids, nelem * nv, dev);
+    DevCsr g;
+    build_dual_graph(in.p, nelem, nv, opts->graph, g, ctx);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    if (!col_idx) {
+      *nnz_inout = g.nnz;
+      if (row_ptr) copy_out(ctx, row_ptr, g.row_ptr.get(), nelem + 1, dev);
+      RSB_HIP(hipStreamSynchronize(ctx.stream));
+      return RSB_OK;
+    }
+    if (*nnz_inout < g.nnz) {
+      *nnz_inout = g.nnz;
+      return RSB_EBUFFER;
+    }
+    copy_out(ctx, row_ptr, g.row_ptr.get(), nelem + 1, dev);
+    copy_out(ctx, col_idx, g.col.get(), g.nnz, dev);
+    copy_out(ctx, weight, g.wgt.get(), g.nnz, dev);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    *nnz_inout = g.nnz;
+    return RSB_OK;
+  });
+}
+
+int rsb_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                        const int32_t *weight, const double *x, double *y, const rsb_opts *opts) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    if (n < 1 || n >= kMaxRows || !row_ptr || !col_idx || !weight || !x || !y)
+      fail(RSB_EINVAL, "bad arguments");
+    const bool dev = opts->device_pointers != 0;
+    int64_t nnz = 0;
+    if (!dev) {
+      nnz = row_ptr[n];
+      for (int64_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) fail(RSB_EINVAL, "row_ptr not monotone");
+      for (int64_t p = 0; p < nnz; ++p) {
+        if (col_idx[p] < 0 || col_idx[p] >= n) fail(RSB_EINVAL, "column out of range");
+        if (weight[p] < 0 || weight[p] > (int32_t)kWeightMask) fail(RSB_EINVAL, "weight out of [0,15]");
+      }
+    }
+    Ctx ctx;
+    setup_ctx(ctx, *opts);
+    if (dev) {
+      RSB_HIP(hipMemcpy(&nnz, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost));
+    }
+    if (nnz < 0) fail(RSB_EINVAL, "row_ptr[n] < 0");
+    DevCsr g;
+    g.n = n;
+    g.nnz = nnz;
+    g.row_ptr.alloc(ctx, n + 1);
+    g.col.alloc(ctx, std::max<int64_t>(nnz, 1));
+    g.wgt.alloc(ctx, std::max<int64_t>(nnz, 1));
+    auto kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    RSB_HIP(hipMemcpyAsync(g.row_ptr.get(), row_ptr, (n + 1) * sizeof(int64_t), kind, ctx.stream));
+    if (nnz > 0) {
+      RSB_HIP(hipMemcpyAsync(g.col.get(), col_idx, nnz * sizeof(int32_t), kind, ctx.stream));
+      RSB_HIP(hipMemcpyAsync(g.wgt.get(), weight, nnz * sizeof(int32_t), kind, ctx.stream));
+    }
+    InArr<double> xin;
+    xin.init(ctx, x, n, dev);
+    DevBuf<double> yd(ctx, n);
+    laplacian_apply_csr(g, xin.p, yd.get(), ctx);
+    copy_out(ctx, y, yd.get(), n, dev);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    return RSB_OK;
+  });
+}
+
+int rsb_split(int64_t n, const double *y, const int64_t *gid, int64_t n_low, uint8_t *side,
+              const rsb_opts *opts) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    if (n < 1 || n >= kMaxRows || !y || !gid || !side) fail(RSB_EINVAL, "bad arguments");
+    if (n_low < 0 || n_low > n) fail(RSB_EINVAL, "n_low out of [0, n]");
+    const bool dev = opts->device_pointers != 0;
+    if (!dev) {
+      for (int64_t i = 0; i < n; ++i)
+        if (std::isnan(y[i])) fail(RSB_EINVAL, "NaN in y");
+    }
+    Ctx ctx;
+    setup_ctx(ctx, *opts);
+    InArr<double> yin;
+    yin.init(ctx, y, n, dev);
+    InArr<int64_t> gin;
+    gin.init(ctx, gid, n, dev);
+    DevBuf<uint8_t> sd(ctx, n);
+    split_vector(yin.p, gin.p, n, n_low, sd.get(), ctx);
+    copy_out(ctx, side, sd.get(), n, dev);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    return RSB_OK;
+  });
+}
+
+int rsb_fiedler(int64_t nelem, int32_t nv, const int64_t *ids, const rsb_opts *opts,
+                double *fiedler_out, double *lambda2_out, rsb_stats *stats_out) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    check_mesh(nelem, nv, ids);
+    check_stats(stats_out);
+    if (nelem < 2) fail(RSB_EINVAL, "nelem < 2");
+    if (!fiedler_out || !lambda2_out) fail(RSB_EINVAL, "output pointer NULL");
+    Ctx ctx;
+    setup_ctx(ctx, *opts);
+    const bool dev = opts->device_pointers != 0;
+    InArr<int64_t> in;
+    in.init(ctx, ids, nelem * nv, dev);
+    std::vector<MeshIn> meshes{{nelem, in.p, 2}};
+    DevBuf<double> yd(ctx, nelem);
+    RunOut r = run_rsb(meshes, nv, *opts, ctx, nullptr, stats_out, yd.get());
+    int status = r.status;
+    if (r.flip) {
+      k_negate<<<(unsigned)((nelem + 255) / 256), 256, 0, ctx.stream>>>(yd.get(), nelem);
+      RSB_LAUNCHED();
+    }
+    copy_out(ctx, fiedler_out, yd.get(), nelem, dev);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    *lambda2_out = r.lambda;
+    return status;
+  });
+}
+
+int rsb_partition(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts,
+                  const rsb_opts *opts, int32_t *part_out, rsb_stats *stats_out) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    check_mesh(nelem, nv, ids);
+    check_stats(stats_out);
+    if (nparts < 1 || nparts > nelem) fail(RSB_EINVAL, "nparts must be in [1, nelem]");
+    if (!part_out) fail(RSB_EINVAL, "part_out is NULL");
+    Ctx ctx;
+    setup_ctx(ctx, *opts);
+    const bool dev = opts->device_pointers != 0;
+    InArr<int64_t> in;
+    in.init(ctx, ids, nelem * nv, dev);
+    DevBuf<int32_t> own;
+    int32_t *dpart = part_out;
+    if (!dev) {
+      own.alloc(ctx, nelem);
+      dpart = own.get();
+    }
+    std::vector<MeshIn> meshes{{nelem, in.p, nparts}};
+    RunOut r = run_rsb(meshes, nv, *opts, ctx, dpart, stats_out, nullptr);
+    if (!dev) copy_out(ctx, part_out, (const int32_t *)dpart, nelem, false);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    return r.status;
+  });
+}
+
+int rsb_partition_batch(int32_t nmesh, const int64_t *nelem, int32_t nv,
+                        const int64_t *const *ids, const int32_t *nparts, const rsb_opts *opts,
+                        int32_t *const *part_out, rsb_stats *stats_out) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    check_stats(stats_out);
+    if (nmesh < 1 || !nelem || !ids || !nparts || !part_out) fail(RSB_EINVAL, "bad arguments");
+    int64_t total = 0;
+    for (int b = 0; b < nmesh; ++b) {
+      check_mesh(nelem[b], nv, ids[b]);
+      if (nparts[b] < 1 || nparts[b] > nelem[b]) fail(RSB_EINVAL, "nparts out of range");
+      if (!part_out[b]) fail(RSB_EINVAL, "part_out entry NULL");
+      total += nelem[b];
+    }
+    if (total >= kMaxRows) fail(RSB_EINVAL, "too many elements (limit 2^28 per call)");
+    Ctx ctx;
+    setup_ctx(ctx, *opts);
+    const bool dev = opts->device_pointers != 0;
+    std::vector<InArr<int64_t>> in(nmesh);
+    std::vector<MeshIn> meshes;
+    for (int b = 0; b < nmesh; ++b) {
+      in[b].init(ctx, ids[b], nelem[b] * nv, dev);
+      meshes.push_back({nelem[b], in[b].p, nparts[b]});
+    }
+    DevBuf<int32_t> dpart(ctx, total);
+    RunOut r = run_rsb(meshes, nv, *opts, ctx, dpart.get(), stats_out, nullptr);
+    int64_t off = 0;
+    for (int b = 0; b < nmesh; ++b) {
+      copy_out(ctx, part_out[b], (const int32_t *)dpart.get() + off, nelem[b], dev);
+      off += nelem[b];
+    }
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    return r.status;
+  });
+}
+
+}  // extern "C"

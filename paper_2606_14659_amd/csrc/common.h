@@ -1,0 +1,165 @@
+// common.h -- shared host/device helpers of the gfx950 RSB library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/rsb.h"
+
+namespace rsb {
+
+constexpr int kWave = 64;    // CDNA wavefront width
+constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
+constexpr int kMaxM = 250;   // largest Lanczos cycle length
+constexpr int kGroup = 32;   // blocks per first-level reduction group
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws, the C entry points convert to return codes.
+// ---------------------------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] inline void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+#define RSB_HIP(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      ::rsb::fail(e_ == hipErrorOutOfMemory ? RSB_ENOMEM : RSB_EDEVICE,                      \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                        \
+  } while (0)
+
+#define RSB_LAUNCHED()                                                                       \
+  do {                                                                                       \
+    hipError_t e_ = hipGetLastError();                                                       \
+    if (e_ != hipSuccess)                                                                    \
+      ::rsb::fail(RSB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e_));      \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory from the stream-ordered pool, freed when the owner dies.
+// ---------------------------------------------------------------------------
+struct Ctx {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;  // created for a call that passed the null stream
+  int device = 0;
+  int64_t limit = 0;  // 0 = unlimited
+  int64_t in_use = 0;
+  int64_t peak = 0;
+  int verbose = 0;
+  Ctx() = default;
+  Ctx(const Ctx &) = delete;
+  Ctx &operator=(const Ctx &) = delete;
+  ~Ctx() {
+    if (own_stream && stream) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipStreamDestroy(stream);
+    }
+  }
+};
+
+template <typename T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  Ctx *ctx = nullptr;
+  DevBuf() = default;
+  DevBuf(Ctx &c, size_t count) { alloc(c, count); }
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), ctx(o.ctx) { o.p = nullptr; o.n = 0; }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p; n = o.n; ctx = o.ctx;
+      o.p = nullptr; o.n = 0;
+    }
+    return *this;
+  }
+  void alloc(Ctx &c, size_t count) {
+    release();
+    ctx = &c;
+    n = count;
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (c.limit > 0 && c.in_use + (int64_t)bytes > c.limit)
+      fail(RSB_ENOMEM, "device_mem_limit exceeded: need " + std::to_string(c.in_use + bytes) +
+                           " bytes, limit " + std::to_string(c.limit));
+    hipError_t e = hipMallocAsync((void **)&p, bytes, c.stream);
+    if (e != hipSuccess) {
+      p = nullptr;
+      fail(e == hipErrorOutOfMemory ? RSB_ENOMEM : RSB_EDEVICE,
+           std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    }
+    c.in_use += bytes;
+    c.peak = std::max(c.peak, c.in_use);
+  }
+  void release() {
+    if (p) {
+      (void)hipFreeAsync(p, ctx->stream);
+      ctx->in_use -= std::max<size_t>(n, 1) * sizeof(T);
+      p = nullptr;
+    }
+    n = 0;
+  }
+  ~DevBuf() { release(); }
+  T *get() const { return p; }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+// ---------------------------------------------------------------------------
+// Packed column word of the sliced-ELL Laplacian: (column << 4) | weight.
+// Weight 0 marks a padding slot; padding words are 0 (column 0, weight 0).
+// ---------------------------------------------------------------------------
+constexpr int kColShift = 4;
+constexpr uint32_t kWeightMask = 15u;
+constexpr int64_t kMaxRows = int64_t(1) << 28;
+
+__host__ __device__ inline uint32_t pack_colw(uint32_t col, uint32_t w) {
+  return (col << kColShift) | w;
+}
+__host__ __device__ inline uint32_t colw_col(uint32_t word) { return word >> kColShift; }
+__host__ __device__ inline uint32_t colw_wt(uint32_t word) { return word & kWeightMask; }
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Workgroup ids are dispatched round-robin over the 8 XCDs of the chip.
+// Map them so that each XCD works on one contiguous range of logical blocks
+// (its L2 then sees one contiguous slice of rows and their neighbours).
+__device__ inline int xcd_block(int b, int nb) {
+  int x = b & 7, i = b >> 3;
+  int q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ inline int wave_sum_i(int v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum of NV values over a 256-thread block; result valid in thread t < NV
+// for value t (returned), fixed summation order.
+template <int NV>
+__device__ inline void block_sum_multi(double (&v)[NV], double *lds /* [4*NV] */) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[wave * NV + k] = v[k];
+  }
+  __syncthreads();
+}
+
+}  // namespace rsb

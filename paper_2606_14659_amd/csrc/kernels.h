@@ -1,0 +1,186 @@
+// kernels.h -- internal interfaces between the library's translation units.
+#pragma once
+#include "common.h"
+
+namespace rsb {
+
+// ---------------------------------------------------------------------------
+// Plain CSR on the device (output of the dual-graph builder).
+// ---------------------------------------------------------------------------
+struct DevCsr {
+  int64_t n = 0, nnz = 0;
+  DevBuf<int64_t> row_ptr;
+  DevBuf<int32_t> col;
+  DevBuf<int32_t> wgt;
+};
+
+void scan_exclusive(const int64_t *in, int64_t n, int64_t *out, int64_t *total, Ctx &ctx);
+void scan_exclusive(const int32_t *in, int64_t n, int64_t *out, int64_t *total, Ctx &ctx);
+void fill_i32(int32_t *p, int64_t n, int32_t v, Ctx &ctx);
+
+// Dual graph of nelem elements with nv vertex ids each (device ids).
+void build_dual_graph(const int64_t *d_ids, int64_t nelem, int nv, int graph, DevCsr &out,
+                      Ctx &ctx);
+
+// ---------------------------------------------------------------------------
+// A bisection level: all segments (subgraphs still to be split) side by side.
+//
+// Rows of a level are the elements of all segments, each segment starting at a
+// multiple of 64 and padded to a multiple of 64 with empty rows.  The
+// Laplacian is stored as sliced ELL with slices of 64 rows: slice c holds
+// `width_c` slot columns, slot k of row r at cols[chunk_ptr[c] + 64 k + r%64]
+// as a packed (column, weight) word; unused slots are 0.  Columns are level
+// row indices; cut edges to other segments are absent (induced subgraphs).
+// ---------------------------------------------------------------------------
+struct SegDev {
+  int64_t row0;   // first row
+  int32_t n;      // elements
+  int32_t npad;   // rows (n rounded up to 64)
+  int32_t P;      // parts this segment is divided into
+  int32_t p0;     // first part id
+  int32_t nlow;   // elements of the low child: floor(n * floor(P/2) / P)
+  int32_t blk0, nblk, grp0, ngrp;
+  int32_t mesh;   // input mesh of the segment
+};
+
+struct BlkDev {
+  int64_t row0;   // first row of the tile
+  int32_t nrows;  // rows in the tile (multiple of 64)
+  int32_t seg;
+  int32_t grp;
+  int32_t pad;
+};
+
+struct GrpDev {
+  int32_t seg, blk0, nblk, pad;
+};
+
+// Per-segment scalars of the eigen-solver (device resident).
+struct SegState {
+  double c, s;          // input vector transform: q = (w - c u0) * s
+  double theta;         // Ritz value of the last cycle
+  double tnorm;         // running estimate of ||T||
+  double lq2;           // ||L q_j||^2 of the current step
+  double alpha_tmp;     // alpha before the second Gram-Schmidt pass
+  double res;           // residual norm of the last Ritz pair
+  double rho;           // Rayleigh quotient of the last Ritz vector
+  double invsqrt_nc;    // 1/sqrt(size of the solved component)
+  int32_t k;            // Lanczos steps in the current cycle
+  int32_t active;       // still iterating
+  int32_t cycle_done;   // current cycle ended (length m or breakdown)
+  int32_t need2;        // second Gram-Schmidt pass pending
+  int32_t converged;    // tolerance met
+  int32_t restarts;     // cycles run after the first
+  int32_t strad;        // root row of the component being cut (-1: none)
+  int32_t ncomp;        // components in the segment
+  int32_t nlow2;        // low-side count inside the cut component
+  int32_t solve;        // 1 if this segment has a component to cut
+  int32_t flip;         // sign flip of the final vector
+  int32_t first;        // row of the sign-deciding element
+  int64_t steps;        // Lanczos steps run (all cycles)
+  int32_t cycles;       // cycles run
+  int32_t pad;
+};
+
+struct Level {
+  int64_t nrows = 0;     // padded rows
+  int64_t nchunks = 0;   // nrows / 64
+  int32_t nseg = 0;
+  int32_t nblk = 0, ngrp = 0;
+  int32_t rpt = 16;      // rows per thread of the streaming kernels (tile = 256 rpt)
+  std::vector<SegDev> seg;
+  std::vector<BlkDev> blk;
+  std::vector<GrpDev> grp;
+  DevBuf<SegDev> d_seg;
+  DevBuf<BlkDev> d_blk;
+  DevBuf<GrpDev> d_grp;
+  DevBuf<int64_t> chunk_ptr;   // [nchunks + 1] word offsets
+  DevBuf<uint32_t> cols;       // packed words
+  DevBuf<int32_t> orig;        // row -> index in the concatenated input (-1: pad)
+  DevBuf<int32_t> gid;         // row -> element id within its mesh
+  int64_t words = 0;
+};
+
+// Fill host block/group tables of a level from its segment table and
+// upload all three tables.
+void level_tables(Level &L, int rpt, Ctx &ctx);
+
+// Level 0 from per-mesh CSR graphs (segments in mesh order).
+void level0_from_csr(Level &L, const std::vector<const DevCsr *> &g,
+                     const std::vector<int32_t> &nparts, int rpt, Ctx &ctx);
+
+// ---------------------------------------------------------------------------
+// Eigen-solver buffers for one level and one vector precision.
+// ---------------------------------------------------------------------------
+struct SolveDev {
+  DevBuf<SegState> st;
+  DevBuf<double> alpha, beta, h, tvec;   // [nseg][pstride]
+  DevBuf<double> part, gpart;            // [nblk][pstride], [ngrp][pstride]
+  DevBuf<unsigned> gcnt, scnt;           // counters (zero between launches)
+  DevBuf<int32_t> n_active;              // [4]: active count, stats
+  DevBuf<int64_t> counters;              // [4]: segment steps
+  int pstride = 0;
+  int m = 0;
+};
+
+struct CompDev {
+  DevBuf<int32_t> root;    // component root row of every row
+  DevBuf<int32_t> size;    // component size at the root row
+  DevBuf<int64_t> pre;     // exclusive prefix of sizes within a segment (at roots)
+};
+
+// Components of every segment and the part of each segment to cut.
+void components_and_targets(Level &L, CompDev &C, SolveDev &S, Ctx &ctx);
+
+// Lanczos solve of every segment with a component to cut.  Precision T of
+// the vectors; FP64 scalars.  Result: y64[row] (unit norm on the component,
+// zero elsewhere in the segment).  Returns the number of level-steps run.
+struct LanczosParams {
+  int m;
+  int max_restarts;
+  double tol;
+  int phase32;        // FP32 phase of mixed precision (floor-aware stop)
+  int use_graph;
+  uint64_t seed;
+};
+// basis: (m + 3) * L.nrows values of T (u0, q_1..q_m, two work vectors).
+// y32_in: the FP32 phase's basis buffer (mixed precision refinement start),
+// S32 its solver state; both null for a random start.
+void solve_alloc(SolveDev &S, const Level &L, int m, Ctx &ctx);
+template <typename T>
+int64_t lanczos_level(Level &L, CompDev &C, SolveDev &S, const LanczosParams &p,
+                      const float *y32_in, const SolveDev *S32, T *basis, double *y64_out,
+                      Ctx &ctx);
+
+// Inverse iteration with CG on every segment with a component to cut.
+struct InverseParams {
+  int max_outer;
+  int cg_max_iter;
+  double cg_tol;
+  double tol;
+  uint64_t seed;
+};
+int64_t inverse_level(Level &L, CompDev &C, SolveDev &S, const InverseParams &p,
+                      double *y64_out, Ctx &ctx);
+
+// Sign rule, radix select and side assignment.  side[row]: 0 low, 1 high,
+// 2 padding.
+void split_level(Level &L, CompDev &C, SolveDev &S, const double *y64, uint8_t *side, Ctx &ctx);
+
+// Split of a single vector with given gids (test entry point).
+void split_vector(const double *d_y, const int64_t *d_gid, int64_t n, int64_t n_low,
+                  uint8_t *d_side, Ctx &ctx);
+
+// Next level from the sides; leaves write part ids into part_out (indexed
+// by orig).  Returns the new level (possibly empty).
+void compact_level(Level &L, const uint8_t *side, int32_t *d_part_out, Level &next, int rpt,
+                   Ctx &ctx);
+
+// y = L x on a plain CSR (FP64), through the sliced-ELL kernel.
+void laplacian_apply_csr(const DevCsr &g, const double *d_x, double *d_y, Ctx &ctx);
+
+// Edge cut and neighbour counts of a partition on the level-0 graph.
+void partition_metrics(Level &L0, const int32_t *d_part, int32_t nparts_total,
+                       const std::vector<int32_t> &part_offset, rsb_stats *st, Ctx &ctx);
+
+}  // namespace rsb

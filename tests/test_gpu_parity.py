@@ -1,0 +1,168 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle.
+
+Integer results (dual graph, split given a vector, partitions on boxes with a
+unique longest axis) must be bit-exact; the Fiedler value within 1e-8
+relative in FP64 and 1e-5 with FP32 vectors (mixed precision); edge cuts on
+meshes with holes within 1%.
+"""
+import numpy as np
+import pytest
+
+import meshgen as mg
+import paper_2606_14659_amd as rsb
+
+pytestmark = pytest.mark.gpu
+
+
+def _meshes():
+    out = {
+        "paper": np.array([[1, 2, 3, 4], [2, 5, 4, 6], [3, 4, 7, 8]], dtype=np.int64),
+        "box5x4x3": mg.box_hex(5, 4, 3).ids,
+        "cube16": mg.cube16().ids,
+        "holes": mg.uniform_holes(mg.box_hex(23, 17, 9), 0.07, 3).ids,
+        "quad": mg.uniform_holes(mg.box_quad(40, 33), 0.1, 4).ids,
+        "renum": mg.shuffle_elements(mg.renumber_vertices(
+            mg.uniform_holes(mg.box_hex(19, 11, 13), 0.05, 6), 7), 8).ids,
+        "collapsed": np.array([[1, 2, 3, 4], [4, 4, 5, 6], [3, 4, 7, 8]], dtype=np.int64),
+        "clustered": mg.clustered_holes(mg.box_hex(30, 26, 22), 0.1, 9).ids,
+    }
+    return out
+
+
+MESHES = _meshes()
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("graph", ["weighted", "unit", "face"])
+def test_dual_graph_bit_exact(orc, name, graph):
+    ids = MESHES[name]
+    print(f"dual graph {name} {graph} n={len(ids)}", flush=True)
+    rp, col, w = rsb.dual_graph(ids, graph=graph)
+    orp, ocol, ow = orc.dual_graph(ids, graph=graph)
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(col, ocol)
+    assert np.array_equal(w, ow)
+
+
+def test_dual_graph_device_arrays(orc):
+    import torch
+    ids = MESHES["holes"]
+    rp, col, w = rsb.dual_graph(torch.as_tensor(ids).cuda(), device=True)
+    orp, ocol, ow = orc.dual_graph(ids)
+    assert np.array_equal(rp.cpu().numpy(), orp)
+    assert np.array_equal(col.cpu().numpy(), ocol)
+    assert np.array_equal(w.cpu().numpy(), ow)
+
+
+@pytest.mark.parametrize("name", ["holes", "quad", "renum", "cube16"])
+def test_laplacian_apply(orc, name):
+    ids = MESHES[name]
+    rp, col, w = orc.dual_graph(ids)
+    x = np.random.default_rng(1).standard_normal(len(ids))
+    y = rsb.laplacian_apply(rp, col, w, x)
+    oy = orc.laplacian_apply(rp, col, w, x)
+    scale = np.abs(x).max() * max(1, w.max()) * 27
+    assert np.max(np.abs(y - oy)) <= 1e-13 * scale
+
+
+def test_split_bit_exact(orc):
+    rng = np.random.default_rng(5)
+    for trial in range(12):
+        n = int(rng.integers(1, 5000)) if trial else 1
+        vals = np.array([-1.5, -0.0, 0.0, 2.0, 1e-300, -1e-300, 7.0])
+        y = rng.choice(vals, size=n) if trial % 2 else rng.standard_normal(n)
+        gid = rng.permutation(3 * n)[:n].astype(np.int64)
+        for n_low in sorted({0, n, n // 2, int(rng.integers(0, n + 1))}):
+            side = rsb.split(y, gid, n_low)
+            oside = orc.split(y, gid, n_low)
+            assert np.array_equal(side, oside), (trial, n, n_low)
+
+
+@pytest.mark.parametrize("name", ["paper", "box5x4x3", "holes", "quad", "renum"])
+def test_fiedler_fp64(orc, name):
+    ids = MESHES[name]
+    print(f"fiedler fp64 {name}", flush=True)
+    st, lam, y, stats = rsb.fiedler(ids, tol=1e-9)
+    ost, olam, oy, oinfo = orc.fiedler(ids, tol=1e-9)
+    assert st == ost
+    assert abs(lam - olam) <= 1e-8 * olam
+    assert abs(np.linalg.norm(y) - 1) < 1e-10
+    assert abs(y.sum()) < 1e-9 * np.sqrt(len(y))
+    assert abs(abs(float(y @ oy)) - 1) < 1e-6
+
+
+def test_fiedler_face_cube_closed_form():
+    ids = MESHES["cube16"]
+    st, lam, y, stats = rsb.fiedler(ids, graph="face", tol=1e-10, lanczos_m=100)
+    assert st == 0
+    exact = 2 - 2 * np.cos(np.pi / 16)
+    assert abs(lam - exact) <= 1e-10 * exact
+
+
+@pytest.mark.parametrize("name", ["box5x4x3", "holes", "renum"])
+def test_fiedler_mixed(orc, name):
+    ids = MESHES[name]
+    st, lam, y, stats = rsb.fiedler(ids, precision="mixed", tol=1e-8)
+    ost, olam, oy, _ = orc.fiedler(ids, tol=1e-10)
+    assert st == ost
+    assert abs(lam - olam) <= 1e-5 * olam
+
+
+@pytest.mark.parametrize("dims,graph,nparts", [((24, 20, 18), "face", 8),
+                                              ((48, 40, 36), "weighted", 8),
+                                              ((24, 20, 18), "weighted", 4),
+                                              ((30, 14, 9), "face", 6)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_partition_identical_on_boxes(orc, dims, graph, nparts, precision):
+    mesh = mg.box_hex(*dims)
+    print(f"partition {dims} {graph} {nparts} {precision}", flush=True)
+    st, part, stats = rsb.partition(mesh.ids, nparts, graph=graph, precision=precision, tol=1e-8)
+    ost, opart, _ = orc.partition(mesh.ids, nparts, graph=graph, tol=1e-8)
+    assert st == ost == 0
+    assert np.array_equal(part, opart)
+    met = orc.metrics(mesh.ids, part, nparts)
+    assert stats["edge_cut"] == met["weighted_cut"]
+    assert stats["cut_pairs"] == met["cut_pairs"]
+    assert stats["max_neighbors"] == met["max_neighbors"]
+    assert abs(stats["avg_neighbors"] - met["avg_neighbors"]) < 1e-12
+
+
+@pytest.mark.parametrize("name,nparts", [("holes", 16), ("renum", 8), ("clustered", 32),
+                                         ("quad", 10)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_partition_cut_within_one_percent(orc, name, nparts, precision):
+    ids = MESHES[name]
+    print(f"partition {name} {nparts} {precision}", flush=True)
+    st, part, stats = rsb.partition(ids, nparts, precision=precision, tol=1e-8)
+    ost, opart, _ = orc.partition(ids, nparts, tol=1e-8)
+    assert st >= 0
+    sizes = np.bincount(part, minlength=nparts)
+    assert sizes.min() >= len(ids) // nparts and sizes.max() <= -(-len(ids) // nparts)
+    assert np.array_equal(np.sort(sizes), np.sort(np.bincount(opart, minlength=nparts)))
+    cut = orc.metrics(ids, part, nparts)["weighted_cut"]
+    ocut = orc.metrics(ids, opart, nparts)["weighted_cut"]
+    assert abs(cut - ocut) <= 0.01 * ocut
+
+
+def test_disconnected_rule(orc):
+    a = mg.box_hex(4, 3, 3)
+    b = mg.box_hex(3, 3, 2)
+    ids = np.concatenate([a.ids, b.ids + 10_000])
+    for nparts in (2, 3, 5):
+        st, part, _ = rsb.partition(ids, nparts)
+        ost, opart, _ = orc.partition(ids, nparts)
+        assert st == ost == 2
+        assert np.array_equal(part, opart)
+    ids2 = np.concatenate([b.ids, b.ids + 10_000])
+    st, lam, y, _ = rsb.fiedler(ids2)
+    ost, olam, oy, _ = orc.fiedler(ids2)
+    assert st == ost == 2 and lam == 0.0 and np.all(y == 0)
+
+
+def test_batch_equals_single_calls():
+    meshes = mg.batch64(seed=77, count=6, smin=2e3, smax=2e4)
+    nparts = [4, 7, 16, 1, 3, 8]
+    st, parts, stats = rsb.partition_batch([m.ids for m in meshes], nparts)
+    for m, p, q in zip(meshes, nparts, parts):
+        s1, part1, _ = rsb.partition(m.ids, p)
+        assert np.array_equal(part1, q)

@@ -1,0 +1,97 @@
+"""CPU-side checks of the GPU library: it loads, exports every function that
+include/rsb.h declares, and its host-side argument checks reject bad input
+(no kernel runs in any of these)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2606_14659_amd as rsb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rsb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for need in ("rsb_opts_init", "rsb_partition", "rsb_fiedler", "rsb_dual_graph",
+                 "rsb_partition_batch", "rsb_strerror", "rsb_last_error", "rsb_split",
+                 "rsb_laplacian_apply"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.CDLL(rsb.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) == set(rsb._SIGNATURES)
+
+
+def test_struct_sizes_match():
+    o = rsb.Opts()
+    assert rsb.lib().rsb_opts_init(C.byref(o)) == 0
+    assert o.struct_size == C.sizeof(rsb.Opts)
+    assert o.lanczos_m == 100 and o.max_restarts == 50 and o.seed == 20261203
+    assert rsb.lib().rsb_opts_init(None) == rsb.EINVAL
+
+
+def test_strerror():
+    for code in (0, 1, 2, -1, -2, -3, -4, -5):
+        assert rsb.lib().rsb_strerror(code)
+    assert rsb.lib().rsb_strerror(99) == b"unknown code"
+
+
+def test_bad_options_rejected_before_any_device_call():
+    ids = np.array([[0, 1, 2, 3], [2, 3, 4, 5]], dtype=np.int64)
+    o = rsb.Opts()
+    rsb.lib().rsb_opts_init(C.byref(o))
+    bad = []
+    for field, value in (("struct_size", 4), ("graph", 7), ("lanczos_m", 0), ("lanczos_m", 251),
+                         ("tol", 0.0), ("cg_full_projection", 1), ("precision", 5)):
+        oo = rsb.Opts.from_buffer_copy(o)
+        setattr(oo, field, value)
+        part = np.zeros(2, dtype=np.int32)
+        code = rsb.lib().rsb_partition(2, 4, ids.ctypes.data_as(C.c_void_p), 2, C.byref(oo),
+                                       part.ctypes.data_as(C.c_void_p), None)
+        bad.append(code)
+        assert rsb.lib().rsb_last_error()
+    assert all(c == rsb.EINVAL for c in bad), bad
+
+
+def test_bad_arguments_rejected():
+    ids = np.array([[0, 1, 2, 3], [2, 3, 4, 5]], dtype=np.int64)
+    o = rsb.make_opts()
+    part = np.zeros(2, dtype=np.int32)
+    P = lambda a: a.ctypes.data_as(C.c_void_p)
+    L = rsb.lib()
+    assert L.rsb_partition(2, 4, None, 2, C.byref(o), P(part), None) == rsb.EINVAL
+    assert L.rsb_partition(0, 4, P(ids), 1, C.byref(o), P(part), None) == rsb.EINVAL
+    assert L.rsb_partition(2, 0, P(ids), 1, C.byref(o), P(part), None) == rsb.EINVAL
+    assert L.rsb_partition(2, 4, P(ids), 3, C.byref(o), P(part), None) == rsb.EINVAL
+    assert L.rsb_partition(2, 4, P(ids), 0, C.byref(o), P(part), None) == rsb.EINVAL
+    st = rsb.Stats()
+    st.struct_size = 3
+    assert L.rsb_partition(2, 4, P(ids), 2, C.byref(o), P(part), C.byref(st)) == rsb.EINVAL
+    y = np.array([0.0, np.nan])
+    g = np.array([0, 1], dtype=np.int64)
+    side = np.zeros(2, dtype=np.uint8)
+    assert L.rsb_split(2, P(y), P(g), 1, P(side), C.byref(o)) == rsb.EINVAL
+    y = np.array([0.0, 1.0])
+    assert L.rsb_split(2, P(y), P(g), 3, P(side), C.byref(o)) == rsb.EINVAL
+    assert L.rsb_fiedler(1, 4, P(ids), C.byref(o), P(y), C.byref(C.c_double()), None) == rsb.EINVAL
+    nnz = C.c_int64(0)
+    assert L.rsb_dual_graph(2, 4, P(ids), C.byref(o), None, None, None, None) == rsb.EINVAL
+
+
+def test_python_binding_raises_without_library(monkeypatch):
+    monkeypatch.setattr(rsb, "_lib", None)
+    monkeypatch.setattr(rsb, "LIB_PATH", "/nonexistent/librsb.so")
+    with pytest.raises(RuntimeError):
+        rsb.lib()
