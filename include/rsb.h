@@ -59,8 +59,13 @@ extern "C" {
 #define RSB_INVERSE_CG 1 /* inverse iteration, CG inner solves (Sec. 7, Alg. 2) */
 
 #define RSB_FP64 0  /* all vectors and arithmetic in FP64 */
-#define RSB_MIXED 1 /* FP32 vectors and SpMV; FP64 coefficients, projections,
-                       tridiagonal solve; then FP64 refinement of the pair */
+#define RSB_MIXED 1 /* Lanczos directions q_2..q_m and their SpMV in FP32 (FP32
+                       accumulation); in FP64: the restart (Ritz) vector and the
+                       first Lanczos vector of every cycle, residuals, alpha,
+                       beta, reorthogonalisation projections and the
+                       tridiagonal solve.  Each restart refines the FP64 Ritz
+                       vector by an FP32 correction, so the pair converges to
+                       the FP64 tolerance. */
 
 typedef struct rsb_opts {
   int32_t struct_size;      /* sizeof(rsb_opts); set by rsb_opts_init */
@@ -69,10 +74,8 @@ typedef struct rsb_opts {
   int32_t precision;        /* RSB_FP64 or RSB_MIXED */
   int32_t lanczos_m;        /* Lanczos steps per cycle (default 100, max 250) */
   int32_t max_restarts;     /* restarts after the first cycle (default 50) */
-  double tol;               /* converged when ||L y - theta y||_2 <= tol * theta */
-  int32_t refine_m;         /* MIXED: steps per FP64 refinement cycle (20) */
-  int32_t refine_max_restarts; /* MIXED: FP64 refinement cycles - 1 (50) */
-  double tol_fp32;          /* MIXED: tolerance that ends the FP32 phase (1e-2) */
+  double tol;               /* converged when ||L y - rho y||_2 <= tol * rho, rho =
+                               y^T L y / y^T y of the Ritz vector y (default 1e-6) */
   int32_t inv_max_outer;    /* INVERSE_CG: outer iterations cap (50) */
   int32_t cg_max_iter;      /* INVERSE_CG: CG steps per solve cap (20000) */
   double cg_tol;            /* INVERSE_CG: CG stops at ||r|| <= cg_tol ||b|| (1e-8) */
@@ -87,8 +90,12 @@ typedef struct rsb_opts {
   int32_t device_pointers;  /* 0: host arrays; 1: device arrays */
   void *stream;             /* hipStream_t, NULL for the null stream */
   int64_t device_mem_limit; /* 0: no limit; else bytes of scratch allowed */
-  int32_t verbose;          /* 1: one line per level on stderr */
-  int32_t reserved[8];
+  int32_t verbose;          /* 1: one line per level on stderr; 2: also per segment */
+  int32_t profile;          /* 1: time every launch of the SpMV-and-projection
+                               kernel of Lanczos steps j >= 3 with HIP events
+                               (cycles are then launched directly, not replayed
+                               as graphs); results in rsb_stats.kernel_* */
+  int32_t reserved[7];
 } rsb_opts;
 
 typedef struct rsb_stats {
@@ -98,7 +105,7 @@ typedef struct rsb_stats {
                                 segments of a level */
   int64_t segment_steps;     /* the same counted per segment */
   int64_t cycles;            /* Lanczos cycles summed over levels */
-  int64_t refine_steps;      /* MIXED: FP64 refinement steps (level-steps) */
+  int64_t spmv_fp64;         /* SpMVs run with FP64 vectors (level launches) */
   int32_t not_converged;     /* segments that hit the iteration caps */
   int32_t disconnected;      /* bisections of disconnected graphs */
   double lambda2;            /* rsb_fiedler: Rayleigh quotient of the output */
@@ -107,15 +114,23 @@ typedef struct rsb_stats {
   double ms_solve;           /* eigen-solves */
   double ms_split;           /* components, split and compaction */
   double ms_total;           /* whole call, host wall clock */
-  double edge_cut;           /* rsb_partition: weighted edge cut of the result */
+  /* Partition quality, measured on the dual graph selected by opts->graph
+   * (with the default vertex-shared graph, neighbours are the parts that
+   * share at least one mesh vertex, as in the paper's Sec. 8 tables). */
+  double edge_cut;           /* rsb_partition: sum of the weights of cut edges */
   int64_t cut_pairs;         /* rsb_partition: adjacent element pairs cut */
-  int32_t max_neighbors;     /* rsb_partition: max parts sharing a vertex with a part
-                                (-1 when nparts > 16384) */
-  double avg_neighbors;      /* rsb_partition: mean of the same */
+  int32_t max_neighbors;     /* rsb_partition: max neighbour parts of a part
+                                (-1 when the total number of parts > 16384) */
+  double avg_neighbors;      /* rsb_partition: mean neighbour parts of a part */
   int64_t nnz;               /* off-diagonal nonzeros of the level-0 Laplacian */
-  double spmv_bytes;         /* algorithmic bytes moved by all SpMVs */
-  double ms_spmv_est;        /* reserved */
-  int32_t reserved[8];
+  /* opts->profile = 1: the SpMV-and-projection kernel of Lanczos steps j >= 3 */
+  double kernel_bytes;       /* algorithmic bytes of all its launches: per launch at
+                                step j over n rows with nnz off-diagonal entries,
+                                4 (n + 1) + 4 nnz + n (s_x + s_Lq + s_q + 16 +
+                                (j - 2) s_q), s_ = bytes per value */
+  double kernel_ms;          /* summed device time of its launches (HIP events) */
+  int64_t kernel_launches;   /* its launches */
+  int32_t reserved[6];
 } rsb_stats;
 
 /* Fills *o with the defaults listed above.  Returns RSB_OK or RSB_EINVAL (o NULL). */

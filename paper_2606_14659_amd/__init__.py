@@ -29,26 +29,25 @@ class Opts(C.Structure):
     _fields_ = [
         ("struct_size", C.c_int32), ("graph", C.c_int32), ("method", C.c_int32),
         ("precision", C.c_int32), ("lanczos_m", C.c_int32), ("max_restarts", C.c_int32),
-        ("tol", C.c_double), ("refine_m", C.c_int32), ("refine_max_restarts", C.c_int32),
-        ("tol_fp32", C.c_double), ("inv_max_outer", C.c_int32), ("cg_max_iter", C.c_int32),
+        ("tol", C.c_double), ("inv_max_outer", C.c_int32), ("cg_max_iter", C.c_int32),
         ("cg_tol", C.c_double), ("cg_full_projection", C.c_int32), ("batched", C.c_int32),
         ("seed", C.c_uint64), ("use_hipgraph", C.c_int32), ("autotune", C.c_int32),
         ("autotune_cache", C.c_char_p), ("device", C.c_int32), ("device_pointers", C.c_int32),
         ("stream", C.c_void_p), ("device_mem_limit", C.c_int64), ("verbose", C.c_int32),
-        ("reserved", C.c_int32 * 8),
+        ("profile", C.c_int32), ("reserved", C.c_int32 * 7),
     ]
 
 
 class Stats(C.Structure):
     _fields_ = [
         ("struct_size", C.c_int32), ("levels", C.c_int32), ("level_steps", C.c_int64),
-        ("segment_steps", C.c_int64), ("cycles", C.c_int64), ("refine_steps", C.c_int64),
+        ("segment_steps", C.c_int64), ("cycles", C.c_int64), ("spmv_fp64", C.c_int64),
         ("not_converged", C.c_int32), ("disconnected", C.c_int32), ("lambda2", C.c_double),
         ("residual", C.c_double), ("ms_graph", C.c_double), ("ms_solve", C.c_double),
         ("ms_split", C.c_double), ("ms_total", C.c_double), ("edge_cut", C.c_double),
         ("cut_pairs", C.c_int64), ("max_neighbors", C.c_int32), ("avg_neighbors", C.c_double),
-        ("nnz", C.c_int64), ("spmv_bytes", C.c_double), ("ms_spmv_est", C.c_double),
-        ("reserved", C.c_int32 * 8),
+        ("nnz", C.c_int64), ("kernel_bytes", C.c_double), ("kernel_ms", C.c_double),
+        ("kernel_launches", C.c_int64), ("reserved", C.c_int32 * 6),
     ]
 
     def as_dict(self):
@@ -82,6 +81,23 @@ _SIGNATURES = {
 }
 
 
+def _share_torch_hip_runtime():
+    """Load PyTorch's HIP runtime before librsb.so.
+
+    PyTorch-ROCm ships its own libamdhip64; two HIP runtimes in one process
+    cannot both open the GPU.  Loading torch's copy first makes the loader
+    resolve librsb.so's libamdhip64 dependency to it, so torch tensors and the
+    library share one runtime whichever is imported first.
+    """
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if not (spec and spec.origin):
+        return
+    path = os.path.join(os.path.dirname(spec.origin), "lib", "libamdhip64.so")
+    if os.path.exists(path):
+        C.CDLL(path, mode=C.RTLD_GLOBAL)
+
+
 def lib():
     """The loaded library (raises if it has not been built)."""
     global _lib
@@ -89,6 +105,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2606_14659_amd.build`")
+        _share_torch_hip_runtime()
         L = C.CDLL(LIB_PATH)
         for name, (args, res) in _SIGNATURES.items():
             f = getattr(L, name)

@@ -35,13 +35,35 @@ def _compile(src: str) -> str:
     return obj
 
 
+def hip_runtime_dir() -> str:
+    """Directory of the HIP runtime the process will use.
+
+    PyTorch-ROCm ships its own libamdhip64 / libhsa-runtime64; a second copy
+    of the runtime in the same process cannot open the GPU.  When torch is
+    installed, link against its copy (and find it there at run time) so that
+    the library and torch share one runtime; otherwise use /opt/rocm/lib.
+    """
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec and spec.origin:
+        d = os.path.join(os.path.dirname(spec.origin), "lib")
+        if os.path.exists(os.path.join(d, "libamdhip64.so")):
+            return d
+    return "/opt/rocm/lib"
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs]
+    rt = hip_runtime_dir()
+    clangxx = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "bin", "clang++")
+    if not os.path.exists(clangxx):
+        clangxx = "/opt/rocm/llvm/bin/clang++"
+    cmd = [clangxx, "-shared", "-fPIC", "-o", tmp, *objs, os.path.join(rt, "libamdhip64.so"),
+           f"-Wl,-rpath,{rt}", "-Wl,--no-undefined", "-Wl,--enable-new-dtags"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -43,9 +43,8 @@ void check_opts(const rsb_opts *o) {
   if (o->method < 0 || o->method > 1) fail(RSB_EINVAL, "method");
   if (o->precision < 0 || o->precision > 1) fail(RSB_EINVAL, "precision");
   if (o->lanczos_m < 1 || o->lanczos_m > kMaxM) fail(RSB_EINVAL, "lanczos_m must be in [1, 250]");
-  if (o->refine_m < 1 || o->refine_m > kMaxM) fail(RSB_EINVAL, "refine_m must be in [1, 250]");
-  if (o->max_restarts < 0 || o->refine_max_restarts < 0) fail(RSB_EINVAL, "negative restarts");
-  if (!(o->tol > 0) || !(o->tol_fp32 > 0) || !(o->cg_tol > 0)) fail(RSB_EINVAL, "tolerances");
+  if (o->max_restarts < 0) fail(RSB_EINVAL, "negative max_restarts");
+  if (!(o->tol > 0) || !(o->cg_tol > 0)) fail(RSB_EINVAL, "tolerances must be positive");
   if (o->inv_max_outer < 1 || o->cg_max_iter < 1) fail(RSB_EINVAL, "inverse iteration caps");
   if (o->cg_full_projection != 0) fail(RSB_EINVAL, "cg_full_projection is not supported");
   if (o->autotune < 0 || o->autotune > 2) fail(RSB_EINVAL, "autotune");
@@ -102,10 +101,10 @@ void copy_out(Ctx &ctx, T *dst, const T *dsrc, int64_t n, bool device) {
                          device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx.stream));
 }
 
+// Rows per thread of the streaming kernels (tile = 256 * rpt rows): large
+// tiles on big levels, small tiles when there are few rows.
 int pick_rpt(int64_t nrows) {
-  // rows per thread of the streaming kernels: enough blocks to fill 256 CUs
-  if (nrows >= (int64_t)8 * 256 * kBlock * 8) return 8;
-  if (nrows >= (int64_t)2 * 256 * kBlock * 4) return 4;
+  if (nrows >= (int64_t)4 * 256 * kBlock * 8) return 8;
   return 4;
 }
 
@@ -120,6 +119,81 @@ struct RunOut {
   int flip = 0;  // rsb_fiedler: the returned vector must be negated (sign rule)
   double lambda = 0.0, residual = 0.0;
 };
+
+// Tables of a single segment of a level (the per-subgraph reference mode).
+struct OneSeg {
+  DevBuf<SegDev> seg;
+  DevBuf<BlkDev> blk;
+  DevBuf<GrpDev> grp;
+  int nblk = 0, ngrp = 0;
+};
+
+void one_segment_tables(const Level &L, int s, OneSeg &o, Ctx &ctx) {
+  Level tmp;
+  tmp.seg.push_back(L.seg[s]);
+  tmp.nseg = 1;
+  tmp.nrows = L.nrows;
+  level_tables(tmp, L.rpt, ctx);
+  o.seg = std::move(tmp.d_seg);
+  o.blk = std::move(tmp.d_blk);
+  o.grp = std::move(tmp.d_grp);
+  o.nblk = tmp.nblk;
+  o.ngrp = tmp.ngrp;
+}
+
+// Eigen-solve of one level: all segments batched, or one segment at a time.
+int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, void *work,
+                    double *y64, KernelProfile *prof, Ctx &ctx) {
+  const bool mixed = o.precision == RSB_MIXED;
+  auto run = [&](const LevelView &v, SolveDev &SS, bool graph) -> int64_t {
+    if (o.method == RSB_INVERSE_CG) {
+      InverseParams ip{o.inv_max_outer, o.cg_max_iter, o.cg_tol, o.tol, o.seed};
+      return inverse_level(v, C, SS, ip, work, y64, graph, ctx);
+    }
+    LanczosParams lp{o.lanczos_m, o.max_restarts, o.tol, graph ? 1 : 0, o.seed, prof, v.nnz};
+    return mixed ? lanczos_level<float>(v, C, SS, lp, work, y64, ctx)
+                 : lanczos_level<double>(v, C, SS, lp, work, y64, ctx);
+  };
+  if (o.batched) return run(view_of(L), S, o.use_hipgraph != 0);
+  // reference mode: every subgraph with its own launches sized to it
+  std::vector<SegState> hs(L.nseg);
+  RSB_HIP(hipMemcpyAsync(hs.data(), S.st.get(), L.nseg * sizeof(SegState), hipMemcpyDeviceToHost,
+                         ctx.stream));
+  RSB_HIP(hipStreamSynchronize(ctx.stream));
+  int64_t steps = 0;
+  for (int s = 0; s < L.nseg; ++s) {
+    if (!hs[s].solve) continue;
+    OneSeg os;
+    one_segment_tables(L, s, os, ctx);
+    SolveDev S1;
+    solve_alloc(S1, 1, os.nblk, os.ngrp, std::max(o.lanczos_m, 1), ctx);
+    RSB_HIP(hipMemcpyAsync(S1.st.get(), S.st.get() + s, sizeof(SegState),
+                           hipMemcpyDeviceToDevice, ctx.stream));
+    LevelView v = view_of(L);
+    v.nseg = 1;
+    v.nblk = os.nblk;
+    v.seg = os.seg.get();
+    v.blk = os.blk.get();
+    v.grp = os.grp.get();
+    v.nnz = (int64_t)((double)L.nnz * L.seg[s].npad / std::max<int64_t>(L.nrows, 1));
+    steps += run(v, S1, false);
+    RSB_HIP(hipMemcpyAsync(S.st.get() + s, S1.st.get(), sizeof(SegState),
+                           hipMemcpyDeviceToDevice, ctx.stream));
+    int64_t c = 0;
+    RSB_HIP(hipMemcpyAsync(&c, S1.counters.get(), sizeof(int64_t), hipMemcpyDeviceToHost,
+                           ctx.stream));
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    int64_t acc = 0;
+    RSB_HIP(hipMemcpyAsync(&acc, S.counters.get(), sizeof(int64_t), hipMemcpyDeviceToHost,
+                           ctx.stream));
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    acc += c;
+    RSB_HIP(hipMemcpyAsync(S.counters.get(), &acc, sizeof(int64_t), hipMemcpyHostToDevice,
+                           ctx.stream));
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+  }
+  return steps;
+}
 
 // The whole hot path for a batch of meshes: graph, then level by level
 // components -> eigen-solve -> split -> compaction.  part: concatenated
@@ -140,8 +214,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
   }
   if (total >= kMaxRows) fail(RSB_EINVAL, "too many elements (limit 2^28 per call)");
   RSB_HIP(hipStreamSynchronize(ctx.stream));
-  const double t1 = now_ms();
-  st.ms_graph = t1 - t0;
+  st.ms_graph = now_ms() - t0;
   // 2. level 0
   std::vector<const DevCsr *> gp;
   std::vector<int32_t> np;
@@ -151,7 +224,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     np.push_back(fiedler_y ? 2 : meshes[b].nparts);
     parts_total += meshes[b].nparts;
   }
-  int rpt = pick_rpt(total);
+  const int rpt = pick_rpt(total);
   Level L0;
   level0_from_csr(L0, gp, np, rpt, ctx);
   for (auto &g : graphs) {
@@ -160,26 +233,23 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     g.row_ptr.release();
   }
   if (d_part) fill_i32(d_part, total, -1, ctx);
-  // meshes kept whole (one part)
-  {
+  {  // meshes kept whole (one part)
     int64_t off = 0;
     for (size_t b = 0; b < meshes.size(); ++b) {
       if (np[b] < 2 && d_part) fill_i32(d_part + off, meshes[b].nelem, 0, ctx);
       off += meshes[b].nelem;
     }
   }
-  // 3. buffers sized for the largest level
-  const int64_t cap_rows = round_up(total, kWave) + (int64_t)kWave * (parts_total + 2 * (int64_t)meshes.size());
-  const bool mixed = o.precision == RSB_MIXED && o.method == RSB_LANCZOS;
-  const int m64 = mixed ? o.refine_m : o.lanczos_m;
-  DevBuf<float> basis32;
-  DevBuf<double> basis64;
-  if (o.method == RSB_LANCZOS) {
-    if (mixed) basis32.alloc(ctx, (size_t)(o.lanczos_m + 3) * cap_rows);
-    basis64.alloc(ctx, (size_t)(m64 + 3) * cap_rows);
-  }
+  // 3. work space sized for the largest level
+  const int64_t cap_rows =
+      round_up(total, kWave) + (int64_t)kWave * (parts_total + 2 * (int64_t)meshes.size());
+  const size_t wbytes = (o.method == RSB_INVERSE_CG)
+                            ? inverse_workspace_bytes(cap_rows)
+                            : lanczos_workspace_bytes(cap_rows, o.lanczos_m, o.precision == RSB_MIXED);
+  DevBuf<char> work(ctx, wbytes);
   DevBuf<double> y64(ctx, cap_rows);
   DevBuf<uint8_t> side(ctx, cap_rows);
+  KernelProfile prof;
   Level LA, LB;
   Level *L = &L0;
   Level *next = &LA;
@@ -187,93 +257,85 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
   int worst = RSB_OK;
   while (L->nseg > 0) {
     const double ta = now_ms();
-    SolveDev S32, S64;
+    SolveDev S;
     CompDev C;
-    solve_alloc(S64, *L, std::max(m64, 1), ctx);
-    components_and_targets(*L, C, S64, ctx);
-    int64_t steps = 0, ref_steps = 0;
-    if (o.method == RSB_LANCZOS) {
-      LanczosParams p64{m64, mixed ? o.refine_max_restarts : o.max_restarts, o.tol, 0,
-                        o.use_hipgraph, o.seed};
-      if (mixed) {
-        solve_alloc(S32, *L, o.lanczos_m, ctx);
-        RSB_HIP(hipMemcpyAsync(S32.st.get(), S64.st.get(), L->nseg * sizeof(SegState),
-                               hipMemcpyDeviceToDevice, ctx.stream));
-        LanczosParams p32{o.lanczos_m, o.max_restarts, o.tol_fp32, 1, o.use_hipgraph, o.seed};
-        steps += lanczos_level<float>(*L, C, S32, p32, nullptr, nullptr, basis32.get(), nullptr,
-                                      ctx);
-        ref_steps = lanczos_level<double>(*L, C, S64, p64, basis32.get(), &S32, basis64.get(),
-                                          y64.get(), ctx);
-        steps += ref_steps;
-      } else {
-        steps += lanczos_level<double>(*L, C, S64, p64, nullptr, nullptr, basis64.get(),
-                                       y64.get(), ctx);
-      }
-    } else {
-      InverseParams ip{o.inv_max_outer, o.cg_max_iter, o.cg_tol, o.tol, o.seed};
-      steps += inverse_level(*L, C, S64, ip, y64.get(), ctx);
-    }
-    // per-segment outcome
+    solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), ctx);
+    components_and_targets(*L, C, S, ctx);
+    const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(),
+                                      o.profile ? &prof : nullptr, ctx);
     std::vector<SegState> hs(L->nseg);
-    RSB_HIP(hipMemcpyAsync(hs.data(), S64.st.get(), L->nseg * sizeof(SegState),
+    RSB_HIP(hipMemcpyAsync(hs.data(), S.st.get(), L->nseg * sizeof(SegState),
                            hipMemcpyDeviceToHost, ctx.stream));
-    int64_t segsteps[2] = {0, 0};
-    RSB_HIP(hipMemcpyAsync(segsteps, S64.counters.get(), sizeof(int64_t), hipMemcpyDeviceToHost,
+    int64_t segsteps = 0;
+    RSB_HIP(hipMemcpyAsync(&segsteps, S.counters.get(), sizeof(int64_t), hipMemcpyDeviceToHost,
                            ctx.stream));
-    if (mixed)
-      RSB_HIP(hipMemcpyAsync(segsteps + 1, S32.counters.get(), sizeof(int64_t),
-                             hipMemcpyDeviceToHost, ctx.stream));
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     const double tb = now_ms();
     st.ms_solve += tb - ta;
     st.level_steps += steps;
-    st.refine_steps += mixed ? ref_steps : 0;
-    st.segment_steps += segsteps[0] + segsteps[1];
-    int disc = 0, notconv = 0;
+    st.segment_steps += segsteps;
+    int disc = 0, notconv = 0, cyc = 0;
     for (auto &s : hs) {
       if (s.ncomp > 1) ++disc;
       if (s.solve && !s.converged) ++notconv;
       st.cycles += s.cycles;
+      cyc = std::max(cyc, s.cycles);
     }
+    // FP64 SpMV launches: all of them in FP64 mode; steps 1-2 and the
+    // residual of every cycle with FP32 directions
+    st.spmv_fp64 += (o.precision == RSB_MIXED && o.method == RSB_LANCZOS) ? 3 * (int64_t)cyc
+                                                                          : steps + cyc;
     st.disconnected += disc;
     st.not_converged += notconv;
     if (disc) worst = std::max(worst, RSB_WARN_DISCONNECTED);
     if (notconv && worst == RSB_OK) worst = RSB_WARN_NOT_CONVERGED;
+    if (ctx.verbose >= 2)
+      for (int i = 0; i < L->nseg; ++i)
+        fprintf(stderr,
+                "[rsb]   seg %d: n %d P %d ncomp %d solve %d conv %d cycles %d steps %lld "
+                "res %.3e rho %.12g theta %.12g\n",
+                i, L->seg[i].n, L->seg[i].P, hs[i].ncomp, hs[i].solve, hs[i].converged,
+                hs[i].cycles, (long long)hs[i].steps, hs[i].res, hs[i].rho, hs[i].theta);
     if (fiedler_y) {
       const SegState &s = hs[0];
       RSB_HIP(hipMemcpyAsync(fiedler_y, y64.get(), meshes[0].nelem * sizeof(double),
                              hipMemcpyDeviceToDevice, ctx.stream));
-      // canonical sign: computed by the split's sign rule
-      split_level(*L, C, S64, y64.get(), side.get(), ctx);
-      std::vector<SegState> hs2(1);
-      RSB_HIP(hipMemcpyAsync(hs2.data(), S64.st.get(), sizeof(SegState), hipMemcpyDeviceToHost,
+      // the sign rule is applied by the split's sign pass
+      split_level(*L, C, S, y64.get(), side.get(), ctx);
+      SegState s2;
+      RSB_HIP(hipMemcpyAsync(&s2, S.st.get(), sizeof(SegState), hipMemcpyDeviceToHost,
                              ctx.stream));
       RSB_HIP(hipStreamSynchronize(ctx.stream));
       out.lambda = s.solve ? s.rho : 0.0;
       out.residual = s.solve ? s.res : 0.0;
-      out.flip = hs2[0].flip;
+      out.flip = s2.flip;
       out.status = (s.ncomp > 1) ? RSB_WARN_DISCONNECTED
                                  : (s.solve && !s.converged ? RSB_WARN_NOT_CONVERGED : RSB_OK);
       st.lambda2 = out.lambda;
       st.residual = out.residual;
       st.levels = 1;
+      st.kernel_ms = prof.ms;
+      st.kernel_bytes = prof.bytes;
+      st.kernel_launches = prof.launches;
       st.ms_total = now_ms() - t0;
       if (stats) {
-        int32_t sz = stats->struct_size;
+        const int32_t sz = stats->struct_size;
         *stats = st;
         stats->struct_size = sz;
       }
       return out;
     }
-    split_level(*L, C, S64, y64.get(), side.get(), ctx);
+    split_level(*L, C, S, y64.get(), side.get(), ctx);
     compact_level(*L, side.get(), d_part, *next, rpt, ctx);
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     st.ms_split += now_ms() - tb;
     if (ctx.verbose)
-      fprintf(stderr, "[rsb] level %d: %d segments, %lld rows, %lld level-steps, %.1f ms solve\n",
-              level, L->nseg, (long long)L->nrows, (long long)steps, tb - ta);
+      fprintf(stderr,
+              "[rsb] level %d: %d segments, %lld rows, %lld level-steps, %.1f ms solve, "
+              "%.1f ms split\n",
+              level, L->nseg, (long long)L->nrows, (long long)steps, tb - ta, now_ms() - tb);
     ++level;
-    // advance: keep level 0 for the metrics
+    // advance; level 0 stays alive for the metrics
     Level *done = L;
     L = next;
     next = (done == &L0) ? &LB : done;
@@ -288,11 +350,14 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
       off += meshes[b].nparts;
     }
   }
-  if (stats && L0.nseg > 0) partition_metrics(L0, d_part, (int32_t)parts_total, poff, &st, ctx);
+  if (L0.nseg > 0) partition_metrics(L0, d_part, (int32_t)parts_total, poff, &st, ctx);
   RSB_HIP(hipStreamSynchronize(ctx.stream));
+  st.kernel_ms = prof.ms;
+  st.kernel_bytes = prof.bytes;
+  st.kernel_launches = prof.launches;
   st.ms_total = now_ms() - t0;
   if (stats) {
-    int32_t sz = stats->struct_size;
+    const int32_t sz = stats->struct_size;
     *stats = st;
     stats->struct_size = sz;
   }
@@ -303,6 +368,24 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
 __global__ void k_negate(double *y, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = -y[i];
+}
+
+// Device-side validation of a caller CSR (device pointers): columns in
+// range, weights in [0, 15], rows monotone.
+__global__ void k_check_csr(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                            const int32_t *__restrict__ w, int64_t n, int *__restrict__ bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t a = rp[i], b = rp[i + 1];
+  if (b < a || a < 0) {
+    atomicOr(bad, 1);
+    return;
+  }
+  for (int64_t p = a; p < b; ++p)
+    if (col[p] < 0 || col[p] >= n || w[p] < 0 || w[p] > (int32_t)kWeightMask) {
+      atomicOr(bad, 1);
+      return;
+    }
 }
 
 void check_mesh(int64_t nelem, int32_t nv, const int64_t *ids) {
@@ -335,9 +418,6 @@ int rsb_opts_init(rsb_opts *o) {
   o->lanczos_m = 100;
   o->max_restarts = 50;
   o->tol = 1e-6;
-  o->refine_m = 20;
-  o->refine_max_restarts = 50;
-  o->tol_fp32 = 1e-4;
   o->inv_max_outer = 50;
   o->cg_max_iter = 20000;
   o->cg_tol = 1e-8;
@@ -352,6 +432,7 @@ int rsb_opts_init(rsb_opts *o) {
   o->stream = nullptr;
   o->device_mem_limit = 0;
   o->verbose = 0;
+  o->profile = 0;
   return RSB_OK;
 }
 
@@ -415,17 +496,30 @@ int rsb_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col_id
     int64_t nnz = 0;
     if (!dev) {
       nnz = row_ptr[n];
+      if (row_ptr[0] != 0) fail(RSB_EINVAL, "row_ptr[0] must be 0");
       for (int64_t i = 0; i < n; ++i)
         if (row_ptr[i + 1] < row_ptr[i]) fail(RSB_EINVAL, "row_ptr not monotone");
       for (int64_t p = 0; p < nnz; ++p) {
         if (col_idx[p] < 0 || col_idx[p] >= n) fail(RSB_EINVAL, "column out of range");
-        if (weight[p] < 0 || weight[p] > (int32_t)kWeightMask) fail(RSB_EINVAL, "weight out of [0,15]");
+        if (weight[p] < 0 || weight[p] > (int32_t)kWeightMask)
+          fail(RSB_EINVAL, "weight out of [0, 15]");
       }
     }
     Ctx ctx;
     setup_ctx(ctx, *opts);
     if (dev) {
-      RSB_HIP(hipMemcpy(&nnz, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost));
+      int64_t r0 = 0;
+      RSB_HIP(hipMemcpyAsync(&nnz, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, ctx.stream));
+      RSB_HIP(hipMemcpyAsync(&r0, row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost, ctx.stream));
+      DevBuf<int> bad(ctx, 1);
+      RSB_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), ctx.stream));
+      k_check_csr<<<(unsigned)((n + 255) / 256), 256, 0, ctx.stream>>>(row_ptr, col_idx, weight, n,
+                                                                      bad.get());
+      RSB_LAUNCHED();
+      int hbad = 0;
+      RSB_HIP(hipMemcpyAsync(&hbad, bad.get(), sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+      RSB_HIP(hipStreamSynchronize(ctx.stream));
+      if (hbad || r0 != 0) fail(RSB_EINVAL, "invalid CSR (row_ptr, column or weight)");
     }
     if (nnz < 0) fail(RSB_EINVAL, "row_ptr[n] < 0");
     DevCsr g;
@@ -491,7 +585,6 @@ int rsb_fiedler(int64_t nelem, int32_t nv, const int64_t *ids, const rsb_opts *o
     std::vector<MeshIn> meshes{{nelem, in.p, 2}};
     DevBuf<double> yd(ctx, nelem);
     RunOut r = run_rsb(meshes, nv, *opts, ctx, nullptr, stats_out, yd.get());
-    int status = r.status;
     if (r.flip) {
       k_negate<<<(unsigned)((nelem + 255) / 256), 256, 0, ctx.stream>>>(yd.get(), nelem);
       RSB_LAUNCHED();
@@ -499,7 +592,7 @@ int rsb_fiedler(int64_t nelem, int32_t nv, const int64_t *ids, const rsb_opts *o
     copy_out(ctx, fiedler_out, yd.get(), nelem, dev);
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     *lambda2_out = r.lambda;
-    return status;
+    return r.status;
   });
 }
 

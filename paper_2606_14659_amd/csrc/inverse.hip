@@ -1,14 +1,400 @@
 // inverse.hip -- inverse iteration with conjugate gradients (paper Sec. 7,
-// Alg. 2) for all segments of a bisection level.
+// Alg. 2) for all segments of a bisection level, in FP64.
+//
+// Outer iteration: b <- b - (u0^T b) u0, b <- b / ||b||, solve L x = b, b <- x.
+// Inner solver: CG from x0 = 0 whose first search direction is the
+// unpreconditioned residual (the preconditioner is the identity here), with
+// the Polak-Ribiere ("flexible") beta.  The outer loop stops when a solve
+// needed a single CG step (b was an eigenvector, the stopping rule of
+// Sec. 7) or when the Rayleigh-quotient residual of b meets the tolerance,
+// or after max_outer iterations.  Every launch covers all segments of the
+// level; reductions are fixed-order per segment as in the Lanczos solver.
+#include <algorithm>
+#include <cmath>
+
 #include "common.h"
 #include "kernels.h"
+#include "solver_dev.h"
 
 namespace rsb {
 
-int64_t inverse_level(Level &L, CompDev &C, SolveDev &S, const InverseParams &p,
-                      double *y64_out, Ctx &ctx) {
-  (void)L; (void)C; (void)S; (void)p; (void)y64_out; (void)ctx;
-  fail(RSB_EINVAL, "method RSB_INVERSE_CG is not available in this build");
+namespace {
+
+struct InvArgs {
+  const BlkDev *blk;
+  const GrpDev *grp;
+  const SegDev *seg;
+  SegState *st;
+  double *part, *gpart;
+  unsigned *gcnt, *scnt;
+  int ps;
+  const int64_t *chunk_ptr;
+  const uint32_t *cols;
+  const int32_t *root;
+  const int32_t *gid;
+  double *U0, *B, *X, *R, *P0, *P1, *LP;
+  double cg_tol, tol;
+  int max_outer, cg_max_iter;
+  int32_t *flags;           // [0] segments still running (CG or outer)
+  unsigned long long *ctr;  // [0] segment CG steps
+  uint64_t seed;
+};
+
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_inv_begin(InvArgs a) {
+  __shared__ double red[4 * 2];
+  __shared__ double vals[2];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.solve) return;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int lr = r * kBlock + threadIdx.x;
+    if (lr >= b.nrows) break;
+    const int64_t row = b.row0 + lr;
+    const bool in = (a.root[row] == S.strad);
+    const double u = in ? S.invsqrt_nc : 0.0;
+    const double x = in ? start_value(a.seed, a.gid[row]) : 0.0;
+    a.U0[row] = u;
+    a.B[row] = x;
+    acc[0] += u * x;
+    acc[1] += x * x;
+  }
+  block_reduce_into<2>(acc, red, vals, 2);
+  if (!hier_reduce(a, lb, vals, 2)) return;
+  if (threadIdx.x == 0) {
+    SegState &W = a.st[b.seg];
+    W.c = vals[0];
+    W.s = 1.0 / sqrt(fmax(vals[1] - vals[0] * vals[0], 1e-300));
+    W.active = 1;
+    W.converged = 0;
+    W.cycles = 0;
+    W.steps = 0;
+    W.theta = 0.0;
+  }
+}
+
+// x = 0, r = b_hat = (b - c u0) s, p_old = 0; rr = r^T r.
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_cg_init(InvArgs a) {
+  __shared__ double red[4];
+  __shared__ double vals[1];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active) return;
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int lr = r * kBlock + threadIdx.x;
+    if (lr >= b.nrows) break;
+    const int64_t row = b.row0 + lr;
+    const double rv = (a.B[row] - S.c * a.U0[row]) * S.s;
+    a.R[row] = rv;
+    a.X[row] = 0.0;
+    a.P1[row] = 0.0;
+    acc[0] += rv * rv;
+  }
+  block_reduce_into<1>(acc, red, vals, 1);
+  if (!hier_reduce(a, lb, vals, 1)) return;
+  if (threadIdx.x == 0) {
+    SegState &W = a.st[b.seg];
+    W.rr = vals[0];
+    W.cg_it = 0;
+    W.cg_done = (sqrt(vals[0]) <= a.cg_tol) ? 1 : 0;
+    W.cg_beta = 0.0;
+  }
+}
+
+// p_new = r + beta p_old (rows) and L p_new (gathers r and p_old); p^T L p.
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_cg_a(InvArgs a, int it) {
+  __shared__ double red[4];
+  __shared__ double vals[1];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active || S.cg_done) return;
+  const double *Pold = (it & 1) ? a.P0 : a.P1;
+  double *Pnew = (it & 1) ? a.P1 : a.P0;
+  const double beta = S.cg_beta;
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int lr = r * kBlock + threadIdx.x;
+    if (lr >= b.nrows) break;
+    const int64_t row = b.row0 + lr;
+    const double pi = a.R[row] + beta * Pold[row];
+    const int64_t c = row >> 6;
+    const int lane = (int)(row & 63);
+    const int64_t p = a.chunk_ptr[c];
+    const int width = (int)((a.chunk_ptr[c + 1] - p) >> 6);
+    double lp = 0.0;
+    for (int k = 0; k < width; ++k) {
+      const uint32_t w = a.cols[p + (int64_t)k * 64 + lane];
+      const uint32_t j = colw_col(w);
+      lp += (double)colw_wt(w) * (pi - (a.R[j] + beta * Pold[j]));
+    }
+    Pnew[row] = pi;
+    a.LP[row] = lp;
+    acc[0] += pi * lp;
+  }
+  block_reduce_into<1>(acc, red, vals, 1);
+  if (!hier_reduce(a, lb, vals, 1)) return;
+  if (threadIdx.x == 0) a.st[b.seg].cg_alpha = a.st[b.seg].rr / vals[0];
+}
+
+// x += alpha p; r -= alpha L p; Polak-Ribiere beta; stop test.
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_cg_b(InvArgs a, int it) {
+  __shared__ double red[4 * 2];
+  __shared__ double vals[2];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active || S.cg_done) return;
+  const double *Pnew = (it & 1) ? a.P1 : a.P0;
+  const double alpha = S.cg_alpha;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int lr = r * kBlock + threadIdx.x;
+    if (lr >= b.nrows) break;
+    const int64_t row = b.row0 + lr;
+    a.X[row] += alpha * Pnew[row];
+    const double rold = a.R[row];
+    const double rnew = rold - alpha * a.LP[row];
+    a.R[row] = rnew;
+    acc[0] += rnew * rnew;
+    acc[1] += rnew * rold;
+  }
+  block_reduce_into<2>(acc, red, vals, 2);
+  if (!hier_reduce(a, lb, vals, 2)) return;
+  if (threadIdx.x != 0) return;
+  SegState &W = a.st[b.seg];
+  W.cg_it += 1;
+  W.steps += 1;
+  atomicAdd(&a.ctr[0], 1ull);
+  const double rr = vals[0];
+  if (sqrt(rr) <= a.cg_tol || W.cg_it >= a.cg_max_iter) {
+    W.cg_done = 1;
+  } else {
+    W.cg_beta = (rr - vals[1]) / W.rr;
+    W.rr = rr;
+    atomicAdd(&a.flags[0], 1);
+  }
+}
+
+// After a solve: transform of the new b = x (c, s) and a shift estimate
+// theta = x_hat^T b_hat / x_hat^T x_hat (L x ~ b_hat).
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_inv_eval(InvArgs a) {
+  __shared__ double red[4 * 3];
+  __shared__ double vals[3];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int lr = r * kBlock + threadIdx.x;
+    if (lr >= b.nrows) break;
+    const int64_t row = b.row0 + lr;
+    const double x = a.X[row];
+    const double bh = (a.B[row] - S.c * a.U0[row]) * S.s;
+    a.B[row] = x;  // the next b (row-local: read before write)
+    acc[0] += a.U0[row] * x;
+    acc[1] += x * x;
+    acc[2] += x * bh;
+  }
+  block_reduce_into<3>(acc, red, vals, 3);
+  if (!hier_reduce(a, lb, vals, 3)) return;
+  if (threadIdx.x == 0) {
+    SegState &W = a.st[b.seg];
+    const double c = vals[0];
+    const double xx = fmax(vals[1] - c * c, 1e-300);
+    W.c = c;
+    W.s = 1.0 / sqrt(xx);
+    W.theta = vals[2] / xx;  // (u0^T b_hat = 0)
+  }
+}
+
+// Rayleigh-quotient residual of the normalised new b (= x); outer stop test.
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_inv_res(InvArgs a) {
+  __shared__ double red[4 * 3];
+  __shared__ double vals[3];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active) return;
+  const double c = S.c, sc = S.s, th = S.theta;
+  double p[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int lr = r * kBlock + threadIdx.x;
+    if (lr >= b.nrows) break;
+    const int64_t row = b.row0 + lr;
+    const double xi = a.X[row];
+    const double y = (xi - c * a.U0[row]) * sc;
+    const double ly = sc * lap_row<double>(a.chunk_ptr, a.cols, a.X, row, xi);
+    const double rr = ly - th * y;
+    p[0] += rr * rr;
+    p[1] += y * ly;
+    p[2] += y * y;
+  }
+  block_reduce_into<3>(p, red, vals, 3);
+  if (!hier_reduce(a, lb, vals, 3)) return;
+  if (threadIdx.x != 0) return;
+  SegState &W = a.st[b.seg];
+  const double rho = vals[1] / vals[2];
+  const double dth = th - rho;
+  const double res = sqrt(fmax(vals[0] - dth * dth * vals[2], 0.0));
+  W.res = res;
+  W.rho = rho;
+  W.cycles += 1;
+  if (W.cg_it <= 1 || res <= a.tol * rho) {
+    W.converged = 1;
+    W.active = 0;
+  } else if (W.cycles >= a.max_outer) {
+    W.active = 0;
+  } else {
+    atomicAdd(&a.flags[0], 1);
+  }
+}
+
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_inv_output(InvArgs a, double *__restrict__ y64) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int lr = r * kBlock + threadIdx.x;
+    if (lr >= b.nrows) break;
+    const int64_t row = b.row0 + lr;
+    y64[row] = S.solve ? (a.B[row] - S.c * a.U0[row]) * S.s : 0.0;
+  }
+}
+
+__global__ void k_flag_reset(int32_t *flags) { flags[0] = 0; }
+
+constexpr int kCgChunk = 16;  // CG steps per captured graph (even: keeps p parity)
+
+template <int RPT>
+int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseParams &p,
+                     void *work, double *y64_out, bool use_graph, Ctx &ctx) {
+  InvArgs a{};
+  a.blk = L.blk;
+  a.grp = L.grp;
+  a.seg = L.seg;
+  a.st = S.st.get();
+  a.part = S.part.get();
+  a.gpart = S.gpart.get();
+  a.gcnt = S.gcnt.get();
+  a.scnt = S.scnt.get();
+  a.ps = S.pstride;
+  a.chunk_ptr = L.chunk_ptr;
+  a.cols = L.cols;
+  a.root = C.root.get();
+  a.gid = L.gid;
+  double *w = (double *)work;
+  a.U0 = w;
+  a.B = w + L.nrows;
+  a.X = w + 2 * L.nrows;
+  a.R = w + 3 * L.nrows;
+  a.P0 = w + 4 * L.nrows;
+  a.P1 = w + 5 * L.nrows;
+  a.LP = w + 6 * L.nrows;
+  a.cg_tol = p.cg_tol;
+  a.tol = p.tol;
+  a.max_outer = p.max_outer;
+  a.cg_max_iter = p.cg_max_iter;
+  a.flags = S.n_active.get();
+  a.ctr = (unsigned long long *)S.counters.get();
+  a.seed = p.seed;
+  const int nblk = L.nblk;
+  hipStream_t s = ctx.stream;
+  k_inv_begin<RPT><<<nblk, kBlock, 0, s>>>(a);
+  RSB_LAUNCHED();
+  int64_t steps = 0;
+  int32_t flags = 0;
+  auto read_flags = [&]() {
+    RSB_HIP(hipMemcpyAsync(&flags, a.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    RSB_HIP(hipStreamSynchronize(s));
+  };
+  for (int outer = 0; outer < p.max_outer; ++outer) {
+    k_cg_init<RPT><<<nblk, kBlock, 0, s>>>(a);
+    RSB_LAUNCHED();
+    // CG chunks, each as one graph launch (or direct launches)
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    auto chunk = [&]() {
+      k_flag_reset<<<1, 1, 0, s>>>(a.flags);
+      for (int it = 0; it < kCgChunk; ++it) {
+        k_cg_a<RPT><<<nblk, kBlock, 0, s>>>(a, it);
+        k_cg_b<RPT><<<nblk, kBlock, 0, s>>>(a, it);
+      }
+    };
+    if (use_graph) {
+      RSB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      chunk();
+      hipError_t e = hipStreamEndCapture(s, &graph);
+      if (e != hipSuccess) fail(RSB_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        fail(RSB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+      }
+    }
+    struct GraphGuard {
+      hipGraphExec_t &e;
+      hipGraph_t &g;
+      ~GraphGuard() {
+        if (e) (void)hipGraphExecDestroy(e);
+        if (g) (void)hipGraphDestroy(g);
+      }
+    } guard{exec, graph};
+    for (int done = 0; done < p.cg_max_iter; done += kCgChunk) {
+      if (exec) RSB_HIP(hipGraphLaunch(exec, s));
+      else {
+        chunk();
+        RSB_LAUNCHED();
+      }
+      steps += kCgChunk;
+      read_flags();
+      if (flags == 0) break;
+    }
+    k_flag_reset<<<1, 1, 0, s>>>(a.flags);
+    k_inv_eval<RPT><<<nblk, kBlock, 0, s>>>(a);
+    k_inv_res<RPT><<<nblk, kBlock, 0, s>>>(a);
+    RSB_LAUNCHED();
+    read_flags();
+    if (flags == 0) break;
+  }
+  if (y64_out) {
+    k_inv_output<RPT><<<nblk, kBlock, 0, s>>>(a, y64_out);
+    RSB_LAUNCHED();
+  }
+  return steps;
+}
+
+}  // namespace
+
+size_t inverse_workspace_bytes(int64_t rows) { return (size_t)rows * 7 * sizeof(double); }
+
+int64_t inverse_level(const LevelView &L, CompDev &C, SolveDev &S, const InverseParams &p,
+                      void *work, double *y64_out, bool use_graph, Ctx &ctx) {
+  if (L.nseg == 0) return 0;
+  switch (L.rpt) {
+    case 4: return inverse_impl<4>(L, C, S, p, work, y64_out, use_graph, ctx);
+    case 8: return inverse_impl<8>(L, C, S, p, work, y64_out, use_graph, ctx);
+    case 16: return inverse_impl<16>(L, C, S, p, work, y64_out, use_graph, ctx);
+    default: fail(RSB_EINTERNAL, "unsupported rows-per-thread");
+  }
 }
 
 }  // namespace rsb

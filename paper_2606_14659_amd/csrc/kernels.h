@@ -77,8 +77,12 @@ struct SegState {
   int32_t solve;        // 1 if this segment has a component to cut
   int32_t flip;         // sign flip of the final vector
   int32_t first;        // row of the sign-deciding element
-  int64_t steps;        // Lanczos steps run (all cycles)
-  int32_t cycles;       // cycles run
+  int64_t steps;        // Lanczos or CG steps run (all cycles)
+  int32_t cycles;       // cycles (Lanczos) or outer iterations (inverse iteration)
+  int32_t cg_it;        // CG steps of the current solve
+  double rr;            // CG: r^T r
+  double cg_alpha, cg_beta;
+  int32_t cg_done;      // CG solve finished
   int32_t pad;
 };
 
@@ -99,7 +103,38 @@ struct Level {
   DevBuf<int32_t> orig;        // row -> index in the concatenated input (-1: pad)
   DevBuf<int32_t> gid;         // row -> element id within its mesh
   int64_t words = 0;
+  int64_t nnz = 0;             // off-diagonal nonzeros (non-padding words)
 };
+
+// Non-owning view of a level, or of some of its segments: vectors keep the
+// level's row indexing (stride nrows), the tables may cover a subset.
+struct LevelView {
+  int64_t nrows = 0;
+  int32_t nseg = 0, nblk = 0, rpt = 16;
+  const SegDev *seg = nullptr;
+  const BlkDev *blk = nullptr;
+  const GrpDev *grp = nullptr;
+  const int64_t *chunk_ptr = nullptr;
+  const uint32_t *cols = nullptr;
+  const int32_t *gid = nullptr;
+  int64_t nnz = 0;
+};
+
+inline LevelView view_of(const Level &L) {
+  LevelView v;
+  v.nrows = L.nrows;
+  v.nseg = L.nseg;
+  v.nblk = L.nblk;
+  v.rpt = L.rpt;
+  v.seg = L.d_seg.get();
+  v.blk = L.d_blk.get();
+  v.grp = L.d_grp.get();
+  v.chunk_ptr = L.chunk_ptr.get();
+  v.cols = L.cols.get();
+  v.gid = L.gid.get();
+  v.nnz = L.nnz;
+  return v;
+}
 
 // Fill host block/group tables of a level from its segment table and
 // upload all three tables.
@@ -135,22 +170,29 @@ void components_and_targets(Level &L, CompDev &C, SolveDev &S, Ctx &ctx);
 // Lanczos solve of every segment with a component to cut.  Precision T of
 // the vectors; FP64 scalars.  Result: y64[row] (unit norm on the component,
 // zero elsewhere in the segment).  Returns the number of level-steps run.
+struct KernelProfile {
+  double ms = 0.0;       // summed device time of the profiled kernel
+  double bytes = 0.0;    // its algorithmic bytes
+  int64_t launches = 0;
+};
+
 struct LanczosParams {
   int m;
   int max_restarts;
   double tol;
-  int phase32;        // FP32 phase of mixed precision (floor-aware stop)
   int use_graph;
   uint64_t seed;
+  KernelProfile *prof;   // non-null: time the step-j>=3 project kernel with events
+  int64_t nnz;           // off-diagonal nonzeros of the level (for the byte count)
 };
-// basis: (m + 3) * L.nrows values of T (u0, q_1..q_m, two work vectors).
-// y32_in: the FP32 phase's basis buffer (mixed precision refinement start),
-// S32 its solver state; both null for a random start.
-void solve_alloc(SolveDev &S, const Level &L, int m, Ctx &ctx);
+// work: lanczos_workspace_bytes(L.nrows, m, T is float) bytes of device memory
+// (FP64 u0, q_1, restart and work vectors; type-T directions q_2..q_m and two
+// work vectors).  T = double: all FP64; T = float: mixed precision.
+void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, Ctx &ctx);
+size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32);
 template <typename T>
-int64_t lanczos_level(Level &L, CompDev &C, SolveDev &S, const LanczosParams &p,
-                      const float *y32_in, const SolveDev *S32, T *basis, double *y64_out,
-                      Ctx &ctx);
+int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p,
+                      void *work, double *y64_out, Ctx &ctx);
 
 // Inverse iteration with CG on every segment with a component to cut.
 struct InverseParams {
@@ -160,8 +202,9 @@ struct InverseParams {
   double tol;
   uint64_t seed;
 };
-int64_t inverse_level(Level &L, CompDev &C, SolveDev &S, const InverseParams &p,
-                      double *y64_out, Ctx &ctx);
+size_t inverse_workspace_bytes(int64_t rows);
+int64_t inverse_level(const LevelView &L, CompDev &C, SolveDev &S, const InverseParams &p,
+                      void *work, double *y64_out, bool use_graph, Ctx &ctx);
 
 // Sign rule, radix select and side assignment.  side[row]: 0 low, 1 high,
 // 2 padding.

@@ -19,11 +19,20 @@
 // vector y = Q t becomes the next start vector and its residual decides
 // convergence.  Reductions are two-level and in a fixed order (per block,
 // per group of 32 blocks, per segment), done by the last block to finish.
+//
+// Precision.  The restart vector Y (the Ritz vector of the previous cycle),
+// u0, q_1 and the first residual direction are FP64 in both modes; the
+// directions q_2 .. q_m, their work vectors and their SpMVs have type T
+// (double, or float with float accumulation).  With T = float the Ritz vector
+// y = t_1 q_1 + sum_k t_k q_k is an FP64 vector plus an FP32 correction, so
+// each restart gains about the FP32 precision factor and the pair reaches the
+// FP64 tolerance; scalars, projections and the tridiagonal solve are FP64.
 #include <algorithm>
 #include <cmath>
 
 #include "common.h"
 #include "kernels.h"
+#include "solver_dev.h"
 
 namespace rsb {
 
@@ -43,144 +52,75 @@ struct LzArgs {
   const uint32_t *cols;
   const int32_t *root;
   const int32_t *gid;
-  T *V;          // basis: V[k] at V + k * vs; V[0] = u0
+  double *U0;    // u0 (ones vector of the cut component, normalised)
+  double *Q1;    // q_1 of the current cycle
+  double *Y;     // restart vector (unnormalised Ritz vector)
+  double *Wd;    // FP64 work vector of step 1
+  T *V;          // q_k at V + k * vs for k >= 2
   int64_t vs;
-  T *W0, *W1;    // ping-pong work vectors
+  T *Wt0, *Wt1;  // ping-pong work vectors of steps >= 2
   int m;
   double tol;
   int max_restarts;
-  int phase32;
-  double brk;    // breakdown threshold relative to ||T||
+  double brk;    // breakdown threshold (relative to ||T||) of the type-T steps
   int32_t *flags;          // [0] active segments after the cycle, [1] max steps in the cycle
   unsigned long long *ctr; // [0] segment steps
   uint64_t seed;
 };
 
-// splitmix64 output for counter gid+1 of the stream started at seed
-// (Steele, Lea, Flood 2014), mapped to [-1, 1).
-__device__ inline double start_value(uint64_t seed, int64_t gid) {
-  uint64_t z = seed + (uint64_t)(gid + 1) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
-}
-
-// Fixed-order two-level reduction of `nval` block values held in LDS
-// `vals`.  Returns true in the one block that finishes the segment; there
-// `vals` holds the segment totals.
-template <typename A>
-__device__ bool hier_reduce(const A &a, int lb, double *vals, int nval) {
-  __shared__ int s_flag;
-  const BlkDev b = a.blk[lb];
-  const int t = threadIdx.x;
-  for (int i = t; i < nval; i += kBlock) a.part[(int64_t)lb * a.ps + i] = vals[i];
-  __threadfence();
-  __syncthreads();
-  if (t == 0) {
-    unsigned prev = atomicAdd(&a.gcnt[b.grp], 1u);
-    s_flag = (prev == (unsigned)a.grp[b.grp].nblk - 1u);
-  }
-  __syncthreads();
-  if (!s_flag) return false;
-  __threadfence();
-  const GrpDev g = a.grp[b.grp];
-  const SegDev sg = a.seg[b.seg];
-  if (t == 0) a.gcnt[b.grp] = 0;
-  for (int i = t; i < nval; i += kBlock) {
-    double sum = 0.0;
-    for (int q = 0; q < g.nblk; ++q) sum += a.part[(int64_t)(g.blk0 + q) * a.ps + i];
-    vals[i] = sum;
-  }
-  __syncthreads();
-  if (sg.ngrp == 1) return true;
-  for (int i = t; i < nval; i += kBlock) a.gpart[(int64_t)b.grp * a.ps + i] = vals[i];
-  __threadfence();
-  __syncthreads();
-  if (t == 0) {
-    unsigned prev = atomicAdd(&a.scnt[b.seg], 1u);
-    s_flag = (prev == (unsigned)sg.ngrp - 1u);
-  }
-  __syncthreads();
-  if (!s_flag) return false;
-  __threadfence();
-  if (t == 0) a.scnt[b.seg] = 0;
-  for (int i = t; i < nval; i += kBlock) {
-    double sum = 0.0;
-    for (int q = 0; q < sg.ngrp; ++q) sum += a.gpart[(int64_t)(sg.grp0 + q) * a.ps + i];
-    vals[i] = sum;
-  }
-  __syncthreads();
-  return true;
-}
-
-// Sum NV per-thread values over the block into vals[0..NV) (fixed order).
-template <int NV>
-__device__ inline void block_reduce_into(double (&v)[NV], double *red /* [4*NV] */,
-                                         double *vals, int count) {
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x < (unsigned)count) {
-    double s = 0.0;
-    for (int w = 0; w < kBlock / kWave; ++w) s += red[w * NV + threadIdx.x];
-    vals[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
-// Sliced-ELL Laplacian row in difference form: sum_j w_ij (x_i - x_j).
+// Vector types of step j: STEP 1 reads Y and works in FP64; STEP 2 reads the
+// FP64 work vector and writes type T; STEP 3 (j >= 3) is all type T.
+template <typename T, int STEP>
+struct StepTypes;
 template <typename T>
-__device__ inline T lap_row(const int64_t *__restrict__ chunk_ptr, const uint32_t *__restrict__ cols,
-                            const T *__restrict__ x, int64_t row, T xi) {
-  const int64_t c = row >> 6;
-  const int lane = (int)(row & 63);
-  const int64_t p = chunk_ptr[c];
-  const int width = (int)((chunk_ptr[c + 1] - p) >> 6);
-  const uint32_t *cp = cols + p + lane;
-  T acc = 0;
-  int k = 0;
-  for (; k + 4 <= width; k += 4) {
-    uint32_t w0 = cp[(k + 0) * 64], w1 = cp[(k + 1) * 64], w2 = cp[(k + 2) * 64],
-             w3 = cp[(k + 3) * 64];
-    T x0 = x[colw_col(w0)], x1 = x[colw_col(w1)], x2 = x[colw_col(w2)], x3 = x[colw_col(w3)];
-    acc += (T)colw_wt(w0) * (xi - x0);
-    acc += (T)colw_wt(w1) * (xi - x1);
-    acc += (T)colw_wt(w2) * (xi - x2);
-    acc += (T)colw_wt(w3) * (xi - x3);
-  }
-  for (; k < width; ++k) {
-    uint32_t w = cp[k * 64];
-    acc += (T)colw_wt(w) * (xi - x[colw_col(w)]);
-  }
-  return acc;
+struct StepTypes<T, 1> {
+  using Tin = double;
+  using Tw = double;
+};
+template <typename T>
+struct StepTypes<T, 2> {
+  using Tin = double;
+  using Tw = T;
+};
+template <typename T>
+struct StepTypes<T, 3> {
+  using Tin = T;
+  using Tw = T;
+};
+
+template <typename T, int STEP>
+__device__ inline const typename StepTypes<T, STEP>::Tin *step_in(const LzArgs<T> &a, int j) {
+  if constexpr (STEP == 1) return a.Y;
+  else if constexpr (STEP == 2) return a.Wd;
+  else return ((j - 1) & 1) ? a.Wt1 : a.Wt0;
+}
+
+template <typename T, int STEP>
+__device__ inline typename StepTypes<T, STEP>::Tw *step_out(const LzArgs<T> &a, int j) {
+  if constexpr (STEP == 1) return a.Wd;
+  else return (j & 1) ? a.Wt1 : a.Wt0;
+}
+
+// basis vector k at row (k = 0: u0, k = 1: q_1, k >= 2: q_k)
+template <typename T>
+__device__ inline double basis_at(const LzArgs<T> &a, int k, int64_t row) {
+  if (k == 0) return a.U0[row];
+  if (k == 1) return a.Q1[row];
+  return (double)a.V[(int64_t)k * a.vs + row];
 }
 
 // ----------------------------------------------------------------------------
-// begin: u0 and the start vector of every segment with a component to cut.
-// SRC 0: hashed random start (Sec. 7, Alg. 2 line 1; the Lanczos start);
-// SRC 1: from the FP32 phase's final vector (mixed precision refinement).
+// begin: u0 and the hashed random start vector (the Lanczos start; Sec. 7,
+// Alg. 2 uses the same kind of start) of every segment with a component to cut.
 // ----------------------------------------------------------------------------
-template <typename T, int RPT, int SRC>
-__global__ __launch_bounds__(kBlock) void k_lz_begin(LzArgs<T> a, const float *__restrict__ y32,
-                                                     const SegState *__restrict__ st32,
-                                                     const float *__restrict__ u32) {
+template <typename T, int RPT>
+__global__ __launch_bounds__(kBlock) void k_lz_begin(LzArgs<T> a) {
   __shared__ double red[4 * 2];
   __shared__ double vals[2];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
   if (!S.solve) return;
-  double c32 = 0, s32 = 0;
-  if (SRC == 1) {
-    c32 = st32[b.seg].c;
-    s32 = st32[b.seg].s;
-  }
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
@@ -189,16 +129,11 @@ __global__ __launch_bounds__(kBlock) void k_lz_begin(LzArgs<T> a, const float *_
     const int64_t row = b.row0 + lr;
     const bool in = (a.root[row] == S.strad);
     const double u = in ? S.invsqrt_nc : 0.0;
-    double x = 0.0;
-    if (in) {
-      if (SRC == 0) x = start_value(a.seed, a.gid[row]);
-      else x = ((double)y32[row] - c32 * (double)u32[row]) * s32;
-    }
-    const T ut = (T)u, xt = (T)x;
-    a.V[row] = ut;
-    a.W0[row] = xt;
-    acc[0] += (double)ut * (double)xt;
-    acc[1] += (double)xt * (double)xt;
+    const double x = in ? start_value(a.seed, a.gid[row]) : 0.0;
+    a.U0[row] = u;
+    a.Y[row] = x;
+    acc[0] += u * x;
+    acc[1] += x * x;
   }
   block_reduce_into<2>(acc, red, vals, 2);
   if (!hier_reduce(a, lb, vals, 2)) return;
@@ -221,11 +156,13 @@ __global__ __launch_bounds__(kBlock) void k_lz_begin(LzArgs<T> a, const float *_
 }
 
 // ----------------------------------------------------------------------------
-// project: MODE 0 = first pass of step j (SpMV of q_j, write q_j to V[j]);
+// project: MODE 0 = first pass of step j (SpMV of q_j, write q_j);
 //          MODE 1 = second Gram-Schmidt pass (project the current w again).
 // ----------------------------------------------------------------------------
-template <typename T, int RPT, int MODE>
+template <typename T, int RPT, int MODE, int STEP>
 __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
+  using Tin = typename StepTypes<T, STEP>::Tin;
+  using Tw = typename StepTypes<T, STEP>::Tw;
   __shared__ double red[4 * 8];
   __shared__ double vals[kMaxM + 8];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -233,8 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
   const SegState S = a.st[b.seg];
   if (!S.active || S.cycle_done) return;
   if (MODE == 1 && !S.need2) return;
-  const T *Win = ((j - 1) & 1) ? a.W1 : a.W0;
-  T *Wout = ((j - 1) & 1) ? a.W0 : a.W1;
+  const Tin *Win = step_in<T, STEP>(a, j);
+  Tw *Wout = step_out<T, STEP>(a, j);
   const double c = S.c, sc = S.s;
   double z[RPT], qv[RPT], uv[RPT];
 #pragma unroll
@@ -243,14 +180,20 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
     z[r] = qv[r] = uv[r] = 0.0;
     if (lr < b.nrows) {
       const int64_t row = b.row0 + lr;
-      const double u = (double)a.V[row];
+      const double u = a.U0[row];
       uv[r] = u;
       if (MODE == 0) {
-        const T wi = Win[row];
-        const T q = (T)(((double)wi - c * u) * sc);
-        a.V[(int64_t)j * a.vs + row] = q;
-        qv[r] = (double)q;
-        const T lq = (T)(sc * (double)lap_row<T>(a.chunk_ptr, a.cols, Win, row, wi));
+        const Tin wi = Win[row];
+        const double qd = ((double)wi - c * u) * sc;
+        if (STEP == 1) {
+          a.Q1[row] = qd;
+          qv[r] = qd;
+        } else {
+          const T q = (T)qd;
+          a.V[(int64_t)j * a.vs + row] = q;
+          qv[r] = (double)q;
+        }
+        const Tw lq = (Tw)(sc * (double)lap_row<Tin>(a.chunk_ptr, a.cols, Win, row, wi));
         Wout[row] = lq;
         z[r] = (double)lq;
       } else {
@@ -275,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
         double v;
         if (k == 0) v = uv[r];
         else if (MODE == 0 && k == j) v = qv[r];
-        else v = (double)a.V[(int64_t)k * a.vs + row];
+        else v = basis_at(a, k, row);
         acc[kk] += v * z[r];
       }
     }
@@ -297,8 +240,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
 // update: w -= [u0, Q] h; ||w||^2; finish the step (PASS 1 first pass,
 // PASS 2 after the second Gram-Schmidt pass).
 // ----------------------------------------------------------------------------
-template <typename T, int RPT, int PASS>
+template <typename T, int RPT, int PASS, int STEP>
 __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
+  using Tw = typename StepTypes<T, STEP>::Tw;
   __shared__ double red[4];
   __shared__ double vals[2];
   __shared__ double hs[kMaxM + 2];
@@ -310,17 +254,16 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
   const double *hg = a.h + (int64_t)b.seg * a.ps;
   for (int k = threadIdx.x; k <= j; k += kBlock) hs[k] = hg[k];
   __syncthreads();
-  T *Wout = ((j - 1) & 1) ? a.W0 : a.W1;
+  Tw *Wout = step_out<T, STEP>(a, j);
   double acc[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
   for (int k = 0; k <= j; ++k) {
     const double hk = hs[k];
-    const T *vk = a.V + (int64_t)k * a.vs + b.row0;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int lr = r * kBlock + threadIdx.x;
-      if (lr < b.nrows) acc[r] += (double)vk[lr] * hk;
+      if (lr < b.nrows) acc[r] += basis_at(a, k, b.row0 + lr) * hk;
     }
   }
   double nn[1] = {0.0};
@@ -329,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
     const int lr = r * kBlock + threadIdx.x;
     if (lr < b.nrows) {
       const int64_t row = b.row0 + lr;
-      const T zt = (T)((double)Wout[row] - acc[r]);
+      const Tw zt = (Tw)((double)Wout[row] - acc[r]);
       Wout[row] = zt;
       nn[0] += (double)zt * (double)zt;
     }
@@ -360,7 +303,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
   const double bprev = (j >= 2) ? be[j - 1] : 0.0;
   W.tnorm = fmax(W.tnorm, fabs(alpha_j) + beta + bprev);
   W.k = j;
-  if (j >= a.m || beta <= a.brk * W.tnorm) {
+  // the FP64 first step breaks down only at FP64 rounding level
+  const double brk = (STEP == 1) ? 1e-12 : a.brk;
+  if (j >= a.m || beta <= brk * W.tnorm) {
     W.cycle_done = 1;
   } else {
     be[j] = beta;
@@ -484,7 +429,7 @@ __global__ __launch_bounds__(kWave) void k_trieig(SegState *__restrict__ st,
 }
 
 // ----------------------------------------------------------------------------
-// Ritz vector y = Q t into W0 (the next start vector) and its transform.
+// Ritz vector y = Q t into Y (FP64; the next start vector) and its transform.
 // ----------------------------------------------------------------------------
 template <typename T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_lz_ritz(LzArgs<T> a) {
@@ -504,11 +449,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_ritz(LzArgs<T> a) {
   for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
   for (int c = 0; c < k; ++c) {
     const double tc = ts[c];
-    const T *vc = a.V + (int64_t)(c + 1) * a.vs + b.row0;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int lr = r * kBlock + threadIdx.x;
-      if (lr < b.nrows) acc[r] += (double)vc[lr] * tc;
+      if (lr < b.nrows) acc[r] += basis_at(a, c + 1, b.row0 + lr) * tc;
     }
   }
   double p[2] = {0.0, 0.0};
@@ -517,10 +461,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_ritz(LzArgs<T> a) {
     const int lr = r * kBlock + threadIdx.x;
     if (lr < b.nrows) {
       const int64_t row = b.row0 + lr;
-      const T y = (T)acc[r];
-      a.W0[row] = y;
-      p[0] += (double)a.V[row] * (double)y;
-      p[1] += (double)y * (double)y;
+      a.Y[row] = acc[r];
+      p[0] += a.U0[row] * acc[r];
+      p[1] += acc[r] * acc[r];
     }
   }
   block_reduce_into<2>(p, red, vals, 2);
@@ -537,9 +480,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_ritz(LzArgs<T> a) {
 }
 
 // ----------------------------------------------------------------------------
-// residual of the (projected, normalised) Ritz vector; convergence, restart.
-// ||L y - rho y|| with rho the Rayleigh quotient, from ||L y - theta y||^2 =
-// ||L y - rho y||^2 + (theta - rho)^2 ||y||^2.
+// residual of the (projected, normalised) Ritz vector in FP64; convergence,
+// restart.  ||L y - rho y|| with rho the Rayleigh quotient, from
+// ||L y - theta y||^2 = ||L y - rho y||^2 + (theta - rho)^2 ||y||^2.
 // ----------------------------------------------------------------------------
 template <typename T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
@@ -556,9 +499,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
     const int lr = r * kBlock + threadIdx.x;
     if (lr >= b.nrows) break;
     const int64_t row = b.row0 + lr;
-    const T wi = a.W0[row];
-    const double y = ((double)wi - c * (double)a.V[row]) * sc;
-    const double ly = sc * (double)lap_row<T>(a.chunk_ptr, a.cols, a.W0, row, wi);
+    const double wi = a.Y[row];
+    const double y = (wi - c * a.U0[row]) * sc;
+    const double ly = sc * lap_row<double>(a.chunk_ptr, a.cols, a.Y, row, wi);
     const double rr = ly - th * y;
     p[0] += rr * rr;
     p[1] += y * ly;
@@ -571,7 +514,6 @@ __global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
   const double rho = vals[1] / vals[2];
   const double dth = th - rho;
   const double res = sqrt(fmax(vals[0] - dth * dth * vals[2], 0.0));
-  const double prev = W.res;
   W.res = res;
   W.rho = rho;
   W.cycles += 1;
@@ -579,8 +521,6 @@ __global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
   if (res <= a.tol * rho) {
     W.converged = 1;
     stop = true;
-  } else if (a.phase32 && W.cycles >= 2 && res > 0.9 * prev) {
-    stop = true;  // FP32 floor reached: hand over to the FP64 refinement
   } else if (W.restarts >= a.max_restarts) {
     stop = true;
   }
@@ -596,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
   }
 }
 
-// final vector in FP64: y = (w - c u0) s on the component, 0 elsewhere
+// final vector: y = (Y - c u0) s on the component, 0 elsewhere
 template <typename T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_lz_output(LzArgs<T> a, double *__restrict__ y64) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -608,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_output(LzArgs<T> a, double *__res
     if (lr >= b.nrows) break;
     const int64_t row = b.row0 + lr;
     double y = 0.0;
-    if (S.solve) y = ((double)a.W0[row] - S.c * (double)a.V[row]) * S.s;
+    if (S.solve) y = (a.Y[row] - S.c * a.U0[row]) * S.s;
     y64[row] = y;
   }
 }
@@ -620,20 +560,33 @@ __global__ void k_flags_reset(int32_t *flags) {
 
 template <typename T, int RPT>
 struct LzLaunch {
-  static void begin(const LzArgs<T> &a, int nblk, const float *y32, const SegState *st32,
-                    const float *u32, hipStream_t s) {
-    if (y32)
-      k_lz_begin<T, RPT, 1><<<nblk, kBlock, 0, s>>>(a, y32, st32, u32);
-    else
-      k_lz_begin<T, RPT, 0><<<nblk, kBlock, 0, s>>>(a, nullptr, nullptr, nullptr);
+  static void begin(const LzArgs<T> &a, int nblk, hipStream_t s) {
+    k_lz_begin<T, RPT><<<nblk, kBlock, 0, s>>>(a);
   }
-  static void cycle(const LzArgs<T> &a, int nblk, int nseg, hipStream_t s) {
+  template <int STEP>
+  static void step(const LzArgs<T> &a, int nblk, int j, hipStream_t s) {
+    k_lz_project<T, RPT, 0, STEP><<<nblk, kBlock, 0, s>>>(a, j);
+    k_lz_update<T, RPT, 1, STEP><<<nblk, kBlock, 0, s>>>(a, j);
+    k_lz_project<T, RPT, 1, STEP><<<nblk, kBlock, 0, s>>>(a, j);
+    k_lz_update<T, RPT, 2, STEP><<<nblk, kBlock, 0, s>>>(a, j);
+  }
+  // ev: null, or 2*m events bracketing the first-pass project launch of
+  // every step j >= 3 (ev[2j], ev[2j+1]).
+  static void cycle(const LzArgs<T> &a, int nblk, int nseg, hipStream_t s,
+                    hipEvent_t *ev = nullptr) {
     k_flags_reset<<<1, 1, 0, s>>>(a.flags);
     for (int j = 1; j <= a.m; ++j) {
-      k_lz_project<T, RPT, 0><<<nblk, kBlock, 0, s>>>(a, j);
-      k_lz_update<T, RPT, 1><<<nblk, kBlock, 0, s>>>(a, j);
-      k_lz_project<T, RPT, 1><<<nblk, kBlock, 0, s>>>(a, j);
-      k_lz_update<T, RPT, 2><<<nblk, kBlock, 0, s>>>(a, j);
+      if (j == 1) step<1>(a, nblk, j, s);
+      else if (j == 2) step<2>(a, nblk, j, s);
+      else if (!ev) step<3>(a, nblk, j, s);
+      else {
+        (void)hipEventRecord(ev[2 * j], s);
+        k_lz_project<T, RPT, 0, 3><<<nblk, kBlock, 0, s>>>(a, j);
+        (void)hipEventRecord(ev[2 * j + 1], s);
+        k_lz_update<T, RPT, 1, 3><<<nblk, kBlock, 0, s>>>(a, j);
+        k_lz_project<T, RPT, 1, 3><<<nblk, kBlock, 0, s>>>(a, j);
+        k_lz_update<T, RPT, 2, 3><<<nblk, kBlock, 0, s>>>(a, j);
+      }
     }
     k_trieig<<<nseg, kWave, 0, s>>>(a.st, a.alpha, a.beta, a.tvec, a.ps, nseg);
     k_lz_ritz<T, RPT><<<nblk, kBlock, 0, s>>>(a);
@@ -656,10 +609,10 @@ void dispatch_rpt(int rpt, F &&f) {
 
 }  // namespace
 
-void solve_alloc(SolveDev &S, const Level &L, int m, Ctx &ctx) {
+void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, Ctx &ctx) {
   S.m = m;
   S.pstride = m + 4;
-  const size_t ns = std::max(L.nseg, 1), nb = std::max(L.nblk, 1), ng = std::max(L.ngrp, 1);
+  const size_t ns = std::max(nseg, 1), nb = std::max(nblk, 1), ng = std::max(ngrp, 1);
   if (!S.st.p || S.st.n < ns) S.st.alloc(ctx, ns);
   S.alpha.alloc(ctx, ns * S.pstride);
   S.beta.alloc(ctx, ns * S.pstride);
@@ -677,16 +630,20 @@ void solve_alloc(SolveDev &S, const Level &L, int m, Ctx &ctx) {
   RSB_HIP(hipMemsetAsync(S.beta.get(), 0, S.beta.bytes(), ctx.stream));
 }
 
+size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32) {
+  const size_t t = fp32 ? 4 : 8;
+  return (size_t)rows * (5 * 8 + (size_t)(m + 3) * t);
+}
+
 template <typename T>
-int64_t lanczos_level(Level &L, CompDev &C, SolveDev &S, const LanczosParams &p,
-                      const float *y32_in, const SolveDev *S32, T *basis, double *y64_out,
-                      Ctx &ctx) {
+int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p, void *work,
+                      double *y64_out, Ctx &ctx) {
   if (L.nseg == 0) return 0;
   if (p.m < 1 || p.m > kMaxM) fail(RSB_EINVAL, "lanczos_m must be in [1, 250]");
   LzArgs<T> a{};
-  a.blk = L.d_blk.get();
-  a.grp = L.d_grp.get();
-  a.seg = L.d_seg.get();
+  a.blk = L.blk;
+  a.grp = L.grp;
+  a.seg = L.seg;
   a.st = S.st.get();
   a.alpha = S.alpha.get();
   a.beta = S.beta.get();
@@ -697,78 +654,97 @@ int64_t lanczos_level(Level &L, CompDev &C, SolveDev &S, const LanczosParams &p,
   a.gcnt = S.gcnt.get();
   a.scnt = S.scnt.get();
   a.ps = S.pstride;
-  a.chunk_ptr = L.chunk_ptr.get();
-  a.cols = L.cols.get();
+  a.chunk_ptr = L.chunk_ptr;
+  a.cols = L.cols;
   a.root = C.root.get();
-  a.gid = L.gid.get();
-  a.V = basis;
+  a.gid = L.gid;
+  // workspace layout: U0, Q1, Y, Wd (FP64), then V (m+1 slots), Wt0, Wt1 (T)
+  double *wd = (double *)work;
+  a.U0 = wd;
+  a.Q1 = wd + L.nrows;
+  a.Y = wd + 2 * L.nrows;
+  a.Wd = wd + 3 * L.nrows;
+  T *wt = (T *)(wd + 4 * L.nrows);
+  a.V = wt;
   a.vs = L.nrows;
-  a.W0 = basis + (int64_t)(p.m + 1) * L.nrows;
-  a.W1 = a.W0 + L.nrows;
+  a.Wt0 = wt + (int64_t)(p.m + 1) * L.nrows;
+  a.Wt1 = a.Wt0 + L.nrows;
   a.m = p.m;
   a.tol = p.tol;
   a.max_restarts = p.max_restarts;
-  a.phase32 = p.phase32;
   a.brk = sizeof(T) == 4 ? 1e-5 : 1e-12;
   a.flags = S.n_active.get();
   a.ctr = (unsigned long long *)S.counters.get();
   a.seed = p.seed;
   const int nblk = L.nblk, nseg = L.nseg;
-  const float *u32 = nullptr;
-  const SegState *st32 = nullptr;
-  if (y32_in) {
-    // the FP32 phase's basis: u0 at its start, W0 after its m+1 vectors
-    u32 = y32_in;
-    st32 = S32->st.get();
-  }
   int64_t level_steps = 0;
   dispatch_rpt<T>(L.rpt, [&](auto launcher) {
     using Lz = decltype(launcher);
-    const float *y32 = y32_in ? y32_in + (int64_t)(S32->m + 1) * L.nrows : nullptr;
-    Lz::begin(a, nblk, y32, st32, u32, ctx.stream);
+    Lz::begin(a, nblk, ctx.stream);
     RSB_LAUNCHED();
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    if (p.use_graph) {
+    struct Res {
+      hipGraphExec_t exec = nullptr;
+      hipGraph_t graph = nullptr;
+      std::vector<hipEvent_t> ev;
+      ~Res() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : ev) (void)hipEventDestroy(e);
+      }
+    } res;
+    const bool prof = p.prof != nullptr;
+    if (prof) {
+      res.ev.resize(2 * (a.m + 1));
+      for (auto &e : res.ev) RSB_HIP(hipEventCreate(&e));
+    } else if (p.use_graph) {
       RSB_HIP(hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal));
       Lz::cycle(a, nblk, nseg, ctx.stream);
-      hipError_t e = hipStreamEndCapture(ctx.stream, &graph);
+      hipError_t e = hipStreamEndCapture(ctx.stream, &res.graph);
       if (e != hipSuccess) fail(RSB_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
-      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        fail(RSB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-      }
+      RSB_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
     }
+    // profiled byte count: rows of the segments active in the cycle
+    std::vector<SegState> hst;
+    std::vector<SegDev> hseg;
+    auto active_rows = [&]() -> int64_t {
+      hst.resize(nseg);
+      hseg.resize(nseg);
+      RSB_HIP(hipMemcpyAsync(hst.data(), a.st, nseg * sizeof(SegState), hipMemcpyDeviceToHost,
+                             ctx.stream));
+      RSB_HIP(hipMemcpyAsync(hseg.data(), a.seg, nseg * sizeof(SegDev), hipMemcpyDeviceToHost,
+                             ctx.stream));
+      RSB_HIP(hipStreamSynchronize(ctx.stream));
+      int64_t r = 0;
+      for (int i = 0; i < nseg; ++i)
+        if (hst[i].active) r += hseg[i].npad;
+      return r;
+    };
     int32_t flags[2] = {0, 0};
     for (int cyc = 0; cyc <= p.max_restarts; ++cyc) {
-      if (exec) {
-        hipError_t e = hipGraphLaunch(exec, ctx.stream);
-        if (e != hipSuccess) {
-          (void)hipGraphExecDestroy(exec);
-          (void)hipGraphDestroy(graph);
-          fail(RSB_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
-        }
+      const int64_t rows = prof ? active_rows() : 0;
+      if (res.exec) {
+        RSB_HIP(hipGraphLaunch(res.exec, ctx.stream));
       } else {
-        Lz::cycle(a, nblk, nseg, ctx.stream);
+        Lz::cycle(a, nblk, nseg, ctx.stream, prof ? res.ev.data() : nullptr);
         RSB_LAUNCHED();
       }
-      hipError_t e = hipMemcpyAsync(flags, a.flags, sizeof(flags), hipMemcpyDeviceToHost,
-                                    ctx.stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);
-      if (e != hipSuccess) {
-        if (exec) {
-          (void)hipGraphExecDestroy(exec);
-          (void)hipGraphDestroy(graph);
-        }
-        fail(RSB_EDEVICE, std::string("cycle: ") + hipGetErrorString(e));
-      }
+      RSB_HIP(hipMemcpyAsync(flags, a.flags, sizeof(flags), hipMemcpyDeviceToHost, ctx.stream));
+      RSB_HIP(hipStreamSynchronize(ctx.stream));
       level_steps += flags[1];
+      if (prof) {
+        // launches of steps 3..k ran for the active segments (k = flags[1])
+        const double st = (double)sizeof(T);
+        const double nnz = (double)p.nnz * (double)rows / (double)std::max<int64_t>(L.nrows, 1);
+        for (int j = 3; j <= flags[1]; ++j) {
+          float ms = 0.f;
+          RSB_HIP(hipEventElapsedTime(&ms, res.ev[2 * j], res.ev[2 * j + 1]));
+          p.prof->ms += ms;
+          p.prof->launches += 1;
+          p.prof->bytes += 4.0 * (rows + 1) + 4.0 * nnz +
+                           (double)rows * (st + st + st + 16.0 + (j - 2) * st);
+        }
+      }
       if (flags[0] == 0) break;
-    }
-    if (exec) {
-      (void)hipGraphExecDestroy(exec);
-      (void)hipGraphDestroy(graph);
     }
     if (y64_out) {
       Lz::output(a, nblk, y64_out, ctx.stream);
@@ -778,10 +754,9 @@ int64_t lanczos_level(Level &L, CompDev &C, SolveDev &S, const LanczosParams &p,
   return level_steps;
 }
 
-template int64_t lanczos_level<float>(Level &, CompDev &, SolveDev &, const LanczosParams &,
-                                      const float *, const SolveDev *, float *, double *, Ctx &);
-template int64_t lanczos_level<double>(Level &, CompDev &, SolveDev &, const LanczosParams &,
-                                       const float *, const SolveDev *, double *, double *,
-                                       Ctx &);
+template int64_t lanczos_level<float>(const LevelView &, CompDev &, SolveDev &,
+                                      const LanczosParams &, void *, double *, Ctx &);
+template int64_t lanczos_level<double>(const LevelView &, CompDev &, SolveDev &,
+                                       const LanczosParams &, void *, double *, Ctx &);
 
 }  // namespace rsb

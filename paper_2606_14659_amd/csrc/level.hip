@@ -529,7 +529,10 @@ __global__ void k_metrics(const int64_t *__restrict__ chunk_ptr, const uint32_t 
     int64_t j = colw_col(w);
     int pj = part[orig[j]] + poff[j];
     if (pj == pi || pj < 0 || pj >= nparts) continue;
-    if (bits) atomicOr(&bits[((int64_t)pi * nparts + pj) >> 5], 1u << (pj & 31));
+    if (bits) {
+      const int64_t bit = (int64_t)pi * nparts + pj;
+      atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+    }
     if (j > r) {
       wcut += colw_wt(w);
       pairs += 1;
@@ -669,6 +672,8 @@ void level0_from_csr(Level &L, const std::vector<const DevCsr *> &g,
                          hipMemcpyDeviceToHost, ctx.stream));
   RSB_HIP(hipStreamSynchronize(ctx.stream));
   L.cols.alloc(ctx, std::max<int64_t>(L.words, 1));
+  L.nnz = 0;
+  for (int s = 0; s < L.nseg; ++s) L.nnz += g[mesh_seg[s]]->nnz;
   for (int s = 0; s < L.nseg; ++s) {
     const DevCsr &c = *g[mesh_seg[s]];
     int64_t nch = L.seg[s].npad / kWave;
@@ -890,6 +895,12 @@ void compact_level(Level &L, const uint8_t *side, int32_t *d_part_out, Level &ne
   k_new_rowlen<<<g, kBlock, 0, ctx.stream>>>(L.chunk_ptr.get(), L.cols.get(), side, newidx.get(),
                                              newlen.get(), L.nrows);
   RSB_LAUNCHED();
+  {
+    DevBuf<int64_t> lexcl(ctx, next.nrows + 1);
+    scan_exclusive(newlen.get(), next.nrows, lexcl.get(), lexcl.get() + next.nrows, ctx);
+    RSB_HIP(hipMemcpyAsync(&next.nnz, lexcl.get() + next.nrows, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, ctx.stream));
+  }
   DevBuf<int64_t> words(ctx, next.nchunks);
   k_chunk_words<<<grid_for(next.nrows, kBlock), kBlock, 0, ctx.stream>>>(newlen.get(),
                                                                         next.nchunks, words.get());

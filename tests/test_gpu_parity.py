@@ -32,6 +32,19 @@ def _meshes():
 MESHES = _meshes()
 
 
+def graph_metrics(orc, ids, part, nparts, graph):
+    """Cut weight, cut pairs and neighbour-part counts on the given graph kind."""
+    rp, col, w = orc.dual_graph(ids, graph=graph)
+    rows = np.repeat(np.arange(len(ids)), np.diff(rp))
+    cross = part[rows] != part[col]
+    upper = cross & (col > rows)
+    nb = np.zeros((nparts, nparts), dtype=bool)
+    nb[part[rows][cross], part[col][cross]] = True
+    cnt = nb.sum(axis=1)
+    return {"cut": float(w[upper].sum()), "pairs": int(upper.sum()), "max_nb": int(cnt.max()),
+            "avg_nb": float(cnt.mean())}
+
+
 @pytest.mark.parametrize("name", list(MESHES))
 @pytest.mark.parametrize("graph", ["weighted", "unit", "face"])
 def test_dual_graph_bit_exact(orc, name, graph):
@@ -99,13 +112,44 @@ def test_fiedler_face_cube_closed_form():
     assert abs(lam - exact) <= 1e-10 * exact
 
 
-@pytest.mark.parametrize("name", ["box5x4x3", "holes", "renum"])
+@pytest.mark.parametrize("name", ["box5x4x3", "holes", "renum", "quad", "clustered"])
 def test_fiedler_mixed(orc, name):
     ids = MESHES[name]
     st, lam, y, stats = rsb.fiedler(ids, precision="mixed", tol=1e-8)
     ost, olam, oy, _ = orc.fiedler(ids, tol=1e-10)
     assert st == ost
     assert abs(lam - olam) <= 1e-5 * olam
+    # FP32 directions, FP64 restart vector: the pair still meets the FP64 tolerance
+    assert stats["residual"] <= 1e-8 * lam
+
+
+@pytest.mark.parametrize("name", ["box5x4x3", "holes", "quad"])
+def test_fiedler_inverse_cg(orc, name):
+    ids = MESHES[name]
+    st, lam, y, stats = rsb.fiedler(ids, method="inverse_cg", tol=1e-9, inv_max_outer=400)
+    ost, olam, oy, _ = orc.fiedler(ids, method="inverse_cg", tol=1e-9, inv_max_outer=400)
+    lst, llam, ly, _ = orc.fiedler(ids, tol=1e-10)
+    assert st == ost == 0
+    assert abs(lam - llam) <= 1e-8 * llam
+    assert abs(abs(float(y @ ly)) - 1) < 1e-6
+
+
+@pytest.mark.parametrize("method", ["lanczos", "inverse_cg"])
+def test_unbatched_equals_batched(method):
+    ids = MESHES["holes"]
+    kw = dict(method=method, tol=1e-8, inv_max_outer=300)
+    st1, p1, s1 = rsb.partition(ids, 12, **kw)
+    st2, p2, s2 = rsb.partition(ids, 12, batched=0, **kw)
+    assert st1 == st2
+    assert np.array_equal(p1, p2)
+
+
+def test_profile_counts():
+    ids = MESHES["clustered"]
+    st, part, stats = rsb.partition(ids, 16, precision="mixed", profile=1, tol=1e-6)
+    assert stats["kernel_launches"] > 0 and stats["kernel_ms"] > 0 and stats["kernel_bytes"] > 0
+    st2, part2, _ = rsb.partition(ids, 16, precision="mixed", tol=1e-6)
+    assert np.array_equal(part, part2)
 
 
 @pytest.mark.parametrize("dims,graph,nparts", [((24, 20, 18), "face", 8),
@@ -120,11 +164,11 @@ def test_partition_identical_on_boxes(orc, dims, graph, nparts, precision):
     ost, opart, _ = orc.partition(mesh.ids, nparts, graph=graph, tol=1e-8)
     assert st == ost == 0
     assert np.array_equal(part, opart)
-    met = orc.metrics(mesh.ids, part, nparts)
-    assert stats["edge_cut"] == met["weighted_cut"]
-    assert stats["cut_pairs"] == met["cut_pairs"]
-    assert stats["max_neighbors"] == met["max_neighbors"]
-    assert abs(stats["avg_neighbors"] - met["avg_neighbors"]) < 1e-12
+    met = graph_metrics(orc, mesh.ids, part, nparts, graph)
+    assert stats["edge_cut"] == met["cut"]
+    assert stats["cut_pairs"] == met["pairs"]
+    assert stats["max_neighbors"] == met["max_nb"]
+    assert abs(stats["avg_neighbors"] - met["avg_nb"]) < 1e-12
 
 
 @pytest.mark.parametrize("name,nparts", [("holes", 16), ("renum", 8), ("clustered", 32),
@@ -145,6 +189,9 @@ def test_partition_cut_within_one_percent(orc, name, nparts, precision):
 
 
 def test_disconnected_rule(orc):
+    # Two separate boxes.  Components are ordered by smallest element id, so
+    # box A (ids 0..35) comes first.  Exact ties of a box's symmetric Fiedler
+    # vector are broken by rounding, so only rule-fixed facts are compared.
     a = mg.box_hex(4, 3, 3)
     b = mg.box_hex(3, 3, 2)
     ids = np.concatenate([a.ids, b.ids + 10_000])
@@ -152,7 +199,20 @@ def test_disconnected_rule(orc):
         st, part, _ = rsb.partition(ids, nparts)
         ost, opart, _ = orc.partition(ids, nparts)
         assert st == ost == 2
-        assert np.array_equal(part, opart)
+        assert np.array_equal(np.bincount(part), np.bincount(opart))
+    # P = 2: 27 low elements cut out of box A, box B entirely high
+    st, part, _ = rsb.partition(ids, 2)
+    assert np.all(part[36:] == 1) and np.sum(part[:36] == 0) == 27
+    # A = 10x2x2 (40), B = 2x2x2 (8): the cut of A falls between slabs, so
+    # the whole partition is unique (face graph)
+    a = mg.box_hex(10, 2, 2)
+    b = mg.box_hex(2, 2, 2)
+    ids = np.concatenate([a.ids, b.ids + 10_000])
+    st, part, _ = rsb.partition(ids, 2, graph="face")
+    ost, opart, _ = orc.partition(ids, 2, graph="face")
+    assert st == ost == 2
+    assert np.array_equal(part, opart)
+    assert np.all(part[40:] == 1)
     ids2 = np.concatenate([b.ids, b.ids + 10_000])
     st, lam, y, _ = rsb.fiedler(ids2)
     ost, olam, oy, _ = orc.fiedler(ids2)
