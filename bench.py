@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--workload", default="box256x256x128-clustered10-renum-4096",
                     choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--tol", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=1e-2)
     ap.add_argument("--m", type=int, default=100)
     ap.add_argument("--max-restarts", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")

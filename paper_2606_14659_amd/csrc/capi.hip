@@ -172,6 +172,7 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     LevelView v = view_of(L);
     v.nseg = 1;
     v.nblk = os.nblk;
+    v.ngrp = os.ngrp;
     v.seg = os.seg.get();
     v.blk = os.blk.get();
     v.grp = os.grp.get();

@@ -15,6 +15,9 @@ constexpr int kWave = 64;    // CDNA wavefront width
 constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
 constexpr int kMaxM = 250;   // largest Lanczos cycle length
 constexpr int kGroup = 32;   // blocks per first-level reduction group
+constexpr int kSlotGroup = 16;  // ELL slots a row reads at once (unconditional loads)
+// zero words after the last slice so that a row may read a whole slot group
+constexpr int64_t kColSlack = (int64_t)kSlotGroup * 64;
 
 // ---------------------------------------------------------------------------
 // Errors: internal code throws, the C entry points convert to return codes.

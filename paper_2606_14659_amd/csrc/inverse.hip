@@ -48,12 +48,12 @@ __global__ __launch_bounds__(kBlock) void k_inv_begin(InvArgs a) {
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
   if (!S.solve) return;
+  const TileRows<RPT> tr(b);
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    if (lr >= b.nrows) break;
-    const int64_t row = b.row0 + lr;
+    if (!tr.ok[r]) continue;
+    const int64_t row = tr.row[r];
     const bool in = (a.root[row] == S.strad);
     const double u = in ? S.invsqrt_nc : 0.0;
     const double x = in ? start_value(a.seed, a.gid[row]) : 0.0;
@@ -63,20 +63,10 @@ __global__ __launch_bounds__(kBlock) void k_inv_begin(InvArgs a) {
     acc[1] += x * x;
   }
   block_reduce_into<2>(acc, red, vals, 2);
-  if (!hier_reduce(a, lb, vals, 2)) return;
-  if (threadIdx.x == 0) {
-    SegState &W = a.st[b.seg];
-    W.c = vals[0];
-    W.s = 1.0 / sqrt(fmax(vals[1] - vals[0] * vals[0], 1e-300));
-    W.active = 1;
-    W.converged = 0;
-    W.cycles = 0;
-    W.steps = 0;
-    W.theta = 0.0;
-  }
+  write_partials(a, lb, vals, 2);
 }
 
-// x = 0, r = b_hat = (b - c u0) s, p_old = 0; rr = r^T r.
+// x = 0, r = b_hat = (b - c u0) s, p_old = 0; partial sums of r^T r.
 template <int RPT>
 __global__ __launch_bounds__(kBlock) void k_cg_init(InvArgs a) {
   __shared__ double red[4];
@@ -85,30 +75,25 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(InvArgs a) {
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
   if (!S.active) return;
+  const TileRows<RPT> tr(b);
   double acc[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    if (lr >= b.nrows) break;
-    const int64_t row = b.row0 + lr;
+    const int64_t row = tr.row[r];
     const double rv = (a.B[row] - S.c * a.U0[row]) * S.s;
-    a.R[row] = rv;
-    a.X[row] = 0.0;
-    a.P1[row] = 0.0;
-    acc[0] += rv * rv;
+    if (tr.ok[r]) {
+      a.R[row] = rv;
+      a.X[row] = 0.0;
+      a.P1[row] = 0.0;
+      acc[0] += rv * rv;
+    }
   }
   block_reduce_into<1>(acc, red, vals, 1);
-  if (!hier_reduce(a, lb, vals, 1)) return;
-  if (threadIdx.x == 0) {
-    SegState &W = a.st[b.seg];
-    W.rr = vals[0];
-    W.cg_it = 0;
-    W.cg_done = (sqrt(vals[0]) <= a.cg_tol) ? 1 : 0;
-    W.cg_beta = 0.0;
-  }
+  write_partials(a, lb, vals, 1);
 }
 
-// p_new = r + beta p_old (rows) and L p_new (gathers r and p_old); p^T L p.
+// p_new = r + beta p_old (rows) and L p_new (gathers r and p_old); partial
+// sums of p^T L p.
 template <int RPT>
 __global__ __launch_bounds__(kBlock) void k_cg_a(InvArgs a, int it) {
   __shared__ double red[4];
@@ -120,33 +105,46 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(InvArgs a, int it) {
   const double *Pold = (it & 1) ? a.P0 : a.P1;
   double *Pnew = (it & 1) ? a.P1 : a.P0;
   const double beta = S.cg_beta;
+  const TileRows<RPT> tr(b);
   double acc[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    if (lr >= b.nrows) break;
-    const int64_t row = b.row0 + lr;
+    const int64_t row = tr.row[r];
     const double pi = a.R[row] + beta * Pold[row];
     const int64_t c = row >> 6;
     const int lane = (int)(row & 63);
     const int64_t p = a.chunk_ptr[c];
     const int width = (int)((a.chunk_ptr[c + 1] - p) >> 6);
+    const uint32_t *cp = a.cols + p + lane;
     double lp = 0.0;
-    for (int k = 0; k < width; ++k) {
-      const uint32_t w = a.cols[p + (int64_t)k * 64 + lane];
-      const uint32_t j = colw_col(w);
-      lp += (double)colw_wt(w) * (pi - (a.R[j] + beta * Pold[j]));
+    // unconditional loads of a whole slot group, masked as in lap_row
+    for (int k0 = 0; k0 < width; k0 += kSlotGroup) {
+      uint32_t w[kSlotGroup];
+#pragma unroll
+      for (int u = 0; u < kSlotGroup; ++u) w[u] = cp[(int64_t)(k0 + u) * 64];
+#pragma unroll
+      for (int u = 0; u < kSlotGroup; ++u) w[u] = (k0 + u < width) ? w[u] : 0u;
+      double rj[kSlotGroup], pj[kSlotGroup];
+#pragma unroll
+      for (int u = 0; u < kSlotGroup; ++u) {
+        rj[u] = a.R[colw_col(w[u])];
+        pj[u] = Pold[colw_col(w[u])];
+      }
+#pragma unroll
+      for (int u = 0; u < kSlotGroup; ++u)
+        lp += colw_wt(w[u]) ? (double)colw_wt(w[u]) * (pi - (rj[u] + beta * pj[u])) : 0.0;
     }
-    Pnew[row] = pi;
-    a.LP[row] = lp;
-    acc[0] += pi * lp;
+    if (tr.ok[r]) {
+      Pnew[row] = pi;
+      a.LP[row] = lp;
+      acc[0] += pi * lp;
+    }
   }
   block_reduce_into<1>(acc, red, vals, 1);
-  if (!hier_reduce(a, lb, vals, 1)) return;
-  if (threadIdx.x == 0) a.st[b.seg].cg_alpha = a.st[b.seg].rr / vals[0];
+  write_partials(a, lb, vals, 1);
 }
 
-// x += alpha p; r -= alpha L p; Polak-Ribiere beta; stop test.
+// x += alpha p; r -= alpha L p; partial sums of r_new^T r_new, r_new^T r_old.
 template <int RPT>
 __global__ __launch_bounds__(kBlock) void k_cg_b(InvArgs a, int it) {
   __shared__ double red[4 * 2];
@@ -157,38 +155,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(InvArgs a, int it) {
   if (!S.active || S.cg_done) return;
   const double *Pnew = (it & 1) ? a.P1 : a.P0;
   const double alpha = S.cg_alpha;
+  const TileRows<RPT> tr(b);
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    if (lr >= b.nrows) break;
-    const int64_t row = b.row0 + lr;
-    a.X[row] += alpha * Pnew[row];
+    const int64_t row = tr.row[r];
+    const double xn = a.X[row] + alpha * Pnew[row];
     const double rold = a.R[row];
     const double rnew = rold - alpha * a.LP[row];
-    a.R[row] = rnew;
-    acc[0] += rnew * rnew;
-    acc[1] += rnew * rold;
+    if (tr.ok[r]) {
+      a.X[row] = xn;
+      a.R[row] = rnew;
+      acc[0] += rnew * rnew;
+      acc[1] += rnew * rold;
+    }
   }
   block_reduce_into<2>(acc, red, vals, 2);
-  if (!hier_reduce(a, lb, vals, 2)) return;
-  if (threadIdx.x != 0) return;
-  SegState &W = a.st[b.seg];
-  W.cg_it += 1;
-  W.steps += 1;
-  atomicAdd(&a.ctr[0], 1ull);
-  const double rr = vals[0];
-  if (sqrt(rr) <= a.cg_tol || W.cg_it >= a.cg_max_iter) {
-    W.cg_done = 1;
-  } else {
-    W.cg_beta = (rr - vals[1]) / W.rr;
-    W.rr = rr;
-    atomicAdd(&a.flags[0], 1);
-  }
+  write_partials(a, lb, vals, 2);
 }
 
-// After a solve: transform of the new b = x (c, s) and a shift estimate
-// theta = x_hat^T b_hat / x_hat^T x_hat (L x ~ b_hat).
+// After a solve: partial sums for the transform of the new b = x (c, s) and
+// the shift estimate theta = x_hat^T b_hat / x_hat^T x_hat (L x ~ b_hat).
 template <int RPT>
 __global__ __launch_bounds__(kBlock) void k_inv_eval(InvArgs a) {
   __shared__ double red[4 * 3];
@@ -197,12 +184,12 @@ __global__ __launch_bounds__(kBlock) void k_inv_eval(InvArgs a) {
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
   if (!S.active) return;
+  const TileRows<RPT> tr(b);
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    if (lr >= b.nrows) break;
-    const int64_t row = b.row0 + lr;
+    if (!tr.ok[r]) continue;
+    const int64_t row = tr.row[r];
     const double x = a.X[row];
     const double bh = (a.B[row] - S.c * a.U0[row]) * S.s;
     a.B[row] = x;  // the next b (row-local: read before write)
@@ -211,18 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_inv_eval(InvArgs a) {
     acc[2] += x * bh;
   }
   block_reduce_into<3>(acc, red, vals, 3);
-  if (!hier_reduce(a, lb, vals, 3)) return;
-  if (threadIdx.x == 0) {
-    SegState &W = a.st[b.seg];
-    const double c = vals[0];
-    const double xx = fmax(vals[1] - c * c, 1e-300);
-    W.c = c;
-    W.s = 1.0 / sqrt(xx);
-    W.theta = vals[2] / xx;  // (u0^T b_hat = 0)
-  }
+  write_partials(a, lb, vals, 3);
 }
 
-// Rayleigh-quotient residual of the normalised new b (= x); outer stop test.
+// Partial sums of the Rayleigh-quotient residual of the normalised new b.
 template <int RPT>
 __global__ __launch_bounds__(kBlock) void k_inv_res(InvArgs a) {
   __shared__ double red[4 * 3];
@@ -232,37 +211,119 @@ __global__ __launch_bounds__(kBlock) void k_inv_res(InvArgs a) {
   const SegState S = a.st[b.seg];
   if (!S.active) return;
   const double c = S.c, sc = S.s, th = S.theta;
+  const TileRows<RPT> tr(b);
   double p[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    if (lr >= b.nrows) break;
-    const int64_t row = b.row0 + lr;
+    const int64_t row = tr.row[r];
     const double xi = a.X[row];
     const double y = (xi - c * a.U0[row]) * sc;
     const double ly = sc * lap_row<double>(a.chunk_ptr, a.cols, a.X, row, xi);
     const double rr = ly - th * y;
-    p[0] += rr * rr;
-    p[1] += y * ly;
-    p[2] += y * y;
+    if (tr.ok[r]) {
+      p[0] += rr * rr;
+      p[1] += y * ly;
+      p[2] += y * y;
+    }
   }
   block_reduce_into<3>(p, red, vals, 3);
-  if (!hier_reduce(a, lb, vals, 3)) return;
+  write_partials(a, lb, vals, 3);
+}
+
+// Reductions and the per-segment logic that finishes each launch above.
+enum InvOp { OP_BEGIN, OP_CG_INIT, OP_CG_A, OP_CG_B, OP_EVAL, OP_RES };
+
+template <int OP>
+__global__ __launch_bounds__(kBlock) void k_inv_reduce(InvArgs a) {
+  __shared__ double vals[4];
+  const int g = blockIdx.x;
+  const int s = a.grp[g].seg;
+  const SegState S = a.st[s];
+  int nval;
+  switch (OP) {
+    case OP_BEGIN:
+      if (!S.solve) return;
+      nval = 2;
+      break;
+    case OP_CG_INIT:
+      if (!S.active) return;
+      nval = 1;
+      break;
+    case OP_CG_A:
+      if (!S.active || S.cg_done) return;
+      nval = 1;
+      break;
+    case OP_CG_B:
+      if (!S.active || S.cg_done) return;
+      nval = 2;
+      break;
+    default:
+      if (!S.active) return;
+      nval = 3;
+      break;
+  }
+  if (!group_reduce(a, g, vals, nval)) return;
   if (threadIdx.x != 0) return;
-  SegState &W = a.st[b.seg];
-  const double rho = vals[1] / vals[2];
-  const double dth = th - rho;
-  const double res = sqrt(fmax(vals[0] - dth * dth * vals[2], 0.0));
-  W.res = res;
-  W.rho = rho;
-  W.cycles += 1;
-  if (W.cg_it <= 1 || res <= a.tol * rho) {
-    W.converged = 1;
-    W.active = 0;
-  } else if (W.cycles >= a.max_outer) {
-    W.active = 0;
-  } else {
-    atomicAdd(&a.flags[0], 1);
+  SegState &W = a.st[s];
+  switch (OP) {
+    case OP_BEGIN:
+      W.c = vals[0];
+      W.s = 1.0 / sqrt(fmax(vals[1] - vals[0] * vals[0], 1e-300));
+      W.active = 1;
+      W.converged = 0;
+      W.cycles = 0;
+      W.steps = 0;
+      W.theta = 0.0;
+      break;
+    case OP_CG_INIT:
+      W.rr = vals[0];
+      W.cg_it = 0;
+      W.cg_done = (sqrt(vals[0]) <= a.cg_tol) ? 1 : 0;
+      W.cg_beta = 0.0;
+      break;
+    case OP_CG_A:
+      W.cg_alpha = W.rr / vals[0];
+      break;
+    case OP_CG_B: {
+      W.cg_it += 1;
+      W.steps += 1;
+      atomicAdd(&a.ctr[0], 1ull);
+      const double rr = vals[0];
+      if (sqrt(rr) <= a.cg_tol || W.cg_it >= a.cg_max_iter) {
+        W.cg_done = 1;
+      } else {
+        W.cg_beta = (rr - vals[1]) / W.rr;
+        W.rr = rr;
+        atomicAdd(&a.flags[0], 1);
+      }
+      break;
+    }
+    case OP_EVAL: {
+      const double c = vals[0];
+      const double xx = fmax(vals[1] - c * c, 1e-300);
+      W.c = c;
+      W.s = 1.0 / sqrt(xx);
+      W.theta = vals[2] / xx;  // (u0^T b_hat = 0)
+      break;
+    }
+    default: {
+      const double th = W.theta;
+      const double rho = vals[1] / vals[2];
+      const double dth = th - rho;
+      const double res = sqrt(fmax(vals[0] - dth * dth * vals[2], 0.0));
+      W.res = res;
+      W.rho = rho;
+      W.cycles += 1;
+      if (W.cg_it <= 1 || res <= a.tol * rho) {
+        W.converged = 1;
+        W.active = 0;
+      } else if (W.cycles >= a.max_outer) {
+        W.active = 0;
+      } else {
+        atomicAdd(&a.flags[0], 1);
+      }
+      break;
+    }
   }
 }
 
@@ -316,9 +377,10 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
   a.flags = S.n_active.get();
   a.ctr = (unsigned long long *)S.counters.get();
   a.seed = p.seed;
-  const int nblk = L.nblk;
+  const int nblk = L.nblk, ngrp = L.ngrp;
   hipStream_t s = ctx.stream;
   k_inv_begin<RPT><<<nblk, kBlock, 0, s>>>(a);
+  k_inv_reduce<OP_BEGIN><<<ngrp, kBlock, 0, s>>>(a);
   RSB_LAUNCHED();
   int64_t steps = 0;
   int32_t flags = 0;
@@ -328,6 +390,7 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
   };
   for (int outer = 0; outer < p.max_outer; ++outer) {
     k_cg_init<RPT><<<nblk, kBlock, 0, s>>>(a);
+    k_inv_reduce<OP_CG_INIT><<<ngrp, kBlock, 0, s>>>(a);
     RSB_LAUNCHED();
     // CG chunks, each as one graph launch (or direct launches)
     hipGraphExec_t exec = nullptr;
@@ -336,7 +399,9 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
       k_flag_reset<<<1, 1, 0, s>>>(a.flags);
       for (int it = 0; it < kCgChunk; ++it) {
         k_cg_a<RPT><<<nblk, kBlock, 0, s>>>(a, it);
+        k_inv_reduce<OP_CG_A><<<ngrp, kBlock, 0, s>>>(a);
         k_cg_b<RPT><<<nblk, kBlock, 0, s>>>(a, it);
+        k_inv_reduce<OP_CG_B><<<ngrp, kBlock, 0, s>>>(a);
       }
     };
     if (use_graph) {
@@ -370,7 +435,9 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
     }
     k_flag_reset<<<1, 1, 0, s>>>(a.flags);
     k_inv_eval<RPT><<<nblk, kBlock, 0, s>>>(a);
+    k_inv_reduce<OP_EVAL><<<ngrp, kBlock, 0, s>>>(a);
     k_inv_res<RPT><<<nblk, kBlock, 0, s>>>(a);
+    k_inv_reduce<OP_RES><<<ngrp, kBlock, 0, s>>>(a);
     RSB_LAUNCHED();
     read_flags();
     if (flags == 0) break;

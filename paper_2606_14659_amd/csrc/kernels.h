@@ -110,7 +110,7 @@ struct Level {
 // level's row indexing (stride nrows), the tables may cover a subset.
 struct LevelView {
   int64_t nrows = 0;
-  int32_t nseg = 0, nblk = 0, rpt = 16;
+  int32_t nseg = 0, nblk = 0, ngrp = 0, rpt = 16;
   const SegDev *seg = nullptr;
   const BlkDev *blk = nullptr;
   const GrpDev *grp = nullptr;
@@ -125,6 +125,7 @@ inline LevelView view_of(const Level &L) {
   v.nrows = L.nrows;
   v.nseg = L.nseg;
   v.nblk = L.nblk;
+  v.ngrp = L.ngrp;
   v.rpt = L.rpt;
   v.seg = L.d_seg.get();
   v.blk = L.d_blk.get();

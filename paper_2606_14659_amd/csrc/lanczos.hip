@@ -5,20 +5,21 @@
 // to the component being cut, orthogonal to the ones vector of that component
 // (Sec. 4: L x = lambda x with 1^T x = 0).  Per Lanczos step j of a cycle:
 //
-//   project  (one launch): q_j = (w - c u0) s is written to the basis, the
-//            Laplacian is applied in difference form (L q)_i = s sum_j w_ij
-//            (w_i - w_j), and h = [u0, q_1 .. q_j]^T (L q_j) is reduced;
-//   update   (one launch): w = L q_j - [u0, Q] h, ||w||^2 reduced; alpha_j =
+//   project: q_j = (w - c u0) s is written to the basis, the Laplacian is
+//            applied in difference form (L q)_i = s sum_j w_ij (w_i - w_j),
+//            and the partial sums of h = [u0, q_1 .. q_j]^T (L q_j) are
+//            written per block;
+//   update:  w = L q_j - [u0, Q] h and the partial sums of ||w||^2; alpha_j =
 //            h_j, beta_{j+1} = ||w||.  If the norm dropped below 1/sqrt(2) of
 //            the three-term-recurrence norm a second Gram-Schmidt pass runs
-//            (two more launches that return at once otherwise).
+//            (its launches return at once otherwise).
 //
-// q_{j+1} = w / beta_{j+1} is never formed as a separate pass: the next
-// project launch reads w and applies the scale.  After m steps (or
-// breakdown) the tridiagonal eigenproblem is solved on the device, the Ritz
-// vector y = Q t becomes the next start vector and its residual decides
-// convergence.  Reductions are two-level and in a fixed order (per block,
-// per group of 32 blocks, per segment), done by the last block to finish.
+// Each of these streaming launches is followed by a small reduction launch
+// (fixed summation order per segment) that finishes the step.  q_{j+1} =
+// w / beta_{j+1} is never formed as a separate pass: the next project launch
+// reads w and applies the scale.  After m steps (or breakdown) the
+// tridiagonal eigenproblem is solved on the device, the Ritz vector y = Q t
+// becomes the next start vector and its residual decides convergence.
 //
 // Precision.  The restart vector Y (the Ritz vector of the previous cycle),
 // u0, q_1 and the first residual direction are FP64 in both modes; the
@@ -101,12 +102,51 @@ __device__ inline typename StepTypes<T, STEP>::Tw *step_out(const LzArgs<T> &a, 
   else return (j & 1) ? a.Wt1 : a.Wt0;
 }
 
-// basis vector k at row (k = 0: u0, k = 1: q_1, k >= 2: q_k)
-template <typename T>
-__device__ inline double basis_at(const LzArgs<T> &a, int k, int64_t row) {
-  if (k == 0) return a.U0[row];
-  if (k == 1) return a.Q1[row];
-  return (double)a.V[(int64_t)k * a.vs + row];
+// v_k^T z over one tile for a wavefront: slices of 64 rows, NSL of them
+// (compile-time for full tiles), lane-strided, all loads issued together.
+template <int NSL, typename P>
+__device__ inline double wave_dot_full(const P *__restrict__ v, const double *zs, int lane) {
+  double x[NSL];
+#pragma unroll
+  for (int t = 0; t < NSL; ++t) x[t] = (double)v[t * kWave];
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < NSL; ++t) acc += x[t] * zs[t * kWave + lane];
+  return acc;
+}
+
+template <typename P>
+__device__ inline double wave_dot_part(const P *__restrict__ v, const double *zs, int lane,
+                                       int nsl) {
+  double acc = 0.0;
+  for (int t = 0; t < nsl; ++t) acc += (double)v[t * kWave] * zs[t * kWave + lane];
+  return acc;
+}
+
+// acc[r] += sum_{k = k0..k1} c_k V[k][row_r], 4 basis vectors per round so
+// that 4 * RPT loads are in flight per thread.
+template <typename T, int RPT>
+__device__ inline void accumulate_basis(const LzArgs<T> &a, const TileRows<RPT> &tr,
+                                        const double *coef, int k0, int k1, double (&acc)[RPT]) {
+  int k = k0;
+  for (; k + 4 <= k1 + 1; k += 4) {
+    T v[4][RPT];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) v[kk][r] = a.V[(int64_t)(k + kk) * a.vs + tr.row[r]];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const double ck = coef[k + kk];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) acc[r] += (double)v[kk][r] * ck;
+    }
+  }
+  for (; k <= k1; ++k) {
+    const double ck = coef[k];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) acc[r] += (double)a.V[(int64_t)k * a.vs + tr.row[r]] * ck;
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -121,12 +161,12 @@ __global__ __launch_bounds__(kBlock) void k_lz_begin(LzArgs<T> a) {
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
   if (!S.solve) return;
+  const TileRows<RPT> tr(b);
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    if (lr >= b.nrows) break;
-    const int64_t row = b.row0 + lr;
+    if (!tr.ok[r]) continue;
+    const int64_t row = tr.row[r];
     const bool in = (a.root[row] == S.strad);
     const double u = in ? S.invsqrt_nc : 0.0;
     const double x = in ? start_value(a.seed, a.gid[row]) : 0.0;
@@ -136,35 +176,27 @@ __global__ __launch_bounds__(kBlock) void k_lz_begin(LzArgs<T> a) {
     acc[1] += x * x;
   }
   block_reduce_into<2>(acc, red, vals, 2);
-  if (!hier_reduce(a, lb, vals, 2)) return;
-  if (threadIdx.x == 0) {
-    SegState &W = a.st[b.seg];
-    const double c = vals[0];
-    W.c = c;
-    W.s = 1.0 / sqrt(fmax(vals[1] - c * c, 1e-300));
-    W.active = 1;
-    W.k = 0;
-    W.cycle_done = 0;
-    W.need2 = 0;
-    W.converged = 0;
-    W.restarts = 0;
-    W.tnorm = 0.0;
-    W.res = 0.0;
-    W.cycles = 0;
-    W.steps = 0;
-  }
+  write_partials(a, lb, vals, 2);
 }
 
 // ----------------------------------------------------------------------------
 // project: MODE 0 = first pass of step j (SpMV of q_j, write q_j);
 //          MODE 1 = second Gram-Schmidt pass (project the current w again).
+// Phase 1 (RPT rows per thread): the vector z to project is formed and
+// staged in LDS.  Phase 2: each wavefront takes every fourth basis vector k
+// and reduces v_k^T z over the whole tile with coalesced loads, so no
+// block-wide reduction is needed per coefficient.
 // ----------------------------------------------------------------------------
 template <typename T, int RPT, int MODE, int STEP>
 __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
   using Tin = typename StepTypes<T, STEP>::Tin;
   using Tw = typename StepTypes<T, STEP>::Tw;
-  __shared__ double red[4 * 8];
+  constexpr int TILE = kBlock * RPT;
+  constexpr int NSL = TILE / kWave;
+  __shared__ double zs[TILE];
+  __shared__ double qs[MODE == 0 ? TILE : 1];
   __shared__ double vals[kMaxM + 8];
+  __shared__ double red[kBlock / kWave];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
@@ -173,72 +205,66 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
   const Tin *Win = step_in<T, STEP>(a, j);
   Tw *Wout = step_out<T, STEP>(a, j);
   const double c = S.c, sc = S.s;
-  double z[RPT], qv[RPT], uv[RPT];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const TileRows<RPT> tr(b);
+  double zz = 0.0;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    z[r] = qv[r] = uv[r] = 0.0;
-    if (lr < b.nrows) {
-      const int64_t row = b.row0 + lr;
-      const double u = a.U0[row];
-      uv[r] = u;
-      if (MODE == 0) {
-        const Tin wi = Win[row];
-        const double qd = ((double)wi - c * u) * sc;
-        if (STEP == 1) {
-          a.Q1[row] = qd;
-          qv[r] = qd;
-        } else {
-          const T q = (T)qd;
-          a.V[(int64_t)j * a.vs + row] = q;
-          qv[r] = (double)q;
-        }
-        const Tw lq = (Tw)(sc * (double)lap_row<Tin>(a.chunk_ptr, a.cols, Win, row, wi));
-        Wout[row] = lq;
-        z[r] = (double)lq;
+    const int64_t row = tr.row[r];
+    double z, q = 0.0;
+    if (MODE == 0) {
+      const Tin wi = Win[row];
+      const double qd = ((double)wi - c * a.U0[row]) * sc;
+      const Tw lq = (Tw)(sc * (double)lap_row<Tin>(a.chunk_ptr, a.cols, Win, row, wi));
+      if (STEP == 1) {
+        q = qd;
+        if (tr.ok[r]) a.Q1[row] = qd;
       } else {
-        z[r] = (double)Wout[row];
+        const T qt = (T)qd;
+        q = (double)qt;
+        if (tr.ok[r]) a.V[(int64_t)j * a.vs + row] = qt;
       }
+      if (tr.ok[r]) Wout[row] = lq;
+      z = (double)lq;
+    } else {
+      z = (double)Wout[row];
     }
+    if (!tr.ok[r]) z = q = 0.0;
+    zs[r * kBlock + threadIdx.x] = z;
+    if (MODE == 0) qs[r * kBlock + threadIdx.x] = q;
+    zz += z * z;
   }
-  // h_k = v_k^T z for k = 0..j, plus ||z||^2 at index j+1
-  for (int k0 = 0; k0 <= j; k0 += 8) {
-    double acc[8];
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) acc[kk] = 0.0;
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int lr = r * kBlock + threadIdx.x;
-      if (lr >= b.nrows) break;
-      const int64_t row = b.row0 + lr;
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const int k = k0 + kk;
-        if (k > j) break;
-        double v;
-        if (k == 0) v = uv[r];
-        else if (MODE == 0 && k == j) v = qv[r];
-        else v = basis_at(a, k, row);
-        acc[kk] += v * z[r];
-      }
+  zz = wave_sum(zz);
+  if (lane == 0) red[wave] = zz;
+  __syncthreads();
+  // h_k = v_k^T z, k = 0..j, one wavefront per k
+  const bool full = (b.nrows == TILE);
+  const int nsl = b.nrows / kWave;
+  for (int k = wave; k <= j; k += kBlock / kWave) {
+    double acc;
+    if (MODE == 0 && k == j) {
+      acc = full ? wave_dot_full<NSL>(qs + lane, zs, lane) : wave_dot_part(qs + lane, zs, lane, nsl);
+    } else if (k <= 1) {
+      const double *v = (k == 0 ? a.U0 : a.Q1) + b.row0 + lane;
+      acc = full ? wave_dot_full<NSL>(v, zs, lane) : wave_dot_part(v, zs, lane, nsl);
+    } else {
+      const T *v = a.V + (int64_t)k * a.vs + b.row0 + lane;
+      acc = full ? wave_dot_full<NSL>(v, zs, lane) : wave_dot_part(v, zs, lane, nsl);
     }
-    block_reduce_into<8>(acc, red, vals + k0, std::min(8, j + 1 - k0));
+    acc = wave_sum(acc);
+    if (lane == 0) vals[k] = acc;
   }
-  {
-    double zz[1] = {0.0};
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) zz[0] += z[r] * z[r];
-    block_reduce_into<1>(zz, red, vals + j + 1, 1);
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) s += red[w];
+    vals[j + 1] = s;
   }
-  if (!hier_reduce(a, lb, vals, j + 2)) return;
-  double *hs = a.h + (int64_t)b.seg * a.ps;
-  for (int k = threadIdx.x; k <= j; k += kBlock) hs[k] = vals[k];
-  if (threadIdx.x == 0 && MODE == 0) a.st[b.seg].lq2 = vals[j + 1];
+  __syncthreads();
+  write_partials(a, lb, vals, j + 2);
 }
 
 // ----------------------------------------------------------------------------
-// update: w -= [u0, Q] h; ||w||^2; finish the step (PASS 1 first pass,
-// PASS 2 after the second Gram-Schmidt pass).
+// update: w -= [u0, Q] h and the partial sums of ||w||^2.
 // ----------------------------------------------------------------------------
 template <typename T, int RPT, int PASS, int STEP>
 __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
@@ -255,35 +281,194 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
   for (int k = threadIdx.x; k <= j; k += kBlock) hs[k] = hg[k];
   __syncthreads();
   Tw *Wout = step_out<T, STEP>(a, j);
+  const TileRows<RPT> tr(b);
   double acc[RPT];
+  {
+    const double h0 = hs[0], h1 = hs[1];
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
-  for (int k = 0; k <= j; ++k) {
-    const double hk = hs[k];
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int lr = r * kBlock + threadIdx.x;
-      if (lr < b.nrows) acc[r] += basis_at(a, k, b.row0 + lr) * hk;
-    }
+    for (int r = 0; r < RPT; ++r) acc[r] = a.U0[tr.row[r]] * h0 + a.Q1[tr.row[r]] * h1;
   }
+  accumulate_basis<T, RPT>(a, tr, hs, 2, j, acc);
   double nn[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    if (lr < b.nrows) {
-      const int64_t row = b.row0 + lr;
-      const Tw zt = (Tw)((double)Wout[row] - acc[r]);
-      Wout[row] = zt;
+    const Tw zt = (Tw)((double)Wout[tr.row[r]] - acc[r]);
+    if (tr.ok[r]) {
+      Wout[tr.row[r]] = zt;
       nn[0] += (double)zt * (double)zt;
     }
   }
   block_reduce_into<1>(nn, red, vals, 1);
-  if (!hier_reduce(a, lb, vals, 1)) return;
+  write_partials(a, lb, vals, 1);
+}
+
+// ----------------------------------------------------------------------------
+// Ritz vector y = Q t into Y (FP64; the next start vector) and the partial
+// sums of u0^T y and y^T y.
+// ----------------------------------------------------------------------------
+template <typename T, int RPT>
+__global__ __launch_bounds__(kBlock) void k_lz_ritz(LzArgs<T> a) {
+  __shared__ double red[4 * 2];
+  __shared__ double vals[2];
+  __shared__ double ts[kMaxM + 2];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active) return;
+  const int k = S.k;
+  // ts[c] = coefficient of basis vector c (c = 1: q_1, ...)
+  const double *tg = a.tvec + (int64_t)b.seg * a.ps;
+  if (threadIdx.x == 0) ts[0] = 0.0;
+  for (int i = threadIdx.x; i < k; i += kBlock) ts[i + 1] = tg[i];
+  __syncthreads();
+  const TileRows<RPT> tr(b);
+  double acc[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) acc[r] = a.Q1[tr.row[r]] * ts[1];
+  accumulate_basis<T, RPT>(a, tr, ts, 2, k, acc);
+  double p[2] = {0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    if (tr.ok[r]) {
+      a.Y[tr.row[r]] = acc[r];
+      p[0] += a.U0[tr.row[r]] * acc[r];
+      p[1] += acc[r] * acc[r];
+    }
+  }
+  block_reduce_into<2>(p, red, vals, 2);
+  write_partials(a, lb, vals, 2);
+}
+
+// ----------------------------------------------------------------------------
+// residual of the (projected, normalised) Ritz vector in FP64: partial sums
+// of ||L y - theta y||^2, y^T L y and y^T y.
+// ----------------------------------------------------------------------------
+template <typename T, int RPT>
+__global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
+  __shared__ double red[4 * 3];
+  __shared__ double vals[3];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active) return;
+  const double c = S.c, sc = S.s, th = S.theta;
+  const TileRows<RPT> tr(b);
+  double p[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int64_t row = tr.row[r];
+    const double wi = a.Y[row];
+    const double y = (wi - c * a.U0[row]) * sc;
+    const double ly = sc * lap_row<double>(a.chunk_ptr, a.cols, a.Y, row, wi);
+    const double rr = ly - th * y;
+    if (tr.ok[r]) {
+      p[0] += rr * rr;
+      p[1] += y * ly;
+      p[2] += y * y;
+    }
+  }
+  block_reduce_into<3>(p, red, vals, 3);
+  write_partials(a, lb, vals, 3);
+}
+
+// ----------------------------------------------------------------------------
+// Reductions and the per-segment logic that finishes each launch above.
+// ----------------------------------------------------------------------------
+enum LzOp { OP_BEGIN, OP_PROJ0, OP_PROJ1, OP_UPD1, OP_UPD2, OP_RITZ, OP_RESID };
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
+  __shared__ double vals[kMaxM + 8];
+  const int g = blockIdx.x;
+  const int s = a.grp[g].seg;
+  const SegState S = a.st[s];
+  int nval;
+  switch (OP) {
+    case OP_BEGIN:
+      if (!S.solve) return;
+      nval = 2;
+      break;
+    case OP_PROJ0:
+    case OP_UPD1:
+      if (!S.active || S.cycle_done) return;
+      nval = (OP == OP_PROJ0) ? j + 2 : 1;
+      break;
+    case OP_PROJ1:
+    case OP_UPD2:
+      if (!S.active || S.cycle_done || !S.need2) return;
+      nval = (OP == OP_PROJ1) ? j + 2 : 1;
+      break;
+    case OP_RITZ:
+      if (!S.active) return;
+      nval = 2;
+      break;
+    default:
+      if (!S.active) return;
+      nval = 3;
+      break;
+  }
+  if (!group_reduce(a, g, vals, nval)) return;
+  double *hs = a.h + (int64_t)s * a.ps;
+  if (OP == OP_PROJ0 || OP == OP_PROJ1) {
+    for (int k = threadIdx.x; k <= j; k += kBlock) hs[k] = vals[k];
+    if (threadIdx.x == 0 && OP == OP_PROJ0) a.st[s].lq2 = vals[j + 1];
+    return;
+  }
   if (threadIdx.x != 0) return;
-  SegState &W = a.st[b.seg];
+  SegState &W = a.st[s];
+  if (OP == OP_BEGIN || OP == OP_RITZ) {
+    const double c = vals[0];
+    W.c = c;
+    W.s = 1.0 / sqrt(fmax(vals[1] - c * c, 1e-300));
+    if (OP == OP_BEGIN) {
+      W.active = 1;
+      W.k = 0;
+      W.cycle_done = 0;
+      W.need2 = 0;
+      W.converged = 0;
+      W.restarts = 0;
+      W.tnorm = 0.0;
+      W.res = 0.0;
+      W.cycles = 0;
+      W.steps = 0;
+    } else {
+      W.steps += W.k;
+      atomicAdd(&a.ctr[0], (unsigned long long)W.k);
+      atomicMax(&a.flags[1], W.k);
+    }
+    return;
+  }
+  if (OP == OP_RESID) {
+    const double th = W.theta;
+    const double rho = vals[1] / vals[2];
+    const double dth = th - rho;
+    const double res = sqrt(fmax(vals[0] - dth * dth * vals[2], 0.0));
+    W.res = res;
+    W.rho = rho;
+    W.cycles += 1;
+    bool stop = false;
+    if (res <= a.tol * rho) {
+      W.converged = 1;
+      stop = true;
+    } else if (W.restarts >= a.max_restarts) {
+      stop = true;
+    }
+    if (stop) {
+      W.active = 0;
+    } else {
+      W.restarts += 1;
+      W.k = 0;
+      W.cycle_done = 0;
+      W.need2 = 0;
+      W.tnorm = 0.0;
+      atomicAdd(&a.flags[0], 1);
+    }
+    return;
+  }
+  // OP_UPD1 / OP_UPD2: finish step j
   const double w2 = vals[0];
   double alpha_j;
-  if (PASS == 1) {
+  if (OP == OP_UPD1) {
     const double hj = hs[j], hj1 = (j >= 2) ? hs[j - 1] : 0.0;
     const double ref2 = W.lq2 - hj * hj - hj1 * hj1;
     if (w2 < 0.5 * ref2) {
@@ -297,14 +482,14 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
     W.need2 = 0;
   }
   const double beta = sqrt(w2);
-  double *al = a.alpha + (int64_t)b.seg * a.ps;
-  double *be = a.beta + (int64_t)b.seg * a.ps;
+  double *al = a.alpha + (int64_t)s * a.ps;
+  double *be = a.beta + (int64_t)s * a.ps;
   al[j - 1] = alpha_j;
   const double bprev = (j >= 2) ? be[j - 1] : 0.0;
   W.tnorm = fmax(W.tnorm, fabs(alpha_j) + beta + bprev);
   W.k = j;
   // the FP64 first step breaks down only at FP64 rounding level
-  const double brk = (STEP == 1) ? 1e-12 : a.brk;
+  const double brk = (j == 1) ? 1e-12 : a.brk;
   if (j >= a.m || beta <= brk * W.tnorm) {
     W.cycle_done = 1;
   } else {
@@ -319,11 +504,11 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
 // iteration with partial pivoting by lane 0).  Ritz values below 1e-10 ||T||
 // are taken as spurious null modes and skipped.
 // ----------------------------------------------------------------------------
-__device__ inline int sturm_count(const double *a, const double *b, int k, double x) {
+__device__ inline int sturm_count(const double *a, const double *b2, int k, double x) {
   int cnt = 0;
   double q = 1.0;
   for (int i = 0; i < k; ++i) {
-    const double off = (i == 0) ? 0.0 : b[i] * b[i] / q;
+    const double off = (i == 0) ? 0.0 : b2[i] / q;
     q = (a[i] - x) - off;
     if (q == 0.0) q = -1e-300;
     cnt += (q < 0.0);
@@ -335,7 +520,7 @@ __global__ __launch_bounds__(kWave) void k_trieig(SegState *__restrict__ st,
                                                   const double *__restrict__ alpha,
                                                   const double *__restrict__ beta,
                                                   double *__restrict__ tvec, int ps, int nseg) {
-  __shared__ double ad[kMaxM], bd[kMaxM];
+  __shared__ double ad[kMaxM], bd[kMaxM], b2[kMaxM];
   __shared__ double d[kMaxM], u[kMaxM], u2[kMaxM], l[kMaxM], rhs[kMaxM];
   const int s = blockIdx.x;
   if (s >= nseg) return;
@@ -346,6 +531,7 @@ __global__ __launch_bounds__(kWave) void k_trieig(SegState *__restrict__ st,
   for (int i = lane; i < k; i += kWave) {
     ad[i] = alpha[(int64_t)s * ps + i];
     bd[i] = (i == 0) ? 0.0 : beta[(int64_t)s * ps + i];
+    b2[i] = bd[i] * bd[i];
   }
   __syncthreads();
   // Gershgorin bounds
@@ -360,13 +546,13 @@ __global__ __launch_bounds__(kWave) void k_trieig(SegState *__restrict__ st,
     hi = fmax(hi, __shfl_xor(hi, off, kWave));
   }
   const double thr = 1e-10 * S.tnorm;
-  const int c0 = sturm_count(ad, bd, k, thr);
+  const int c0 = sturm_count(ad, b2, k, thr);
   const int target = std::min(c0 + 1, k);
   lo = fmax(lo, thr);
   hi = hi + 1e-12 * fabs(hi) + 1e-300;
   for (int it = 0; it < 40; ++it) {
     const double x = lo + (hi - lo) * (double)(lane + 1) / (double)(kWave + 1);
-    const bool ge = sturm_count(ad, bd, k, x) >= target;
+    const bool ge = sturm_count(ad, b2, k, x) >= target;
     const unsigned long long mask = __ballot(ge);
     const int f = mask ? (__ffsll((unsigned long long)mask) - 1) : kWave;
     const double xf = __shfl(x, f < kWave ? f : 0, kWave);
@@ -385,7 +571,7 @@ __global__ __launch_bounds__(kWave) void k_trieig(SegState *__restrict__ st,
     const double tiny = fmax(scale, 1e-300) * 2.220446049250313e-16;
     double *t = tvec + (int64_t)s * ps;
     for (int i = 0; i < k; ++i) rhs[i] = 1.0;
-    for (int it = 0; it < 4; ++it) {
+    for (int it = 0; it < 3; ++it) {
       for (int i = 0; i < k; ++i) {
         d[i] = ad[i] - th;
         u[i] = (i + 1 < k) ? bd[i + 1] : 0.0;
@@ -428,114 +614,6 @@ __global__ __launch_bounds__(kWave) void k_trieig(SegState *__restrict__ st,
   }
 }
 
-// ----------------------------------------------------------------------------
-// Ritz vector y = Q t into Y (FP64; the next start vector) and its transform.
-// ----------------------------------------------------------------------------
-template <typename T, int RPT>
-__global__ __launch_bounds__(kBlock) void k_lz_ritz(LzArgs<T> a) {
-  __shared__ double red[4 * 2];
-  __shared__ double vals[2];
-  __shared__ double ts[kMaxM];
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const BlkDev b = a.blk[lb];
-  const SegState S = a.st[b.seg];
-  if (!S.active) return;
-  const int k = S.k;
-  const double *tg = a.tvec + (int64_t)b.seg * a.ps;
-  for (int i = threadIdx.x; i < k; i += kBlock) ts[i] = tg[i];
-  __syncthreads();
-  double acc[RPT];
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) acc[r] = 0.0;
-  for (int c = 0; c < k; ++c) {
-    const double tc = ts[c];
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int lr = r * kBlock + threadIdx.x;
-      if (lr < b.nrows) acc[r] += basis_at(a, c + 1, b.row0 + lr) * tc;
-    }
-  }
-  double p[2] = {0.0, 0.0};
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    if (lr < b.nrows) {
-      const int64_t row = b.row0 + lr;
-      a.Y[row] = acc[r];
-      p[0] += a.U0[row] * acc[r];
-      p[1] += acc[r] * acc[r];
-    }
-  }
-  block_reduce_into<2>(p, red, vals, 2);
-  if (!hier_reduce(a, lb, vals, 2)) return;
-  if (threadIdx.x == 0) {
-    SegState &W = a.st[b.seg];
-    const double c = vals[0];
-    W.c = c;
-    W.s = 1.0 / sqrt(fmax(vals[1] - c * c, 1e-300));
-    W.steps += k;
-    atomicAdd(&a.ctr[0], (unsigned long long)k);
-    atomicMax(&a.flags[1], k);
-  }
-}
-
-// ----------------------------------------------------------------------------
-// residual of the (projected, normalised) Ritz vector in FP64; convergence,
-// restart.  ||L y - rho y|| with rho the Rayleigh quotient, from
-// ||L y - theta y||^2 = ||L y - rho y||^2 + (theta - rho)^2 ||y||^2.
-// ----------------------------------------------------------------------------
-template <typename T, int RPT>
-__global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
-  __shared__ double red[4 * 3];
-  __shared__ double vals[3];
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const BlkDev b = a.blk[lb];
-  const SegState S = a.st[b.seg];
-  if (!S.active) return;
-  const double c = S.c, sc = S.s, th = S.theta;
-  double p[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int lr = r * kBlock + threadIdx.x;
-    if (lr >= b.nrows) break;
-    const int64_t row = b.row0 + lr;
-    const double wi = a.Y[row];
-    const double y = (wi - c * a.U0[row]) * sc;
-    const double ly = sc * lap_row<double>(a.chunk_ptr, a.cols, a.Y, row, wi);
-    const double rr = ly - th * y;
-    p[0] += rr * rr;
-    p[1] += y * ly;
-    p[2] += y * y;
-  }
-  block_reduce_into<3>(p, red, vals, 3);
-  if (!hier_reduce(a, lb, vals, 3)) return;
-  if (threadIdx.x != 0) return;
-  SegState &W = a.st[b.seg];
-  const double rho = vals[1] / vals[2];
-  const double dth = th - rho;
-  const double res = sqrt(fmax(vals[0] - dth * dth * vals[2], 0.0));
-  W.res = res;
-  W.rho = rho;
-  W.cycles += 1;
-  bool stop = false;
-  if (res <= a.tol * rho) {
-    W.converged = 1;
-    stop = true;
-  } else if (W.restarts >= a.max_restarts) {
-    stop = true;
-  }
-  if (stop) {
-    W.active = 0;
-  } else {
-    W.restarts += 1;
-    W.k = 0;
-    W.cycle_done = 0;
-    W.need2 = 0;
-    W.tnorm = 0.0;
-    atomicAdd(&a.flags[0], 1);
-  }
-}
-
 // final vector: y = (Y - c u0) s on the component, 0 elsewhere
 template <typename T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_lz_output(LzArgs<T> a, double *__restrict__ y64) {
@@ -560,37 +638,39 @@ __global__ void k_flags_reset(int32_t *flags) {
 
 template <typename T, int RPT>
 struct LzLaunch {
-  static void begin(const LzArgs<T> &a, int nblk, hipStream_t s) {
+  static void begin(const LzArgs<T> &a, int nblk, int ngrp, hipStream_t s) {
     k_lz_begin<T, RPT><<<nblk, kBlock, 0, s>>>(a);
+    k_lz_reduce<T, OP_BEGIN><<<ngrp, kBlock, 0, s>>>(a, 0);
   }
   template <int STEP>
-  static void step(const LzArgs<T> &a, int nblk, int j, hipStream_t s) {
+  static void step(const LzArgs<T> &a, int nblk, int ngrp, int j, hipStream_t s,
+                   hipEvent_t *ev) {
+    if (ev) (void)hipEventRecord(ev[0], s);
     k_lz_project<T, RPT, 0, STEP><<<nblk, kBlock, 0, s>>>(a, j);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    k_lz_reduce<T, OP_PROJ0><<<ngrp, kBlock, 0, s>>>(a, j);
     k_lz_update<T, RPT, 1, STEP><<<nblk, kBlock, 0, s>>>(a, j);
+    k_lz_reduce<T, OP_UPD1><<<ngrp, kBlock, 0, s>>>(a, j);
     k_lz_project<T, RPT, 1, STEP><<<nblk, kBlock, 0, s>>>(a, j);
+    k_lz_reduce<T, OP_PROJ1><<<ngrp, kBlock, 0, s>>>(a, j);
     k_lz_update<T, RPT, 2, STEP><<<nblk, kBlock, 0, s>>>(a, j);
+    k_lz_reduce<T, OP_UPD2><<<ngrp, kBlock, 0, s>>>(a, j);
   }
-  // ev: null, or 2*m events bracketing the first-pass project launch of
-  // every step j >= 3 (ev[2j], ev[2j+1]).
-  static void cycle(const LzArgs<T> &a, int nblk, int nseg, hipStream_t s,
+  // ev: null, or 2*(m+1) events; ev[2j], ev[2j+1] bracket the first-pass
+  // project launch of every step j >= 3.
+  static void cycle(const LzArgs<T> &a, int nblk, int ngrp, int nseg, hipStream_t s,
                     hipEvent_t *ev = nullptr) {
     k_flags_reset<<<1, 1, 0, s>>>(a.flags);
     for (int j = 1; j <= a.m; ++j) {
-      if (j == 1) step<1>(a, nblk, j, s);
-      else if (j == 2) step<2>(a, nblk, j, s);
-      else if (!ev) step<3>(a, nblk, j, s);
-      else {
-        (void)hipEventRecord(ev[2 * j], s);
-        k_lz_project<T, RPT, 0, 3><<<nblk, kBlock, 0, s>>>(a, j);
-        (void)hipEventRecord(ev[2 * j + 1], s);
-        k_lz_update<T, RPT, 1, 3><<<nblk, kBlock, 0, s>>>(a, j);
-        k_lz_project<T, RPT, 1, 3><<<nblk, kBlock, 0, s>>>(a, j);
-        k_lz_update<T, RPT, 2, 3><<<nblk, kBlock, 0, s>>>(a, j);
-      }
+      if (j == 1) step<1>(a, nblk, ngrp, j, s, nullptr);
+      else if (j == 2) step<2>(a, nblk, ngrp, j, s, nullptr);
+      else step<3>(a, nblk, ngrp, j, s, ev ? ev + 2 * j : nullptr);
     }
     k_trieig<<<nseg, kWave, 0, s>>>(a.st, a.alpha, a.beta, a.tvec, a.ps, nseg);
     k_lz_ritz<T, RPT><<<nblk, kBlock, 0, s>>>(a);
+    k_lz_reduce<T, OP_RITZ><<<ngrp, kBlock, 0, s>>>(a, 0);
     k_lz_residual<T, RPT><<<nblk, kBlock, 0, s>>>(a);
+    k_lz_reduce<T, OP_RESID><<<ngrp, kBlock, 0, s>>>(a, 0);
   }
   static void output(const LzArgs<T> &a, int nblk, double *y64, hipStream_t s) {
     k_lz_output<T, RPT><<<nblk, kBlock, 0, s>>>(a, y64);
@@ -602,7 +682,6 @@ void dispatch_rpt(int rpt, F &&f) {
   switch (rpt) {
     case 4: f(LzLaunch<T, 4>()); break;
     case 8: f(LzLaunch<T, 8>()); break;
-    case 16: f(LzLaunch<T, 16>()); break;
     default: fail(RSB_EINTERNAL, "unsupported rows-per-thread " + std::to_string(rpt));
   }
 }
@@ -636,8 +715,8 @@ size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32) {
 }
 
 template <typename T>
-int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p, void *work,
-                      double *y64_out, Ctx &ctx) {
+int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p,
+                      void *work, double *y64_out, Ctx &ctx) {
   if (L.nseg == 0) return 0;
   if (p.m < 1 || p.m > kMaxM) fail(RSB_EINVAL, "lanczos_m must be in [1, 250]");
   LzArgs<T> a{};
@@ -676,11 +755,11 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
   a.flags = S.n_active.get();
   a.ctr = (unsigned long long *)S.counters.get();
   a.seed = p.seed;
-  const int nblk = L.nblk, nseg = L.nseg;
+  const int nblk = L.nblk, nseg = L.nseg, ngrp = L.ngrp;
   int64_t level_steps = 0;
   dispatch_rpt<T>(L.rpt, [&](auto launcher) {
     using Lz = decltype(launcher);
-    Lz::begin(a, nblk, ctx.stream);
+    Lz::begin(a, nblk, ngrp, ctx.stream);
     RSB_LAUNCHED();
     struct Res {
       hipGraphExec_t exec = nullptr;
@@ -698,7 +777,7 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
       for (auto &e : res.ev) RSB_HIP(hipEventCreate(&e));
     } else if (p.use_graph) {
       RSB_HIP(hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal));
-      Lz::cycle(a, nblk, nseg, ctx.stream);
+      Lz::cycle(a, nblk, ngrp, nseg, ctx.stream);
       hipError_t e = hipStreamEndCapture(ctx.stream, &res.graph);
       if (e != hipSuccess) fail(RSB_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
       RSB_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
@@ -725,12 +804,20 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
       if (res.exec) {
         RSB_HIP(hipGraphLaunch(res.exec, ctx.stream));
       } else {
-        Lz::cycle(a, nblk, nseg, ctx.stream, prof ? res.ev.data() : nullptr);
+        Lz::cycle(a, nblk, ngrp, nseg, ctx.stream, prof ? res.ev.data() : nullptr);
         RSB_LAUNCHED();
       }
       RSB_HIP(hipMemcpyAsync(flags, a.flags, sizeof(flags), hipMemcpyDeviceToHost, ctx.stream));
       RSB_HIP(hipStreamSynchronize(ctx.stream));
       level_steps += flags[1];
+      if (ctx.verbose >= 3) {
+        std::vector<SegState> hv(nseg);
+        RSB_HIP(hipMemcpy(hv.data(), a.st, nseg * sizeof(SegState), hipMemcpyDeviceToHost));
+        for (int i = 0; i < std::min(nseg, 4); ++i)
+          fprintf(stderr, "[rsb]     cycle %d seg %d: k %d res/rho %.3e rho %.12g theta %.12g\n",
+                  cyc, i, hv[i].k, hv[i].res / std::max(hv[i].rho, 1e-300), hv[i].rho,
+                  hv[i].theta);
+      }
       if (prof) {
         // launches of steps 3..k ran for the active segments (k = flags[1])
         const double st = (double)sizeof(T);

@@ -133,7 +133,12 @@ __global__ void k_cc_compress(int32_t *parent, int32_t *__restrict__ size,
   if (i >= nrows) return;
   int r = cc_rep(parent, (int)i);
   cc_store(&parent[i], r);
-  if (orig[i] >= 0) atomicAdd(&size[r], 1);
+  // component sizes: lanes sharing the root of lane 0 add together
+  const bool real = orig[i] >= 0;
+  const int r0 = __shfl(r, 0, kWave);
+  const unsigned long long same = __ballot(real && r == r0);
+  if ((threadIdx.x & (kWave - 1)) == 0 && same) atomicAdd(&size[r0], (int)__popcll(same));
+  if (real && r != r0) atomicAdd(&size[r], 1);
 }
 
 __global__ void k_seg_state_init(SegState *__restrict__ st, const SegDev *__restrict__ seg,
@@ -183,26 +188,38 @@ __device__ inline bool in_solve(const int32_t *root, const SegState &s, int64_t 
   return s.strad >= 0 && root[row] == s.strad;
 }
 
+// Rows are handled one per thread; a wavefront covers 64 rows of a single
+// segment (segments are 64-row aligned), so values are reduced over the
+// wavefront first and one lane does the atomic.
 __global__ void k_sign_max(const double *__restrict__ y, const int32_t *__restrict__ root,
                            const SegDev *__restrict__ seg, int nseg,
                            const SegState *__restrict__ st, unsigned long long *__restrict__ ymax,
                            int64_t nrows) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
+  if (i >= nrows) return;  // whole wavefronts (nrows is a multiple of 64)
   int s = seg_of_row(seg, nseg, i);
-  if (!in_solve(root, st[s], i)) return;
-  atomicMax(&ymax[s], (unsigned long long)__double_as_longlong(fabs(y[i])));
+  unsigned long long v =
+      in_solve(root, st[s], i) ? (unsigned long long)__double_as_longlong(fabs(y[i])) : 0ull;
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(v, off, kWave);
+    v = v > o ? v : o;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicMax(&ymax[s], v);
 }
 
 __global__ void k_sign_first(const double *__restrict__ y, const int32_t *__restrict__ root,
                              const SegDev *__restrict__ seg, int nseg, SegState *__restrict__ st,
                              const unsigned long long *__restrict__ ymax, int64_t nrows) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
+  if (i >= nrows) return;  // whole wavefronts
   int s = seg_of_row(seg, nseg, i);
-  if (!in_solve(root, st[s], i)) return;
-  double m = __longlong_as_double((long long)ymax[s]);
-  if (fabs(y[i]) >= 1e-3 * m) atomicMin(&st[s].first, (int)i);
+  int cand = 0x7fffffff;
+  if (in_solve(root, st[s], i)) {
+    double m = __longlong_as_double((long long)ymax[s]);
+    if (fabs(y[i]) >= 1e-3 * m) cand = (int)i;
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0 && cand != 0x7fffffff) atomicMin(&st[s].first, cand);
 }
 
 __global__ void k_sign_flip(const double *__restrict__ y, SegState *__restrict__ st, int nseg,
@@ -497,6 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv64(const int64_t *__restrict__ c
   double xi = x[r], acc = 0.0;
   for (int k = 0; k < width; ++k) {
     uint32_t w = cols[p + (int64_t)k * kWave + lane];
+    if (colw_wt(w) == 0) continue;  // padding slot
     acc += (double)colw_wt(w) * (xi - x[colw_col(w)]);
   }
   y[r] = acc;
@@ -511,17 +529,18 @@ __global__ void k_metrics(const int64_t *__restrict__ chunk_ptr, const uint32_t 
                           unsigned long long *__restrict__ acc, unsigned *__restrict__ bits,
                           int32_t nparts, int64_t nrows) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
-  if (orig[r] < 0) return;
+  if (r >= nrows) return;  // whole wavefronts
   int64_t c = r / kWave;
   int lane = (int)(r & (kWave - 1));
   int64_t p = chunk_ptr[c];
   int width = (int)((chunk_ptr[c + 1] - p) / kWave);
-  int pi = part[orig[r]] + poff[r];
-  if (pi < 0 || pi >= nparts) {
+  const bool real = orig[r] >= 0;
+  int pi = real ? part[orig[r]] + poff[r] : -1;
+  if (real && (pi < 0 || pi >= nparts)) {
     atomicAdd(&acc[4], 1ull);  // unassigned element: reported as an internal error
-    return;
+    pi = -1;
   }
+  if (pi < 0) width = 0;
   unsigned long long wcut = 0, pairs = 0;
   for (int k = 0; k < width; ++k) {
     uint32_t w = cols[p + (int64_t)k * kWave + lane];
@@ -538,7 +557,11 @@ __global__ void k_metrics(const int64_t *__restrict__ chunk_ptr, const uint32_t 
       pairs += 1;
     }
   }
-  if (wcut) {
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    wcut += __shfl_xor(wcut, off, kWave);
+    pairs += __shfl_xor(pairs, off, kWave);
+  }
+  if (lane == 0 && wcut) {
     atomicAdd(&acc[0], wcut);
     atomicAdd(&acc[1], pairs);
   }
@@ -671,7 +694,10 @@ void level0_from_csr(Level &L, const std::vector<const DevCsr *> &g,
   RSB_HIP(hipMemcpyAsync(&L.words, L.chunk_ptr.get() + L.nchunks, sizeof(int64_t),
                          hipMemcpyDeviceToHost, ctx.stream));
   RSB_HIP(hipStreamSynchronize(ctx.stream));
-  L.cols.alloc(ctx, std::max<int64_t>(L.words, 1));
+  L.cols.alloc(ctx, L.words + kColSlack);
+  k_zero_u32<<<grid_for(kColSlack, kBlock), kBlock, 0, ctx.stream>>>(L.cols.get() + L.words,
+                                                                     kColSlack);
+  RSB_LAUNCHED();
   L.nnz = 0;
   for (int s = 0; s < L.nseg; ++s) L.nnz += g[mesh_seg[s]]->nnz;
   for (int s = 0; s < L.nseg; ++s) {
@@ -910,8 +936,9 @@ void compact_level(Level &L, const uint8_t *side, int32_t *d_part_out, Level &ne
   RSB_HIP(hipMemcpyAsync(&next.words, next.chunk_ptr.get() + next.nchunks, sizeof(int64_t),
                          hipMemcpyDeviceToHost, ctx.stream));
   RSB_HIP(hipStreamSynchronize(ctx.stream));
-  next.cols.alloc(ctx, std::max<int64_t>(next.words, 1));
-  k_zero_u32<<<grid_for(next.words, kBlock), kBlock, 0, ctx.stream>>>(next.cols.get(), next.words);
+  next.cols.alloc(ctx, next.words + kColSlack);
+  k_zero_u32<<<grid_for(next.words + kColSlack, kBlock), kBlock, 0, ctx.stream>>>(
+      next.cols.get(), next.words + kColSlack);
   RSB_LAUNCHED();
   k_new_fill<<<g, kBlock, 0, ctx.stream>>>(L.chunk_ptr.get(), L.cols.get(), side, newidx.get(),
                                            L.orig.get(), L.gid.get(), next.chunk_ptr.get(),

@@ -16,47 +16,44 @@ __device__ inline double start_value(uint64_t seed, int64_t gid) {
   return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
 }
 
-// Fixed-order two-level reduction of `nval` block values held in LDS
-// `vals` (A provides blk, grp, seg, part, gpart, gcnt, scnt, ps).  Returns
-// true in the one block that finishes the segment; there `vals` holds the
-// segment totals.  Block partials are published with a device-scope fence
-// before the arrival counter is bumped, and read after an acquire fence.
+// Segmented reductions are split in two launches.  The streaming kernel
+// writes one partial vector per block (plain stores, no fence: a device-scope
+// release in every block of a large launch would write back the L2 each
+// time).  A small reduction kernel with one block per group of up to 32
+// blocks then sums the partials in a fixed order; a segment with several
+// groups is finished by its last group to arrive (its fences are cheap: at
+// that point the L2 holds only the few group sums).
 template <typename A>
-__device__ bool hier_reduce(const A &a, int lb, double *vals, int nval) {
+__device__ inline void write_partials(const A &a, int lb, const double *vals, int nval) {
+  for (int i = threadIdx.x; i < nval; i += kBlock) a.part[(int64_t)lb * a.ps + i] = vals[i];
+}
+
+// Reduction-kernel side (block g = group g).  Returns true in the one block
+// that finishes the segment; there vals[0..nval) holds the segment totals.
+template <typename A>
+__device__ bool group_reduce(const A &a, int g, double *vals, int nval) {
   __shared__ int s_flag;
-  const BlkDev b = a.blk[lb];
   const int t = threadIdx.x;
-  for (int i = t; i < nval; i += kBlock) a.part[(int64_t)lb * a.ps + i] = vals[i];
-  __threadfence();
-  __syncthreads();
-  if (t == 0) {
-    unsigned prev = atomicAdd(&a.gcnt[b.grp], 1u);
-    s_flag = (prev == (unsigned)a.grp[b.grp].nblk - 1u);
-  }
-  __syncthreads();
-  if (!s_flag) return false;
-  __threadfence();
-  const GrpDev g = a.grp[b.grp];
-  const SegDev sg = a.seg[b.seg];
-  if (t == 0) a.gcnt[b.grp] = 0;
+  const GrpDev G = a.grp[g];
+  const SegDev sg = a.seg[G.seg];
   for (int i = t; i < nval; i += kBlock) {
     double sum = 0.0;
-    for (int q = 0; q < g.nblk; ++q) sum += a.part[(int64_t)(g.blk0 + q) * a.ps + i];
+    for (int q = 0; q < G.nblk; ++q) sum += a.part[(int64_t)(G.blk0 + q) * a.ps + i];
     vals[i] = sum;
   }
   __syncthreads();
   if (sg.ngrp == 1) return true;
-  for (int i = t; i < nval; i += kBlock) a.gpart[(int64_t)b.grp * a.ps + i] = vals[i];
+  for (int i = t; i < nval; i += kBlock) a.gpart[(int64_t)g * a.ps + i] = vals[i];
   __threadfence();
   __syncthreads();
   if (t == 0) {
-    unsigned prev = atomicAdd(&a.scnt[b.seg], 1u);
+    unsigned prev = atomicAdd(&a.scnt[G.seg], 1u);
     s_flag = (prev == (unsigned)sg.ngrp - 1u);
   }
   __syncthreads();
   if (!s_flag) return false;
   __threadfence();
-  if (t == 0) a.scnt[b.seg] = 0;
+  if (t == 0) a.scnt[G.seg] = 0;
   for (int i = t; i < nval; i += kBlock) {
     double sum = 0.0;
     for (int q = 0; q < sg.ngrp; ++q) sum += a.gpart[(int64_t)(sg.grp0 + q) * a.ps + i];
@@ -65,6 +62,24 @@ __device__ bool hier_reduce(const A &a, int lb, double *vals, int nval) {
   __syncthreads();
   return true;
 }
+
+// Rows of a block tile.  Thread t owns rows t, t + 256, ... (RPT of them); a
+// row past the tile end is clamped to the tile's first row for its loads and
+// its results are dropped, so the hot loops have no per-row branches and all
+// their loads can be in flight together.
+template <int RPT>
+struct TileRows {
+  int64_t row[RPT];
+  bool ok[RPT];
+  __device__ TileRows(const BlkDev &b) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int lr = r * kBlock + (int)threadIdx.x;
+      ok[r] = lr < b.nrows;
+      row[r] = b.row0 + (ok[r] ? lr : 0);
+    }
+  }
+};
 
 // Sum NV per-thread values over the block into vals[0..count) (fixed order).
 template <int NV>
@@ -97,19 +112,23 @@ __device__ inline X lap_row(const int64_t *__restrict__ chunk_ptr, const uint32_
   const int width = (int)((chunk_ptr[c + 1] - p) >> 6);
   const uint32_t *cp = cols + p + lane;
   X acc = 0;
-  int k = 0;
-  for (; k + 4 <= width; k += 4) {
-    uint32_t w0 = cp[(k + 0) * 64], w1 = cp[(k + 1) * 64], w2 = cp[(k + 2) * 64],
-             w3 = cp[(k + 3) * 64];
-    X x0 = x[colw_col(w0)], x1 = x[colw_col(w1)], x2 = x[colw_col(w2)], x3 = x[colw_col(w3)];
-    acc += (X)colw_wt(w0) * (xi - x0);
-    acc += (X)colw_wt(w1) * (xi - x1);
-    acc += (X)colw_wt(w2) * (xi - x2);
-    acc += (X)colw_wt(w3) * (xi - x3);
-  }
-  for (; k < width; ++k) {
-    uint32_t w = cp[k * 64];
-    acc += (X)colw_wt(w) * (xi - x[colw_col(w)]);
+  // kSlotGroup slots at a time with unconditional loads (all column words,
+  // then all gathers, so they are in flight together).  Slots past the row's
+  // width read the next slice or the zero slack after the last one and are
+  // masked to weight 0; a weight-0 slot contributes exactly 0 whatever it
+  // gathered.
+  for (int k0 = 0; k0 < width; k0 += kSlotGroup) {
+    uint32_t w[kSlotGroup];
+#pragma unroll
+    for (int u = 0; u < kSlotGroup; ++u) w[u] = cp[(int64_t)(k0 + u) * 64];
+#pragma unroll
+    for (int u = 0; u < kSlotGroup; ++u) w[u] = (k0 + u < width) ? w[u] : 0u;
+    X xv[kSlotGroup];
+#pragma unroll
+    for (int u = 0; u < kSlotGroup; ++u) xv[u] = x[colw_col(w[u])];
+#pragma unroll
+    for (int u = 0; u < kSlotGroup; ++u)
+      acc += colw_wt(w[u]) ? (X)colw_wt(w[u]) * (xi - xv[u]) : (X)0;
   }
   return acc;
 }
