@@ -85,6 +85,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0)
     ap.add_argument("--unbatched", action="store_true")
+    ap.add_argument("--rows-per-thread", type=int, default=0, choices=[0, 2, 4, 8])
+    ap.add_argument("--autotune", type=int, default=0, choices=[0, 1, 2])
+    ap.add_argument("--autotune-cache", default=None)
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time the steps with graph replay and no kernel timing (no roofline)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -104,7 +109,10 @@ def main():
     part = torch.empty(mesh.nelem, dtype=torch.int32, device="cuda")
     opts = dict(precision=args.precision, tol=args.tol, lanczos_m=args.m,
                 max_restarts=args.max_restarts, verbose=args.verbose,
-                batched=0 if args.unbatched else 1)
+                batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
+                autotune=args.autotune)
+    if args.autotune_cache:
+        opts["autotune_cache"] = args.autotune_cache
 
     def one_step(profile):
         o = rsb.make_opts(True, profile=1 if profile else 0, **opts)
@@ -127,7 +135,7 @@ def main():
     kern_launches = 0
     last = None
     for i in range(args.steps):
-        code, st = one_step(True)
+        code, st = one_step(not args.no_profile)
         total_steps += st["level_steps"]
         kern_ms += st["kernel_ms"]
         kern_bytes += st["kernel_bytes"]
@@ -171,7 +179,8 @@ def main():
         "ms_split": st["ms_split"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_lz_project<float,8,0,3> (SpMV + projection, Lanczos steps j>=3)",
+                     "kernel": (f"k_lz_project (SpMV + projection, Lanczos steps j>=3), "
+                                f"{st['tile_rows']}-row tiles at level 0"),
                      "launches": kern_launches,
                      "avg_us": kern_ms * 1e3 / max(kern_launches, 1)},
     }

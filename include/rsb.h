@@ -95,7 +95,10 @@ typedef struct rsb_opts {
                                kernel of Lanczos steps j >= 3 with HIP events
                                (cycles are then launched directly, not replayed
                                as graphs); results in rsb_stats.kernel_* */
-  int32_t reserved[7];
+  int32_t rows_per_thread;  /* tile of the streaming kernels, 256 * rows_per_thread
+                               rows per workgroup: 0 = chosen by the library (see
+                               autotune), else 2, 4 or 8 for every level */
+  int32_t reserved[6];
 } rsb_opts;
 
 typedef struct rsb_stats {
@@ -130,7 +133,8 @@ typedef struct rsb_stats {
                                 (j - 2) s_q), s_ = bytes per value */
   double kernel_ms;          /* summed device time of its launches (HIP events) */
   int64_t kernel_launches;   /* its launches */
-  int32_t reserved[6];
+  int32_t tile_rows;         /* rows per workgroup of the streaming kernels at level 0 */
+  int32_t reserved[5];
 } rsb_stats;
 
 /* Fills *o with the defaults listed above.  Returns RSB_OK or RSB_EINVAL (o NULL). */

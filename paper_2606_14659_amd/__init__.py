@@ -34,7 +34,7 @@ class Opts(C.Structure):
         ("seed", C.c_uint64), ("use_hipgraph", C.c_int32), ("autotune", C.c_int32),
         ("autotune_cache", C.c_char_p), ("device", C.c_int32), ("device_pointers", C.c_int32),
         ("stream", C.c_void_p), ("device_mem_limit", C.c_int64), ("verbose", C.c_int32),
-        ("profile", C.c_int32), ("reserved", C.c_int32 * 7),
+        ("profile", C.c_int32), ("rows_per_thread", C.c_int32), ("reserved", C.c_int32 * 6),
     ]
 
 
@@ -47,7 +47,7 @@ class Stats(C.Structure):
         ("ms_split", C.c_double), ("ms_total", C.c_double), ("edge_cut", C.c_double),
         ("cut_pairs", C.c_int64), ("max_neighbors", C.c_int32), ("avg_neighbors", C.c_double),
         ("nnz", C.c_int64), ("kernel_bytes", C.c_double), ("kernel_ms", C.c_double),
-        ("kernel_launches", C.c_int64), ("reserved", C.c_int32 * 6),
+        ("kernel_launches", C.c_int64), ("tile_rows", C.c_int32), ("reserved", C.c_int32 * 5),
     ]
 
     def as_dict(self):
@@ -136,6 +136,8 @@ def make_opts(device_arrays: bool = False, **kw) -> Opts:
             v = METHOD[v]
         elif k == "precision" and isinstance(v, str):
             v = PRECISION[v]
+        elif k == "autotune_cache" and isinstance(v, str):
+            v = v.encode()
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)

@@ -48,6 +48,9 @@ void check_opts(const rsb_opts *o) {
   if (o->inv_max_outer < 1 || o->cg_max_iter < 1) fail(RSB_EINVAL, "inverse iteration caps");
   if (o->cg_full_projection != 0) fail(RSB_EINVAL, "cg_full_projection is not supported");
   if (o->autotune < 0 || o->autotune > 2) fail(RSB_EINVAL, "autotune");
+  if (o->rows_per_thread != 0 && o->rows_per_thread != 2 && o->rows_per_thread != 4 &&
+      o->rows_per_thread != 8)
+    fail(RSB_EINVAL, "rows_per_thread must be 0, 2, 4 or 8");
 }
 
 void setup_ctx(Ctx &ctx, const rsb_opts &o) {
@@ -99,13 +102,6 @@ void copy_out(Ctx &ctx, T *dst, const T *dsrc, int64_t n, bool device) {
   if (n <= 0) return;
   RSB_HIP(hipMemcpyAsync(dst, dsrc, n * sizeof(T),
                          device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx.stream));
-}
-
-// Rows per thread of the streaming kernels (tile = 256 * rpt rows): large
-// tiles on big levels, small tiles when there are few rows.
-int pick_rpt(int64_t nrows) {
-  if (nrows >= (int64_t)4 * 256 * kBlock * 8) return 8;
-  return 4;
 }
 
 struct MeshIn {
@@ -225,7 +221,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     np.push_back(fiedler_y ? 2 : meshes[b].nparts);
     parts_total += meshes[b].nparts;
   }
-  const int rpt = pick_rpt(total);
+  const int rpt = o.rows_per_thread ? o.rows_per_thread : default_rpt(total);
   Level L0;
   level0_from_csr(L0, gp, np, rpt, ctx);
   for (auto &g : graphs) {
@@ -258,8 +254,11 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
   int worst = RSB_OK;
   while (L->nseg > 0) {
     const double ta = now_ms();
+    const double prof_ms0 = prof.ms, prof_bytes0 = prof.bytes;
     SolveDev S;
     CompDev C;
+    choose_tile(*L, o, work.get(), ctx);
+    if (level == 0) st.tile_rows = kBlock * L->rpt;
     solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), ctx);
     components_and_targets(*L, C, S, ctx);
     const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(),
@@ -330,11 +329,17 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     compact_level(*L, side.get(), d_part, *next, rpt, ctx);
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     st.ms_split += now_ms() - tb;
-    if (ctx.verbose)
+    if (ctx.verbose) {
       fprintf(stderr,
-              "[rsb] level %d: %d segments, %lld rows, %lld level-steps, %.1f ms solve, "
-              "%.1f ms split\n",
-              level, L->nseg, (long long)L->nrows, (long long)steps, tb - ta, now_ms() - tb);
+              "[rsb] level %d: %d segments, %lld rows, tile %d, %lld level-steps, max %d cycles, "
+              "%.1f ms solve, %.1f ms split",
+              level, L->nseg, (long long)L->nrows, kBlock * L->rpt, (long long)steps, cyc, tb - ta,
+              now_ms() - tb);
+      if (o.profile && prof.ms > prof_ms0)
+        fprintf(stderr, "; projection kernel %.1f ms, %.0f GB/s", prof.ms - prof_ms0,
+                (prof.bytes - prof_bytes0) / (prof.ms - prof_ms0) * 1e-6);
+      fprintf(stderr, "\n");
+    }
     ++level;
     // advance; level 0 stays alive for the metrics
     Level *done = L;

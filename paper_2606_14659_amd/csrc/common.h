@@ -14,7 +14,7 @@ namespace rsb {
 constexpr int kWave = 64;    // CDNA wavefront width
 constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
 constexpr int kMaxM = 250;   // largest Lanczos cycle length
-constexpr int kGroup = 32;   // blocks per first-level reduction group
+constexpr int kGroup = 32;   // least blocks per first-level reduction group
 constexpr int kSlotGroup = 16;  // ELL slots a row reads at once (unconditional loads)
 // zero words after the last slice so that a row may read a whole slot group
 constexpr int64_t kColSlack = (int64_t)kSlotGroup * 64;
@@ -55,6 +55,7 @@ struct Ctx {
   int64_t in_use = 0;
   int64_t peak = 0;
   int verbose = 0;
+  std::vector<std::string> tuned;  // tile classes timed during this call
   Ctx() = default;
   Ctx(const Ctx &) = delete;
   Ctx &operator=(const Ctx &) = delete;

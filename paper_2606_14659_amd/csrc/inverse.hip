@@ -457,9 +457,9 @@ int64_t inverse_level(const LevelView &L, CompDev &C, SolveDev &S, const Inverse
                       void *work, double *y64_out, bool use_graph, Ctx &ctx) {
   if (L.nseg == 0) return 0;
   switch (L.rpt) {
+    case 2: return inverse_impl<2>(L, C, S, p, work, y64_out, use_graph, ctx);
     case 4: return inverse_impl<4>(L, C, S, p, work, y64_out, use_graph, ctx);
     case 8: return inverse_impl<8>(L, C, S, p, work, y64_out, use_graph, ctx);
-    case 16: return inverse_impl<16>(L, C, S, p, work, y64_out, use_graph, ctx);
     default: fail(RSB_EINTERNAL, "unsupported rows-per-thread");
   }
 }

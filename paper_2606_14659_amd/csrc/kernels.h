@@ -141,6 +141,12 @@ inline LevelView view_of(const Level &L) {
 // upload all three tables.
 void level_tables(Level &L, int rpt, Ctx &ctx);
 
+// Tile of the streaming kernels: the built-in rows per thread, and the
+// choice for one level (options, cache or timing trials; rebuilds the
+// level's tables when it changes the tile).  work: the Lanczos workspace.
+int default_rpt(int64_t nrows);
+void choose_tile(Level &L, const rsb_opts &o, void *work, Ctx &ctx);
+
 // Level 0 from per-mesh CSR graphs (segments in mesh order).
 void level0_from_csr(Level &L, const std::vector<const DevCsr *> &g,
                      const std::vector<int32_t> &nparts, int rpt, Ctx &ctx);
@@ -191,6 +197,9 @@ struct LanczosParams {
 // work vectors).  T = double: all FP64; T = float: mixed precision.
 void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, Ctx &ctx);
 size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32);
+// Device time (ms) of one Lanczos step of the level with its current tile.
+template <typename T>
+double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx);
 template <typename T>
 int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p,
                       void *work, double *y64_out, Ctx &ctx);

@@ -30,6 +30,7 @@
 // FP64 tolerance; scalars, projections and the tridiagonal solve are FP64.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "common.h"
 #include "kernels.h"
@@ -638,6 +639,7 @@ __global__ void k_flags_reset(int32_t *flags) {
 
 template <typename T, int RPT>
 struct LzLaunch {
+  static constexpr int kRpt = RPT;
   static void begin(const LzArgs<T> &a, int nblk, int ngrp, hipStream_t s) {
     k_lz_begin<T, RPT><<<nblk, kBlock, 0, s>>>(a);
     k_lz_reduce<T, OP_BEGIN><<<ngrp, kBlock, 0, s>>>(a, 0);
@@ -680,6 +682,7 @@ struct LzLaunch {
 template <typename T, typename F>
 void dispatch_rpt(int rpt, F &&f) {
   switch (rpt) {
+    case 2: f(LzLaunch<T, 2>()); break;
     case 4: f(LzLaunch<T, 4>()); break;
     case 8: f(LzLaunch<T, 8>()); break;
     default: fail(RSB_EINTERNAL, "unsupported rows-per-thread " + std::to_string(rpt));
@@ -775,32 +778,44 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
     if (prof) {
       res.ev.resize(2 * (a.m + 1));
       for (auto &e : res.ev) RSB_HIP(hipEventCreate(&e));
-    } else if (p.use_graph) {
+    }
+    if (p.use_graph && !prof) {
+      // (HIP events recorded by graph nodes cannot be timed: profiled cycles
+      // are launched directly)
       RSB_HIP(hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal));
       Lz::cycle(a, nblk, ngrp, nseg, ctx.stream);
       hipError_t e = hipStreamEndCapture(ctx.stream, &res.graph);
       if (e != hipSuccess) fail(RSB_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
       RSB_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
     }
-    // profiled byte count: rows of the segments active in the cycle
+    // profiled byte count: per segment active in the cycle, its rows for
+    // every step it ran (its nonzeros taken in proportion to its rows)
     std::vector<SegState> hst;
     std::vector<SegDev> hseg;
-    auto active_rows = [&]() -> int64_t {
+    std::vector<char> was_active;
+    std::vector<int64_t> steps0;
+    auto read_state = [&]() {
       hst.resize(nseg);
-      hseg.resize(nseg);
       RSB_HIP(hipMemcpyAsync(hst.data(), a.st, nseg * sizeof(SegState), hipMemcpyDeviceToHost,
                              ctx.stream));
+      RSB_HIP(hipStreamSynchronize(ctx.stream));
+    };
+    if (prof) {
+      hseg.resize(nseg);
       RSB_HIP(hipMemcpyAsync(hseg.data(), a.seg, nseg * sizeof(SegDev), hipMemcpyDeviceToHost,
                              ctx.stream));
-      RSB_HIP(hipStreamSynchronize(ctx.stream));
-      int64_t r = 0;
-      for (int i = 0; i < nseg; ++i)
-        if (hst[i].active) r += hseg[i].npad;
-      return r;
-    };
+      was_active.resize(nseg);
+      steps0.resize(nseg);
+    }
     int32_t flags[2] = {0, 0};
     for (int cyc = 0; cyc <= p.max_restarts; ++cyc) {
-      const int64_t rows = prof ? active_rows() : 0;
+      if (prof) {
+        read_state();
+        for (int i = 0; i < nseg; ++i) {
+          was_active[i] = hst[i].active != 0;
+          steps0[i] = hst[i].steps;
+        }
+      }
       if (res.exec) {
         RSB_HIP(hipGraphLaunch(res.exec, ctx.stream));
       } else {
@@ -819,16 +834,21 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
                   hv[i].theta);
       }
       if (prof) {
-        // launches of steps 3..k ran for the active segments (k = flags[1])
+        // launches of steps 3..flags[1] were timed; segment i took part in
+        // those of steps 3..k_i (k_i: the steps it added in this cycle)
+        read_state();
         const double st = (double)sizeof(T);
-        const double nnz = (double)p.nnz * (double)rows / (double)std::max<int64_t>(L.nrows, 1);
+        const double nnz_per_row = (double)p.nnz / (double)std::max<int64_t>(L.nrows, 1);
         for (int j = 3; j <= flags[1]; ++j) {
           float ms = 0.f;
           RSB_HIP(hipEventElapsedTime(&ms, res.ev[2 * j], res.ev[2 * j + 1]));
+          double rows = 0.0;
+          for (int i = 0; i < nseg; ++i)
+            if (was_active[i] && hst[i].steps - steps0[i] >= j) rows += (double)hseg[i].npad;
           p.prof->ms += ms;
           p.prof->launches += 1;
-          p.prof->bytes += 4.0 * (rows + 1) + 4.0 * nnz +
-                           (double)rows * (st + st + st + 16.0 + (j - 2) * st);
+          p.prof->bytes += 4.0 * (rows + 1) + 4.0 * nnz_per_row * rows +
+                           rows * (st + st + st + 16.0 + (j - 2) * st);
         }
       }
       if (flags[0] == 0) break;
@@ -840,6 +860,99 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
   });
   return level_steps;
 }
+
+// Device time of one Lanczos step (the two streaming launches and their
+// reductions) at step j = max(3, m / 2) on the level's own matrix, for tile
+// selection.  The vectors hold whatever the workspace holds; every segment
+// is marked active and the state is restored before each timed repetition.
+template <typename T>
+double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
+  if (L.nseg == 0 || L.nblk == 0 || m < 4 || m > kMaxM) return 0.0;
+  const int j = m / 2 >= 3 ? m / 2 : 3;
+  SolveDev S;
+  solve_alloc(S, L.nseg, L.nblk, L.ngrp, m, ctx);
+  std::vector<SegState> hs(L.nseg);
+  for (auto &x : hs) {
+    std::memset(&x, 0, sizeof(x));
+    x.active = 1;
+    x.solve = 1;
+    x.s = 1.0;
+    x.tnorm = 1.0;
+  }
+  DevBuf<SegState> pristine(ctx, L.nseg);
+  RSB_HIP(hipMemcpyAsync(pristine.get(), hs.data(), L.nseg * sizeof(SegState),
+                         hipMemcpyHostToDevice, ctx.stream));
+  RSB_HIP(hipMemsetAsync(S.h.get(), 0, S.h.bytes(), ctx.stream));
+  LzArgs<T> a{};
+  a.blk = L.blk;
+  a.grp = L.grp;
+  a.seg = L.seg;
+  a.st = S.st.get();
+  a.alpha = S.alpha.get();
+  a.beta = S.beta.get();
+  a.h = S.h.get();
+  a.tvec = S.tvec.get();
+  a.part = S.part.get();
+  a.gpart = S.gpart.get();
+  a.gcnt = S.gcnt.get();
+  a.scnt = S.scnt.get();
+  a.ps = S.pstride;
+  a.chunk_ptr = L.chunk_ptr;
+  a.cols = L.cols;
+  double *wd = (double *)work;
+  a.U0 = wd;
+  a.Q1 = wd + L.nrows;
+  a.Y = wd + 2 * L.nrows;
+  a.Wd = wd + 3 * L.nrows;
+  T *wt = (T *)(wd + 4 * L.nrows);
+  a.V = wt;
+  a.vs = L.nrows;
+  a.Wt0 = wt + (int64_t)(m + 1) * L.nrows;
+  a.Wt1 = a.Wt0 + L.nrows;
+  a.m = m;
+  a.tol = 1.0;
+  a.brk = 0.0;
+  a.flags = S.n_active.get();
+  a.ctr = (unsigned long long *)S.counters.get();
+  const int nblk = L.nblk, ngrp = L.ngrp;
+  double total = 0.0;
+  dispatch_rpt<T>(L.rpt, [&](auto launcher) {
+    (void)launcher;
+    constexpr int RPT = decltype(launcher)::kRpt;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RSB_HIP(hipEventCreate(&e0));
+    hipError_t err = hipEventCreate(&e1);
+    if (err != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      fail(RSB_EDEVICE, "hipEventCreate");
+    }
+    constexpr int kReps = 4;  // the first one is a warm-up
+    for (int r = 0; r < kReps && err == hipSuccess; ++r) {
+      err = hipMemcpyAsync(a.st, pristine.get(), L.nseg * sizeof(SegState),
+                           hipMemcpyDeviceToDevice, ctx.stream);
+      if (err != hipSuccess) break;
+      (void)hipEventRecord(e0, ctx.stream);
+      k_lz_project<T, RPT, 0, 3><<<nblk, kBlock, 0, ctx.stream>>>(a, j);
+      k_lz_reduce<T, OP_PROJ0><<<ngrp, kBlock, 0, ctx.stream>>>(a, j);
+      k_lz_update<T, RPT, 1, 3><<<nblk, kBlock, 0, ctx.stream>>>(a, j);
+      k_lz_reduce<T, OP_UPD1><<<ngrp, kBlock, 0, ctx.stream>>>(a, j);
+      (void)hipEventRecord(e1, ctx.stream);
+      err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) total += ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) fail(RSB_EDEVICE, std::string("tile trial: ") + hipGetErrorString(err));
+    RSB_LAUNCHED();
+    total /= (kReps - 1);
+  });
+  return total;
+}
+
+template double lanczos_trial_ms<float>(const LevelView &, int, void *, Ctx &);
+template double lanczos_trial_ms<double>(const LevelView &, int, void *, Ctx &);
 
 template int64_t lanczos_level<float>(const LevelView &, CompDev &, SolveDev &,
                                       const LanczosParams &, void *, double *, Ctx &);

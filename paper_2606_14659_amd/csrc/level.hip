@@ -611,21 +611,25 @@ void level_tables(Level &L, int rpt, Ctx &ctx) {
     sg.blk0 = (int32_t)L.blk.size();
     sg.grp0 = (int32_t)L.grp.size();
     int64_t nb = std::max<int64_t>(1, (sg.npad + tile - 1) / tile);
+    // about sqrt(nb) blocks per group (at least kGroup): both reduction
+    // stages then read about as many partials per segment
+    int64_t gs = kGroup;
+    while (gs * gs < nb) gs += 8;
     for (int64_t b = 0; b < nb; ++b) {
       BlkDev bd{};
       bd.row0 = sg.row0 + b * tile;
       bd.nrows = (int32_t)std::min<int64_t>(tile, sg.npad - b * tile);
       bd.seg = s;
-      bd.grp = sg.grp0 + (int32_t)(b / kGroup);
+      bd.grp = sg.grp0 + (int32_t)(b / gs);
       L.blk.push_back(bd);
     }
     sg.nblk = (int32_t)nb;
-    int64_t ng = (nb + kGroup - 1) / kGroup;
+    int64_t ng = (nb + gs - 1) / gs;
     for (int64_t g = 0; g < ng; ++g) {
       GrpDev gd{};
       gd.seg = s;
-      gd.blk0 = sg.blk0 + (int32_t)(g * kGroup);
-      gd.nblk = (int32_t)std::min<int64_t>(kGroup, nb - g * kGroup);
+      gd.blk0 = sg.blk0 + (int32_t)(g * gs);
+      gd.nblk = (int32_t)std::min<int64_t>(gs, nb - g * gs);
       L.grp.push_back(gd);
     }
     sg.ngrp = (int32_t)ng;

@@ -28,20 +28,53 @@ __device__ inline void write_partials(const A &a, int lb, const double *vals, in
   for (int i = threadIdx.x; i < nval; i += kBlock) a.part[(int64_t)lb * a.ps + i] = vals[i];
 }
 
+// Sums over n rows of partials: vals[i] = sum_q src[q * ps + i], i < nval.
+// K threads share a value (the largest power of two with K nval <= kBlock);
+// thread sub of a value sums rows q = sub, sub + K, ... in increasing order,
+// eight loads in flight at a time, then the K sums are added by a fixed tree,
+// so the result does not depend on timing.
+__device__ inline void sum_rows(const double *__restrict__ src, int n, int ps, int nval,
+                                double *vals, double *lds /* [kBlock] */) {
+  int K = 1;
+  while (2 * K * nval <= kBlock) K *= 2;
+  const int t = threadIdx.x;
+  const int sub = t % K;
+  for (int i0 = 0; i0 < nval; i0 += kBlock / K) {
+    const int i = i0 + t / K;
+    double acc = 0.0;
+    if (i < nval) {
+      for (int q0 = sub; q0 < n; q0 += 8 * K) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int q = q0 + u * K;
+          v[u] = (q < n) ? src[(int64_t)q * ps + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+      }
+    }
+    lds[t] = acc;
+    __syncthreads();
+    for (int h = K / 2; h > 0; h >>= 1) {
+      if (sub < h) lds[t] += lds[t + h];
+      __syncthreads();
+    }
+    if (sub == 0 && i < nval) vals[i] = lds[t];
+    __syncthreads();
+  }
+}
+
 // Reduction-kernel side (block g = group g).  Returns true in the one block
 // that finishes the segment; there vals[0..nval) holds the segment totals.
 template <typename A>
 __device__ bool group_reduce(const A &a, int g, double *vals, int nval) {
+  __shared__ double lds[kBlock];
   __shared__ int s_flag;
   const int t = threadIdx.x;
   const GrpDev G = a.grp[g];
   const SegDev sg = a.seg[G.seg];
-  for (int i = t; i < nval; i += kBlock) {
-    double sum = 0.0;
-    for (int q = 0; q < G.nblk; ++q) sum += a.part[(int64_t)(G.blk0 + q) * a.ps + i];
-    vals[i] = sum;
-  }
-  __syncthreads();
+  sum_rows(a.part + (int64_t)G.blk0 * a.ps, G.nblk, a.ps, nval, vals, lds);
   if (sg.ngrp == 1) return true;
   for (int i = t; i < nval; i += kBlock) a.gpart[(int64_t)g * a.ps + i] = vals[i];
   __threadfence();
@@ -54,12 +87,7 @@ __device__ bool group_reduce(const A &a, int g, double *vals, int nval) {
   if (!s_flag) return false;
   __threadfence();
   if (t == 0) a.scnt[G.seg] = 0;
-  for (int i = t; i < nval; i += kBlock) {
-    double sum = 0.0;
-    for (int q = 0; q < sg.ngrp; ++q) sum += a.gpart[(int64_t)(sg.grp0 + q) * a.ps + i];
-    vals[i] = sum;
-  }
-  __syncthreads();
+  sum_rows(a.gpart + (int64_t)sg.grp0 * a.ps, sg.ngrp, a.ps, nval, vals, lds);
   return true;
 }
 

@@ -188,6 +188,37 @@ def test_partition_cut_within_one_percent(orc, name, nparts, precision):
     assert abs(cut - ocut) <= 0.01 * ocut
 
 
+@pytest.mark.parametrize("rpt", [2, 4, 8])
+def test_tile_sizes_identical_partition(orc, rpt):
+    # 69,120 elements: many tiles and reduction groups and a ragged last
+    # tile for every tile size; unique longest axis at every level
+    mesh = mg.box_hex(48, 40, 36)
+    print(f"tile rows_per_thread={rpt}", flush=True)
+    st, part, stats = rsb.partition(mesh.ids, 8, precision="mixed", tol=1e-8,
+                                    rows_per_thread=rpt)
+    ost, opart, _ = orc.partition(mesh.ids, 8, tol=1e-8)
+    assert st == ost == 0
+    assert np.array_equal(part, opart)
+
+
+def test_autotune_cache(tmp_path):
+    ids = MESHES["clustered"]
+    path = str(tmp_path / "tiles.txt")
+    st1, p1, _ = rsb.partition(ids, 16, precision="mixed", autotune=2, autotune_cache=path)
+    lines = open(path).read().splitlines()
+    assert lines
+    for line in lines:
+        f = line.split()
+        assert f[:2] == ["rsb-tile", "1"] and f[2].startswith("gfx") and len(f) == 9
+        assert int(f[-1]) in (2, 4, 8)
+    keys = [" ".join(line.split()[2:8]) for line in lines]
+    assert len(keys) == len(set(keys))  # each class timed once per call
+    st2, p2, _ = rsb.partition(ids, 16, precision="mixed", autotune=1, autotune_cache=path)
+    assert st1 == st2
+    assert np.array_equal(p1, p2)
+    assert open(path).read().splitlines() == lines  # served from the cache
+
+
 def test_disconnected_rule(orc):
     # Two separate boxes.  Components are ordered by smallest element id, so
     # box A (ids 0..35) comes first.  Exact ties of a box's symmetric Fiedler

@@ -54,7 +54,8 @@ def test_bad_options_rejected_before_any_device_call():
     rsb.lib().rsb_opts_init(C.byref(o))
     bad = []
     for field, value in (("struct_size", 4), ("graph", 7), ("lanczos_m", 0), ("lanczos_m", 251),
-                         ("tol", 0.0), ("cg_full_projection", 1), ("precision", 5)):
+                         ("tol", 0.0), ("cg_full_projection", 1), ("precision", 5),
+                         ("rows_per_thread", 3), ("rows_per_thread", 16), ("autotune", 3)):
         oo = rsb.Opts.from_buffer_copy(o)
         setattr(oo, field, value)
         part = np.zeros(2, dtype=np.int32)
