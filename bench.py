@@ -18,6 +18,7 @@ import argparse
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -26,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Lanczos iters/s + SpMV HBM GB/s; time to 4096-way RSB at matched edge cut"
 HBM_PEAK_GBS = 8000.0
+KERNEL_LABEL = "k_lz_project (SpMV + projection, Lanczos steps j>=3)"
 
 WORKLOADS = {
     "box256x256x128-clustered10-renum-4096": dict(nparts=4096),
@@ -71,6 +73,120 @@ def cpu_baseline(mesh, seconds_target=20.0):
             "cpu": platform.processor() or platform.machine()}
 
 
+KERNEL_SOURCES = ("lanczos.hip", "solver_dev.h", "common.h", "kernels.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles",
+                            "k_lz_project_box256x256x128-clustered10-renum-4096_traffic.txt")
+
+
+def kernel_source_hash():
+    """sha256 over the sources of the profiled kernel (stale counters are not reported)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_14659_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, kernel):
+    """HBM bytes per launch of the kernel from the committed counter summary,
+    or None when there is none for this workload and kernel or the kernel's
+    sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if (kv.get("workload") != workload or kv.get("kernel") != kernel
+            or kv.get("source_sha256_16") != kernel_source_hash()):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def copy_probe():
+    """A plain device copy of known size, run under the same counters as the
+    kernel to calibrate FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = 1 << 28  # float32 elements: 1 GiB per buffer
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
+
+
+def _counter_mean(csv_path, name_re, counter):
+    """Mean per-dispatch value of a counter over the dispatches whose kernel
+    name matches name_re (rocprofv3 counter_collection.csv)."""
+    import csv
+    import re
+    vals = {}
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] == counter and re.search(name_re, r["Kernel_Name"]):
+            key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    if not vals:
+        raise SystemExit(f"no {counter} rows for /{name_re}/ in {csv_path}")
+    return sum(vals.values()) / len(vals), len(vals)
+
+
+def stats_summary(a):
+    """Text table of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    import csv
+    rows = list(csv.DictReader(open(a.stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = [f"# rocprofv3 kernel statistics, workload {a.workload}",
+           f"# command: {a.commands}",
+           f"# all kernels: {total / 1e6:.1f} ms device time",
+           f"{'kernel':72s} {'calls':>8s} {'total ms':>10s} {'avg us':>10s} {'%':>6s}"]
+    for r in rows[:a.top]:
+        name = re.sub(r"rsb::\(anonymous namespace\)::", "", r["Name"])
+        name = re.sub(r"\(.*", "", name.replace("void ", ""))[:72]
+        out.append(f"{name:72s} {int(r['Calls']):8d} {float(r['TotalDurationNs']) / 1e6:10.2f} "
+                   f"{float(r['AverageNs']) / 1e3:10.1f} {float(r['Percentage']):6.2f}")
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def traffic_summary(a):
+    """Write the counter summary that bench.py reads for roofline.traffic."""
+    kre = re.escape(a.kernel_name)
+    f_k, nk = _counter_mean(a.fetch_csv, kre, "FETCH_SIZE")
+    w_k, nkw = _counter_mean(a.write_csv, kre, "WRITE_SIZE")
+    f_c, nc = _counter_mean(a.copy_fetch_csv, "elementwise|copy", "FETCH_SIZE")
+    w_c, _ = _counter_mean(a.copy_write_csv, "elementwise|copy", "WRITE_SIZE")
+    copy_bytes = float(1 << 30)
+    f_fac = copy_bytes / (f_c * 1024.0)
+    w_fac = copy_bytes / (w_c * 1024.0)
+    traffic = f_k * 1024.0 * f_fac + w_k * 1024.0 * w_fac
+    lines = [
+        "# HBM traffic of the dominant bench kernel from rocprofv3 counters",
+        f"# commands: {a.commands}",
+        f"workload: {a.workload}",
+        f"kernel: {a.kernel_label}",
+        f"kernel_name: {a.kernel_name}",
+        f"source_sha256_16: {kernel_source_hash()}",
+        f"dispatches_fetch: {nk}",
+        f"dispatches_write: {nkw}",
+        f"fetch_kib_per_dispatch: {f_k:.1f}",
+        f"write_kib_per_dispatch: {w_k:.1f}",
+        f"copy_fetch_kib_per_1GiB_copy: {f_c:.1f}",
+        f"copy_write_kib_per_1GiB_copy: {w_c:.1f}",
+        f"fetch_scale: {f_fac:.4f}",
+        f"write_scale: {w_fac:.4f}",
+        f"hbm_bytes_per_launch: {traffic:.0f}",
+    ]
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,10 +206,31 @@ def main():
     ap.add_argument("--autotune-cache", default=None)
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps with graph replay and no kernel timing (no roofline)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--traffic-summary", action="store_true",
+                    help="write the counter summary from rocprofv3 counter CSVs (no GPU)")
+    ap.add_argument("--fetch-csv")
+    ap.add_argument("--write-csv")
+    ap.add_argument("--copy-fetch-csv")
+    ap.add_argument("--copy-write-csv")
+    ap.add_argument("--kernel-name", default="k_lz_project<float, 4, 0, 3>")
+    ap.add_argument("--kernel-label", default=KERNEL_LABEL)
+    ap.add_argument("--commands", default="")
+    ap.add_argument("--out", default=TRAFFIC_FILE)
+    ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV", dest="stats_csv",
+                    help="write a text table of a rocprofv3 kernel_stats.csv to --out (no GPU)")
+    ap.add_argument("--top", type=int, default=30)
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args)
+        return
+    if args.stats_csv:
+        stats_summary(args)
+        return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "design is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has "
+              "no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -101,6 +238,9 @@ def main():
 
     import paper_2606_14659_amd as rsb
 
+    if args.copy_probe:
+        copy_probe()
+        return
     wl = WORKLOADS[args.workload]
     mesh = make_mesh(args.workload)
     print(f"[bench] {args.workload}: {mesh.nelem} elements", file=sys.stderr, flush=True)
@@ -178,9 +318,12 @@ def main():
         "ms_solve": st["ms_solve"],
         "ms_split": st["ms_split"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": (f"k_lz_project (SpMV + projection, Lanczos steps j>=3), "
-                                f"{st['tile_rows']}-row tiles at level 0"),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic(args.workload, KERNEL_LABEL) if st["tile_rows"] == 1024
+                     else None,
+                     "kernel": KERNEL_LABEL,
+                     "tile_rows_level0": st["tile_rows"],
+                     "algorithmic_bytes_per_launch": kern_bytes / max(kern_launches, 1),
                      "launches": kern_launches,
                      "avg_us": kern_ms * 1e3 / max(kern_launches, 1)},
     }
