@@ -159,8 +159,8 @@ def traffic_summary(a):
     kre = re.escape(a.kernel_name)
     f_k, nk = _counter_mean(a.fetch_csv, kre, "FETCH_SIZE")
     w_k, nkw = _counter_mean(a.write_csv, kre, "WRITE_SIZE")
-    f_c, nc = _counter_mean(a.copy_fetch_csv, "elementwise|copy", "FETCH_SIZE")
-    w_c, _ = _counter_mean(a.copy_write_csv, "elementwise|copy", "WRITE_SIZE")
+    f_c, nc = _counter_mean(a.copy_fetch_csv, "copyBuffer", "FETCH_SIZE")
+    w_c, _ = _counter_mean(a.copy_write_csv, "copyBuffer", "WRITE_SIZE")
     copy_bytes = float(1 << 30)
     f_fac = copy_bytes / (f_c * 1024.0)
     w_fac = copy_bytes / (w_c * 1024.0)

@@ -283,6 +283,21 @@ def test_inverse_iteration_agrees_with_lanczos(orc):
     assert abs(abs(y1 @ y2) - 1.0) < 1e-6
 
 
+@pytest.mark.parametrize("keep", [0, 3, 8])
+def test_inverse_iteration_matches_dense_eigh(orc, keep):
+    # plain CG (keep = 0) and CG with each new direction L-orthogonalised
+    # against up to `keep` earlier ones reach the same Fiedler pair
+    mesh = mg.uniform_holes(mg.box_hex(7, 6, 5), 0.05, 11)
+    rp, col, w = orc.dual_graph(mesh.ids)
+    ev, V = np.linalg.eigh(dense_laplacian(rp, col, w))
+    assert ev[2] - ev[1] > 1e-3 * ev[1]
+    st, lam, y, info = orc.fiedler(mesh.ids, method="inverse_cg", tol=1e-10, inv_max_outer=400,
+                                   cg_full_projection=keep)
+    assert st == 0
+    assert abs(lam - ev[1]) <= 1e-9 * ev[1]
+    assert abs(abs(y @ V[:, 1]) - 1.0) < 1e-7
+
+
 def test_cg_one_step_on_eigenvector(orc):
     # With b an exact eigenvector, CG from x0 = 0 returns b / lambda in one
     # step, so inverse iteration stops after its first outer pass (Sec. 7).
