@@ -24,7 +24,8 @@ class Opts(C.Structure):
     _fields_ = [("graph", C.c_int32), ("method", C.c_int32), ("lanczos_m", C.c_int32),
                 ("max_restarts", C.c_int32), ("tol", C.c_double), ("inv_max_outer", C.c_int32),
                 ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
-                ("cg_full_projection", C.c_int32), ("seed", C.c_uint64)]
+                ("cg_full_projection", C.c_int32), ("seed", C.c_uint64),
+                ("lanczos_keep", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -63,6 +64,7 @@ def lib():
                                           C.c_void_p, C.c_void_p]
         L.orc_tridiag_smallest.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
                                            P(C.c_double), C.c_void_p]
+        L.orc_jacobi_eigen.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_fiedler.argtypes = [C.c_int64, C.c_int32, C.c_void_p, P(Opts), C.c_void_p,
                                   P(C.c_double), P(Info)]
         L.orc_fiedler_csr.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -90,6 +92,16 @@ def opts(**kw) -> Opts:
             v = METHOD[v]
         setattr(o, k, v)
     return o
+
+
+def jacobi_eigen(A):
+    """(eigenvalues ascending, eigenvectors as columns) of a symmetric matrix."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    k = A.shape[0]
+    ev = np.zeros(k)
+    V = np.zeros((k, k))
+    lib().orc_jacobi_eigen(k, _ptr(A), _ptr(ev), _ptr(V))
+    return ev, V
 
 
 def start_value(seed: int, gid: int) -> float:

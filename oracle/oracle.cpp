@@ -11,8 +11,8 @@
 //  * the ones vector u0 = 1/sqrt(n) is kept in the reorthogonalisation basis;
 //  * two classical Gram-Schmidt passes per Lanczos step;
 //  * convergence when ||L y - rho y||_2 <= tol * rho (rho the Rayleigh quotient
-//    of the Ritz vector); explicit restart
-//    from the Ritz vector; at most max_restarts restarts;
+//    of the Ritz vector); explicit restart from the Ritz vector, or thick
+//    restart keeping the smallest Ritz pairs; at most max_restarts restarts;
 //  * canonical sign: the first element (in global-id order) whose |y| is at
 //    least 1e-3 max|y| gets y <= 0;
 //  * ties in the sort broken by global id, -0.0 before +0.0;
@@ -256,7 +256,77 @@ double rayleigh(const Graph &g, const Vec &y, int64_t &matvecs) {
   return dot(y, ly) / dot(y, y);
 }
 
+// Eigen-decomposition of a symmetric k x k matrix (row-major) by the cyclic
+// Jacobi method (Golub & Van Loan, Sec. 8.5): rotations in every (p, q)
+// plane until the off-diagonal part is at rounding level.  Output: the
+// eigenvalues in ascending order and the eigenvectors as columns of V.
+void jacobi_eigen(int k, Vec A, Vec &ev, Vec &V) {
+  V.assign((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) V[(size_t)i * k + i] = 1.0;
+  double fro = 0.0;
+  for (double v : A) fro += v * v;
+  fro = std::sqrt(fro);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) off += 2.0 * A[(size_t)p * k + q] * A[(size_t)p * k + q];
+    if (std::sqrt(off) <= 1e-15 * fro || fro == 0.0) break;
+    for (int p = 0; p < k; ++p) {
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A[(size_t)p * k + q];
+        if (apq == 0.0) continue;
+        // 2x2 symmetric Schur decomposition: c, s with tan = t
+        const double tau = (A[(size_t)q * k + q] - A[(size_t)p * k + p]) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        // A <- J^T A J with J the rotation in the (p, q) plane
+        for (int r = 0; r < k; ++r) {
+          const double arp = A[(size_t)r * k + p], arq = A[(size_t)r * k + q];
+          A[(size_t)r * k + p] = c * arp - sn * arq;
+          A[(size_t)r * k + q] = sn * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double apr = A[(size_t)p * k + r], aqr = A[(size_t)q * k + r];
+          A[(size_t)p * k + r] = c * apr - sn * aqr;
+          A[(size_t)q * k + r] = sn * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = V[(size_t)r * k + p], vrq = V[(size_t)r * k + q];
+          V[(size_t)r * k + p] = c * vrp - sn * vrq;
+          V[(size_t)r * k + q] = sn * vrp + c * vrq;
+        }
+      }
+    }
+  }
+  // sort ascending (stable selection on the diagonal)
+  std::vector<int> order(k);
+  for (int i = 0; i < k; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return A[(size_t)a * k + a] < A[(size_t)b * k + b];
+  });
+  Vec V2((size_t)k * k);
+  ev.assign(k, 0.0);
+  for (int c = 0; c < k; ++c) {
+    ev[c] = A[(size_t)order[c] * k + order[c]];
+    for (int r = 0; r < k; ++r) V2[(size_t)r * k + c] = V[(size_t)r * k + order[c]];
+  }
+  V.swap(V2);
+}
+
 // Restarted Lanczos with full reorthogonalisation (Sec. 6).
+//
+// keep = 0: explicit restart -- every cycle starts a new Krylov space from
+// the current Ritz vector (the scheme the paper describes).
+// keep > 0: thick restart (Wu and Simon, the Lanczos variant the paper
+// cites in Sec. 6): the cycle keeps the `keep` smallest Ritz pairs
+// (theta_i, y_i) and continues from the last Lanczos residual direction
+// q = w / beta.  The projected matrix of the next cycle is then
+//   [ diag(theta)  s        ]
+//   [ s^T          alpha ... ]  (tridiagonal from there on),
+// with s_i = beta * (last component of the i-th Ritz vector of the small
+// problem).  The first kept vector is the Ritz vector used for the
+// convergence test, re-projected against the ones vector and normalised.
+// A cycle that ends by breakdown restarts explicitly.
 int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_opts &o, Vec &y,
                     double &lambda, orc_info &info) {
   const int64_t n = g.n;
@@ -265,23 +335,38 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
   for (int64_t i = 0; i < n; ++i) q[i] = start_value(o.seed, gid[i]);
   deflate_ones(q);
   normalize(q);
-  int m = std::max(1, o.lanczos_m);
+  const int m = std::max(1, o.lanczos_m);
+  const int keep = std::max(0, o.lanczos_keep);
   int converged = 0;
   double theta = 0.0, res = 0.0;
   y = q;
+  std::vector<Vec> Y;         // kept Ritz vectors (thick restart)
+  Vec th_keep, s_keep;        // their Ritz values and couplings to q
   for (int cycle = 0; cycle <= o.max_restarts; ++cycle) {
-    std::vector<Vec> Q;
+    const int nk = (int)Y.size();
+    std::vector<Vec> Q(Y);
     Q.push_back(q);
-    std::vector<double> alpha, beta(1, 0.0);  // beta[j] couples Q[j-1] and Q[j]
-    Vec w(n);
+    Vec H((size_t)m * m, 0.0);  // projected matrix (thick restart)
+    std::vector<double> alpha(nk, 0.0), beta(nk + 1, 0.0);  // beta[j] couples Q[j-1], Q[j]
     double tnorm = 0.0;
-    for (int j = 0; j < m; ++j) {
+    for (int i = 0; i < nk; ++i) {
+      H[(size_t)i * m + i] = th_keep[i];
+      H[(size_t)i * m + nk] = H[(size_t)nk * m + i] = s_keep[i];
+      tnorm = std::max(tnorm, std::fabs(th_keep[i]) + std::fabs(s_keep[i]));
+    }
+    Vec w(n);
+    double last_b = 0.0;
+    bool breakdown = false;
+    for (int j = nk; j < m; ++j) {
       apply_laplacian(g, Q[j], w);
       ++info.matvecs;
       double a = dot(Q[j], w);
       for (int64_t i = 0; i < n; ++i) {
         w[i] -= a * Q[j][i];
-        if (j > 0) w[i] -= beta[j] * Q[j - 1][i];
+        if (j == nk)
+          for (int c = 0; c < nk; ++c) w[i] -= s_keep[c] * Y[c][i];
+        else
+          w[i] -= beta[j] * Q[j - 1][i];
       }
       // two classical Gram-Schmidt passes against [u0, Q[0..j]]
       for (int pass = 0; pass < 2; ++pass) {
@@ -297,17 +382,39 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
         a += h[j];
       }
       alpha.push_back(a);
+      H[(size_t)j * m + j] = a;
       double b = norm2(w);
-      tnorm = std::max(tnorm, std::fabs(a) + b + beta[j]);
-      if (j == m - 1 || b <= 1e-12 * tnorm) break;
+      tnorm = std::max(tnorm, std::fabs(a) + b + (j == nk ? 0.0 : beta[j]));
+      last_b = b;
+      if (j == m - 1) break;
+      if (b <= 1e-12 * tnorm) {
+        breakdown = true;
+        break;
+      }
       beta.push_back(b);
+      H[(size_t)j * m + j + 1] = H[(size_t)(j + 1) * m + j] = b;
       Vec qn(n);
       for (int64_t i = 0; i < n; ++i) qn[i] = w[i] / b;
       Q.push_back(qn);
     }
-    int k = (int)alpha.size();
-    Vec t;
-    if (tridiag_smallest(k, alpha.data(), beta.data(), 1e-10 * tnorm, &theta, t) != 0) return -5;
+    const int k = (int)Q.size();
+    const double thr = 1e-10 * tnorm;
+    Vec t;                    // Ritz coefficients of the vector tested for convergence
+    Vec ev, EV;               // all eigenpairs of H (thick restart)
+    int first = 0;
+    if (keep == 0) {
+      if (tridiag_smallest(k, alpha.data(), beta.data(), thr, &theta, t) != 0) return -5;
+    } else {
+      Vec Hk((size_t)k * k);
+      for (int r = 0; r < k; ++r)
+        for (int c = 0; c < k; ++c) Hk[(size_t)r * k + c] = H[(size_t)r * m + c];
+      jacobi_eigen(k, Hk, ev, EV);
+      while (first < k && ev[first] < thr) ++first;
+      if (first >= k) return -5;
+      theta = ev[first];
+      t.assign(k, 0.0);
+      for (int r = 0; r < k; ++r) t[r] = EV[(size_t)r * k + first];
+    }
     // Ritz vector y = Q t, re-projected against the ones vector and normalised
     y.assign(n, 0.0);
     for (int c = 0; c < k; ++c)
@@ -322,7 +429,31 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
       converged = 1;
       break;
     }
-    q = y;
+    if (keep == 0 || breakdown || k < 2) {
+      Y.clear();
+      q = y;
+      continue;
+    }
+    // thick restart: keep the smallest Ritz pairs above the threshold
+    const int nkeep = std::min(std::min(keep, k - 1), k - first);
+    std::vector<Vec> Ynew;
+    Ynew.push_back(y);
+    for (int c = 1; c < nkeep; ++c) {
+      Vec yc(n, 0.0);
+      for (int r = 0; r < k; ++r) {
+        const double tr = EV[(size_t)r * k + first + c];
+        for (int64_t i = 0; i < n; ++i) yc[i] += tr * Q[r][i];
+      }
+      Ynew.push_back(yc);
+    }
+    th_keep.assign(nkeep, 0.0);
+    s_keep.assign(nkeep, 0.0);
+    for (int c = 0; c < nkeep; ++c) {
+      th_keep[c] = ev[first + c];
+      s_keep[c] = last_b * EV[(size_t)(k - 1) * k + first + c];
+    }
+    Y.swap(Ynew);
+    for (int64_t i = 0; i < n; ++i) q[i] = w[i] / last_b;
   }
   info.theta = theta;
   info.residual = res;
@@ -619,6 +750,7 @@ void orc_opts_default(orc_opts *o) {
   o->cg_tol = 1e-8;
   o->cg_full_projection = 0;
   o->seed = 20261203ULL;
+  o->lanczos_keep = 0;
 }
 
 double orc_start_value(uint64_t seed, int64_t gid) { return start_value(seed, gid); }
@@ -662,6 +794,13 @@ int orc_tridiag_smallest(int32_t k, const double *a, const double *b, double spu
   int r = tridiag_smallest(k, a, b, spurious_thr, theta, tv);
   if (r == 0) std::copy(tv.begin(), tv.end(), t);
   return r;
+}
+
+void orc_jacobi_eigen(int32_t k, const double *A, double *ev, double *V) {
+  Vec a(A, A + (size_t)k * k), e, v;
+  jacobi_eigen(k, a, e, v);
+  std::copy(e.begin(), e.end(), ev);
+  std::copy(v.begin(), v.end(), V);
 }
 
 int orc_fiedler_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,

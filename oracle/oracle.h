@@ -40,6 +40,8 @@ typedef struct orc_opts {
   int32_t cg_full_projection;/* 0: plain CG; k>0: L-orthogonalise each new
                                 direction against up to k kept directions */
   uint64_t seed;             /* start-vector seed */
+  int32_t lanczos_keep;      /* 0: explicit restart from the Ritz vector; k > 0:
+                                thick restart keeping the k smallest Ritz pairs */
 } orc_opts;
 
 typedef struct orc_info {
@@ -67,6 +69,10 @@ int orc_dual_graph(int64_t nelem, int32_t nv, const int64_t *ids, int32_t graph,
 /* y = L x with L = D - A from the CSR above. */
 void orc_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col,
                          const int32_t *weight, const double *x, double *y);
+
+/* Eigenvalues (ascending) and eigenvectors (columns of V, row-major k x k)
+ * of a symmetric k x k matrix A (row-major), cyclic Jacobi. */
+void orc_jacobi_eigen(int32_t k, const double *A, double *ev, double *V);
 
 /* Smallest eigenpair of the symmetric tridiagonal matrix with diagonal
  * a[0..k-1] and off-diagonal b[1..k-1] (b[0] ignored), skipping eigenvalues

@@ -1,0 +1,175 @@
+"""GPU checks at the full sizes of the benchmark configurations, in the launch
+configuration the benchmark uses (device-resident ids, batched levels,
+default tiles).  Where the oracle cannot finish in seconds the checks are
+sampled outputs it (or the plain definition) computes one by one, and
+properties that hold at any size.
+
+C1 16^3 cube, face graph: one 100-step Lanczos cycle and RSB to 8.
+C2 128x128x64, 5% holes: dual graph bit-exact; Fiedler pair by Lanczos
+   (FP64) and by inverse iteration, residual checked in FP64 on the CPU.
+C3/C4 256x256x64, 3% holes: RSB to 1024 in FP64 and mixed precision.
+C5a 256x256x128, 10% clustered holes, renumbered ids: RSB to 4096 as the
+   benchmark runs it.
+C5b 64 meshes of 10k-500k elements, 16 parts each, one batched call.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+import paper_2606_14659_amd as rsb
+
+pytestmark = pytest.mark.gpu
+
+BENCH = dict(precision="mixed", tol=1e-2, lanczos_m=100, max_restarts=50)
+
+
+def _torch_ids(ids):
+    import torch
+    return torch.as_tensor(ids).cuda()
+
+
+def _host(a):
+    return a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+
+
+def check_balance(part, nelem, nparts):
+    sizes = np.bincount(part, minlength=nparts)
+    assert part.min() >= 0 and part.max() < nparts
+    assert sizes.min() == nelem // nparts
+    assert sizes.max() == -(-nelem // nparts)
+
+
+def cut_from_csr(rp, col, w, part):
+    rows = np.repeat(np.arange(len(rp) - 1, dtype=np.int64), np.diff(rp))
+    cross = part[rows] != part[col]
+    return float(w[cross].sum()) / 2.0, int(cross.sum()) // 2
+
+
+def brute_force_rows(ids, rows):
+    """Dual-graph rows of the given elements from the definition: s_ij =
+    number of distinct vertex ids shared by elements i and j."""
+    flat = ids.ravel()
+    order = np.argsort(flat, kind="stable")
+    sv = flat[order]
+    owner = order // ids.shape[1]
+    out = {}
+    for i in rows:
+        cnt = {}
+        for v in np.unique(ids[i]):
+            lo, hi = np.searchsorted(sv, v, "left"), np.searchsorted(sv, v, "right")
+            for j in np.unique(owner[lo:hi]):
+                if j != i:
+                    cnt[int(j)] = cnt.get(int(j), 0) + 1
+        out[int(i)] = sorted(cnt.items())
+    return out
+
+
+def check_sampled_rows(ids, rp, col, w, count, seed):
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(len(ids), size=count, replace=False))
+    ref = brute_force_rows(ids, rows)
+    for i in rows:
+        got = list(zip(col[rp[i]:rp[i + 1]].tolist(), w[rp[i]:rp[i + 1]].tolist()))
+        assert got == ref[int(i)], f"row {i}"
+
+
+def test_c1_cube16_one_cycle_and_rsb8(orc):
+    ids = mg.cube16().ids
+    lam_exact = 2.0 - 2.0 * math.cos(math.pi / 16)  # multiplicity 3
+    kw = dict(graph="face", lanczos_m=100, max_restarts=0, tol=1e-14)
+    st, lam, y, _ = rsb.fiedler(ids, **kw)
+    ost, olam, oy, _ = orc.fiedler(ids, **kw)
+    # one cycle of 100 steps from the same start vector on both sides
+    assert abs(lam - olam) <= 1e-10 * olam
+    assert abs(lam - lam_exact) <= 1e-8 * lam_exact
+    st, part, stats = rsb.partition(ids, 8, graph="face", tol=1e-8)
+    ost, opart, _ = orc.partition(ids, 8, graph="face", tol=1e-8)
+    check_balance(part, len(ids), 8)
+    cut = orc.metrics(ids, part, 8)["weighted_cut"]
+    ocut = orc.metrics(ids, opart, 8)["weighted_cut"]
+    assert abs(cut - ocut) <= 0.01 * ocut
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return mg.box128_holes5()
+
+
+def test_c2_dual_graph_bit_exact(orc, c2):
+    rp, col, w = rsb.dual_graph(c2.ids)
+    orp, ocol, ow = orc.dual_graph(c2.ids)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol) and np.array_equal(w, ow)
+
+
+@pytest.mark.parametrize("method", ["lanczos", "inverse_cg"])
+def test_c2_fiedler_fp64(orc, c2, method):
+    tol = 1e-6
+    st, lam, y, stats = rsb.fiedler(c2.ids, method=method, tol=tol, inv_max_outer=100)
+    assert st == 0
+    rp, col, w = orc.dual_graph(c2.ids)
+    ly = orc.laplacian_apply(rp, col, w, y)
+    rho = float(y @ ly)
+    assert abs(np.linalg.norm(y) - 1.0) < 1e-12
+    assert abs(y.sum()) < 1e-9 * math.sqrt(len(y))
+    assert abs(lam - rho) <= 1e-12 * rho
+    res = np.linalg.norm(ly - rho * y)
+    assert res <= 1.01 * tol * rho
+    # every Fiedler pair of the mesh has the same Rayleigh quotient to O(res^2 / gap)
+    test_c2_fiedler_fp64.lams = getattr(test_c2_fiedler_fp64, "lams", {})
+    test_c2_fiedler_fp64.lams[method] = lam
+    if len(test_c2_fiedler_fp64.lams) == 2:
+        a, b = test_c2_fiedler_fp64.lams.values()
+        assert abs(a - b) <= 1e-6 * a
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return mg.box256_holes3()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c3_c4_rsb_1024(c3, precision):
+    ids = _torch_ids(c3.ids)
+    st, part, stats = rsb.partition(ids, 1024, device=True, precision=precision, tol=1e-2)
+    assert st in (0, 1)
+    part = _host(part)
+    check_balance(part, c3.nelem, 1024)
+    rp, col, w = rsb.dual_graph(ids, device=True)
+    cut, pairs = cut_from_csr(_host(rp), _host(col), _host(w), part)
+    assert stats["edge_cut"] == cut and stats["cut_pairs"] == pairs
+    test_c3_c4_rsb_1024.cuts = getattr(test_c3_c4_rsb_1024, "cuts", {})
+    test_c3_c4_rsb_1024.cuts[precision] = cut
+    if len(test_c3_c4_rsb_1024.cuts) == 2:
+        a, b = test_c3_c4_rsb_1024.cuts["fp64"], test_c3_c4_rsb_1024.cuts["mixed"]
+        print(f"C3/C4 weighted cut fp64 {a:.0f} mixed {b:.0f} ({(b - a) / a:+.3%})")
+        assert abs(b - a) <= 0.05 * a
+
+
+def test_c5a_rsb_4096_as_benchmarked():
+    mesh = mg.box256x128_clustered10()
+    ids = _torch_ids(mesh.ids)
+    st, part, stats = rsb.partition(ids, 4096, device=True, **BENCH)
+    assert st in (0, 1)
+    part = _host(part)
+    check_balance(part, mesh.nelem, 4096)
+    rp, col, w = rsb.dual_graph(ids, device=True)
+    rp, col, w = _host(rp), _host(col), _host(w)
+    check_sampled_rows(mesh.ids, rp, col, w, count=300, seed=5)
+    cut, pairs = cut_from_csr(rp, col, w, part)
+    assert stats["edge_cut"] == cut and stats["cut_pairs"] == pairs
+    assert stats["levels"] == 12
+
+
+def test_c5b_batch64_16_parts():
+    meshes = mg.batch64()
+    st, parts, stats = rsb.partition_batch([m.ids for m in meshes], [16] * len(meshes), **BENCH)
+    assert st in (0, 1)
+    for m, p in zip(meshes, parts):
+        check_balance(np.asarray(p), m.nelem, 16)
+    # single calls on sampled meshes give the same partitions
+    sizes = np.array([m.nelem for m in meshes])
+    for b in (int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2])):
+        s1, p1, _ = rsb.partition(meshes[b].ids, 16, **BENCH)
+        assert np.array_equal(p1, parts[b])

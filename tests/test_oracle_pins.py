@@ -298,6 +298,63 @@ def test_inverse_iteration_matches_dense_eigh(orc, keep):
     assert abs(abs(y @ V[:, 1]) - 1.0) < 1e-7
 
 
+@pytest.mark.parametrize("k", [1, 2, 7, 40])
+def test_jacobi_eigen_matches_eigh(orc, k):
+    rng = np.random.default_rng(k)
+    A = rng.standard_normal((k, k))
+    A = A + A.T
+    if k >= 7:  # a close pair as well
+        Q, _ = np.linalg.qr(rng.standard_normal((k, k)))
+        d = np.sort(rng.standard_normal(k))
+        d[1] = d[0] + 1e-9
+        A = (Q * d) @ Q.T
+        A = 0.5 * (A + A.T)
+    ev, V = orc.jacobi_eigen(A)
+    scale = np.abs(A).max()
+    assert np.all(np.diff(ev) >= 0)
+    assert np.abs(ev - np.linalg.eigvalsh(A)).max() <= 1e-13 * k * scale
+    assert np.abs(A @ V - V * ev).max() <= 1e-13 * k * scale
+    assert np.abs(V.T @ V - np.eye(k)).max() <= 1e-13 * k
+
+
+def test_thick_restart_keep_one_is_explicit_restart(orc):
+    # keeping one Ritz vector and the residual direction spans the same
+    # Krylov space as restarting from the Ritz vector, cycle after cycle
+    mesh = mg.uniform_holes(mg.box_hex(16, 16, 8), 0.05, 3)
+    kw = dict(lanczos_m=8, tol=1e-15, max_restarts=4)
+    _, lam0, y0, i0 = orc.fiedler(mesh.ids, lanczos_keep=0, **kw)
+    _, lam1, y1, i1 = orc.fiedler(mesh.ids, lanczos_keep=1, **kw)
+    assert abs(lam0 - lam1) <= 1e-12 * lam0
+    assert abs(i0["theta"] - i1["theta"]) <= 1e-12 * lam0
+    assert abs(abs(y0 @ y1) - 1.0) < 1e-9
+
+
+@pytest.mark.parametrize("name,mesh", small_meshes())
+def test_thick_restart_matches_dense_eigh(orc, name, mesh):
+    rp, col, w = orc.dual_graph(mesh.ids)
+    ev, V = np.linalg.eigh(dense_laplacian(rp, col, w))
+    if int(np.sum(np.abs(ev) < 1e-9)) != 1:
+        return
+    m = max(4, min(12, len(mesh.ids) - 2))
+    st, lam, y, info = orc.fiedler(mesh.ids, lanczos_m=m, lanczos_keep=3, tol=1e-10,
+                                   max_restarts=500)
+    assert st == 0
+    assert abs(lam - ev[1]) <= 1e-10 * ev[1]
+    if ev[2] - ev[1] > 1e-6 * ev[1]:
+        assert abs(abs(y @ V[:, 1]) - 1.0) < 1e-8
+
+
+def test_thick_restart_does_not_stagnate(orc):
+    # near-degenerate Fiedler pair (16 x 16 x 8 box with holes): restarting
+    # from the Ritz vector stalls, keeping the lowest Ritz pairs converges
+    mesh = mg.uniform_holes(mg.box_hex(16, 16, 8), 0.05, 3)
+    kw = dict(lanczos_m=12, tol=1e-8, max_restarts=100)
+    st0, _, _, i0 = orc.fiedler(mesh.ids, lanczos_keep=0, **kw)
+    st4, lam4, _, i4 = orc.fiedler(mesh.ids, lanczos_keep=4, **kw)
+    assert st0 == 1 and i0["residual"] > 1e-6 * lam4
+    assert st4 == 0 and i4["cycles"] < 40
+
+
 def test_cg_one_step_on_eigenvector(orc):
     # With b an exact eigenvector, CG from x0 = 0 returns b / lambda in one
     # step, so inverse iteration stops after its first outer pass (Sec. 7).
