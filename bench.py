@@ -197,6 +197,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--tol", type=float, default=1e-2)
     ap.add_argument("--m", type=int, default=100)
+    ap.add_argument("--keep", type=int, default=0,
+                    help="thick restart keeping this many Ritz pairs (0: explicit restart)")
     ap.add_argument("--max-restarts", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0)
@@ -248,7 +250,7 @@ def main():
     ids = torch.as_tensor(mesh.ids).cuda()
     part = torch.empty(mesh.nelem, dtype=torch.int32, device="cuda")
     opts = dict(precision=args.precision, tol=args.tol, lanczos_m=args.m,
-                max_restarts=args.max_restarts, verbose=args.verbose,
+                max_restarts=args.max_restarts, verbose=args.verbose, lanczos_keep=args.keep,
                 batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
                 autotune=args.autotune)
     if args.autotune_cache:
@@ -302,7 +304,8 @@ def main():
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "elements": mesh.nelem, "nparts": wl["nparts"],
-                   "precision": args.precision, "lanczos_m": args.m, "tol": args.tol,
+                   "precision": args.precision, "lanczos_m": args.m, "lanczos_keep": args.keep,
+                   "tol": args.tol,
                    "max_restarts": args.max_restarts, "graph": "weighted vertex-shared",
                    "batched": not args.unbatched},
         "time_to_partition_ms": dt * 1e3 / args.steps,

@@ -98,7 +98,14 @@ typedef struct rsb_opts {
   int32_t rows_per_thread;  /* tile of the streaming kernels, 256 * rows_per_thread
                                rows per workgroup: 0 = chosen by the library (see
                                autotune), else 2, 4 or 8 for every level */
-  int32_t reserved[6];
+  int32_t lanczos_keep;     /* 0 (default): explicit restart, every cycle starts
+                               from the current Ritz vector (Sec. 6); k in
+                               [1, min(16, lanczos_m - 1)]: thick restart (the
+                               Lanczos variant the paper cites in Sec. 6) keeping
+                               the k smallest Ritz pairs and continuing from the
+                               last residual direction.  Thick restart needs
+                               precision = RSB_FP64 (RSB_EINVAL otherwise). */
+  int32_t reserved[5];
 } rsb_opts;
 
 typedef struct rsb_stats {

@@ -34,7 +34,8 @@ class Opts(C.Structure):
         ("seed", C.c_uint64), ("use_hipgraph", C.c_int32), ("autotune", C.c_int32),
         ("autotune_cache", C.c_char_p), ("device", C.c_int32), ("device_pointers", C.c_int32),
         ("stream", C.c_void_p), ("device_mem_limit", C.c_int64), ("verbose", C.c_int32),
-        ("profile", C.c_int32), ("rows_per_thread", C.c_int32), ("reserved", C.c_int32 * 6),
+        ("profile", C.c_int32), ("rows_per_thread", C.c_int32), ("lanczos_keep", C.c_int32),
+        ("reserved", C.c_int32 * 5),
     ]
 
 

@@ -48,6 +48,14 @@ void check_opts(const rsb_opts *o) {
   if (o->inv_max_outer < 1 || o->cg_max_iter < 1) fail(RSB_EINVAL, "inverse iteration caps");
   if (o->cg_full_projection != 0) fail(RSB_EINVAL, "cg_full_projection is not supported");
   if (o->autotune < 0 || o->autotune > 2) fail(RSB_EINVAL, "autotune");
+  if (o->lanczos_keep < 0 || o->lanczos_keep > kMaxKeep ||
+      (o->lanczos_keep > 0 && o->lanczos_keep >= o->lanczos_m))
+    fail(RSB_EINVAL, "lanczos_keep must be 0 or in [1, min(16, lanczos_m - 1)]");
+  if (o->lanczos_keep > 0 && o->precision == RSB_MIXED && o->method == RSB_LANCZOS)
+    fail(RSB_EINVAL,
+         "thick restart (lanczos_keep > 0) needs FP64 vectors: with FP32 directions a "
+         "second Gram-Schmidt pass on every step would be needed to keep them orthogonal "
+         "to the kept Ritz vectors");
   if (o->rows_per_thread != 0 && o->rows_per_thread != 2 && o->rows_per_thread != 4 &&
       o->rows_per_thread != 8)
     fail(RSB_EINVAL, "rows_per_thread must be 0, 2, 4 or 8");
@@ -146,7 +154,8 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
       InverseParams ip{o.inv_max_outer, o.cg_max_iter, o.cg_tol, o.tol, o.seed};
       return inverse_level(v, C, SS, ip, work, y64, graph, ctx);
     }
-    LanczosParams lp{o.lanczos_m, o.max_restarts, o.tol, graph ? 1 : 0, o.seed, prof, v.nnz};
+    LanczosParams lp{o.lanczos_m, o.lanczos_keep, o.max_restarts, o.tol, graph ? 1 : 0,
+                     o.seed,      prof,           v.nnz};
     return mixed ? lanczos_level<float>(v, C, SS, lp, work, y64, ctx)
                  : lanczos_level<double>(v, C, SS, lp, work, y64, ctx);
   };
@@ -162,7 +171,7 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     OneSeg os;
     one_segment_tables(L, s, os, ctx);
     SolveDev S1;
-    solve_alloc(S1, 1, os.nblk, os.ngrp, std::max(o.lanczos_m, 1), ctx);
+    solve_alloc(S1, 1, os.nblk, os.ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
     RSB_HIP(hipMemcpyAsync(S1.st.get(), S.st.get() + s, sizeof(SegState),
                            hipMemcpyDeviceToDevice, ctx.stream));
     LevelView v = view_of(L);
@@ -259,7 +268,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     CompDev C;
     choose_tile(*L, o, work.get(), ctx);
     if (level == 0) st.tile_rows = kBlock * L->rpt;
-    solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), ctx);
+    solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
     components_and_targets(*L, C, S, ctx);
     const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(),
                                       o.profile ? &prof : nullptr, ctx);

@@ -83,6 +83,9 @@ struct SegState {
   double rr;            // CG: r^T r
   double cg_alpha, cg_beta;
   int32_t cg_done;      // CG solve finished
+  int32_t j0;           // first Lanczos step of the current cycle (1, or nk + 1 after a thick restart)
+  int32_t nk;           // Ritz pairs kept at the head of the current cycle's basis
+  int32_t nnext;        // Ritz pairs formed at the end of the cycle (thick restart)
   int32_t pad;
 };
 
@@ -156,7 +159,11 @@ void level0_from_csr(Level &L, const std::vector<const DevCsr *> &g,
 // ---------------------------------------------------------------------------
 struct SolveDev {
   DevBuf<SegState> st;
-  DevBuf<double> alpha, beta, h, tvec;   // [nseg][pstride]
+  DevBuf<double> alpha, beta, h;         // [nseg][pstride]
+  DevBuf<double> tvec;                   // [nseg][nkcap][pstride] Ritz coefficients
+  DevBuf<double> tvals;                  // [nseg][nkcap] Ritz values
+  DevBuf<double> arrow;                  // [nseg][pstride] couplings of kept Ritz vectors
+  int nkcap = 1;                         // Ritz vectors formed per cycle (1, or the kept count)
   DevBuf<double> part, gpart;            // [nblk][pstride], [ngrp][pstride]
   DevBuf<unsigned> gcnt, scnt;           // counters (zero between launches)
   DevBuf<int32_t> n_active;              // [4]: active count, stats
@@ -185,6 +192,7 @@ struct KernelProfile {
 
 struct LanczosParams {
   int m;
+  int keep;              // 0: explicit restart; k > 0: thick restart keeping k Ritz pairs
   int max_restarts;
   double tol;
   int use_graph;
@@ -195,7 +203,7 @@ struct LanczosParams {
 // work: lanczos_workspace_bytes(L.nrows, m, T is float) bytes of device memory
 // (FP64 u0, q_1, restart and work vectors; type-T directions q_2..q_m and two
 // work vectors).  T = double: all FP64; T = float: mixed precision.
-void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, Ctx &ctx);
+void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx &ctx);
 size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32);
 // Device time (ms) of one Lanczos step of the level with its current tile.
 template <typename T>

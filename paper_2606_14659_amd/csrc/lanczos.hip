@@ -46,7 +46,11 @@ struct LzArgs {
   const GrpDev *grp;
   const SegDev *seg;
   SegState *st;
-  double *alpha, *beta, *h, *tvec;  // [nseg][ps]
+  double *alpha, *beta, *h;         // [nseg][ps]
+  double *tvec, *tvals;             // [nseg][nkcap][ps], [nseg][nkcap]
+  double *arrow;                    // [nseg][ps]
+  int nkcap;
+  int keep;                         // 0: explicit restart; k > 0: thick restart
   double *part, *gpart;             // [nblk][ps], [ngrp][ps]
   unsigned *gcnt, *scnt;
   int ps;
@@ -59,13 +63,16 @@ struct LzArgs {
   double *Y;     // restart vector (unnormalised Ritz vector)
   double *Wd;    // FP64 work vector of step 1
   T *V;          // q_k at V + k * vs for k >= 2
+  double *K;     // kept Ritz vectors of a thick restart, slot k (2 <= k <= nk) at
+                 // K + (k - 2) * vs (the basis slots; thick restart needs T = double)
   int64_t vs;
   T *Wt0, *Wt1;  // ping-pong work vectors of steps >= 2
   int m;
   double tol;
   int max_restarts;
   double brk;    // breakdown threshold (relative to ||T||) of the type-T steps
-  int32_t *flags;          // [0] active segments after the cycle, [1] max steps in the cycle
+  int32_t *flags;          // [0] active segments after the cycle, [1] last step index
+                           // reached in the cycle, [2] most steps run by a segment
   unsigned long long *ctr; // [0] segment steps
   uint64_t seed;
 };
@@ -124,18 +131,19 @@ __device__ inline double wave_dot_part(const P *__restrict__ v, const double *zs
   return acc;
 }
 
-// acc[r] += sum_{k = k0..k1} c_k V[k][row_r], 4 basis vectors per round so
-// that 4 * RPT loads are in flight per thread.
-template <typename T, int RPT>
-__device__ inline void accumulate_basis(const LzArgs<T> &a, const TileRows<RPT> &tr,
-                                        const double *coef, int k0, int k1, double (&acc)[RPT]) {
+// acc[r] += sum_{k = k0..k1} c_k B[k - kb][row_r] (vectors of stride vs), 4
+// vectors per round so that 4 * RPT loads are in flight per thread.
+template <typename P, int RPT>
+__device__ inline void accumulate_slots(const P *__restrict__ B, int kb, int64_t vs,
+                                        const TileRows<RPT> &tr, const double *coef, int k0,
+                                        int k1, double (&acc)[RPT]) {
   int k = k0;
   for (; k + 4 <= k1 + 1; k += 4) {
-    T v[4][RPT];
+    P v[4][RPT];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) v[kk][r] = a.V[(int64_t)(k + kk) * a.vs + tr.row[r]];
+      for (int r = 0; r < RPT; ++r) v[kk][r] = B[(int64_t)(k + kk - kb) * vs + tr.row[r]];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const double ck = coef[k + kk];
@@ -146,8 +154,18 @@ __device__ inline void accumulate_basis(const LzArgs<T> &a, const TileRows<RPT> 
   for (; k <= k1; ++k) {
     const double ck = coef[k];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) acc[r] += (double)a.V[(int64_t)k * a.vs + tr.row[r]] * ck;
+    for (int r = 0; r < RPT; ++r) acc[r] += (double)B[(int64_t)(k - kb) * vs + tr.row[r]] * ck;
   }
+}
+
+// acc[r] += sum_{k = 2..k1} c_k b_k[row_r] over the basis slots >= 2: the
+// FP64 kept Ritz vectors (2..nk) and the type-T Lanczos vectors after them.
+template <typename T, int RPT>
+__device__ inline void accumulate_basis(const LzArgs<T> &a, const TileRows<RPT> &tr,
+                                        const double *coef, int nk, int k1, double (&acc)[RPT]) {
+  const int kk = min(nk, k1);
+  if (kk >= 2) accumulate_slots<double, RPT>(a.K, 2, a.vs, tr, coef, 2, kk, acc);
+  accumulate_slots<T, RPT>(a.V, 0, a.vs, tr, coef, max(2, kk + 1), k1, acc);
 }
 
 // ----------------------------------------------------------------------------
@@ -201,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
-  if (!S.active || S.cycle_done) return;
+  if (!S.active || S.cycle_done || j < S.j0) return;
   if (MODE == 1 && !S.need2) return;
   const Tin *Win = step_in<T, STEP>(a, j);
   Tw *Wout = step_out<T, STEP>(a, j);
@@ -248,6 +266,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
     } else if (k <= 1) {
       const double *v = (k == 0 ? a.U0 : a.Q1) + b.row0 + lane;
       acc = full ? wave_dot_full<NSL>(v, zs, lane) : wave_dot_part(v, zs, lane, nsl);
+    } else if (k <= S.nk) {
+      const double *v = a.K + (int64_t)(k - 2) * a.vs + b.row0 + lane;
+      acc = full ? wave_dot_full<NSL>(v, zs, lane) : wave_dot_part(v, zs, lane, nsl);
     } else {
       const T *v = a.V + (int64_t)k * a.vs + b.row0 + lane;
       acc = full ? wave_dot_full<NSL>(v, zs, lane) : wave_dot_part(v, zs, lane, nsl);
@@ -276,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
-  if (!S.active || S.cycle_done) return;
+  if (!S.active || S.cycle_done || j < S.j0) return;
   if (PASS == 2 && !S.need2) return;
   const double *hg = a.h + (int64_t)b.seg * a.ps;
   for (int k = threadIdx.x; k <= j; k += kBlock) hs[k] = hg[k];
@@ -289,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
 #pragma unroll
     for (int r = 0; r < RPT; ++r) acc[r] = a.U0[tr.row[r]] * h0 + a.Q1[tr.row[r]] * h1;
   }
-  accumulate_basis<T, RPT>(a, tr, hs, 2, j, acc);
+  accumulate_basis<T, RPT>(a, tr, hs, S.nk, j, acc);
   double nn[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
@@ -326,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_ritz(LzArgs<T> a) {
   double acc[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) acc[r] = a.Q1[tr.row[r]] * ts[1];
-  accumulate_basis<T, RPT>(a, tr, ts, 2, k, acc);
+  accumulate_basis<T, RPT>(a, tr, ts, 0, k, acc);
   double p[2] = {0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
@@ -363,6 +384,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
     const double ly = sc * lap_row<double>(a.chunk_ptr, a.cols, a.Y, row, wi);
     const double rr = ly - th * y;
     if (tr.ok[r]) {
+      // the normalised Ritz vector is q_1 of a thick-restarted next cycle
+      // (an explicitly restarted one forms the same values in its step 1)
+      a.Q1[row] = y;
       p[0] += rr * rr;
       p[1] += y * ly;
       p[2] += y * y;
@@ -370,6 +394,88 @@ __global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
   }
   block_reduce_into<3>(p, red, vals, 3);
   write_partials(a, lb, vals, 3);
+}
+
+// ----------------------------------------------------------------------------
+// Thick restart: the nnext smallest Ritz vectors y_c = Q t_c.  y_1 goes to Y
+// (it is tested for convergence and, normalised, heads the next basis);
+// y_c for c >= 2 become the kept slots c of the next cycle, rewritten in
+// place, which is safe because each thread reads every basis value of a
+// row before it writes that row.  The last residual direction (output of
+// step m) is copied to the input buffer of step nnext + 1, where the next
+// cycle continues.  (Thick restart runs with FP64 vectors: with FP32
+// directions, the selective second Gram-Schmidt pass no longer keeps new
+// directions orthogonal to the kept vectors.)
+// ----------------------------------------------------------------------------
+template <typename T, int RPT, int NKB>
+__global__ __launch_bounds__(kBlock) void k_lz_ritz_thick(LzArgs<T> a) {
+  constexpr int TS = kMaxM + 4;
+  __shared__ double red[4 * 2];
+  __shared__ double vals[2];
+  __shared__ double ts[NKB][TS];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active) return;
+  const int k = S.k, nv = S.nnext, nkc = S.nk;
+  // ts[c][l]: coefficient of basis slot l (1..k) in y_{c+1}; zero elsewhere
+  const double *tg = a.tvec + (int64_t)b.seg * a.nkcap * a.ps;
+  for (int i = threadIdx.x; i < NKB * TS; i += kBlock) {
+    const int c = i / TS, l = i % TS;
+    ts[c][l] = (c < nv && l >= 1 && l <= k) ? tg[(int64_t)c * a.ps + l - 1] : 0.0;
+  }
+  __syncthreads();
+  const bool cont = (k == a.m && k >= 2 && nv >= 1);
+  const T *csrc = (k & 1) ? a.Wt1 : a.Wt0;          // output of step k >= 2
+  T *cdst = (nv & 1) ? a.Wt1 : a.Wt0;               // input of step nv + 1 >= 3
+  const bool to_wd = (nv == 1);                     // step 2 reads the FP64 vector
+  const TileRows<RPT> tr(b);
+  double p[2] = {0.0, 0.0};
+  for (int r = 0; r < RPT; ++r) {
+    const int64_t row = tr.row[r];
+    double acc[NKB];
+    const double q1 = a.Q1[row];
+#pragma unroll
+    for (int c = 0; c < NKB; ++c) acc[c] = q1 * ts[c][1];
+    // kept FP64 slots 2..nk, then type-T slots (coefficients past k are 0)
+    const int kk = min(nkc, k);
+    for (int l = 2; l <= kk; l += 4) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = a.K[(int64_t)(min(l + u, kk) - 2) * a.vs + row];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double vu = (l + u <= kk) ? v[u] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NKB; ++c) acc[c] += vu * ts[c][l + u];
+      }
+    }
+    for (int l = max(2, kk + 1); l <= k; l += 4) {
+      T v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = a.V[(int64_t)min(l + u, k) * a.vs + row];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double vu = (double)v[u];
+#pragma unroll
+        for (int c = 0; c < NKB; ++c) acc[c] += vu * ts[c][l + u];
+      }
+    }
+    if (tr.ok[r]) {
+      a.Y[row] = acc[0];
+      p[0] += a.U0[row] * acc[0];
+      p[1] += acc[0] * acc[0];
+#pragma unroll
+      for (int c = 1; c < NKB; ++c)
+        if (c < nv) a.K[(int64_t)(c - 1) * a.vs + row] = acc[c];
+      if (cont) {
+        if (to_wd) a.Wd[row] = (double)csrc[row];
+        else if (cdst != csrc) cdst[row] = csrc[row];
+      }
+    }
+  }
+  block_reduce_into<2>(p, red, vals, 2);
+  write_partials(a, lb, vals, 2);
 }
 
 // ----------------------------------------------------------------------------
@@ -391,12 +497,12 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
       break;
     case OP_PROJ0:
     case OP_UPD1:
-      if (!S.active || S.cycle_done) return;
+      if (!S.active || S.cycle_done || j < S.j0) return;
       nval = (OP == OP_PROJ0) ? j + 2 : 1;
       break;
     case OP_PROJ1:
     case OP_UPD2:
-      if (!S.active || S.cycle_done || !S.need2) return;
+      if (!S.active || S.cycle_done || j < S.j0 || !S.need2) return;
       nval = (OP == OP_PROJ1) ? j + 2 : 1;
       break;
     case OP_RITZ:
@@ -412,7 +518,14 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
   double *hs = a.h + (int64_t)s * a.ps;
   if (OP == OP_PROJ0 || OP == OP_PROJ1) {
     for (int k = threadIdx.x; k <= j; k += kBlock) hs[k] = vals[k];
-    if (threadIdx.x == 0 && OP == OP_PROJ0) a.st[s].lq2 = vals[j + 1];
+    if (threadIdx.x == 0 && OP == OP_PROJ0) {
+      // what one projection pass is expected to leave: ||L q_j||^2 minus the
+      // squares of all projections (three-term part, and the couplings to
+      // the kept Ritz vectors after a thick restart)
+      double h2 = 0.0;
+      for (int k = 0; k <= j; ++k) h2 += vals[k] * vals[k];
+      a.st[s].lq2 = vals[j + 1] - h2;
+    }
     return;
   }
   if (threadIdx.x != 0) return;
@@ -424,6 +537,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
     if (OP == OP_BEGIN) {
       W.active = 1;
       W.k = 0;
+      W.j0 = 1;
+      W.nk = 0;
+      W.nnext = 0;
       W.cycle_done = 0;
       W.need2 = 0;
       W.converged = 0;
@@ -433,9 +549,11 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
       W.cycles = 0;
       W.steps = 0;
     } else {
-      W.steps += W.k;
-      atomicAdd(&a.ctr[0], (unsigned long long)W.k);
+      const int ran = W.k - W.j0 + 1;  // steps of this cycle
+      W.steps += ran;
+      atomicAdd(&a.ctr[0], (unsigned long long)ran);
       atomicMax(&a.flags[1], W.k);
+      atomicMax(&a.flags[2], ran);
     }
     return;
   }
@@ -456,23 +574,56 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
     }
     if (stop) {
       W.active = 0;
-    } else {
-      W.restarts += 1;
-      W.k = 0;
-      W.cycle_done = 0;
-      W.need2 = 0;
-      W.tnorm = 0.0;
-      atomicAdd(&a.flags[0], 1);
+      return;
     }
+    W.restarts += 1;
+    W.cycle_done = 0;
+    W.need2 = 0;
+    const double *be = a.beta + (int64_t)s * a.ps;
+    const int kc = W.k;
+    if (a.keep > 0 && kc == a.m && W.nnext >= 1 && be[kc] > 0.0) {
+      // thick restart: the kept Ritz pairs head the next basis and the last
+      // residual direction w / beta continues it (step nk + 1)
+      const int nk = W.nnext;
+      double *al = a.alpha + (int64_t)s * a.ps;
+      double *bw = a.beta + (int64_t)s * a.ps;
+      double *ar = a.arrow + (int64_t)s * a.ps;
+      const double *tv = a.tvec + (int64_t)s * a.nkcap * a.ps;
+      const double *tl = a.tvals + (int64_t)s * a.nkcap;
+      const double bl = be[kc];
+      double tn = 0.0;
+      for (int i = 0; i < nk; ++i) {
+        al[i] = tl[i];
+        ar[i] = bl * tv[(int64_t)i * a.ps + kc - 1];
+        bw[i + 1] = 0.0;
+        tn = fmax(tn, fabs(al[i]) + fabs(ar[i]));
+      }
+      W.nk = nk;
+      W.j0 = nk + 1;
+      W.k = nk;
+      W.tnorm = tn;
+      W.c = 0.0;
+      W.s = 1.0 / bl;
+    } else {
+      // explicit restart from the Ritz vector (c, s stay the transform of Y)
+      W.nk = 0;
+      W.j0 = 1;
+      W.k = 0;
+      W.tnorm = 0.0;
+    }
+    atomicAdd(&a.flags[0], 1);
     return;
   }
   // OP_UPD1 / OP_UPD2: finish step j
   const double w2 = vals[0];
   double alpha_j;
   if (OP == OP_UPD1) {
-    const double hj = hs[j], hj1 = (j >= 2) ? hs[j - 1] : 0.0;
-    const double ref2 = W.lq2 - hj * hj - hj1 * hj1;
-    if (w2 < 0.5 * ref2) {
+    const double hj = hs[j];
+    // second Gram-Schmidt pass: on every step after a thick restart (the
+    // kept Ritz vectors are trusted to stay orthogonal to the new
+    // directions across cycles), otherwise when ||w||^2 fell below half of
+    // what one pass is expected to leave (cancellation)
+    if (a.keep > 0 || w2 < 0.5 * W.lq2) {
       W.need2 = 1;
       W.alpha_tmp = hj;
       return;
@@ -491,10 +642,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
   W.k = j;
   // the FP64 first step breaks down only at FP64 rounding level
   const double brk = (j == 1) ? 1e-12 : a.brk;
+  be[j] = beta;  // (beta_{m+1} couples the kept Ritz vectors of a thick restart)
   if (j >= a.m || beta <= brk * W.tnorm) {
     W.cycle_done = 1;
   } else {
-    be[j] = beta;
     W.c = 0.0;
     W.s = 1.0 / beta;
   }
@@ -615,6 +766,276 @@ __global__ __launch_bounds__(kWave) void k_trieig(SegState *__restrict__ st,
   }
 }
 
+// ----------------------------------------------------------------------------
+// Thick restart: the nnext smallest eigenpairs, above the spurious-mode
+// threshold, of the cycle's projected matrix
+//   [ diag(theta_1 .. theta_nk)  s                       ]
+//   [ s^T                        alpha_{nk+1}  beta ...   ]
+//   [                            beta          tridiagonal]
+// (nk = 0: plain tridiagonal).  Eigenvalues: lane c bisects the c-th one
+// with Sturm counts from the LDL^T pivots taken in the order kept rows
+// first (their pivots are theta_i - x; the next row collects
+// -sum s_i^2 / (theta_i - x)).  Eigenvectors: inverse iteration per lane
+// with the same elimination order and partial pivoting in the tridiagonal
+// part, then modified Gram-Schmidt across the lanes' vectors, which keeps
+// the vectors of close Ritz values orthonormal.
+// ----------------------------------------------------------------------------
+__device__ inline int sturm_arrow(const double *a, const double *b2, const double *s2, int nk,
+                                  int k, double x) {
+  int cnt = 0;
+  double sum = 0.0;
+  for (int i = 0; i < nk; ++i) {
+    double d = a[i] - x;
+    if (d == 0.0) d = -1e-300;
+    cnt += (d < 0.0);
+    sum += s2[i] / d;
+  }
+  double q = (a[nk] - x) - sum;
+  if (q == 0.0) q = -1e-300;
+  cnt += (q < 0.0);
+  for (int i = nk + 1; i < k; ++i) {
+    q = (a[i] - x) - b2[i] / q;
+    if (q == 0.0) q = -1e-300;
+    cnt += (q < 0.0);
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(kWave) void k_trieig_arrow(SegState *__restrict__ st,
+                                                        const double *__restrict__ alpha,
+                                                        const double *__restrict__ beta,
+                                                        const double *__restrict__ arrow,
+                                                        double *__restrict__ tvec,
+                                                        double *__restrict__ tvals, int ps,
+                                                        int nkcap, int keep, int nseg) {
+  __shared__ double ad[kMaxM], bd[kMaxM], b2[kMaxM], sv[kMaxKeep], s2[kMaxKeep];
+  // per-lane work of the inverse iteration, [row][lane]
+  __shared__ double wd[kMaxM][kMaxKeep], wu[kMaxM][kMaxKeep], wu2[kMaxM][kMaxKeep],
+      wr[kMaxM][kMaxKeep];
+  __shared__ double red[kWave];
+  const int seg = blockIdx.x;
+  if (seg >= nseg) return;
+  const SegState S = st[seg];
+  if (!S.active) return;
+  const int k = S.k, nk = S.nk;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < k; i += kWave) {
+    ad[i] = alpha[(int64_t)seg * ps + i];
+    bd[i] = (i <= nk) ? 0.0 : beta[(int64_t)seg * ps + i];  // bd[i] couples rows i-1, i
+    b2[i] = bd[i] * bd[i];
+  }
+  for (int i = lane; i < nk; i += kWave) {
+    sv[i] = arrow[(int64_t)seg * ps + i];
+    s2[i] = sv[i] * sv[i];
+  }
+  __syncthreads();
+  // Gershgorin bounds and scale
+  double lo = 1e300, hi = -1e300, scale = 0.0;
+  double ssum = 0.0;
+  for (int i = 0; i < nk; ++i) ssum += fabs(sv[i]);
+  for (int i = lane; i < k; i += kWave) {
+    double r;
+    if (i < nk) r = fabs(sv[i]);
+    else if (i == nk) r = ssum + (i + 1 < k ? fabs(bd[i + 1]) : 0.0);
+    else r = fabs(bd[i]) + (i + 1 < k ? fabs(bd[i + 1]) : 0.0);
+    lo = fmin(lo, ad[i] - r);
+    hi = fmax(hi, ad[i] + r);
+    scale = fmax(scale, fabs(ad[i]) + r);
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, kWave));
+    hi = fmax(hi, __shfl_xor(hi, off, kWave));
+    scale = fmax(scale, __shfl_xor(scale, off, kWave));
+  }
+  const double thr = 1e-10 * S.tnorm;
+  const int c0 = sturm_arrow(ad, b2, s2, nk, k, thr);
+  int nv = (keep > 0) ? min(min(keep, k - 1), k - c0) : 1;
+  nv = max(1, min(nv, kMaxKeep));
+  const double tiny = fmax(scale, 1e-300) * 2.220446049250313e-16;
+  double th = 0.0;
+  if (lane < nv) {
+    const int target = min(c0 + 1 + lane, k);
+    double l0 = fmax(lo, thr), h0 = hi + 1e-12 * fabs(hi) + 1e-300;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (l0 + h0);
+      if (!(mid > l0 && mid < h0)) break;
+      if (sturm_arrow(ad, b2, s2, nk, k, mid) >= target) h0 = mid;
+      else l0 = mid;
+    }
+    th = 0.5 * (l0 + h0);
+    // distinct start vectors per lane (a fixed hash of row and lane), so
+    // that close eigenvalues do not start from the same vector
+    for (int i = 0; i < k; ++i) {
+      uint64_t z = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull + (uint64_t)(lane + 1) * 0xD1B54A32D192ED03ull;
+      z = (z ^ (z >> 31)) * 0xBF58476D1CE4E5B9ull;
+      z ^= z >> 29;
+      wr[i][lane] = 1.0 + 0.5 * ((double)(z >> 11) * 0x1.0p-53);
+    }
+  }
+  __syncthreads();
+  // inverse subspace iteration: every lane one shifted solve per sweep,
+  // then modified Gram-Schmidt across the lanes' vectors
+  for (int it = 0; it < 4; ++it) {
+    if (lane < nv) {
+      // kept rows eliminated into row nk
+      double dn = ad[nk] - th, rn = wr[nk][lane];
+      for (int i = 0; i < nk; ++i) {
+        double dk = ad[i] - th;
+        if (fabs(dk) < tiny) dk = (dk < 0.0) ? -tiny : tiny;
+        dn -= s2[i] / dk;
+        rn -= sv[i] * wr[i][lane] / dk;
+      }
+      // tridiagonal rows nk..k-1 with partial pivoting (bands d, u, u2)
+      for (int i = nk; i < k; ++i) {
+        wd[i][lane] = (i == nk) ? dn : ad[i] - th;
+        wu[i][lane] = (i + 1 < k) ? bd[i + 1] : 0.0;
+        wu2[i][lane] = 0.0;
+      }
+      wr[nk][lane] = rn;
+      for (int i = nk; i + 1 < k; ++i) {
+        double li = bd[i + 1];  // sub-diagonal entry of row i + 1
+        if (fabs(li) > fabs(wd[i][lane])) {
+          double t;
+          t = wd[i][lane]; wd[i][lane] = li; li = t;
+          t = wu[i][lane]; wu[i][lane] = wd[i + 1][lane]; wd[i + 1][lane] = t;
+          t = wu2[i][lane]; wu2[i][lane] = wu[i + 1][lane]; wu[i + 1][lane] = t;
+          t = wr[i][lane]; wr[i][lane] = wr[i + 1][lane]; wr[i + 1][lane] = t;
+        }
+        if (wd[i][lane] == 0.0) wd[i][lane] = tiny;
+        const double f = li / wd[i][lane];
+        wd[i + 1][lane] -= f * wu[i][lane];
+        wu[i + 1][lane] -= f * wu2[i][lane];
+        wr[i + 1][lane] -= f * wr[i][lane];
+      }
+      if (wd[k - 1][lane] == 0.0) wd[k - 1][lane] = tiny;
+      for (int i = k - 1; i >= nk; --i) {
+        double v = wr[i][lane];
+        if (i + 1 < k) v -= wu[i][lane] * wr[i + 1][lane];
+        if (i + 2 < k) v -= wu2[i][lane] * wr[i + 2][lane];
+        wr[i][lane] = v / wd[i][lane];
+      }
+      const double xn = wr[nk][lane];
+      for (int i = 0; i < nk; ++i) {
+        double dk = ad[i] - th;
+        if (fabs(dk) < tiny) dk = (dk < 0.0) ? -tiny : tiny;
+        wr[i][lane] = (wr[i][lane] - sv[i] * xn) / dk;
+      }
+      double big = 0.0;
+      for (int i = 0; i < k; ++i) big = fmax(big, fabs(wr[i][lane]));
+      for (int i = 0; i < k; ++i) wr[i][lane] /= big;
+    }
+    __syncthreads();
+    for (int c = 0; c < nv; ++c) {
+      for (int c2 = 0; c2 < c; ++c2) {
+        double d = 0.0;
+        for (int i = lane; i < k; i += kWave) d += wr[i][c] * wr[i][c2];
+        d = wave_sum(d);
+        for (int i = lane; i < k; i += kWave) wr[i][c] -= d * wr[i][c2];
+        __syncthreads();
+      }
+      double nn = 0.0;
+      for (int i = lane; i < k; i += kWave) nn += wr[i][c] * wr[i][c];
+      nn = wave_sum(nn);
+      const double inv = 1.0 / sqrt(fmax(nn, 1e-300));
+      for (int i = lane; i < k; i += kWave) wr[i][c] *= inv;
+      __syncthreads();
+    }
+  }
+  // Rayleigh-Ritz in the span of the vectors: G = X^T H X (H applied in
+  // its arrow form), diagonalised by cyclic Jacobi; the rotated vectors
+  // and G's eigenvalues are the Ritz pairs handed on, consistent with each
+  // other whatever the spacing of the eigenvalues
+  if (lane < nv) {
+    double xs = 0.0;  // sum_i s_i x_i over the kept rows
+    for (int i = 0; i < nk; ++i) xs += sv[i] * wr[i][lane];
+    const double xn = wr[nk][lane];
+    for (int i = 0; i < k; ++i) {
+      double hx;
+      if (i < nk) hx = ad[i] * wr[i][lane] + sv[i] * xn;
+      else {
+        hx = ad[i] * wr[i][lane];
+        if (i == nk) hx += xs;
+        else hx += bd[i] * wr[i - 1][lane];
+        if (i + 1 < k) hx += bd[i + 1] * wr[i + 1][lane];
+      }
+      wd[i][lane] = hx;
+    }
+  }
+  __syncthreads();
+  __shared__ double G[kMaxKeep][kMaxKeep], U[kMaxKeep][kMaxKeep], gev[kMaxKeep];
+  if (lane < nv)
+    for (int c2 = 0; c2 < nv; ++c2) {
+      double g = 0.0;
+      for (int i = 0; i < k; ++i) g += wr[i][lane] * wd[i][c2];
+      G[lane][c2] = g;
+    }
+  __syncthreads();
+  if (lane == 0) {
+    for (int a1 = 0; a1 < nv; ++a1)
+      for (int b1 = 0; b1 < nv; ++b1) U[a1][b1] = (a1 == b1) ? 1.0 : 0.0;
+    for (int a1 = 0; a1 < nv; ++a1)
+      for (int b1 = a1 + 1; b1 < nv; ++b1) G[a1][b1] = G[b1][a1] = 0.5 * (G[a1][b1] + G[b1][a1]);
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      double off = 0.0, dia = 0.0;
+      for (int a1 = 0; a1 < nv; ++a1) {
+        dia += G[a1][a1] * G[a1][a1];
+        for (int b1 = a1 + 1; b1 < nv; ++b1) off += G[a1][b1] * G[a1][b1];
+      }
+      if (off <= 1e-32 * dia) break;
+      for (int p1 = 0; p1 < nv; ++p1)
+        for (int q1 = p1 + 1; q1 < nv; ++q1) {
+          const double gpq = G[p1][q1];
+          if (gpq == 0.0) continue;
+          const double tau = (G[q1][q1] - G[p1][p1]) / (2.0 * gpq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+          for (int r = 0; r < nv; ++r) {
+            const double grp = G[r][p1], grq = G[r][q1];
+            G[r][p1] = cs * grp - sn * grq;
+            G[r][q1] = sn * grp + cs * grq;
+          }
+          for (int r = 0; r < nv; ++r) {
+            const double gpr = G[p1][r], gqr = G[q1][r];
+            G[p1][r] = cs * gpr - sn * gqr;
+            G[q1][r] = sn * gpr + cs * gqr;
+          }
+          for (int r = 0; r < nv; ++r) {
+            const double urp = U[r][p1], urq = U[r][q1];
+            U[r][p1] = cs * urp - sn * urq;
+            U[r][q1] = sn * urp + cs * urq;
+          }
+        }
+    }
+    // ascending order of the Ritz values (selection sort of the columns)
+    for (int a1 = 0; a1 < nv; ++a1) gev[a1] = G[a1][a1];
+    for (int a1 = 0; a1 < nv; ++a1) {
+      int mn = a1;
+      for (int b1 = a1 + 1; b1 < nv; ++b1)
+        if (gev[b1] < gev[mn]) mn = b1;
+      if (mn != a1) {
+        double t = gev[a1]; gev[a1] = gev[mn]; gev[mn] = t;
+        for (int r = 0; r < nv; ++r) {
+          t = U[r][a1]; U[r][a1] = U[r][mn]; U[r][mn] = t;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double *tv = tvec + (int64_t)seg * nkcap * ps;
+  for (int i = lane; i < k; i += kWave)
+    for (int c = 0; c < nv; ++c) {
+      double v = 0.0;
+      for (int c2 = 0; c2 < nv; ++c2) v += wr[i][c2] * U[c2][c];
+      tv[(int64_t)c * ps + i] = v;
+    }
+  if (lane < nv) tvals[(int64_t)seg * nkcap + lane] = gev[lane];
+  if (lane == 0) {
+    st[seg].theta = gev[0];
+    st[seg].nnext = nv;
+  }
+  (void)red;
+}
+
 // final vector: y = (Y - c u0) s on the component, 0 elsewhere
 template <typename T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_lz_output(LzArgs<T> a, double *__restrict__ y64) {
@@ -635,6 +1056,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_output(LzArgs<T> a, double *__res
 __global__ void k_flags_reset(int32_t *flags) {
   flags[0] = 0;
   flags[1] = 0;
+  flags[2] = 0;
 }
 
 template <typename T, int RPT>
@@ -668,8 +1090,16 @@ struct LzLaunch {
       else if (j == 2) step<2>(a, nblk, ngrp, j, s, nullptr);
       else step<3>(a, nblk, ngrp, j, s, ev ? ev + 2 * j : nullptr);
     }
-    k_trieig<<<nseg, kWave, 0, s>>>(a.st, a.alpha, a.beta, a.tvec, a.ps, nseg);
-    k_lz_ritz<T, RPT><<<nblk, kBlock, 0, s>>>(a);
+    if (a.keep > 0) {
+      k_trieig_arrow<<<nseg, kWave, 0, s>>>(a.st, a.alpha, a.beta, a.arrow, a.tvec, a.tvals,
+                                            a.ps, a.nkcap, a.keep, nseg);
+      if (a.keep <= 4) k_lz_ritz_thick<T, RPT, 4><<<nblk, kBlock, 0, s>>>(a);
+      else if (a.keep <= 8) k_lz_ritz_thick<T, RPT, 8><<<nblk, kBlock, 0, s>>>(a);
+      else k_lz_ritz_thick<T, RPT, 16><<<nblk, kBlock, 0, s>>>(a);
+    } else {
+      k_trieig<<<nseg, kWave, 0, s>>>(a.st, a.alpha, a.beta, a.tvec, a.ps, nseg);
+      k_lz_ritz<T, RPT><<<nblk, kBlock, 0, s>>>(a);
+    }
     k_lz_reduce<T, OP_RITZ><<<ngrp, kBlock, 0, s>>>(a, 0);
     k_lz_residual<T, RPT><<<nblk, kBlock, 0, s>>>(a);
     k_lz_reduce<T, OP_RESID><<<ngrp, kBlock, 0, s>>>(a, 0);
@@ -691,15 +1121,18 @@ void dispatch_rpt(int rpt, F &&f) {
 
 }  // namespace
 
-void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, Ctx &ctx) {
+void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx &ctx) {
   S.m = m;
   S.pstride = m + 4;
+  S.nkcap = std::max(1, keep);
   const size_t ns = std::max(nseg, 1), nb = std::max(nblk, 1), ng = std::max(ngrp, 1);
   if (!S.st.p || S.st.n < ns) S.st.alloc(ctx, ns);
   S.alpha.alloc(ctx, ns * S.pstride);
   S.beta.alloc(ctx, ns * S.pstride);
   S.h.alloc(ctx, ns * S.pstride);
-  S.tvec.alloc(ctx, ns * S.pstride);
+  S.tvec.alloc(ctx, ns * S.nkcap * S.pstride);
+  S.tvals.alloc(ctx, ns * S.nkcap);
+  S.arrow.alloc(ctx, ns * S.pstride);
   S.part.alloc(ctx, nb * S.pstride);
   S.gpart.alloc(ctx, ng * S.pstride);
   S.gcnt.alloc(ctx, ng);
@@ -731,6 +1164,9 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
   a.beta = S.beta.get();
   a.h = S.h.get();
   a.tvec = S.tvec.get();
+  a.tvals = S.tvals.get();
+  a.arrow = S.arrow.get();
+  a.nkcap = S.nkcap;
   a.part = S.part.get();
   a.gpart = S.gpart.get();
   a.gcnt = S.gcnt.get();
@@ -751,10 +1187,18 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
   a.vs = L.nrows;
   a.Wt0 = wt + (int64_t)(p.m + 1) * L.nrows;
   a.Wt1 = a.Wt0 + L.nrows;
+  // kept Ritz vectors: the basis slots themselves (thick restart runs with
+  // FP64 directions only)
+  a.K = sizeof(T) == 8 ? (double *)(a.V + 2 * L.nrows) : nullptr;
   a.m = p.m;
   a.tol = p.tol;
   a.max_restarts = p.max_restarts;
   a.brk = sizeof(T) == 4 ? 1e-5 : 1e-12;
+  a.keep = p.keep;
+  if (p.keep < 0 || p.keep > kMaxKeep || (p.keep > 0 && p.keep >= p.m))
+    fail(RSB_EINVAL, "lanczos_keep must be 0 or in [1, min(16, lanczos_m - 1)]");
+  if (p.keep > 0 && sizeof(T) != 8) fail(RSB_EINVAL, "thick restart needs FP64 vectors");
+  if (S.nkcap < std::max(1, p.keep)) fail(RSB_EINTERNAL, "Ritz buffers smaller than lanczos_keep");
   a.flags = S.n_active.get();
   a.ctr = (unsigned long long *)S.counters.get();
   a.seed = p.seed;
@@ -794,6 +1238,7 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
     std::vector<SegDev> hseg;
     std::vector<char> was_active;
     std::vector<int64_t> steps0;
+    std::vector<int32_t> j00;
     auto read_state = [&]() {
       hst.resize(nseg);
       RSB_HIP(hipMemcpyAsync(hst.data(), a.st, nseg * sizeof(SegState), hipMemcpyDeviceToHost,
@@ -806,14 +1251,16 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
                              ctx.stream));
       was_active.resize(nseg);
       steps0.resize(nseg);
+      j00.resize(nseg);
     }
-    int32_t flags[2] = {0, 0};
+    int32_t flags[3] = {0, 0, 0};
     for (int cyc = 0; cyc <= p.max_restarts; ++cyc) {
       if (prof) {
         read_state();
         for (int i = 0; i < nseg; ++i) {
           was_active[i] = hst[i].active != 0;
           steps0[i] = hst[i].steps;
+          j00[i] = hst[i].j0;
         }
       }
       if (res.exec) {
@@ -824,7 +1271,7 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
       }
       RSB_HIP(hipMemcpyAsync(flags, a.flags, sizeof(flags), hipMemcpyDeviceToHost, ctx.stream));
       RSB_HIP(hipStreamSynchronize(ctx.stream));
-      level_steps += flags[1];
+      level_steps += flags[2];
       if (ctx.verbose >= 3) {
         std::vector<SegState> hv(nseg);
         RSB_HIP(hipMemcpy(hv.data(), a.st, nseg * sizeof(SegState), hipMemcpyDeviceToHost));
@@ -835,7 +1282,8 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
       }
       if (prof) {
         // launches of steps 3..flags[1] were timed; segment i took part in
-        // those of steps 3..k_i (k_i: the steps it added in this cycle)
+        // those of steps j0_i..k_i (k_i - j0_i + 1: the steps it added in
+        // this cycle); launches that no segment took part in count 0 bytes
         read_state();
         const double st = (double)sizeof(T);
         const double nnz_per_row = (double)p.nnz / (double)std::max<int64_t>(L.nrows, 1);
@@ -844,7 +1292,8 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
           RSB_HIP(hipEventElapsedTime(&ms, res.ev[2 * j], res.ev[2 * j + 1]));
           double rows = 0.0;
           for (int i = 0; i < nseg; ++i)
-            if (was_active[i] && hst[i].steps - steps0[i] >= j) rows += (double)hseg[i].npad;
+            if (was_active[i] && j >= j00[i] && hst[i].steps - steps0[i] + j00[i] - 1 >= j)
+              rows += (double)hseg[i].npad;
           p.prof->ms += ms;
           p.prof->launches += 1;
           p.prof->bytes += 4.0 * (rows + 1) + 4.0 * nnz_per_row * rows +
@@ -870,7 +1319,7 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
   if (L.nseg == 0 || L.nblk == 0 || m < 4 || m > kMaxM) return 0.0;
   const int j = m / 2 >= 3 ? m / 2 : 3;
   SolveDev S;
-  solve_alloc(S, L.nseg, L.nblk, L.ngrp, m, ctx);
+  solve_alloc(S, L.nseg, L.nblk, L.ngrp, m, 0, ctx);
   std::vector<SegState> hs(L.nseg);
   for (auto &x : hs) {
     std::memset(&x, 0, sizeof(x));
@@ -892,6 +1341,9 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
   a.beta = S.beta.get();
   a.h = S.h.get();
   a.tvec = S.tvec.get();
+  a.tvals = S.tvals.get();
+  a.arrow = S.arrow.get();
+  a.nkcap = S.nkcap;
   a.part = S.part.get();
   a.gpart = S.gpart.get();
   a.gcnt = S.gcnt.get();

@@ -123,6 +123,51 @@ def test_fiedler_mixed(orc, name):
     assert stats["residual"] <= 1e-8 * lam
 
 
+@pytest.mark.parametrize("m,keep", [(12, 4), (30, 10)])
+@pytest.mark.parametrize("name", ["box5x4x3", "holes", "renum", "clustered"])
+def test_fiedler_thick_restart(orc, name, m, keep):
+    ids = MESHES[name]
+    print(f"thick restart {name} m={m} keep={keep}", flush=True)
+    kw = dict(lanczos_m=m, lanczos_keep=keep, max_restarts=400)
+    st, lam, y, stats = rsb.fiedler(ids, tol=1e-8, **kw)
+    ost, olam, oy, _ = orc.fiedler(ids, tol=1e-10, **kw)
+    assert st == 0 and ost == 0
+    assert abs(lam - olam) <= 1e-8 * olam
+    assert stats["residual"] <= 1.01e-8 * lam
+    assert abs(y.sum()) < 1e-9 * np.sqrt(len(y))
+
+
+NEAR_DEGENERATE = mg.uniform_holes(mg.box_hex(16, 16, 8), 0.05, 3).ids
+
+
+def test_thick_restart_keep_one_is_explicit_restart():
+    kw = dict(lanczos_m=8, tol=1e-15, max_restarts=4)
+    _, lam0, y0, _ = rsb.fiedler(NEAR_DEGENERATE, lanczos_keep=0, **kw)
+    _, lam1, y1, _ = rsb.fiedler(NEAR_DEGENERATE, lanczos_keep=1, **kw)
+    assert abs(lam0 - lam1) <= 1e-11 * lam0
+    assert abs(abs(float(y0 @ y1)) - 1.0) < 1e-8
+
+
+def test_thick_restart_cycles_match_oracle(orc):
+    # a fixed number of cycles, so the intermediate iterates are compared
+    kw = dict(lanczos_m=12, lanczos_keep=4, tol=1e-15, max_restarts=6)
+    st, lam, y, stats = rsb.fiedler(NEAR_DEGENERATE, **kw)
+    ost, olam, oy, oinfo = orc.fiedler(NEAR_DEGENERATE, **kw)
+    assert st == ost == 1
+    assert stats["cycles"] == oinfo["cycles"] == 7
+    assert abs(lam - olam) <= 1e-10 * olam
+
+
+def test_thick_restart_does_not_stagnate(orc):
+    kw = dict(lanczos_m=12, tol=1e-8, max_restarts=100)
+    st0, lam0, _, s0 = rsb.fiedler(NEAR_DEGENERATE, lanczos_keep=0, **kw)
+    st4, lam4, _, s4 = rsb.fiedler(NEAR_DEGENERATE, lanczos_keep=4, **kw)
+    ost, olam, _, _ = orc.fiedler(NEAR_DEGENERATE, lanczos_keep=4, **kw)
+    assert st0 == 1 and s0["residual"] > 1e-6 * lam4
+    assert st4 == 0 and ost == 0 and s4["cycles"] < 40
+    assert abs(lam4 - olam) <= 1e-8 * olam
+
+
 @pytest.mark.parametrize("name", ["box5x4x3", "holes", "quad"])
 def test_fiedler_inverse_cg(orc, name):
     ids = MESHES[name]
@@ -134,10 +179,10 @@ def test_fiedler_inverse_cg(orc, name):
     assert abs(abs(float(y @ ly)) - 1) < 1e-6
 
 
-@pytest.mark.parametrize("method", ["lanczos", "inverse_cg"])
-def test_unbatched_equals_batched(method):
+@pytest.mark.parametrize("method,keep", [("lanczos", 0), ("lanczos", 6), ("inverse_cg", 0)])
+def test_unbatched_equals_batched(method, keep):
     ids = MESHES["holes"]
-    kw = dict(method=method, tol=1e-8, inv_max_outer=300)
+    kw = dict(method=method, tol=1e-8, inv_max_outer=300, lanczos_m=40, lanczos_keep=keep)
     st1, p1, s1 = rsb.partition(ids, 12, **kw)
     st2, p2, s2 = rsb.partition(ids, 12, batched=0, **kw)
     assert st1 == st2
@@ -156,12 +201,13 @@ def test_profile_counts():
                                               ((48, 40, 36), "weighted", 8),
                                               ((24, 20, 18), "weighted", 4),
                                               ((30, 14, 9), "face", 6)])
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_partition_identical_on_boxes(orc, dims, graph, nparts, precision):
+@pytest.mark.parametrize("precision,keep", [("fp64", 0), ("mixed", 0), ("fp64", 10)])
+def test_partition_identical_on_boxes(orc, dims, graph, nparts, precision, keep):
     mesh = mg.box_hex(*dims)
-    print(f"partition {dims} {graph} {nparts} {precision}", flush=True)
-    st, part, stats = rsb.partition(mesh.ids, nparts, graph=graph, precision=precision, tol=1e-8)
-    ost, opart, _ = orc.partition(mesh.ids, nparts, graph=graph, tol=1e-8)
+    print(f"partition {dims} {graph} {nparts} {precision} keep={keep}", flush=True)
+    st, part, stats = rsb.partition(mesh.ids, nparts, graph=graph, precision=precision, tol=1e-8,
+                                    lanczos_keep=keep)
+    ost, opart, _ = orc.partition(mesh.ids, nparts, graph=graph, tol=1e-8, lanczos_keep=keep)
     assert st == ost == 0
     assert np.array_equal(part, opart)
     met = graph_metrics(orc, mesh.ids, part, nparts, graph)

@@ -55,7 +55,8 @@ def test_bad_options_rejected_before_any_device_call():
     bad = []
     for field, value in (("struct_size", 4), ("graph", 7), ("lanczos_m", 0), ("lanczos_m", 251),
                          ("tol", 0.0), ("cg_full_projection", 1), ("precision", 5),
-                         ("rows_per_thread", 3), ("rows_per_thread", 16), ("autotune", 3)):
+                         ("rows_per_thread", 3), ("rows_per_thread", 16), ("autotune", 3),
+                         ("lanczos_keep", -1), ("lanczos_keep", 17), ("lanczos_keep", 100)):
         oo = rsb.Opts.from_buffer_copy(o)
         setattr(oo, field, value)
         part = np.zeros(2, dtype=np.int32)
@@ -64,6 +65,14 @@ def test_bad_options_rejected_before_any_device_call():
         bad.append(code)
         assert rsb.lib().rsb_last_error()
     assert all(c == rsb.EINVAL for c in bad), bad
+    # thick restart with FP32 directions is refused
+    oo = rsb.Opts.from_buffer_copy(o)
+    oo.lanczos_keep = 10
+    oo.precision = 1
+    part = np.zeros(2, dtype=np.int32)
+    assert rsb.lib().rsb_partition(2, 4, ids.ctypes.data_as(C.c_void_p), 2, C.byref(oo),
+                                   part.ctypes.data_as(C.c_void_p), None) == rsb.EINVAL
+    assert b"FP64" in rsb.lib().rsb_last_error()
 
 
 def test_bad_arguments_rejected():
