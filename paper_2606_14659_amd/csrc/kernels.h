@@ -163,6 +163,7 @@ struct SolveDev {
   DevBuf<double> tvec;                   // [nseg][nkcap][pstride] Ritz coefficients
   DevBuf<double> tvals;                  // [nseg][nkcap] Ritz values
   DevBuf<double> arrow;                  // [nseg][pstride] couplings of kept Ritz vectors
+  DevBuf<double> cdel;                   // [nseg][pstride] delayed second-pass coefficients
   int nkcap = 1;                         // Ritz vectors formed per cycle (1, or the kept count)
   DevBuf<double> part, gpart;            // [nblk][pstride], [ngrp][pstride]
   DevBuf<unsigned> gcnt, scnt;           // counters (zero between launches)

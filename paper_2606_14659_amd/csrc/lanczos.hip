@@ -49,6 +49,7 @@ struct LzArgs {
   double *alpha, *beta, *h;         // [nseg][ps]
   double *tvec, *tvals;             // [nseg][nkcap][ps], [nseg][nkcap]
   double *arrow;                    // [nseg][ps]
+  double *cdel;                     // [nseg][ps] delayed second-pass coefficients
   int nkcap;
   int keep;                         // 0: explicit restart; k > 0: thick restart
   double *part, *gpart;             // [nblk][ps], [ngrp][ps]
@@ -131,6 +132,48 @@ __device__ inline double wave_dot_part(const P *__restrict__ v, const double *zs
   return acc;
 }
 
+// Two dot products of v_k with the staged vectors z and q from one read of
+// v_k (thick restart: the projection of L q_j and, for the delayed second
+// Gram-Schmidt pass, of q_j itself).
+template <int NSL, typename P>
+__device__ inline void wave_dot2_full(const P *__restrict__ v, const double *zs, const double *qs,
+                                      int lane, double &az, double &aq) {
+  double x[NSL];
+#pragma unroll
+  for (int t = 0; t < NSL; ++t) x[t] = (double)v[t * kWave];
+  az = 0.0;
+  aq = 0.0;
+#pragma unroll
+  for (int t = 0; t < NSL; ++t) {
+    az += x[t] * zs[t * kWave + lane];
+    aq += x[t] * qs[t * kWave + lane];
+  }
+}
+
+template <typename P>
+__device__ inline void wave_dot2_part(const P *__restrict__ v, const double *zs, const double *qs,
+                                      int lane, int nsl, double &az, double &aq) {
+  az = 0.0;
+  aq = 0.0;
+  for (int t = 0; t < nsl; ++t) {
+    const double x = (double)v[t * kWave];
+    az += x * zs[t * kWave + lane];
+    aq += x * qs[t * kWave + lane];
+  }
+}
+
+template <int NSL, typename P>
+__device__ inline void proj_dot(bool dual, bool full, const P *__restrict__ v, const double *zs,
+                                const double *qs, int lane, int nsl, double &az, double &aq) {
+  if (dual) {
+    if (full) wave_dot2_full<NSL>(v, zs, qs, lane, az, aq);
+    else wave_dot2_part(v, zs, qs, lane, nsl, az, aq);
+  } else {
+    az = full ? wave_dot_full<NSL>(v, zs, lane) : wave_dot_part(v, zs, lane, nsl);
+    aq = 0.0;
+  }
+}
+
 // acc[r] += sum_{k = k0..k1} c_k B[k - kb][row_r] (vectors of stride vs), 4
 // vectors per round so that 4 * RPT loads are in flight per thread.
 template <typename P, int RPT>
@@ -158,6 +201,40 @@ __device__ inline void accumulate_slots(const P *__restrict__ B, int kb, int64_t
   }
 }
 
+// Two combinations from one read: acc[r] += sum a_k B.., acd[r] += sum d_k B..
+template <typename P, int RPT>
+__device__ inline void accumulate_slots2(const P *__restrict__ B, int kb, int64_t vs,
+                                         const TileRows<RPT> &tr, const double *ca,
+                                         const double *cd, int k0, int k1, double (&acc)[RPT],
+                                         double (&acd)[RPT]) {
+  int k = k0;
+  for (; k + 4 <= k1 + 1; k += 4) {
+    P v[4][RPT];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) v[kk][r] = B[(int64_t)(k + kk - kb) * vs + tr.row[r]];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const double a = ca[k + kk], d = cd[k + kk];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        acc[r] += (double)v[kk][r] * a;
+        acd[r] += (double)v[kk][r] * d;
+      }
+    }
+  }
+  for (; k <= k1; ++k) {
+    const double a = ca[k], d = cd[k];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const double x = (double)B[(int64_t)(k - kb) * vs + tr.row[r]];
+      acc[r] += x * a;
+      acd[r] += x * d;
+    }
+  }
+}
+
 // acc[r] += sum_{k = 2..k1} c_k b_k[row_r] over the basis slots >= 2: the
 // FP64 kept Ritz vectors (2..nk) and the type-T Lanczos vectors after them.
 template <typename T, int RPT>
@@ -166,6 +243,15 @@ __device__ inline void accumulate_basis(const LzArgs<T> &a, const TileRows<RPT> 
   const int kk = min(nk, k1);
   if (kk >= 2) accumulate_slots<double, RPT>(a.K, 2, a.vs, tr, coef, 2, kk, acc);
   accumulate_slots<T, RPT>(a.V, 0, a.vs, tr, coef, max(2, kk + 1), k1, acc);
+}
+
+template <typename T, int RPT>
+__device__ inline void accumulate_basis2(const LzArgs<T> &a, const TileRows<RPT> &tr,
+                                         const double *ca, const double *cd, int nk, int k1,
+                                         double (&acc)[RPT], double (&acd)[RPT]) {
+  const int kk = min(nk, k1);
+  if (kk >= 2) accumulate_slots2<double, RPT>(a.K, 2, a.vs, tr, ca, cd, 2, kk, acc, acd);
+  accumulate_slots2<T, RPT>(a.V, 0, a.vs, tr, ca, cd, max(2, kk + 1), k1, acc, acd);
 }
 
 // ----------------------------------------------------------------------------
@@ -214,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
   constexpr int NSL = TILE / kWave;
   __shared__ double zs[TILE];
   __shared__ double qs[MODE == 0 ? TILE : 1];
-  __shared__ double vals[kMaxM + 8];
+  __shared__ double vals[2 * kMaxM + 8];
   __shared__ double red[kBlock / kWave];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
@@ -256,25 +342,35 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
   zz = wave_sum(zz);
   if (lane == 0) red[wave] = zz;
   __syncthreads();
-  // h_k = v_k^T z, k = 0..j, one wavefront per k
+  // h_k = v_k^T z, k = 0..j, one wavefront per k.  With thick restart the
+  // same loads also give c_k = v_k^T q_j for k < j: the second Gram-Schmidt
+  // pass of q_j, applied by the update launch of this step (delayed
+  // reorthogonalisation, so both passes cost one read of the basis)
   const bool full = (b.nrows == TILE);
   const int nsl = b.nrows / kWave;
+  const bool delayed = (MODE == 0) && a.keep > 0;
   for (int k = wave; k <= j; k += kBlock / kWave) {
-    double acc;
+    double acc, accq;
+    const bool dual = delayed && k < j;
     if (MODE == 0 && k == j) {
       acc = full ? wave_dot_full<NSL>(qs + lane, zs, lane) : wave_dot_part(qs + lane, zs, lane, nsl);
+      accq = 0.0;
     } else if (k <= 1) {
       const double *v = (k == 0 ? a.U0 : a.Q1) + b.row0 + lane;
-      acc = full ? wave_dot_full<NSL>(v, zs, lane) : wave_dot_part(v, zs, lane, nsl);
+      proj_dot<NSL>(dual, full, v, zs, qs, lane, nsl, acc, accq);
     } else if (k <= S.nk) {
       const double *v = a.K + (int64_t)(k - 2) * a.vs + b.row0 + lane;
-      acc = full ? wave_dot_full<NSL>(v, zs, lane) : wave_dot_part(v, zs, lane, nsl);
+      proj_dot<NSL>(dual, full, v, zs, qs, lane, nsl, acc, accq);
     } else {
       const T *v = a.V + (int64_t)k * a.vs + b.row0 + lane;
-      acc = full ? wave_dot_full<NSL>(v, zs, lane) : wave_dot_part(v, zs, lane, nsl);
+      proj_dot<NSL>(dual, full, v, zs, qs, lane, nsl, acc, accq);
     }
     acc = wave_sum(acc);
-    if (lane == 0) vals[k] = acc;
+    if (dual) accq = wave_sum(accq);
+    if (lane == 0) {
+      vals[k] = acc;
+      if (dual) vals[j + 2 + k] = accq;
+    }
   }
   if (threadIdx.x == 0) {
     double s = 0.0;
@@ -282,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
     vals[j + 1] = s;
   }
   __syncthreads();
-  write_partials(a, lb, vals, j + 2);
+  write_partials(a, lb, vals, delayed ? 2 * j + 2 : j + 2);
 }
 
 // ----------------------------------------------------------------------------
@@ -294,23 +390,49 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
   __shared__ double red[4];
   __shared__ double vals[2];
   __shared__ double hs[kMaxM + 2];
+  __shared__ double cs[PASS == 1 ? kMaxM + 2 : 1];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
   if (!S.active || S.cycle_done || j < S.j0) return;
   if (PASS == 2 && !S.need2) return;
+  const bool delayed = (PASS == 1) && a.keep > 0;
   const double *hg = a.h + (int64_t)b.seg * a.ps;
-  for (int k = threadIdx.x; k <= j; k += kBlock) hs[k] = hg[k];
+  const double *cg = a.cdel + (int64_t)b.seg * a.ps;
+  for (int k = threadIdx.x; k <= j; k += kBlock) {
+    hs[k] = hg[k];
+    if (delayed) cs[k] = (k < j) ? cg[k] : 0.0;
+  }
   __syncthreads();
   Tw *Wout = step_out<T, STEP>(a, j);
   const TileRows<RPT> tr(b);
   double acc[RPT];
-  {
+  if (!delayed) {
     const double h0 = hs[0], h1 = hs[1];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) acc[r] = a.U0[tr.row[r]] * h0 + a.Q1[tr.row[r]] * h1;
+    accumulate_basis<T, RPT>(a, tr, hs, S.nk, j, acc);
+  } else {
+    // w = L q_j - [u0, Q] h as usual, and in the same pass over the basis
+    // the second Gram-Schmidt pass of q_j: q_j -= [u0, q_1..q_{j-1}] c
+    double acd[RPT];
+    const double h0 = hs[0], h1 = hs[1], c0 = cs[0], c1 = cs[1];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const double u = a.U0[tr.row[r]], q1 = a.Q1[tr.row[r]];
+      acc[r] = u * h0 + q1 * h1;
+      acd[r] = u * c0 + q1 * c1;
+    }
+    accumulate_basis2<T, RPT>(a, tr, hs, cs, S.nk, j, acc, acd);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      if (!tr.ok[r]) continue;
+      const int64_t row = tr.row[r];
+      // (steps run from j0 = nk + 1, so q_j is never a kept slot)
+      if (j == 1) a.Q1[row] -= acd[r];
+      else a.V[(int64_t)j * a.vs + row] = (T)((double)a.V[(int64_t)j * a.vs + row] - acd[r]);
+    }
   }
-  accumulate_basis<T, RPT>(a, tr, hs, S.nk, j, acc);
   double nn[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
@@ -485,7 +607,7 @@ enum LzOp { OP_BEGIN, OP_PROJ0, OP_PROJ1, OP_UPD1, OP_UPD2, OP_RITZ, OP_RESID };
 
 template <typename T, int OP>
 __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
-  __shared__ double vals[kMaxM + 8];
+  __shared__ double vals[2 * kMaxM + 8];
   const int g = blockIdx.x;
   const int s = a.grp[g].seg;
   const SegState S = a.st[s];
@@ -498,7 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
     case OP_PROJ0:
     case OP_UPD1:
       if (!S.active || S.cycle_done || j < S.j0) return;
-      nval = (OP == OP_PROJ0) ? j + 2 : 1;
+      nval = (OP == OP_PROJ0) ? (a.keep > 0 ? 2 * j + 2 : j + 2) : 1;
       break;
     case OP_PROJ1:
     case OP_UPD2:
@@ -517,7 +639,29 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
   if (!group_reduce(a, g, vals, nval)) return;
   double *hs = a.h + (int64_t)s * a.ps;
   if (OP == OP_PROJ0 || OP == OP_PROJ1) {
-    for (int k = threadIdx.x; k <= j; k += kBlock) hs[k] = vals[k];
+    if (OP == OP_PROJ0 && a.keep > 0) {
+      // delayed second pass: q_j = q~_j - sum_{k<j} c_k b_k.  The step must
+      // project L q~_j against the corrected q_j, whose coefficient is
+      // q_j^T L q~_j = h~_j - sum c_k h_k; expressed on the stored q~_j the
+      // other coefficients become h_k - h_j c_k (k < j)
+      __shared__ double s_hj;
+      if (threadIdx.x == 0) {
+        double t = vals[j];
+        for (int k = 0; k < j; ++k) t -= vals[j + 2 + k] * vals[k];
+        s_hj = t;
+      }
+      __syncthreads();
+      const double hj = s_hj;
+      double *cd = a.cdel + (int64_t)s * a.ps;
+      for (int k = threadIdx.x; k < j; k += kBlock) {
+        const double ck = vals[j + 2 + k];
+        cd[k] = ck;
+        hs[k] = vals[k] - hj * ck;
+      }
+      if (threadIdx.x == 0) hs[j] = hj;
+    } else {
+      for (int k = threadIdx.x; k <= j; k += kBlock) hs[k] = vals[k];
+    }
     if (threadIdx.x == 0 && OP == OP_PROJ0) {
       // what one projection pass is expected to leave: ||L q_j||^2 minus the
       // squares of all projections (three-term part, and the couplings to
@@ -619,11 +763,10 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
   double alpha_j;
   if (OP == OP_UPD1) {
     const double hj = hs[j];
-    // second Gram-Schmidt pass: on every step after a thick restart (the
-    // kept Ritz vectors are trusted to stay orthogonal to the new
-    // directions across cycles), otherwise when ||w||^2 fell below half of
-    // what one pass is expected to leave (cancellation)
-    if (a.keep > 0 || w2 < 0.5 * W.lq2) {
+    // immediate second Gram-Schmidt pass when ||w||^2 fell below half of
+    // what one pass is expected to leave (cancellation); with thick restart
+    // every vector gets its second pass, delayed into the next step
+    if (a.keep == 0 && w2 < 0.5 * W.lq2) {
       W.need2 = 1;
       W.alpha_tmp = hj;
       return;
@@ -1123,7 +1266,7 @@ void dispatch_rpt(int rpt, F &&f) {
 
 void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx &ctx) {
   S.m = m;
-  S.pstride = m + 4;
+  S.pstride = 2 * m + 8;  // partial sums of 2 j + 2 values (delayed second pass)
   S.nkcap = std::max(1, keep);
   const size_t ns = std::max(nseg, 1), nb = std::max(nblk, 1), ng = std::max(ngrp, 1);
   if (!S.st.p || S.st.n < ns) S.st.alloc(ctx, ns);
@@ -1133,6 +1276,7 @@ void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx
   S.tvec.alloc(ctx, ns * S.nkcap * S.pstride);
   S.tvals.alloc(ctx, ns * S.nkcap);
   S.arrow.alloc(ctx, ns * S.pstride);
+  S.cdel.alloc(ctx, ns * S.pstride);
   S.part.alloc(ctx, nb * S.pstride);
   S.gpart.alloc(ctx, ng * S.pstride);
   S.gcnt.alloc(ctx, ng);
@@ -1167,6 +1311,7 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
   a.tvals = S.tvals.get();
   a.arrow = S.arrow.get();
   a.nkcap = S.nkcap;
+  a.cdel = S.cdel.get();
   a.part = S.part.get();
   a.gpart = S.gpart.get();
   a.gcnt = S.gcnt.get();
@@ -1344,6 +1489,7 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
   a.tvals = S.tvals.get();
   a.arrow = S.arrow.get();
   a.nkcap = S.nkcap;
+  a.cdel = S.cdel.get();
   a.part = S.part.get();
   a.gpart = S.gpart.get();
   a.gcnt = S.gcnt.get();
