@@ -138,15 +138,20 @@ __device__ inline double wave_dot_part(const P *__restrict__ v, const double *zs
 template <int NSL, typename P>
 __device__ inline void wave_dot2_full(const P *__restrict__ v, const double *zs, const double *qs,
                                       int lane, double &az, double &aq) {
-  double x[NSL];
-#pragma unroll
-  for (int t = 0; t < NSL; ++t) x[t] = (double)v[t * kWave];
+  // slices in batches of 8 loads (fewer live registers than one batch)
+  constexpr int NB = NSL < 8 ? NSL : 8;
   az = 0.0;
   aq = 0.0;
 #pragma unroll
-  for (int t = 0; t < NSL; ++t) {
-    az += x[t] * zs[t * kWave + lane];
-    aq += x[t] * qs[t * kWave + lane];
+  for (int t0 = 0; t0 < NSL; t0 += NB) {
+    P x[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) x[t] = v[(t0 + t) * kWave];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      az += (double)x[t] * zs[(t0 + t) * kWave + lane];
+      aq += (double)x[t] * qs[(t0 + t) * kWave + lane];
+    }
   }
 }
 
@@ -292,16 +297,27 @@ __global__ __launch_bounds__(kBlock) void k_lz_begin(LzArgs<T> a) {
 // and reduces v_k^T z over the whole tile with coalesced loads, so no
 // block-wide reduction is needed per coefficient.
 // ----------------------------------------------------------------------------
+// Threads per block of the projection launch: up to 512, so that a thread
+// owns few rows (their gathers are not overlapped with each other) while
+// the register budget still allows several blocks per compute unit.
+template <int RPT>
+constexpr int proj_threads() {
+  return (kBlock * RPT <= 512) ? kBlock * RPT : 512;
+}
+
 template <typename T, int RPT, int MODE, int STEP>
-__global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
+__global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_per_eu(RPT <= 4 ? 6 : 4))) void k_lz_project(LzArgs<T> a, int j) {
   using Tin = typename StepTypes<T, STEP>::Tin;
   using Tw = typename StepTypes<T, STEP>::Tw;
+  constexpr int NT = proj_threads<RPT>();
   constexpr int TILE = kBlock * RPT;
+  constexpr int RT = TILE / NT;  // rows per thread
+  constexpr int NW = NT / kWave;
   constexpr int NSL = TILE / kWave;
   __shared__ double zs[TILE];
   __shared__ double qs[MODE == 0 ? TILE : 1];
   __shared__ double vals[2 * kMaxM + 8];
-  __shared__ double red[kBlock / kWave];
+  __shared__ double red[NW];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
@@ -311,11 +327,18 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
   Tw *Wout = step_out<T, STEP>(a, j);
   const double c = S.c, sc = S.s;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const TileRows<RPT> tr(b);
+  int64_t rows[RT];
+  bool oks[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int lr = r * NT + (int)threadIdx.x;
+    oks[r] = lr < b.nrows;
+    rows[r] = b.row0 + (oks[r] ? lr : 0);
+  }
   double zz = 0.0;
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int64_t row = tr.row[r];
+  for (int r = 0; r < RT; ++r) {
+    const int64_t row = rows[r];
     double z, q = 0.0;
     if (MODE == 0) {
       const Tin wi = Win[row];
@@ -323,33 +346,29 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
       const Tw lq = (Tw)(sc * (double)lap_row<Tin>(a.chunk_ptr, a.cols, Win, row, wi));
       if (STEP == 1) {
         q = qd;
-        if (tr.ok[r]) a.Q1[row] = qd;
+        if (oks[r]) a.Q1[row] = qd;
       } else {
         const T qt = (T)qd;
         q = (double)qt;
-        if (tr.ok[r]) a.V[(int64_t)j * a.vs + row] = qt;
+        if (oks[r]) a.V[(int64_t)j * a.vs + row] = qt;
       }
-      if (tr.ok[r]) Wout[row] = lq;
+      if (oks[r]) Wout[row] = lq;
       z = (double)lq;
     } else {
       z = (double)Wout[row];
     }
-    if (!tr.ok[r]) z = q = 0.0;
-    zs[r * kBlock + threadIdx.x] = z;
-    if (MODE == 0) qs[r * kBlock + threadIdx.x] = q;
+    if (!oks[r]) z = q = 0.0;
+    zs[r * NT + threadIdx.x] = z;
+    if (MODE == 0) qs[r * NT + threadIdx.x] = q;
     zz += z * z;
   }
   zz = wave_sum(zz);
   if (lane == 0) red[wave] = zz;
   __syncthreads();
-  // h_k = v_k^T z, k = 0..j, one wavefront per k.  With thick restart the
-  // same loads also give c_k = v_k^T q_j for k < j: the second Gram-Schmidt
-  // pass of q_j, applied by the update launch of this step (delayed
-  // reorthogonalisation, so both passes cost one read of the basis)
   const bool full = (b.nrows == TILE);
   const int nsl = b.nrows / kWave;
   const bool delayed = (MODE == 0) && a.keep > 0;
-  for (int k = wave; k <= j; k += kBlock / kWave) {
+  for (int k = wave; k <= j; k += NW) {
     double acc, accq;
     const bool dual = delayed && k < j;
     if (MODE == 0 && k == j) {
@@ -374,11 +393,12 @@ __global__ __launch_bounds__(kBlock) void k_lz_project(LzArgs<T> a, int j) {
   }
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int w = 0; w < kBlock / kWave; ++w) s += red[w];
+    for (int w = 0; w < NW; ++w) s += red[w];
     vals[j + 1] = s;
   }
   __syncthreads();
-  write_partials(a, lb, vals, delayed ? 2 * j + 2 : j + 2);
+  const int nval = delayed ? 2 * j + 2 : j + 2;
+  for (int i = threadIdx.x; i < nval; i += NT) a.part[(int64_t)lb * a.ps + i] = vals[i];
 }
 
 // ----------------------------------------------------------------------------
@@ -1213,12 +1233,13 @@ struct LzLaunch {
   static void step(const LzArgs<T> &a, int nblk, int ngrp, int j, hipStream_t s,
                    hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[0], s);
-    k_lz_project<T, RPT, 0, STEP><<<nblk, kBlock, 0, s>>>(a, j);
+    k_lz_project<T, RPT, 0, STEP><<<nblk, proj_threads<RPT>(), 0, s>>>(a, j);
     if (ev) (void)hipEventRecord(ev[1], s);
     k_lz_reduce<T, OP_PROJ0><<<ngrp, kBlock, 0, s>>>(a, j);
     k_lz_update<T, RPT, 1, STEP><<<nblk, kBlock, 0, s>>>(a, j);
     k_lz_reduce<T, OP_UPD1><<<ngrp, kBlock, 0, s>>>(a, j);
-    k_lz_project<T, RPT, 1, STEP><<<nblk, kBlock, 0, s>>>(a, j);
+    if (a.keep > 0) return;  // thick restart: the second pass is folded into the next step
+    k_lz_project<T, RPT, 1, STEP><<<nblk, proj_threads<RPT>(), 0, s>>>(a, j);
     k_lz_reduce<T, OP_PROJ1><<<ngrp, kBlock, 0, s>>>(a, j);
     k_lz_update<T, RPT, 2, STEP><<<nblk, kBlock, 0, s>>>(a, j);
     k_lz_reduce<T, OP_UPD2><<<ngrp, kBlock, 0, s>>>(a, j);
@@ -1530,7 +1551,7 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
                            hipMemcpyDeviceToDevice, ctx.stream);
       if (err != hipSuccess) break;
       (void)hipEventRecord(e0, ctx.stream);
-      k_lz_project<T, RPT, 0, 3><<<nblk, kBlock, 0, ctx.stream>>>(a, j);
+      k_lz_project<T, RPT, 0, 3><<<nblk, proj_threads<RPT>(), 0, ctx.stream>>>(a, j);
       k_lz_reduce<T, OP_PROJ0><<<ngrp, kBlock, 0, ctx.stream>>>(a, j);
       k_lz_update<T, RPT, 1, 3><<<nblk, kBlock, 0, ctx.stream>>>(a, j);
       k_lz_reduce<T, OP_UPD1><<<ngrp, kBlock, 0, ctx.stream>>>(a, j);

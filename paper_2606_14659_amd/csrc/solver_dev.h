@@ -131,33 +131,41 @@ __device__ inline void block_reduce_into(double (&v)[NV], double *red /* [4*NV] 
 
 // Sliced-ELL Laplacian row in difference form: sum_j w_ij (x_i - x_j),
 // accumulated in the vector type (paper Sec. 5: the action of L on x).
+template <int G, typename X>
+__device__ inline void lap_slots(const uint32_t *__restrict__ cp, const X *__restrict__ x, int k0,
+                                 int width, X xi, X &acc) {
+  uint32_t w[G];
+#pragma unroll
+  for (int u = 0; u < G; ++u) w[u] = cp[(int64_t)(k0 + u) * 64];
+#pragma unroll
+  for (int u = 0; u < G; ++u) w[u] = (k0 + u < width) ? w[u] : 0u;
+  X xv[G];
+#pragma unroll
+  for (int u = 0; u < G; ++u) xv[u] = x[colw_col(w[u])];
+#pragma unroll
+  for (int u = 0; u < G; ++u) acc += colw_wt(w[u]) ? (X)colw_wt(w[u]) * (xi - xv[u]) : (X)0;
+}
+
 template <typename X>
 __device__ inline X lap_row(const int64_t *__restrict__ chunk_ptr, const uint32_t *__restrict__ cols,
                             const X *__restrict__ x, int64_t row, X xi) {
+  // slots read at once: 16 for 4-byte values, 8 for 8-byte values (register
+  // budget), and a group of 4 for a short remainder; never more than the
+  // zero slack after the last slice
+  constexpr int G = sizeof(X) == 8 ? kSlotGroup / 2 : kSlotGroup;
   const int64_t c = row >> 6;
   const int lane = (int)(row & 63);
   const int64_t p = chunk_ptr[c];
   const int width = (int)((chunk_ptr[c + 1] - p) >> 6);
   const uint32_t *cp = cols + p + lane;
   X acc = 0;
-  // kSlotGroup slots at a time with unconditional loads (all column words,
-  // then all gathers, so they are in flight together).  Slots past the row's
-  // width read the next slice or the zero slack after the last one and are
-  // masked to weight 0; a weight-0 slot contributes exactly 0 whatever it
-  // gathered.
-  for (int k0 = 0; k0 < width; k0 += kSlotGroup) {
-    uint32_t w[kSlotGroup];
-#pragma unroll
-    for (int u = 0; u < kSlotGroup; ++u) w[u] = cp[(int64_t)(k0 + u) * 64];
-#pragma unroll
-    for (int u = 0; u < kSlotGroup; ++u) w[u] = (k0 + u < width) ? w[u] : 0u;
-    X xv[kSlotGroup];
-#pragma unroll
-    for (int u = 0; u < kSlotGroup; ++u) xv[u] = x[colw_col(w[u])];
-#pragma unroll
-    for (int u = 0; u < kSlotGroup; ++u)
-      acc += colw_wt(w[u]) ? (X)colw_wt(w[u]) * (xi - xv[u]) : (X)0;
-  }
+  // Groups of slots with unconditional loads (all column words, then all
+  // gathers, so they are in flight together).  Slots past the row's width
+  // read the next slice or the zero slack after the last one and are masked
+  // to weight 0; a weight-0 slot contributes exactly 0 whatever it gathered.
+  int k0 = 0;
+  for (; k0 + 4 < width; k0 += G) lap_slots<G>(cp, x, k0, width, xi, acc);
+  if (k0 < width) lap_slots<4>(cp, x, k0, width, xi, acc);
   return acc;
 }
 
