@@ -197,6 +197,8 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     RSB_HIP(hipMemcpyAsync(S.counters.get(), &acc, sizeof(int64_t), hipMemcpyHostToDevice,
                            ctx.stream));
     RSB_HIP(hipStreamSynchronize(ctx.stream));
+    if (ctx.verbose >= 2 && (s % 64 == 63 || s + 1 == L.nseg))
+      fprintf(stderr, "[rsb]   subgraph %d of %d solved\n", s + 1, L.nseg);
   }
   return steps;
 }
