@@ -103,8 +103,11 @@ typedef struct rsb_opts {
                                [1, min(16, lanczos_m - 1)]: thick restart (the
                                Lanczos variant the paper cites in Sec. 6) keeping
                                the k smallest Ritz pairs and continuing from the
-                               last residual direction.  Thick restart needs
-                               precision = RSB_FP64 (RSB_EINVAL otherwise). */
+                               last residual direction.  With precision =
+                               RSB_MIXED the kept Ritz vectors stay FP64 and the
+                               FP32 directions limit the reachable residual to
+                               about 1e-5 lambda (lambda itself is accurate to
+                               about 1e-12); use RSB_FP64 for tighter tol. */
   int32_t reserved[5];
 } rsb_opts;
 

@@ -51,11 +51,6 @@ void check_opts(const rsb_opts *o) {
   if (o->lanczos_keep < 0 || o->lanczos_keep > kMaxKeep ||
       (o->lanczos_keep > 0 && o->lanczos_keep >= o->lanczos_m))
     fail(RSB_EINVAL, "lanczos_keep must be 0 or in [1, min(16, lanczos_m - 1)]");
-  if (o->lanczos_keep > 0 && o->precision == RSB_MIXED && o->method == RSB_LANCZOS)
-    fail(RSB_EINVAL,
-         "thick restart (lanczos_keep > 0) needs FP64 vectors: with FP32 directions a "
-         "second Gram-Schmidt pass on every step would be needed to keep them orthogonal "
-         "to the kept Ritz vectors");
   if (o->rows_per_thread != 0 && o->rows_per_thread != 2 && o->rows_per_thread != 4 &&
       o->rows_per_thread != 8)
     fail(RSB_EINVAL, "rows_per_thread must be 0, 2, 4 or 8");
@@ -253,7 +248,8 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
       round_up(total, kWave) + (int64_t)kWave * (parts_total + 2 * (int64_t)meshes.size());
   const size_t wbytes = (o.method == RSB_INVERSE_CG)
                             ? inverse_workspace_bytes(cap_rows)
-                            : lanczos_workspace_bytes(cap_rows, o.lanczos_m, o.precision == RSB_MIXED);
+                            : lanczos_workspace_bytes(cap_rows, o.lanczos_m, o.precision == RSB_MIXED,
+                                                      o.lanczos_keep);
   DevBuf<char> work(ctx, wbytes);
   DevBuf<double> y64(ctx, cap_rows);
   DevBuf<uint8_t> side(ctx, cap_rows);

@@ -201,11 +201,12 @@ struct LanczosParams {
   KernelProfile *prof;   // non-null: time the step-j>=3 project kernel with events
   int64_t nnz;           // off-diagonal nonzeros of the level (for the byte count)
 };
-// work: lanczos_workspace_bytes(L.nrows, m, T is float) bytes of device memory
-// (FP64 u0, q_1, restart and work vectors; type-T directions q_2..q_m and two
-// work vectors).  T = double: all FP64; T = float: mixed precision.
+// work: lanczos_workspace_bytes(L.nrows, m, T is float, keep) bytes of device
+// memory (FP64 u0, q_1, restart and work vectors; type-T directions q_2..q_m
+// and two work vectors; FP64 kept Ritz vectors 2..keep when T is float).
+// T = double: all FP64; T = float: mixed precision.
 void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx &ctx);
-size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32);
+size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32, int keep);
 // Device time (ms) of one Lanczos step of the level with its current tile.
 template <typename T>
 double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx);

@@ -65,7 +65,7 @@ struct LzArgs {
   double *Wd;    // FP64 work vector of step 1
   T *V;          // q_k at V + k * vs for k >= 2
   double *K;     // kept Ritz vectors of a thick restart, slot k (2 <= k <= nk) at
-                 // K + (k - 2) * vs (the basis slots; thick restart needs T = double)
+                 // K + (k - 2) * vs, FP64 (the basis slots themselves when T = double)
   int64_t vs;
   T *Wt0, *Wt1;  // ping-pong work vectors of steps >= 2
   int m;
@@ -545,9 +545,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
 // place, which is safe because each thread reads every basis value of a
 // row before it writes that row.  The last residual direction (output of
 // step m) is copied to the input buffer of step nnext + 1, where the next
-// cycle continues.  (Thick restart runs with FP64 vectors: with FP32
-// directions, the selective second Gram-Schmidt pass no longer keeps new
-// directions orthogonal to the kept vectors.)
+// cycle continues.  The kept vectors are FP64 whatever T is: rounded to
+// FP32, their coupling to the next (high-frequency) direction would carry an
+// error of order 1e-7 ||L||, large next to the small eigenvalues sought.
 // ----------------------------------------------------------------------------
 template <typename T, int RPT, int NKB>
 __global__ __launch_bounds__(kBlock) void k_lz_ritz_thick(LzArgs<T> a) {
@@ -1310,9 +1310,10 @@ void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx
   RSB_HIP(hipMemsetAsync(S.beta.get(), 0, S.beta.bytes(), ctx.stream));
 }
 
-size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32) {
+size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32, int keep) {
   const size_t t = fp32 ? 4 : 8;
-  return (size_t)rows * (5 * 8 + (size_t)(m + 3) * t);
+  const size_t kept = (fp32 && keep > 1) ? (size_t)(keep - 1) * 8 : 0;
+  return (size_t)rows * (5 * 8 + (size_t)(m + 3) * t + kept);
 }
 
 template <typename T>
@@ -1353,9 +1354,9 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
   a.vs = L.nrows;
   a.Wt0 = wt + (int64_t)(p.m + 1) * L.nrows;
   a.Wt1 = a.Wt0 + L.nrows;
-  // kept Ritz vectors: the basis slots themselves (thick restart runs with
-  // FP64 directions only)
-  a.K = sizeof(T) == 8 ? (double *)(a.V + 2 * L.nrows) : nullptr;
+  // kept Ritz vectors (FP64): after the work vectors when the directions are
+  // FP32, else the basis slots themselves
+  a.K = sizeof(T) == 8 ? (double *)(a.V + 2 * L.nrows) : (double *)(a.Wt1 + L.nrows);
   a.m = p.m;
   a.tol = p.tol;
   a.max_restarts = p.max_restarts;
@@ -1363,7 +1364,7 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
   a.keep = p.keep;
   if (p.keep < 0 || p.keep > kMaxKeep || (p.keep > 0 && p.keep >= p.m))
     fail(RSB_EINVAL, "lanczos_keep must be 0 or in [1, min(16, lanczos_m - 1)]");
-  if (p.keep > 0 && sizeof(T) != 8) fail(RSB_EINVAL, "thick restart needs FP64 vectors");
+
   if (S.nkcap < std::max(1, p.keep)) fail(RSB_EINTERNAL, "Ritz buffers smaller than lanczos_keep");
   a.flags = S.n_active.get();
   a.ctr = (unsigned long long *)S.counters.get();

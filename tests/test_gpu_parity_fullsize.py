@@ -22,7 +22,7 @@ import paper_2606_14659_amd as rsb
 
 pytestmark = pytest.mark.gpu
 
-BENCH = dict(precision="fp64", lanczos_keep=8, tol=1e-2, lanczos_m=40, max_restarts=50)
+BENCH = dict(precision="mixed", lanczos_keep=8, tol=1e-2, lanczos_m=40, max_restarts=50)
 
 
 def _torch_ids(ids):

@@ -65,14 +65,6 @@ def test_bad_options_rejected_before_any_device_call():
         bad.append(code)
         assert rsb.lib().rsb_last_error()
     assert all(c == rsb.EINVAL for c in bad), bad
-    # thick restart with FP32 directions is refused
-    oo = rsb.Opts.from_buffer_copy(o)
-    oo.lanczos_keep = 10
-    oo.precision = 1
-    part = np.zeros(2, dtype=np.int32)
-    assert rsb.lib().rsb_partition(2, 4, ids.ctypes.data_as(C.c_void_p), 2, C.byref(oo),
-                                   part.ctypes.data_as(C.c_void_p), None) == rsb.EINVAL
-    assert b"FP64" in rsb.lib().rsb_last_error()
 
 
 def test_bad_arguments_rejected():
