@@ -117,7 +117,7 @@ template <int NSL, typename P>
 __device__ inline double wave_dot_full(const P *__restrict__ v, const double *zs, int lane) {
   double x[NSL];
 #pragma unroll
-  for (int t = 0; t < NSL; ++t) x[t] = (double)v[t * kWave];
+  for (int t = 0; t < NSL; ++t) x[t] = (double)ld_stream(v + t * kWave);
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < NSL; ++t) acc += x[t] * zs[t * kWave + lane];
@@ -128,7 +128,7 @@ template <typename P>
 __device__ inline double wave_dot_part(const P *__restrict__ v, const double *zs, int lane,
                                        int nsl) {
   double acc = 0.0;
-  for (int t = 0; t < nsl; ++t) acc += (double)v[t * kWave] * zs[t * kWave + lane];
+  for (int t = 0; t < nsl; ++t) acc += (double)ld_stream(v + t * kWave) * zs[t * kWave + lane];
   return acc;
 }
 
@@ -146,7 +146,7 @@ __device__ inline void wave_dot2_full(const P *__restrict__ v, const double *zs,
   for (int t0 = 0; t0 < NSL; t0 += NB) {
     P x[NB];
 #pragma unroll
-    for (int t = 0; t < NB; ++t) x[t] = v[(t0 + t) * kWave];
+    for (int t = 0; t < NB; ++t) x[t] = ld_stream(v + (t0 + t) * kWave);
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
       az += (double)x[t] * zs[(t0 + t) * kWave + lane];
@@ -161,7 +161,7 @@ __device__ inline void wave_dot2_part(const P *__restrict__ v, const double *zs,
   az = 0.0;
   aq = 0.0;
   for (int t = 0; t < nsl; ++t) {
-    const double x = (double)v[t * kWave];
+    const double x = (double)ld_stream(v + t * kWave);
     az += x * zs[t * kWave + lane];
     aq += x * qs[t * kWave + lane];
   }
@@ -191,7 +191,7 @@ __device__ inline void accumulate_slots(const P *__restrict__ B, int kb, int64_t
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) v[kk][r] = B[(int64_t)(k + kk - kb) * vs + tr.row[r]];
+      for (int r = 0; r < RPT; ++r) v[kk][r] = ld_stream(B + (int64_t)(k + kk - kb) * vs + tr.row[r]);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const double ck = coef[k + kk];
@@ -218,7 +218,7 @@ __device__ inline void accumulate_slots2(const P *__restrict__ B, int kb, int64_
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) v[kk][r] = B[(int64_t)(k + kk - kb) * vs + tr.row[r]];
+      for (int r = 0; r < RPT; ++r) v[kk][r] = ld_stream(B + (int64_t)(k + kk - kb) * vs + tr.row[r]);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const double a = ca[k + kk], d = cd[k + kk];

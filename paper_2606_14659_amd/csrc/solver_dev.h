@@ -129,6 +129,14 @@ __device__ inline void block_reduce_into(double (&v)[NV], double *red /* [4*NV] 
   __syncthreads();
 }
 
+// Load of data that a launch reads once (matrix words, basis vectors),
+// marked non-temporal so that the stream does not push the gathered vector
+// out of L2.
+template <typename P>
+__device__ inline P ld_stream(const P *p) {
+  return __builtin_nontemporal_load(p);
+}
+
 // Sliced-ELL Laplacian row in difference form: sum_j w_ij (x_i - x_j),
 // accumulated in the vector type (paper Sec. 5: the action of L on x).
 template <int G, typename X>
@@ -136,7 +144,7 @@ __device__ inline void lap_slots(const uint32_t *__restrict__ cp, const X *__res
                                  int width, X xi, X &acc) {
   uint32_t w[G];
 #pragma unroll
-  for (int u = 0; u < G; ++u) w[u] = cp[(int64_t)(k0 + u) * 64];
+  for (int u = 0; u < G; ++u) w[u] = ld_stream(cp + (int64_t)(k0 + u) * 64);
 #pragma unroll
   for (int u = 0; u < G; ++u) w[u] = (k0 + u < width) ? w[u] : 0u;
   X xv[G];
