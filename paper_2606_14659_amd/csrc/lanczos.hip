@@ -1450,21 +1450,25 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
       if (prof) {
         // launches of steps 3..flags[1] were timed; segment i took part in
         // those of steps j0_i..k_i (k_i - j0_i + 1: the steps it added in
-        // this cycle); launches that no segment took part in count 0 bytes
+        // this cycle); launches that no segment took part in count 0 bytes.
+        // A thick-restart cycle starts at j0 = nk + 1 with the kept Ritz
+        // vectors in basis slots 2..nk, stored in FP64 whatever T is.
         read_state();
         const double st = (double)sizeof(T);
         const double nnz_per_row = (double)p.nnz / (double)std::max<int64_t>(L.nrows, 1);
         for (int j = 3; j <= flags[1]; ++j) {
           float ms = 0.f;
           RSB_HIP(hipEventElapsedTime(&ms, res.ev[2 * j], res.ev[2 * j + 1]));
-          double rows = 0.0;
+          double rows = 0.0, kept_rows = 0.0;
           for (int i = 0; i < nseg; ++i)
-            if (was_active[i] && j >= j00[i] && hst[i].steps - steps0[i] + j00[i] - 1 >= j)
+            if (was_active[i] && j >= j00[i] && hst[i].steps - steps0[i] + j00[i] - 1 >= j) {
               rows += (double)hseg[i].npad;
+              kept_rows += (double)hseg[i].npad * std::max(0, j00[i] - 2);
+            }
           p.prof->ms += ms;
           p.prof->launches += 1;
           p.prof->bytes += 4.0 * (rows + 1) + 4.0 * nnz_per_row * rows +
-                           rows * (st + st + st + 16.0 + (j - 2) * st);
+                           rows * (st + st + st + 16.0 + (j - 2) * st) + kept_rows * (8.0 - st);
         }
       }
       if (flags[0] == 0) break;
