@@ -18,6 +18,7 @@ SRC = os.path.join(HERE, "oracle.cpp")
 
 GRAPH = {"weighted": 0, "unit": 1, "face": 2}
 METHOD = {"lanczos": 0, "inverse_cg": 1}
+PRECOND = {"none": 0, "amg": 1}
 
 
 class Opts(C.Structure):
@@ -25,13 +26,14 @@ class Opts(C.Structure):
                 ("max_restarts", C.c_int32), ("tol", C.c_double), ("inv_max_outer", C.c_int32),
                 ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
                 ("cg_full_projection", C.c_int32), ("seed", C.c_uint64),
-                ("lanczos_keep", C.c_int32)]
+                ("lanczos_keep", C.c_int32), ("inv_precond", C.c_int32),
+                ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double)]
 
 
 class Info(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("matvecs", C.c_int64),
                 ("theta", C.c_double), ("residual", C.c_double), ("ncomp", C.c_int32),
-                ("cg_iters", C.c_int32)]
+                ("cg_iters", C.c_int32), ("amg_levels", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -74,6 +76,11 @@ def lib():
                                     C.c_void_p, P(Info)]
         L.orc_metrics.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                   C.c_void_p]
+        L.orc_amg_level.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_int32, P(C.c_int32), P(C.c_int64), P(C.c_int64),
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_amg_vcycle.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_double, C.c_int32, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -90,6 +97,8 @@ def opts(**kw) -> Opts:
             v = GRAPH[v]
         if k == "method" and isinstance(v, str):
             v = METHOD[v]
+        if k == "inv_precond" and isinstance(v, str):
+            v = PRECOND[v]
         setattr(o, k, v)
     return o
 
@@ -185,6 +194,53 @@ def fiedler_csr(row_ptr, col, w, gid=None, **kw):
     if rc < 0:
         raise RuntimeError(f"orc_fiedler_csr: {rc}")
     return rc, lam.value, y, info.as_dict()
+
+
+def _csr_args(row_ptr, col, w, gid):
+    n = len(row_ptr) - 1
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    ww = np.ascontiguousarray(w, dtype=np.int32)
+    g = np.arange(n, dtype=np.int64) if gid is None else np.ascontiguousarray(gid, dtype=np.int64)
+    return n, rp, c, ww, g
+
+
+def amg_level(row_ptr, col, w, level, gid=None):
+    """Level `level` of the AMG hierarchy: dict with nlevels, row_ptr, col,
+    weight, gid (per row) and agg (row -> row of the next level, -1 on the
+    coarsest level)."""
+    n, rp, c, ww, g = _csr_args(row_ptr, col, w, gid)
+    nl, nr, nz = C.c_int32(0), C.c_int64(0), C.c_int64(0)
+    rc = lib().orc_amg_level(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(g), int(level), C.byref(nl),
+                             C.byref(nr), C.byref(nz), None, None, None, None, None)
+    if rc != 0:
+        raise RuntimeError(f"orc_amg_level: {rc} (levels {nl.value})")
+    out = {"nlevels": nl.value,
+           "row_ptr": np.zeros(nr.value + 1, dtype=np.int64),
+           "col": np.zeros(max(nz.value, 1), dtype=np.int64),
+           "weight": np.zeros(max(nz.value, 1), dtype=np.int64),
+           "gid": np.zeros(nr.value, dtype=np.int64),
+           "agg": np.zeros(nr.value, dtype=np.int64)}
+    rc = lib().orc_amg_level(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(g), int(level), C.byref(nl),
+                             C.byref(nr), C.byref(nz), _ptr(out["row_ptr"]), _ptr(out["col"]),
+                             _ptr(out["weight"]), _ptr(out["gid"]), _ptr(out["agg"]))
+    if rc != 0:
+        raise RuntimeError(f"orc_amg_level: {rc}")
+    out["col"] = out["col"][:nz.value]
+    out["weight"] = out["weight"][:nz.value]
+    return out
+
+
+def amg_vcycle(row_ptr, col, w, f, sigma=2.0 / 3.0, nsmooth=1, gid=None) -> np.ndarray:
+    """u = M f, one V-cycle of the AMG hierarchy of the graph."""
+    n, rp, c, ww, g = _csr_args(row_ptr, col, w, gid)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    u = np.zeros(n, dtype=np.float64)
+    rc = lib().orc_amg_vcycle(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(g), float(sigma), int(nsmooth),
+                              _ptr(f), _ptr(u))
+    if rc != 0:
+        raise RuntimeError(f"orc_amg_vcycle: {rc}")
+    return u
 
 
 def split(y, gid, n_low) -> np.ndarray:

@@ -463,38 +463,225 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
   return converged ? 0 : 1;
 }
 
+// ---------------------------------------------------------------------------
+// Aggregation multigrid preconditioner for the inverse-iteration solves
+// (Sec. 7, Alg. 3).  Every level is the Laplacian of a graph with integer
+// weights; the next level collapses pairs of rows (piecewise-constant
+// prolongation J, Galerkin product J^T L J, which is again a graph
+// Laplacian: the weight between two aggregates is the sum of the weights of
+// the edges between their members, and edges inside an aggregate vanish).
+//
+// Readings (the paper pairs elements by an RCB ordering, which needs
+// coordinates the partitioner is not given):
+//  * pairs come from a handshake matching: in each of kMatchRounds rounds
+//    every unmatched row proposes to its unmatched neighbour of largest
+//    (weight, pair hash), ties to the smaller global id; two rows that
+//    propose to each other are matched.  The pair hash is the splitmix64
+//    output for counter max(gid) of the stream started at min(gid), so both
+//    ends of an edge rank it alike.  Unmatched rows stay single;
+//  * a coarse row is numbered by its first member (fine order) and carries
+//    the smaller global id of its members;
+//  * coarsening stops when the next level would keep more than 90% of the
+//    rows, when a pair's two rows have more than kAmgCandCap entries
+//    together, or after kAmgMaxLevels levels;
+//  * V-cycle smoothing is damped Jacobi with weight sigma; Alg. 3 as printed
+//    subtracts L u from an already updated residual after the coarse
+//    correction; here every post-smoothing step takes the true residual
+//    f - L u.  The coarsest level only runs the pre-smoothing steps.
+// ---------------------------------------------------------------------------
+constexpr int kMatchRounds = 4;
+constexpr int kAmgMaxLevels = 40;
+constexpr int kAmgCandCap = 1024;
+
+struct AmgGraph {
+  int64_t n = 0;
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> adj;  // (neighbour, weight), ascending
+  std::vector<int64_t> gid;
+};
+
+struct AmgLevel {
+  AmgGraph g;
+  std::vector<int64_t> agg;  // row -> row of the next level (empty on the coarsest level)
+  Vec dinv;                  // 1 / L_ii (0 for an isolated row)
+};
+
+uint32_t pair_priority(int64_t ga, int64_t gb) {
+  const uint64_t lo = (uint64_t)std::min(ga, gb), hi = (uint64_t)std::max(ga, gb);
+  return (uint32_t)(splitmix64_at(lo, hi) >> 32);
+}
+
+// Handshake matching; mate[i] = partner, or i for a single row.
+std::vector<int64_t> handshake_matching(const AmgGraph &g) {
+  std::vector<int64_t> mate(g.n, -1), prop(g.n);
+  for (int round = 0; round < kMatchRounds; ++round) {
+    for (int64_t i = 0; i < g.n; ++i) {
+      prop[i] = -1;
+      if (mate[i] >= 0) continue;
+      int64_t bw = -1;
+      uint32_t bh = 0;
+      for (auto &nw : g.adj[i]) {
+        const int64_t j = nw.first;
+        if (mate[j] >= 0) continue;
+        const uint32_t h = pair_priority(g.gid[i], g.gid[j]);
+        const bool better = prop[i] < 0 || nw.second > bw || (nw.second == bw && h > bh) ||
+                            (nw.second == bw && h == bh && g.gid[j] < g.gid[prop[i]]);
+        if (better) {
+          prop[i] = j;
+          bw = nw.second;
+          bh = h;
+        }
+      }
+    }
+    std::vector<int64_t> matched;
+    for (int64_t i = 0; i < g.n; ++i)
+      if (mate[i] < 0 && prop[i] >= 0 && prop[prop[i]] == i) matched.push_back(i);
+    for (int64_t i : matched) mate[i] = prop[i];
+  }
+  for (int64_t i = 0; i < g.n; ++i)
+    if (mate[i] < 0) mate[i] = i;
+  return mate;
+}
+
+Vec diag_inverse(const AmgGraph &g) {
+  Vec d(g.n, 0.0);
+  for (int64_t i = 0; i < g.n; ++i) {
+    int64_t deg = 0;
+    for (auto &nw : g.adj[i]) deg += nw.second;
+    d[i] = deg > 0 ? 1.0 / (double)deg : 0.0;
+  }
+  return d;
+}
+
+// Coarse graph of the matching, or false if coarsening stops here.
+bool coarsen(const AmgGraph &g, std::vector<int64_t> &agg, AmgGraph &c) {
+  std::vector<int64_t> mate = handshake_matching(g);
+  int64_t nc = 0;
+  for (int64_t i = 0; i < g.n; ++i) {
+    if (mate[i] < i) continue;  // the pair is numbered by its first member
+    if ((int64_t)(g.adj[i].size() + (mate[i] != i ? g.adj[mate[i]].size() : 0)) > kAmgCandCap)
+      return false;
+    ++nc;
+  }
+  if (10 * nc > 9 * g.n) return false;
+  agg.assign(g.n, -1);
+  c.n = nc;
+  c.adj.assign(nc, {});
+  c.gid.assign(nc, 0);
+  int64_t k = 0;
+  for (int64_t i = 0; i < g.n; ++i)
+    if (mate[i] >= i) {
+      agg[i] = agg[mate[i]] = k;
+      c.gid[k] = std::min(g.gid[i], g.gid[mate[i]]);
+      ++k;
+    }
+  for (int64_t I = 0; I < nc; ++I) c.adj[I].clear();
+  std::vector<std::map<int64_t, int64_t>> rows(nc);
+  for (int64_t i = 0; i < g.n; ++i)
+    for (auto &nw : g.adj[i])
+      if (agg[nw.first] != agg[i]) rows[agg[i]][agg[nw.first]] += nw.second;
+  for (int64_t I = 0; I < nc; ++I)
+    for (auto &kv : rows[I]) c.adj[I].push_back(kv);
+  return true;
+}
+
+std::vector<AmgLevel> amg_setup(const Graph &g0, const std::vector<int64_t> &gid) {
+  std::vector<AmgLevel> lv(1);
+  lv[0].g.n = g0.n;
+  lv[0].g.gid = gid;
+  lv[0].g.adj.resize(g0.n);
+  for (int64_t i = 0; i < g0.n; ++i)
+    for (auto &nw : g0.adj[i]) lv[0].g.adj[i].push_back({nw.first, nw.second});
+  while ((int)lv.size() < kAmgMaxLevels) {
+    AmgLevel next;
+    if (!coarsen(lv.back().g, lv.back().agg, next.g)) {
+      lv.back().agg.clear();
+      break;
+    }
+    lv.push_back(std::move(next));
+  }
+  for (auto &l : lv) l.dinv = diag_inverse(l.g);
+  return lv;
+}
+
+void amg_apply_laplacian(const AmgGraph &g, const Vec &x, Vec &y) {
+  for (int64_t i = 0; i < g.n; ++i) {
+    double s = 0.0;
+    for (auto &nw : g.adj[i]) s += (double)nw.second * (x[i] - x[nw.first]);
+    y[i] = s;
+  }
+}
+
+// u = M_l f: one V-cycle from level l (Alg. 3 with the readings above).
+void vcycle(const std::vector<AmgLevel> &lv, size_t l, const Vec &f, double sigma, int nsmooth,
+            Vec &u) {
+  const AmgLevel &L = lv[l];
+  const int64_t n = L.g.n;
+  Vec r(n), lu(n);
+  u.assign(n, 0.0);
+  for (int64_t i = 0; i < n; ++i) u[i] = sigma * L.dinv[i] * f[i];
+  auto residual = [&]() {
+    amg_apply_laplacian(L.g, u, lu);
+    for (int64_t i = 0; i < n; ++i) r[i] = f[i] - lu[i];
+  };
+  residual();
+  for (int s = 0; s < nsmooth; ++s) {
+    for (int64_t i = 0; i < n; ++i) u[i] += sigma * L.dinv[i] * r[i];
+    residual();
+  }
+  if (L.agg.empty()) return;  // coarsest level: smoothing only
+  Vec fc(lv[l + 1].g.n, 0.0), ec;
+  for (int64_t i = 0; i < n; ++i) fc[L.agg[i]] += r[i];
+  vcycle(lv, l + 1, fc, sigma, nsmooth, ec);
+  for (int64_t i = 0; i < n; ++i) u[i] += ec[L.agg[i]];
+  for (int s = 0; s < nsmooth; ++s) {
+    residual();
+    for (int64_t i = 0; i < n; ++i) u[i] += sigma * L.dinv[i] * r[i];
+  }
+}
+
 // Conjugate gradients for L x = b with b orthogonal to the ones vector
-// (Sec. 7): x0 = 0, first direction r0 (not preconditioned), Polak-Ribiere
-// beta (identity preconditioner), optional L-orthogonalisation of every new
-// direction against the kept ones ("full projection").  Returns iterations.
-int cg_solve(const Graph &g, const Vec &b, const orc_opts &o, Vec &x, int64_t &matvecs) {
+// (Sec. 7): x0 = 0, first direction r0 (not preconditioned), then the
+// preconditioned residual z = M r (identity, or one V-cycle with the ones
+// component removed) and the flexible (Polak-Ribiere) beta
+// z_new^T (r_new - r_old) / z_old^T r_old; optional L-orthogonalisation of
+// every new direction against the kept ones ("full projection").
+// Returns iterations.
+int cg_solve(const Graph &g, const Vec &b, const orc_opts &o, const std::vector<AmgLevel> *amg,
+             Vec &x, int64_t &matvecs) {
   const int64_t n = g.n;
   x.assign(n, 0.0);
-  Vec r = b, p = b, lp(n);
+  Vec r = b, p, lp(n), z;
   deflate_ones(r);
   p = r;
-  double rr = dot(r, r);
+  z = r;
+  double rz = dot(r, z);
   double bnorm = norm2(b);
   std::vector<Vec> P, LP;
   std::vector<double> pLp;
   int it = 0;
-  if (std::sqrt(rr) <= o.cg_tol * bnorm) return 0;
+  if (norm2(r) <= o.cg_tol * bnorm) return 0;
   for (it = 1; it <= o.cg_max_iter; ++it) {
     apply_laplacian(g, p, lp);
     ++matvecs;
     double plp = dot(p, lp);
-    double alpha = rr / plp;
+    double alpha = rz / plp;
     Vec rn(n);
     for (int64_t i = 0; i < n; ++i) {
       x[i] += alpha * p[i];
       rn[i] = r[i] - alpha * lp[i];
     }
     deflate_ones(rn);
-    double rrn = dot(rn, rn);
-    if (std::sqrt(rrn) <= o.cg_tol * bnorm) break;
+    if (norm2(rn) <= o.cg_tol * bnorm) break;
+    Vec zn;
+    if (amg) {
+      vcycle(*amg, 0, rn, o.amg_sigma, o.amg_smooth, zn);
+      deflate_ones(zn);
+    } else {
+      zn = rn;
+    }
     double diff = 0.0;
-    for (int64_t i = 0; i < n; ++i) diff += rn[i] * (rn[i] - r[i]);
-    double beta = diff / rr;
+    for (int64_t i = 0; i < n; ++i) diff += zn[i] * (rn[i] - r[i]);
+    double beta = diff / rz;
     if (o.cg_full_projection > 0) {
       P.push_back(p);
       LP.push_back(lp);
@@ -505,13 +692,14 @@ int cg_solve(const Graph &g, const Vec &b, const orc_opts &o, Vec &x, int64_t &m
         pLp.erase(pLp.begin());
       }
     }
-    for (int64_t i = 0; i < n; ++i) p[i] = rn[i] + beta * p[i];
+    for (int64_t i = 0; i < n; ++i) p[i] = zn[i] + beta * p[i];
     for (size_t k = 0; k < P.size(); ++k) {
       double c = dot(LP[k], p) / pLp[k];
       for (int64_t i = 0; i < n; ++i) p[i] -= c * P[k][i];
     }
     r = rn;
-    rr = rrn;
+    z = zn;
+    rz = dot(r, z);
   }
   return std::min(it, o.cg_max_iter);
 }
@@ -524,10 +712,13 @@ int inverse_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
   for (int64_t i = 0; i < n; ++i) b[i] = start_value(o.seed, gid[i]);
   int converged = 0;
   double rho = 0.0, res = 0.0;
+  std::vector<AmgLevel> amg;
+  if (o.inv_precond == ORC_PRECOND_AMG) amg = amg_setup(g, gid);
+  info.amg_levels = (int32_t)amg.size();
   for (int outer = 0; outer < o.inv_max_outer; ++outer) {
     deflate_ones(b);
     normalize(b);
-    int its = cg_solve(g, b, o, x, info.matvecs);
+    int its = cg_solve(g, b, o, amg.empty() ? nullptr : &amg, x, info.matvecs);
     info.cg_iters += its;
     b = x;
     info.cycles = outer + 1;
@@ -751,6 +942,9 @@ void orc_opts_default(orc_opts *o) {
   o->cg_full_projection = 0;
   o->seed = 20261203ULL;
   o->lanczos_keep = 0;
+  o->inv_precond = ORC_PRECOND_NONE;
+  o->amg_smooth = 1;
+  o->amg_sigma = 2.0 / 3.0;
 }
 
 double orc_start_value(uint64_t seed, int64_t gid) { return start_value(seed, gid); }
@@ -845,6 +1039,54 @@ int orc_split(int64_t n, const double *y, const int64_t *gid, int64_t n_low, uin
   std::vector<uint8_t> s;
   split_by_keys(yv, gv, n_low, s);
   std::copy(s.begin(), s.end(), side);
+  return 0;
+}
+
+int orc_amg_level(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                  const int64_t *gid, int32_t level, int32_t *nlevels, int64_t *nrows,
+                  int64_t *nnz, int64_t *row_ptr_out, int64_t *col_out, int64_t *weight_out,
+                  int64_t *gid_out, int64_t *agg) {
+  if (n < 1 || !row_ptr || !gid || !nlevels || !nrows || !nnz) return -1;
+  Graph g;
+  to_graph(n, row_ptr, col, weight, g);
+  std::vector<int64_t> gv(gid, gid + n);
+  std::vector<AmgLevel> lv = amg_setup(g, gv);
+  *nlevels = (int32_t)lv.size();
+  if (level < 0 || level >= (int32_t)lv.size()) return -1;
+  const AmgLevel &L = lv[level];
+  *nrows = L.g.n;
+  int64_t k = 0;
+  for (int64_t i = 0; i < L.g.n; ++i) k += (int64_t)L.g.adj[i].size();
+  *nnz = k;
+  if (row_ptr_out && col_out && weight_out) {
+    k = 0;
+    for (int64_t i = 0; i < L.g.n; ++i) {
+      row_ptr_out[i] = k;
+      for (auto &nw : L.g.adj[i]) {
+        col_out[k] = nw.first;
+        weight_out[k] = nw.second;
+        ++k;
+      }
+    }
+    row_ptr_out[L.g.n] = k;
+  }
+  if (gid_out)
+    for (int64_t i = 0; i < L.g.n; ++i) gid_out[i] = L.g.gid[i];
+  if (agg)
+    for (int64_t i = 0; i < L.g.n; ++i) agg[i] = L.agg.empty() ? -1 : L.agg[i];
+  return 0;
+}
+
+int orc_amg_vcycle(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                   const int64_t *gid, double sigma, int32_t nsmooth, const double *f, double *u) {
+  if (n < 1 || !row_ptr || !gid || !f || !u || nsmooth < 0) return -1;
+  Graph g;
+  to_graph(n, row_ptr, col, weight, g);
+  std::vector<int64_t> gv(gid, gid + n);
+  std::vector<AmgLevel> lv = amg_setup(g, gv);
+  Vec fv(f, f + n), uv;
+  vcycle(lv, 0, fv, sigma, nsmooth, uv);
+  std::copy(uv.begin(), uv.end(), u);
   return 0;
 }
 

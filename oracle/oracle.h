@@ -27,6 +27,7 @@ extern "C" {
 
 enum { ORC_GRAPH_WEIGHTED = 0, ORC_GRAPH_UNIT = 1, ORC_GRAPH_FACE = 2 };
 enum { ORC_LANCZOS = 0, ORC_INVERSE_CG = 1 };
+enum { ORC_PRECOND_NONE = 0, ORC_PRECOND_AMG = 1 };
 
 typedef struct orc_opts {
   int32_t graph;             /* ORC_GRAPH_* */
@@ -42,6 +43,9 @@ typedef struct orc_opts {
   uint64_t seed;             /* start-vector seed */
   int32_t lanczos_keep;      /* 0: explicit restart from the Ritz vector; k > 0:
                                 thick restart keeping the k smallest Ritz pairs */
+  int32_t inv_precond;       /* inverse iteration: ORC_PRECOND_NONE or _AMG */
+  int32_t amg_smooth;        /* AMG: damped-Jacobi steps per smoothing phase */
+  double amg_sigma;          /* AMG: Jacobi damping weight */
 } orc_opts;
 
 typedef struct orc_info {
@@ -52,6 +56,7 @@ typedef struct orc_info {
   double residual;     /* ||L y - theta y|| of the returned vector */
   int32_t ncomp;       /* connected components of the graph solved on */
   int32_t cg_iters;    /* inverse iteration: CG steps summed over solves */
+  int32_t amg_levels;  /* inverse iteration with AMG: levels of the hierarchy */
 } orc_info;
 
 void orc_opts_default(orc_opts *o);
@@ -96,6 +101,23 @@ int orc_fiedler_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const
 /* The split rule on a given vector: side[i] = 0 for the n_low smallest keys
  * (y_i, gid_i), 1 otherwise. */
 int orc_split(int64_t n, const double *y, const int64_t *gid, int64_t n_low, uint8_t *side);
+
+/* Level `level` of the aggregation multigrid hierarchy of a CSR graph (the
+ * preconditioner of the inverse-iteration solves, Sec. 7), with gid[i] the
+ * global id of row i.  Writes *nlevels and the level's row count *nrows and
+ * entry count *nnz; when the arrays are non-NULL also its CSR (row_ptr of
+ * nrows + 1, col and weight of nnz entries, columns ascending), the global
+ * id carried by every row, and agg[i] = row of level + 1 that row i of this
+ * level collapses into (-1 on the coarsest level).  Returns 0, -1 on bad
+ * input (level out of range). */
+int orc_amg_level(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                  const int64_t *gid, int32_t level, int32_t *nlevels, int64_t *nrows,
+                  int64_t *nnz, int64_t *row_ptr_out, int64_t *col_out, int64_t *weight_out,
+                  int64_t *gid_out, int64_t *agg);
+
+/* u = M f: one V-cycle of that hierarchy (Sec. 7, Alg. 3). */
+int orc_amg_vcycle(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                   const int64_t *gid, double sigma, int32_t nsmooth, const double *f, double *u);
 
 /* Recursive spectral bisection into nparts parts; part[i] in [0, nparts). */
 int orc_partition(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts,
