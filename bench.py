@@ -203,6 +203,10 @@ def main():
     ap.add_argument("--keep", type=int, default=8,
                     help="thick restart keeping this many Ritz pairs (0: explicit restart)")
     ap.add_argument("--max-restarts", type=int, default=50)
+    ap.add_argument("--method", default="lanczos", choices=["lanczos", "inverse_cg"],
+                    help="eigen-solver; inverse_cg runs report CG steps, not Lanczos steps")
+    ap.add_argument("--precond", default="none", choices=["none", "amg"],
+                    help="inverse_cg: plain CG or aggregation-multigrid preconditioned CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", type=int, default=0)
     ap.add_argument("--unbatched", action="store_true")
@@ -254,6 +258,7 @@ def main():
     part = torch.empty(mesh.nelem, dtype=torch.int32, device="cuda")
     opts = dict(precision=args.precision, tol=args.tol, lanczos_m=args.m,
                 max_restarts=args.max_restarts, verbose=args.verbose, lanczos_keep=args.keep,
+                method=args.method, inv_precond=args.precond, cg_tol=1e-8, inv_max_outer=100,
                 batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
                 autotune=args.autotune)
     if args.autotune_cache:
@@ -296,7 +301,7 @@ def main():
     out = {
         "metric": METRIC,
         "value": total_steps / dt,
-        "unit": "Lanczos iterations/s",
+        "unit": "Lanczos iterations/s" if args.method == "lanczos" else "CG iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -310,6 +315,7 @@ def main():
                    "precision": args.precision, "lanczos_m": args.m, "lanczos_keep": args.keep,
                    "tol": args.tol,
                    "max_restarts": args.max_restarts, "graph": "weighted vertex-shared",
+                   "method": args.method, "precond": args.precond,
                    "batched": not args.unbatched},
         "time_to_partition_ms": dt * 1e3 / args.steps,
         "edge_cut": st["edge_cut"],

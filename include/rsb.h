@@ -58,6 +58,9 @@ extern "C" {
 #define RSB_LANCZOS 0    /* restarted Lanczos, full reorthogonalisation (Sec. 6) */
 #define RSB_INVERSE_CG 1 /* inverse iteration, CG inner solves (Sec. 7, Alg. 2) */
 
+#define RSB_PRECOND_NONE 0 /* INVERSE_CG: plain CG */
+#define RSB_PRECOND_AMG 1  /* INVERSE_CG: aggregation multigrid V-cycle (Sec. 7, Alg. 3) */
+
 #define RSB_FP64 0  /* all vectors and arithmetic in FP64 */
 #define RSB_MIXED 1 /* Lanczos directions q_2..q_m and their SpMV in FP32 (FP32
                        accumulation); in FP64: the restart (Ritz) vector and the
@@ -108,7 +111,18 @@ typedef struct rsb_opts {
                                FP32 directions limit the reachable residual to
                                about 1e-5 lambda (lambda itself is accurate to
                                about 1e-12); use RSB_FP64 for tighter tol. */
-  int32_t reserved[5];
+  int32_t inv_precond;      /* INVERSE_CG: RSB_PRECOND_NONE (default) or
+                               RSB_PRECOND_AMG.  With AMG the first direction
+                               of every CG solve is still the plain residual
+                               (Sec. 7); later ones are one V-cycle of the
+                               residual.  The hierarchy collapses pairs of rows
+                               chosen by a handshake matching on edge weight
+                               (the paper pairs elements along an RCB order;
+                               no coordinates are given here) into Galerkin
+                               coarse Laplacians, per subgraph. */
+  int32_t amg_smooth;       /* AMG: damped-Jacobi steps per smoothing phase (1) */
+  double amg_sigma;         /* AMG: Jacobi damping weight (2/3) */
+  int32_t reserved[2];
 } rsb_opts;
 
 typedef struct rsb_stats {
@@ -140,11 +154,14 @@ typedef struct rsb_stats {
   double kernel_bytes;       /* algorithmic bytes of all its launches: per launch at
                                 step j over n rows with nnz off-diagonal entries,
                                 4 (n + 1) + 4 nnz + n (s_x + s_Lq + s_q + 16 +
-                                (j - 2) s_q), s_ = bytes per value */
+                                (j - 2) s_q + (k - 1)(8 - s_q)), s_ = bytes per
+                                value, k = Ritz pairs kept by a thick restart
+                                (FP64 basis slots 2..k; no term for k <= 1) */
   double kernel_ms;          /* summed device time of its launches (HIP events) */
   int64_t kernel_launches;   /* its launches */
   int32_t tile_rows;         /* rows per workgroup of the streaming kernels at level 0 */
-  int32_t reserved[5];
+  int32_t amg_levels;        /* INVERSE_CG with AMG: levels of the deepest hierarchy */
+  int32_t reserved[4];
 } rsb_stats;
 
 /* Fills *o with the defaults listed above.  Returns RSB_OK or RSB_EINVAL (o NULL). */
@@ -171,6 +188,28 @@ int rsb_dual_graph(int64_t nelem, int32_t nv_per_elem, const int64_t *elem_verte
  * Exposed for testing the SpMV.  RSB_EINVAL on bad sizes or weights. */
 int rsb_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
                         const int32_t *weight, const double *x, double *y, const rsb_opts *opts);
+
+/* Level `level` of the aggregation multigrid hierarchy that preconditions the
+ * inverse-iteration solves (Sec. 7, Alg. 3: pairs of rows collapsed by a
+ * Boolean prolongation J, coarse Laplacian J^T L J), built on a caller CSR
+ * as in rsb_laplacian_apply with row i's global id = i and every row taking
+ * part.  Exposed for testing the setup.  Two-call protocol: with col_out ==
+ * NULL only *nlevels, *nrows and *nnz are written; otherwise the arrays must
+ * hold nrows + 1 (row_ptr_out), nnz (col_out, weight_out) and nrows (gid_out,
+ * agg_out: the row of level + 1 each row collapses into, -1 on the coarsest
+ * level) entries, host memory, and receive the level's CSR (columns
+ * ascending, int64 weights).  RSB_EINVAL on bad sizes or a level outside
+ * [0, *nlevels). */
+int rsb_amg_level(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                  const int32_t *weight, int32_t level, const rsb_opts *opts, int32_t *nlevels,
+                  int64_t *nrows, int64_t *nnz, int64_t *row_ptr_out, int64_t *col_out,
+                  int64_t *weight_out, int64_t *gid_out, int64_t *agg_out);
+
+/* u = M f: one V-cycle of that hierarchy (opts->amg_sigma, opts->amg_smooth)
+ * on a caller CSR (same conventions), f and u of n doubles (host or device
+ * per opts->device_pointers).  Exposed for testing the V-cycle. */
+int rsb_amg_vcycle(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                   const int32_t *weight, const double *f, double *u, const rsb_opts *opts);
 
 /* Fiedler pair of the mesh's dual-graph Laplacian (Sec. 4: L x = lambda x
  * with 1^T x = 0; Sec. 6 Lanczos or Sec. 7 inverse iteration).  fiedler_out

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "librsb.so")
 GRAPH = {"weighted": 0, "unit": 1, "face": 2}
 METHOD = {"lanczos": 0, "inverse_cg": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
+PRECOND = {"none": 0, "amg": 1}
 
 OK, WARN_NOT_CONVERGED, WARN_DISCONNECTED = 0, 1, 2
 EINVAL, ENOMEM, EDEVICE, EBUFFER, EINTERNAL = -1, -2, -3, -4, -5
@@ -35,7 +36,8 @@ class Opts(C.Structure):
         ("autotune_cache", C.c_char_p), ("device", C.c_int32), ("device_pointers", C.c_int32),
         ("stream", C.c_void_p), ("device_mem_limit", C.c_int64), ("verbose", C.c_int32),
         ("profile", C.c_int32), ("rows_per_thread", C.c_int32), ("lanczos_keep", C.c_int32),
-        ("reserved", C.c_int32 * 5),
+        ("inv_precond", C.c_int32), ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double),
+        ("reserved", C.c_int32 * 2),
     ]
 
 
@@ -48,7 +50,8 @@ class Stats(C.Structure):
         ("ms_split", C.c_double), ("ms_total", C.c_double), ("edge_cut", C.c_double),
         ("cut_pairs", C.c_int64), ("max_neighbors", C.c_int32), ("avg_neighbors", C.c_double),
         ("nnz", C.c_int64), ("kernel_bytes", C.c_double), ("kernel_ms", C.c_double),
-        ("kernel_launches", C.c_int64), ("tile_rows", C.c_int32), ("reserved", C.c_int32 * 5),
+        ("kernel_launches", C.c_int64), ("tile_rows", C.c_int32), ("amg_levels", C.c_int32),
+        ("reserved", C.c_int32 * 4),
     ]
 
     def as_dict(self):
@@ -77,6 +80,11 @@ _SIGNATURES = {
                        C.c_void_p], C.c_int),
     "rsb_partition_batch": ([C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "rsb_amg_level": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                       C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "rsb_amg_vcycle": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                        C.c_void_p], C.c_int),
     "rsb_strerror": ([C.c_int], C.c_char_p),
     "rsb_last_error": ([], C.c_char_p),
 }
@@ -137,6 +145,8 @@ def make_opts(device_arrays: bool = False, **kw) -> Opts:
             v = METHOD[v]
         elif k == "precision" and isinstance(v, str):
             v = PRECISION[v]
+        elif k == "inv_precond" and isinstance(v, str):
+            v = PRECOND[v]
         elif k == "autotune_cache" and isinstance(v, str):
             v = v.encode()
         if not hasattr(o, k):
@@ -211,6 +221,49 @@ def laplacian_apply(row_ptr, col, weight, x, device: bool = False, **kw):
     _check(lib().rsb_laplacian_apply(n, rp.ptr, c.ptr, w.ptr, xx.ptr, yp, C.byref(o)),
            "rsb_laplacian_apply")
     return y
+
+
+def amg_level(row_ptr, col, weight, level: int, **kw) -> dict:
+    """Level `level` of the AMG hierarchy of a CSR graph (host arrays):
+    nlevels, row_ptr, col, weight, gid, agg (-1 on the coarsest level)."""
+    n = len(row_ptr) - 1
+    o = make_opts(False, **kw)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col if len(col) else np.zeros(1), dtype=np.int32)
+    w = np.ascontiguousarray(weight if len(weight) else np.zeros(1), dtype=np.int32)
+    nl, nr, nz = C.c_int32(0), C.c_int64(0), C.c_int64(0)
+    L = lib()
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    _check(L.rsb_amg_level(n, ptr(rp), ptr(c), ptr(w), int(level), C.byref(o), C.byref(nl),
+                           C.byref(nr), C.byref(nz), None, None, None, None, None),
+           "rsb_amg_level")
+    out = {"nlevels": nl.value, "row_ptr": np.zeros(nr.value + 1, dtype=np.int64),
+           "col": np.zeros(max(nz.value, 1), dtype=np.int64),
+           "weight": np.zeros(max(nz.value, 1), dtype=np.int64),
+           "gid": np.zeros(max(nr.value, 1), dtype=np.int64),
+           "agg": np.zeros(max(nr.value, 1), dtype=np.int64)}
+    _check(L.rsb_amg_level(n, ptr(rp), ptr(c), ptr(w), int(level), C.byref(o), C.byref(nl),
+                           C.byref(nr), C.byref(nz), ptr(out["row_ptr"]), ptr(out["col"]),
+                           ptr(out["weight"]), ptr(out["gid"]), ptr(out["agg"])),
+           "rsb_amg_level")
+    out["col"] = out["col"][:nz.value]
+    out["weight"] = out["weight"][:nz.value]
+    out["gid"] = out["gid"][:nr.value]
+    out["agg"] = out["agg"][:nr.value]
+    return out
+
+
+def amg_vcycle(row_ptr, col, weight, f, device: bool = False, **kw):
+    """u = M f, one V-cycle of the AMG hierarchy of a CSR graph."""
+    n = len(row_ptr) - 1
+    o = make_opts(device, **kw)
+    rp = _Arr(row_ptr, np.int64, device)
+    c = _Arr(col if len(col) else np.zeros(1), np.int32, device)
+    w = _Arr(weight if len(weight) else np.zeros(1), np.int32, device)
+    ff = _Arr(f, np.float64, device)
+    u, up = _out(n, np.float64, device)
+    _check(lib().rsb_amg_vcycle(n, rp.ptr, c.ptr, w.ptr, ff.ptr, up, C.byref(o)), "rsb_amg_vcycle")
+    return u
 
 
 def split(y, gid, n_low, device: bool = False, **kw):

@@ -54,6 +54,10 @@ void check_opts(const rsb_opts *o) {
   if (o->rows_per_thread != 0 && o->rows_per_thread != 2 && o->rows_per_thread != 4 &&
       o->rows_per_thread != 8)
     fail(RSB_EINVAL, "rows_per_thread must be 0, 2, 4 or 8");
+  if (o->inv_precond != RSB_PRECOND_NONE && o->inv_precond != RSB_PRECOND_AMG)
+    fail(RSB_EINVAL, "inv_precond must be RSB_PRECOND_NONE or RSB_PRECOND_AMG");
+  if (o->amg_smooth < 0 || o->amg_smooth > 16) fail(RSB_EINVAL, "amg_smooth must be in [0, 16]");
+  if (!(o->amg_sigma > 0.0 && o->amg_sigma < 2.0)) fail(RSB_EINVAL, "amg_sigma must be in (0, 2)");
 }
 
 void setup_ctx(Ctx &ctx, const rsb_opts &o) {
@@ -142,11 +146,12 @@ void one_segment_tables(const Level &L, int s, OneSeg &o, Ctx &ctx) {
 
 // Eigen-solve of one level: all segments batched, or one segment at a time.
 int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, void *work,
-                    double *y64, KernelProfile *prof, Ctx &ctx) {
+                    double *y64, KernelProfile *prof, int *amg_levels, Ctx &ctx) {
   const bool mixed = o.precision == RSB_MIXED;
   auto run = [&](const LevelView &v, SolveDev &SS, bool graph) -> int64_t {
     if (o.method == RSB_INVERSE_CG) {
-      InverseParams ip{o.inv_max_outer, o.cg_max_iter, o.cg_tol, o.tol, o.seed};
+      InverseParams ip{o.inv_max_outer, o.cg_max_iter, o.cg_tol, o.tol,       o.seed,
+                       o.inv_precond,   o.amg_sigma,     o.amg_smooth, amg_levels};
       return inverse_level(v, C, SS, ip, work, y64, graph, ctx);
     }
     LanczosParams lp{o.lanczos_m, o.lanczos_keep, o.max_restarts, o.tol, graph ? 1 : 0,
@@ -268,8 +273,10 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     if (level == 0) st.tile_rows = kBlock * L->rpt;
     solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
     components_and_targets(*L, C, S, ctx);
+    int amg_levels = 0;
     const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(),
-                                      o.profile ? &prof : nullptr, ctx);
+                                      o.profile ? &prof : nullptr, &amg_levels, ctx);
+    st.amg_levels = std::max(st.amg_levels, amg_levels);
     std::vector<SegState> hs(L->nseg);
     RSB_HIP(hipMemcpyAsync(hs.data(), S.st.get(), L->nseg * sizeof(SegState),
                            hipMemcpyDeviceToHost, ctx.stream));
@@ -419,6 +426,85 @@ void check_stats(rsb_stats *s) {
 
 using namespace rsb;
 
+namespace {
+
+// Validated device copy of a caller CSR (row_ptr int64[n+1], col int32,
+// weight int32 in [0, 15]).
+void load_csr(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const int32_t *weight,
+              const rsb_opts &o, Ctx &ctx, DevCsr &g) {
+  if (n < 1 || n >= kMaxRows || !row_ptr || !col_idx || !weight) fail(RSB_EINVAL, "bad arguments");
+  const bool dev = o.device_pointers != 0;
+  int64_t nnz = 0;
+  if (!dev) {
+    nnz = row_ptr[n];
+    if (row_ptr[0] != 0) fail(RSB_EINVAL, "row_ptr[0] must be 0");
+    for (int64_t i = 0; i < n; ++i)
+      if (row_ptr[i + 1] < row_ptr[i]) fail(RSB_EINVAL, "row_ptr not monotone");
+    for (int64_t p = 0; p < nnz; ++p) {
+      if (col_idx[p] < 0 || col_idx[p] >= n) fail(RSB_EINVAL, "column out of range");
+      if (weight[p] < 0 || weight[p] > (int32_t)kWeightMask)
+        fail(RSB_EINVAL, "weight out of [0, 15]");
+    }
+  }
+  setup_ctx(ctx, o);
+  if (dev) {
+    int64_t r0 = 0;
+    RSB_HIP(hipMemcpyAsync(&nnz, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, ctx.stream));
+    RSB_HIP(hipMemcpyAsync(&r0, row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost, ctx.stream));
+    DevBuf<int> bad(ctx, 1);
+    RSB_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), ctx.stream));
+    k_check_csr<<<(unsigned)((n + 255) / 256), 256, 0, ctx.stream>>>(row_ptr, col_idx, weight, n,
+                                                                    bad.get());
+    RSB_LAUNCHED();
+    int hbad = 0;
+    RSB_HIP(hipMemcpyAsync(&hbad, bad.get(), sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    if (hbad || r0 != 0) fail(RSB_EINVAL, "invalid CSR (row_ptr, column or weight)");
+  }
+  if (nnz < 0) fail(RSB_EINVAL, "row_ptr[n] < 0");
+  g.n = n;
+  g.nnz = nnz;
+  g.row_ptr.alloc(ctx, n + 1);
+  g.col.alloc(ctx, std::max<int64_t>(nnz, 1));
+  g.wgt.alloc(ctx, std::max<int64_t>(nnz, 1));
+  auto kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  RSB_HIP(hipMemcpyAsync(g.row_ptr.get(), row_ptr, (n + 1) * sizeof(int64_t), kind, ctx.stream));
+  if (nnz > 0) {
+    RSB_HIP(hipMemcpyAsync(g.col.get(), col_idx, nnz * sizeof(int32_t), kind, ctx.stream));
+    RSB_HIP(hipMemcpyAsync(g.wgt.get(), weight, nnz * sizeof(int32_t), kind, ctx.stream));
+  }
+}
+
+// AMG hierarchy of a whole CSR graph (one segment, every row taking part),
+// for the test entry points.
+struct CsrAmg {
+  Level L;
+  DevBuf<int32_t> root;
+  DevBuf<SegState> st;
+  AmgDev A;
+};
+
+void csr_amg_setup(const DevCsr &g, CsrAmg &t, Ctx &ctx) {
+  std::vector<const DevCsr *> gs{&g};
+  std::vector<int32_t> np{2};
+  level0_from_csr(t.L, gs, np, default_rpt(g.n), ctx);
+  // the single segment starts at row 0: rows below n are elements
+  std::vector<int32_t> hroot(t.L.nrows);
+  for (int64_t i = 0; i < t.L.nrows; ++i) hroot[i] = i < g.n ? 0 : -1;
+  SegState hs{};
+  hs.solve = 1;
+  hs.strad = 0;
+  hs.active = 1;
+  t.root.alloc(ctx, t.L.nrows);
+  t.st.alloc(ctx, 1);
+  RSB_HIP(hipMemcpyAsync(t.root.get(), hroot.data(), t.L.nrows * sizeof(int32_t),
+                         hipMemcpyHostToDevice, ctx.stream));
+  RSB_HIP(hipMemcpyAsync(t.st.get(), &hs, sizeof(SegState), hipMemcpyHostToDevice, ctx.stream));
+  amg_setup(view_of(t.L), t.root.get(), t.st.get(), t.A, ctx);
+}
+
+}  // namespace
+
 extern "C" {
 
 int rsb_opts_init(rsb_opts *o) {
@@ -446,6 +532,9 @@ int rsb_opts_init(rsb_opts *o) {
   o->device_mem_limit = 0;
   o->verbose = 0;
   o->profile = 0;
+  o->inv_precond = RSB_PRECOND_NONE;
+  o->amg_smooth = 1;
+  o->amg_sigma = 2.0 / 3.0;
   return RSB_OK;
 }
 
@@ -503,55 +592,117 @@ int rsb_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col_id
                         const int32_t *weight, const double *x, double *y, const rsb_opts *opts) {
   return guarded([&]() -> int {
     check_opts(opts);
-    if (n < 1 || n >= kMaxRows || !row_ptr || !col_idx || !weight || !x || !y)
-      fail(RSB_EINVAL, "bad arguments");
-    const bool dev = opts->device_pointers != 0;
-    int64_t nnz = 0;
-    if (!dev) {
-      nnz = row_ptr[n];
-      if (row_ptr[0] != 0) fail(RSB_EINVAL, "row_ptr[0] must be 0");
-      for (int64_t i = 0; i < n; ++i)
-        if (row_ptr[i + 1] < row_ptr[i]) fail(RSB_EINVAL, "row_ptr not monotone");
-      for (int64_t p = 0; p < nnz; ++p) {
-        if (col_idx[p] < 0 || col_idx[p] >= n) fail(RSB_EINVAL, "column out of range");
-        if (weight[p] < 0 || weight[p] > (int32_t)kWeightMask)
-          fail(RSB_EINVAL, "weight out of [0, 15]");
-      }
-    }
+    if (!x || !y) fail(RSB_EINVAL, "bad arguments");
     Ctx ctx;
-    setup_ctx(ctx, *opts);
-    if (dev) {
-      int64_t r0 = 0;
-      RSB_HIP(hipMemcpyAsync(&nnz, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, ctx.stream));
-      RSB_HIP(hipMemcpyAsync(&r0, row_ptr, sizeof(int64_t), hipMemcpyDeviceToHost, ctx.stream));
-      DevBuf<int> bad(ctx, 1);
-      RSB_HIP(hipMemsetAsync(bad.get(), 0, sizeof(int), ctx.stream));
-      k_check_csr<<<(unsigned)((n + 255) / 256), 256, 0, ctx.stream>>>(row_ptr, col_idx, weight, n,
-                                                                      bad.get());
-      RSB_LAUNCHED();
-      int hbad = 0;
-      RSB_HIP(hipMemcpyAsync(&hbad, bad.get(), sizeof(int), hipMemcpyDeviceToHost, ctx.stream));
-      RSB_HIP(hipStreamSynchronize(ctx.stream));
-      if (hbad || r0 != 0) fail(RSB_EINVAL, "invalid CSR (row_ptr, column or weight)");
-    }
-    if (nnz < 0) fail(RSB_EINVAL, "row_ptr[n] < 0");
     DevCsr g;
-    g.n = n;
-    g.nnz = nnz;
-    g.row_ptr.alloc(ctx, n + 1);
-    g.col.alloc(ctx, std::max<int64_t>(nnz, 1));
-    g.wgt.alloc(ctx, std::max<int64_t>(nnz, 1));
-    auto kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    RSB_HIP(hipMemcpyAsync(g.row_ptr.get(), row_ptr, (n + 1) * sizeof(int64_t), kind, ctx.stream));
-    if (nnz > 0) {
-      RSB_HIP(hipMemcpyAsync(g.col.get(), col_idx, nnz * sizeof(int32_t), kind, ctx.stream));
-      RSB_HIP(hipMemcpyAsync(g.wgt.get(), weight, nnz * sizeof(int32_t), kind, ctx.stream));
-    }
+    load_csr(n, row_ptr, col_idx, weight, *opts, ctx, g);
+    const bool dev = opts->device_pointers != 0;
     InArr<double> xin;
     xin.init(ctx, x, n, dev);
     DevBuf<double> yd(ctx, n);
     laplacian_apply_csr(g, xin.p, yd.get(), ctx);
     copy_out(ctx, y, yd.get(), n, dev);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    return RSB_OK;
+  });
+}
+
+int rsb_amg_level(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                  const int32_t *weight, int32_t level, const rsb_opts *opts, int32_t *nlevels,
+                  int64_t *nrows, int64_t *nnz, int64_t *row_ptr_out, int64_t *col_out,
+                  int64_t *weight_out, int64_t *gid_out, int64_t *agg_out) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    if (!nlevels || !nrows || !nnz) fail(RSB_EINVAL, "nlevels/nrows/nnz is NULL");
+    if (col_out && (!row_ptr_out || !weight_out || !gid_out || !agg_out))
+      fail(RSB_EINVAL, "output arrays must all be given");
+    Ctx ctx;
+    DevCsr g;
+    load_csr(n, row_ptr, col_idx, weight, *opts, ctx, g);
+    CsrAmg t;
+    csr_amg_setup(g, t, ctx);
+    *nlevels = (int32_t)t.A.lv.size();
+    if (level < 0 || level >= *nlevels) fail(RSB_EINVAL, "level out of range");
+    const AmgLevelDev &Z = t.A.lv[level];
+    // host copies of the level (coarse levels: sliced ELL with separate words)
+    const int64_t rows = Z.n;
+    std::vector<int32_t> seg(rows), agg(rows), gid(rows), len(rows);
+    RSB_HIP(hipMemcpyAsync(seg.data(), Z.seg.get(), rows * 4, hipMemcpyDeviceToHost, ctx.stream));
+    RSB_HIP(hipMemcpyAsync(agg.data(), Z.agg.get(), rows * 4, hipMemcpyDeviceToHost, ctx.stream));
+    RSB_HIP(hipMemcpyAsync(gid.data(), Z.gid, rows * 4, hipMemcpyDeviceToHost, ctx.stream));
+    RSB_HIP(hipMemcpyAsync(len.data(), Z.rowlen.get(), rows * 4, hipMemcpyDeviceToHost,
+                           ctx.stream));
+    const int64_t nch = rows / 64;
+    std::vector<int64_t> cp(nch + 1);
+    const int64_t words = level == 0 ? t.L.words : Z.words;
+    std::vector<uint32_t> packed, w;
+    std::vector<int32_t> col;
+    RSB_HIP(hipMemcpyAsync(cp.data(), Z.mat.chunk_ptr, (nch + 1) * 8, hipMemcpyDeviceToHost,
+                           ctx.stream));
+    if (level == 0) {
+      packed.resize(std::max<int64_t>(words, 1));
+      RSB_HIP(hipMemcpyAsync(packed.data(), Z.mat.packed, words * 4, hipMemcpyDeviceToHost,
+                             ctx.stream));
+    } else {
+      col.resize(std::max<int64_t>(words, 1));
+      w.resize(std::max<int64_t>(words, 1));
+      RSB_HIP(hipMemcpyAsync(col.data(), Z.mat.col, words * 4, hipMemcpyDeviceToHost, ctx.stream));
+      RSB_HIP(hipMemcpyAsync(w.data(), Z.mat.wgt, words * 4, hipMemcpyDeviceToHost, ctx.stream));
+    }
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    int64_t nr = 0, nz = 0;
+    for (int64_t i = 0; i < rows; ++i)
+      if (seg[i] >= 0) {
+        if (i != nr) fail(RSB_EINTERNAL, "AMG level rows not contiguous");
+        ++nr;
+        nz += len[i];
+      }
+    *nrows = nr;
+    *nnz = nz;
+    if (!col_out) return RSB_OK;
+    int64_t k = 0;
+    for (int64_t i = 0; i < nr; ++i) {
+      row_ptr_out[i] = k;
+      const int64_t base = cp[i >> 6] + (i & 63), width = (cp[(i >> 6) + 1] - cp[i >> 6]) >> 6;
+      for (int64_t q = 0; q < width; ++q) {
+        const int64_t at = base + q * 64;
+        const int64_t c = level == 0 ? (int64_t)colw_col(packed[at]) : col[at];
+        const int64_t wt = level == 0 ? (int64_t)colw_wt(packed[at]) : (int64_t)w[at];
+        if (wt == 0) continue;
+        col_out[k] = c;
+        weight_out[k] = wt;
+        ++k;
+      }
+      gid_out[i] = gid[i];
+      agg_out[i] = agg[i];
+    }
+    row_ptr_out[nr] = k;
+    if (k != nz) fail(RSB_EINTERNAL, "AMG level row lengths disagree with slots");
+    return RSB_OK;
+  });
+}
+
+int rsb_amg_vcycle(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                   const int32_t *weight, const double *f, double *u, const rsb_opts *opts) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    if (!f || !u) fail(RSB_EINVAL, "bad arguments");
+    Ctx ctx;
+    DevCsr g;
+    load_csr(n, row_ptr, col_idx, weight, *opts, ctx, g);
+    CsrAmg t;
+    t.A.sigma = opts->amg_sigma;
+    t.A.nsmooth = opts->amg_smooth;
+    csr_amg_setup(g, t, ctx);
+    const bool dev = opts->device_pointers != 0;
+    InArr<double> fin;
+    fin.init(ctx, f, n, dev);
+    DevBuf<double> fl(ctx, t.L.nrows);
+    RSB_HIP(hipMemsetAsync(fl.get(), 0, fl.bytes(), ctx.stream));
+    RSB_HIP(hipMemcpyAsync(fl.get(), fin.p, n * sizeof(double), hipMemcpyDeviceToDevice,
+                           ctx.stream));
+    amg_vcycle(t.A, fl.get(), nullptr, ctx.stream);
+    copy_out(ctx, u, t.A.lv[0].u.get(), n, dev);
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     return RSB_OK;
   });

@@ -3,8 +3,10 @@
 //
 // Outer iteration: b <- b - (u0^T b) u0, b <- b / ||b||, solve L x = b, b <- x.
 // Inner solver: CG from x0 = 0 whose first search direction is the
-// unpreconditioned residual (the preconditioner is the identity here), with
-// the Polak-Ribiere ("flexible") beta.  The outer loop stops when a solve
+// unpreconditioned residual; later directions use the preconditioned
+// residual z = M r (the identity, or one aggregation-multigrid V-cycle with
+// the u0 component removed) and the flexible (Polak-Ribiere) beta
+// z_new^T (r_new - r_old) / z_old^T r_old.  The outer loop stops when a solve
 // needed a single CG step (b was an eigenvector, the stopping rule of
 // Sec. 7) or when the Rayleigh-quotient residual of b meets the tolerance,
 // or after max_outer iterations.  Every launch covers all segments of the
@@ -33,6 +35,9 @@ struct InvArgs {
   const int32_t *root;
   const int32_t *gid;
   double *U0, *B, *X, *R, *P0, *P1, *LP;
+  double *ROLD;             // previous residual (preconditioned CG)
+  const double *Z;          // V-cycle output M r (preconditioned CG)
+  int pre;                  // 1: AMG preconditioner
   double cg_tol, tol;
   int max_outer, cg_max_iter;
   int32_t *flags;           // [0] segments still running (CG or outer)
@@ -94,7 +99,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(InvArgs a) {
 
 // p_new = r + beta p_old (rows) and L p_new (gathers r and p_old); partial
 // sums of p^T L p.
-template <int RPT>
+// z = r (identity, or the first direction of a solve) or z = Z - c u0.
+template <int RPT, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_cg_a(InvArgs a, int it) {
   __shared__ double red[4];
   __shared__ double vals[1];
@@ -105,12 +111,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(InvArgs a, int it) {
   const double *Pold = (it & 1) ? a.P0 : a.P1;
   double *Pnew = (it & 1) ? a.P1 : a.P0;
   const double beta = S.cg_beta;
+  const bool use_z = PRE && S.cg_it > 0;
+  const double cz = S.cg_c;
   const TileRows<RPT> tr(b);
   double acc[1] = {0.0};
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int64_t row = tr.row[r];
-    const double pi = a.R[row] + beta * Pold[row];
+    const double zi = use_z ? a.Z[row] - cz * a.U0[row] : a.R[row];
+    const double pi = zi + beta * Pold[row];
     const int64_t c = row >> 6;
     const int lane = (int)(row & 63);
     const int64_t p = a.chunk_ptr[c];
@@ -127,8 +136,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(InvArgs a, int it) {
       double rj[kSlotGroup], pj[kSlotGroup];
 #pragma unroll
       for (int u = 0; u < kSlotGroup; ++u) {
-        rj[u] = a.R[colw_col(w[u])];
-        pj[u] = Pold[colw_col(w[u])];
+        const uint32_t j = colw_col(w[u]);
+        rj[u] = use_z ? a.Z[j] - cz * a.U0[j] : a.R[j];
+        pj[u] = Pold[j];
       }
 #pragma unroll
       for (int u = 0; u < kSlotGroup; ++u)
@@ -166,12 +176,41 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(InvArgs a, int it) {
     if (tr.ok[r]) {
       a.X[row] = xn;
       a.R[row] = rnew;
+      if (a.pre) a.ROLD[row] = rold;
       acc[0] += rnew * rnew;
       acc[1] += rnew * rold;
     }
   }
   block_reduce_into<2>(acc, red, vals, 2);
   write_partials(a, lb, vals, 2);
+}
+
+// Preconditioned CG, after the V-cycle Z = M r: partial sums of u0^T Z,
+// Z^T r, Z^T r_old, u0^T r and u0^T r_old (the u0 component of Z is removed
+// in the finisher's formulas and in the next direction).
+template <int RPT>
+__global__ __launch_bounds__(kBlock) void k_cg_z(InvArgs a) {
+  __shared__ double red[4 * 5];
+  __shared__ double vals[5];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active || S.cg_done) return;
+  const TileRows<RPT> tr(b);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    if (!tr.ok[r]) continue;
+    const int64_t row = tr.row[r];
+    const double z = a.Z[row], u = a.U0[row], rn = a.R[row], ro = a.ROLD[row];
+    acc[0] += u * z;
+    acc[1] += z * rn;
+    acc[2] += z * ro;
+    acc[3] += u * rn;
+    acc[4] += u * ro;
+  }
+  block_reduce_into<5>(acc, red, vals, 5);
+  write_partials(a, lb, vals, 5);
 }
 
 // After a solve: partial sums for the transform of the new b = x (c, s) and
@@ -231,11 +270,11 @@ __global__ __launch_bounds__(kBlock) void k_inv_res(InvArgs a) {
 }
 
 // Reductions and the per-segment logic that finishes each launch above.
-enum InvOp { OP_BEGIN, OP_CG_INIT, OP_CG_A, OP_CG_B, OP_EVAL, OP_RES };
+enum InvOp { OP_BEGIN, OP_CG_INIT, OP_CG_A, OP_CG_B, OP_CG_Z, OP_EVAL, OP_RES };
 
 template <int OP>
 __global__ __launch_bounds__(kBlock) void k_inv_reduce(InvArgs a) {
-  __shared__ double vals[4];
+  __shared__ double vals[5];
   const int g = blockIdx.x;
   const int s = a.grp[g].seg;
   const SegState S = a.st[s];
@@ -256,6 +295,10 @@ __global__ __launch_bounds__(kBlock) void k_inv_reduce(InvArgs a) {
     case OP_CG_B:
       if (!S.active || S.cg_done) return;
       nval = 2;
+      break;
+    case OP_CG_Z:
+      if (!S.active || S.cg_done) return;
+      nval = 5;
       break;
     default:
       if (!S.active) return;
@@ -278,6 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_inv_reduce(InvArgs a) {
     case OP_CG_INIT:
       W.rr = vals[0];
       W.cg_it = 0;
+      W.cg_c = 0.0;
       W.cg_done = (sqrt(vals[0]) <= a.cg_tol) ? 1 : 0;
       W.cg_beta = 0.0;
       break;
@@ -292,10 +336,22 @@ __global__ __launch_bounds__(kBlock) void k_inv_reduce(InvArgs a) {
       if (sqrt(rr) <= a.cg_tol || W.cg_it >= a.cg_max_iter) {
         W.cg_done = 1;
       } else {
-        W.cg_beta = (rr - vals[1]) / W.rr;
-        W.rr = rr;
+        if (!a.pre) {
+          W.cg_beta = (rr - vals[1]) / W.rr;
+          W.rr = rr;
+        }
         atomicAdd(&a.flags[0], 1);
       }
+      break;
+    }
+    case OP_CG_Z: {
+      // z = Z - c u0; z^T r and z^T r_old with the u0 part taken out
+      const double c = vals[0];
+      const double zr = vals[1] - c * vals[3];
+      const double zro = vals[2] - c * vals[4];
+      W.cg_c = c;
+      W.cg_beta = (zr - zro) / W.rr;
+      W.rr = zr;
       break;
     }
     case OP_EVAL: {
@@ -370,6 +426,8 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
   a.P0 = w + 4 * L.nrows;
   a.P1 = w + 5 * L.nrows;
   a.LP = w + 6 * L.nrows;
+  a.ROLD = w + 7 * L.nrows;
+  a.pre = (p.precond == RSB_PRECOND_AMG) ? 1 : 0;
   a.cg_tol = p.cg_tol;
   a.tol = p.tol;
   a.max_outer = p.max_outer;
@@ -379,6 +437,14 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
   a.seed = p.seed;
   const int nblk = L.nblk, ngrp = L.ngrp;
   hipStream_t s = ctx.stream;
+  AmgDev amg;
+  if (a.pre) {
+    amg.sigma = p.amg_sigma;
+    amg.nsmooth = p.amg_smooth;
+    amg_setup(L, C.root.get(), a.st, amg, ctx);
+    a.Z = amg.lv[0].u.get();
+    if (p.amg_levels) *p.amg_levels = std::max(*p.amg_levels, (int)amg.lv.size());
+  }
   k_inv_begin<RPT><<<nblk, kBlock, 0, s>>>(a);
   k_inv_reduce<OP_BEGIN><<<ngrp, kBlock, 0, s>>>(a);
   RSB_LAUNCHED();
@@ -398,10 +464,16 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
     auto chunk = [&]() {
       k_flag_reset<<<1, 1, 0, s>>>(a.flags);
       for (int it = 0; it < kCgChunk; ++it) {
-        k_cg_a<RPT><<<nblk, kBlock, 0, s>>>(a, it);
+        if (a.pre) k_cg_a<RPT, true><<<nblk, kBlock, 0, s>>>(a, it);
+        else k_cg_a<RPT, false><<<nblk, kBlock, 0, s>>>(a, it);
         k_inv_reduce<OP_CG_A><<<ngrp, kBlock, 0, s>>>(a);
         k_cg_b<RPT><<<nblk, kBlock, 0, s>>>(a, it);
         k_inv_reduce<OP_CG_B><<<ngrp, kBlock, 0, s>>>(a);
+        if (a.pre) {
+          amg_vcycle(amg, a.R, a.st, s);
+          k_cg_z<RPT><<<nblk, kBlock, 0, s>>>(a);
+          k_inv_reduce<OP_CG_Z><<<ngrp, kBlock, 0, s>>>(a);
+        }
       }
     };
     if (use_graph) {
@@ -451,7 +523,7 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
 
 }  // namespace
 
-size_t inverse_workspace_bytes(int64_t rows) { return (size_t)rows * 7 * sizeof(double); }
+size_t inverse_workspace_bytes(int64_t rows) { return (size_t)rows * 8 * sizeof(double); }
 
 int64_t inverse_level(const LevelView &L, CompDev &C, SolveDev &S, const InverseParams &p,
                       void *work, double *y64_out, bool use_graph, Ctx &ctx) {

@@ -82,6 +82,7 @@ struct SegState {
   int32_t cg_it;        // CG steps of the current solve
   double rr;            // CG: r^T r
   double cg_alpha, cg_beta;
+  double cg_c;          // CG with AMG: u0 component removed from the preconditioned residual
   int32_t cg_done;      // CG solve finished
   int32_t j0;           // first Lanczos step of the current cycle (1, or nk + 1 after a thick restart)
   int32_t nk;           // Ritz pairs kept at the head of the current cycle's basis
@@ -214,6 +215,48 @@ template <typename T>
 int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p,
                       void *work, double *y64_out, Ctx &ctx);
 
+// Aggregation multigrid hierarchy of a bisection level (preconditioner of
+// the inverse-iteration solves).  Level 0 aliases the level's packed sliced
+// ELL; coarse levels own sliced-ELL column and weight words.
+struct MatDevHost {
+  const int64_t *chunk_ptr = nullptr;
+  const uint32_t *packed = nullptr;  // level 0
+  const int32_t *col = nullptr;      // coarse levels
+  const uint32_t *wgt = nullptr;
+};
+
+struct AmgLevelDev {
+  int64_t n = 0;                 // rows (coarse levels: padded to a multiple of 64)
+  int64_t words = 0;             // slots of a coarse level
+  MatDevHost mat;
+  const int32_t *gid = nullptr;  // global id carried by every row
+  DevBuf<int32_t> gid_own;       // coarse levels
+  DevBuf<int64_t> chunk_ptr;     // coarse levels
+  DevBuf<int32_t> col;
+  DevBuf<uint32_t> wgt;
+  DevBuf<int32_t> seg;           // segment of a live row, -1 otherwise
+  DevBuf<int32_t> rowlen;        // nonzero slots of the row
+  DevBuf<double> dinv;           // 1 / L_ii (0 for an empty row)
+  DevBuf<int32_t> agg;           // row of the next level (-1: none)
+  DevBuf<int32_t> mem;           // coarse levels: the 1 or 2 rows collapsed into each row
+  DevBuf<double> f, u, r;        // V-cycle right side (coarse levels), correction, residual
+};
+
+struct AmgDev {
+  std::vector<AmgLevelDev> lv;
+  double sigma = 2.0 / 3.0;      // damped-Jacobi weight
+  int nsmooth = 1;               // Jacobi steps per smoothing phase
+};
+
+// Hierarchy of every segment with a component to cut (rows with
+// root == that segment's strad); d_st: the solver's segment states.
+void amg_setup(const LevelView &L, const int32_t *d_root, const SegState *d_st, AmgDev &A,
+               Ctx &ctx);
+// u = M f into A.lv[0].u (zero on rows that take no part) for the rows of
+// running segments (d_st == nullptr:
+// all live rows).  Launches only; graph-capturable.
+void amg_vcycle(AmgDev &A, const double *d_f, const SegState *d_st, hipStream_t s);
+
 // Inverse iteration with CG on every segment with a component to cut.
 struct InverseParams {
   int max_outer;
@@ -221,6 +264,10 @@ struct InverseParams {
   double cg_tol;
   double tol;
   uint64_t seed;
+  int precond;           // RSB_PRECOND_NONE or RSB_PRECOND_AMG
+  double amg_sigma;
+  int amg_smooth;
+  int *amg_levels;       // out (may be null): levels of the largest hierarchy
 };
 size_t inverse_workspace_bytes(int64_t rows);
 int64_t inverse_level(const LevelView &L, CompDev &C, SolveDev &S, const InverseParams &p,

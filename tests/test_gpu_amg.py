@@ -1,0 +1,123 @@
+"""GPU parity of the aggregation multigrid preconditioner (paper Sec. 7,
+Alg. 3) and of AMG-preconditioned inverse iteration, through the C ABI,
+against the CPU oracle.
+
+The hierarchy is integer work (matching decisions, aggregate numbering,
+summed weights): every level must be bit-exact.  The V-cycle is FP64 with the
+same operation order per row (sums in ascending column order); only fused
+multiply-adds differ, so it must agree to 1e-11 of its magnitude.  Fiedler
+pairs match the oracle as for plain inverse iteration; partitions on boxes
+with a unique longest axis are identical.
+"""
+import numpy as np
+import pytest
+
+import meshgen as mg
+import paper_2606_14659_amd as rsb
+
+pytestmark = pytest.mark.gpu
+
+MESHES = {
+    "holes": lambda: mg.uniform_holes(mg.box_hex(23, 17, 9), 0.07, 3).ids,
+    "quad": lambda: mg.uniform_holes(mg.box_quad(40, 33), 0.1, 4).ids,
+    "renum": lambda: mg.shuffle_elements(mg.renumber_vertices(
+        mg.uniform_holes(mg.box_hex(19, 11, 13), 0.05, 6), 7), 8).ids,
+    "clustered": lambda: mg.clustered_holes(mg.box_hex(30, 26, 22), 0.1, 9).ids,
+    "box48x32x24-holes": lambda: mg.uniform_holes(mg.box_hex(48, 32, 24), 0.05, 7).ids,
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_amg_hierarchy_bit_exact(orc, name):
+    ids = MESHES[name]()
+    rp, col, w = orc.dual_graph(ids)
+    print(f"amg hierarchy {name} n={len(ids)}", flush=True)
+    first = orc.amg_level(rp, col, w, 0)
+    g0 = rsb.amg_level(rp, col, w, 0)
+    assert g0["nlevels"] == first["nlevels"] >= 3
+    for l in range(first["nlevels"]):
+        o = orc.amg_level(rp, col, w, l)
+        g = rsb.amg_level(rp, col, w, l)
+        for k in ("row_ptr", "col", "weight", "gid", "agg"):
+            assert np.array_equal(g[k], o[k]), (l, k)
+
+
+@pytest.mark.parametrize("sigma,nu", [(2.0 / 3.0, 1), (0.9, 2), (0.5, 0)])
+@pytest.mark.parametrize("device", [False, True])
+def test_amg_vcycle_matches_oracle(orc, sigma, nu, device):
+    ids = MESHES["clustered"]()
+    rp, col, w = orc.dual_graph(ids)
+    f = np.random.default_rng(17).standard_normal(len(ids))
+    uo = orc.amg_vcycle(rp, col, w, f, sigma=sigma, nsmooth=nu)
+    if device:
+        import torch
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a, dtype=dt)).cuda()
+        ug = rsb.amg_vcycle(t(rp, np.int64), t(col, np.int32), t(w, np.int32), t(f, np.float64),
+                            device=True, amg_sigma=sigma, amg_smooth=nu).cpu().numpy()
+    else:
+        ug = rsb.amg_vcycle(rp, col, w, f, amg_sigma=sigma, amg_smooth=nu)
+    assert np.abs(ug - uo).max() <= 1e-11 * np.abs(uo).max()
+
+
+@pytest.mark.parametrize("name", ["holes", "quad", "renum"])
+def test_amg_inverse_fiedler_matches_oracle(orc, name):
+    ids = MESHES[name]()
+    kw = dict(method="inverse_cg", inv_precond="amg", tol=1e-9, inv_max_outer=400)
+    st, lam, y, stats = rsb.fiedler(ids, **kw)
+    ost, olam, oy, oinfo = orc.fiedler(ids, **kw)
+    lst, llam, ly, _ = orc.fiedler(ids, tol=1e-10)
+    print(f"{name}: gpu cg {stats['segment_steps']} levels {stats['amg_levels']}; "
+          f"oracle cg {oinfo['cg_iters']} levels {oinfo['amg_levels']}", flush=True)
+    assert st == ost == 0
+    assert stats["amg_levels"] == oinfo["amg_levels"]
+    assert abs(lam - llam) <= 1e-8 * llam
+    assert abs(abs(float(y @ ly)) - 1) < 1e-6
+    # same algorithm on both sides: CG step counts agree up to rounding
+    assert abs(stats["segment_steps"] - oinfo["cg_iters"]) <= max(3, 0.05 * oinfo["cg_iters"])
+
+
+def test_amg_reduces_cg_steps():
+    ids = MESHES["box48x32x24-holes"]()
+    kw = dict(method="inverse_cg", tol=1e-6, inv_max_outer=100)
+    st0, lam0, _, s0 = rsb.fiedler(ids, **kw)
+    st1, lam1, _, s1 = rsb.fiedler(ids, inv_precond="amg", **kw)
+    print(f"cg steps plain {s0['segment_steps']} amg {s1['segment_steps']}", flush=True)
+    assert st0 == st1 == 0
+    assert abs(lam0 - lam1) <= 1e-8 * lam0
+    assert s1["segment_steps"] < 0.5 * s0["segment_steps"]
+
+
+@pytest.mark.parametrize("dims,graph,nparts", [((24, 20, 18), "weighted", 4),
+                                              ((30, 14, 9), "face", 6)])
+def test_amg_partition_identical_on_boxes(orc, dims, graph, nparts):
+    mesh = mg.box_hex(*dims)
+    kw = dict(graph=graph, method="inverse_cg", inv_precond="amg", tol=1e-8, inv_max_outer=400)
+    print(f"amg partition {dims} {graph} {nparts}", flush=True)
+    st, part, stats = rsb.partition(mesh.ids, nparts, **kw)
+    ost, opart, _ = orc.partition(mesh.ids, nparts, **kw)
+    assert st == ost == 0
+    assert np.array_equal(part, opart)
+
+
+def test_amg_unbatched_equals_batched():
+    ids = MESHES["holes"]()
+    kw = dict(method="inverse_cg", inv_precond="amg", tol=1e-8, inv_max_outer=300)
+    st1, p1, s1 = rsb.partition(ids, 12, **kw)
+    st2, p2, s2 = rsb.partition(ids, 12, batched=0, **kw)
+    assert st1 == st2
+    assert np.array_equal(p1, p2)
+
+
+def test_amg_disconnected_segment(orc):
+    # Two boxes: A (600 elements) lies wholly on the low side; B is cut by
+    # its own Fiedler vector two slabs from its end.  Rows of A share B's
+    # segment but take no part in B's hierarchy or V-cycles.
+    a = mg.box_hex(20, 6, 5)
+    b = mg.box_hex(24, 6, 5)
+    ids = np.concatenate([a.ids, b.ids + 100_000])
+    kw = dict(graph="face", method="inverse_cg", inv_precond="amg", tol=1e-8, inv_max_outer=400)
+    st, part, _ = rsb.partition(ids, 2, **kw)
+    ost, opart, _ = orc.partition(ids, 2, **kw)
+    assert st == ost == 2
+    assert np.array_equal(part, opart)
+    assert np.all(part[:600] == 0) and np.sum(part[600:] == 0) == 60

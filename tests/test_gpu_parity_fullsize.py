@@ -6,7 +6,9 @@ properties that hold at any size.
 
 C1 16^3 cube, face graph: one 100-step Lanczos cycle and RSB to 8.
 C2 128x128x64, 5% holes: dual graph bit-exact; Fiedler pair by Lanczos
-   (FP64) and by inverse iteration, residual checked in FP64 on the CPU.
+   (FP64) and by inverse iteration (plain CG and AMG-preconditioned CG),
+   residual checked in FP64 on the CPU; the AMG hierarchy's first coarse
+   level against its definition on sampled rows.
 C3/C4 256x256x64, 3% holes: RSB to 1024 in FP64 and mixed precision.
 C5a 256x256x128, 10% clustered holes, renumbered ids: RSB to 4096 as the
    benchmark runs it.
@@ -130,6 +132,63 @@ def test_c2_fiedler_fp64(orc, c2, method, keep, tol):
         lz, inv = C2_LAMBDA["lanczos"], C2_LAMBDA["inverse_cg"]
         assert lz <= inv * (1 + 1e-9)
         assert inv - lz <= 1e-3 * lz
+
+
+def test_c2_amg_hierarchy_sampled(orc, c2):
+    # full size: the first coarse level against its definition on sampled
+    # rows (members from the aggregate map, weights summed over the edges
+    # between members and other aggregates), and the hierarchy's invariants
+    rp, col, w = orc.dual_graph(c2.ids)
+    l0 = rsb.amg_level(rp, col, w, 0)
+    l1 = rsb.amg_level(rp, col, w, 1)
+    n0, n1 = len(rp) - 1, len(l1["gid"])
+    agg = l0["agg"]
+    assert l0["nlevels"] >= 10 and 10 * n1 <= 9 * n0
+    counts = np.bincount(agg, minlength=n1)
+    assert counts.min() >= 1 and counts.max() <= 2
+    first = np.full(n1, n0)
+    np.minimum.at(first, agg, np.arange(n0))
+    assert np.all(np.diff(first) > 0)
+    members = {}
+    for i in np.flatnonzero(np.isin(agg, np.random.default_rng(3).choice(n1, 400, replace=False))):
+        members.setdefault(int(agg[i]), []).append(int(i))
+    for I, mem in members.items():
+        acc = {}
+        for i in mem:
+            for p in range(rp[i], rp[i + 1]):
+                J = int(agg[col[p]])
+                if J != I:
+                    acc[J] = acc.get(J, 0) + int(w[p])
+        got = dict(zip(l1["col"][l1["row_ptr"][I]:l1["row_ptr"][I + 1]].tolist(),
+                       l1["weight"][l1["row_ptr"][I]:l1["row_ptr"][I + 1]].tolist()))
+        assert got == acc, I
+        assert l1["gid"][I] == min(mem)
+        if len(mem) == 2:
+            assert mem[1] in col[rp[mem[0]]:rp[mem[0] + 1]]
+    # Galerkin products keep the total weight of the edges between aggregates
+    cut = w[agg[np.repeat(np.arange(n0), np.diff(rp))] != agg[col]].sum()
+    assert l1["weight"].sum() == cut
+
+
+def test_c2_inverse_amg(orc, c2):
+    import time
+    kw = dict(method="inverse_cg", tol=1e-3, inv_max_outer=100)
+    t0 = time.perf_counter()
+    st0, lam0, y0, s0 = rsb.fiedler(c2.ids, **kw)
+    t1 = time.perf_counter()
+    st, lam, y, stats = rsb.fiedler(c2.ids, inv_precond="amg", **kw)
+    t2 = time.perf_counter()
+    print(f"C2 inverse iteration: plain {s0['segment_steps']} CG steps {1e3 * (t1 - t0):.0f} ms; "
+          f"AMG ({stats['amg_levels']} levels) {stats['segment_steps']} CG steps "
+          f"{1e3 * (t2 - t1):.0f} ms; lambda {lam0:.10g} / {lam:.10g}", flush=True)
+    assert st == 0
+    rp, col, w = orc.dual_graph(c2.ids)
+    ly = orc.laplacian_apply(rp, col, w, y)
+    rho = float(y @ ly)
+    assert abs(np.linalg.norm(y) - 1.0) < 1e-12
+    assert abs(lam - rho) <= 1e-12 * rho
+    assert np.linalg.norm(ly - rho * y) <= 1.01 * 1e-3 * rho
+    assert stats["segment_steps"] < 0.5 * s0["segment_steps"]
 
 
 @pytest.fixture(scope="module")

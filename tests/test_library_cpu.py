@@ -39,6 +39,7 @@ def test_struct_sizes_match():
     assert rsb.lib().rsb_opts_init(C.byref(o)) == 0
     assert o.struct_size == C.sizeof(rsb.Opts)
     assert o.lanczos_m == 100 and o.max_restarts == 50 and o.seed == 20261203
+    assert o.inv_precond == 0 and o.amg_smooth == 1 and abs(o.amg_sigma - 2.0 / 3.0) < 1e-15
     assert rsb.lib().rsb_opts_init(None) == rsb.EINVAL
 
 
@@ -56,7 +57,9 @@ def test_bad_options_rejected_before_any_device_call():
     for field, value in (("struct_size", 4), ("graph", 7), ("lanczos_m", 0), ("lanczos_m", 251),
                          ("tol", 0.0), ("cg_full_projection", 1), ("precision", 5),
                          ("rows_per_thread", 3), ("rows_per_thread", 16), ("autotune", 3),
-                         ("lanczos_keep", -1), ("lanczos_keep", 17), ("lanczos_keep", 100)):
+                         ("lanczos_keep", -1), ("lanczos_keep", 17), ("lanczos_keep", 100),
+                         ("inv_precond", 2), ("inv_precond", -1), ("amg_smooth", -1),
+                         ("amg_smooth", 17), ("amg_sigma", 0.0), ("amg_sigma", 2.0)):
         oo = rsb.Opts.from_buffer_copy(o)
         setattr(oo, field, value)
         part = np.zeros(2, dtype=np.int32)
