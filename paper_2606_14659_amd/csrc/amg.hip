@@ -29,7 +29,11 @@
 // (the printed algorithm subtracts L u from an already updated residual
 // after the coarse correction; the true residual is used here).  A segment's
 // coarsest level runs only the first part (smoothing).  Every launch covers
-// all segments; rows of segments whose solve has ended are skipped.
+// all segments; rows of segments whose solve has ended are skipped.  Each
+// smoothing step is one launch: the Jacobi update of a neighbour (and the
+// coarse correction before the first post-smoothing step) is formed on the
+// fly where the residual gathers it, and results alternate between two
+// buffers per level.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -79,6 +83,35 @@ struct RowSlots {
     }
   }
 };
+
+// sum_j w_ij (u_i - v(j)) over the row's slots in slot (ascending column)
+// order, as the oracle sums it.  Slots are taken in groups: the group's
+// column words first, then its gathers, so that they are in flight
+// together.  Padding slots gather the row itself and add nothing.
+template <bool PACKED, typename V>
+__device__ inline double row_diff_sum(const MatDev &m, int64_t i, double ui, V v) {
+  constexpr int G = 8;
+  const RowSlots<PACKED> rs(m, i);
+  double acc = 0.0;
+  for (int k0 = 0; k0 < rs.width; k0 += G) {
+    int64_t j[G];
+    uint32_t w[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      j[t] = i;
+      w[t] = 0;
+      if (k0 + t < rs.width) rs.get(k0 + t, j[t], w[t]);
+      if (w[t] == 0) j[t] = i;
+    }
+    double x[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) x[t] = v(j[t]);
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+      if (w[t]) acc += (double)w[t] * (ui - x[t]);
+  }
+  return acc;
+}
 
 __device__ inline uint32_t pair_priority(int64_t ga, int64_t gb) {
   const uint64_t lo = (uint64_t)(ga < gb ? ga : gb), hi = (uint64_t)(ga < gb ? gb : ga);
@@ -189,23 +222,44 @@ __global__ void k_amg_accept(const int32_t *__restrict__ prop, int64_t n,
 }
 
 // Unmatched rows become single; per-segment counts of live rows, coarse
-// rows and pairs too wide for the coarse-row kernel.
-__global__ void k_amg_count(const int32_t *__restrict__ seg, const int32_t *__restrict__ rowlen,
-                            int64_t n, int32_t *__restrict__ mate, int32_t *__restrict__ nrow_s,
-                            int32_t *__restrict__ ncoarse_s, int32_t *__restrict__ wide_s) {
+// rows and pairs too wide for the coarse-row kernel.  A wavefront whose
+// rows all belong to one segment adds its totals with one atomic each.
+__global__ __launch_bounds__(kBlock) void k_amg_count(
+    const int32_t *__restrict__ seg, const int32_t *__restrict__ rowlen, int64_t n,
+    int32_t *__restrict__ mate, int32_t *__restrict__ nrow_s, int32_t *__restrict__ ncoarse_s,
+    int32_t *__restrict__ wide_s) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t s = seg[i];
-  if (s < 0) return;
-  int32_t p = mate[i];
-  if (p == -1) {
-    p = (int32_t)i;
-    mate[i] = p;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t s = i < n ? seg[i] : -1;
+  int live = 0, lead = 0, wide = 0;
+  if (s >= 0) {
+    int32_t p = mate[i];
+    if (p == -1) {
+      p = (int32_t)i;
+      mate[i] = p;
+    }
+    live = 1;
+    if (p >= i) {
+      lead = 1;
+      wide = (rowlen[i] + (p != i ? rowlen[p] : 0) > kAmgCandCap) ? 1 : 0;
+    }
   }
-  atomicAdd(&nrow_s[s], 1);
-  if (p >= i) {
-    atomicAdd(&ncoarse_s[s], 1);
-    if (rowlen[i] + (p != i ? rowlen[p] : 0) > kAmgCandCap) atomicOr(&wide_s[s], 1);
+  const uint64_t act = __ballot(s >= 0);
+  if (act == 0) return;
+  const int first = __ffsll((unsigned long long)act) - 1;
+  const int32_t s0 = __shfl(s, first, kWave);
+  const bool uniform = __ballot(s >= 0 && s != s0) == 0;
+  if (uniform) {
+    const int nl = wave_sum_i(live), nc = wave_sum_i(lead), nw = wave_sum_i(wide);
+    if (lane == first) {
+      atomicAdd(&nrow_s[s0], nl);
+      atomicAdd(&ncoarse_s[s0], nc);
+      if (nw) atomicOr(&wide_s[s0], 1);
+    }
+  } else if (s >= 0) {
+    atomicAdd(&nrow_s[s], live);
+    if (lead) atomicAdd(&ncoarse_s[s], 1);
+    if (wide) atomicOr(&wide_s[s], 1);
   }
 }
 
@@ -381,48 +435,40 @@ __global__ void k_amg_pad_rows(int64_t n1, int64_t n1pad, int32_t *__restrict__ 
 // V-cycle kernels (one thread per row of a level)
 // ---------------------------------------------------------------------------
 
-// u = sigma D f
-__global__ void k_vc_first(const int32_t *__restrict__ seg, const SegState *__restrict__ st,
-                           const double *__restrict__ dinv, const double *__restrict__ f,
-                           double sigma, int64_t n, double *__restrict__ u) {
+// Pre-smoothing, first step: u = sigma D f and r = f - L u, the neighbours'
+// u_j = sigma D_j f_j formed from f_j on the fly.
+template <bool PACKED>
+__global__ void k_vc_pre0(MatDev m, const int32_t *__restrict__ seg,
+                          const SegState *__restrict__ st, const double *__restrict__ dinv,
+                          const double *__restrict__ f, double sigma, int64_t n,
+                          double *__restrict__ u_out, double *__restrict__ r_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (!seg_running(st, seg[i])) return;
-  u[i] = sigma * dinv[i] * f[i];
+  const double fi = f[i];
+  const double ui = sigma * dinv[i] * fi;
+  const double acc =
+      row_diff_sum<PACKED>(m, i, ui, [&](int64_t j) { return sigma * dinv[j] * f[j]; });
+  u_out[i] = ui;
+  r_out[i] = fi - acc;
 }
 
-// r = f - L u on the rows of running segments (POST: only rows whose
-// segment continues below this level)
-template <bool PACKED, bool POST>
-__global__ void k_vc_resid(MatDev m, const int32_t *__restrict__ seg,
-                           const int32_t *__restrict__ agg, const SegState *__restrict__ st,
-                           const double *__restrict__ f, const double *__restrict__ u, int64_t n,
-                           double *__restrict__ r) {
+// Pre-smoothing step: u' = u + sigma D r and r' = f - L u' (neighbours' u'
+// formed on the fly; new values go to the other buffers).
+template <bool PACKED>
+__global__ void k_vc_pre(MatDev m, const int32_t *__restrict__ seg,
+                         const SegState *__restrict__ st, const double *__restrict__ dinv,
+                         const double *__restrict__ f, const double *__restrict__ u_in,
+                         const double *__restrict__ r_in, double sigma, int64_t n,
+                         double *__restrict__ u_out, double *__restrict__ r_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (!seg_running(st, seg[i]) || (POST && agg[i] < 0)) return;
-  const double ui = u[i];
-  double s = 0.0;
-  RowSlots<PACKED> rs(m, i);
-  for (int k = 0; k < rs.width; ++k) {
-    int64_t j;
-    uint32_t w;
-    rs.get(k, j, w);
-    if (w) s += (double)w * (ui - u[j]);
-  }
-  r[i] = f[i] - s;
-}
-
-// u += sigma D r
-template <bool POST>
-__global__ void k_vc_jacobi(const int32_t *__restrict__ seg, const int32_t *__restrict__ agg,
-                            const SegState *__restrict__ st, const double *__restrict__ dinv,
-                            const double *__restrict__ r, double sigma, int64_t n,
-                            double *__restrict__ u) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (!seg_running(st, seg[i]) || (POST && agg[i] < 0)) return;
-  u[i] += sigma * dinv[i] * r[i];
+  if (!seg_running(st, seg[i])) return;
+  const double ui = u_in[i] + sigma * dinv[i] * r_in[i];
+  const double acc = row_diff_sum<PACKED>(
+      m, i, ui, [&](int64_t j) { return u_in[j] + sigma * dinv[j] * r_in[j]; });
+  u_out[i] = ui;
+  r_out[i] = f[i] - acc;
 }
 
 // f_c = J^T r (coarse rows)
@@ -436,7 +482,7 @@ __global__ void k_vc_restrict(const int32_t *__restrict__ seg1, const int32_t *_
   f1[I] = b >= 0 ? r[a] + r[b] : r[a];
 }
 
-// u += J e_c
+// u += J e_c in place (no smoothing steps after the coarse correction)
 __global__ void k_vc_prolong(const int32_t *__restrict__ seg, const int32_t *__restrict__ agg,
                              const SegState *__restrict__ st, const double *__restrict__ e1,
                              int64_t n, double *__restrict__ u) {
@@ -444,6 +490,32 @@ __global__ void k_vc_prolong(const int32_t *__restrict__ seg, const int32_t *__r
   if (i >= n) return;
   if (!seg_running(st, seg[i]) || agg[i] < 0) return;
   u[i] += e1[agg[i]];
+}
+
+// Post-smoothing step: r = f - L u, u' = u + sigma D r; with PROLONG the
+// coarse correction u += J e_c is applied first (to the row and, on the
+// fly, to its neighbours).  Rows whose segment stopped coarsening at this
+// level keep u (copied to the output buffer).
+template <bool PACKED, bool PROLONG>
+__global__ void k_vc_post(MatDev m, const int32_t *__restrict__ seg,
+                          const int32_t *__restrict__ agg, const SegState *__restrict__ st,
+                          const double *__restrict__ dinv, const double *__restrict__ f,
+                          const double *__restrict__ u_in, const double *__restrict__ e1,
+                          double sigma, int64_t n, double *__restrict__ u_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (!seg_running(st, seg[i])) return;
+  const int32_t ai = agg[i];
+  if (ai < 0) {
+    u_out[i] = u_in[i];
+    return;
+  }
+  const double ui = PROLONG ? u_in[i] + e1[ai] : u_in[i];
+  // (neighbours of a row whose segment continues have an aggregate)
+  const double acc = row_diff_sum<PACKED>(
+      m, i, ui, [&](int64_t j) { return PROLONG ? u_in[j] + e1[agg[j]] : u_in[j]; });
+  const double ri = f[i] - acc;
+  u_out[i] = ui + sigma * dinv[i] * ri;
 }
 
 }  // namespace
@@ -469,12 +541,15 @@ void amg_setup(const LevelView &L, const int32_t *d_root, const SegState *d_st, 
     z.dinv.alloc(ctx, std::max<int64_t>(z.n, 1));
     z.agg.alloc(ctx, std::max<int64_t>(z.n, 1));
     z.u.alloc(ctx, std::max<int64_t>(z.n, 1));
+    z.u2.alloc(ctx, std::max<int64_t>(z.n, 1));
     z.r.alloc(ctx, std::max<int64_t>(z.n, 1));
+    z.r2.alloc(ctx, std::max<int64_t>(z.n, 1));
     if (z.n > 0) {
       // the cycle writes only live rows: the level-0 correction is zero on
       // every other row (other components, padding) for its callers
       k_amg_fill<<<grid_for(z.n, kBlock), kBlock, 0, s>>>(z.seg.get(), z.n, -1);
       k_amg_zero<<<grid_for(z.n, kBlock), kBlock, 0, s>>>(z.u.get(), z.n);
+      k_amg_zero<<<grid_for(z.n, kBlock), kBlock, 0, s>>>(z.u2.get(), z.n);
       RSB_LAUNCHED();
     }
     if (L.nblk > 0) {
@@ -540,7 +615,9 @@ void amg_setup(const LevelView &L, const int32_t *d_root, const SegState *d_st, 
     C.mem.alloc(ctx, 2 * n1pad);
     C.f.alloc(ctx, n1pad);
     C.u.alloc(ctx, n1pad);
+    C.u2.alloc(ctx, n1pad);
     C.r.alloc(ctx, n1pad);
+    C.r2.alloc(ctx, n1pad);
     k_amg_link<<<g, kBlock, 0, s>>>(F.seg.get(), F.gid, mate.get(), cont.get(), cidx.get(), n,
                                     F.agg.get(), C.mem.get(), C.gid_own.get(), C.seg.get());
     if (n1pad > n1)
@@ -601,54 +678,75 @@ void amg_setup(const LevelView &L, const int32_t *d_root, const SegState *d_st, 
 
 namespace {
 
-template <bool PACKED>
-void vc_resid(const AmgLevelDev &Z, const SegState *st, const double *f, bool post, hipStream_t s) {
-  MatDev m{Z.mat.chunk_ptr, Z.mat.packed, Z.mat.col, Z.mat.wgt};
-  const unsigned g = grid_for(Z.n, kBlock);
-  if (post)
-    k_vc_resid<PACKED, true><<<g, kBlock, 0, s>>>(m, Z.seg.get(), Z.agg.get(), st, f, Z.u.get(),
-                                                  Z.n, Z.r.get());
-  else
-    k_vc_resid<PACKED, false><<<g, kBlock, 0, s>>>(m, Z.seg.get(), Z.agg.get(), st, f, Z.u.get(),
-                                                   Z.n, Z.r.get());
-}
-
-void vc_level(AmgDev &A, size_t l, const double *f, const SegState *st, hipStream_t s) {
+// Launches of one level (and, recursively, the levels below).  Returns the
+// buffer (0 or 1) that holds the level's result u.
+int vc_level(AmgDev &A, size_t l, const double *f, const SegState *st, hipStream_t s) {
   AmgLevelDev &Z = A.lv[l];
-  if (Z.n == 0) return;
   const unsigned g = grid_for(Z.n, kBlock);
   const bool packed = (l == 0);
-  auto resid = [&](bool post) {
-    if (packed) vc_resid<true>(Z, st, f, post, s);
-    else vc_resid<false>(Z, st, f, post, s);
-  };
-  k_vc_first<<<g, kBlock, 0, s>>>(Z.seg.get(), st, Z.dinv.get(), f, A.sigma, Z.n, Z.u.get());
-  resid(false);
-  for (int k = 0; k < A.nsmooth; ++k) {
-    k_vc_jacobi<false><<<g, kBlock, 0, s>>>(Z.seg.get(), Z.agg.get(), st, Z.dinv.get(), Z.r.get(),
-                                            A.sigma, Z.n, Z.u.get());
-    resid(false);
+  MatDev m{Z.mat.chunk_ptr, Z.mat.packed, Z.mat.col, Z.mat.wgt};
+  double *u[2] = {Z.u.get(), Z.u2.get()};
+  double *r[2] = {Z.r.get(), Z.r2.get()};
+  const double sg = A.sigma;
+  if (packed)
+    k_vc_pre0<true><<<g, kBlock, 0, s>>>(m, Z.seg.get(), st, Z.dinv.get(), f, sg, Z.n, u[0], r[0]);
+  else
+    k_vc_pre0<false><<<g, kBlock, 0, s>>>(m, Z.seg.get(), st, Z.dinv.get(), f, sg, Z.n, u[0],
+                                          r[0]);
+  int cur = 0;
+  for (int k = 0; k < A.nsmooth; ++k, cur ^= 1) {
+    if (packed)
+      k_vc_pre<true><<<g, kBlock, 0, s>>>(m, Z.seg.get(), st, Z.dinv.get(), f, u[cur], r[cur],
+                                          sg, Z.n, u[cur ^ 1], r[cur ^ 1]);
+    else
+      k_vc_pre<false><<<g, kBlock, 0, s>>>(m, Z.seg.get(), st, Z.dinv.get(), f, u[cur], r[cur],
+                                           sg, Z.n, u[cur ^ 1], r[cur ^ 1]);
   }
-  if (l + 1 < A.lv.size()) {
-    AmgLevelDev &C = A.lv[l + 1];
-    k_vc_restrict<<<grid_for(C.n, kBlock), kBlock, 0, s>>>(C.seg.get(), C.mem.get(), st,
-                                                           Z.r.get(), C.n, C.f.get());
-    vc_level(A, l + 1, C.f.get(), st, s);
-    k_vc_prolong<<<g, kBlock, 0, s>>>(Z.seg.get(), Z.agg.get(), st, C.u.get(), Z.n, Z.u.get());
-    for (int k = 0; k < A.nsmooth; ++k) {
-      resid(true);
-      k_vc_jacobi<true><<<g, kBlock, 0, s>>>(Z.seg.get(), Z.agg.get(), st, Z.dinv.get(),
-                                             Z.r.get(), A.sigma, Z.n, Z.u.get());
-    }
+  if (l + 1 >= A.lv.size()) return cur;
+  AmgLevelDev &C = A.lv[l + 1];
+  k_vc_restrict<<<grid_for(C.n, kBlock), kBlock, 0, s>>>(C.seg.get(), C.mem.get(), st, r[cur],
+                                                         C.n, C.f.get());
+  const int cb = vc_level(A, l + 1, C.f.get(), st, s);
+  const double *e1 = cb ? C.u2.get() : C.u.get();
+  if (A.nsmooth == 0) {
+    k_vc_prolong<<<g, kBlock, 0, s>>>(Z.seg.get(), Z.agg.get(), st, e1, Z.n, u[cur]);
+    return cur;
   }
+  for (int k = 0; k < A.nsmooth; ++k, cur ^= 1) {
+    const double *ui = u[cur];
+    double *uo = u[cur ^ 1];
+    if (packed && k == 0)
+      k_vc_post<true, true><<<g, kBlock, 0, s>>>(m, Z.seg.get(), Z.agg.get(), st, Z.dinv.get(), f,
+                                                 ui, e1, sg, Z.n, uo);
+    else if (packed)
+      k_vc_post<true, false><<<g, kBlock, 0, s>>>(m, Z.seg.get(), Z.agg.get(), st, Z.dinv.get(),
+                                                  f, ui, e1, sg, Z.n, uo);
+    else if (k == 0)
+      k_vc_post<false, true><<<g, kBlock, 0, s>>>(m, Z.seg.get(), Z.agg.get(), st, Z.dinv.get(),
+                                                  f, ui, e1, sg, Z.n, uo);
+    else
+      k_vc_post<false, false><<<g, kBlock, 0, s>>>(m, Z.seg.get(), Z.agg.get(), st, Z.dinv.get(),
+                                                   f, ui, e1, sg, Z.n, uo);
+  }
+  return cur;
 }
 
 }  // namespace
 
-void amg_vcycle(AmgDev &A, const double *d_f, const SegState *d_st, hipStream_t s) {
-  if (A.lv.empty()) return;
-  vc_level(A, 0, d_f, d_st, s);
+const double *amg_vcycle(AmgDev &A, const double *d_f, const SegState *d_st, hipStream_t s) {
+  if (A.lv.empty()) return nullptr;
+  const int b = vc_level(A, 0, d_f, d_st, s);
   RSB_LAUNCHED();
+  return b ? A.lv[0].u2.get() : A.lv[0].u.get();
+}
+
+const double *amg_result(const AmgDev &A) {
+  // pre-smoothing leaves a level's result in buffer nsmooth % 2; on a level
+  // with a level below, nsmooth post-smoothing steps (or the in-place
+  // correction when nsmooth = 0) bring it back to buffer 0
+  if (A.lv.empty()) return nullptr;
+  const bool second = A.lv.size() == 1 && (A.nsmooth & 1);
+  return second ? A.lv[0].u2.get() : A.lv[0].u.get();
 }
 
 }  // namespace rsb

@@ -701,8 +701,9 @@ int rsb_amg_vcycle(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
     RSB_HIP(hipMemsetAsync(fl.get(), 0, fl.bytes(), ctx.stream));
     RSB_HIP(hipMemcpyAsync(fl.get(), fin.p, n * sizeof(double), hipMemcpyDeviceToDevice,
                            ctx.stream));
-    amg_vcycle(t.A, fl.get(), nullptr, ctx.stream);
-    copy_out(ctx, u, t.A.lv[0].u.get(), n, dev);
+    const double *res = amg_vcycle(t.A, fl.get(), nullptr, ctx.stream);
+    if (res != amg_result(t.A)) fail(RSB_EINTERNAL, "V-cycle result buffer");
+    copy_out(ctx, u, res, n, dev);
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     return RSB_OK;
   });

@@ -442,7 +442,7 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
     amg.sigma = p.amg_sigma;
     amg.nsmooth = p.amg_smooth;
     amg_setup(L, C.root.get(), a.st, amg, ctx);
-    a.Z = amg.lv[0].u.get();
+    a.Z = amg_result(amg);
     if (p.amg_levels) *p.amg_levels = std::max(*p.amg_levels, (int)amg.lv.size());
   }
   k_inv_begin<RPT><<<nblk, kBlock, 0, s>>>(a);

@@ -239,7 +239,8 @@ struct AmgLevelDev {
   DevBuf<double> dinv;           // 1 / L_ii (0 for an empty row)
   DevBuf<int32_t> agg;           // row of the next level (-1: none)
   DevBuf<int32_t> mem;           // coarse levels: the 1 or 2 rows collapsed into each row
-  DevBuf<double> f, u, r;        // V-cycle right side (coarse levels), correction, residual
+  DevBuf<double> f;              // V-cycle right side (coarse levels)
+  DevBuf<double> u, u2, r, r2;   // correction and residual, two buffers each
 };
 
 struct AmgDev {
@@ -252,10 +253,11 @@ struct AmgDev {
 // root == that segment's strad); d_st: the solver's segment states.
 void amg_setup(const LevelView &L, const int32_t *d_root, const SegState *d_st, AmgDev &A,
                Ctx &ctx);
-// u = M f into A.lv[0].u (zero on rows that take no part) for the rows of
-// running segments (d_st == nullptr:
-// all live rows).  Launches only; graph-capturable.
-void amg_vcycle(AmgDev &A, const double *d_f, const SegState *d_st, hipStream_t s);
+// u = M f for the rows of running segments (d_st == nullptr: all live rows)
+// into the level-0 buffer amg_result(A) (zero on rows that take no part),
+// which it returns.  Launches only; graph-capturable.
+const double *amg_vcycle(AmgDev &A, const double *d_f, const SegState *d_st, hipStream_t s);
+const double *amg_result(const AmgDev &A);
 
 // Inverse iteration with CG on every segment with a component to cut.
 struct InverseParams {
