@@ -27,13 +27,15 @@ class Opts(C.Structure):
                 ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
                 ("cg_full_projection", C.c_int32), ("seed", C.c_uint64),
                 ("lanczos_keep", C.c_int32), ("inv_precond", C.c_int32),
-                ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double)]
+                ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double),
+                ("fiedler_sweep", C.c_int32), ("sweep_gap", C.c_double)]
 
 
 class Info(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("matvecs", C.c_int64),
                 ("theta", C.c_double), ("residual", C.c_double), ("ncomp", C.c_int32),
-                ("cg_iters", C.c_int32), ("amg_levels", C.c_int32)]
+                ("cg_iters", C.c_int32), ("amg_levels", C.c_int32), ("sweeps", C.c_int32),
+                ("sweep_moved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

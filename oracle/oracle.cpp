@@ -327,8 +327,16 @@ void jacobi_eigen(int k, Vec A, Vec &ev, Vec &V) {
 // problem).  The first kept vector is the Ritz vector used for the
 // convergence test, re-projected against the ones vector and normalised.
 // A cycle that ends by breakdown restarts explicitly.
+// Second Ritz pair of the last cycle (thick restart only): the Ritz vector
+// next to the Fiedler one and both Ritz values, for the sweep over the pair.
+struct SecondPair {
+  bool ok = false;
+  Vec y2;
+  double theta1 = 0.0, theta2 = 0.0;
+};
+
 int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_opts &o, Vec &y,
-                    double &lambda, orc_info &info) {
+                    double &lambda, orc_info &info, SecondPair *second = nullptr) {
   const int64_t n = g.n;
   const double u0 = 1.0 / std::sqrt((double)n);
   Vec q(n);
@@ -425,6 +433,18 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
     double rho = rayleigh(g, y, info.matvecs);
     res = residual_norm(g, y, rho, info.matvecs);
     info.cycles = cycle + 1;
+    if (second) {
+      second->ok = (keep >= 2 && first + 1 < k && std::min(keep, k - 1) >= 2);
+      if (second->ok) {
+        second->theta1 = ev[first];
+        second->theta2 = ev[first + 1];
+        second->y2.assign(n, 0.0);
+        for (int c = 0; c < k; ++c) {
+          const double tc = EV[(size_t)c * k + first + 1];
+          for (int64_t i = 0; i < n; ++i) second->y2[i] += tc * Q[c][i];
+        }
+      }
+    }
     if (res <= o.tol * rho) {
       converged = 1;
       break;
@@ -828,6 +848,56 @@ struct SolveResult {
   double lambda = 0.0;
 };
 
+// Weight of the edges between the two sides of a bisection.
+int64_t bisection_cut(const Graph &g, const std::vector<uint8_t> &side) {
+  int64_t cut = 0;
+  for (int64_t i = 0; i < g.n; ++i)
+    for (auto &nw : g.adj[i])
+      if (nw.first > i && side[i] != side[nw.first]) cut += nw.second;
+  return cut;
+}
+
+// Sweep over the Fiedler pair (the paper's suggestion for a degenerate pair,
+// Sec. 9): when the second Ritz value is within sweep_gap (relative) of the
+// first, y1 and the second Ritz vector orthonormalised against u0 and y1,
+// each with the canonical sign, are combined as cos(a) y1 + sin(a) y2 for
+// a = k pi / S, k = 0..S-1; every combination (canonical sign) is split by
+// the usual rule and the one of smallest cut replaces y (ties: smallest k).
+void sweep_pair(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const orc_opts &o,
+                const SecondPair &sp, Vec &y, orc_info &info) {
+  if (!(sp.theta2 - sp.theta1 <= o.sweep_gap * sp.theta1)) return;
+  const int64_t n = g.n;
+  Vec y2 = sp.y2;
+  deflate_ones(y2);
+  const double b = dot(y, y2);
+  for (int64_t i = 0; i < n; ++i) y2[i] -= b * y[i];
+  const double nn = norm2(y2);
+  if (!(nn > 1e-6)) return;
+  for (double &v : y2) v /= nn;
+  canonical_sign(y2, gid);
+  info.sweeps += 1;
+  int64_t best_cut = -1;
+  int best = 0;
+  Vec best_y;
+  for (int k = 0; k < o.fiedler_sweep; ++k) {
+    const double a = M_PI * (double)k / (double)o.fiedler_sweep;
+    const double c = std::cos(a), sn = std::sin(a);
+    Vec yk(n);
+    for (int64_t i = 0; i < n; ++i) yk[i] = c * y[i] + sn * y2[i];
+    canonical_sign(yk, gid);
+    std::vector<uint8_t> side;
+    split_by_keys(yk, gid, n_low, side);
+    const int64_t cut = bisection_cut(g, side);
+    if (best_cut < 0 || cut < best_cut) {
+      best_cut = cut;
+      best = k;
+      best_y = yk;
+    }
+  }
+  if (best != 0) info.sweep_moved += 1;
+  y = best_y;
+}
+
 // One bisection of graph g (vertices in ascending gid order) into a low side
 // of n_low vertices and a high side.  y receives the vector used (zero
 // outside the component that was cut).  Returns the status of the solve.
@@ -868,12 +938,15 @@ int bisect(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const
   for (size_t i = 0; i < members.size(); ++i) sub_gid[i] = gid[members[i]];
   Vec ys;
   int st;
+  SecondPair second;
   if (o.method == ORC_INVERSE_CG)
     st = inverse_fiedler(sub, sub_gid, o, ys, lambda, info);
   else
-    st = lanczos_fiedler(sub, sub_gid, o, ys, lambda, info);
+    st = lanczos_fiedler(sub, sub_gid, o, ys, lambda, info, o.fiedler_sweep > 0 ? &second : nullptr);
   if (st < 0) return st;
   std::vector<uint8_t> sub_side;
+  if (second.ok)
+    sweep_pair(sub, sub_gid, n_low - strad_before, o, second, ys, info);
   split_by_keys(ys, sub_gid, n_low - strad_before, sub_side);
   for (size_t i = 0; i < members.size(); ++i) {
     side[members[i]] = sub_side[i];
@@ -919,6 +992,8 @@ int rsb_recurse(const Graph &g, const std::vector<int64_t> &elems, int32_t p0, i
   info.matvecs += li.matvecs;
   info.cycles += li.cycles;
   info.cg_iters += li.cg_iters;
+  info.sweeps += li.sweeps;
+  info.sweep_moved += li.sweep_moved;
   std::vector<int64_t> lo, hi;
   for (size_t i = 0; i < elems.size(); ++i) (side[i] ? hi : lo).push_back(elems[i]);
   int r = rsb_recurse(g, lo, p0, pl, o, part, info, worst);
@@ -945,6 +1020,8 @@ void orc_opts_default(orc_opts *o) {
   o->inv_precond = ORC_PRECOND_NONE;
   o->amg_smooth = 1;
   o->amg_sigma = 2.0 / 3.0;
+  o->fiedler_sweep = 0;
+  o->sweep_gap = 0.1;
 }
 
 double orc_start_value(uint64_t seed, int64_t gid) { return start_value(seed, gid); }

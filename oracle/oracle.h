@@ -46,6 +46,9 @@ typedef struct orc_opts {
   int32_t inv_precond;       /* inverse iteration: ORC_PRECOND_NONE or _AMG */
   int32_t amg_smooth;        /* AMG: damped-Jacobi steps per smoothing phase */
   double amg_sigma;          /* AMG: Jacobi damping weight */
+  int32_t fiedler_sweep;     /* Lanczos with thick restart: S > 0 sweeps S angles of
+                                the Fiedler pair when it is within sweep_gap */
+  double sweep_gap;          /* relative gap (theta2 - theta1) / theta1 of the sweep */
 } orc_opts;
 
 typedef struct orc_info {
@@ -57,6 +60,8 @@ typedef struct orc_info {
   int32_t ncomp;       /* connected components of the graph solved on */
   int32_t cg_iters;    /* inverse iteration: CG steps summed over solves */
   int32_t amg_levels;  /* inverse iteration with AMG: levels of the hierarchy */
+  int32_t sweeps;      /* bisections whose Fiedler pair was swept */
+  int32_t sweep_moved; /* of those, bisections where an angle other than 0 won */
 } orc_info;
 
 void orc_opts_default(orc_opts *o);
