@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--max-restarts", type=int, default=50)
     ap.add_argument("--method", default="lanczos", choices=["lanczos", "inverse_cg"],
                     help="eigen-solver; inverse_cg runs report CG steps, not Lanczos steps")
+    ap.add_argument("--sweep", type=int, default=0,
+                    help="sweep S angles of a near-degenerate Fiedler pair for the smallest cut")
     ap.add_argument("--precond", default="none", choices=["none", "amg"],
                     help="inverse_cg: plain CG or aggregation-multigrid preconditioned CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -259,6 +261,7 @@ def main():
     opts = dict(precision=args.precision, tol=args.tol, lanczos_m=args.m,
                 max_restarts=args.max_restarts, verbose=args.verbose, lanczos_keep=args.keep,
                 method=args.method, inv_precond=args.precond, cg_tol=1e-8, inv_max_outer=100,
+                fiedler_sweep=args.sweep,
                 batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
                 autotune=args.autotune)
     if args.autotune_cache:
@@ -315,7 +318,7 @@ def main():
                    "precision": args.precision, "lanczos_m": args.m, "lanczos_keep": args.keep,
                    "tol": args.tol,
                    "max_restarts": args.max_restarts, "graph": "weighted vertex-shared",
-                   "method": args.method, "precond": args.precond,
+                   "method": args.method, "precond": args.precond, "fiedler_sweep": args.sweep,
                    "batched": not args.unbatched},
         "time_to_partition_ms": dt * 1e3 / args.steps,
         "edge_cut": st["edge_cut"],
@@ -324,6 +327,7 @@ def main():
         "avg_neighbors": st["avg_neighbors"],
         "part_sizes": [int(sizes.min()), int(sizes.max())],
         "status": code,
+        "swept_bisections": st["sweeps"],
         "not_converged_segments": st["not_converged"],
         "level_steps_per_partition": st["level_steps"],
         "ms_graph": st["ms_graph"],

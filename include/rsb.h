@@ -122,7 +122,18 @@ typedef struct rsb_opts {
                                coarse Laplacians, per subgraph. */
   int32_t amg_smooth;       /* AMG: damped-Jacobi steps per smoothing phase (1) */
   double amg_sigma;         /* AMG: Jacobi damping weight (2/3) */
-  int32_t reserved[2];
+  int32_t fiedler_sweep;    /* LANCZOS with lanczos_keep >= 2: S > 0 sweeps the
+                               Fiedler pair (Sec. 9: search the combinations of a
+                               near-degenerate pair for the smallest cut).  When
+                               the second Ritz value is within sweep_gap of the
+                               first, S combinations cos(a) y1 + sin(a) y2,
+                               a = k pi / S, are split and the one that cuts the
+                               least weight is used (ties: smallest k).  0: off
+                               (default); at most 64.  An exactly degenerate pair
+                               shows a single Ritz vector and is not swept. */
+  int32_t reserved;
+  double sweep_gap;         /* relative gap (theta2 - theta1) / theta1 below which
+                               the pair is swept (0.1) */
 } rsb_opts;
 
 typedef struct rsb_stats {
@@ -161,7 +172,9 @@ typedef struct rsb_stats {
   int64_t kernel_launches;   /* its launches */
   int32_t tile_rows;         /* rows per workgroup of the streaming kernels at level 0 */
   int32_t amg_levels;        /* INVERSE_CG with AMG: levels of the deepest hierarchy */
-  int32_t reserved[4];
+  int32_t sweeps;            /* fiedler_sweep: bisections whose Fiedler pair was swept */
+  int32_t sweep_moved;       /* of those, bisections where an angle other than 0 won */
+  int32_t reserved[2];
 } rsb_stats;
 
 /* Fills *o with the defaults listed above.  Returns RSB_OK or RSB_EINVAL (o NULL). */

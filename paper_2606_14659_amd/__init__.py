@@ -37,7 +37,7 @@ class Opts(C.Structure):
         ("stream", C.c_void_p), ("device_mem_limit", C.c_int64), ("verbose", C.c_int32),
         ("profile", C.c_int32), ("rows_per_thread", C.c_int32), ("lanczos_keep", C.c_int32),
         ("inv_precond", C.c_int32), ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double),
-        ("reserved", C.c_int32 * 2),
+        ("fiedler_sweep", C.c_int32), ("reserved", C.c_int32), ("sweep_gap", C.c_double),
     ]
 
 
@@ -51,7 +51,7 @@ class Stats(C.Structure):
         ("cut_pairs", C.c_int64), ("max_neighbors", C.c_int32), ("avg_neighbors", C.c_double),
         ("nnz", C.c_int64), ("kernel_bytes", C.c_double), ("kernel_ms", C.c_double),
         ("kernel_launches", C.c_int64), ("tile_rows", C.c_int32), ("amg_levels", C.c_int32),
-        ("reserved", C.c_int32 * 4),
+        ("sweeps", C.c_int32), ("sweep_moved", C.c_int32), ("reserved", C.c_int32 * 2),
     ]
 
     def as_dict(self):

@@ -58,6 +58,11 @@ void check_opts(const rsb_opts *o) {
     fail(RSB_EINVAL, "inv_precond must be RSB_PRECOND_NONE or RSB_PRECOND_AMG");
   if (o->amg_smooth < 0 || o->amg_smooth > 16) fail(RSB_EINVAL, "amg_smooth must be in [0, 16]");
   if (!(o->amg_sigma > 0.0 && o->amg_sigma < 2.0)) fail(RSB_EINVAL, "amg_sigma must be in (0, 2)");
+  if (o->fiedler_sweep < 0 || o->fiedler_sweep > 64)
+    fail(RSB_EINVAL, "fiedler_sweep must be in [0, 64]");
+  if (o->fiedler_sweep > 0 && (o->method != RSB_LANCZOS || o->lanczos_keep < 2))
+    fail(RSB_EINVAL, "fiedler_sweep needs method RSB_LANCZOS with lanczos_keep >= 2");
+  if (!(o->sweep_gap >= 0.0)) fail(RSB_EINVAL, "sweep_gap must be >= 0");
 }
 
 void setup_ctx(Ctx &ctx, const rsb_opts &o) {
@@ -146,7 +151,7 @@ void one_segment_tables(const Level &L, int s, OneSeg &o, Ctx &ctx) {
 
 // Eigen-solve of one level: all segments batched, or one segment at a time.
 int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, void *work,
-                    double *y64, KernelProfile *prof, int *amg_levels, Ctx &ctx) {
+                    double *y64, double *y2, KernelProfile *prof, int *amg_levels, Ctx &ctx) {
   const bool mixed = o.precision == RSB_MIXED;
   auto run = [&](const LevelView &v, SolveDev &SS, bool graph) -> int64_t {
     if (o.method == RSB_INVERSE_CG) {
@@ -155,7 +160,7 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
       return inverse_level(v, C, SS, ip, work, y64, graph, ctx);
     }
     LanczosParams lp{o.lanczos_m, o.lanczos_keep, o.max_restarts, o.tol, graph ? 1 : 0,
-                     o.seed,      prof,           v.nnz};
+                     o.seed,      prof,           v.nnz,          y2};
     return mixed ? lanczos_level<float>(v, C, SS, lp, work, y64, ctx)
                  : lanczos_level<double>(v, C, SS, lp, work, y64, ctx);
   };
@@ -185,6 +190,10 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     steps += run(v, S1, false);
     RSB_HIP(hipMemcpyAsync(S.st.get() + s, S1.st.get(), sizeof(SegState),
                            hipMemcpyDeviceToDevice, ctx.stream));
+    // the Ritz values of the last cycle (read by the sweep over the pair)
+    RSB_HIP(hipMemcpyAsync(S.tvals.get() + (int64_t)s * S.nkcap, S1.tvals.get(),
+                           std::min(S.nkcap, S1.nkcap) * sizeof(double), hipMemcpyDeviceToDevice,
+                           ctx.stream));
     int64_t c = 0;
     RSB_HIP(hipMemcpyAsync(&c, S1.counters.get(), sizeof(int64_t), hipMemcpyDeviceToHost,
                            ctx.stream));
@@ -257,6 +266,8 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
                                                       o.lanczos_keep);
   DevBuf<char> work(ctx, wbytes);
   DevBuf<double> y64(ctx, cap_rows);
+  DevBuf<double> y2;
+  if (o.fiedler_sweep > 0) y2.alloc(ctx, cap_rows);
   DevBuf<uint8_t> side(ctx, cap_rows);
   KernelProfile prof;
   Level LA, LB;
@@ -274,7 +285,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
     components_and_targets(*L, C, S, ctx);
     int amg_levels = 0;
-    const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(),
+    const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(), y2.get(),
                                       o.profile ? &prof : nullptr, &amg_levels, ctx);
     st.amg_levels = std::max(st.amg_levels, amg_levels);
     std::vector<SegState> hs(L->nseg);
@@ -310,6 +321,9 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
                 "res %.3e rho %.12g theta %.12g\n",
                 i, L->seg[i].n, L->seg[i].P, hs[i].ncomp, hs[i].solve, hs[i].converged,
                 hs[i].cycles, (long long)hs[i].steps, hs[i].res, hs[i].rho, hs[i].theta);
+    if (o.fiedler_sweep > 0)
+      fiedler_sweep(*L, C, S, y64.get(), y2.get(), o.fiedler_sweep, o.sweep_gap, &st.sweeps,
+                    &st.sweep_moved, ctx);
     if (fiedler_y) {
       const SegState &s = hs[0];
       RSB_HIP(hipMemcpyAsync(fiedler_y, y64.get(), meshes[0].nelem * sizeof(double),
@@ -535,6 +549,8 @@ int rsb_opts_init(rsb_opts *o) {
   o->inv_precond = RSB_PRECOND_NONE;
   o->amg_smooth = 1;
   o->amg_sigma = 2.0 / 3.0;
+  o->fiedler_sweep = 0;
+  o->sweep_gap = 0.1;
   return RSB_OK;
 }
 

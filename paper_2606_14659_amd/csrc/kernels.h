@@ -201,6 +201,7 @@ struct LanczosParams {
   uint64_t seed;
   KernelProfile *prof;   // non-null: time the step-j>=3 project kernel with events
   int64_t nnz;           // off-diagonal nonzeros of the level (for the byte count)
+  double *y2_out;        // non-null (thick restart): the second Ritz vector, FP64
 };
 // work: lanczos_workspace_bytes(L.nrows, m, T is float, keep) bytes of device
 // memory (FP64 u0, q_1, restart and work vectors; type-T directions q_2..q_m
@@ -274,6 +275,17 @@ struct InverseParams {
 size_t inverse_workspace_bytes(int64_t rows);
 int64_t inverse_level(const LevelView &L, CompDev &C, SolveDev &S, const InverseParams &p,
                       void *work, double *y64_out, bool use_graph, Ctx &ctx);
+
+// Sweep over the Fiedler pair (thick restart): for every segment whose
+// second Ritz value lies within sweep_gap (relative) of the first, replace
+// y64 by the combination cos(a) y1 + sin(a) y2 (y2 orthonormalised against
+// u0 and y1, both with the canonical sign; a = k pi / nangles) whose split
+// cuts the least weight.  Counts swept segments and those that moved.
+void fiedler_sweep(Level &L, CompDev &C, SolveDev &S, double *y64, const double *y2, int nangles,
+                   double sweep_gap, int *swept, int *moved, Ctx &ctx);
+
+// Canonical sign of y on every segment being cut (in place).
+void canonical_sign_level(Level &L, CompDev &C, SolveDev &S, double *y, Ctx &ctx);
 
 // Sign rule, radix select and side assignment.  side[row]: 0 low, 1 high,
 // 2 padding.

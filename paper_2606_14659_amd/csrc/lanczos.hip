@@ -1216,6 +1216,24 @@ __global__ __launch_bounds__(kBlock) void k_lz_output(LzArgs<T> a, double *__res
   }
 }
 
+// Second Ritz vector of the last thick-restart cycle (kept basis slot 2,
+// FP64) on the rows of the component being cut; zero elsewhere and where the
+// cycle formed a single Ritz vector.
+template <typename T, int RPT>
+__global__ __launch_bounds__(kBlock) void k_lz_output2(LzArgs<T> a, double *__restrict__ y2) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  const bool have = S.solve && S.nnext >= 2 && a.keep >= 2;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int lr = r * kBlock + threadIdx.x;
+    if (lr >= b.nrows) break;
+    const int64_t row = b.row0 + lr;
+    y2[row] = (have && a.U0[row] != 0.0) ? a.K[row] : 0.0;
+  }
+}
+
 __global__ void k_flags_reset(int32_t *flags) {
   flags[0] = 0;
   flags[1] = 0;
@@ -1270,6 +1288,9 @@ struct LzLaunch {
   }
   static void output(const LzArgs<T> &a, int nblk, double *y64, hipStream_t s) {
     k_lz_output<T, RPT><<<nblk, kBlock, 0, s>>>(a, y64);
+  }
+  static void output2(const LzArgs<T> &a, int nblk, double *y2, hipStream_t s) {
+    k_lz_output2<T, RPT><<<nblk, kBlock, 0, s>>>(a, y2);
   }
 };
 
@@ -1475,6 +1496,10 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
     }
     if (y64_out) {
       Lz::output(a, nblk, y64_out, ctx.stream);
+      RSB_LAUNCHED();
+    }
+    if (p.y2_out) {
+      Lz::output2(a, nblk, p.y2_out, ctx.stream);
       RSB_LAUNCHED();
     }
   });

@@ -222,6 +222,21 @@ __global__ void k_sign_first(const double *__restrict__ y, const int32_t *__rest
   if ((threadIdx.x & (kWave - 1)) == 0 && cand != 0x7fffffff) atomicMin(&st[s].first, cand);
 }
 
+__global__ void k_sign_reset(SegState *__restrict__ st, int nseg) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nseg) st[s].first = 0x7fffffff;
+}
+
+// y <- -y on the rows being cut of every segment whose sign pass flipped.
+__global__ void k_sign_apply(double *__restrict__ y, const int32_t *__restrict__ root,
+                             const SegDev *__restrict__ seg, int nseg,
+                             const SegState *__restrict__ st, int64_t nrows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int s = seg_of_row(seg, nseg, i);
+  if (in_solve(root, st[s], i) && st[s].flip) y[i] = -y[i];
+}
+
 __global__ void k_sign_flip(const double *__restrict__ y, SegState *__restrict__ st, int nseg,
                             uint64_t *__restrict__ pk, uint32_t *__restrict__ pg,
                             int64_t *__restrict__ rank) {
@@ -749,6 +764,7 @@ void split_level(Level &L, CompDev &C, SolveDev &S, const double *y64, uint8_t *
   RSB_HIP(hipMemsetAsync(ymax.get(), 0, ymax.bytes(), ctx.stream));
   RSB_HIP(hipMemsetAsync(hist.get(), 0, hist.bytes(), ctx.stream));
   unsigned g = grid_for(n, kBlock);
+  k_sign_reset<<<grid_for(L.nseg, 64), 64, 0, ctx.stream>>>(S.st.get(), L.nseg);
   k_sign_max<<<g, kBlock, 0, ctx.stream>>>(y64, C.root.get(), L.d_seg.get(), L.nseg, S.st.get(),
                                            ymax.get(), n);
   RSB_LAUNCHED();
@@ -770,6 +786,27 @@ void split_level(Level &L, CompDev &C, SolveDev &S, const double *y64, uint8_t *
   k_side<<<g, kBlock, 0, ctx.stream>>>(y64, L.gid.get(), C.root.get(), C.size.get(), C.pre.get(),
                                        L.orig.get(), L.d_seg.get(), L.nseg, S.st.get(), pk.get(),
                                        pg.get(), side, n);
+  RSB_LAUNCHED();
+}
+
+void canonical_sign_level(Level &L, CompDev &C, SolveDev &S, double *y, Ctx &ctx) {
+  const int64_t n = L.nrows;
+  if (n == 0) return;
+  DevBuf<unsigned long long> ymax(ctx, L.nseg);
+  DevBuf<uint64_t> pk(ctx, L.nseg);
+  DevBuf<uint32_t> pg(ctx, L.nseg);
+  DevBuf<int64_t> rank(ctx, L.nseg);
+  RSB_HIP(hipMemsetAsync(ymax.get(), 0, ymax.bytes(), ctx.stream));
+  const unsigned g = grid_for(n, kBlock);
+  k_sign_reset<<<grid_for(L.nseg, 64), 64, 0, ctx.stream>>>(S.st.get(), L.nseg);
+  k_sign_max<<<g, kBlock, 0, ctx.stream>>>(y, C.root.get(), L.d_seg.get(), L.nseg, S.st.get(),
+                                           ymax.get(), n);
+  k_sign_first<<<g, kBlock, 0, ctx.stream>>>(y, C.root.get(), L.d_seg.get(), L.nseg, S.st.get(),
+                                             ymax.get(), n);
+  k_sign_flip<<<grid_for(L.nseg, 64), 64, 0, ctx.stream>>>(y, S.st.get(), L.nseg, pk.get(),
+                                                           pg.get(), rank.get());
+  k_sign_apply<<<g, kBlock, 0, ctx.stream>>>(y, C.root.get(), L.d_seg.get(), L.nseg, S.st.get(),
+                                             n);
   RSB_LAUNCHED();
 }
 

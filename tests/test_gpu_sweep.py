@@ -1,0 +1,80 @@
+"""GPU parity of the sweep over the Fiedler pair against the CPU oracle.
+
+The cut of every swept bisection must equal the oracle's (both pick the
+smallest cut among the same combinations of the converged pair); one angle
+reproduces the plain method exactly; an exactly degenerate pair is not swept.
+"""
+import numpy as np
+import pytest
+
+import meshgen as mg
+import paper_2606_14659_amd as rsb
+
+pytestmark = pytest.mark.gpu
+
+KW = dict(lanczos_keep=8, lanczos_m=30, tol=1e-10)
+
+
+def half_cut(orc, ids, y):
+    rp, col, w = orc.dual_graph(ids)
+    n = len(y)
+    side = orc.split(y, np.arange(n), n // 2)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    c = (side[rows] != side[col]) & (col > rows)
+    return int(w[c].sum())
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sweep_fiedler_cut_matches_oracle(orc, seed):
+    ids = mg.uniform_holes(mg.box_hex(10, 10, 4), 0.06, seed).ids
+    st, lam, y, stats = rsb.fiedler(ids, fiedler_sweep=16, **KW)
+    ost, olam, oy, oinfo = orc.fiedler(ids, fiedler_sweep=16, **KW)
+    assert st == ost == 0
+    assert stats["sweeps"] == oinfo["sweeps"] == 1
+    assert abs(lam - olam) <= 1e-8 * olam
+    assert half_cut(orc, ids, y) == half_cut(orc, ids, oy)
+    assert abs(np.linalg.norm(y) - 1) < 1e-10
+
+
+def test_sweep_one_angle_is_plain():
+    ids = mg.uniform_holes(mg.box_hex(24, 24, 12), 0.05, 3).ids
+    kw = dict(lanczos_keep=8, lanczos_m=40, tol=1e-6)
+    st0, p0, s0 = rsb.partition(ids, 16, **kw)
+    st1, p1, s1 = rsb.partition(ids, 16, fiedler_sweep=1, **kw)
+    assert s1["sweeps"] > 0 and s1["sweep_moved"] == 0
+    assert np.array_equal(p0, p1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sweep_partition_cut_vs_oracle(orc, precision):
+    m = mg.uniform_holes(mg.box_hex(24, 24, 12), 0.05, 3)
+    tol = 1e-4 if precision == "mixed" else 1e-6
+    kw = dict(lanczos_keep=8, lanczos_m=40, tol=tol)
+    st, part, stats = rsb.partition(m.ids, 16, precision=precision, fiedler_sweep=8, **kw)
+    st0, part0, stats0 = rsb.partition(m.ids, 16, precision=precision, **kw)
+    ost, opart, oinfo = orc.partition(m.ids, 16, fiedler_sweep=8, lanczos_keep=8, lanczos_m=40,
+                                      tol=1e-6)
+    ocut = orc.metrics(m.ids, opart, 16)["weighted_cut"]
+    print(f"24x24x12 holes -> 16 ({precision}): cut plain {stats0['edge_cut']:.0f}, swept "
+          f"{stats['edge_cut']:.0f} ({stats['sweeps']} swept, {stats['sweep_moved']} moved); "
+          f"oracle swept {ocut:.0f} ({oinfo['sweeps']}, {oinfo['sweep_moved']})", flush=True)
+    sizes = np.bincount(part, minlength=16)
+    assert sizes.max() - sizes.min() <= 1
+    assert stats["sweeps"] == oinfo["sweeps"]
+    assert abs(stats["edge_cut"] - ocut) <= 0.01 * ocut
+    assert stats["edge_cut"] < stats0["edge_cut"]
+
+
+def test_exactly_degenerate_pair_is_not_swept():
+    ids = mg.box_hex(16, 16, 4).ids
+    st, lam, y, stats = rsb.fiedler(ids, graph="face", fiedler_sweep=32, **KW)
+    assert st == 0 and stats["sweeps"] == 0
+
+
+def test_sweep_unbatched_equals_batched():
+    ids = mg.uniform_holes(mg.box_hex(20, 20, 10), 0.05, 5).ids
+    kw = dict(lanczos_keep=8, lanczos_m=40, tol=1e-8, fiedler_sweep=8)
+    st1, p1, s1 = rsb.partition(ids, 8, **kw)
+    st2, p2, s2 = rsb.partition(ids, 8, batched=0, **kw)
+    assert s1["sweeps"] == s2["sweeps"] > 0
+    assert np.array_equal(p1, p2)
