@@ -327,6 +327,12 @@ void jacobi_eigen(int k, Vec A, Vec &ev, Vec &V) {
 // problem).  The first kept vector is the Ritz vector used for the
 // convergence test, re-projected against the ones vector and normalised.
 // A cycle that ends by breakdown restarts explicitly.
+// Warm start (an addition; the paper leaves the start vector open): a child
+// subgraph's solve starts from its parent's second Ritz vector, scaled to
+// unit root-mean-square on the parent's component, plus kWarmNoise times the
+// usual random start; elements without such a value take the random start.
+constexpr double kWarmNoise = 0.1;
+
 // Second Ritz pair of the last cycle (thick restart only): the Ritz vector
 // next to the Fiedler one and both Ritz values, for the sweep over the pair.
 struct SecondPair {
@@ -335,12 +341,22 @@ struct SecondPair {
   double theta1 = 0.0, theta2 = 0.0;
 };
 
+// Warm start values by global id (carried from a parent bisection).
+typedef std::unordered_map<int64_t, double> WarmMap;
+
 int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_opts &o, Vec &y,
-                    double &lambda, orc_info &info, SecondPair *second = nullptr) {
+                    double &lambda, orc_info &info, SecondPair *second = nullptr,
+                    const WarmMap *warm = nullptr) {
   const int64_t n = g.n;
   const double u0 = 1.0 / std::sqrt((double)n);
   Vec q(n);
-  for (int64_t i = 0; i < n; ++i) q[i] = start_value(o.seed, gid[i]);
+  for (int64_t i = 0; i < n; ++i) {
+    q[i] = start_value(o.seed, gid[i]);
+    if (warm) {
+      auto it = warm->find(gid[i]);
+      if (it != warm->end()) q[i] = it->second + kWarmNoise * q[i];
+    }
+  }
   deflate_ones(q);
   normalize(q);
   const int m = std::max(1, o.lanczos_m);
@@ -902,7 +918,8 @@ void sweep_pair(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, 
 // of n_low vertices and a high side.  y receives the vector used (zero
 // outside the component that was cut).  Returns the status of the solve.
 int bisect(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const orc_opts &o,
-           std::vector<uint8_t> &side, Vec &y, double &lambda, orc_info &info) {
+           std::vector<uint8_t> &side, Vec &y, double &lambda, orc_info &info,
+           WarmMap *warm = nullptr) {
   std::vector<int32_t> comp;
   int nc = components(g, gid, comp);
   info.ncomp = nc;
@@ -942,10 +959,18 @@ int bisect(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const
   if (o.method == ORC_INVERSE_CG)
     st = inverse_fiedler(sub, sub_gid, o, ys, lambda, info);
   else
-    st = lanczos_fiedler(sub, sub_gid, o, ys, lambda, info, o.fiedler_sweep > 0 ? &second : nullptr);
+    st = lanczos_fiedler(sub, sub_gid, o, ys, lambda, info,
+                         (o.fiedler_sweep > 0 || warm) ? &second : nullptr, warm);
   if (st < 0) return st;
+  if (warm && second.ok) {
+    // values for the children: y2 at unit root-mean-square on the component
+    double nn = 0.0;
+    for (double v : second.y2) nn += v * v;
+    const double scale = std::sqrt((double)sub_gid.size()) / std::sqrt(nn);
+    for (size_t i = 0; i < sub_gid.size(); ++i) (*warm)[sub_gid[i]] = second.y2[i] * scale;
+  }
   std::vector<uint8_t> sub_side;
-  if (second.ok)
+  if (second.ok && o.fiedler_sweep > 0)
     sweep_pair(sub, sub_gid, n_low - strad_before, o, second, ys, info);
   split_by_keys(ys, sub_gid, n_low - strad_before, sub_side);
   for (size_t i = 0; i < members.size(); ++i) {
@@ -974,7 +999,7 @@ bool valid_mesh(int64_t nelem, int32_t nv, const int64_t *ids) {
 // Recursion of Alg. 1 on the vertex list `elems` (ascending global ids),
 // parts [p0, p0 + np).
 int rsb_recurse(const Graph &g, const std::vector<int64_t> &elems, int32_t p0, int32_t np,
-                const orc_opts &o, int32_t *part, orc_info &info, int &worst) {
+                const orc_opts &o, int32_t *part, orc_info &info, int &worst, WarmMap &warm) {
   if (np == 1) {
     for (int64_t e : elems) part[e] = p0;
     return 0;
@@ -986,7 +1011,7 @@ int rsb_recurse(const Graph &g, const std::vector<int64_t> &elems, int32_t p0, i
   Vec y;
   double lam;
   orc_info li{};
-  int st = bisect(sub, elems, n_low, o, side, y, lam, li);
+  int st = bisect(sub, elems, n_low, o, side, y, lam, li, o.warm_start ? &warm : nullptr);
   if (st < 0) return st;
   worst = std::max(worst, st);
   info.matvecs += li.matvecs;
@@ -996,9 +1021,9 @@ int rsb_recurse(const Graph &g, const std::vector<int64_t> &elems, int32_t p0, i
   info.sweep_moved += li.sweep_moved;
   std::vector<int64_t> lo, hi;
   for (size_t i = 0; i < elems.size(); ++i) (side[i] ? hi : lo).push_back(elems[i]);
-  int r = rsb_recurse(g, lo, p0, pl, o, part, info, worst);
+  int r = rsb_recurse(g, lo, p0, pl, o, part, info, worst, warm);
   if (r < 0) return r;
-  return rsb_recurse(g, hi, p0 + pl, np - pl, o, part, info, worst);
+  return rsb_recurse(g, hi, p0 + pl, np - pl, o, part, info, worst, warm);
 }
 
 }  // namespace
@@ -1022,6 +1047,7 @@ void orc_opts_default(orc_opts *o) {
   o->amg_sigma = 2.0 / 3.0;
   o->fiedler_sweep = 0;
   o->sweep_gap = 0.1;
+  o->warm_start = 0;
 }
 
 double orc_start_value(uint64_t seed, int64_t gid) { return start_value(seed, gid); }
@@ -1175,7 +1201,8 @@ int orc_partition(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts,
   for (int64_t i = 0; i < nelem; ++i) all[i] = i;
   orc_info li{};
   int worst = 0;
-  int r = rsb_recurse(g, all, 0, nparts, *o, part, li, worst);
+  WarmMap warm;
+  int r = rsb_recurse(g, all, 0, nparts, *o, part, li, worst, warm);
   if (info) *info = li;
   if (r < 0) return r;
   return worst;

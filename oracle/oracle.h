@@ -49,6 +49,9 @@ typedef struct orc_opts {
   int32_t fiedler_sweep;     /* Lanczos with thick restart: S > 0 sweeps S angles of
                                 the Fiedler pair when it is within sweep_gap */
   double sweep_gap;          /* relative gap (theta2 - theta1) / theta1 of the sweep */
+  int32_t warm_start;        /* thick restart: a child's solve starts from its
+                                parent's second Ritz vector (plus 0.1 x the
+                                random start) */
 } orc_opts;
 
 typedef struct orc_info {
