@@ -207,6 +207,8 @@ def main():
                     help="eigen-solver; inverse_cg runs report CG steps, not Lanczos steps")
     ap.add_argument("--sweep", type=int, default=0,
                     help="sweep S angles of a near-degenerate Fiedler pair for the smallest cut")
+    ap.add_argument("--warm-start", type=int, default=0, choices=[0, 1],
+                    help="start child solves from the parent's second Ritz vector")
     ap.add_argument("--precond", default="none", choices=["none", "amg"],
                     help="inverse_cg: plain CG or aggregation-multigrid preconditioned CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -261,7 +263,7 @@ def main():
     opts = dict(precision=args.precision, tol=args.tol, lanczos_m=args.m,
                 max_restarts=args.max_restarts, verbose=args.verbose, lanczos_keep=args.keep,
                 method=args.method, inv_precond=args.precond, cg_tol=1e-8, inv_max_outer=100,
-                fiedler_sweep=args.sweep,
+                fiedler_sweep=args.sweep, warm_start=args.warm_start,
                 batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
                 autotune=args.autotune)
     if args.autotune_cache:
@@ -319,6 +321,7 @@ def main():
                    "tol": args.tol,
                    "max_restarts": args.max_restarts, "graph": "weighted vertex-shared",
                    "method": args.method, "precond": args.precond, "fiedler_sweep": args.sweep,
+                   "warm_start": bool(args.warm_start),
                    "batched": not args.unbatched},
         "time_to_partition_ms": dt * 1e3 / args.steps,
         "edge_cut": st["edge_cut"],

@@ -131,7 +131,13 @@ typedef struct rsb_opts {
                                least weight is used (ties: smallest k).  0: off
                                (default); at most 64.  An exactly degenerate pair
                                shows a single Ritz vector and is not swept. */
-  int32_t reserved;
+  int32_t warm_start;       /* LANCZOS with lanczos_keep >= 2: 1 = the solve of a
+                               subgraph starts from its parent's second Ritz
+                               vector (unit root-mean-square on the parent's cut
+                               component) plus 0.1 x the random start; elements
+                               without one take the random start.  The paper
+                               leaves the start vector open; 0 (default): the
+                               random start everywhere. */
   double sweep_gap;         /* relative gap (theta2 - theta1) / theta1 below which
                                the pair is swept (0.1) */
 } rsb_opts;

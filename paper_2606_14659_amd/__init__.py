@@ -37,7 +37,7 @@ class Opts(C.Structure):
         ("stream", C.c_void_p), ("device_mem_limit", C.c_int64), ("verbose", C.c_int32),
         ("profile", C.c_int32), ("rows_per_thread", C.c_int32), ("lanczos_keep", C.c_int32),
         ("inv_precond", C.c_int32), ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double),
-        ("fiedler_sweep", C.c_int32), ("reserved", C.c_int32), ("sweep_gap", C.c_double),
+        ("fiedler_sweep", C.c_int32), ("warm_start", C.c_int32), ("sweep_gap", C.c_double),
     ]
 
 

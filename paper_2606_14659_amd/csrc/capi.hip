@@ -63,6 +63,9 @@ void check_opts(const rsb_opts *o) {
   if (o->fiedler_sweep > 0 && (o->method != RSB_LANCZOS || o->lanczos_keep < 2))
     fail(RSB_EINVAL, "fiedler_sweep needs method RSB_LANCZOS with lanczos_keep >= 2");
   if (!(o->sweep_gap >= 0.0)) fail(RSB_EINVAL, "sweep_gap must be >= 0");
+  if (o->warm_start != 0 && o->warm_start != 1) fail(RSB_EINVAL, "warm_start must be 0 or 1");
+  if (o->warm_start && (o->method != RSB_LANCZOS || o->lanczos_keep < 2))
+    fail(RSB_EINVAL, "warm_start needs method RSB_LANCZOS with lanczos_keep >= 2");
 }
 
 void setup_ctx(Ctx &ctx, const rsb_opts &o) {
@@ -151,7 +154,8 @@ void one_segment_tables(const Level &L, int s, OneSeg &o, Ctx &ctx) {
 
 // Eigen-solve of one level: all segments batched, or one segment at a time.
 int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, void *work,
-                    double *y64, double *y2, KernelProfile *prof, int *amg_levels, Ctx &ctx) {
+                    double *y64, double *y2, const double *warm, KernelProfile *prof,
+                    int *amg_levels, Ctx &ctx) {
   const bool mixed = o.precision == RSB_MIXED;
   auto run = [&](const LevelView &v, SolveDev &SS, bool graph) -> int64_t {
     if (o.method == RSB_INVERSE_CG) {
@@ -160,7 +164,7 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
       return inverse_level(v, C, SS, ip, work, y64, graph, ctx);
     }
     LanczosParams lp{o.lanczos_m, o.lanczos_keep, o.max_restarts, o.tol, graph ? 1 : 0,
-                     o.seed,      prof,           v.nnz,          y2};
+                     o.seed,      prof,           v.nnz,          y2, warm};
     return mixed ? lanczos_level<float>(v, C, SS, lp, work, y64, ctx)
                  : lanczos_level<double>(v, C, SS, lp, work, y64, ctx);
   };
@@ -266,8 +270,12 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
                                                       o.lanczos_keep);
   DevBuf<char> work(ctx, wbytes);
   DevBuf<double> y64(ctx, cap_rows);
-  DevBuf<double> y2;
-  if (o.fiedler_sweep > 0) y2.alloc(ctx, cap_rows);
+  DevBuf<double> y2, warm;
+  if (o.fiedler_sweep > 0 || o.warm_start) y2.alloc(ctx, cap_rows);
+  if (o.warm_start) {
+    warm.alloc(ctx, std::max<int64_t>(total, 1));
+    fill_f64(warm.get(), total, std::nan(""), ctx);
+  }
   DevBuf<uint8_t> side(ctx, cap_rows);
   KernelProfile prof;
   Level LA, LB;
@@ -285,8 +293,9 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
     components_and_targets(*L, C, S, ctx);
     int amg_levels = 0;
-    const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(), y2.get(),
+    const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(), y2.get(), warm.get(),
                                       o.profile ? &prof : nullptr, &amg_levels, ctx);
+    if (o.warm_start) warm_update(*L, C, S, y2.get(), warm.get(), ctx);
     st.amg_levels = std::max(st.amg_levels, amg_levels);
     std::vector<SegState> hs(L->nseg);
     RSB_HIP(hipMemcpyAsync(hs.data(), S.st.get(), L->nseg * sizeof(SegState),

@@ -154,6 +154,11 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // One wavefront per element.  PASS 0 writes row lengths, PASS 1 columns and
 // weights at row_ptr.
 template <int PASS>
@@ -231,6 +236,12 @@ inline unsigned grid_for(int64_t n, int per_block) {
 }
 
 }  // namespace
+
+void fill_f64(double *p, int64_t n, double v, Ctx &ctx) {
+  if (n <= 0) return;
+  k_fill_f64<<<grid_for(n, kBlock), kBlock, 0, ctx.stream>>>(p, n, v);
+  RSB_LAUNCHED();
+}
 
 void fill_i32(int32_t *p, int64_t n, int32_t v, Ctx &ctx) {
   if (n <= 0) return;

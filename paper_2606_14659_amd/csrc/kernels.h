@@ -17,6 +17,7 @@ struct DevCsr {
 void scan_exclusive(const int64_t *in, int64_t n, int64_t *out, int64_t *total, Ctx &ctx);
 void scan_exclusive(const int32_t *in, int64_t n, int64_t *out, int64_t *total, Ctx &ctx);
 void fill_i32(int32_t *p, int64_t n, int32_t v, Ctx &ctx);
+void fill_f64(double *p, int64_t n, double v, Ctx &ctx);
 
 // Dual graph of nelem elements with nv vertex ids each (device ids).
 void build_dual_graph(const int64_t *d_ids, int64_t nelem, int nv, int graph, DevCsr &out,
@@ -121,6 +122,7 @@ struct LevelView {
   const int64_t *chunk_ptr = nullptr;
   const uint32_t *cols = nullptr;
   const int32_t *gid = nullptr;
+  const int32_t *orig = nullptr;
   int64_t nnz = 0;
 };
 
@@ -137,6 +139,7 @@ inline LevelView view_of(const Level &L) {
   v.chunk_ptr = L.chunk_ptr.get();
   v.cols = L.cols.get();
   v.gid = L.gid.get();
+  v.orig = L.orig.get();
   v.nnz = L.nnz;
   return v;
 }
@@ -202,6 +205,7 @@ struct LanczosParams {
   KernelProfile *prof;   // non-null: time the step-j>=3 project kernel with events
   int64_t nnz;           // off-diagonal nonzeros of the level (for the byte count)
   double *y2_out;        // non-null (thick restart): the second Ritz vector, FP64
+  const double *warm;    // non-null: warm start by element index (NaN: none)
 };
 // work: lanczos_workspace_bytes(L.nrows, m, T is float, keep) bytes of device
 // memory (FP64 u0, q_1, restart and work vectors; type-T directions q_2..q_m
@@ -283,6 +287,11 @@ int64_t inverse_level(const LevelView &L, CompDev &C, SolveDev &S, const Inverse
 // cuts the least weight.  Counts swept segments and those that moved.
 void fiedler_sweep(Level &L, CompDev &C, SolveDev &S, double *y64, const double *y2, int nangles,
                    double sweep_gap, int *swept, int *moved, Ctx &ctx);
+
+// Warm start for the next level: warm[orig[row]] = the second Ritz vector y2
+// at unit root-mean-square on each segment's cut component (segments whose
+// last cycle formed a second Ritz vector; other entries keep their values).
+void warm_update(Level &L, CompDev &C, SolveDev &S, const double *y2, double *warm, Ctx &ctx);
 
 // Canonical sign of y on every segment being cut (in place).
 void canonical_sign_level(Level &L, CompDev &C, SolveDev &S, double *y, Ctx &ctx);

@@ -40,6 +40,10 @@ namespace rsb {
 
 namespace {
 
+// Warm start of a child subgraph: weight of the random start added to the
+// parent's second Ritz vector.
+constexpr double kWarmNoise = 0.1;
+
 template <typename T>
 struct LzArgs {
   const BlkDev *blk;
@@ -76,6 +80,8 @@ struct LzArgs {
                            // reached in the cycle, [2] most steps run by a segment
   unsigned long long *ctr; // [0] segment steps
   uint64_t seed;
+  const int32_t *orig;     // row -> element index of the whole call (-1: padding)
+  const double *warm;      // warm start by element (NaN: none), or null
 };
 
 // Vector types of step j: STEP 1 reads Y and works in FP64; STEP 2 reads the
@@ -279,7 +285,12 @@ __global__ __launch_bounds__(kBlock) void k_lz_begin(LzArgs<T> a) {
     const int64_t row = tr.row[r];
     const bool in = (a.root[row] == S.strad);
     const double u = in ? S.invsqrt_nc : 0.0;
-    const double x = in ? start_value(a.seed, a.gid[row]) : 0.0;
+    double x = in ? start_value(a.seed, a.gid[row]) : 0.0;
+    if (in && a.warm) {
+      // the parent's second Ritz vector, if it had one, plus 0.1 x the random start
+      const double v = a.warm[a.orig[row]];
+      if (!isnan(v)) x = v + kWarmNoise * x;
+    }
     a.U0[row] = u;
     a.Y[row] = x;
     acc[0] += u * x;
@@ -1364,6 +1375,8 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
   a.cols = L.cols;
   a.root = C.root.get();
   a.gid = L.gid;
+  a.orig = L.orig;
+  a.warm = p.warm;
   // workspace layout: U0, Q1, Y, Wd (FP64), then V (m+1 slots), Wt0, Wt1 (T)
   double *wd = (double *)work;
   a.U0 = wd;

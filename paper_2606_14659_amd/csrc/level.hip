@@ -90,6 +90,14 @@ __device__ inline int cc_rep(int32_t *parent, int x) {
   return curr;
 }
 
+// Root of x by a read-only walk (no writes), for use once hooking is done:
+// every parent pointer leads to the same root, whatever other threads store.
+__device__ inline int cc_root(int32_t *parent, int x) {
+  int curr = x, next;
+  while ((next = cc_load(&parent[curr])) != curr) curr = next;
+  return curr;
+}
+
 __global__ void k_cc_init(int32_t *__restrict__ parent, int32_t *__restrict__ size, int64_t nrows) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;
@@ -131,7 +139,10 @@ __global__ void k_cc_compress(int32_t *parent, int32_t *__restrict__ size,
                               const int32_t *__restrict__ orig, int64_t nrows) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;
-  int r = cc_rep(parent, (int)i);
+  // A walk that halved paths here could store an intermediate node over the
+  // root that another row just stored for itself; the read-only walk leaves
+  // every pointer an ancestor, and each row then stores only its own root.
+  int r = cc_root(parent, (int)i);
   cc_store(&parent[i], r);
   // component sizes: lanes sharing the root of lane 0 add together
   const bool real = orig[i] >= 0;

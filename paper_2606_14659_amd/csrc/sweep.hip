@@ -12,6 +12,11 @@
 // cos(a) y1 + sin(a) y2 is split by the usual rule and its cut weight summed
 // (exact integer sums).  The combination with the smallest cut (ties: the
 // smallest k) replaces y1.  All segments of a level are swept together.
+//
+// The same second Ritz vector also seeds the next level (warm start, an
+// addition: the paper leaves the start vector open): scaled to unit
+// root-mean-square on the segment's cut component, it is kept per element
+// and the children's solves start from it plus a small random part.
 #include <cmath>
 #include <vector>
 
@@ -183,7 +188,71 @@ __global__ void k_sw_row_seg(const BlkDev *__restrict__ blk, int32_t *__restrict
   for (int lr = threadIdx.x; lr < b.nrows; lr += kBlock) row_seg[b.row0 + lr] = b.seg;
 }
 
+// warm start: partial sums of y2^2 over the rows being cut of a tile
+__global__ __launch_bounds__(kBlock) void k_wu_dots(SwArgs a, const double *__restrict__ y2) {
+  __shared__ double red[4];
+  __shared__ double vals[1];
+  const int lb = blockIdx.x;
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  double acc[1] = {0.0};
+  for (int lr = threadIdx.x; lr < b.nrows; lr += kBlock) {
+    const int64_t row = b.row0 + lr;
+    if (in_cut(a.root, S, row)) acc[0] += y2[row] * y2[row];
+  }
+  block_reduce_into<1>(acc, red, vals, 1);
+  write_partials(a, lb, vals, 1);
+}
+
+// scale = sqrt(component size) / ||y2|| (0: no second Ritz vector)
+__global__ __launch_bounds__(kBlock) void k_wu_scale(SwArgs a, double *__restrict__ scale) {
+  __shared__ double vals[1];
+  const int g = blockIdx.x;
+  if (!group_reduce(a, g, vals, 1)) return;
+  if (threadIdx.x != 0) return;
+  const int s = a.grp[g].seg;
+  const SegState &S = a.st[s];
+  const bool pair = S.solve && S.strad >= 0 && S.nnext >= 2 && vals[0] > 0.0;
+  scale[s] = pair ? 1.0 / (S.invsqrt_nc * sqrt(vals[0])) : 0.0;
+}
+
+__global__ void k_wu_scatter(SwArgs a, const int32_t *__restrict__ row_seg,
+                             const int32_t *__restrict__ orig, const double *__restrict__ scale,
+                             const double *__restrict__ y2, int64_t nrows,
+                             double *__restrict__ warm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int s = row_seg[i];
+  if (s < 0 || orig[i] < 0) return;
+  const double sc = scale[s];
+  if (sc > 0.0 && in_cut(a.root, a.st[s], i)) warm[orig[i]] = y2[i] * sc;
+}
+
 }  // namespace
+
+void warm_update(Level &L, CompDev &C, SolveDev &S, const double *y2, double *warm, Ctx &ctx) {
+  const int64_t n = L.nrows;
+  if (n == 0 || L.nseg == 0) return;
+  hipStream_t st = ctx.stream;
+  DevBuf<double> scale(ctx, L.nseg);
+  DevBuf<int32_t> row_seg(ctx, n);
+  SwArgs a{};
+  a.blk = L.d_blk.get();
+  a.grp = L.d_grp.get();
+  a.seg = L.d_seg.get();
+  a.st = S.st.get();
+  a.part = S.part.get();
+  a.gpart = S.gpart.get();
+  a.scnt = S.scnt.get();
+  a.ps = S.pstride;
+  a.root = C.root.get();
+  k_sw_row_seg<<<L.nblk, kBlock, 0, st>>>(L.d_blk.get(), row_seg.get());
+  k_wu_dots<<<L.nblk, kBlock, 0, st>>>(a, y2);
+  k_wu_scale<<<L.ngrp, kBlock, 0, st>>>(a, scale.get());
+  k_wu_scatter<<<grid_for(n, kBlock), kBlock, 0, st>>>(a, row_seg.get(), L.orig.get(),
+                                                       scale.get(), y2, n, warm);
+  RSB_LAUNCHED();
+}
 
 void fiedler_sweep(Level &L, CompDev &C, SolveDev &S, double *y64, const double *y2, int nangles,
                    double sweep_gap, int *swept, int *moved, Ctx &ctx) {

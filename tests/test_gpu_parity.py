@@ -320,3 +320,18 @@ def test_batch_equals_single_calls():
     for m, p, q in zip(meshes, nparts, parts):
         s1, part1, _ = rsb.partition(m.ids, p)
         assert np.array_equal(part1, q)
+
+
+def test_repeated_partitions_identical(orc):
+    # Component labels must not depend on thread timing: every row's label
+    # is its component's root.  Many repetitions, with other solves between
+    # them, give the same converged partition as the oracle's each time.
+    ids = mg.box_hex(24, 20, 18).ids
+    kw = dict(graph="face", lanczos_keep=8, lanczos_m=30, tol=1e-8)
+    ost, opart, _ = orc.partition(ids, 8, **kw)
+    for it in range(60):
+        st, part, stats = rsb.partition(ids, 8, **kw)
+        assert st == 0 and stats["disconnected"] == 0, it
+        assert np.array_equal(part, opart), it
+        m = mg.uniform_holes(mg.box_hex(10 + it % 7, 10, 4), 0.06, it)
+        rsb.fiedler(m.ids, lanczos_keep=8, lanczos_m=30, tol=1e-10)

@@ -78,3 +78,48 @@ def test_sweep_unbatched_equals_batched():
     st2, p2, s2 = rsb.partition(ids, 8, batched=0, **kw)
     assert s1["sweeps"] == s2["sweeps"] > 0
     assert np.array_equal(p1, p2)
+
+
+# --- warm start of the child solves from the parent's second Ritz vector ---
+
+@pytest.mark.parametrize("dims,graph,nparts", [((24, 20, 18), "face", 8),
+                                              ((30, 14, 9), "face", 6),
+                                              ((30, 16, 7), "face", 4)])
+def test_warm_start_partition_identical(orc, dims, graph, nparts):
+    ids = mg.box_hex(*dims).ids
+    kw = dict(graph=graph, lanczos_keep=8, lanczos_m=30, tol=1e-8)
+    import os
+    st, part, stats = rsb.partition(ids, nparts, warm_start=1,
+                                    verbose=int(os.environ.get("RSB_TEST_VERBOSE", "0")), **kw)
+    ost, opart, _ = orc.partition(ids, nparts, warm_start=1, **kw)
+    st0, part0, stats0 = rsb.partition(ids, nparts, **kw)
+    print(f"{dims} {graph} {nparts}: status warm {st} oracle {ost} plain {st0}; segment steps "
+          f"{stats['segment_steps']} / {stats0['segment_steps']}", flush=True)
+    assert st == ost == st0 == 0
+    assert np.array_equal(part, opart) and np.array_equal(part, part0)
+    assert stats["segment_steps"] <= stats0["segment_steps"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_warm_start_fewer_steps_same_cut(orc, precision):
+    m = mg.clustered_holes(mg.box_hex(48, 48, 24), 0.1, 9)
+    kw = dict(lanczos_keep=8, lanczos_m=40, tol=1e-2)
+    st0, p0, s0 = rsb.partition(m.ids, 64, precision=precision, **kw)
+    st1, p1, s1 = rsb.partition(m.ids, 64, precision=precision, warm_start=1, **kw)
+    ost, op, oinfo = orc.partition(m.ids, 64, warm_start=1, **kw)
+    ocut = orc.metrics(m.ids, op, 64)["weighted_cut"]
+    print(f"48x48x24 clustered -> 64 ({precision}): level-steps {s0['level_steps']} -> "
+          f"{s1['level_steps']}, segment-steps {s0['segment_steps']} -> {s1['segment_steps']}; "
+          f"cut {s0['edge_cut']:.0f} -> {s1['edge_cut']:.0f} (oracle warm {ocut:.0f})", flush=True)
+    assert s1["segment_steps"] < 0.85 * s0["segment_steps"]
+    assert abs(s1["edge_cut"] - ocut) <= 0.01 * ocut
+    sizes = np.bincount(p1, minlength=64)
+    assert sizes.max() - sizes.min() <= 1
+
+
+def test_warm_start_unbatched_equals_batched():
+    ids = mg.uniform_holes(mg.box_hex(20, 20, 10), 0.05, 5).ids
+    kw = dict(lanczos_keep=8, lanczos_m=40, tol=1e-8, warm_start=1)
+    st1, p1, s1 = rsb.partition(ids, 8, **kw)
+    st2, p2, s2 = rsb.partition(ids, 8, batched=0, **kw)
+    assert np.array_equal(p1, p2)

@@ -60,7 +60,8 @@ def test_bad_options_rejected_before_any_device_call():
                          ("lanczos_keep", -1), ("lanczos_keep", 17), ("lanczos_keep", 100),
                          ("inv_precond", 2), ("inv_precond", -1), ("amg_smooth", -1),
                          ("amg_smooth", 17), ("amg_sigma", 0.0), ("amg_sigma", 2.0),
-                         ("fiedler_sweep", -1), ("fiedler_sweep", 65), ("sweep_gap", -1.0)):
+                         ("fiedler_sweep", -1), ("fiedler_sweep", 65), ("sweep_gap", -1.0),
+                         ("warm_start", 2), ("warm_start", -1)):
         oo = rsb.Opts.from_buffer_copy(o)
         setattr(oo, field, value)
         part = np.zeros(2, dtype=np.int32)
@@ -73,6 +74,10 @@ def test_bad_options_rejected_before_any_device_call():
     for method, keep in ((0, 0), (0, 1), (1, 8)):
         oo = rsb.Opts.from_buffer_copy(o)
         oo.fiedler_sweep, oo.method, oo.lanczos_keep = 8, method, keep
+        part = np.zeros(2, dtype=np.int32)
+        assert rsb.lib().rsb_partition(2, 4, ids.ctypes.data_as(C.c_void_p), 2, C.byref(oo),
+                                       part.ctypes.data_as(C.c_void_p), None) == rsb.EINVAL
+        oo.fiedler_sweep, oo.warm_start = 0, 1
         part = np.zeros(2, dtype=np.int32)
         assert rsb.lib().rsb_partition(2, 4, ids.ctypes.data_as(C.c_void_p), 2, C.byref(oo),
                                        part.ctypes.data_as(C.c_void_p), None) == rsb.EINVAL
