@@ -6,7 +6,8 @@ spherical clusters and vertex ids randomly renumbered onto 64-bit values
 (7,549,747 elements), partitioned into 4096 parts by batched RSB with
 thick-restart Lanczos with FP32 directions and FP64 scalars, restart vector
 and kept Ritz vectors (cycles of m = 40 steps, 8 kept Ritz pairs, tolerance
-1e-2).
+1e-2), every child subgraph's solve started from its parent's second Ritz
+vector.
 Inputs are resident in HBM (torch tensors)
 before the timed region; one step is one whole partition: dual graph, then
 12 levels of components, Lanczos, split and compaction.
@@ -207,7 +208,7 @@ def main():
                     help="eigen-solver; inverse_cg runs report CG steps, not Lanczos steps")
     ap.add_argument("--sweep", type=int, default=0,
                     help="sweep S angles of a near-degenerate Fiedler pair for the smallest cut")
-    ap.add_argument("--warm-start", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--warm-start", type=int, default=1, choices=[0, 1],
                     help="start child solves from the parent's second Ritz vector")
     ap.add_argument("--precond", default="none", choices=["none", "amg"],
                     help="inverse_cg: plain CG or aggregation-multigrid preconditioned CG")

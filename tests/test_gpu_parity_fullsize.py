@@ -24,7 +24,8 @@ import paper_2606_14659_amd as rsb
 
 pytestmark = pytest.mark.gpu
 
-BENCH = dict(precision="mixed", lanczos_keep=8, tol=1e-2, lanczos_m=40, max_restarts=50)
+BENCH = dict(precision="mixed", lanczos_keep=8, tol=1e-2, lanczos_m=40, max_restarts=50,
+             warm_start=1)
 
 
 def _torch_ids(ids):
