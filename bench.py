@@ -37,11 +37,14 @@ WORKLOADS = {
     "box256x256x128-clustered10-renum-4096": dict(nparts=4096),
     "box256x256x64-holes3-1024": dict(nparts=1024),
     "box128x128x64-holes5-2": dict(nparts=2),
+    "box256x256x128-clustered10-renum-shuffled-4096": dict(nparts=4096),
 }
 
 
 def make_mesh(name):
     import meshgen as mg
+    if name.startswith("box256x256x128") and "shuffled" in name:
+        return mg.shuffle_elements(mg.box256x128_clustered10(), mg.config_seed(4) + 7)
     if name.startswith("box256x256x128"):
         return mg.box256x128_clustered10()
     if name.startswith("box256x256x64"):
@@ -210,6 +213,8 @@ def main():
                     help="sweep S angles of a near-degenerate Fiedler pair for the smallest cut")
     ap.add_argument("--warm-start", type=int, default=1, choices=[0, 1],
                     help="start child solves from the parent's second Ritz vector")
+    ap.add_argument("--reorder", type=int, default=0, choices=[0, 1],
+                    help="store rows in breadth-first order before the first level")
     ap.add_argument("--precond", default="none", choices=["none", "amg"],
                     help="inverse_cg: plain CG or aggregation-multigrid preconditioned CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -264,7 +269,7 @@ def main():
     opts = dict(precision=args.precision, tol=args.tol, lanczos_m=args.m,
                 max_restarts=args.max_restarts, verbose=args.verbose, lanczos_keep=args.keep,
                 method=args.method, inv_precond=args.precond, cg_tol=1e-8, inv_max_outer=100,
-                fiedler_sweep=args.sweep, warm_start=args.warm_start,
+                fiedler_sweep=args.sweep, warm_start=args.warm_start, reorder=args.reorder,
                 batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
                 autotune=args.autotune)
     if args.autotune_cache:
@@ -322,7 +327,7 @@ def main():
                    "tol": args.tol,
                    "max_restarts": args.max_restarts, "graph": "weighted vertex-shared",
                    "method": args.method, "precond": args.precond, "fiedler_sweep": args.sweep,
-                   "warm_start": bool(args.warm_start),
+                   "warm_start": bool(args.warm_start), "reorder": bool(args.reorder),
                    "batched": not args.unbatched},
         "time_to_partition_ms": dt * 1e3 / args.steps,
         "edge_cut": st["edge_cut"],
@@ -337,6 +342,7 @@ def main():
         "ms_graph": st["ms_graph"],
         "ms_solve": st["ms_solve"],
         "ms_split": st["ms_split"],
+        "ms_reorder": st["ms_reorder"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": stored_traffic(args.workload, KERNEL_LABEL) if st["tile_rows"] == 1024

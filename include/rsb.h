@@ -140,6 +140,14 @@ typedef struct rsb_opts {
                                random start everywhere. */
   double sweep_gap;         /* relative gap (theta2 - theta1) / theta1 below which
                                the pair is swept (0.1) */
+  int32_t reorder;          /* rsb_partition(_batch): 1 = store each mesh's rows in
+                               breadth-first order of its dual graph (from a
+                               pseudo-peripheral element) before the first level,
+                               so that neighbours lie close in memory (the paper
+                               sorts by RCB first; no coordinates are given here).
+                               Element ids, start vectors, tie-breaks and outputs
+                               keep the input numbering.  0 (default): input order. */
+  int32_t reserved;
 } rsb_opts;
 
 typedef struct rsb_stats {
@@ -180,7 +188,8 @@ typedef struct rsb_stats {
   int32_t amg_levels;        /* INVERSE_CG with AMG: levels of the deepest hierarchy */
   int32_t sweeps;            /* fiedler_sweep: bisections whose Fiedler pair was swept */
   int32_t sweep_moved;       /* of those, bisections where an angle other than 0 won */
-  int32_t reserved[2];
+  double ms_reorder;         /* opts->reorder = 1: locality order of the rows (host wall
+                                clock, included in ms_total) */
 } rsb_stats;
 
 /* Fills *o with the defaults listed above.  Returns RSB_OK or RSB_EINVAL (o NULL). */
@@ -207,6 +216,19 @@ int rsb_dual_graph(int64_t nelem, int32_t nv_per_elem, const int64_t *elem_verte
  * Exposed for testing the SpMV.  RSB_EINVAL on bad sizes or weights. */
 int rsb_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
                         const int32_t *weight, const double *x, double *y, const rsb_opts *opts);
+
+/* The locality order that opts->reorder = 1 gives the level-0 rows, on a
+ * caller CSR as in rsb_laplacian_apply: order[k] = row placed at position k
+ * (int32[n], host or device memory as opts->device_pointers says).  It is the
+ * Cuthill-McKee order: breadth-first levels from the row farthest from row 0
+ * (smallest index among the farthest), each level ordered by the least
+ * position of a neighbour in the level before, ties by row index, rows not
+ * reached last by row index.  Not a step of the paper's method: it stands in
+ * for the coordinate pre-sort (recursive coordinate bisection) the paper
+ * applies before partitioning, as the input carries no coordinates.
+ * Exposed for testing.  RSB_EINVAL on bad sizes or weights. */
+int rsb_locality_order(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                       const int32_t *weight, int32_t *order, const rsb_opts *opts);
 
 /* Level `level` of the aggregation multigrid hierarchy that preconditions the
  * inverse-iteration solves (Sec. 7, Alg. 3: pairs of rows collapsed by a

@@ -75,6 +75,7 @@ def lib():
         L.orc_fiedler_csr.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       P(Opts), C.c_void_p, P(C.c_double), P(Info)]
         L.orc_split.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.orc_locality_order.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_partition.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, P(Opts),
                                     C.c_void_p, P(Info)]
         L.orc_metrics.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
@@ -154,6 +155,19 @@ def laplacian_apply(row_ptr, col, w, x) -> np.ndarray:
     ww = np.ascontiguousarray(w, dtype=np.int32)
     lib().orc_laplacian_apply(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(x), _ptr(y))
     return y
+
+
+def locality_order(row_ptr, col, w) -> np.ndarray:
+    """Cuthill-McKee order: order[k] = row placed at position k."""
+    n = len(row_ptr) - 1
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    ww = np.ascontiguousarray(w, dtype=np.int32)
+    out = np.zeros(n, dtype=np.int32)
+    rc = lib().orc_locality_order(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_locality_order: {rc}")
+    return out
 
 
 def tridiag_smallest(a, b, thr=0.0):

@@ -1026,6 +1026,51 @@ int rsb_recurse(const Graph &g, const std::vector<int64_t> &elems, int32_t p0, i
   return rsb_recurse(g, hi, p0 + pl, np - pl, o, part, info, worst, warm);
 }
 
+// ---------------------------------------------------------------------------
+// Locality order of the rows.  Not a step of the paper's method, which
+// pre-sorts elements by recursive coordinate bisection before partitioning
+// (that needs coordinates, which the input does not carry).  Classic
+// Cuthill-McKee in its queue form: breadth-first search from a
+// pseudo-peripheral row -- the row farthest from row 0, smallest index among
+// the farthest -- where each row taken from the queue appends its unvisited
+// neighbours in increasing index; rows the search never reaches follow in
+// increasing index.  order[k] = old row placed at position k.
+// ---------------------------------------------------------------------------
+std::vector<int32_t> bfs_levels(const Graph &g, int64_t src) {
+  std::vector<int32_t> dist(g.n, -1);
+  std::vector<int64_t> queue{src};
+  dist[src] = 0;
+  for (size_t h = 0; h < queue.size(); ++h) {
+    const int64_t i = queue[h];
+    for (auto &e : g.adj[i])
+      if (dist[e.first] < 0) {
+        dist[e.first] = dist[i] + 1;
+        queue.push_back(e.first);
+      }
+  }
+  return dist;
+}
+
+std::vector<int32_t> cuthill_mckee(Graph g) {
+  for (auto &a : g.adj) std::sort(a.begin(), a.end());
+  const std::vector<int32_t> d0 = bfs_levels(g, 0);
+  int64_t far = 0;
+  for (int64_t i = 0; i < g.n; ++i)
+    if (d0[i] > d0[far]) far = i;
+  std::vector<char> seen(g.n, 0);
+  std::vector<int32_t> order{(int32_t)far};
+  seen[far] = 1;
+  for (size_t h = 0; h < order.size(); ++h)
+    for (auto &e : g.adj[order[h]])
+      if (!seen[e.first]) {
+        seen[e.first] = 1;
+        order.push_back(e.first);
+      }
+  for (int64_t i = 0; i < g.n; ++i)
+    if (!seen[i]) order.push_back((int32_t)i);
+  return order;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1177,6 +1222,16 @@ int orc_amg_level(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
     for (int64_t i = 0; i < L.g.n; ++i) gid_out[i] = L.g.gid[i];
   if (agg)
     for (int64_t i = 0; i < L.g.n; ++i) agg[i] = L.agg.empty() ? -1 : L.agg[i];
+  return 0;
+}
+
+int orc_locality_order(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                       const int32_t *weight, int32_t *order) {
+  if (n < 1 || !row_ptr || !col || !weight || !order) return -1;
+  Graph g;
+  to_graph(n, row_ptr, col, weight, g);
+  const std::vector<int32_t> o = cuthill_mckee(g);
+  std::copy(o.begin(), o.end(), order);
   return 0;
 }
 

@@ -127,6 +127,14 @@ int orc_amg_level(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
 int orc_amg_vcycle(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
                    const int64_t *gid, double sigma, int32_t nsmooth, const double *f, double *u);
 
+/* Cuthill-McKee order of a CSR graph (queue form, from the row farthest
+ * from row 0, neighbours appended in increasing index, unreached rows last):
+ * order[k] = row placed at position k.  Not part of the paper's method (it
+ * stands in for the coordinate pre-sort of the elements).  Returns 0, -1 on
+ * bad input. */
+int orc_locality_order(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                       const int32_t *weight, int32_t *order);
+
 /* Recursive spectral bisection into nparts parts; part[i] in [0, nparts). */
 int orc_partition(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts,
                   const orc_opts *o, int32_t *part, orc_info *info);

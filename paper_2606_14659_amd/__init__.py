@@ -38,6 +38,7 @@ class Opts(C.Structure):
         ("profile", C.c_int32), ("rows_per_thread", C.c_int32), ("lanczos_keep", C.c_int32),
         ("inv_precond", C.c_int32), ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double),
         ("fiedler_sweep", C.c_int32), ("warm_start", C.c_int32), ("sweep_gap", C.c_double),
+        ("reorder", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -51,7 +52,7 @@ class Stats(C.Structure):
         ("cut_pairs", C.c_int64), ("max_neighbors", C.c_int32), ("avg_neighbors", C.c_double),
         ("nnz", C.c_int64), ("kernel_bytes", C.c_double), ("kernel_ms", C.c_double),
         ("kernel_launches", C.c_int64), ("tile_rows", C.c_int32), ("amg_levels", C.c_int32),
-        ("sweeps", C.c_int32), ("sweep_moved", C.c_int32), ("reserved", C.c_int32 * 2),
+        ("sweeps", C.c_int32), ("sweep_moved", C.c_int32), ("ms_reorder", C.c_double),
     ]
 
     def as_dict(self):
@@ -73,6 +74,8 @@ _SIGNATURES = {
                         C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "rsb_laplacian_apply": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p], C.c_int),
+    "rsb_locality_order": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_void_p], C.c_int),
     "rsb_fiedler": ([C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "rsb_split": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
@@ -221,6 +224,19 @@ def laplacian_apply(row_ptr, col, weight, x, device: bool = False, **kw):
     _check(lib().rsb_laplacian_apply(n, rp.ptr, c.ptr, w.ptr, xx.ptr, yp, C.byref(o)),
            "rsb_laplacian_apply")
     return y
+
+
+def locality_order(row_ptr, col, weight, device: bool = False, **kw):
+    """Cuthill-McKee order of a CSR graph: order[k] = row placed at position k."""
+    n = len(row_ptr) - 1
+    o = make_opts(device, **kw)
+    rp = _Arr(row_ptr, np.int64, device)
+    c = _Arr(col if len(col) else np.zeros(1), np.int32, device)
+    w = _Arr(weight if len(weight) else np.zeros(1), np.int32, device)
+    out, op = _out(n, np.int32, device)
+    _check(lib().rsb_locality_order(n, rp.ptr, c.ptr, w.ptr, op, C.byref(o)),
+           "rsb_locality_order")
+    return out
 
 
 def amg_level(row_ptr, col, weight, level: int, **kw) -> dict:

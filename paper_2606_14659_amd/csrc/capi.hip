@@ -64,6 +64,7 @@ void check_opts(const rsb_opts *o) {
     fail(RSB_EINVAL, "fiedler_sweep needs method RSB_LANCZOS with lanczos_keep >= 2");
   if (!(o->sweep_gap >= 0.0)) fail(RSB_EINVAL, "sweep_gap must be >= 0");
   if (o->warm_start != 0 && o->warm_start != 1) fail(RSB_EINVAL, "warm_start must be 0 or 1");
+  if (o->reorder != 0 && o->reorder != 1) fail(RSB_EINVAL, "reorder must be 0 or 1");
   if (o->warm_start && (o->method != RSB_LANCZOS || o->lanczos_keep < 2))
     fail(RSB_EINVAL, "warm_start needs method RSB_LANCZOS with lanczos_keep >= 2");
 }
@@ -246,8 +247,22 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     parts_total += meshes[b].nparts;
   }
   const int rpt = o.rows_per_thread ? o.rows_per_thread : default_rpt(total);
+  // locality order of each mesh's rows (not for rsb_fiedler, whose vector
+  // is returned row by row)
+  std::vector<DevBuf<int32_t>> perms;
+  std::vector<const int32_t *> perm_ptr;
+  if (o.reorder && !fiedler_y) {
+    const double tr = now_ms();
+    perms.resize(meshes.size());
+    for (size_t b = 0; b < meshes.size(); ++b) {
+      locality_order(graphs[b], perms[b], ctx);
+      perm_ptr.push_back(perms[b].get());
+    }
+    st.ms_reorder = now_ms() - tr;
+  }
   Level L0;
-  level0_from_csr(L0, gp, np, rpt, ctx);
+  level0_from_csr(L0, gp, np, rpt, ctx, perm_ptr.empty() ? nullptr : &perm_ptr);
+  perms.clear();
   for (auto &g : graphs) {
     g.col.release();
     g.wgt.release();
@@ -627,6 +642,22 @@ int rsb_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col_id
     DevBuf<double> yd(ctx, n);
     laplacian_apply_csr(g, xin.p, yd.get(), ctx);
     copy_out(ctx, y, yd.get(), n, dev);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    return RSB_OK;
+  });
+}
+
+int rsb_locality_order(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                       const int32_t *weight, int32_t *order, const rsb_opts *opts) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    if (!order) fail(RSB_EINVAL, "bad arguments");
+    Ctx ctx;
+    DevCsr g;
+    load_csr(n, row_ptr, col_idx, weight, *opts, ctx, g);
+    DevBuf<int32_t> perm;
+    locality_order(g, perm, ctx);
+    copy_out(ctx, order, perm.get(), n, opts->device_pointers != 0);
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     return RSB_OK;
   });

@@ -237,6 +237,34 @@ inline unsigned grid_for(int64_t n, int per_block) {
 
 }  // namespace
 
+// Stable LSD radix sort of (key, value) pairs by the low `bits` bits of the
+// keys, 8 bits per pass; the sorted pairs end in keys/vals.
+void sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int bits, Ctx &ctx, bool sync) {
+  if (n <= 1 || bits <= 0) return;
+  const int passes = (bits + 7) / 8;
+  DevBuf<uint64_t> kb(ctx, n);
+  DevBuf<uint32_t> vb(ctx, n);
+  const int64_t nblocks = (n + kTile - 1) / kTile;
+  DevBuf<int64_t> hist(ctx, 256 * nblocks), offs(ctx, 256 * nblocks);
+  uint64_t *kin = keys, *kout = kb.get();
+  uint32_t *vin = vals, *vout = vb.get();
+  for (int p = 0; p < passes; ++p) {
+    k_radix_hist<<<(unsigned)nblocks, kBlock, 0, ctx.stream>>>(kin, n, 8 * p, nblocks, hist.get());
+    RSB_LAUNCHED();
+    scan_exclusive(hist.get(), 256 * nblocks, offs.get(), nullptr, ctx);
+    k_radix_scatter<<<(unsigned)nblocks, kBlock, 0, ctx.stream>>>(kin, vin, n, 8 * p, nblocks,
+                                                                  offs.get(), kout, vout);
+    RSB_LAUNCHED();
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  if (kin != keys) {
+    RSB_HIP(hipMemcpyAsync(keys, kin, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, ctx.stream));
+    RSB_HIP(hipMemcpyAsync(vals, vin, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, ctx.stream));
+  }
+  if (sync) RSB_HIP(hipStreamSynchronize(ctx.stream));
+}
+
 void fill_f64(double *p, int64_t n, double v, Ctx &ctx) {
   if (n <= 0) return;
   k_fill_f64<<<grid_for(n, kBlock), kBlock, 0, ctx.stream>>>(p, n, v);

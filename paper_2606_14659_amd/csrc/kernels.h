@@ -18,6 +18,16 @@ void scan_exclusive(const int64_t *in, int64_t n, int64_t *out, int64_t *total, 
 void scan_exclusive(const int32_t *in, int64_t n, int64_t *out, int64_t *total, Ctx &ctx);
 void fill_i32(int32_t *p, int64_t n, int32_t v, Ctx &ctx);
 void fill_f64(double *p, int64_t n, double v, Ctx &ctx);
+// Stable LSD radix sort of (keys, vals) by the low `bits` bits of the keys;
+// with sync = false the result is only ordered on ctx.stream.
+void sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int bits, Ctx &ctx,
+                bool sync = true);
+
+// Locality order of a graph (Cuthill-McKee: breadth-first levels from a
+// pseudo-peripheral row, each level ordered by the least position of a
+// neighbour in the level before, ties by row): perm[new row] = old row.  The
+// CSR is rewritten in that order (columns relabelled).
+void locality_order(DevCsr &g, DevBuf<int32_t> &perm, Ctx &ctx);
 
 // Dual graph of nelem elements with nv vertex ids each (device ids).
 void build_dual_graph(const int64_t *d_ids, int64_t nelem, int nv, int graph, DevCsr &out,
@@ -154,9 +164,11 @@ void level_tables(Level &L, int rpt, Ctx &ctx);
 int default_rpt(int64_t nrows);
 void choose_tile(Level &L, const rsb_opts &o, void *work, Ctx &ctx);
 
-// Level 0 from per-mesh CSR graphs (segments in mesh order).
+// Level 0 from per-mesh CSR graphs (segments in mesh order).  perm (optional,
+// per mesh, device): row r of the CSR is element perm[r] of its mesh.
 void level0_from_csr(Level &L, const std::vector<const DevCsr *> &g,
-                     const std::vector<int32_t> &nparts, int rpt, Ctx &ctx);
+                     const std::vector<int32_t> &nparts, int rpt, Ctx &ctx,
+                     const std::vector<const int32_t *> *perm = nullptr);
 
 // ---------------------------------------------------------------------------
 // Eigen-solver buffers for one level and one vector precision.

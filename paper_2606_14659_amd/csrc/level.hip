@@ -44,7 +44,7 @@ __global__ void k_fill_sell_csr(const int64_t *__restrict__ row_ptr, const int32
                                 int64_t chunk_base, int64_t nchunks_mesh,
                                 const int64_t *__restrict__ chunk_ptr, uint32_t *__restrict__ cols,
                                 int32_t *__restrict__ orig, int32_t *__restrict__ gid,
-                                int64_t orig_base) {
+                                int64_t orig_base, const int32_t *__restrict__ perm) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t c = r / kWave;
   if (c >= nchunks_mesh) return;
@@ -62,8 +62,9 @@ __global__ void k_fill_sell_csr(const int64_t *__restrict__ row_ptr, const int32
     if (k < len) word = pack_colw((uint32_t)(row_base + col[a + k]), (uint32_t)wgt[a + k]);
     cols[p + (int64_t)k * kWave + lane] = word;
   }
-  orig[row_base + r] = (r < n) ? (int32_t)(orig_base + r) : -1;
-  gid[row_base + r] = (r < n) ? (int32_t)r : -1;
+  const int64_t e = (r < n) ? (perm ? perm[r] : r) : -1;  // element of this row
+  orig[row_base + r] = (r < n) ? (int32_t)(orig_base + e) : -1;
+  gid[row_base + r] = (r < n) ? (int32_t)e : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -152,6 +153,59 @@ __global__ void k_cc_compress(int32_t *parent, int32_t *__restrict__ size,
   if (real && r != r0) atomicAdd(&size[r], 1);
 }
 
+// Least global id of every component, at its root.
+__global__ void k_cc_mingid(const int32_t *__restrict__ root, const int32_t *__restrict__ gid,
+                            const int32_t *__restrict__ orig, int64_t nrows,
+                            int32_t *__restrict__ mingid) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows || orig[i] < 0) return;
+  atomicMin(&mingid[root[i]], gid[i]);
+}
+
+__global__ void k_cc_root_flag(const int32_t *__restrict__ root, const int32_t *__restrict__ orig,
+                               int64_t nrows, int32_t *__restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  flag[i] = (orig[i] >= 0 && root[i] == (int32_t)i) ? 1 : 0;
+}
+
+// roots as (segment, least gid) keys and their rows
+__global__ void k_cc_root_keys(const int32_t *__restrict__ flag, const int64_t *__restrict__ pos,
+                               const int32_t *__restrict__ mingid, const SegDev *__restrict__ seg,
+                               int nseg, int64_t nrows, uint64_t *__restrict__ keys,
+                               uint32_t *__restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows || !flag[i]) return;
+  const int s = seg_of_row(seg, nseg, i);
+  keys[pos[i]] = ((uint64_t)s << 32) | (uint32_t)mingid[i];
+  vals[pos[i]] = (uint32_t)i;
+}
+
+__global__ void k_cc_root_sizes(const uint32_t *__restrict__ vals,
+                                const int32_t *__restrict__ size, int64_t nroots,
+                                int64_t *__restrict__ sz) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nroots) sz[k] = size[vals[k]];
+}
+
+// base[segment] = prefix at the segment's first root in sorted order
+__global__ void k_cc_seg_base(const uint64_t *__restrict__ keys, const int64_t *__restrict__ off,
+                              int64_t nroots, int64_t *__restrict__ base) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nroots) return;
+  if (k == 0 || (keys[k - 1] >> 32) != (keys[k] >> 32)) base[keys[k] >> 32] = off[k];
+}
+
+// pre[root] = offset of the component among its segment's components taken
+// in order of least global id (roots sorted by (segment, least gid))
+__global__ void k_cc_root_pre(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                              const int64_t *__restrict__ off, const int64_t *__restrict__ base,
+                              int64_t nroots, int64_t *__restrict__ pre) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nroots) return;
+  pre[vals[k]] = off[k] - base[keys[k] >> 32];
+}
+
 __global__ void k_seg_state_init(SegState *__restrict__ st, const SegDev *__restrict__ seg,
                                  int nseg) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -162,8 +216,9 @@ __global__ void k_seg_state_init(SegState *__restrict__ st, const SegDev *__rest
   st[s] = z;
 }
 
-// pre[] is the global exclusive scan of size[]; make it segment-relative and
-// pick the component that straddles the low-side count of each segment.
+// pre[root] is the segment-relative offset of the component (the elements of
+// the segment's components with a smaller least global id); pick the
+// component that straddles the low-side count of each segment.
 __global__ void k_cc_targets(const int32_t *__restrict__ parent, const int32_t *__restrict__ size,
                              int64_t *__restrict__ pre, const int32_t *__restrict__ orig,
                              const SegDev *__restrict__ seg, int nseg, SegState *__restrict__ st,
@@ -172,10 +227,7 @@ __global__ void k_cc_targets(const int32_t *__restrict__ parent, const int32_t *
   if (i >= nrows) return;
   if (orig[i] < 0 || parent[i] != (int32_t)i) return;
   int s = seg_of_row(seg, nseg, i);
-  // segment-relative prefix; pre at the segment's first row is the base
-  // (written before any change because the first row of a segment is its
-  // own root or precedes every root of the segment)
-  int64_t rel = pre[i] - pre[seg[s].row0];
+  int64_t rel = pre[i];
   int64_t sz = size[i];
   int64_t nlow = seg[s].nlow;
   atomicAdd(&st[s].ncomp, 1);
@@ -218,24 +270,27 @@ __global__ void k_sign_max(const double *__restrict__ y, const int32_t *__restri
   if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicMax(&ymax[s], v);
 }
 
+// The deciding element is the one of least global id among the large
+// entries (rows need not be in global-id order): min of (gid, row).
 __global__ void k_sign_first(const double *__restrict__ y, const int32_t *__restrict__ root,
-                             const SegDev *__restrict__ seg, int nseg, SegState *__restrict__ st,
-                             const unsigned long long *__restrict__ ymax, int64_t nrows) {
+                             const int32_t *__restrict__ gid, const SegDev *__restrict__ seg,
+                             int nseg, const SegState *__restrict__ st,
+                             const unsigned long long *__restrict__ ymax, int64_t nrows,
+                             unsigned long long *__restrict__ firstkey) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;  // whole wavefronts
   int s = seg_of_row(seg, nseg, i);
-  int cand = 0x7fffffff;
+  unsigned long long cand = ~0ull;
   if (in_solve(root, st[s], i)) {
     double m = __longlong_as_double((long long)ymax[s]);
-    if (fabs(y[i]) >= 1e-3 * m) cand = (int)i;
+    if (fabs(y[i]) >= 1e-3 * m)
+      cand = ((unsigned long long)(uint32_t)gid[i] << 32) | (unsigned long long)(uint32_t)i;
   }
-  for (int off = kWave / 2; off > 0; off >>= 1) cand = min(cand, __shfl_xor(cand, off, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0 && cand != 0x7fffffff) atomicMin(&st[s].first, cand);
-}
-
-__global__ void k_sign_reset(SegState *__restrict__ st, int nseg) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < nseg) st[s].first = 0x7fffffff;
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(cand, off, kWave);
+    cand = cand < o ? cand : o;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0 && cand != ~0ull) atomicMin(&firstkey[s], cand);
 }
 
 // y <- -y on the rows being cut of every segment whose sign pass flipped.
@@ -250,9 +305,12 @@ __global__ void k_sign_apply(double *__restrict__ y, const int32_t *__restrict__
 
 __global__ void k_sign_flip(const double *__restrict__ y, SegState *__restrict__ st, int nseg,
                             uint64_t *__restrict__ pk, uint32_t *__restrict__ pg,
-                            int64_t *__restrict__ rank) {
+                            int64_t *__restrict__ rank,
+                            const unsigned long long *__restrict__ firstkey) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nseg) return;
+  const unsigned long long fk = firstkey[s];
+  st[s].first = (fk == ~0ull) ? 0x7fffffff : (int32_t)(fk & 0xffffffffull);
   int f = 0;
   if (st[s].strad >= 0 && st[s].first != 0x7fffffff) f = (y[st[s].first] > 0.0) ? 1 : 0;
   st[s].flip = f;
@@ -371,7 +429,7 @@ __global__ void k_side(const double *__restrict__ y, const int32_t *__restrict__
     bool low = (key < kp) || (key == kp && g <= gp);
     side[i] = low ? 0 : 1;
   } else {
-    int64_t rel = pre[r] - pre[seg[s].row0];
+    int64_t rel = pre[r];
     side[i] = (rel + size[r] <= seg[s].nlow) ? 0 : 1;
   }
 }
@@ -676,7 +734,8 @@ void level_tables(Level &L, int rpt, Ctx &ctx) {
 }
 
 void level0_from_csr(Level &L, const std::vector<const DevCsr *> &g,
-                     const std::vector<int32_t> &nparts, int rpt, Ctx &ctx) {
+                     const std::vector<int32_t> &nparts, int rpt, Ctx &ctx,
+                     const std::vector<const int32_t *> *perm) {
   // segments for meshes that need splitting
   L.seg.clear();
   int64_t row = 0;
@@ -736,7 +795,7 @@ void level0_from_csr(Level &L, const std::vector<const DevCsr *> &g,
     k_fill_sell_csr<<<grid_for(L.seg[s].npad, kBlock), kBlock, 0, ctx.stream>>>(
         c.row_ptr.get(), c.col.get(), c.wgt.get(), c.n, L.seg[s].row0, L.seg[s].row0 / kWave,
         nch, L.chunk_ptr.get(), L.cols.get(), L.orig.get(), L.gid.get(),
-        orig_base[mesh_seg[s]]);
+        orig_base[mesh_seg[s]], perm ? (*perm)[mesh_seg[s]] : nullptr);
     RSB_LAUNCHED();
   }
   level_tables(L, rpt, ctx);
@@ -758,7 +817,44 @@ void components_and_targets(Level &L, CompDev &C, SolveDev &S, Ctx &ctx) {
   RSB_LAUNCHED();
   k_cc_compress<<<g, kBlock, 0, ctx.stream>>>(C.root.get(), C.size.get(), L.orig.get(), n);
   RSB_LAUNCHED();
-  scan_exclusive(C.size.get(), n, C.pre.get(), C.pre.get() + n, ctx);
+  // components in order of their least global id within each segment (the
+  // rows need not be in global-id order, see the locality order)
+  {
+    DevBuf<int32_t> mingid(ctx, n), flag(ctx, n);
+    DevBuf<int64_t> pos(ctx, n + 1);
+    fill_i32(mingid.get(), n, 0x7fffffff, ctx);
+    k_cc_mingid<<<g, kBlock, 0, ctx.stream>>>(C.root.get(), L.gid.get(), L.orig.get(), n,
+                                              mingid.get());
+    k_cc_root_flag<<<g, kBlock, 0, ctx.stream>>>(C.root.get(), L.orig.get(), n, flag.get());
+    RSB_LAUNCHED();
+    scan_exclusive(flag.get(), n, pos.get(), pos.get() + n, ctx);
+    int64_t nroots = 0;
+    RSB_HIP(hipMemcpyAsync(&nroots, pos.get() + n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                           ctx.stream));
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    if (nroots > 0) {
+      DevBuf<uint64_t> keys(ctx, nroots);
+      DevBuf<uint32_t> vals(ctx, nroots);
+      DevBuf<int64_t> sz(ctx, nroots), off(ctx, nroots + 1);
+      k_cc_root_keys<<<g, kBlock, 0, ctx.stream>>>(flag.get(), pos.get(), mingid.get(),
+                                                   L.d_seg.get(), L.nseg, n, keys.get(),
+                                                   vals.get());
+      RSB_LAUNCHED();
+      int segbits = 0;
+      while ((1ll << segbits) < (int64_t)L.nseg) ++segbits;
+      sort_pairs(keys.get(), vals.get(), nroots, 32 + segbits, ctx);
+      const unsigned gk = grid_for(nroots, kBlock);
+      k_cc_root_sizes<<<gk, kBlock, 0, ctx.stream>>>(vals.get(), C.size.get(), nroots, sz.get());
+      RSB_LAUNCHED();
+      scan_exclusive(sz.get(), nroots, off.get(), off.get() + nroots, ctx);
+      DevBuf<int64_t> base(ctx, std::max(L.nseg, 1));
+      k_cc_seg_base<<<gk, kBlock, 0, ctx.stream>>>(keys.get(), off.get(), nroots, base.get());
+      k_cc_root_pre<<<gk, kBlock, 0, ctx.stream>>>(keys.get(), vals.get(), off.get(), base.get(),
+                                                   nroots, C.pre.get());
+      RSB_LAUNCHED();
+    }
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+  }
   k_cc_targets<<<g, kBlock, 0, ctx.stream>>>(C.root.get(), C.size.get(), C.pre.get(),
                                              L.orig.get(), L.d_seg.get(), L.nseg, S.st.get(), n);
   RSB_LAUNCHED();
@@ -775,15 +871,16 @@ void split_level(Level &L, CompDev &C, SolveDev &S, const double *y64, uint8_t *
   RSB_HIP(hipMemsetAsync(ymax.get(), 0, ymax.bytes(), ctx.stream));
   RSB_HIP(hipMemsetAsync(hist.get(), 0, hist.bytes(), ctx.stream));
   unsigned g = grid_for(n, kBlock);
-  k_sign_reset<<<grid_for(L.nseg, 64), 64, 0, ctx.stream>>>(S.st.get(), L.nseg);
+  DevBuf<unsigned long long> firstkey(ctx, L.nseg);
+  RSB_HIP(hipMemsetAsync(firstkey.get(), 0xFF, firstkey.bytes(), ctx.stream));
   k_sign_max<<<g, kBlock, 0, ctx.stream>>>(y64, C.root.get(), L.d_seg.get(), L.nseg, S.st.get(),
                                            ymax.get(), n);
   RSB_LAUNCHED();
-  k_sign_first<<<g, kBlock, 0, ctx.stream>>>(y64, C.root.get(), L.d_seg.get(), L.nseg,
-                                             S.st.get(), ymax.get(), n);
+  k_sign_first<<<g, kBlock, 0, ctx.stream>>>(y64, C.root.get(), L.gid.get(), L.d_seg.get(),
+                                             L.nseg, S.st.get(), ymax.get(), n, firstkey.get());
   RSB_LAUNCHED();
   k_sign_flip<<<grid_for(L.nseg, 64), 64, 0, ctx.stream>>>(y64, S.st.get(), L.nseg, pk.get(),
-                                                           pg.get(), rank.get());
+                                                           pg.get(), rank.get(), firstkey.get());
   RSB_LAUNCHED();
   for (int pass = 0; pass < 12; ++pass) {
     k_sel_hist<<<L.nblk, kBlock, 0, ctx.stream>>>(y64, L.gid.get(), C.root.get(), L.d_blk.get(),
@@ -809,13 +906,14 @@ void canonical_sign_level(Level &L, CompDev &C, SolveDev &S, double *y, Ctx &ctx
   DevBuf<int64_t> rank(ctx, L.nseg);
   RSB_HIP(hipMemsetAsync(ymax.get(), 0, ymax.bytes(), ctx.stream));
   const unsigned g = grid_for(n, kBlock);
-  k_sign_reset<<<grid_for(L.nseg, 64), 64, 0, ctx.stream>>>(S.st.get(), L.nseg);
+  DevBuf<unsigned long long> firstkey(ctx, L.nseg);
+  RSB_HIP(hipMemsetAsync(firstkey.get(), 0xFF, firstkey.bytes(), ctx.stream));
   k_sign_max<<<g, kBlock, 0, ctx.stream>>>(y, C.root.get(), L.d_seg.get(), L.nseg, S.st.get(),
                                            ymax.get(), n);
-  k_sign_first<<<g, kBlock, 0, ctx.stream>>>(y, C.root.get(), L.d_seg.get(), L.nseg, S.st.get(),
-                                             ymax.get(), n);
+  k_sign_first<<<g, kBlock, 0, ctx.stream>>>(y, C.root.get(), L.gid.get(), L.d_seg.get(), L.nseg,
+                                             S.st.get(), ymax.get(), n, firstkey.get());
   k_sign_flip<<<grid_for(L.nseg, 64), 64, 0, ctx.stream>>>(y, S.st.get(), L.nseg, pk.get(),
-                                                           pg.get(), rank.get());
+                                                           pg.get(), rank.get(), firstkey.get());
   k_sign_apply<<<g, kBlock, 0, ctx.stream>>>(y, C.root.get(), L.d_seg.get(), L.nseg, S.st.get(),
                                              n);
   RSB_LAUNCHED();
