@@ -214,7 +214,7 @@ def main():
     ap.add_argument("--warm-start", type=int, default=1, choices=[0, 1],
                     help="start child solves from the parent's second Ritz vector")
     ap.add_argument("--reorder", type=int, default=0, choices=[0, 1],
-                    help="store rows in breadth-first order before the first level")
+                    help="store rows in Cuthill-McKee order before the first level")
     ap.add_argument("--precond", default="none", choices=["none", "amg"],
                     help="inverse_cg: plain CG or aggregation-multigrid preconditioned CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")

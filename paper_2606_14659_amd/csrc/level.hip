@@ -106,6 +106,26 @@ __global__ void k_cc_init(int32_t *__restrict__ parent, int32_t *__restrict__ si
   size[i] = 0;
 }
 
+// Each live row starts linked to its least neighbour when that is below it
+// (a forest, since links only go down), so that most of the hooking below
+// finds both ends already joined.
+__global__ void k_cc_init_link(const int64_t *__restrict__ chunk_ptr,
+                               const uint32_t *__restrict__ cols, const int32_t *__restrict__ orig,
+                               int32_t *__restrict__ parent, int64_t nrows) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows || orig[r] < 0) return;
+  int64_t c = r / kWave;
+  int lane = (int)(r & (kWave - 1));
+  int64_t p = chunk_ptr[c];
+  int width = (int)((chunk_ptr[c + 1] - p) / kWave);
+  int best = (int)r;
+  for (int k = 0; k < width; ++k) {
+    uint32_t w = cols[p + (int64_t)k * kWave + lane];
+    if (colw_wt(w) != 0) best = min(best, (int)colw_col(w));
+  }
+  parent[r] = best;
+}
+
 __global__ void k_cc_hook(const int64_t *__restrict__ chunk_ptr, const uint32_t *__restrict__ cols,
                           const int32_t *__restrict__ orig, int32_t *parent, int64_t nrows) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,13 +173,21 @@ __global__ void k_cc_compress(int32_t *parent, int32_t *__restrict__ size,
   if (real && r != r0) atomicAdd(&size[r], 1);
 }
 
-// Least global id of every component, at its root.
+// Least global id of every component, at its root.  Most lanes of a wave
+// share one component: those reduce over the wave and make one atomic; the
+// others make theirs only when they lower the stored value.
 __global__ void k_cc_mingid(const int32_t *__restrict__ root, const int32_t *__restrict__ gid,
                             const int32_t *__restrict__ orig, int64_t nrows,
                             int32_t *__restrict__ mingid) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows || orig[i] < 0) return;
-  atomicMin(&mingid[root[i]], gid[i]);
+  const bool real = i < nrows && orig[i] >= 0;
+  const int r = real ? root[i] : -1;
+  const int g = real ? gid[i] : 0x7fffffff;
+  const int r0 = __shfl(r, 0, kWave);
+  int m = (r == r0) ? g : 0x7fffffff;
+  for (int off = kWave / 2; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0 && r0 >= 0 && m < mingid[r0]) atomicMin(&mingid[r0], m);
+  if (real && r != r0 && g < mingid[r]) atomicMin(&mingid[r], g);
 }
 
 __global__ void k_cc_root_flag(const int32_t *__restrict__ root, const int32_t *__restrict__ orig,
@@ -811,6 +839,9 @@ void components_and_targets(Level &L, CompDev &C, SolveDev &S, Ctx &ctx) {
   if (n == 0) return;
   unsigned g = grid_for(n, kBlock);
   k_cc_init<<<g, kBlock, 0, ctx.stream>>>(C.root.get(), C.size.get(), n);
+  RSB_LAUNCHED();
+  k_cc_init_link<<<g, kBlock, 0, ctx.stream>>>(L.chunk_ptr.get(), L.cols.get(), L.orig.get(),
+                                               C.root.get(), n);
   RSB_LAUNCHED();
   k_cc_hook<<<g, kBlock, 0, ctx.stream>>>(L.chunk_ptr.get(), L.cols.get(), L.orig.get(),
                                           C.root.get(), n);
