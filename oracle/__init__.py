@@ -75,6 +75,7 @@ def lib():
         L.orc_fiedler_csr.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       P(Opts), C.c_void_p, P(C.c_double), P(Info)]
         L.orc_split.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.orc_gs_apply.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_locality_order.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_partition.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, P(Opts),
                                     C.c_void_p, P(Info)]
@@ -154,6 +155,18 @@ def laplacian_apply(row_ptr, col, w, x) -> np.ndarray:
     c = np.ascontiguousarray(col, dtype=np.int32)
     ww = np.ascontiguousarray(w, dtype=np.int32)
     lib().orc_laplacian_apply(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(x), _ptr(y))
+    return y
+
+
+def gs_apply(ids, x) -> np.ndarray:
+    """y = L x in the gather-scatter form (element -> vertex -> element)."""
+    a = _ids(ids)
+    n, nv = a.shape
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.zeros(n, dtype=np.float64)
+    rc = lib().orc_gs_apply(n, nv, _ptr(a), _ptr(xx), _ptr(y))
+    if rc != 0:
+        raise RuntimeError(f"orc_gs_apply: {rc}")
     return y
 
 

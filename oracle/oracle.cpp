@@ -1225,6 +1225,34 @@ int orc_amg_level(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
   return 0;
 }
 
+// Gather-scatter form of the weighted Laplacian (Sec. 5): each element's
+// value is copied to its distinct vertices (P), the copies are summed per
+// vertex (Q Q^T) and gathered back (P^T), so (A_w x)_e = sum over e's
+// vertices v of u_v, u_v = sum of x over the elements containing v; with
+// D = diag(A_w 1), L x = D x - A_w x.
+int orc_gs_apply(int64_t nelem, int32_t nv, const int64_t *ids, const double *x, double *y) {
+  if (!valid_mesh(nelem, nv, ids) || !x || !y) return -1;
+  std::vector<std::vector<int64_t>> verts(nelem);
+  std::map<int64_t, double> u, count;
+  for (int64_t e = 0; e < nelem; ++e) {
+    std::set<int64_t> d(ids + e * nv, ids + (e + 1) * nv);
+    verts[e].assign(d.begin(), d.end());
+    for (int64_t v : verts[e]) {
+      u[v] += x[e];
+      count[v] += 1.0;
+    }
+  }
+  for (int64_t e = 0; e < nelem; ++e) {
+    double ax = 0.0, diag = 0.0;
+    for (int64_t v : verts[e]) {
+      ax += u[v];
+      diag += count[v];
+    }
+    y[e] = diag * x[e] - ax;
+  }
+  return 0;
+}
+
 int orc_locality_order(int64_t n, const int64_t *row_ptr, const int32_t *col,
                        const int32_t *weight, int32_t *order) {
   if (n < 1 || !row_ptr || !col || !weight || !order) return -1;

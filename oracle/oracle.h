@@ -127,6 +127,11 @@ int orc_amg_level(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
 int orc_amg_vcycle(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
                    const int64_t *gid, double sigma, int32_t nsmooth, const double *f, double *u);
 
+/* y = L x with the weighted Laplacian in gather-scatter form (Sec. 5):
+ * A_w = P^T Q Q^T P over the distinct vertex ids of each element,
+ * L = diag(A_w 1) - A_w.  Returns 0, -1 on bad input. */
+int orc_gs_apply(int64_t nelem, int32_t nv, const int64_t *ids, const double *x, double *y);
+
 /* Cuthill-McKee order of a CSR graph (queue form, from the row farthest
  * from row 0, neighbours appended in increasing index, unreached rows last):
  * order[k] = row placed at position k.  Not part of the paper's method (it
