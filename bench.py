@@ -215,6 +215,8 @@ def main():
                     help="start child solves from the parent's second Ritz vector")
     ap.add_argument("--reorder", type=int, default=0, choices=[0, 1],
                     help="store rows in Cuthill-McKee order before the first level")
+    ap.add_argument("--gather-scatter", type=int, default=0, choices=[0, 1],
+                    help="Lanczos SpMV in the gather-scatter form instead of the sliced ELL")
     ap.add_argument("--precond", default="none", choices=["none", "amg"],
                     help="inverse_cg: plain CG or aggregation-multigrid preconditioned CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -270,7 +272,7 @@ def main():
                 max_restarts=args.max_restarts, verbose=args.verbose, lanczos_keep=args.keep,
                 method=args.method, inv_precond=args.precond, cg_tol=1e-8, inv_max_outer=100,
                 fiedler_sweep=args.sweep, warm_start=args.warm_start, reorder=args.reorder,
-                batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
+                gather_scatter=args.gather_scatter, batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
                 autotune=args.autotune)
     if args.autotune_cache:
         opts["autotune_cache"] = args.autotune_cache
@@ -328,6 +330,7 @@ def main():
                    "max_restarts": args.max_restarts, "graph": "weighted vertex-shared",
                    "method": args.method, "precond": args.precond, "fiedler_sweep": args.sweep,
                    "warm_start": bool(args.warm_start), "reorder": bool(args.reorder),
+                   "gather_scatter": bool(args.gather_scatter),
                    "batched": not args.unbatched},
         "time_to_partition_ms": dt * 1e3 / args.steps,
         "edge_cut": st["edge_cut"],
@@ -345,7 +348,8 @@ def main():
         "ms_reorder": st["ms_reorder"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": stored_traffic(args.workload, KERNEL_LABEL) if st["tile_rows"] == 1024
+                     "traffic": stored_traffic(args.workload, KERNEL_LABEL)
+                     if st["tile_rows"] == 1024 and not args.gather_scatter and not args.reorder
                      else None,
                      "kernel": KERNEL_LABEL,
                      "tile_rows_level0": st["tile_rows"],

@@ -141,13 +141,20 @@ typedef struct rsb_opts {
   double sweep_gap;         /* relative gap (theta2 - theta1) / theta1 below which
                                the pair is swept (0.1) */
   int32_t reorder;          /* rsb_partition(_batch): 1 = store each mesh's rows in
-                               breadth-first order of its dual graph (from a
-                               pseudo-peripheral element) before the first level,
-                               so that neighbours lie close in memory (the paper
-                               sorts by RCB first; no coordinates are given here).
+                               Cuthill-McKee order of its dual graph (see
+                               rsb_locality_order) before the first level, so that
+                               neighbours lie close in memory (the paper sorts by
+                               RCB first; no coordinates are given here).
                                Element ids, start vectors, tie-breaks and outputs
                                keep the input numbering.  0 (default): input order. */
-  int32_t reserved;
+  int32_t gather_scatter;   /* 1 = the Lanczos SpMV applies the Laplacian in the
+                               paper's gather-scatter form (Sec. 5: element values
+                               summed per mesh vertex and subgraph, then gathered
+                               back per element) instead of the assembled sliced-ELL
+                               matrix; the same operator, so results agree to
+                               rounding.  Needs graph RSB_GRAPH_WEIGHTED, method
+                               RSB_LANCZOS and at most 64 slots per vertex id.
+                               0 (default): sliced ELL. */
 } rsb_opts;
 
 typedef struct rsb_stats {
@@ -216,6 +223,17 @@ int rsb_dual_graph(int64_t nelem, int32_t nv_per_elem, const int64_t *elem_verte
  * Exposed for testing the SpMV.  RSB_EINVAL on bad sizes or weights. */
 int rsb_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
                         const int32_t *weight, const double *x, double *y, const rsb_opts *opts);
+
+/* y = L x in the gather-scatter form (Sec. 5: L = diag(A_w 1) - A_w,
+ * A_w = P^T Q Q^T P over the mesh's vertex ids) for one mesh of nelem
+ * elements with nv_per_elem vertex ids each (a repeated id within an element
+ * counts once), evaluated on the GPU as for opts->gather_scatter = 1 at the
+ * first level.  x, y: nelem doubles, host or device memory as
+ * opts->device_pointers says.  Exposed for testing.  Errors as
+ * rsb_dual_graph, and RSB_EINVAL when a vertex id appears in more than 64
+ * slots. */
+int rsb_gs_apply(int64_t nelem, int32_t nv_per_elem, const int64_t *elem_vertex_ids,
+                 const double *x, double *y, const rsb_opts *opts);
 
 /* The locality order that opts->reorder = 1 gives the level-0 rows, on a
  * caller CSR as in rsb_laplacian_apply: order[k] = row placed at position k

@@ -38,7 +38,7 @@ class Opts(C.Structure):
         ("profile", C.c_int32), ("rows_per_thread", C.c_int32), ("lanczos_keep", C.c_int32),
         ("inv_precond", C.c_int32), ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double),
         ("fiedler_sweep", C.c_int32), ("warm_start", C.c_int32), ("sweep_gap", C.c_double),
-        ("reorder", C.c_int32), ("reserved", C.c_int32),
+        ("reorder", C.c_int32), ("gather_scatter", C.c_int32),
     ]
 
 
@@ -74,6 +74,8 @@ _SIGNATURES = {
                         C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "rsb_laplacian_apply": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p], C.c_int),
+    "rsb_gs_apply": ([C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+                     C.c_int),
     "rsb_locality_order": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                             C.c_void_p], C.c_int),
     "rsb_fiedler": ([C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -223,6 +225,17 @@ def laplacian_apply(row_ptr, col, weight, x, device: bool = False, **kw):
     y, yp = _out(n, np.float64, device)
     _check(lib().rsb_laplacian_apply(n, rp.ptr, c.ptr, w.ptr, xx.ptr, yp, C.byref(o)),
            "rsb_laplacian_apply")
+    return y
+
+
+def gs_apply(ids, x, device: bool = False, **kw):
+    """y = L x in the gather-scatter form (element -> vertex -> element)."""
+    n, nv = _ids_shape(ids)
+    ids_a = _Arr(ids, np.int64, device)
+    o = make_opts(device, **kw)
+    xx = _Arr(x, np.float64, device)
+    y, yp = _out(n, np.float64, device)
+    _check(lib().rsb_gs_apply(n, nv, ids_a.ptr, xx.ptr, yp, C.byref(o)), "rsb_gs_apply")
     return y
 
 

@@ -65,6 +65,10 @@ void check_opts(const rsb_opts *o) {
   if (!(o->sweep_gap >= 0.0)) fail(RSB_EINVAL, "sweep_gap must be >= 0");
   if (o->warm_start != 0 && o->warm_start != 1) fail(RSB_EINVAL, "warm_start must be 0 or 1");
   if (o->reorder != 0 && o->reorder != 1) fail(RSB_EINVAL, "reorder must be 0 or 1");
+  if (o->gather_scatter != 0 && o->gather_scatter != 1)
+    fail(RSB_EINVAL, "gather_scatter must be 0 or 1");
+  if (o->gather_scatter && (o->graph != RSB_GRAPH_WEIGHTED || o->method != RSB_LANCZOS))
+    fail(RSB_EINVAL, "gather_scatter needs graph RSB_GRAPH_WEIGHTED and method RSB_LANCZOS");
   if (o->warm_start && (o->method != RSB_LANCZOS || o->lanczos_keep < 2))
     fail(RSB_EINVAL, "warm_start needs method RSB_LANCZOS with lanczos_keep >= 2");
 }
@@ -192,6 +196,7 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     v.blk = os.blk.get();
     v.grp = os.grp.get();
     v.nnz = (int64_t)((double)L.nnz * L.seg[s].npad / std::max<int64_t>(L.nrows, 1));
+    v.gs.only_seg = s;
     steps += run(v, S1, false);
     RSB_HIP(hipMemcpyAsync(S.st.get() + s, S1.st.get(), sizeof(SegState),
                            hipMemcpyDeviceToDevice, ctx.stream));
@@ -262,6 +267,21 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
   }
   Level L0;
   level0_from_csr(L0, gp, np, rpt, ctx, perm_ptr.empty() ? nullptr : &perm_ptr);
+  // gather-scatter operator: the vertex incidence of all meshes, once
+  GsBase gsb;
+  if (o.gather_scatter) {
+    std::vector<const int64_t *> ids;
+    std::vector<int64_t> ne;
+    for (auto &m : meshes) {
+      ids.push_back(m.d_ids);
+      ne.push_back(m.nelem);
+    }
+    // element -> first-level row
+    DevBuf<int32_t> rank(ctx, std::max<int64_t>(total, 1));
+    fill_i32(rank.get(), total, 0, ctx);
+    gs_rank_of_rows(L0.orig.get(), L0.nrows, rank.get(), ctx);
+    gs_base_build(ids, ne, nv, rank.get(), gsb, ctx);
+  }
   perms.clear();
   for (auto &g : graphs) {
     g.col.release();
@@ -303,6 +323,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     const double prof_ms0 = prof.ms, prof_bytes0 = prof.bytes;
     SolveDev S;
     CompDev C;
+    if (o.gather_scatter) gs_level_build(gsb, *L, total, L->gs, ctx);
     choose_tile(*L, o, work.get(), ctx);
     if (level == 0) st.tile_rows = kBlock * L->rpt;
     solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
@@ -642,6 +663,48 @@ int rsb_laplacian_apply(int64_t n, const int64_t *row_ptr, const int32_t *col_id
     DevBuf<double> yd(ctx, n);
     laplacian_apply_csr(g, xin.p, yd.get(), ctx);
     copy_out(ctx, y, yd.get(), n, dev);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    return RSB_OK;
+  });
+}
+
+int rsb_gs_apply(int64_t nelem, int32_t nv, const int64_t *ids, const double *x, double *y,
+                 const rsb_opts *opts) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    check_mesh(nelem, nv, ids);
+    if (!x || !y) fail(RSB_EINVAL, "bad arguments");
+    Ctx ctx;
+    setup_ctx(ctx, *opts);
+    const bool dev = opts->device_pointers != 0;
+    InArr<int64_t> in;
+    in.init(ctx, ids, nelem * nv, dev);
+    GsBase B;
+    gs_base_build({in.p}, {nelem}, nv, nullptr, B, ctx);
+    // one level holding the whole mesh as one subgraph, rows = elements
+    Level L;
+    L.nrows = round_up(nelem, kWave);
+    L.nseg = 1;
+    std::vector<int32_t> orig(L.nrows, -1);
+    for (int64_t i = 0; i < nelem; ++i) orig[i] = (int32_t)i;
+    L.orig.alloc(ctx, L.nrows);
+    RSB_HIP(hipMemcpyAsync(L.orig.get(), orig.data(), L.nrows * sizeof(int32_t),
+                           hipMemcpyHostToDevice, ctx.stream));
+    SegDev sd{};
+    sd.row0 = 0;
+    sd.n = (int32_t)nelem;
+    sd.npad = (int32_t)L.nrows;
+    L.d_seg.alloc(ctx, 1);
+    RSB_HIP(hipMemcpyAsync(L.d_seg.get(), &sd, sizeof(sd), hipMemcpyHostToDevice, ctx.stream));
+    gs_level_build(B, L, nelem, L.gs, ctx);
+    InArr<double> xin;
+    xin.init(ctx, x, nelem, dev);
+    DevBuf<double> xd(ctx, L.nrows), yd(ctx, L.nrows);
+    RSB_HIP(hipMemsetAsync(xd.get(), 0, L.nrows * sizeof(double), ctx.stream));
+    RSB_HIP(hipMemcpyAsync(xd.get(), xin.p, nelem * sizeof(double), hipMemcpyDeviceToDevice,
+                           ctx.stream));
+    gs_apply(view_of(L).gs, L.nrows, xd.get(), yd.get(), ctx);
+    copy_out(ctx, y, yd.get(), nelem, dev);
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     return RSB_OK;
   });

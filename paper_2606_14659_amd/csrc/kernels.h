@@ -101,6 +101,44 @@ struct SegState {
   int32_t pad;
 };
 
+// The Laplacian in gather-scatter form (Sec. 5: A_w = P^T Q Q^T P,
+// L = diag(A_w 1) - A_w), on the weighted vertex-shared graph.  A group is
+// one mesh vertex within one subgraph; row e's value of L x is the sum over
+// its distinct vertices' groups g of (size_g x_e - U_g), U_g the sum of x
+// over the group's rows.
+constexpr uint32_t kGsNone = 0xFFFFFFFFu;  // slot without a group
+constexpr int kGsMaxDeg = 64;              // most elements sharing one vertex
+
+struct GsView {
+  int nv = 0;                      // vertex slots per row; 0: sliced ELL operator
+  const uint32_t *ev = nullptr;    // [nrows / 64][nv][64] group of each row slot
+  const int32_t *deg = nullptr;    // [nrows] sum of the row's group sizes
+  const uint32_t *gptr = nullptr;  // [ngroups + 1] offsets into gent (< 2^32 pairs)
+  const int32_t *gent = nullptr;   // rows of every group, ascending
+  const int32_t *gseg = nullptr;   // [ngroups] subgraph of the group
+  double *U = nullptr;             // [ngroups] group sums of the vector multiplied
+  int64_t ngroups = 0;
+  int32_t only_seg = -1;           // >= 0: only that subgraph's groups (state slot 0)
+};
+
+// Vertex -> (element, slot) incidence of all meshes of a call, vertices in
+// increasing id; a slot repeating an id already in its element is kGsNone.
+struct GsBase {
+  int nv = 0;
+  int64_t nvert = 0, npairs = 0;
+  DevBuf<int64_t> vptr;    // [nvert + 1]
+  DevBuf<uint32_t> vent;   // [npairs] element * nv + slot, or kGsNone
+};
+
+struct GsLevel {
+  int nv = 0;
+  int64_t ngroups = 0, nent = 0;
+  DevBuf<uint32_t> ev;
+  DevBuf<int32_t> deg, gent, gseg;
+  DevBuf<uint32_t> gptr;
+  DevBuf<double> U;
+};
+
 struct Level {
   int64_t nrows = 0;     // padded rows
   int64_t nchunks = 0;   // nrows / 64
@@ -119,6 +157,7 @@ struct Level {
   DevBuf<int32_t> gid;         // row -> element id within its mesh
   int64_t words = 0;
   int64_t nnz = 0;             // off-diagonal nonzeros (non-padding words)
+  GsLevel gs;                  // gather-scatter operator, when selected
 };
 
 // Non-owning view of a level, or of some of its segments: vectors keep the
@@ -134,6 +173,7 @@ struct LevelView {
   const int32_t *gid = nullptr;
   const int32_t *orig = nullptr;
   int64_t nnz = 0;
+  GsView gs;
 };
 
 inline LevelView view_of(const Level &L) {
@@ -151,8 +191,29 @@ inline LevelView view_of(const Level &L) {
   v.gid = L.gid.get();
   v.orig = L.orig.get();
   v.nnz = L.nnz;
+  if (L.gs.nv > 0) {
+    v.gs.nv = L.gs.nv;
+    v.gs.ev = L.gs.ev.get();
+    v.gs.deg = L.gs.deg.get();
+    v.gs.gptr = L.gs.gptr.get();
+    v.gs.gent = L.gs.gent.get();
+    v.gs.gseg = L.gs.gseg.get();
+    v.gs.U = L.gs.U.get();
+    v.gs.ngroups = L.gs.ngroups;
+  }
   return v;
 }
+
+// Gather-scatter operator: the incidence of the call's meshes, vertices
+// ordered by the least rank[e] of their elements (rank: element -> first
+// level row; null: the element index), and its groups on one level.
+void gs_base_build(const std::vector<const int64_t *> &ids, const std::vector<int64_t> &nelem,
+                   int nv, const int32_t *rank, GsBase &B, Ctx &ctx);
+void gs_level_build(const GsBase &B, const Level &L, int64_t nelem_total, GsLevel &G, Ctx &ctx);
+// rank[orig[r]] = r for the live rows r of a level
+void gs_rank_of_rows(const int32_t *orig, int64_t nrows, int32_t *rank, Ctx &ctx);
+// y = L x on the rows of a level (FP64; vectors indexed by row).
+void gs_apply(const GsView &g, int64_t nrows, const double *x, double *y, Ctx &ctx);
 
 // Fill host block/group tables of a level from its segment table and
 // upload all three tables.

@@ -82,6 +82,7 @@ struct LzArgs {
   uint64_t seed;
   const int32_t *orig;     // row -> element index of the whole call (-1: padding)
   const double *warm;      // warm start by element (NaN: none), or null
+  GsView gs;               // gather-scatter operator (gs.nv > 0) instead of the sliced ELL
 };
 
 // Vector types of step j: STEP 1 reads Y and works in FP64; STEP 2 reads the
@@ -354,7 +355,8 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
     if (MODE == 0) {
       const Tin wi = Win[row];
       const double qd = ((double)wi - c * a.U0[row]) * sc;
-      const Tw lq = (Tw)(sc * (double)lap_row<Tin>(a.chunk_ptr, a.cols, Win, row, wi));
+      const Tin lw = a.gs.nv ? gs_row<Tin>(a.gs, row, wi) : lap_row<Tin>(a.chunk_ptr, a.cols, Win, row, wi);
+      const Tw lq = (Tw)(sc * (double)lw);
       if (STEP == 1) {
         q = qd;
         if (oks[r]) a.Q1[row] = qd;
@@ -534,7 +536,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
     const int64_t row = tr.row[r];
     const double wi = a.Y[row];
     const double y = (wi - c * a.U0[row]) * sc;
-    const double ly = sc * lap_row<double>(a.chunk_ptr, a.cols, a.Y, row, wi);
+    const double ly =
+        sc * (a.gs.nv ? gs_row<double>(a.gs, row, wi) : lap_row<double>(a.chunk_ptr, a.cols, a.Y, row, wi));
     const double rr = ly - th * y;
     if (tr.ok[r]) {
       // the normalised Ritz vector is q_1 of a thick-restarted next cycle
@@ -630,6 +633,42 @@ __global__ __launch_bounds__(kBlock) void k_lz_ritz_thick(LzArgs<T> a) {
   block_reduce_into<2>(p, red, vals, 2);
   write_partials(a, lb, vals, 2);
 }
+
+// ----------------------------------------------------------------------------
+// Gather-scatter operator: the group sums of the vector that the next launch
+// multiplies (the step's input, or the Ritz vector for the residual), for
+// the groups of the segments that launch works on.
+// ----------------------------------------------------------------------------
+template <typename T>
+__device__ inline bool gs_group_live(const LzArgs<T> &a, int64_t g, int j, bool resid) {
+  int sg = a.gs.gseg[g];
+  if (a.gs.only_seg >= 0) {
+    if (sg != a.gs.only_seg) return false;
+    sg = 0;
+  }
+  const SegState S = a.st[sg];
+  return resid ? S.active != 0 : (S.active && !S.cycle_done && j >= S.j0);
+}
+
+template <typename T, int STEP>
+__global__ __launch_bounds__(kBlock) void k_lz_gsum(LzArgs<T> a, int j) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.gs.ngroups) return;
+  const uint32_t p0 = a.gs.gptr[g], p1 = a.gs.gptr[g + 1];
+  if (!gs_group_live(a, g, j, false)) return;
+  gs_group_sum(a.gs, g, p0, p1, step_in<T, STEP>(a, j));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lz_gsum_y(LzArgs<T> a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.gs.ngroups) return;
+  const uint32_t p0 = a.gs.gptr[g], p1 = a.gs.gptr[g + 1];
+  if (!gs_group_live(a, g, 0, true)) return;
+  gs_group_sum(a.gs, g, p0, p1, a.Y);
+}
+
+inline unsigned gs_grid(const GsView &g) { return (unsigned)((g.ngroups + kBlock - 1) / kBlock); }
 
 // ----------------------------------------------------------------------------
 // Reductions and the per-segment logic that finishes each launch above.
@@ -1261,6 +1300,7 @@ struct LzLaunch {
   template <int STEP>
   static void step(const LzArgs<T> &a, int nblk, int ngrp, int j, hipStream_t s,
                    hipEvent_t *ev) {
+    if (a.gs.nv) k_lz_gsum<T, STEP><<<gs_grid(a.gs), kBlock, 0, s>>>(a, j);
     if (ev) (void)hipEventRecord(ev[0], s);
     k_lz_project<T, RPT, 0, STEP><<<nblk, proj_threads<RPT>(), 0, s>>>(a, j);
     if (ev) (void)hipEventRecord(ev[1], s);
@@ -1294,6 +1334,7 @@ struct LzLaunch {
       k_lz_ritz<T, RPT><<<nblk, kBlock, 0, s>>>(a);
     }
     k_lz_reduce<T, OP_RITZ><<<ngrp, kBlock, 0, s>>>(a, 0);
+    if (a.gs.nv) k_lz_gsum_y<T><<<gs_grid(a.gs), kBlock, 0, s>>>(a);
     k_lz_residual<T, RPT><<<nblk, kBlock, 0, s>>>(a);
     k_lz_reduce<T, OP_RESID><<<ngrp, kBlock, 0, s>>>(a, 0);
   }
@@ -1377,6 +1418,7 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
   a.gid = L.gid;
   a.orig = L.orig;
   a.warm = p.warm;
+  a.gs = L.gs;
   // workspace layout: U0, Q1, Y, Wd (FP64), then V (m+1 slots), Wt0, Wt1 (T)
   double *wd = (double *)work;
   a.U0 = wd;
@@ -1490,6 +1532,11 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
         read_state();
         const double st = (double)sizeof(T);
         const double nnz_per_row = (double)p.nnz / (double)std::max<int64_t>(L.nrows, 1);
+        // operator bytes per row: sliced ELL words, or the gather-scatter
+        // slot words, degree and group sums (each group read once)
+        const double op_row = L.gs.nv ? 4.0 * L.gs.nv + 4.0 +
+                                            8.0 * (double)L.gs.ngroups / (double)std::max<int64_t>(L.nrows, 1)
+                                      : 4.0 * nnz_per_row;
         for (int j = 3; j <= flags[1]; ++j) {
           float ms = 0.f;
           RSB_HIP(hipEventElapsedTime(&ms, res.ev[2 * j], res.ev[2 * j + 1]));
@@ -1501,7 +1548,7 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
             }
           p.prof->ms += ms;
           p.prof->launches += 1;
-          p.prof->bytes += 4.0 * (rows + 1) + 4.0 * nnz_per_row * rows +
+          p.prof->bytes += (L.gs.nv ? 0.0 : 4.0 * (rows + 1)) + op_row * rows +
                            rows * (st + st + st + 16.0 + (j - 2) * st) + kept_rows * (8.0 - st);
         }
       }
@@ -1561,6 +1608,7 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
   a.ps = S.pstride;
   a.chunk_ptr = L.chunk_ptr;
   a.cols = L.cols;
+  a.gs = L.gs;
   double *wd = (double *)work;
   a.U0 = wd;
   a.Q1 = wd + L.nrows;
@@ -1594,6 +1642,7 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
                            hipMemcpyDeviceToDevice, ctx.stream);
       if (err != hipSuccess) break;
       (void)hipEventRecord(e0, ctx.stream);
+      if (a.gs.nv) k_lz_gsum<T, 3><<<gs_grid(a.gs), kBlock, 0, ctx.stream>>>(a, j);
       k_lz_project<T, RPT, 0, 3><<<nblk, proj_threads<RPT>(), 0, ctx.stream>>>(a, j);
       k_lz_reduce<T, OP_PROJ0><<<ngrp, kBlock, 0, ctx.stream>>>(a, j);
       k_lz_update<T, RPT, 1, 3><<<nblk, kBlock, 0, ctx.stream>>>(a, j);

@@ -177,4 +177,46 @@ __device__ inline X lap_row(const int64_t *__restrict__ chunk_ptr, const uint32_
   return acc;
 }
 
+// Gather-scatter row (Sec. 5): (L x)_e = deg_e x_e - sum of U over the row's
+// vertex groups, U already holding the group sums of x.  Slots are read four
+// at a time (loads in flight together); a slot without a group adds 0.
+template <typename X>
+__device__ inline X gs_row(const GsView &g, int64_t row, X xi) {
+  const uint32_t *ep = g.ev + (row >> 6) * 64 * (int64_t)g.nv + (row & 63);
+  double s = 0.0;
+  for (int k0 = 0; k0 < g.nv; k0 += 4) {
+    uint32_t w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = (k0 + u < g.nv) ? ld_stream(ep + (int64_t)(k0 + u) * 64) : kGsNone;
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = (w[u] != kGsNone) ? g.U[w[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += v[u];
+  }
+  return (X)((double)g.deg[row] * (double)xi - s);
+}
+
+// U_gi = sum of x over the rows gent[a..b) of group gi, in ascending row
+// order (FP64); four rows' loads are issued before they are added (eight
+// measured slower: fewer waves in flight).
+template <typename X>
+__device__ inline void gs_group_sum(const GsView &g, int64_t gi, uint32_t a, uint32_t b,
+                                    const X *__restrict__ x) {
+  double s = 0.0;
+  uint32_t k = a;
+  for (; k + 4 <= b; k += 4) {
+    int32_t r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) r[u] = g.gent[k + u];
+    X v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = x[r[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += (double)v[u];
+  }
+  for (; k < b; ++k) s += (double)x[g.gent[k]];
+  g.U[gi] = s;
+}
+
 }  // namespace rsb

@@ -23,7 +23,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for need in ("rsb_opts_init", "rsb_partition", "rsb_fiedler", "rsb_dual_graph",
                  "rsb_partition_batch", "rsb_strerror", "rsb_last_error", "rsb_split",
-                 "rsb_laplacian_apply", "rsb_locality_order"):
+                 "rsb_laplacian_apply", "rsb_locality_order", "rsb_gs_apply"):
         assert need in names
 
 
@@ -61,7 +61,8 @@ def test_bad_options_rejected_before_any_device_call():
                          ("inv_precond", 2), ("inv_precond", -1), ("amg_smooth", -1),
                          ("amg_smooth", 17), ("amg_sigma", 0.0), ("amg_sigma", 2.0),
                          ("fiedler_sweep", -1), ("fiedler_sweep", 65), ("sweep_gap", -1.0),
-                         ("warm_start", 2), ("warm_start", -1), ("reorder", 2)):
+                         ("warm_start", 2), ("warm_start", -1), ("reorder", 2),
+                         ("gather_scatter", 2), ("gather_scatter", -1)):
         oo = rsb.Opts.from_buffer_copy(o)
         setattr(oo, field, value)
         part = np.zeros(2, dtype=np.int32)
@@ -78,6 +79,14 @@ def test_bad_options_rejected_before_any_device_call():
         assert rsb.lib().rsb_partition(2, 4, ids.ctypes.data_as(C.c_void_p), 2, C.byref(oo),
                                        part.ctypes.data_as(C.c_void_p), None) == rsb.EINVAL
         oo.fiedler_sweep, oo.warm_start = 0, 1
+        part = np.zeros(2, dtype=np.int32)
+        assert rsb.lib().rsb_partition(2, 4, ids.ctypes.data_as(C.c_void_p), 2, C.byref(oo),
+                                       part.ctypes.data_as(C.c_void_p), None) == rsb.EINVAL
+    # the gather-scatter operator is the weighted Laplacian, applied by Lanczos
+    for graph, method in ((1, 0), (2, 0), (0, 1)):
+        oo = rsb.Opts.from_buffer_copy(o)
+        oo.gather_scatter, oo.graph, oo.method = 1, graph, method
+        oo.warm_start = 0
         part = np.zeros(2, dtype=np.int32)
         assert rsb.lib().rsb_partition(2, 4, ids.ctypes.data_as(C.c_void_p), 2, C.byref(oo),
                                        part.ctypes.data_as(C.c_void_p), None) == rsb.EINVAL
