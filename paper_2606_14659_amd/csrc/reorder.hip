@@ -2,18 +2,19 @@
 //
 // The solver streams every row of a level once per Lanczos step and gathers
 // the vector at each row's neighbours.  With elements in an arbitrary order
-// (the paper's partitioner starts from an effectively random distribution
-// and pre-sorts by recursive coordinate bisection for locality) those
-// gathers touch the whole vector.  Coordinates are not part of the input,
-// so the rows are ordered by breadth-first levels of the graph instead (the
-// Cuthill-McKee order): a first search from row 0 finds the farthest row
+// those gathers touch the whole vector.  The paper's partitioner also starts
+// from an effectively random distribution and pre-sorts it by recursive
+// coordinate bisection for locality (Sec. 5, Sec. 8).  Coordinates are not
+// part of the input, so the rows are ordered by the graph instead, in
+// Cuthill-McKee order: a first search from row 0 finds the farthest row
 // (smallest index among the farthest), a second search from there gives
 // every row its level; rows are grouped by level (stable radix sort), and
 // level by level each row is placed by the least position of its neighbours
 // in the level before (ties in input order), so that a run of rows in one
 // level gathers from a run in the next; rows the search does not reach go
-// last in their old order.  The order changes only where rows live: element ids, start
-// vectors, tie-breaks and outputs still follow the input numbering.
+// last in their old order.  The order changes only where rows live: element
+// ids, start vectors, tie-breaks and outputs still follow the input
+// numbering.
 #include <algorithm>
 
 #include "common.h"
