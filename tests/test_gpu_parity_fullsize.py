@@ -242,3 +242,98 @@ def test_c5b_batch64_16_parts():
     for b in (int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2])):
         s1, p1, _ = rsb.partition(meshes[b].ids, 16, **BENCH)
         assert np.array_equal(p1, parts[b])
+
+
+def test_c5a_gather_scatter_operator_sampled_rows():
+    # the gather-scatter operator at full size against the definition
+    # (sum over the element's neighbours of s_ij (x_i - x_j)) on sampled rows
+    import torch
+    mesh = mg.box256x128_clustered10()
+    x = np.random.default_rng(11).standard_normal(mesh.nelem)
+    y = _host(rsb.gs_apply(_torch_ids(mesh.ids), torch.as_tensor(x).cuda(), device=True))
+    rng = np.random.default_rng(12)
+    rows = np.sort(rng.choice(mesh.nelem, size=300, replace=False))
+    ref = brute_force_rows(mesh.ids, rows)
+    for i in rows:
+        nb = ref[int(i)]
+        want = sum(w * (x[i] - x[j]) for j, w in nb)
+        scale = sum(w * (abs(x[i]) + abs(x[j])) for j, w in nb)
+        assert abs(y[i] - want) <= 1e-12 * scale, f"row {i}"
+
+
+def test_c5a_options_as_benchmarked():
+    # the benchmark with the gather-scatter operator, and on the shuffled
+    # mesh with the locality order: balanced, cut accounting exact, cut
+    # within 0.5% of the default run's
+    mesh = mg.box256x128_clustered10()
+    ids = _torch_ids(mesh.ids)
+    st0, p0, s0 = rsb.partition(ids, 4096, device=True, **BENCH)
+    st1, p1, s1 = rsb.partition(ids, 4096, device=True, gather_scatter=1, **BENCH)
+    assert st0 >= 0 and st1 >= 0
+    p1 = _host(p1)
+    check_balance(p1, mesh.nelem, 4096)
+    rp, col, w = (_host(a) for a in rsb.dual_graph(ids, device=True))
+    cut1, pairs1 = cut_from_csr(rp, col, w, p1)
+    assert s1["edge_cut"] == cut1 and s1["cut_pairs"] == pairs1
+    assert abs(cut1 - s0["edge_cut"]) <= 0.005 * s0["edge_cut"]
+    print(f"C5a cut: sliced ELL {s0['edge_cut']:.0f}, gather-scatter {cut1:.0f}")
+    del rp, col, w
+    sh = mg.shuffle_elements(mesh, mg.config_seed(4) + 7)
+    sids = _torch_ids(sh.ids)
+    st2, p2, s2 = rsb.partition(sids, 4096, device=True, reorder=1, **BENCH)
+    assert st2 >= 0
+    p2 = _host(p2)
+    check_balance(p2, sh.nelem, 4096)
+    rp, col, w = (_host(a) for a in rsb.dual_graph(sids, device=True))
+    cut2, pairs2 = cut_from_csr(rp, col, w, p2)
+    assert s2["edge_cut"] == cut2 and s2["cut_pairs"] == pairs2
+    assert abs(cut2 - s0["edge_cut"]) <= 0.005 * s0["edge_cut"]
+    print(f"C5a shuffled + locality order cut {cut2:.0f}, ordering {s2['ms_reorder']:.0f} ms")
+
+
+def _bfs_levels(rp, col, src):
+    n = len(rp) - 1
+    dist = np.full(n, -1, dtype=np.int64)
+    dist[src] = 0
+    front = np.array([src], dtype=np.int64)
+    d = 0
+    while len(front):
+        starts, ends = rp[front], rp[front + 1]
+        lens = ends - starts
+        idx = np.repeat(starts - np.cumsum(lens) + lens, lens) + np.arange(lens.sum())
+        nb = np.unique(col[idx])
+        nb = nb[dist[nb] < 0]
+        d += 1
+        dist[nb] = d
+        front = nb
+    return dist
+
+
+def test_c5a_locality_order_properties():
+    # the Cuthill-McKee order of the shuffled benchmark mesh: a permutation
+    # starting at the row farthest from row 0 (least index among them),
+    # breadth-first levels never decreasing, and within a level the least
+    # position of a neighbour in the level before never decreasing (sampled)
+    sh = mg.shuffle_elements(mg.box256x128_clustered10(), mg.config_seed(4) + 7)
+    rp, col, w = (_host(a) for a in rsb.dual_graph(_torch_ids(sh.ids), device=True))
+    order = _host(rsb.locality_order(rp, col, w))
+    n = len(rp) - 1
+    assert np.array_equal(np.sort(order), np.arange(n))
+    d0 = _bfs_levels(rp, col, 0)
+    far = int(np.flatnonzero(d0 == d0.max())[0])
+    assert order[0] == far
+    lev = _bfs_levels(rp, col, far)
+    assert (lev >= 0).all()  # one piece
+    lo = lev[order]
+    assert np.all(np.diff(lo) >= 0)
+    pos = np.empty(n, dtype=np.int64)
+    pos[order] = np.arange(n)
+    rng = np.random.default_rng(13)
+    for k in rng.choice(np.arange(1, n - 1), size=2000, replace=False):
+        if lo[k] != lo[k + 1]:
+            continue
+        keys = []
+        for i in (order[k], order[k + 1]):
+            nb = col[rp[i]:rp[i + 1]]
+            keys.append((pos[nb[lev[nb] == lev[i] - 1]].min(), i))
+        assert keys[0] < keys[1], f"position {k}"
