@@ -126,34 +126,68 @@ __global__ void k_cc_init_link(const int64_t *__restrict__ chunk_ptr,
   parent[r] = best;
 }
 
+// Every row first points at the root of its tree (read-only walk, each row
+// storing only its own pointer).
+__global__ void k_cc_flatten(int32_t *parent, const int32_t *__restrict__ orig, int64_t nrows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows || orig[i] < 0) return;
+  const int r = cc_root(parent, (int)i);
+  cc_store(&parent[i], r);
+}
+
+// Hooking over the edges still needed (the sampling idea of Sutton et al.,
+// "Optimizing parallel graph connectivity computation via subgraph
+// sampling", 2018).  After the initial links every segment's first row is a
+// root (it has no lower neighbour in its segment) and most rows hang under
+// it.  A row whose pointer is that root skips all its edges: it is in that
+// component, and any edge to a row outside it is hooked by the other end,
+// which walks all its edges.  The component only grows during the launch,
+// so a row that sees the root is in it whenever it looks.
+// Join the trees of rows v and j: the larger root is linked under the
+// smaller by compare-and-swap, retried from whatever root it met.
+__device__ inline void cc_hook_pair(int32_t *parent, int v, int j) {
+  int a = cc_rep(parent, v), b = cc_rep(parent, j);
+  while (a != b) {
+    if (a < b) {
+      int ret = atomicCAS(&parent[b], b, a);
+      if (ret == b) break;
+      b = ret;
+    } else {
+      int ret = atomicCAS(&parent[a], a, b);
+      if (ret == a) break;
+      a = ret;
+    }
+  }
+}
+
+// SAMPLE: one more sampled edge per row, its greatest neighbour, which
+// joins most trees whose root has no lower neighbour (rows just past a
+// hole) to the rest.
+template <bool SAMPLE>
 __global__ void k_cc_hook(const int64_t *__restrict__ chunk_ptr, const uint32_t *__restrict__ cols,
-                          const int32_t *__restrict__ orig, int32_t *parent, int64_t nrows) {
+                          const int32_t *__restrict__ orig, const SegDev *__restrict__ seg,
+                          int nseg, int32_t *parent, int64_t nrows) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   if (orig[r] < 0) return;
+  if (!SAMPLE) {
+    const int64_t first = seg[seg_of_row(seg, nseg, r)].row0;
+    if (cc_load(&parent[r]) == (int32_t)first) return;
+  }
   int64_t c = r / kWave;
   int lane = (int)(r & (kWave - 1));
   int64_t p = chunk_ptr[c];
   int width = (int)((chunk_ptr[c + 1] - p) / kWave);
   int v = (int)r;
+  int top = -1;
   for (int k = 0; k < width; ++k) {
     uint32_t w = cols[p + (int64_t)k * kWave + lane];
     if (colw_wt(w) == 0) continue;
     int j = (int)colw_col(w);
-    if (j >= v) continue;
-    int a = cc_rep(parent, v), b = cc_rep(parent, j);
-    while (a != b) {
-      if (a < b) {
-        int ret = atomicCAS(&parent[b], b, a);
-        if (ret == b) break;
-        b = ret;
-      } else {
-        int ret = atomicCAS(&parent[a], a, b);
-        if (ret == a) break;
-        a = ret;
-      }
-    }
+    if (SAMPLE) top = max(top, j);
+    else cc_hook_pair(parent, v, j);
   }
+  if (SAMPLE && top > v) cc_hook_pair(parent, v, top);
 }
 
 __global__ void k_cc_compress(int32_t *parent, int32_t *__restrict__ size,
@@ -843,8 +877,15 @@ void components_and_targets(Level &L, CompDev &C, SolveDev &S, Ctx &ctx) {
   k_cc_init_link<<<g, kBlock, 0, ctx.stream>>>(L.chunk_ptr.get(), L.cols.get(), L.orig.get(),
                                                C.root.get(), n);
   RSB_LAUNCHED();
-  k_cc_hook<<<g, kBlock, 0, ctx.stream>>>(L.chunk_ptr.get(), L.cols.get(), L.orig.get(),
-                                          C.root.get(), n);
+  k_cc_flatten<<<g, kBlock, 0, ctx.stream>>>(C.root.get(), L.orig.get(), n);
+  RSB_LAUNCHED();
+  k_cc_hook<true><<<g, kBlock, 0, ctx.stream>>>(L.chunk_ptr.get(), L.cols.get(), L.orig.get(),
+                                                L.d_seg.get(), L.nseg, C.root.get(), n);
+  RSB_LAUNCHED();
+  k_cc_flatten<<<g, kBlock, 0, ctx.stream>>>(C.root.get(), L.orig.get(), n);
+  RSB_LAUNCHED();
+  k_cc_hook<false><<<g, kBlock, 0, ctx.stream>>>(L.chunk_ptr.get(), L.cols.get(), L.orig.get(),
+                                                 L.d_seg.get(), L.nseg, C.root.get(), n);
   RSB_LAUNCHED();
   k_cc_compress<<<g, kBlock, 0, ctx.stream>>>(C.root.get(), C.size.get(), L.orig.get(), n);
   RSB_LAUNCHED();
