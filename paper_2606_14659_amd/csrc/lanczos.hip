@@ -1014,6 +1014,10 @@ __device__ inline int sturm_arrow(const double *a, const double *b2, const doubl
   return cnt;
 }
 
+// MB >= rows of the projected matrix (lanczos_m), KB >= pairs kept: the
+// per-lane work arrays take 4 MB KB doubles of LDS, so the bucket decides
+// how many segments a compute unit works on at once.
+template <int MB, int KB>
 __global__ __launch_bounds__(kWave) void k_trieig_arrow(SegState *__restrict__ st,
                                                         const double *__restrict__ alpha,
                                                         const double *__restrict__ beta,
@@ -1021,10 +1025,9 @@ __global__ __launch_bounds__(kWave) void k_trieig_arrow(SegState *__restrict__ s
                                                         double *__restrict__ tvec,
                                                         double *__restrict__ tvals, int ps,
                                                         int nkcap, int keep, int nseg) {
-  __shared__ double ad[kMaxM], bd[kMaxM], b2[kMaxM], sv[kMaxKeep], s2[kMaxKeep];
+  __shared__ double ad[MB], bd[MB], b2[MB], sv[KB], s2[KB];
   // per-lane work of the inverse iteration, [row][lane]
-  __shared__ double wd[kMaxM][kMaxKeep], wu[kMaxM][kMaxKeep], wu2[kMaxM][kMaxKeep],
-      wr[kMaxM][kMaxKeep];
+  __shared__ double wd[MB][KB], wu[MB][KB], wu2[MB][KB], wr[MB][KB];
   __shared__ double red[kWave];
   const int seg = blockIdx.x;
   if (seg >= nseg) return;
@@ -1063,19 +1066,45 @@ __global__ __launch_bounds__(kWave) void k_trieig_arrow(SegState *__restrict__ s
   const double thr = 1e-10 * S.tnorm;
   const int c0 = sturm_arrow(ad, b2, s2, nk, k, thr);
   int nv = (keep > 0) ? min(min(keep, k - 1), k - c0) : 1;
-  nv = max(1, min(nv, kMaxKeep));
+  nv = max(1, min(nv, KB));
   const double tiny = fmax(scale, 1e-300) * 2.220446049250313e-16;
-  double th = 0.0;
-  if (lane < nv) {
-    const int target = min(c0 + 1 + lane, k);
-    double l0 = fmax(lo, thr), h0 = hi + 1e-12 * fabs(hi) + 1e-300;
+  // Multisection: GS lanes per eigenvalue (group c = lane / GS finds the
+  // c-th one) each count at one of GS interior points of the group's
+  // bracket; the bracket shrinks to the two points around the first count
+  // that reaches the target, until no interior point is left.
+  constexpr int GS = kWave / KB;
+  const int grp = lane / GS, sub = lane % GS;
+  double l0 = fmax(lo, thr), h0 = hi + 1e-12 * fabs(hi) + 1e-300;
+  {
+    const int target = min(c0 + 1 + grp, k);
+    bool done = grp >= nv;
+    const unsigned long long gm = (((1ull << (GS - 1)) << 1) - 1ull) << (grp * GS);
     for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (l0 + h0);
-      if (!(mid > l0 && mid < h0)) break;
-      if (sturm_arrow(ad, b2, s2, nk, k, mid) >= target) h0 = mid;
-      else l0 = mid;
+      const double x = l0 + (h0 - l0) * (double)(sub + 1) / (double)(GS + 1);
+      // a point rounded onto an end of the bracket takes that end's side
+      const bool inside = x > l0 && x < h0;
+      const bool ge = inside ? sturm_arrow(ad, b2, s2, nk, k, x) >= target : x >= h0;
+      const unsigned long long any_inside = __ballot(inside) & gm;
+      const unsigned long long hit = __ballot(ge) & gm;
+      // first point of the group whose count reaches the target (all lanes
+      // take part in the shuffles)
+      const int f = hit ? (__ffsll((unsigned long long)hit) - 1 - grp * GS) : GS;
+      const double xf = __shfl(x, grp * GS + (f < GS ? f : 0), kWave);
+      const double xp = __shfl(x, grp * GS + (f > 0 ? f - 1 : 0), kWave);
+      if (!done) {
+        const double nl = (f == 0) ? l0 : xp, nh = (f == GS) ? h0 : xf;
+        if (!any_inside || !(nl < nh) || (nl == l0 && nh == h0)) {
+          done = true;
+        } else {
+          l0 = nl;
+          h0 = nh;
+        }
+      }
+      if (__ballot(!done) == 0ull) break;
     }
-    th = 0.5 * (l0 + h0);
+  }
+  double th = __shfl(0.5 * (l0 + h0), min(lane, KB - 1) * GS, kWave);
+  if (lane < nv) {
     // distinct start vectors per lane (a fixed hash of row and lane), so
     // that close eigenvalues do not start from the same vector
     for (int i = 0; i < k; ++i) {
@@ -1175,7 +1204,7 @@ __global__ __launch_bounds__(kWave) void k_trieig_arrow(SegState *__restrict__ s
     }
   }
   __syncthreads();
-  __shared__ double G[kMaxKeep][kMaxKeep], U[kMaxKeep][kMaxKeep], gev[kMaxKeep];
+  __shared__ double G[KB][KB], U[KB][KB], gev[KB];
   if (lane < nv)
     for (int c2 = 0; c2 < nv; ++c2) {
       double g = 0.0;
@@ -1290,6 +1319,24 @@ __global__ void k_flags_reset(int32_t *flags) {
   flags[2] = 0;
 }
 
+template <int MB, int KB, typename T>
+void trieig_arrow_bucket(const LzArgs<T> &a, int nseg, hipStream_t s) {
+  k_trieig_arrow<MB, KB><<<nseg, kWave, 0, s>>>(a.st, a.alpha, a.beta, a.arrow, a.tvec, a.tvals,
+                                               a.ps, a.nkcap, a.keep, nseg);
+}
+
+template <typename T>
+void trieig_arrow_launch(const LzArgs<T> &a, int nseg, hipStream_t s) {
+  static_assert(kMaxM <= 256 && kMaxKeep <= 16, "tri-eig buckets");
+  if (a.m <= 64) {
+    if (a.keep <= 8) trieig_arrow_bucket<64, 8>(a, nseg, s);
+    else trieig_arrow_bucket<64, 16>(a, nseg, s);
+  } else {
+    if (a.keep <= 8) trieig_arrow_bucket<256, 8>(a, nseg, s);
+    else trieig_arrow_bucket<256, 16>(a, nseg, s);
+  }
+}
+
 template <typename T, int RPT>
 struct LzLaunch {
   static constexpr int kRpt = RPT;
@@ -1324,8 +1371,7 @@ struct LzLaunch {
       else step<3>(a, nblk, ngrp, j, s, ev ? ev + 2 * j : nullptr);
     }
     if (a.keep > 0) {
-      k_trieig_arrow<<<nseg, kWave, 0, s>>>(a.st, a.alpha, a.beta, a.arrow, a.tvec, a.tvals,
-                                            a.ps, a.nkcap, a.keep, nseg);
+      trieig_arrow_launch(a, nseg, s);
       if (a.keep <= 4) k_lz_ritz_thick<T, RPT, 4><<<nblk, kBlock, 0, s>>>(a);
       else if (a.keep <= 8) k_lz_ritz_thick<T, RPT, 8><<<nblk, kBlock, 0, s>>>(a);
       else k_lz_ritz_thick<T, RPT, 16><<<nblk, kBlock, 0, s>>>(a);
