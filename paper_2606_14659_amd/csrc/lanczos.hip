@@ -679,34 +679,38 @@ template <typename T, int OP>
 __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
   __shared__ double vals[2 * kMaxM + 8];
   const int g = blockIdx.x;
-  const int s = a.grp[g].seg;
+  const GrpDev G = a.grp[g];
+  const int s = G.seg;
+  // the segment's state and table entry are loaded together with the
+  // group's partial sums (a short chain of dependent loads is most of this
+  // launch's time); whether the segment takes part is decided after
   const SegState S = a.st[s];
-  int nval;
+  const SegDev sg = a.seg[s];
+  const int nval = (OP == OP_BEGIN || OP == OP_RITZ) ? 2
+                   : (OP == OP_PROJ0) ? (a.keep > 0 ? 2 * j + 2 : j + 2)
+                   : (OP == OP_PROJ1) ? j + 2
+                   : (OP == OP_UPD1 || OP == OP_UPD2) ? 1
+                   : 3;
+  group_sums(a, G, vals, nval);
+  bool take;
   switch (OP) {
     case OP_BEGIN:
-      if (!S.solve) return;
-      nval = 2;
+      take = S.solve != 0;
       break;
     case OP_PROJ0:
     case OP_UPD1:
-      if (!S.active || S.cycle_done || j < S.j0) return;
-      nval = (OP == OP_PROJ0) ? (a.keep > 0 ? 2 * j + 2 : j + 2) : 1;
+      take = S.active && !S.cycle_done && j >= S.j0;
       break;
     case OP_PROJ1:
     case OP_UPD2:
-      if (!S.active || S.cycle_done || j < S.j0 || !S.need2) return;
-      nval = (OP == OP_PROJ1) ? j + 2 : 1;
-      break;
-    case OP_RITZ:
-      if (!S.active) return;
-      nval = 2;
+      take = S.active && !S.cycle_done && j >= S.j0 && S.need2;
       break;
     default:
-      if (!S.active) return;
-      nval = 3;
+      take = S.active != 0;
       break;
   }
-  if (!group_reduce(a, g, vals, nval)) return;
+  if (!take) return;
+  if (!group_finish(a, g, G, sg, vals, nval)) return;
   double *hs = a.h + (int64_t)s * a.ps;
   if (OP == OP_PROJ0 || OP == OP_PROJ1) {
     if (OP == OP_PROJ0 && a.keep > 0) {

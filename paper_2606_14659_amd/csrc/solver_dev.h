@@ -65,16 +65,23 @@ __device__ inline void sum_rows(const double *__restrict__ src, int n, int ps, i
   }
 }
 
-// Reduction-kernel side (block g = group g).  Returns true in the one block
-// that finishes the segment; there vals[0..nval) holds the segment totals.
+// Reduction-kernel side (block g = group g), first level: the group's
+// block partials summed into vals[0..nval).  It only reads, so a caller may
+// run it before it knows whether the segment takes part.
 template <typename A>
-__device__ bool group_reduce(const A &a, int g, double *vals, int nval) {
+__device__ inline void group_sums(const A &a, const GrpDev &G, double *vals, int nval) {
+  __shared__ double lds[kBlock];
+  sum_rows(a.part + (int64_t)G.blk0 * a.ps, G.nblk, a.ps, nval, vals, lds);
+}
+
+// Second level, after group_sums: returns true in the one block that
+// finishes the segment; there vals[0..nval) holds the segment totals.
+template <typename A>
+__device__ bool group_finish(const A &a, int g, const GrpDev &G, const SegDev &sg, double *vals,
+                             int nval) {
   __shared__ double lds[kBlock];
   __shared__ int s_flag;
   const int t = threadIdx.x;
-  const GrpDev G = a.grp[g];
-  const SegDev sg = a.seg[G.seg];
-  sum_rows(a.part + (int64_t)G.blk0 * a.ps, G.nblk, a.ps, nval, vals, lds);
   if (sg.ngrp == 1) return true;
   for (int i = t; i < nval; i += kBlock) a.gpart[(int64_t)g * a.ps + i] = vals[i];
   __threadfence();
@@ -89,6 +96,14 @@ __device__ bool group_reduce(const A &a, int g, double *vals, int nval) {
   if (t == 0) a.scnt[G.seg] = 0;
   sum_rows(a.gpart + (int64_t)sg.grp0 * a.ps, sg.ngrp, a.ps, nval, vals, lds);
   return true;
+}
+
+template <typename A>
+__device__ bool group_reduce(const A &a, int g, double *vals, int nval) {
+  const GrpDev G = a.grp[g];
+  const SegDev sg = a.seg[G.seg];
+  group_sums(a, G, vals, nval);
+  return group_finish(a, g, G, sg, vals, nval);
 }
 
 // Rows of a block tile.  Thread t owns rows t, t + 256, ... (RPT of them); a
