@@ -13,7 +13,10 @@
  *     [Sec. 6] or by inverse iteration with conjugate gradients [Sec. 7,
  *     Alg. 2];
  *   - the median split and the recursion into floor(P/2) / ceil(P/2) parts
- *     [Sec. 4, Alg. 1].
+ *     [Sec. 4, Alg. 1];
+ *   - the Laplacian in gather-scatter form [Sec. 5] and a Cuthill-McKee
+ *     locality order of the elements (standing in for the coordinate
+ *     pre-sort of Sec. 5 and Sec. 8).
  *
  * All arithmetic is IEEE double, round to nearest, single-threaded.
  */
