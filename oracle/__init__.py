@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "oracle.cpp")
 
 GRAPH = {"weighted": 0, "unit": 1, "face": 2}
-METHOD = {"lanczos": 0, "inverse_cg": 1}
+METHOD = {"lanczos": 0, "inverse_cg": 1, "auto": 2}
 PRECOND = {"none": 0, "amg": 1}
 
 
@@ -36,7 +36,7 @@ class Info(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("matvecs", C.c_int64),
                 ("theta", C.c_double), ("residual", C.c_double), ("ncomp", C.c_int32),
                 ("cg_iters", C.c_int32), ("amg_levels", C.c_int32), ("sweeps", C.c_int32),
-                ("sweep_moved", C.c_int32)]
+                ("sweep_moved", C.c_int32), ("fallbacks", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

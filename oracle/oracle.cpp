@@ -956,11 +956,19 @@ int bisect(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const
   Vec ys;
   int st;
   SecondPair second;
-  if (o.method == ORC_INVERSE_CG)
+  if (o.method == ORC_INVERSE_CG) {
     st = inverse_fiedler(sub, sub_gid, o, ys, lambda, info);
-  else
+  } else {
     st = lanczos_fiedler(sub, sub_gid, o, ys, lambda, info,
                          (o.fiedler_sweep > 0 || warm) ? &second : nullptr, warm);
+    // ORC_AUTO (Sec. 7: inverse iteration where Lanczos does not converge):
+    // a fresh inverse-iteration solve from the random start replaces the
+    // result; the second Ritz vector of the Lanczos run is still handed on
+    if (o.method == ORC_AUTO && st == 1) {
+      info.fallbacks += 1;
+      st = inverse_fiedler(sub, sub_gid, o, ys, lambda, info);
+    }
+  }
   if (st < 0) return st;
   if (warm && second.ok) {
     // values for the children: y2 at unit root-mean-square on the component
@@ -1019,6 +1027,7 @@ int rsb_recurse(const Graph &g, const std::vector<int64_t> &elems, int32_t p0, i
   info.cg_iters += li.cg_iters;
   info.sweeps += li.sweeps;
   info.sweep_moved += li.sweep_moved;
+  info.fallbacks += li.fallbacks;
   std::vector<int64_t> lo, hi;
   for (size_t i = 0; i < elems.size(); ++i) (side[i] ? hi : lo).push_back(elems[i]);
   int r = rsb_recurse(g, lo, p0, pl, o, part, info, worst, warm);

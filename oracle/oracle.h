@@ -29,12 +29,14 @@ extern "C" {
 #endif
 
 enum { ORC_GRAPH_WEIGHTED = 0, ORC_GRAPH_UNIT = 1, ORC_GRAPH_FACE = 2 };
-enum { ORC_LANCZOS = 0, ORC_INVERSE_CG = 1 };
+enum { ORC_LANCZOS = 0, ORC_INVERSE_CG = 1, ORC_AUTO = 2 };
 enum { ORC_PRECOND_NONE = 0, ORC_PRECOND_AMG = 1 };
 
 typedef struct orc_opts {
   int32_t graph;             /* ORC_GRAPH_* */
-  int32_t method;            /* ORC_LANCZOS or ORC_INVERSE_CG */
+  int32_t method;            /* ORC_LANCZOS, ORC_INVERSE_CG, or ORC_AUTO: Lanczos,
+                                and inverse iteration from a fresh random start
+                                where Lanczos does not converge (Sec. 7) */
   int32_t lanczos_m;         /* Lanczos steps per cycle */
   int32_t max_restarts;      /* cycles after the first one */
   double tol;                /* stop when ||L y - rho y|| <= tol * rho, rho = y^T L y */
@@ -68,6 +70,7 @@ typedef struct orc_info {
   int32_t amg_levels;  /* inverse iteration with AMG: levels of the hierarchy */
   int32_t sweeps;      /* bisections whose Fiedler pair was swept */
   int32_t sweep_moved; /* of those, bisections where an angle other than 0 won */
+  int32_t fallbacks;   /* ORC_AUTO: bisections solved by inverse iteration */
 } orc_info;
 
 void orc_opts_default(orc_opts *o);
