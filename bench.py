@@ -207,7 +207,7 @@ def main():
     ap.add_argument("--keep", type=int, default=8,
                     help="thick restart keeping this many Ritz pairs (0: explicit restart)")
     ap.add_argument("--max-restarts", type=int, default=50)
-    ap.add_argument("--method", default="lanczos", choices=["lanczos", "inverse_cg"],
+    ap.add_argument("--method", default="lanczos", choices=["lanczos", "inverse_cg", "auto"],
                     help="eigen-solver; inverse_cg runs report CG steps, not Lanczos steps")
     ap.add_argument("--sweep", type=int, default=0,
                     help="sweep S angles of a near-degenerate Fiedler pair for the smallest cut")

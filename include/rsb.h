@@ -57,6 +57,10 @@ extern "C" {
 
 #define RSB_LANCZOS 0    /* restarted Lanczos, full reorthogonalisation (Sec. 6) */
 #define RSB_INVERSE_CG 1 /* inverse iteration, CG inner solves (Sec. 7, Alg. 2) */
+#define RSB_AUTO 2       /* Lanczos; every subgraph it leaves unconverged is solved
+                            again by inverse iteration from the random start
+                            (Sec. 7: the paper's fallback where Lanczos did not
+                            converge) */
 
 #define RSB_PRECOND_NONE 0 /* INVERSE_CG: plain CG */
 #define RSB_PRECOND_AMG 1  /* INVERSE_CG: aggregation multigrid V-cycle (Sec. 7, Alg. 3) */
@@ -73,7 +77,7 @@ extern "C" {
 typedef struct rsb_opts {
   int32_t struct_size;      /* sizeof(rsb_opts); set by rsb_opts_init */
   int32_t graph;            /* RSB_GRAPH_* */
-  int32_t method;           /* RSB_LANCZOS or RSB_INVERSE_CG */
+  int32_t method;           /* RSB_LANCZOS, RSB_INVERSE_CG or RSB_AUTO */
   int32_t precision;        /* RSB_FP64 or RSB_MIXED */
   int32_t lanczos_m;        /* Lanczos steps per cycle (default 100, max 250) */
   int32_t max_restarts;     /* restarts after the first cycle (default 50) */
@@ -195,6 +199,8 @@ typedef struct rsb_stats {
   int32_t amg_levels;        /* INVERSE_CG with AMG: levels of the deepest hierarchy */
   int32_t sweeps;            /* fiedler_sweep: bisections whose Fiedler pair was swept */
   int32_t sweep_moved;       /* of those, bisections where an angle other than 0 won */
+  int32_t fallbacks;         /* RSB_AUTO: bisections solved again by inverse iteration */
+  int32_t reserved;
   double ms_reorder;         /* opts->reorder = 1: locality order of the rows (host wall
                                 clock, included in ms_total) */
 } rsb_stats;

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librsb.so")
 
 GRAPH = {"weighted": 0, "unit": 1, "face": 2}
-METHOD = {"lanczos": 0, "inverse_cg": 1}
+METHOD = {"lanczos": 0, "inverse_cg": 1, "auto": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 PRECOND = {"none": 0, "amg": 1}
 
@@ -52,7 +52,8 @@ class Stats(C.Structure):
         ("cut_pairs", C.c_int64), ("max_neighbors", C.c_int32), ("avg_neighbors", C.c_double),
         ("nnz", C.c_int64), ("kernel_bytes", C.c_double), ("kernel_ms", C.c_double),
         ("kernel_launches", C.c_int64), ("tile_rows", C.c_int32), ("amg_levels", C.c_int32),
-        ("sweeps", C.c_int32), ("sweep_moved", C.c_int32), ("ms_reorder", C.c_double),
+        ("sweeps", C.c_int32), ("sweep_moved", C.c_int32), ("fallbacks", C.c_int32),
+        ("reserved", C.c_int32), ("ms_reorder", C.c_double),
     ]
 
     def as_dict(self):

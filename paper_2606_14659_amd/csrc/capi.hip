@@ -40,7 +40,7 @@ void check_opts(const rsb_opts *o) {
   if (o->struct_size != (int32_t)sizeof(rsb_opts))
     fail(RSB_EINVAL, "opts->struct_size mismatch (call rsb_opts_init)");
   if (o->graph < 0 || o->graph > 2) fail(RSB_EINVAL, "graph kind");
-  if (o->method < 0 || o->method > 1) fail(RSB_EINVAL, "method");
+  if (o->method < 0 || o->method > 2) fail(RSB_EINVAL, "method");
   if (o->precision < 0 || o->precision > 1) fail(RSB_EINVAL, "precision");
   if (o->lanczos_m < 1 || o->lanczos_m > kMaxM) fail(RSB_EINVAL, "lanczos_m must be in [1, 250]");
   if (o->max_restarts < 0) fail(RSB_EINVAL, "negative max_restarts");
@@ -60,17 +60,17 @@ void check_opts(const rsb_opts *o) {
   if (!(o->amg_sigma > 0.0 && o->amg_sigma < 2.0)) fail(RSB_EINVAL, "amg_sigma must be in (0, 2)");
   if (o->fiedler_sweep < 0 || o->fiedler_sweep > 64)
     fail(RSB_EINVAL, "fiedler_sweep must be in [0, 64]");
-  if (o->fiedler_sweep > 0 && (o->method != RSB_LANCZOS || o->lanczos_keep < 2))
-    fail(RSB_EINVAL, "fiedler_sweep needs method RSB_LANCZOS with lanczos_keep >= 2");
+  if (o->fiedler_sweep > 0 && (o->method == RSB_INVERSE_CG || o->lanczos_keep < 2))
+    fail(RSB_EINVAL, "fiedler_sweep needs Lanczos (RSB_LANCZOS or RSB_AUTO) with lanczos_keep >= 2");
   if (!(o->sweep_gap >= 0.0)) fail(RSB_EINVAL, "sweep_gap must be >= 0");
   if (o->warm_start != 0 && o->warm_start != 1) fail(RSB_EINVAL, "warm_start must be 0 or 1");
   if (o->reorder != 0 && o->reorder != 1) fail(RSB_EINVAL, "reorder must be 0 or 1");
   if (o->gather_scatter != 0 && o->gather_scatter != 1)
     fail(RSB_EINVAL, "gather_scatter must be 0 or 1");
-  if (o->gather_scatter && (o->graph != RSB_GRAPH_WEIGHTED || o->method != RSB_LANCZOS))
-    fail(RSB_EINVAL, "gather_scatter needs graph RSB_GRAPH_WEIGHTED and method RSB_LANCZOS");
-  if (o->warm_start && (o->method != RSB_LANCZOS || o->lanczos_keep < 2))
-    fail(RSB_EINVAL, "warm_start needs method RSB_LANCZOS with lanczos_keep >= 2");
+  if (o->gather_scatter && (o->graph != RSB_GRAPH_WEIGHTED || o->method == RSB_INVERSE_CG))
+    fail(RSB_EINVAL, "gather_scatter needs graph RSB_GRAPH_WEIGHTED and Lanczos (RSB_LANCZOS or RSB_AUTO)");
+  if (o->warm_start && (o->method == RSB_INVERSE_CG || o->lanczos_keep < 2))
+    fail(RSB_EINVAL, "warm_start needs Lanczos (RSB_LANCZOS or RSB_AUTO) with lanczos_keep >= 2");
 }
 
 void setup_ctx(Ctx &ctx, const rsb_opts &o) {
@@ -158,12 +158,15 @@ void one_segment_tables(const Level &L, int s, OneSeg &o, Ctx &ctx) {
 }
 
 // Eigen-solve of one level: all segments batched, or one segment at a time.
+// RSB_AUTO runs Lanczos and then, for every segment Lanczos left
+// unconverged, inverse iteration from the random start (Sec. 7: the paper
+// switched to inverse iteration where Lanczos did not converge).
 int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, void *work,
                     double *y64, double *y2, const double *warm, KernelProfile *prof,
-                    int *amg_levels, Ctx &ctx) {
+                    int *amg_levels, int *fallbacks, Ctx &ctx) {
   const bool mixed = o.precision == RSB_MIXED;
-  auto run = [&](const LevelView &v, SolveDev &SS, bool graph) -> int64_t {
-    if (o.method == RSB_INVERSE_CG) {
+  auto run = [&](const LevelView &v, SolveDev &SS, bool graph, bool inverse) -> int64_t {
+    if (inverse) {
       InverseParams ip{o.inv_max_outer, o.cg_max_iter, o.cg_tol, o.tol,       o.seed,
                        o.inv_precond,   o.amg_sigma,     o.amg_smooth, amg_levels};
       return inverse_level(v, C, SS, ip, work, y64, graph, ctx);
@@ -173,15 +176,8 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     return mixed ? lanczos_level<float>(v, C, SS, lp, work, y64, ctx)
                  : lanczos_level<double>(v, C, SS, lp, work, y64, ctx);
   };
-  if (o.batched) return run(view_of(L), S, o.use_hipgraph != 0);
-  // reference mode: every subgraph with its own launches sized to it
-  std::vector<SegState> hs(L.nseg);
-  RSB_HIP(hipMemcpyAsync(hs.data(), S.st.get(), L.nseg * sizeof(SegState), hipMemcpyDeviceToHost,
-                         ctx.stream));
-  RSB_HIP(hipStreamSynchronize(ctx.stream));
-  int64_t steps = 0;
-  for (int s = 0; s < L.nseg; ++s) {
-    if (!hs[s].solve) continue;
+  // segment s alone, with launches sized to it; its state goes back to S
+  auto one = [&](int s, bool inverse) -> int64_t {
     OneSeg os;
     one_segment_tables(L, s, os, ctx);
     SolveDev S1;
@@ -197,18 +193,17 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     v.grp = os.grp.get();
     v.nnz = (int64_t)((double)L.nnz * L.seg[s].npad / std::max<int64_t>(L.nrows, 1));
     v.gs.only_seg = s;
-    steps += run(v, S1, false);
+    const int64_t steps = run(v, S1, false, inverse);
     RSB_HIP(hipMemcpyAsync(S.st.get() + s, S1.st.get(), sizeof(SegState),
                            hipMemcpyDeviceToDevice, ctx.stream));
     // the Ritz values of the last cycle (read by the sweep over the pair)
-    RSB_HIP(hipMemcpyAsync(S.tvals.get() + (int64_t)s * S.nkcap, S1.tvals.get(),
-                           std::min(S.nkcap, S1.nkcap) * sizeof(double), hipMemcpyDeviceToDevice,
-                           ctx.stream));
-    int64_t c = 0;
+    if (!inverse)
+      RSB_HIP(hipMemcpyAsync(S.tvals.get() + (int64_t)s * S.nkcap, S1.tvals.get(),
+                             std::min(S.nkcap, S1.nkcap) * sizeof(double),
+                             hipMemcpyDeviceToDevice, ctx.stream));
+    int64_t c = 0, acc = 0;
     RSB_HIP(hipMemcpyAsync(&c, S1.counters.get(), sizeof(int64_t), hipMemcpyDeviceToHost,
                            ctx.stream));
-    RSB_HIP(hipStreamSynchronize(ctx.stream));
-    int64_t acc = 0;
     RSB_HIP(hipMemcpyAsync(&acc, S.counters.get(), sizeof(int64_t), hipMemcpyDeviceToHost,
                            ctx.stream));
     RSB_HIP(hipStreamSynchronize(ctx.stream));
@@ -216,8 +211,36 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     RSB_HIP(hipMemcpyAsync(S.counters.get(), &acc, sizeof(int64_t), hipMemcpyHostToDevice,
                            ctx.stream));
     RSB_HIP(hipStreamSynchronize(ctx.stream));
-    if (ctx.verbose >= 2 && (s % 64 == 63 || s + 1 == L.nseg))
-      fprintf(stderr, "[rsb]   subgraph %d of %d solved\n", s + 1, L.nseg);
+    return steps;
+  };
+  auto states = [&]() {
+    std::vector<SegState> hs(L.nseg);
+    RSB_HIP(hipMemcpyAsync(hs.data(), S.st.get(), L.nseg * sizeof(SegState),
+                           hipMemcpyDeviceToHost, ctx.stream));
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    return hs;
+  };
+  const bool inverse_only = o.method == RSB_INVERSE_CG;
+  int64_t steps = 0;
+  if (o.batched) {
+    steps = run(view_of(L), S, o.use_hipgraph != 0, inverse_only);
+  } else {
+    // reference mode: every subgraph with its own launches sized to it
+    const std::vector<SegState> hs = states();
+    for (int s = 0; s < L.nseg; ++s) {
+      if (!hs[s].solve) continue;
+      steps += one(s, inverse_only);
+      if (ctx.verbose >= 2 && (s % 64 == 63 || s + 1 == L.nseg))
+        fprintf(stderr, "[rsb]   subgraph %d of %d solved\n", s + 1, L.nseg);
+    }
+  }
+  if (o.method == RSB_AUTO) {
+    const std::vector<SegState> hs = states();
+    for (int s = 0; s < L.nseg; ++s) {
+      if (!hs[s].solve || hs[s].converged) continue;
+      if (fallbacks) ++*fallbacks;
+      steps += one(s, true);
+    }
   }
   return steps;
 }
@@ -299,10 +322,12 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
   // 3. work space sized for the largest level
   const int64_t cap_rows =
       round_up(total, kWave) + (int64_t)kWave * (parts_total + 2 * (int64_t)meshes.size());
-  const size_t wbytes = (o.method == RSB_INVERSE_CG)
-                            ? inverse_workspace_bytes(cap_rows)
-                            : lanczos_workspace_bytes(cap_rows, o.lanczos_m, o.precision == RSB_MIXED,
-                                                      o.lanczos_keep);
+  const size_t wlz = lanczos_workspace_bytes(cap_rows, o.lanczos_m, o.precision == RSB_MIXED,
+                                             o.lanczos_keep);
+  const size_t wbytes = (o.method == RSB_INVERSE_CG) ? inverse_workspace_bytes(cap_rows)
+                        : (o.method == RSB_AUTO)
+                            ? std::max(wlz, inverse_workspace_bytes(cap_rows))
+                            : wlz;
   DevBuf<char> work(ctx, wbytes);
   DevBuf<double> y64(ctx, cap_rows);
   DevBuf<double> y2, warm;
@@ -330,7 +355,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     components_and_targets(*L, C, S, ctx);
     int amg_levels = 0;
     const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(), y2.get(), warm.get(),
-                                      o.profile ? &prof : nullptr, &amg_levels, ctx);
+                                      o.profile ? &prof : nullptr, &amg_levels, &st.fallbacks, ctx);
     if (o.warm_start) warm_update(*L, C, S, y2.get(), warm.get(), ctx);
     st.amg_levels = std::max(st.amg_levels, amg_levels);
     std::vector<SegState> hs(L->nseg);
@@ -353,7 +378,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     }
     // FP64 SpMV launches: all of them in FP64 mode; steps 1-2 and the
     // residual of every cycle with FP32 directions
-    st.spmv_fp64 += (o.precision == RSB_MIXED && o.method == RSB_LANCZOS) ? 3 * (int64_t)cyc
+    st.spmv_fp64 += (o.precision == RSB_MIXED && o.method != RSB_INVERSE_CG) ? 3 * (int64_t)cyc
                                                                           : steps + cyc;
     st.disconnected += disc;
     st.not_converged += notconv;

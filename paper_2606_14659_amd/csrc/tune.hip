@@ -105,7 +105,7 @@ void choose_tile(Level &L, const rsb_opts &o, void *work, Ctx &ctx) {
   int want;
   if (o.rows_per_thread) {
     want = o.rows_per_thread;
-  } else if (o.autotune == 0 || o.method != RSB_LANCZOS || o.lanczos_m < 4) {
+  } else if (o.autotune == 0 || o.method == RSB_INVERSE_CG || o.lanczos_m < 4) {
     want = default_rpt(L.nrows);
   } else {
     const int64_t nnz_row = L.nrows > 0 ? (L.nnz + L.nrows / 2) / L.nrows : 0;
