@@ -86,7 +86,11 @@ typedef struct rsb_opts {
   int32_t inv_max_outer;    /* INVERSE_CG: outer iterations cap (50) */
   int32_t cg_max_iter;      /* INVERSE_CG: CG steps per solve cap (20000) */
   double cg_tol;            /* INVERSE_CG: CG stops at ||r|| <= cg_tol ||b|| (1e-8) */
-  int32_t cg_full_projection; /* reserved; must be 0 */
+  int32_t cg_full_projection; /* inverse iteration: 0 (default) plain flexible CG; k in
+                                 [1, 32]: every new direction is L-orthogonalised
+                                 against the last k directions of the solve (the
+                                 paper's CG "augmented with full projection",
+                                 Sec. 7) */
   int32_t batched;          /* 1: all subgraphs of a level in one launch sequence;
                                0: one subgraph at a time (reference mode) */
   uint64_t seed;            /* start-vector seed (default 20261203) */

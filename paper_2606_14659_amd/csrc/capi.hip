@@ -46,7 +46,8 @@ void check_opts(const rsb_opts *o) {
   if (o->max_restarts < 0) fail(RSB_EINVAL, "negative max_restarts");
   if (!(o->tol > 0) || !(o->cg_tol > 0)) fail(RSB_EINVAL, "tolerances must be positive");
   if (o->inv_max_outer < 1 || o->cg_max_iter < 1) fail(RSB_EINVAL, "inverse iteration caps");
-  if (o->cg_full_projection != 0) fail(RSB_EINVAL, "cg_full_projection is not supported");
+  if (o->cg_full_projection < 0 || o->cg_full_projection > kMaxFullProj)
+    fail(RSB_EINVAL, "cg_full_projection must be in [0, 32]");
   if (o->autotune < 0 || o->autotune > 2) fail(RSB_EINVAL, "autotune");
   if (o->lanczos_keep < 0 || o->lanczos_keep > kMaxKeep ||
       (o->lanczos_keep > 0 && o->lanczos_keep >= o->lanczos_m))
@@ -167,8 +168,9 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
   const bool mixed = o.precision == RSB_MIXED;
   auto run = [&](const LevelView &v, SolveDev &SS, bool graph, bool inverse) -> int64_t {
     if (inverse) {
-      InverseParams ip{o.inv_max_outer, o.cg_max_iter, o.cg_tol, o.tol,       o.seed,
-                       o.inv_precond,   o.amg_sigma,     o.amg_smooth, amg_levels};
+      InverseParams ip{o.inv_max_outer, o.cg_max_iter, o.cg_tol,     o.tol,
+                       o.seed,          o.inv_precond, o.amg_sigma,  o.amg_smooth,
+                       amg_levels,      o.cg_full_projection};
       return inverse_level(v, C, SS, ip, work, y64, graph, ctx);
     }
     LanczosParams lp{o.lanczos_m, o.lanczos_keep, o.max_restarts, o.tol, graph ? 1 : 0,
@@ -324,10 +326,10 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
       round_up(total, kWave) + (int64_t)kWave * (parts_total + 2 * (int64_t)meshes.size());
   const size_t wlz = lanczos_workspace_bytes(cap_rows, o.lanczos_m, o.precision == RSB_MIXED,
                                              o.lanczos_keep);
-  const size_t wbytes = (o.method == RSB_INVERSE_CG) ? inverse_workspace_bytes(cap_rows)
-                        : (o.method == RSB_AUTO)
-                            ? std::max(wlz, inverse_workspace_bytes(cap_rows))
-                            : wlz;
+  const size_t winv = inverse_workspace_bytes(cap_rows, o.cg_full_projection);
+  const size_t wbytes = (o.method == RSB_INVERSE_CG) ? winv
+                        : (o.method == RSB_AUTO) ? std::max(wlz, winv)
+                                                 : wlz;
   DevBuf<char> work(ctx, wbytes);
   DevBuf<double> y64(ctx, cap_rows);
   DevBuf<double> y2, warm;

@@ -15,6 +15,7 @@ constexpr int kWave = 64;    // CDNA wavefront width
 constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
 constexpr int kMaxM = 250;   // largest Lanczos cycle length
 constexpr int kMaxKeep = 16; // most Ritz pairs kept by a thick restart
+constexpr int kMaxFullProj = 32;  // most CG directions kept by full projection
 constexpr int kGroup = 32;   // least blocks per first-level reduction group
 constexpr int kSlotGroup = 16;  // ELL slots a row reads at once (unconditional loads)
 // zero words after the last slice so that a row may read a whole slot group

@@ -11,6 +11,15 @@
 // Sec. 7) or when the Rayleigh-quotient residual of b meets the tolerance,
 // or after max_outer iterations.  Every launch covers all segments of the
 // level; reductions are fixed-order per segment as in the Lanczos solver.
+//
+// Full projection (the paper's flexible CG "augmented with full
+// projection"): each new direction q = z + beta p_old is L-orthogonalised
+// against the last k directions P_i, p = q - sum_i c_i P_i with
+// c_i = (L P_i)^T q / P_i^T L P_i (classical Gram-Schmidt in the L inner
+// product, all c_i from q).  The kept P_i and L P_i sit in a ring of k
+// slots per row; L p = L q - sum_i c_i L P_i, so the SpMV of the fused
+// direction launch is unchanged and the projection only adds row-local
+// reads.
 #include <algorithm>
 #include <cmath>
 
@@ -43,6 +52,11 @@ struct InvArgs {
   int32_t *flags;           // [0] segments still running (CG or outer)
   unsigned long long *ctr;  // [0] segment CG steps
   uint64_t seed;
+  int fpk;                  // full projection: ring slots (0: off)
+  double *FP, *FLP;         // [fpk][vs] kept directions and their Laplacian
+  int64_t vs;               // row stride of the ring
+  double *fp_plp, *fp_c;    // [nseg][fpk] P_i^T L P_i, coefficients c_i
+  int32_t *fp_tot;          // [nseg] directions pushed in the current solve
 };
 
 template <int RPT>
@@ -144,14 +158,64 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(InvArgs a, int it) {
       for (int u = 0; u < kSlotGroup; ++u)
         lp += colw_wt(w[u]) ? (double)colw_wt(w[u]) * (pi - (rj[u] + beta * pj[u])) : 0.0;
     }
+    double pf = pi, lf = lp;
+    if (a.fpk) {
+      const int nk = min(a.fp_tot[b.seg], a.fpk);
+      const double *cf = a.fp_c + (int64_t)b.seg * a.fpk;
+      for (int k = 0; k < nk; ++k) {
+        pf -= cf[k] * a.FP[(int64_t)k * a.vs + row];
+        lf -= cf[k] * a.FLP[(int64_t)k * a.vs + row];
+      }
+    }
     if (tr.ok[r]) {
-      Pnew[row] = pi;
-      a.LP[row] = lp;
-      acc[0] += pi * lp;
+      Pnew[row] = pf;
+      a.LP[row] = lf;
+      acc[0] += pf * lf;
     }
   }
   block_reduce_into<1>(acc, red, vals, 1);
   write_partials(a, lb, vals, 1);
+}
+
+// Full projection, before the direction launch: partial sums of
+// (L P_i)^T q over the kept slots i, q = z + beta p_old.  The tile's q is
+// staged in LDS and each wave reduces every fourth slot over the tile.
+template <int RPT, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_cg_fpdots(InvArgs a, int it) {
+  constexpr int TILE = kBlock * RPT;
+  __shared__ double qs[TILE];
+  __shared__ double vals[kMaxFullProj];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active || S.cg_done) return;
+  const int nk = min(a.fp_tot[b.seg], a.fpk);
+  if (nk == 0) return;
+  const double *Pold = (it & 1) ? a.P0 : a.P1;
+  const double beta = S.cg_beta;
+  const bool use_z = PRE && S.cg_it > 0;
+  const double cz = S.cg_c;
+  for (int r = 0; r < RPT; ++r) {
+    const int lr = r * kBlock + (int)threadIdx.x;
+    double q = 0.0;
+    if (lr < b.nrows) {
+      const int64_t row = b.row0 + lr;
+      const double zi = use_z ? a.Z[row] - cz * a.U0[row] : a.R[row];
+      q = zi + beta * Pold[row];
+    }
+    qs[lr] = q;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int k = wave; k < nk; k += kBlock / kWave) {
+    const double *v = a.FLP + (int64_t)k * a.vs + b.row0;
+    double acc = 0.0;
+    for (int i = lane; i < b.nrows; i += kWave) acc += v[i] * qs[i];
+    acc = wave_sum(acc);
+    if (lane == 0) vals[k] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nk; i += kBlock) a.part[(int64_t)lb * a.ps + i] = vals[i];
 }
 
 // x += alpha p; r -= alpha L p; partial sums of r_new^T r_new, r_new^T r_old.
@@ -177,6 +241,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(InvArgs a, int it) {
       a.X[row] = xn;
       a.R[row] = rnew;
       if (a.pre) a.ROLD[row] = rold;
+      if (a.fpk) {
+        // this step's direction joins the kept ones (oldest slot reused)
+        const int64_t slot = a.fp_tot[b.seg] % a.fpk;
+        a.FP[slot * a.vs + row] = Pnew[row];
+        a.FLP[slot * a.vs + row] = a.LP[row];
+      }
       acc[0] += rnew * rnew;
       acc[1] += rnew * rold;
     }
@@ -270,11 +340,11 @@ __global__ __launch_bounds__(kBlock) void k_inv_res(InvArgs a) {
 }
 
 // Reductions and the per-segment logic that finishes each launch above.
-enum InvOp { OP_BEGIN, OP_CG_INIT, OP_CG_A, OP_CG_B, OP_CG_Z, OP_EVAL, OP_RES };
+enum InvOp { OP_BEGIN, OP_CG_INIT, OP_CG_A, OP_CG_B, OP_CG_Z, OP_EVAL, OP_RES, OP_CG_FP };
 
 template <int OP>
 __global__ __launch_bounds__(kBlock) void k_inv_reduce(InvArgs a) {
-  __shared__ double vals[5];
+  __shared__ double vals[OP == OP_CG_FP ? kMaxFullProj : 5];
   const int g = blockIdx.x;
   const int s = a.grp[g].seg;
   const SegState S = a.st[s];
@@ -300,12 +370,23 @@ __global__ __launch_bounds__(kBlock) void k_inv_reduce(InvArgs a) {
       if (!S.active || S.cg_done) return;
       nval = 5;
       break;
+    case OP_CG_FP:
+      if (!S.active || S.cg_done) return;
+      nval = min(a.fp_tot[s], a.fpk);
+      if (nval == 0) return;
+      break;
     default:
       if (!S.active) return;
       nval = 3;
       break;
   }
   if (!group_reduce(a, g, vals, nval)) return;
+  if (OP == OP_CG_FP) {
+    const double *pl = a.fp_plp + (int64_t)s * a.fpk;
+    double *cf = a.fp_c + (int64_t)s * a.fpk;
+    for (int k = threadIdx.x; k < nval; k += kBlock) cf[k] = vals[k] / pl[k];
+    return;
+  }
   if (threadIdx.x != 0) return;
   SegState &W = a.st[s];
   switch (OP) {
@@ -319,6 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_inv_reduce(InvArgs a) {
       W.theta = 0.0;
       break;
     case OP_CG_INIT:
+      if (a.fpk) a.fp_tot[s] = 0;
       W.rr = vals[0];
       W.cg_it = 0;
       W.cg_c = 0.0;
@@ -327,8 +409,10 @@ __global__ __launch_bounds__(kBlock) void k_inv_reduce(InvArgs a) {
       break;
     case OP_CG_A:
       W.cg_alpha = W.rr / vals[0];
+      if (a.fpk) a.fp_plp[(int64_t)s * a.fpk + a.fp_tot[s] % a.fpk] = vals[0];
       break;
     case OP_CG_B: {
+      if (a.fpk) a.fp_tot[s] += 1;
       W.cg_it += 1;
       W.steps += 1;
       atomicAdd(&a.ctr[0], 1ull);
@@ -435,6 +519,21 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
   a.flags = S.n_active.get();
   a.ctr = (unsigned long long *)S.counters.get();
   a.seed = p.seed;
+  a.fpk = p.full_projection;
+  a.vs = L.nrows;
+  DevBuf<double> fp_plp, fp_c;
+  DevBuf<int32_t> fp_tot;
+  if (a.fpk) {
+    a.FP = w + 8 * L.nrows;
+    a.FLP = a.FP + (int64_t)a.fpk * L.nrows;
+    fp_plp.alloc(ctx, (size_t)L.nseg * a.fpk);
+    fp_c.alloc(ctx, (size_t)L.nseg * a.fpk);
+    fp_tot.alloc(ctx, L.nseg);
+    fill_i32(fp_tot.get(), L.nseg, 0, ctx);
+    a.fp_plp = fp_plp.get();
+    a.fp_c = fp_c.get();
+    a.fp_tot = fp_tot.get();
+  }
   const int nblk = L.nblk, ngrp = L.ngrp;
   hipStream_t s = ctx.stream;
   AmgDev amg;
@@ -464,6 +563,11 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
     auto chunk = [&]() {
       k_flag_reset<<<1, 1, 0, s>>>(a.flags);
       for (int it = 0; it < kCgChunk; ++it) {
+        if (a.fpk) {
+          if (a.pre) k_cg_fpdots<RPT, true><<<nblk, kBlock, 0, s>>>(a, it);
+          else k_cg_fpdots<RPT, false><<<nblk, kBlock, 0, s>>>(a, it);
+          k_inv_reduce<OP_CG_FP><<<ngrp, kBlock, 0, s>>>(a);
+        }
         if (a.pre) k_cg_a<RPT, true><<<nblk, kBlock, 0, s>>>(a, it);
         else k_cg_a<RPT, false><<<nblk, kBlock, 0, s>>>(a, it);
         k_inv_reduce<OP_CG_A><<<ngrp, kBlock, 0, s>>>(a);
@@ -523,7 +627,9 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
 
 }  // namespace
 
-size_t inverse_workspace_bytes(int64_t rows) { return (size_t)rows * 8 * sizeof(double); }
+size_t inverse_workspace_bytes(int64_t rows, int full_projection) {
+  return (size_t)rows * (8 + 2 * (size_t)full_projection) * sizeof(double);
+}
 
 int64_t inverse_level(const LevelView &L, CompDev &C, SolveDev &S, const InverseParams &p,
                       void *work, double *y64_out, bool use_graph, Ctx &ctx) {

@@ -348,8 +348,11 @@ struct InverseParams {
   double amg_sigma;
   int amg_smooth;
   int *amg_levels;       // out (may be null): levels of the largest hierarchy
+  int full_projection;   // 0, or k: L-orthogonalise each new direction against the last k
 };
-size_t inverse_workspace_bytes(int64_t rows);
+// FP64 vectors of the inverse-iteration workspace: 8, plus 2 k for the
+// directions kept by full projection
+size_t inverse_workspace_bytes(int64_t rows, int full_projection = 0);
 int64_t inverse_level(const LevelView &L, CompDev &C, SolveDev &S, const InverseParams &p,
                       void *work, double *y64_out, bool use_graph, Ctx &ctx);
 

@@ -1410,7 +1410,9 @@ void dispatch_rpt(int rpt, F &&f) {
 
 void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx &ctx) {
   S.m = m;
-  S.pstride = 2 * m + 8;  // partial sums of 2 j + 2 values (delayed second pass)
+  // partial sums of 2 j + 2 values (delayed second pass), or of the kept
+  // directions' coefficients of CG with full projection
+  S.pstride = std::max(2 * m + 8, kMaxFullProj);
   S.nkcap = std::max(1, keep);
   const size_t ns = std::max(nseg, 1), nb = std::max(nblk, 1), ng = std::max(ngrp, 1);
   if (!S.st.p || S.st.n < ns) S.st.alloc(ctx, ns);

@@ -56,7 +56,8 @@ def test_bad_options_rejected_before_any_device_call():
     bad = []
     for field, value in (("struct_size", 4), ("graph", 7), ("method", 3), ("method", -1),
                          ("lanczos_m", 0), ("lanczos_m", 251),
-                         ("tol", 0.0), ("cg_full_projection", 1), ("precision", 5),
+                         ("tol", 0.0), ("cg_full_projection", 33), ("cg_full_projection", -1),
+                         ("precision", 5),
                          ("rows_per_thread", 3), ("rows_per_thread", 16), ("autotune", 3),
                          ("lanczos_keep", -1), ("lanczos_keep", 17), ("lanczos_keep", 100),
                          ("inv_precond", 2), ("inv_precond", -1), ("amg_smooth", -1),
