@@ -880,7 +880,7 @@ int64_t bisection_cut(const Graph &g, const std::vector<uint8_t> &side) {
 // a = k pi / S, k = 0..S-1; every combination (canonical sign) is split by
 // the usual rule and the one of smallest cut replaces y (ties: smallest k).
 void sweep_pair(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const orc_opts &o,
-                const SecondPair &sp, Vec &y, orc_info &info) {
+                const SecondPair &sp, Vec &y, orc_info &info, double min_perp = 1e-6) {
   if (!(sp.theta2 - sp.theta1 <= o.sweep_gap * sp.theta1)) return;
   const int64_t n = g.n;
   Vec y2 = sp.y2;
@@ -888,7 +888,7 @@ void sweep_pair(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, 
   const double b = dot(y, y2);
   for (int64_t i = 0; i < n; ++i) y2[i] -= b * y[i];
   const double nn = norm2(y2);
-  if (!(nn > 1e-6)) return;
+  if (!(nn > min_perp)) return;
   for (double &v : y2) v /= nn;
   canonical_sign(y2, gid);
   info.sweeps += 1;
@@ -978,8 +978,26 @@ int bisect(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const
     for (size_t i = 0; i < sub_gid.size(); ++i) (*warm)[sub_gid[i]] = second.y2[i] * scale;
   }
   std::vector<uint8_t> sub_side;
-  if (second.ok && o.fiedler_sweep > 0)
+  if (o.second_solve && o.fiedler_sweep > 0 && o.method != ORC_INVERSE_CG) {
+    // the pair from two solves: Lanczos again from another random start
+    // (no warm start); a second vector within sweep_gap of the first and at
+    // least 0.1 away from its direction is swept with it, a vector the
+    // solve brought back to y1 is not
+    orc_opts o2 = o;
+    o2.seed = o.seed ^ ORC_SECOND_SEED;
+    orc_info i2{};
+    SecondPair two;
+    double lam2 = 0.0;
+    const int s2 = lanczos_fiedler(sub, sub_gid, o2, two.y2, lam2, i2);
+    if (s2 < 0) return s2;
+    info.matvecs += i2.matvecs;
+    two.ok = true;
+    two.theta1 = lambda;
+    two.theta2 = lam2;
+    sweep_pair(sub, sub_gid, n_low - strad_before, o, two, ys, info, 0.1);
+  } else if (second.ok && o.fiedler_sweep > 0) {
     sweep_pair(sub, sub_gid, n_low - strad_before, o, second, ys, info);
+  }
   split_by_keys(ys, sub_gid, n_low - strad_before, sub_side);
   for (size_t i = 0; i < members.size(); ++i) {
     side[members[i]] = sub_side[i];
@@ -1102,6 +1120,7 @@ void orc_opts_default(orc_opts *o) {
   o->fiedler_sweep = 0;
   o->sweep_gap = 0.1;
   o->warm_start = 0;
+  o->second_solve = 0;
 }
 
 double orc_start_value(uint64_t seed, int64_t gid) { return start_value(seed, gid); }

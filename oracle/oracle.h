@@ -57,7 +57,13 @@ typedef struct orc_opts {
   int32_t warm_start;        /* thick restart: a child's solve starts from its
                                 parent's second Ritz vector (plus 0.1 x the
                                 random start) */
+  int32_t second_solve;      /* fiedler_sweep > 0: the second vector of the swept
+                                pair comes from a second Lanczos solve from
+                                another random start (seed ^ ORC_SECOND_SEED),
+                                so that an exactly degenerate pair is swept */
 } orc_opts;
+
+#define ORC_SECOND_SEED 0x9E3779B97F4A7C15ull
 
 typedef struct orc_info {
   int32_t cycles;      /* Lanczos cycles (or inverse-iteration outer steps) */

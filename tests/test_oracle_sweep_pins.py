@@ -75,3 +75,37 @@ def test_exactly_degenerate_pair_is_not_swept(orc):
     ids = mg.box_hex(16, 16, 4).ids
     st, lam, y, info = orc.fiedler(ids, graph="face", fiedler_sweep=32, **KW)
     assert st == 0 and info["sweeps"] == 0
+
+
+def test_second_solve_sweeps_an_exactly_degenerate_pair(orc):
+    # the same box with the pair taken from two solves (second random start):
+    # the swept cut equals the sweep over y1 projected on the dense
+    # eigenspace and its orthogonal complement in that space, and is never
+    # above the plain cut
+    ids = mg.box_hex(16, 16, 4).ids
+    rp, col, w = orc.dual_graph(ids, "face")
+    ev, V = np.linalg.eigh(dense(rp, col, w))
+    assert abs(ev[2] - ev[1]) < 1e-10 * ev[1] and ev[3] - ev[2] > 0.1 * ev[1]
+    S = 16
+    st, lam, y, info = orc.fiedler(ids, graph="face", fiedler_sweep=S, second_solve=1, **KW)
+    st0, lam0, y0, _ = orc.fiedler(ids, graph="face", **KW)
+    assert st == st0 == 0 and info["sweeps"] == 1
+    E = V[:, 1:3]
+    p1 = E @ (E.T @ y0)
+    p1 = canonical(p1 / np.linalg.norm(p1))
+    rot = np.array([[0.0, -1.0], [1.0, 0.0]])
+    p2 = canonical(E @ (rot @ (E.T @ p1)))
+    cuts = [half_cut(orc, rp, col, w, canonical(np.cos(np.pi * k / S) * p1 + np.sin(np.pi * k / S) * p2))
+            for k in range(S)]
+    assert half_cut(orc, rp, col, w, y) == min(cuts)
+    assert half_cut(orc, rp, col, w, y) <= half_cut(orc, rp, col, w, y0)
+
+
+def test_second_solve_leaves_a_simple_pair_alone(orc):
+    # unique longest axis: the second solve returns the same vector, which
+    # is not swept; the partition is the plain one
+    ids = mg.box_hex(20, 12, 8).ids
+    st0, p0, _ = orc.partition(ids, 8, fiedler_sweep=8, **KW)
+    st1, p1, info = orc.partition(ids, 8, fiedler_sweep=8, second_solve=1, **KW)
+    assert st0 == st1 == 0 and info["sweeps"] == 0
+    assert np.array_equal(p0, p1)
