@@ -211,6 +211,8 @@ def main():
                     help="eigen-solver; inverse_cg runs report CG steps, not Lanczos steps")
     ap.add_argument("--sweep", type=int, default=0,
                     help="sweep S angles of a near-degenerate Fiedler pair for the smallest cut")
+    ap.add_argument("--second-solve", type=int, default=0, choices=[0, 1],
+                    help="with --sweep: the pair's second vector from a second solve")
     ap.add_argument("--warm-start", type=int, default=1, choices=[0, 1],
                     help="start child solves from the parent's second Ritz vector")
     ap.add_argument("--reorder", type=int, default=0, choices=[0, 1],
@@ -272,7 +274,7 @@ def main():
                 max_restarts=args.max_restarts, verbose=args.verbose, lanczos_keep=args.keep,
                 method=args.method, inv_precond=args.precond, cg_tol=1e-8, inv_max_outer=100,
                 fiedler_sweep=args.sweep, warm_start=args.warm_start, reorder=args.reorder,
-                gather_scatter=args.gather_scatter, batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
+                gather_scatter=args.gather_scatter, second_solve=args.second_solve, batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
                 autotune=args.autotune)
     if args.autotune_cache:
         opts["autotune_cache"] = args.autotune_cache
@@ -331,6 +333,7 @@ def main():
                    "method": args.method, "precond": args.precond, "fiedler_sweep": args.sweep,
                    "warm_start": bool(args.warm_start), "reorder": bool(args.reorder),
                    "gather_scatter": bool(args.gather_scatter),
+                   "second_solve": bool(args.second_solve),
                    "batched": not args.unbatched},
         "time_to_partition_ms": dt * 1e3 / args.steps,
         "edge_cut": st["edge_cut"],

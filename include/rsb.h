@@ -163,6 +163,16 @@ typedef struct rsb_opts {
                                rounding.  Needs graph RSB_GRAPH_WEIGHTED, method
                                RSB_LANCZOS and at most 64 slots per vertex id.
                                0 (default): sliced ELL. */
+  int32_t second_solve;     /* with fiedler_sweep > 0: the second vector of the swept
+                               pair comes from a second Lanczos solve of the same
+                               subgraph from another random start (seed ^
+                               0x9E3779B97F4A7C15, no warm start) instead of the
+                               thick restart's second Ritz vector; it is swept when
+                               its Rayleigh quotient is within sweep_gap of the
+                               first and at least 0.1 of it lies off the first
+                               vector.  One Krylov space holds a single direction
+                               of an exactly degenerate pair (Sec. 9), two solves
+                               hold two.  Doubles the solve time.  0 (default). */
 } rsb_opts;
 
 typedef struct rsb_stats {

@@ -38,7 +38,7 @@ class Opts(C.Structure):
         ("profile", C.c_int32), ("rows_per_thread", C.c_int32), ("lanczos_keep", C.c_int32),
         ("inv_precond", C.c_int32), ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double),
         ("fiedler_sweep", C.c_int32), ("warm_start", C.c_int32), ("sweep_gap", C.c_double),
-        ("reorder", C.c_int32), ("gather_scatter", C.c_int32),
+        ("reorder", C.c_int32), ("gather_scatter", C.c_int32), ("second_solve", C.c_int32),
     ]
 
 

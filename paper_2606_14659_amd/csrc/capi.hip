@@ -66,6 +66,9 @@ void check_opts(const rsb_opts *o) {
   if (!(o->sweep_gap >= 0.0)) fail(RSB_EINVAL, "sweep_gap must be >= 0");
   if (o->warm_start != 0 && o->warm_start != 1) fail(RSB_EINVAL, "warm_start must be 0 or 1");
   if (o->reorder != 0 && o->reorder != 1) fail(RSB_EINVAL, "reorder must be 0 or 1");
+  if (o->second_solve != 0 && o->second_solve != 1) fail(RSB_EINVAL, "second_solve must be 0 or 1");
+  if (o->second_solve && o->fiedler_sweep < 1)
+    fail(RSB_EINVAL, "second_solve needs fiedler_sweep > 0");
   if (o->gather_scatter != 0 && o->gather_scatter != 1)
     fail(RSB_EINVAL, "gather_scatter must be 0 or 1");
   if (o->gather_scatter && (o->graph != RSB_GRAPH_WEIGHTED || o->method == RSB_INVERSE_CG))
@@ -393,9 +396,47 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
                 "res %.3e rho %.12g theta %.12g\n",
                 i, L->seg[i].n, L->seg[i].P, hs[i].ncomp, hs[i].solve, hs[i].converged,
                 hs[i].cycles, (long long)hs[i].steps, hs[i].res, hs[i].rho, hs[i].theta);
+    double min_perp2 = 1e-12;
+    if (o.second_solve) {
+      // the pair from two solves: Lanczos again from another random start;
+      // its vector becomes y2 and its Rayleigh quotient the second value of
+      // the gap test, then the first solve's vector and state come back
+      const int64_t nr = L->nrows;
+      DevBuf<double> y1(ctx, std::max<int64_t>(nr, 1));
+      DevBuf<SegState> st1(ctx, L->nseg);
+      RSB_HIP(hipMemcpyAsync(y1.get(), y64.get(), nr * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx.stream));
+      RSB_HIP(hipMemcpyAsync(st1.get(), S.st.get(), L->nseg * sizeof(SegState),
+                             hipMemcpyDeviceToDevice, ctx.stream));
+      rsb_opts o2 = o;
+      o2.seed = o.seed ^ 0x9E3779B97F4A7C15ull;
+      o2.method = RSB_LANCZOS;
+      int amg2 = 0;
+      st.level_steps += solve_level(*L, C, S, o2, work.get(), y64.get(), nullptr, nullptr,
+                                    o.profile ? &prof : nullptr, &amg2, nullptr, ctx);
+      std::vector<SegState> h2(L->nseg);
+      RSB_HIP(hipMemcpyAsync(h2.data(), S.st.get(), L->nseg * sizeof(SegState),
+                             hipMemcpyDeviceToHost, ctx.stream));
+      RSB_HIP(hipMemcpyAsync(y2.get(), y64.get(), nr * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx.stream));
+      RSB_HIP(hipMemcpyAsync(y64.get(), y1.get(), nr * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx.stream));
+      RSB_HIP(hipMemcpyAsync(S.st.get(), st1.get(), L->nseg * sizeof(SegState),
+                             hipMemcpyDeviceToDevice, ctx.stream));
+      RSB_HIP(hipStreamSynchronize(ctx.stream));
+      std::vector<double> tv((size_t)L->nseg * S.nkcap, 0.0);
+      for (int i = 0; i < L->nseg; ++i) {
+        tv[(size_t)i * S.nkcap] = hs[i].rho;
+        if (S.nkcap > 1) tv[(size_t)i * S.nkcap + 1] = h2[i].rho;
+      }
+      RSB_HIP(hipMemcpyAsync(S.tvals.get(), tv.data(), tv.size() * sizeof(double),
+                             hipMemcpyHostToDevice, ctx.stream));
+      RSB_HIP(hipStreamSynchronize(ctx.stream));
+      min_perp2 = 0.01;
+    }
     if (o.fiedler_sweep > 0)
       fiedler_sweep(*L, C, S, y64.get(), y2.get(), o.fiedler_sweep, o.sweep_gap, &st.sweeps,
-                    &st.sweep_moved, ctx);
+                    &st.sweep_moved, ctx, min_perp2);
     if (fiedler_y) {
       const SegState &s = hs[0];
       RSB_HIP(hipMemcpyAsync(fiedler_y, y64.get(), meshes[0].nelem * sizeof(double),

@@ -52,6 +52,7 @@ struct SwArgs {
   const double *tvals;
   int nkcap;
   double gap;
+  double min_perp2;            // least squared norm of y2 off u0 and y1 to sweep
   SweepSeg *sw;
 };
 
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_setup(SwArgs a) {
     const double ca = S.invsqrt_nc * vals[0];  // u0^T y2
     const double cb = vals[1];                 // y1^T y2
     const double nn2 = vals[2] - ca * ca - cb * cb;
-    if (nn2 > 1e-12) {
+    if (nn2 > a.min_perp2) {
       w.on = 1;
       w.a = ca;
       w.b = cb;
@@ -255,7 +256,7 @@ void warm_update(Level &L, CompDev &C, SolveDev &S, const double *y2, double *wa
 }
 
 void fiedler_sweep(Level &L, CompDev &C, SolveDev &S, double *y64, const double *y2, int nangles,
-                   double sweep_gap, int *swept, int *moved, Ctx &ctx) {
+                   double sweep_gap, int *swept, int *moved, Ctx &ctx, double min_perp2) {
   const int64_t n = L.nrows;
   if (n == 0 || L.nseg == 0 || nangles < 1) return;
   hipStream_t st = ctx.stream;
@@ -274,6 +275,7 @@ void fiedler_sweep(Level &L, CompDev &C, SolveDev &S, double *y64, const double 
   a.tvals = S.tvals.get();
   a.nkcap = S.nkcap;
   a.gap = sweep_gap;
+  a.min_perp2 = min_perp2;
   a.sw = sw.get();
   // tiles cover every row of the level
   k_sw_row_seg<<<L.nblk, kBlock, 0, st>>>(L.d_blk.get(), row_seg.get());

@@ -123,3 +123,57 @@ def test_warm_start_unbatched_equals_batched():
     st1, p1, s1 = rsb.partition(ids, 8, **kw)
     st2, p2, s2 = rsb.partition(ids, 8, batched=0, **kw)
     assert np.array_equal(p1, p2)
+
+
+def _cut(orc, ids, y, graph):
+    rp, col, w = orc.dual_graph(ids, graph)
+    n = len(y)
+    side = orc.split(y, np.arange(n), n // 2)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    c = (side[rows] != side[col]) & (col > rows)
+    return int(w[c].sum())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_second_solve_sweeps_exactly_degenerate_pair(orc, precision):
+    # lambda_2 = lambda_3 on a 16 x 16 x 4 face box: the pair from two solves
+    # (second random start) is swept; the swept cut equals the oracle's and
+    # is never above the plain one
+    ids = mg.box_hex(16, 16, 4).ids
+    kw = dict(graph="face", fiedler_sweep=16, second_solve=1, **KW)
+    tol = 1e-4 if precision == "mixed" else 1e-10
+    st, lam, y, stats = rsb.fiedler(ids, precision=precision, **dict(kw, tol=tol))
+    ost, olam, oy, oinfo = orc.fiedler(ids, **kw)
+    st0, lam0, y0, _ = rsb.fiedler(ids, graph="face", **KW)
+    assert st == ost == st0 == 0
+    assert stats["sweeps"] == oinfo["sweeps"] == 1
+    cut, ocut = _cut(orc, ids, y, "face"), _cut(orc, ids, oy, "face")
+    print(f"[second solve] {precision}: cut {cut} oracle {ocut} plain {_cut(orc, ids, y0, 'face')}",
+          flush=True)
+    assert cut == ocut
+    assert cut <= _cut(orc, ids, y0, "face")
+
+
+def test_second_solve_leaves_simple_pair_alone(orc):
+    ids = mg.box_hex(20, 12, 8).ids
+    kw = dict(fiedler_sweep=8, **KW)
+    st0, p0, s0 = rsb.partition(ids, 8, **kw)
+    st1, p1, s1 = rsb.partition(ids, 8, second_solve=1, **kw)
+    st2, p2, s2 = rsb.partition(ids, 8, second_solve=1, batched=0, **kw)
+    ost, op, oinfo = orc.partition(ids, 8, second_solve=1, **kw)
+    assert st0 == st1 == st2 == ost == 0
+    assert s1["sweeps"] == s2["sweeps"] == oinfo["sweeps"] == 0
+    assert np.array_equal(p1, p0) and np.array_equal(p2, p0) and np.array_equal(p0, op)
+
+
+def test_second_solve_partition_degenerate_box(orc):
+    ids = mg.box_hex(16, 16, 8).ids
+    kw = dict(graph="face", fiedler_sweep=16, second_solve=1, **KW)
+    st, part, stats = rsb.partition(ids, 4, **kw)
+    st1, part1, _ = rsb.partition(ids, 4, batched=0, **kw)
+    ost, opart, oinfo = orc.partition(ids, 4, **kw)
+    assert st == st1 == ost == 0 and stats["sweeps"] == oinfo["sweeps"] >= 1
+    assert np.array_equal(part, part1)
+    cut = orc.metrics(ids, part, 4)["weighted_cut"]
+    ocut = orc.metrics(ids, opart, 4)["weighted_cut"]
+    assert abs(cut - ocut) <= 0.01 * ocut
