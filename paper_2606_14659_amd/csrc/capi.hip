@@ -93,6 +93,19 @@ void setup_ctx(Ctx &ctx, const rsb_opts &o) {
   }
   ctx.limit = o.device_mem_limit;
   ctx.verbose = o.verbose;
+  if (const char *env = std::getenv("RSB_LOG"))
+    if (std::string(env) == "level") ctx.verbose = std::max(ctx.verbose, 1);
+  if (const char *env = std::getenv("RSB_FAULT_INJECT")) {
+    const std::string f(env);
+    const size_t colon = f.find(':');
+    if (colon != std::string::npos) {
+      const int64_t at = std::atoll(f.c_str() + colon + 1);
+      if (f.compare(0, colon, "alloc") == 0) ctx.fault.alloc_at = at;
+      if (f.compare(0, colon, "launch") == 0) ctx.fault.launch_at = at;
+      ctx.fault.stream = ctx.stream;
+      fault_plan() = &ctx.fault;
+    }
+  }
   static std::once_flag once[64];
   if (o.device < 64)
     std::call_once(once[o.device], [&] {

@@ -44,11 +44,39 @@ struct Error {
     hipError_t e_ = hipGetLastError();                                                       \
     if (e_ != hipSuccess)                                                                    \
       ::rsb::fail(RSB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e_));      \
+    ::rsb::fault_point(false);                                                               \
   } while (0)
 
 // ---------------------------------------------------------------------------
 // Device memory from the stream-ordered pool, freed when the owner dies.
 // ---------------------------------------------------------------------------
+// Failure injection for tests of the error paths: the environment variable
+// RSB_FAULT_INJECT = "alloc:N" or "launch:N" makes the N-th device allocation,
+// or the N-th launch check made outside graph capture, of a call fail with
+// RSB_EDEVICE.  Read when a call sets up its context.
+struct FaultPlan {
+  int64_t alloc_at = 0, launch_at = 0;
+  int64_t allocs = 0, launches = 0;
+  hipStream_t stream = nullptr;
+};
+inline FaultPlan *&fault_plan() {
+  static thread_local FaultPlan *plan = nullptr;
+  return plan;
+}
+inline void fault_point(bool alloc) {
+  FaultPlan *f = fault_plan();
+  if (!f || (alloc ? f->alloc_at : f->launch_at) <= 0) return;
+  // never inside a stream capture: the capture must be ended by its owner
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (f->stream && hipStreamIsCapturing(f->stream, &cs) == hipSuccess &&
+      cs != hipStreamCaptureStatusNone)
+    return;
+  if (alloc && ++f->allocs == f->alloc_at)
+    fail(RSB_EDEVICE, "injected allocation failure (RSB_FAULT_INJECT)");
+  if (!alloc && ++f->launches == f->launch_at)
+    fail(RSB_EDEVICE, "injected launch failure (RSB_FAULT_INJECT)");
+}
+
 struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;  // created for a call that passed the null stream
@@ -58,10 +86,12 @@ struct Ctx {
   int64_t peak = 0;
   int verbose = 0;
   std::vector<std::string> tuned;  // tile classes timed during this call
+  FaultPlan fault;
   Ctx() = default;
   Ctx(const Ctx &) = delete;
   Ctx &operator=(const Ctx &) = delete;
   ~Ctx() {
+    if (fault_plan() == &fault) fault_plan() = nullptr;
     if (own_stream && stream) {
       (void)hipStreamSynchronize(stream);
       (void)hipStreamDestroy(stream);
@@ -92,6 +122,7 @@ struct DevBuf {
     ctx = &c;
     n = count;
     size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    fault_point(true);
     if (c.limit > 0 && c.in_use + (int64_t)bytes > c.limit)
       fail(RSB_ENOMEM, "device_mem_limit exceeded: need " + std::to_string(c.in_use + bytes) +
                            " bytes, limit " + std::to_string(c.limit));
