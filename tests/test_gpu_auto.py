@@ -57,3 +57,13 @@ def test_auto_partition_equals_lanczos_when_converged():
     st0, part0, stats0 = rsb.partition(HOLES.ids, 16, method="lanczos", **kw)
     assert stats["fallbacks"] == 0 and st == st0
     assert np.array_equal(part, part0)
+
+
+def test_auto_with_gather_scatter_operator():
+    # the Lanczos part through the gather-scatter operator; every bisection
+    # falls back, so the partition is inverse iteration's either way
+    kw = dict(tol=1e-8, method="auto", **CAPPED)
+    st, part, stats = rsb.partition(MESH.ids, 8, gather_scatter=1, **kw)
+    st0, part0, stats0 = rsb.partition(MESH.ids, 8, **kw)
+    assert stats["fallbacks"] == stats0["fallbacks"] == 7
+    assert st == st0 and np.array_equal(part, part0)
