@@ -1,8 +1,12 @@
 // capi.hip -- the C entry points: argument checks, device set-up, the level
 // loop of recursive spectral bisection (Alg. 1), and error reporting.
+#include <dlfcn.h>
+
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 
 #include "common.h"
@@ -12,6 +16,38 @@ namespace rsb {
 namespace {
 
 thread_local std::string g_last_error;
+
+// Named ranges for timeline tools (ROCTx), loaded at run time when
+// RSB_ROCTX=1 so that the library carries no link dependency on them:
+// rocprofv3 --marker-trace shows the call, each level and its phases.
+struct Roctx {
+  int (*push)(const char *) = nullptr;
+  int (*pop)() = nullptr;
+};
+const Roctx &roctx() {
+  static const Roctx r = [] {
+    Roctx x;
+    const char *e = std::getenv("RSB_ROCTX");
+    if (!e || std::strcmp(e, "1") != 0) return x;
+    void *h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+    if (!h) h = dlopen("/opt/rocm/lib/librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+    if (!h) return x;
+    x.push = (int (*)(const char *))dlsym(h, "roctxRangePushA");
+    x.pop = (int (*)())dlsym(h, "roctxRangePop");
+    if (!x.push || !x.pop) x = Roctx{};
+    return x;
+  }();
+  return r;
+}
+struct Range {
+  bool on;
+  explicit Range(const std::string &name) : on(roctx().push != nullptr) {
+    if (on) roctx().push(name.c_str());
+  }
+  ~Range() {
+    if (on) roctx().pop();
+  }
+};
 
 double now_ms() {
   using namespace std::chrono;
@@ -272,6 +308,15 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
   RunOut out;
   const double t0 = now_ms();
   rsb_stats st{};
+  // one range for the call and one for each phase in turn (ranges form a
+  // stack: the previous phase is closed before the next one opens)
+  Range call_range("rsb: partition");
+  std::unique_ptr<Range> phase;
+  auto phase_to = [&](const std::string &name) {
+    phase.reset();
+    phase.reset(new Range(name));
+  };
+  phase_to("rsb: dual graph");
   // 1. dual graphs
   std::vector<DevCsr> graphs(meshes.size());
   int64_t total = 0;
@@ -362,6 +407,8 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
   int level = 0;
   int worst = RSB_OK;
   while (L->nseg > 0) {
+    const std::string lv = "rsb: level " + std::to_string(level);
+    phase_to(lv + " components");
     const double ta = now_ms();
     const double prof_ms0 = prof.ms, prof_bytes0 = prof.bytes;
     SolveDev S;
@@ -371,6 +418,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     if (level == 0) st.tile_rows = kBlock * L->rpt;
     solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
     components_and_targets(*L, C, S, ctx);
+    phase_to(lv + " solve");
     int amg_levels = 0;
     const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(), y2.get(), warm.get(),
                                       o.profile ? &prof : nullptr, &amg_levels, &st.fallbacks, ctx);
@@ -479,6 +527,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
       }
       return out;
     }
+    phase_to(lv + " split and compaction");
     split_level(*L, C, S, y64.get(), side.get(), ctx);
     compact_level(*L, side.get(), d_part, *next, rpt, ctx);
     RSB_HIP(hipStreamSynchronize(ctx.stream));
@@ -510,6 +559,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
       off += meshes[b].nparts;
     }
   }
+  phase_to("rsb: metrics");
   if (L0.nseg > 0) partition_metrics(L0, d_part, (int32_t)parts_total, poff, &st, ctx);
   RSB_HIP(hipStreamSynchronize(ctx.stream));
   st.kernel_ms = prof.ms;
