@@ -252,7 +252,7 @@ def main():
         stats_summary(args)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build has "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has "
               "no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
