@@ -337,6 +337,8 @@ def partition_batch(ids_list, nparts_list, device: bool = False, **kw):
     """(status, [part], stats) for independent meshes in one call."""
     nmesh = len(ids_list)
     nv = _ids_shape(ids_list[0])[1]
+    if any(_ids_shape(a)[1] != nv for a in ids_list):
+        raise ValueError("every mesh of a batch must have the same number of ids per element")
     o = make_opts(device, **kw)
     arrs = [_Arr(a, np.int64, device) for a in ids_list]
     nelem = (C.c_int64 * nmesh)(*[int(a.shape[0]) for a in ids_list])

@@ -124,3 +124,10 @@ def test_python_binding_raises_without_library(monkeypatch):
     monkeypatch.setattr(rsb, "LIB_PATH", "/nonexistent/librsb.so")
     with pytest.raises(RuntimeError):
         rsb.lib()
+
+
+def test_batch_rejects_mixed_element_sizes():
+    quads = np.array([[0, 1, 2, 3]], dtype=np.int64)
+    hexes = np.arange(16, dtype=np.int64).reshape(2, 8)
+    with pytest.raises(ValueError):
+        rsb.partition_batch([quads, hexes], [1, 2])
