@@ -231,6 +231,18 @@ def test_c5a_rsb_4096_as_benchmarked():
     assert stats["levels"] == 12
 
 
+def test_c5a_run_to_run_identical():
+    # fixed-order reductions and timing-independent labelling: two runs of
+    # the benchmark partition give the same parts, bit for bit
+    mesh = mg.box256x128_clustered10()
+    ids = _torch_ids(mesh.ids)
+    st0, p0, s0 = rsb.partition(ids, 4096, device=True, **BENCH)
+    st1, p1, s1 = rsb.partition(ids, 4096, device=True, **BENCH)
+    assert st0 == st1
+    assert bool((p0 == p1).all())
+    assert s0["edge_cut"] == s1["edge_cut"] and s0["level_steps"] == s1["level_steps"]
+
+
 def test_c5b_batch64_16_parts():
     meshes = mg.batch64()
     st, parts, stats = rsb.partition_batch([m.ids for m in meshes], [16] * len(meshes), **BENCH)
