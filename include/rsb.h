@@ -83,9 +83,10 @@ typedef struct rsb_opts {
   int32_t max_restarts;     /* restarts after the first cycle (default 50) */
   double tol;               /* converged when ||L y - rho y||_2 <= tol * rho, rho =
                                y^T L y / y^T y of the Ritz vector y (default 1e-6) */
-  int32_t inv_max_outer;    /* INVERSE_CG: outer iterations cap (50) */
-  int32_t cg_max_iter;      /* INVERSE_CG: CG steps per solve cap (20000) */
-  double cg_tol;            /* INVERSE_CG: CG stops at ||r|| <= cg_tol ||b|| (1e-8) */
+  int32_t inv_max_outer;    /* inverse iteration (INVERSE_CG, AUTO's fallback): outer
+                               iterations cap (50) */
+  int32_t cg_max_iter;      /* inverse iteration: CG steps per solve cap (20000) */
+  double cg_tol;            /* inverse iteration: CG stops at ||r|| <= cg_tol ||b|| (1e-8) */
   int32_t cg_full_projection; /* inverse iteration: 0 (default) plain flexible CG; k in
                                  [1, 32]: every new direction is L-orthogonalised
                                  against the last k directions of the solve (the
@@ -119,7 +120,7 @@ typedef struct rsb_opts {
                                FP32 directions limit the reachable residual to
                                about 1e-5 lambda (lambda itself is accurate to
                                about 1e-12); use RSB_FP64 for tighter tol. */
-  int32_t inv_precond;      /* INVERSE_CG: RSB_PRECOND_NONE (default) or
+  int32_t inv_precond;      /* inverse iteration: RSB_PRECOND_NONE (default) or
                                RSB_PRECOND_AMG.  With AMG the first direction
                                of every CG solve is still the plain residual
                                (Sec. 7); later ones are one V-cycle of the
@@ -130,7 +131,8 @@ typedef struct rsb_opts {
                                coarse Laplacians, per subgraph. */
   int32_t amg_smooth;       /* AMG: damped-Jacobi steps per smoothing phase (1) */
   double amg_sigma;         /* AMG: Jacobi damping weight (2/3) */
-  int32_t fiedler_sweep;    /* LANCZOS with lanczos_keep >= 2: S > 0 sweeps the
+  int32_t fiedler_sweep;    /* Lanczos (RSB_LANCZOS or RSB_AUTO) with lanczos_keep >= 2:
+                               S > 0 sweeps the
                                Fiedler pair (Sec. 9: search the combinations of a
                                near-degenerate pair for the smallest cut).  When
                                the second Ritz value is within sweep_gap of the
@@ -139,7 +141,7 @@ typedef struct rsb_opts {
                                least weight is used (ties: smallest k).  0: off
                                (default); at most 64.  An exactly degenerate pair
                                shows a single Ritz vector and is not swept. */
-  int32_t warm_start;       /* LANCZOS with lanczos_keep >= 2: 1 = the solve of a
+  int32_t warm_start;       /* Lanczos (LANCZOS or AUTO), lanczos_keep >= 2: 1 = the solve of a
                                subgraph starts from its parent's second Ritz
                                vector (unit root-mean-square on the parent's cut
                                component) plus 0.1 x the random start; elements
