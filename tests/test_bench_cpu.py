@@ -76,3 +76,25 @@ def test_stored_traffic_only_for_its_workload_and_sources(tmp_path):
     f.write_text("workload: wl\nkernel: K\nsource_sha256_16: 0000000000000000\n"
                  "hbm_bytes_per_launch: 1234\n")
     assert bench.stored_traffic("wl", "K") is None
+
+
+def test_kernel_stats_table_sorted_by_device_time(tmp_path):
+    rows = [("void rsb::(anonymous namespace)::k_small<float>(int)", 10, 1.0e6, 1.0e5, 10.0),
+            ("void rsb::(anonymous namespace)::k_big<float, 4>(rsb::LzArgs<float>, int)",
+             4, 8.0e6, 2.0e6, 80.0),
+            ("k_mid", 2, 1.0e6, 5.0e5, 10.0)]
+    src = tmp_path / "kernel_stats.csv"
+    with open(src, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"])
+        w.writerows(rows)
+    out = tmp_path / "stats.txt"
+    r = subprocess.run([sys.executable, BENCH, "--stats-summary", str(src), "--out", str(out),
+                        "--commands", "cmd"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    lines = out.read_text().splitlines()
+    assert lines[1] == "# command: cmd"
+    assert "10.0 ms device time" in lines[2]
+    body = [l.split() for l in lines[4:]]
+    assert [b[0] for b in body] == ["k_big<float,", "k_small<float>", "k_mid"]
+    assert body[0][-4:] == ["4", "8.00", "2000.0", "80.00"]
