@@ -288,7 +288,8 @@ int rsb_amg_level(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
 
 /* u = M f: one V-cycle of that hierarchy (opts->amg_sigma, opts->amg_smooth)
  * on a caller CSR (same conventions), f and u of n doubles (host or device
- * per opts->device_pointers).  Exposed for testing the V-cycle. */
+ * per opts->device_pointers).  Exposed for testing the V-cycle.  Errors as
+ * rsb_amg_level, and RSB_EINVAL for a NULL f or u. */
 int rsb_amg_vcycle(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
                    const int32_t *weight, const double *f, double *u, const rsb_opts *opts);
 
@@ -335,7 +336,9 @@ int rsb_partition(int64_t nelem, int32_t nv_per_elem, const int64_t *elem_vertex
  * nelem[b] elements, ids elem_vertex_ids[b] and is split into nparts[b]
  * parts written to part_out[b].  With device_pointers == 1 the pointer
  * arrays themselves are host arrays of device pointers.  Results equal nmesh
- * separate rsb_partition calls. */
+ * separate rsb_partition calls; stats_out covers the whole call.  Errors:
+ * RSB_EINVAL for nmesh < 1, a NULL array or part_out entry, any mesh that
+ * rsb_partition would reject, or 2^28 or more elements in all. */
 int rsb_partition_batch(int32_t nmesh, const int64_t *nelem, int32_t nv_per_elem,
                         const int64_t *const *elem_vertex_ids, const int32_t *nparts,
                         const rsb_opts *opts, int32_t *const *part_out, rsb_stats *stats_out);
