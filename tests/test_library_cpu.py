@@ -131,3 +131,25 @@ def test_batch_rejects_mixed_element_sizes():
     hexes = np.arange(16, dtype=np.int64).reshape(2, 8)
     with pytest.raises(ValueError):
         rsb.partition_batch([quads, hexes], [1, 2])
+
+
+def test_batch_bad_arguments_rejected_before_any_device_call():
+    L = rsb.lib()
+    o = rsb.make_opts()
+    ids = np.array([[0, 1, 2, 3], [2, 3, 4, 5]], dtype=np.int64)
+    part = np.zeros(2, dtype=np.int32)
+    nelem = (C.c_int64 * 2)(2, 2)
+    idp = (C.c_void_p * 2)(ids.ctypes.data, ids.ctypes.data)
+    parts_ok = (C.c_int32 * 2)(2, 1)
+    out_ok = (C.c_void_p * 2)(part.ctypes.data, part.ctypes.data)
+    out_null = (C.c_void_p * 2)(part.ctypes.data, None)
+    too_many = (C.c_int32 * 2)(2, 3)
+    none = (C.c_int32 * 2)(0, 1)
+    for nmesh, pa, out, why in ((0, parts_ok, out_ok, b"bad arguments"),
+                                (2, parts_ok, out_null, b"part_out entry NULL"),
+                                (2, too_many, out_ok, b"nparts out of range"),
+                                (2, none, out_ok, b"nparts out of range")):
+        code = L.rsb_partition_batch(nmesh, nelem, 4, idp, pa, C.byref(o), out, None)
+        assert code == rsb.EINVAL and why in L.rsb_last_error()
+    assert L.rsb_partition_batch(2, nelem, 4, idp, parts_ok, C.byref(o), None, None) == rsb.EINVAL
+    assert L.rsb_partition_batch(2, None, 4, idp, parts_ok, C.byref(o), out_ok, None) == rsb.EINVAL
