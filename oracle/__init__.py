@@ -42,12 +42,21 @@ class Info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-def build(force: bool = True) -> str:
-    if force or not os.path.exists(LIB):
-        cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-o", LIB + ".tmp", SRC]
+# IEEE double without contraction into fused multiply-adds (the same bits
+# with or without an FMA unit), element loops threaded by OpenMP.
+CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off"]
+
+
+def build(force: bool = True, out: str = LIB, native: bool = False) -> str:
+    """Compile the oracle into `out`.  native=True adds -march=native (for
+    timing on the machine that runs it; the committed tests use the portable
+    build)."""
+    if force or not os.path.exists(out):
+        cmd = ["g++"] + CXXFLAGS + (["-march=native"] if native else []) + [
+            "-o", out + ".tmp", SRC]
         subprocess.run(cmd, check=True)
-        os.replace(LIB + ".tmp", LIB)
-    return LIB
+        os.replace(out + ".tmp", out)
+    return out
 
 
 _lib = None
@@ -58,36 +67,50 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
-        P = C.POINTER
-        L.orc_opts_default.argtypes = [P(Opts)]
-        L.orc_start_value.argtypes = [C.c_uint64, C.c_int64]
-        L.orc_start_value.restype = C.c_double
-        L.orc_dual_graph.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
-                                     C.c_void_p, C.c_void_p, P(C.c_int64)]
-        L.orc_laplacian_apply.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
-                                          C.c_void_p, C.c_void_p]
-        L.orc_tridiag_smallest.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
-                                           P(C.c_double), C.c_void_p]
-        L.orc_jacobi_eigen.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_fiedler.argtypes = [C.c_int64, C.c_int32, C.c_void_p, P(Opts), C.c_void_p,
-                                  P(C.c_double), P(Info)]
-        L.orc_fiedler_csr.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                      P(Opts), C.c_void_p, P(C.c_double), P(Info)]
-        L.orc_split.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
-        L.orc_gs_apply.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_locality_order.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_partition.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, P(Opts),
-                                    C.c_void_p, P(Info)]
-        L.orc_metrics.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
-                                  C.c_void_p]
-        L.orc_amg_level.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                    C.c_int32, P(C.c_int32), P(C.c_int64), P(C.c_int64),
-                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_amg_vcycle.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                     C.c_double, C.c_int32, C.c_void_p, C.c_void_p]
-        _lib = L
+        _lib = load(LIB)
     return _lib
+
+
+def load(path: str):
+    """Load an oracle library file and declare its functions."""
+    L = C.CDLL(path)
+    P = C.POINTER
+    L.orc_opts_default.argtypes = [P(Opts)]
+    L.orc_start_value.argtypes = [C.c_uint64, C.c_int64]
+    L.orc_start_value.restype = C.c_double
+    L.orc_dual_graph.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, P(C.c_int64)]
+    L.orc_laplacian_apply.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]
+    L.orc_tridiag_smallest.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
+                                       P(C.c_double), C.c_void_p]
+    L.orc_jacobi_eigen.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_fiedler.argtypes = [C.c_int64, C.c_int32, C.c_void_p, P(Opts), C.c_void_p,
+                              P(C.c_double), P(Info)]
+    L.orc_fiedler_csr.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  P(Opts), C.c_void_p, P(C.c_double), P(Info)]
+    L.orc_split.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+    L.orc_gs_apply.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_locality_order.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_partition.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, P(Opts),
+                                C.c_void_p, P(Info)]
+    L.orc_metrics.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                              C.c_void_p]
+    L.orc_amg_level.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_int32, P(C.c_int32), P(C.c_int64), P(C.c_int64),
+                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_amg_vcycle.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_double, C.c_int32, C.c_void_p, C.c_void_p]
+    L.orc_cg_solve.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               P(Opts), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                               P(C.c_int32)]
+    L.orc_set_threads.argtypes = [C.c_int32]
+    return L
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's element loops (0: unchanged); returns the count."""
+    return lib().orc_set_threads(int(n))
 
 
 def _ptr(a: np.ndarray):
@@ -271,6 +294,23 @@ def amg_vcycle(row_ptr, col, w, f, sigma=2.0 / 3.0, nsmooth=1, gid=None) -> np.n
     if rc != 0:
         raise RuntimeError(f"orc_amg_vcycle: {rc}")
     return u
+
+
+def cg_solve(row_ptr, col, w, b, gid=None, max_dirs=0, **kw):
+    """One inner CG solve of inverse iteration: (steps, x, directions) with
+    directions[k] = the k-th search direction (at most max_dirs of them)."""
+    n, rp, c, ww, g = _csr_args(row_ptr, col, w, gid)
+    o = opts(**kw)
+    bb = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(n, dtype=np.float64)
+    dirs = np.zeros((max(max_dirs, 1), n), dtype=np.float64)
+    nd = C.c_int32(0)
+    its = lib().orc_cg_solve(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(g), C.byref(o), _ptr(bb),
+                             _ptr(x), int(max_dirs), _ptr(dirs) if max_dirs > 0 else None,
+                             C.byref(nd))
+    if its < 0:
+        raise RuntimeError(f"orc_cg_solve: {its}")
+    return its, x, dirs[:nd.value]
 
 
 def split(y, gid, n_low) -> np.ndarray:

@@ -1,8 +1,10 @@
 // oracle.cpp -- plain FP64 CPU reference for recursive spectral bisection.
 //
 // TEST INFRASTRUCTURE ONLY: the GPU library never includes, links or calls
-// this file.  It is deliberately simple (maps, explicit loops, one thread)
-// so that each function can be checked against the paper by eye.
+// this file.  It is deliberately simple (maps, explicit loops) so that each
+// function can be checked against the paper by eye.  Element loops may run
+// on several OpenMP threads; sums keep one fixed order (fixed_sum), so the
+// thread count never changes a result.
 //
 // Readings where the paper is silent (each is also stated where it is used):
 //  * a vertex id repeated inside one element counts once (set semantics);
@@ -30,10 +32,41 @@
 #include <set>
 #include <unordered_map>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
 typedef std::vector<double> Vec;
+
+// ---------------------------------------------------------------------------
+// Threads (optional).  Loops over vector elements may run on several threads;
+// every sum over elements is taken in one fixed order: consecutive chunks of
+// kSumChunk terms are summed one by one, then the chunk sums in chunk order.
+// Chunk boundaries do not depend on the thread count, so one thread and many
+// threads give the same bits.  Element-wise loops have no order to keep.
+// ---------------------------------------------------------------------------
+constexpr int64_t kSumChunk = 4096;
+// element loops run threaded only above this length (thread start-up costs
+// more than it saves on short vectors)
+constexpr int64_t kThreadMin = 16384;
+
+template <class F>
+double fixed_sum(int64_t n, F term) {
+  const int64_t nc = (n + kSumChunk - 1) / kSumChunk;
+  std::vector<double> part((size_t)std::max<int64_t>(nc, 1), 0.0);
+#pragma omp parallel for schedule(static) if (nc >= 4)
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t lo = c * kSumChunk, hi = std::min(n, lo + kSumChunk);
+    double s = 0.0;
+    for (int64_t i = lo; i < hi; ++i) s += term(i);
+    part[(size_t)c] = s;
+  }
+  double s = 0.0;
+  for (int64_t c = 0; c < nc; ++c) s += part[(size_t)c];
+  return s;
+}
 
 // ---------------------------------------------------------------------------
 // Graph held as adjacency lists (sorted by neighbour index).
@@ -80,6 +113,7 @@ Graph build_dual_graph(int64_t nelem, int nv, const int64_t *ids, int32_t graph)
 
 // y = L x with L = D - A (Sec. 4): l_ii = sum_j w_ij, l_ij = -w_ij.
 void apply_laplacian(const Graph &g, const Vec &x, Vec &y) {
+#pragma omp parallel for schedule(static) if (g.n >= kThreadMin)
   for (int64_t i = 0; i < g.n; ++i) {
     double d = 0.0, ax = 0.0;
     for (auto &nw : g.adj[i]) {
@@ -91,9 +125,8 @@ void apply_laplacian(const Graph &g, const Vec &x, Vec &y) {
 }
 
 double dot(const Vec &a, const Vec &b) {
-  double s = 0.0;
-  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
-  return s;
+  const double *pa = a.data(), *pb = b.data();
+  return fixed_sum((int64_t)a.size(), [=](int64_t i) { return pa[i] * pb[i]; });
 }
 
 double norm2(const Vec &a) { return std::sqrt(dot(a, a)); }
@@ -217,15 +250,20 @@ int tridiag_smallest(int k, const double *a, const double *b, double thr, double
 
 // Remove the ones-vector component: x <- x - (u0^T x) u0 with u0 = 1/sqrt(n).
 void deflate_ones(Vec &x) {
-  double mean = 0.0;
-  for (double v : x) mean += v;
-  mean /= (double)x.size();
-  for (double &v : x) v -= mean;
+  const int64_t n = (int64_t)x.size();
+  double *px = x.data();
+  double mean = fixed_sum(n, [=](int64_t i) { return px[i]; });
+  mean /= (double)n;
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
+  for (int64_t i = 0; i < n; ++i) px[i] -= mean;
 }
 
 void normalize(Vec &x) {
-  double nr = norm2(x);
-  for (double &v : x) v /= nr;
+  const int64_t n = (int64_t)x.size();
+  double *px = x.data();
+  const double nr = norm2(x);
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
+  for (int64_t i = 0; i < n; ++i) px[i] /= nr;
 }
 
 // Canonical sign: the first element in global-id order whose magnitude is at
@@ -244,8 +282,11 @@ double residual_norm(const Graph &g, const Vec &y, double theta, int64_t &matvec
   Vec ly(g.n);
   apply_laplacian(g, y, ly);
   ++matvecs;
-  double s = 0.0;
-  for (int64_t i = 0; i < g.n; ++i) s += (ly[i] - theta * y[i]) * (ly[i] - theta * y[i]);
+  const double *pl = ly.data(), *py = y.data();
+  const double s = fixed_sum(g.n, [=](int64_t i) {
+    const double r = pl[i] - theta * py[i];
+    return r * r;
+  });
   return std::sqrt(s);
 }
 
@@ -350,6 +391,7 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
   const int64_t n = g.n;
   const double u0 = 1.0 / std::sqrt((double)n);
   Vec q(n);
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
   for (int64_t i = 0; i < n; ++i) {
     q[i] = start_value(o.seed, gid[i]);
     if (warm) {
@@ -385,6 +427,7 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
       apply_laplacian(g, Q[j], w);
       ++info.matvecs;
       double a = dot(Q[j], w);
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
       for (int64_t i = 0; i < n; ++i) {
         w[i] -= a * Q[j][i];
         if (j == nk)
@@ -394,10 +437,11 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
       }
       // two classical Gram-Schmidt passes against [u0, Q[0..j]]
       for (int pass = 0; pass < 2; ++pass) {
-        double h0 = 0.0;
-        for (int64_t i = 0; i < n; ++i) h0 += u0 * w[i];
+        const double *pw = w.data();
+        const double h0 = fixed_sum(n, [=](int64_t i) { return u0 * pw[i]; });
         std::vector<double> h(j + 1);
         for (int k = 0; k <= j; ++k) h[k] = dot(Q[k], w);
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
         for (int64_t i = 0; i < n; ++i) {
           double s = h0 * u0;
           for (int k = 0; k <= j; ++k) s += h[k] * Q[k][i];
@@ -418,6 +462,7 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
       beta.push_back(b);
       H[(size_t)j * m + j + 1] = H[(size_t)(j + 1) * m + j] = b;
       Vec qn(n);
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
       for (int64_t i = 0; i < n; ++i) qn[i] = w[i] / b;
       Q.push_back(qn);
     }
@@ -441,8 +486,9 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
     }
     // Ritz vector y = Q t, re-projected against the ones vector and normalised
     y.assign(n, 0.0);
-    for (int c = 0; c < k; ++c)
-      for (int64_t i = 0; i < n; ++i) y[i] += t[c] * Q[c][i];
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
+    for (int64_t i = 0; i < n; ++i)
+      for (int c = 0; c < k; ++c) y[i] += t[c] * Q[c][i];
     deflate_ones(y);
     normalize(y);
     // residual against the Rayleigh quotient rho of the Ritz vector
@@ -455,10 +501,10 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
         second->theta1 = ev[first];
         second->theta2 = ev[first + 1];
         second->y2.assign(n, 0.0);
-        for (int c = 0; c < k; ++c) {
-          const double tc = EV[(size_t)c * k + first + 1];
-          for (int64_t i = 0; i < n; ++i) second->y2[i] += tc * Q[c][i];
-        }
+        Vec &y2 = second->y2;
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
+        for (int64_t i = 0; i < n; ++i)
+          for (int c = 0; c < k; ++c) y2[i] += EV[(size_t)c * k + first + 1] * Q[c][i];
       }
     }
     if (res <= o.tol * rho) {
@@ -476,10 +522,9 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
     Ynew.push_back(y);
     for (int c = 1; c < nkeep; ++c) {
       Vec yc(n, 0.0);
-      for (int r = 0; r < k; ++r) {
-        const double tr = EV[(size_t)r * k + first + c];
-        for (int64_t i = 0; i < n; ++i) yc[i] += tr * Q[r][i];
-      }
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
+      for (int64_t i = 0; i < n; ++i)
+        for (int r = 0; r < k; ++r) yc[i] += EV[(size_t)r * k + first + c] * Q[r][i];
       Ynew.push_back(yc);
     }
     th_keep.assign(nkeep, 0.0);
@@ -489,6 +534,7 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
       s_keep[c] = last_b * EV[(size_t)(k - 1) * k + first + c];
     }
     Y.swap(Ynew);
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
     for (int64_t i = 0; i < n; ++i) q[i] = w[i] / last_b;
   }
   info.theta = theta;
@@ -682,8 +728,10 @@ void vcycle(const std::vector<AmgLevel> &lv, size_t l, const Vec &f, double sigm
 // z_new^T (r_new - r_old) / z_old^T r_old; optional L-orthogonalisation of
 // every new direction against the kept ones ("full projection").
 // Returns iterations.
+// If dirs is given, every search direction p is appended to it before its
+// step (test hook: the directions of one solve).
 int cg_solve(const Graph &g, const Vec &b, const orc_opts &o, const std::vector<AmgLevel> *amg,
-             Vec &x, int64_t &matvecs) {
+             Vec &x, int64_t &matvecs, std::vector<Vec> *dirs = nullptr) {
   const int64_t n = g.n;
   x.assign(n, 0.0);
   Vec r = b, p, lp(n), z;
@@ -697,11 +745,13 @@ int cg_solve(const Graph &g, const Vec &b, const orc_opts &o, const std::vector<
   int it = 0;
   if (norm2(r) <= o.cg_tol * bnorm) return 0;
   for (it = 1; it <= o.cg_max_iter; ++it) {
+    if (dirs) dirs->push_back(p);
     apply_laplacian(g, p, lp);
     ++matvecs;
     double plp = dot(p, lp);
     double alpha = rz / plp;
     Vec rn(n);
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
     for (int64_t i = 0; i < n; ++i) {
       x[i] += alpha * p[i];
       rn[i] = r[i] - alpha * lp[i];
@@ -715,8 +765,8 @@ int cg_solve(const Graph &g, const Vec &b, const orc_opts &o, const std::vector<
     } else {
       zn = rn;
     }
-    double diff = 0.0;
-    for (int64_t i = 0; i < n; ++i) diff += zn[i] * (rn[i] - r[i]);
+    const double *pz = zn.data(), *prn = rn.data(), *pr = r.data();
+    const double diff = fixed_sum(n, [=](int64_t i) { return pz[i] * (prn[i] - pr[i]); });
     double beta = diff / rz;
     if (o.cg_full_projection > 0) {
       P.push_back(p);
@@ -728,10 +778,14 @@ int cg_solve(const Graph &g, const Vec &b, const orc_opts &o, const std::vector<
         pLp.erase(pLp.begin());
       }
     }
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
     for (int64_t i = 0; i < n; ++i) p[i] = zn[i] + beta * p[i];
     for (size_t k = 0; k < P.size(); ++k) {
       double c = dot(LP[k], p) / pLp[k];
-      for (int64_t i = 0; i < n; ++i) p[i] -= c * P[k][i];
+      const double *pk = P[k].data();
+      double *pp = p.data();
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
+      for (int64_t i = 0; i < n; ++i) pp[i] -= c * pk[i];
     }
     r = rn;
     z = zn;
@@ -1188,6 +1242,40 @@ int orc_fiedler_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const
   if (st < 0) return st;
   std::copy(yv.begin(), yv.end(), y);
   return st;
+}
+
+int orc_cg_solve(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                 const int64_t *gid, const orc_opts *o, const double *b, double *x,
+                 int32_t max_dirs, double *dirs, int32_t *ndirs) {
+  if (n < 2 || !row_ptr || !col || !weight || !gid || !o || !b || !x) return -1;
+  if (max_dirs < 0 || (max_dirs > 0 && (!dirs || !ndirs))) return -1;
+  Graph g;
+  to_graph(n, row_ptr, col, weight, g);
+  std::vector<int64_t> gv(gid, gid + n);
+  std::vector<AmgLevel> amg;
+  if (o->inv_precond == ORC_PRECOND_AMG) amg = amg_setup(g, gv);
+  Vec bv(b, b + n), xv;
+  std::vector<Vec> dv;
+  int64_t matvecs = 0;
+  const int its = cg_solve(g, bv, *o, amg.empty() ? nullptr : &amg, xv, matvecs,
+                           max_dirs > 0 ? &dv : nullptr);
+  std::copy(xv.begin(), xv.end(), x);
+  if (max_dirs > 0) {
+    const int32_t nd = (int32_t)std::min<size_t>(dv.size(), (size_t)max_dirs);
+    for (int32_t k = 0; k < nd; ++k) std::copy(dv[k].begin(), dv[k].end(), dirs + (int64_t)k * n);
+    *ndirs = nd;
+  }
+  return its;
+}
+
+int orc_set_threads(int32_t nthreads) {
+#ifdef _OPENMP
+  if (nthreads >= 1) omp_set_num_threads(nthreads);
+  return omp_get_max_threads();
+#else
+  (void)nthreads;
+  return 1;
+#endif
 }
 
 int orc_fiedler(int64_t nelem, int32_t nv, const int64_t *ids, const orc_opts *o, double *y,

@@ -18,7 +18,11 @@
  *     locality order of the elements (standing in for the coordinate
  *     pre-sort of Sec. 5 and Sec. 8).
  *
- * All arithmetic is IEEE double, round to nearest, single-threaded.
+ * All arithmetic is IEEE double, round to nearest, without contraction into
+ * fused multiply-adds.  Loops over vector elements may run on several
+ * threads (OpenMP, see orc_set_threads); every sum over elements is taken in
+ * a fixed order of fixed chunks, so the results do not depend on the number
+ * of threads, bit for bit.
  */
 #ifndef RSB_ORACLE_H
 #define RSB_ORACLE_H
@@ -117,6 +121,21 @@ int orc_fiedler(int64_t nelem, int32_t nv, const int64_t *ids, const orc_opts *o
 int orc_fiedler_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
                     const int64_t *gid, const orc_opts *o, double *y, double *lambda,
                     orc_info *info);
+
+/* One inner solve of inverse iteration (Sec. 7, Alg. 2): CG for L x = b on
+ * the ones-complement, from x = 0, with the options' cg_tol, cg_max_iter,
+ * cg_full_projection and preconditioner (gid[i]: global id of row i, used by
+ * the multigrid setup).  Returns the number of CG steps (<0 on bad input).
+ * With max_dirs > 0 the first max_dirs search directions p_0, p_1, ... are
+ * written row-major to dirs ([max_dirs][n]) and their count to *ndirs. */
+int orc_cg_solve(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                 const int64_t *gid, const orc_opts *o, const double *b, double *x,
+                 int32_t max_dirs, double *dirs, int32_t *ndirs);
+
+/* Threads for the element loops (when built with OpenMP; otherwise one).
+ * nthreads < 1 leaves the setting unchanged.  Returns the thread count in
+ * effect. */
+int orc_set_threads(int32_t nthreads);
 
 /* The split rule on a given vector: side[i] = 0 for the n_low smallest keys
  * (y_i, gid_i), 1 otherwise. */
