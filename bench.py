@@ -54,30 +54,97 @@ def make_mesh(name):
     raise ValueError(name)
 
 
-def cpu_baseline(mesh, seconds_target=20.0):
-    """The CPU oracle on a bounded sample of the workload: one Lanczos cycle
-    (m = 100) on the dual graph of a sub-box of the same mesh (its first
-    elements in lexicographic order), scaled to iterations/s on the full
-    mesh by the element ratio (the work per iteration is linear in n)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(mesh, nparts, m, keep, tol, warm_start, max_restarts):
+    """The CPU oracle (FP64, built here with -O3 -march=native) on a bounded
+    sample of the workload, with the GPU run's solver settings.
+
+    Rate: Lanczos steps of the oracle's solver (cycles of m steps keeping
+    `keep` Ritz pairs, two full Gram-Schmidt passes per step) on the dual
+    graph of the first tenth of the mesh's elements (a slab of the box,
+    lexicographic order), three cycles; scaled by the element ratio to
+    iterations/s of the whole mesh (the work of a step is linear in the
+    rows).  Run on one thread and on every thread the host grants (OpenMP;
+    the oracle's sums keep one order, so the results are the same).
+    Partition: the oracle's whole recursive bisection of the first 1/64 of
+    the elements into nparts/64 parts, every thread.
+    """
+    import tempfile
+
     import numpy as np
 
     import oracle
-    frac = 1.0 / 10.0
-    n_sample = max(2, int(mesh.nelem * frac))
-    ids = mesh.ids[:n_sample]
-    rp, col, w = oracle.dual_graph(ids)
+    path = os.path.join(tempfile.mkdtemp(prefix="rsb_oracle_"), "liboracle_native.so")
+    oracle.build(force=True, out=path, native=True)
+    oracle.use_library(path)
+    nthreads = oracle.set_threads(0)
+    n_sample = max(2, mesh.nelem // 10)
+    rp, col, w = oracle.dual_graph(mesh.ids[:n_sample])
+    kw = dict(lanczos_m=m, lanczos_keep=keep, max_restarts=2, tol=1e-14)
+    rates = {}
+    for thr in (1, nthreads):
+        oracle.set_threads(thr)
+        t0 = time.perf_counter()
+        st, lam, y, info = oracle.fiedler_csr(rp, col, w, None, **kw)
+        dt = time.perf_counter() - t0
+        steps = m + (info["cycles"] - 1) * (m - keep) if keep else m * info["cycles"]
+        rates[thr] = (steps / dt * n_sample / mesh.nelem, steps, dt)
+    n_part = max(2, mesh.nelem // 64)
+    p_part = max(2, nparts // 64)
+    oracle.set_threads(nthreads)
     t0 = time.perf_counter()
-    st, lam, y, info = oracle.fiedler_csr(rp, col, w, np.arange(n_sample), lanczos_m=100,
-                                          max_restarts=0, tol=1e-12)
-    dt = time.perf_counter() - t0
-    steps = 100
-    iters_per_s_sample = steps / dt
-    return {"value": iters_per_s_sample * n_sample / mesh.nelem, "unit": "Lanczos iterations/s",
-            "cores": 1, "kind": "oracle",
-            "sample": (f"one 100-step Lanczos cycle (FP64, full reorthogonalisation) on the dual "
-                       f"graph of the first {n_sample} elements of the same mesh, {dt:.1f} s; "
-                       f"scaled by {n_sample}/{mesh.nelem} elements"),
-            "cpu": platform.processor() or platform.machine()}
+    pst, part, pinfo = oracle.partition(mesh.ids[:n_part], p_part, lanczos_m=m, lanczos_keep=keep,
+                                        tol=tol, warm_start=int(warm_start),
+                                        max_restarts=max_restarts)
+    t_part = time.perf_counter() - t0
+    v1, s1, d1 = rates[1]
+    vn, sn, dn = rates[nthreads]
+    return {"value": vn, "unit": "Lanczos iterations/s", "cores": nthreads, "kind": "oracle",
+            "sample": (f"oracle (FP64, g++ -O3 -march=native, {nthreads} OpenMP threads) thick-"
+                       f"restart Lanczos m={m}, keep={keep}, 3 cycles ({sn} steps, {dn:.1f} s) "
+                       f"on the dual graph of the first {n_sample} of {mesh.nelem} elements, "
+                       f"scaled by the element ratio"),
+            "value_1thread": v1,
+            "sample_1thread": f"the same on one thread: {s1} steps, {d1:.1f} s",
+            "cpu": cpu_model(),
+            "partition_sample": {"elements": n_part, "nparts": p_part, "seconds": t_part,
+                                 "threads": nthreads, "status": pst,
+                                 "settings": f"m={m}, keep={keep}, tol={tol}, "
+                                             f"warm_start={int(warm_start)}"}}
+
+
+GOLDENS = os.path.join(ROOT, "tests", "golden", "config_goldens.json")
+GOLDEN_KEYS = {"box256x256x128-clustered10-renum-4096": ("c5a_level0", "c5a_rsb4096"),
+               "box256x256x64-holes3-1024": ("c3_level0", "c3_rsb1024")}
+
+
+def oracle_comparison(workload, lambda2, residual, cut):
+    """The run's first-bisection eigenvalue and final cut against the
+    oracle's (stored results of the oracle at tight tolerance)."""
+    keys = GOLDEN_KEYS.get(workload)
+    if not keys or not os.path.exists(GOLDENS):
+        return None
+    g = json.load(open(GOLDENS))
+    out = {"source": "tests/golden/config_goldens.json"}
+    if keys[0] in g and lambda2 > 0:
+        ol = g[keys[0]]["lambda2"]
+        out.update(level0_lambda2_oracle=ol, level0_lambda2_rel_err=(lambda2 - ol) / ol,
+                   level0_oracle_tol=g[keys[0]]["solver"]["tol"])
+    if keys[1] in g:
+        oc = g[keys[1]]["edge_cut"]
+        out.update(edge_cut_oracle=oc, edge_cut_rel_diff=(cut - oc) / oc,
+                   oracle_partition_tol=g[keys[1]]["solver"]["tol"])
+    return out
 
 
 KERNEL_SOURCES = ("lanczos.hip", "solver_dev.h", "common.h", "kernels.h")
@@ -222,6 +289,8 @@ def main():
     ap.add_argument("--precond", default="none", choices=["none", "amg"],
                     help="inverse_cg: plain CG or aggregation-multigrid preconditioned CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-per-subgraph", type=int, default=1, choices=[0, 1],
+                    help="after the timed steps, one run of the per-subgraph FP64 path")
     ap.add_argument("--verbose", type=int, default=0)
     ap.add_argument("--unbatched", action="store_true")
     ap.add_argument("--rows-per-thread", type=int, default=0, choices=[0, 2, 4, 8])
@@ -349,6 +418,10 @@ def main():
         "ms_solve": st["ms_solve"],
         "ms_split": st["ms_split"],
         "ms_reorder": st["ms_reorder"],
+        "level0_lambda2": st["lambda2"],
+        "level0_residual_rel": st["residual"] / st["lambda2"] if st["lambda2"] > 0 else None,
+        "oracle": oracle_comparison(args.workload, st["lambda2"], st["residual"],
+                                    st["edge_cut"]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": stored_traffic(args.workload, KERNEL_LABEL)
@@ -360,8 +433,29 @@ def main():
                      "launches": kern_launches,
                      "avg_us": kern_ms * 1e3 / max(kern_launches, 1)},
     }
+    if args.compare_per_subgraph:
+        # the plain per-subgraph FP64 GPU path: the same solver settings,
+        # FP64, every subgraph of a level solved on its own (one run)
+        t0 = time.perf_counter()
+        o = rsb.make_opts(True, **dict(opts, precision="fp64", batched=0))
+        pst = rsb.Stats()
+        pst.struct_size = rsb.C.sizeof(rsb.Stats)
+        pcode = rsb.lib().rsb_partition(mesh.nelem, mesh.nv, rsb.C.c_void_p(ids.data_ptr()),
+                                        wl["nparts"], rsb.C.byref(o),
+                                        rsb.C.c_void_p(part.data_ptr()), rsb.C.byref(pst))
+        rsb._check(pcode, "rsb_partition")
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        ps = pst.as_dict()
+        out["per_subgraph_fp64"] = {"ms": pdt * 1e3, "status": pcode,
+                                    "edge_cut": ps["edge_cut"],
+                                    "segment_steps": ps["segment_steps"],
+                                    "speedup_of_batched": pdt * 1e3 / out["ms_per_step"]}
+        print(f"[bench] per-subgraph FP64: {pdt * 1e3:.0f} ms, status {pcode}", file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh)
+        out["cpu_baseline"] = cpu_baseline(mesh, wl["nparts"], args.m, args.keep, args.tol,
+                                           args.warm_start, args.max_restarts)
     print(json.dumps(out), flush=True)
 
 

@@ -70,9 +70,15 @@ extern "C" {
                        accumulation); in FP64: the restart (Ritz) vector and the
                        first Lanczos vector of every cycle, residuals, alpha,
                        beta, reorthogonalisation projections and the
-                       tridiagonal solve.  Each restart refines the FP64 Ritz
-                       vector by an FP32 correction, so the pair converges to
-                       the FP64 tolerance. */
+                       tridiagonal solve.  Explicit restart: each restart
+                       refines the FP64 Ritz vector by an FP32 correction, so
+                       the pair converges to the FP64 tolerance.  Thick
+                       restart: FP32 rounding stalls the residual near a
+                       multiple of 2^-24 ||L|| (about 0.6 2^-24 ||L|| /
+                       lambda relative); a subgraph whose residual stalls
+                       short of tol continues from its Ritz vector with FP64
+                       directions until the FP64 residual meets tol (its
+                       FP64 cycles count in max_restarts). */
 
 typedef struct rsb_opts {
   int32_t struct_size;      /* sizeof(rsb_opts); set by rsb_opts_init */
@@ -116,10 +122,9 @@ typedef struct rsb_opts {
                                Lanczos variant the paper cites in Sec. 6) keeping
                                the k smallest Ritz pairs and continuing from the
                                last residual direction.  With precision =
-                               RSB_MIXED the kept Ritz vectors stay FP64 and the
-                               FP32 directions limit the reachable residual to
-                               about 1e-5 lambda (lambda itself is accurate to
-                               about 1e-12); use RSB_FP64 for tighter tol. */
+                               RSB_MIXED the kept Ritz vectors stay FP64, and a
+                               solve that stalls short of tol finishes with FP64
+                               directions (see RSB_MIXED). */
   int32_t inv_precond;      /* inverse iteration: RSB_PRECOND_NONE (default) or
                                RSB_PRECOND_AMG.  With AMG the first direction
                                of every CG solve is still the plain residual
@@ -187,8 +192,10 @@ typedef struct rsb_stats {
   int64_t spmv_fp64;         /* SpMVs run with FP64 vectors (level launches) */
   int32_t not_converged;     /* segments that hit the iteration caps */
   int32_t disconnected;      /* bisections of disconnected graphs */
-  double lambda2;            /* rsb_fiedler: Rayleigh quotient of the output */
-  double residual;           /* rsb_fiedler: ||L y - lambda y|| of the output */
+  double lambda2;            /* rsb_fiedler: Rayleigh quotient of the output;
+                                rsb_partition(_batch): of the first bisection's
+                                Fiedler vector (of the first mesh) */
+  double residual;           /* ||L y - lambda y|| of that vector (FP64) */
   double ms_graph;           /* dual-graph build (device time) */
   double ms_solve;           /* eigen-solves */
   double ms_split;           /* components, split and compaction */

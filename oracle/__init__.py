@@ -71,6 +71,14 @@ def lib():
     return _lib
 
 
+def use_library(path: str):
+    """Load the oracle from another build of the same source (for example a
+    -march=native build for timing) and use it from now on."""
+    global _lib
+    _lib = load(path)
+    return _lib
+
+
 def load(path: str):
     """Load an oracle library file and declare its functions."""
     L = C.CDLL(path)

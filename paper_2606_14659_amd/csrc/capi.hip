@@ -420,6 +420,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     components_and_targets(*L, C, S, ctx);
     phase_to(lv + " solve");
     int amg_levels = 0;
+    const int64_t fp64_steps0 = ctx.fp64_level_steps;
     const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(), y2.get(), warm.get(),
                                       o.profile ? &prof : nullptr, &amg_levels, &st.fallbacks, ctx);
     if (o.warm_start) warm_update(*L, C, S, y2.get(), warm.get(), ctx);
@@ -432,6 +433,11 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
                            ctx.stream));
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     const double tb = now_ms();
+    if (level == 0 && L->nseg >= 1 && hs[0].solve) {
+      // the first bisection's Fiedler pair (of the first mesh)
+      st.lambda2 = hs[0].rho;
+      st.residual = hs[0].res;
+    }
     st.ms_solve += tb - ta;
     st.level_steps += steps;
     st.segment_steps += segsteps;
@@ -442,10 +448,12 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
       st.cycles += s.cycles;
       cyc = std::max(cyc, s.cycles);
     }
-    // FP64 SpMV launches: all of them in FP64 mode; steps 1-2 and the
-    // residual of every cycle with FP32 directions
-    st.spmv_fp64 += (o.precision == RSB_MIXED && o.method != RSB_INVERSE_CG) ? 3 * (int64_t)cyc
-                                                                          : steps + cyc;
+    // FP64 SpMV launches: all of them in FP64 mode; with FP32 directions,
+    // steps 1-2 and the residual of every cycle, and every step of the
+    // cycles continued with FP64 directions
+    st.spmv_fp64 += (o.precision == RSB_MIXED && o.method != RSB_INVERSE_CG)
+                        ? 3 * (int64_t)cyc + (ctx.fp64_level_steps - fp64_steps0)
+                        : steps + cyc;
     st.disconnected += disc;
     st.not_converged += notconv;
     if (disc) worst = std::max(worst, RSB_WARN_DISCONNECTED);

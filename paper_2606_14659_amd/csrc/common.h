@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -86,6 +87,7 @@ struct Ctx {
   int64_t peak = 0;
   int verbose = 0;
   std::vector<std::string> tuned;  // tile classes timed during this call
+  int64_t fp64_level_steps = 0;    // mixed precision: level steps continued with FP64 directions
   FaultPlan fault;
   Ctx() = default;
   Ctx(const Ctx &) = delete;

@@ -98,7 +98,10 @@ struct SegState {
   int32_t j0;           // first Lanczos step of the current cycle (1, or nk + 1 after a thick restart)
   int32_t nk;           // Ritz pairs kept at the head of the current cycle's basis
   int32_t nnext;        // Ritz pairs formed at the end of the cycle (thick restart)
-  int32_t pad;
+  int32_t refine;       // mixed precision: 1 = stopped where FP32 directions stall with
+                        // the tolerance not met, 2 = continued with FP64 directions
+  int32_t stall;        // consecutive cycles whose residual changed by <= 5%
+  int32_t pad2;
 };
 
 // The Laplacian in gather-scatter form (Sec. 5: A_w = P^T Q Q^T P,

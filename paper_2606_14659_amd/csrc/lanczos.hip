@@ -44,6 +44,19 @@ namespace {
 // parent's second Ritz vector.
 constexpr double kWarmNoise = 0.1;
 
+// Mixed precision with thick restart: FP32 directions carry rounding errors
+// of order u ||L|| (u = 2^-24) into the Lanczos relation, so the residual of
+// the FP64 Ritz vector stalls near a multiple of u ||L|| (measured: 0.6 u ||T||
+// to within a factor two, from 6.9e-7 lambda on a 60-element box to 4.2e-4
+// lambda on a 1M-element mesh).  A segment whose residual has changed by at
+// most kStallChange over kStallCycles consecutive cycles, within
+// kStallScale u ||T|| (the early cycles of a solve can swing widely above
+// that), and has not met the tolerance, switches to FP64 directions.
+constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24
+constexpr double kStallChange = 0.05;
+constexpr int kStallCycles = 2;
+constexpr double kStallScale = 64.0;
+
 template <typename T>
 struct LzArgs {
   const BlkDev *blk;
@@ -74,10 +87,13 @@ struct LzArgs {
   T *Wt0, *Wt1;  // ping-pong work vectors of steps >= 2
   int m;
   double tol;
+  int fp32_stall;     // T = float, thick restart: park a segment whose residual
+                      // stalls (it continues with FP64 directions)
   int max_restarts;
   double brk;    // breakdown threshold (relative to ||T||) of the type-T steps
   int32_t *flags;          // [0] active segments after the cycle, [1] last step index
-                           // reached in the cycle, [2] most steps run by a segment
+                           // reached in the cycle, [2] most steps run by a segment,
+                           // [3] segments stopped at the FP32 switch point (whole level)
   unsigned long long *ctr; // [0] segment steps
   uint64_t seed;
   const int32_t *orig;     // row -> element index of the whole call (-1: padding)
@@ -761,6 +777,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
       W.cycle_done = 0;
       W.need2 = 0;
       W.converged = 0;
+      W.refine = 0;
+      W.stall = 0;
       W.restarts = 0;
       W.tnorm = 0.0;
       W.res = 0.0;
@@ -780,6 +798,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
     const double rho = vals[1] / vals[2];
     const double dth = th - rho;
     const double res = sqrt(fmax(vals[0] - dth * dth * vals[2], 0.0));
+    const double res_prev = W.res;
     W.res = res;
     W.rho = rho;
     W.cycles += 1;
@@ -794,12 +813,25 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
       W.active = 0;
       return;
     }
+    // FP32 directions stall the residual near a multiple of u ||L||: such a
+    // segment is parked, and the level continues it with FP64 directions by
+    // an explicit restart from the Ritz vector.  (A thick restart would carry
+    // on the relation L y_i = theta_i y_i + s_i q of the kept vectors, which
+    // FP32 rounding has broken at about the stall level: the FP64 cycles
+    // would not see the error and the residual would not move.)
+    bool to_fp64 = false;
+    if (a.fp32_stall) {
+      const bool flat = res_prev > 0.0 && fabs(res - res_prev) <= kStallChange * res_prev &&
+                        res <= kStallScale * kU32 * W.tnorm;
+      W.stall = flat ? W.stall + 1 : 0;
+      to_fp64 = W.stall >= kStallCycles;
+    }
     W.restarts += 1;
     W.cycle_done = 0;
     W.need2 = 0;
     const double *be = a.beta + (int64_t)s * a.ps;
     const int kc = W.k;
-    if (a.keep > 0 && kc == a.m && W.nnext >= 1 && be[kc] > 0.0) {
+    if (a.keep > 0 && kc == a.m && W.nnext >= 1 && be[kc] > 0.0 && !to_fp64) {
       // thick restart: the kept Ritz pairs head the next basis and the last
       // residual direction w / beta continues it (step nk + 1)
       const int nk = W.nnext;
@@ -828,6 +860,12 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
       W.j0 = 1;
       W.k = 0;
       W.tnorm = 0.0;
+    }
+    if (to_fp64) {
+      W.refine = 1;
+      W.active = 0;
+      atomicAdd(&a.flags[3], 1);
+      return;
     }
     atomicAdd(&a.flags[0], 1);
     return;
@@ -1301,12 +1339,16 @@ __global__ __launch_bounds__(kBlock) void k_lz_output(LzArgs<T> a, double *__res
 
 // Second Ritz vector of the last thick-restart cycle (kept basis slot 2,
 // FP64) on the rows of the component being cut; zero elsewhere and where the
-// cycle formed a single Ritz vector.
+// cycle formed a single Ritz vector.  refined = 0: segments whose last cycle
+// ran with these arguments' directions (not continued in FP64); 1: only the
+// segments continued with FP64 directions.
 template <typename T, int RPT>
-__global__ __launch_bounds__(kBlock) void k_lz_output2(LzArgs<T> a, double *__restrict__ y2) {
+__global__ __launch_bounds__(kBlock) void k_lz_output2(LzArgs<T> a, double *__restrict__ y2,
+                                                       int refined) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
+  if ((S.refine == 2) != (refined != 0)) return;
   const bool have = S.solve && S.nnext >= 2 && a.keep >= 2;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
@@ -1315,6 +1357,15 @@ __global__ __launch_bounds__(kBlock) void k_lz_output2(LzArgs<T> a, double *__re
     const int64_t row = b.row0 + lr;
     y2[row] = (have && a.U0[row] != 0.0) ? a.K[row] : 0.0;
   }
+}
+
+// Mixed precision: the segments parked at the switch point take part again
+// (the FP64 cycles start with an explicit restart from their Ritz vector).
+__global__ void k_lz_refine_on(SegState *st, int nseg) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg || st[s].refine != 1) return;
+  st[s].refine = 2;
+  st[s].active = 1;
 }
 
 __global__ void k_flags_reset(int32_t *flags) {
@@ -1391,8 +1442,8 @@ struct LzLaunch {
   static void output(const LzArgs<T> &a, int nblk, double *y64, hipStream_t s) {
     k_lz_output<T, RPT><<<nblk, kBlock, 0, s>>>(a, y64);
   }
-  static void output2(const LzArgs<T> &a, int nblk, double *y2, hipStream_t s) {
-    k_lz_output2<T, RPT><<<nblk, kBlock, 0, s>>>(a, y2);
+  static void output2(const LzArgs<T> &a, int nblk, double *y2, hipStream_t s, int refined) {
+    k_lz_output2<T, RPT><<<nblk, kBlock, 0, s>>>(a, y2, refined);
   }
 };
 
@@ -1441,11 +1492,124 @@ size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32, int keep) {
   return (size_t)rows * (5 * 8 + (size_t)(m + 3) * t + kept);
 }
 
+namespace {
+
+// Per-cycle loop of a level (graph per cycle unless profiled); returns the
+// level steps run.  Lz is the launcher of the argument type.
+template <typename Lz, typename T>
+int64_t run_cycles(const LzArgs<T> &a, const LevelView &L, const LanczosParams &p,
+                   KernelProfile *profp, Ctx &ctx) {
+  const int nblk = L.nblk, nseg = L.nseg, ngrp = L.ngrp;
+  int64_t level_steps = 0;
+  struct Res {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<hipEvent_t> ev;
+    ~Res() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      for (auto e : ev) (void)hipEventDestroy(e);
+    }
+  } res;
+  const bool prof = profp != nullptr;
+  if (prof) {
+    res.ev.resize(2 * (a.m + 1));
+    for (auto &e : res.ev) RSB_HIP(hipEventCreate(&e));
+  }
+  if (p.use_graph && !prof) {
+    // (HIP events recorded by graph nodes cannot be timed: profiled cycles
+    // are launched directly)
+    RSB_HIP(hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal));
+    Lz::cycle(a, nblk, ngrp, nseg, ctx.stream);
+    hipError_t e = hipStreamEndCapture(ctx.stream, &res.graph);
+    if (e != hipSuccess) fail(RSB_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+    RSB_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
+  }
+  // profiled byte count: per segment active in the cycle, its rows for
+  // every step it ran (its nonzeros taken in proportion to its rows)
+  std::vector<SegState> hst;
+  std::vector<SegDev> hseg;
+  std::vector<char> was_active;
+  std::vector<int64_t> steps0;
+  std::vector<int32_t> j00;
+  auto read_state = [&]() {
+    hst.resize(nseg);
+    RSB_HIP(hipMemcpyAsync(hst.data(), a.st, nseg * sizeof(SegState), hipMemcpyDeviceToHost,
+                           ctx.stream));
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+  };
+  if (prof) {
+    hseg.resize(nseg);
+    RSB_HIP(hipMemcpyAsync(hseg.data(), a.seg, nseg * sizeof(SegDev), hipMemcpyDeviceToHost,
+                           ctx.stream));
+    was_active.resize(nseg);
+    steps0.resize(nseg);
+    j00.resize(nseg);
+  }
+  int32_t flags[3] = {0, 0, 0};
+  for (int cyc = 0; cyc <= p.max_restarts; ++cyc) {
+    if (prof) {
+      read_state();
+      for (int i = 0; i < nseg; ++i) {
+        was_active[i] = hst[i].active != 0;
+        steps0[i] = hst[i].steps;
+        j00[i] = hst[i].j0;
+      }
+    }
+    if (res.exec) {
+      RSB_HIP(hipGraphLaunch(res.exec, ctx.stream));
+    } else {
+      Lz::cycle(a, nblk, ngrp, nseg, ctx.stream, prof ? res.ev.data() : nullptr);
+      RSB_LAUNCHED();
+    }
+    RSB_HIP(hipMemcpyAsync(flags, a.flags, sizeof(flags), hipMemcpyDeviceToHost, ctx.stream));
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    level_steps += flags[2];
+    if (ctx.verbose >= 3) {
+      std::vector<SegState> hv(nseg);
+      RSB_HIP(hipMemcpy(hv.data(), a.st, nseg * sizeof(SegState), hipMemcpyDeviceToHost));
+      for (int i = 0; i < std::min(nseg, 4); ++i)
+        fprintf(stderr, "[rsb]     cycle %d seg %d (%s): k %d res/rho %.3e rho %.12g theta %.12g\n",
+                cyc, i, sizeof(T) == 4 ? "fp32" : "fp64", hv[i].k,
+                hv[i].res / std::max(hv[i].rho, 1e-300), hv[i].rho, hv[i].theta);
+    }
+    if (prof) {
+      // launches of steps 3..flags[1] were timed; segment i took part in
+      // those of steps j0_i..k_i (k_i - j0_i + 1: the steps it added in
+      // this cycle); launches that no segment took part in count 0 bytes.
+      // A thick-restart cycle starts at j0 = nk + 1 with the kept Ritz
+      // vectors in basis slots 2..nk, stored in FP64 whatever T is.
+      read_state();
+      const double st = (double)sizeof(T);
+      const double nnz_per_row = (double)p.nnz / (double)std::max<int64_t>(L.nrows, 1);
+      // operator bytes per row: sliced ELL words, or the gather-scatter
+      // slot words, degree and group sums (each group read once)
+      const double op_row = L.gs.nv ? 4.0 * L.gs.nv + 4.0 +
+                                          8.0 * (double)L.gs.ngroups / (double)std::max<int64_t>(L.nrows, 1)
+                                    : 4.0 * nnz_per_row;
+      for (int j = 3; j <= flags[1]; ++j) {
+        float ms = 0.f;
+        RSB_HIP(hipEventElapsedTime(&ms, res.ev[2 * j], res.ev[2 * j + 1]));
+        double rows = 0.0, kept_rows = 0.0;
+        for (int i = 0; i < nseg; ++i)
+          if (was_active[i] && j >= j00[i] && hst[i].steps - steps0[i] + j00[i] - 1 >= j) {
+            rows += (double)hseg[i].npad;
+            kept_rows += (double)hseg[i].npad * std::max(0, j00[i] - 2);
+          }
+        profp->ms += ms;
+        profp->launches += 1;
+        profp->bytes += (L.gs.nv ? 0.0 : 4.0 * (rows + 1)) + op_row * rows +
+                        rows * (st + st + st + 16.0 + (j - 2) * st) + kept_rows * (8.0 - st);
+      }
+    }
+    if (flags[0] == 0) break;
+  }
+  return level_steps;
+}
+
 template <typename T>
-int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p,
-                      void *work, double *y64_out, Ctx &ctx) {
-  if (L.nseg == 0) return 0;
-  if (p.m < 1 || p.m > kMaxM) fail(RSB_EINVAL, "lanczos_m must be in [1, 250]");
+LzArgs<T> level_args(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p,
+                     void *work) {
   LzArgs<T> a{};
   a.blk = L.blk;
   a.grp = L.grp;
@@ -1487,134 +1651,89 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
   a.K = sizeof(T) == 8 ? (double *)(a.V + 2 * L.nrows) : (double *)(a.Wt1 + L.nrows);
   a.m = p.m;
   a.tol = p.tol;
+  a.fp32_stall = 0;
   a.max_restarts = p.max_restarts;
   a.brk = sizeof(T) == 4 ? 1e-5 : 1e-12;
   a.keep = p.keep;
-  if (p.keep < 0 || p.keep > kMaxKeep || (p.keep > 0 && p.keep >= p.m))
-    fail(RSB_EINVAL, "lanczos_keep must be 0 or in [1, min(16, lanczos_m - 1)]");
-
-  if (S.nkcap < std::max(1, p.keep)) fail(RSB_EINTERNAL, "Ritz buffers smaller than lanczos_keep");
   a.flags = S.n_active.get();
   a.ctr = (unsigned long long *)S.counters.get();
   a.seed = p.seed;
-  const int nblk = L.nblk, nseg = L.nseg, ngrp = L.ngrp;
+  return a;
+}
+
+}  // namespace
+
+template <typename T>
+int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p,
+                      void *work, double *y64_out, Ctx &ctx) {
+  if (L.nseg == 0) return 0;
+  if (p.m < 1 || p.m > kMaxM) fail(RSB_EINVAL, "lanczos_m must be in [1, 250]");
+  if (p.keep < 0 || p.keep > kMaxKeep || (p.keep > 0 && p.keep >= p.m))
+    fail(RSB_EINVAL, "lanczos_keep must be 0 or in [1, min(16, lanczos_m - 1)]");
+  if (S.nkcap < std::max(1, p.keep)) fail(RSB_EINTERNAL, "Ritz buffers smaller than lanczos_keep");
+  LzArgs<T> a = level_args<T>(L, C, S, p, work);
+  // FP32 directions with thick restart: a segment whose residual stalls
+  // short of the tolerance continues with FP64 directions until the FP64
+  // residual meets it.  Explicit restart needs no switch: its every restart
+  // starts from the FP64 Ritz vector and gains the FP32 factor.
+  const bool refine = sizeof(T) == 4 && p.keep > 0;
+  a.fp32_stall = refine ? 1 : 0;
+  const int nblk = L.nblk, ngrp = L.ngrp;
   int64_t level_steps = 0;
+  int32_t nref = 0;
   dispatch_rpt<T>(L.rpt, [&](auto launcher) {
     using Lz = decltype(launcher);
     Lz::begin(a, nblk, ngrp, ctx.stream);
     RSB_LAUNCHED();
-    struct Res {
-      hipGraphExec_t exec = nullptr;
-      hipGraph_t graph = nullptr;
-      std::vector<hipEvent_t> ev;
-      ~Res() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        for (auto e : ev) (void)hipEventDestroy(e);
-      }
-    } res;
-    const bool prof = p.prof != nullptr;
-    if (prof) {
-      res.ev.resize(2 * (a.m + 1));
-      for (auto &e : res.ev) RSB_HIP(hipEventCreate(&e));
-    }
-    if (p.use_graph && !prof) {
-      // (HIP events recorded by graph nodes cannot be timed: profiled cycles
-      // are launched directly)
-      RSB_HIP(hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal));
-      Lz::cycle(a, nblk, ngrp, nseg, ctx.stream);
-      hipError_t e = hipStreamEndCapture(ctx.stream, &res.graph);
-      if (e != hipSuccess) fail(RSB_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
-      RSB_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
-    }
-    // profiled byte count: per segment active in the cycle, its rows for
-    // every step it ran (its nonzeros taken in proportion to its rows)
-    std::vector<SegState> hst;
-    std::vector<SegDev> hseg;
-    std::vector<char> was_active;
-    std::vector<int64_t> steps0;
-    std::vector<int32_t> j00;
-    auto read_state = [&]() {
-      hst.resize(nseg);
-      RSB_HIP(hipMemcpyAsync(hst.data(), a.st, nseg * sizeof(SegState), hipMemcpyDeviceToHost,
-                             ctx.stream));
+    if (refine) RSB_HIP(hipMemsetAsync(a.flags + 3, 0, sizeof(int32_t), ctx.stream));
+    level_steps += run_cycles<Lz>(a, L, p, p.prof, ctx);
+    if (refine) {
+      RSB_HIP(hipMemcpyAsync(&nref, a.flags + 3, sizeof(nref), hipMemcpyDeviceToHost, ctx.stream));
       RSB_HIP(hipStreamSynchronize(ctx.stream));
-    };
-    if (prof) {
-      hseg.resize(nseg);
-      RSB_HIP(hipMemcpyAsync(hseg.data(), a.seg, nseg * sizeof(SegDev), hipMemcpyDeviceToHost,
-                             ctx.stream));
-      was_active.resize(nseg);
-      steps0.resize(nseg);
-      j00.resize(nseg);
-    }
-    int32_t flags[3] = {0, 0, 0};
-    for (int cyc = 0; cyc <= p.max_restarts; ++cyc) {
-      if (prof) {
-        read_state();
-        for (int i = 0; i < nseg; ++i) {
-          was_active[i] = hst[i].active != 0;
-          steps0[i] = hst[i].steps;
-          j00[i] = hst[i].j0;
-        }
-      }
-      if (res.exec) {
-        RSB_HIP(hipGraphLaunch(res.exec, ctx.stream));
-      } else {
-        Lz::cycle(a, nblk, ngrp, nseg, ctx.stream, prof ? res.ev.data() : nullptr);
-        RSB_LAUNCHED();
-      }
-      RSB_HIP(hipMemcpyAsync(flags, a.flags, sizeof(flags), hipMemcpyDeviceToHost, ctx.stream));
-      RSB_HIP(hipStreamSynchronize(ctx.stream));
-      level_steps += flags[2];
-      if (ctx.verbose >= 3) {
-        std::vector<SegState> hv(nseg);
-        RSB_HIP(hipMemcpy(hv.data(), a.st, nseg * sizeof(SegState), hipMemcpyDeviceToHost));
-        for (int i = 0; i < std::min(nseg, 4); ++i)
-          fprintf(stderr, "[rsb]     cycle %d seg %d: k %d res/rho %.3e rho %.12g theta %.12g\n",
-                  cyc, i, hv[i].k, hv[i].res / std::max(hv[i].rho, 1e-300), hv[i].rho,
-                  hv[i].theta);
-      }
-      if (prof) {
-        // launches of steps 3..flags[1] were timed; segment i took part in
-        // those of steps j0_i..k_i (k_i - j0_i + 1: the steps it added in
-        // this cycle); launches that no segment took part in count 0 bytes.
-        // A thick-restart cycle starts at j0 = nk + 1 with the kept Ritz
-        // vectors in basis slots 2..nk, stored in FP64 whatever T is.
-        read_state();
-        const double st = (double)sizeof(T);
-        const double nnz_per_row = (double)p.nnz / (double)std::max<int64_t>(L.nrows, 1);
-        // operator bytes per row: sliced ELL words, or the gather-scatter
-        // slot words, degree and group sums (each group read once)
-        const double op_row = L.gs.nv ? 4.0 * L.gs.nv + 4.0 +
-                                            8.0 * (double)L.gs.ngroups / (double)std::max<int64_t>(L.nrows, 1)
-                                      : 4.0 * nnz_per_row;
-        for (int j = 3; j <= flags[1]; ++j) {
-          float ms = 0.f;
-          RSB_HIP(hipEventElapsedTime(&ms, res.ev[2 * j], res.ev[2 * j + 1]));
-          double rows = 0.0, kept_rows = 0.0;
-          for (int i = 0; i < nseg; ++i)
-            if (was_active[i] && j >= j00[i] && hst[i].steps - steps0[i] + j00[i] - 1 >= j) {
-              rows += (double)hseg[i].npad;
-              kept_rows += (double)hseg[i].npad * std::max(0, j00[i] - 2);
-            }
-          p.prof->ms += ms;
-          p.prof->launches += 1;
-          p.prof->bytes += (L.gs.nv ? 0.0 : 4.0 * (rows + 1)) + op_row * rows +
-                           rows * (st + st + st + 16.0 + (j - 2) * st) + kept_rows * (8.0 - st);
-        }
-      }
-      if (flags[0] == 0) break;
-    }
-    if (y64_out) {
-      Lz::output(a, nblk, y64_out, ctx.stream);
-      RSB_LAUNCHED();
     }
     if (p.y2_out) {
-      Lz::output2(a, nblk, p.y2_out, ctx.stream);
+      Lz::output2(a, nblk, p.y2_out, ctx.stream, 0);
       RSB_LAUNCHED();
     }
   });
+  if (nref > 0) {
+    if constexpr (sizeof(T) == 4) {
+      // FP64 directions for the parked segments: u0, q_1, the Ritz vector
+      // and the step-1 work vector stay where they are; the basis, the kept
+      // Ritz vectors and the work vectors get an FP64 layout of their own
+      DevBuf<double> ws2(ctx, (size_t)(p.m + 3) * (size_t)L.nrows);
+      LzArgs<double> d = level_args<double>(L, C, S, p, work);
+      d.U0 = a.U0;
+      d.Q1 = a.Q1;
+      d.Y = a.Y;
+      d.Wd = a.Wd;
+      d.V = ws2.get();
+      d.Wt0 = d.V + (int64_t)(p.m + 1) * L.nrows;
+      d.Wt1 = d.Wt0 + L.nrows;
+      d.K = d.V + 2 * L.nrows;
+      dispatch_rpt<double>(L.rpt, [&](auto launcher) {
+        using Lz = decltype(launcher);
+        k_lz_refine_on<<<(L.nseg + kBlock - 1) / kBlock, kBlock, 0, ctx.stream>>>(d.st, L.nseg);
+        RSB_LAUNCHED();
+        // (the FP64 cycles are not part of the profiled FP32 kernel's count)
+        const int64_t s64 = run_cycles<Lz>(d, L, p, nullptr, ctx);
+        level_steps += s64;
+        ctx.fp64_level_steps += s64;
+        if (p.y2_out) {
+          Lz::output2(d, nblk, p.y2_out, ctx.stream, 1);
+          RSB_LAUNCHED();
+        }
+      });
+      RSB_HIP(hipStreamSynchronize(ctx.stream));  // ws2 is freed on this stream
+    }
+  }
+  if (y64_out) {
+    dispatch_rpt<T>(L.rpt, [&](auto launcher) {
+      using Lz = decltype(launcher);
+      Lz::output(a, nblk, y64_out, ctx.stream);
+      RSB_LAUNCHED();
+    });
+  }
   return level_steps;
 }
 

@@ -9,6 +9,7 @@ import pytest
 
 import meshgen as mg
 import paper_2606_14659_amd as rsb
+from spectral_util import assert_fiedler_close, lambda23
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +36,8 @@ def test_auto_fiedler_falls_back(orc):
     assert st == sti == ost
     assert lam == lami and np.array_equal(y, yi)
     assert abs(lam - olam) <= 1e-8 * olam
-    assert abs(abs(float(y @ oy)) - 1) < 1e-6
+    l2, l3 = lambda23(orc, HOLES.ids)
+    assert_fiedler_close(y, oy, stats["residual"], oinfo["residual"], l3 - l2)
 
 
 @pytest.mark.parametrize("batched", [1, 0])

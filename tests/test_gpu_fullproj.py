@@ -10,6 +10,7 @@ import pytest
 
 import meshgen as mg
 import paper_2606_14659_amd as rsb
+from spectral_util import assert_fiedler_close, lambda23
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +35,8 @@ def test_fiedler_full_projection(orc, name, k, precond):
           f"oracle cg {oinfo['cg_iters']}", flush=True)
     assert st == ost == 0
     assert abs(lam - olam) <= 1e-8 * olam
-    assert abs(abs(float(y @ oy)) - 1) < 1e-6
+    l2, l3 = lambda23(orc, ids)
+    assert_fiedler_close(y, oy, stats["residual"], oinfo["residual"], l3 - l2)
     assert abs(stats["segment_steps"] - oinfo["cg_iters"]) <= max(3, 0.05 * oinfo["cg_iters"])
 
 

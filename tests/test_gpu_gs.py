@@ -13,6 +13,7 @@ import pytest
 
 import meshgen as mg
 import paper_2606_14659_amd as rsb
+from spectral_util import assert_fiedler_close, lambda23
 
 pytestmark = pytest.mark.gpu
 
@@ -78,21 +79,26 @@ def test_fiedler_fp64(orc, name, keep):
     ids = MESHES[name]
     kw = dict(tol=1e-9, lanczos_keep=keep, lanczos_m=30 if keep else 100)
     st, lam, y, stats = rsb.fiedler(ids, gather_scatter=1, **kw)
-    ost, olam, oy, _ = orc.fiedler(ids, **kw)
+    ost, olam, oy, oinfo = orc.fiedler(ids, **kw)
     assert st == ost
     assert abs(lam - olam) <= 1e-8 * olam
-    assert abs(abs(float(y @ oy)) - 1) < 1e-6
+    l2, l3 = lambda23(orc, ids)
+    assert_fiedler_close(y, oy, stats["residual"], oinfo["residual"], l3 - l2)
 
 
 @pytest.mark.parametrize("name", ["box5x4x3", "holes", "clustered"])
 def test_fiedler_mixed_thick(orc, name):
     ids = MESHES[name]
-    st, lam, y, stats = rsb.fiedler(ids, gather_scatter=1, precision="mixed", tol=1e-4,
-                                    lanczos_keep=8, lanczos_m=30)
-    ost, olam, oy, _ = orc.fiedler(ids, tol=1e-9, lanczos_keep=8, lanczos_m=30)
+    # FP32 directions to the switch point, then FP64 directions to 1e-8
+    st, lam, y, stats = rsb.fiedler(ids, gather_scatter=1, precision="mixed", tol=1e-8,
+                                    lanczos_keep=8, lanczos_m=30, max_restarts=400)
+    ost, olam, oy, oinfo = orc.fiedler(ids, tol=1e-9, lanczos_keep=8, lanczos_m=30,
+                                       max_restarts=400)
     assert st == ost == 0
     assert abs(lam - olam) <= 1e-8 * olam
-    assert stats["residual"] <= 1e-4 * lam
+    assert stats["residual"] <= 1.01e-8 * lam
+    l2, l3 = lambda23(orc, ids)
+    assert_fiedler_close(y, oy, stats["residual"], oinfo["residual"], l3 - l2)
 
 
 @pytest.mark.parametrize("dims,nparts", [((48, 40, 36), 8), ((24, 20, 18), 4)])
@@ -101,7 +107,7 @@ def test_fiedler_mixed_thick(orc, name):
 def test_partition_identical_on_boxes(orc, dims, nparts, precision, keep):
     mesh = mg.box_hex(*dims)
     print(f"[gs] partition {dims} {nparts} {precision} keep={keep}", flush=True)
-    tol = 1e-4 if (precision == "mixed" and keep) else 1e-8
+    tol = 1e-8
     st, part, stats = rsb.partition(mesh.ids, nparts, precision=precision, tol=tol,
                                     lanczos_keep=keep, gather_scatter=1)
     ost, opart, _ = orc.partition(mesh.ids, nparts, tol=1e-8, lanczos_keep=keep)
