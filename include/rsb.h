@@ -350,6 +350,30 @@ int rsb_partition_batch(int32_t nmesh, const int64_t *nelem, int32_t nv_per_elem
                         const int64_t *const *elem_vertex_ids, const int32_t *nparts,
                         const rsb_opts *opts, int32_t *const *part_out, rsb_stats *stats_out);
 
+/* For callers that cannot allocate device memory: code that must not call
+ * hipMalloc (tight serving loops, harnesses that forbid allocation).
+ * rsb_partition with every device buffer of the call carved from one fixed
+ * region of RSB_NOALLOC_SCRATCH_BYTES per GPU, a device array the library
+ * holds from load until the process ends; the call makes no hipMalloc,
+ * hipFree or other allocating call.  Arguments, outputs and return codes as
+ * rsb_partition, with these differences: at most RSB_NOALLOC_MAX_ELEMS
+ * elements and RSB_NOALLOC_MAX_PARTS parts (RSB_EINVAL beyond); RSB_ENOMEM,
+ * with the sizes in rsb_last_error, when options need more than the region
+ * (the defaults, and the benchmark's mixed-precision thick restart, fit at
+ * the maximum sizes; lanczos_m near 250 or an AMG hierarchy may not); graph
+ * replay, profiling and tile timing are off whatever opts says; a NULL
+ * opts->stream means the null stream.  The region keeps the last call's
+ * contents; the library clears what it needs itself.  Calls from threads of
+ * one process on one GPU take turns on a lock, and each call drains its
+ * stream before it returns, so no two of them overlap; a call must not be
+ * captured into a graph (it synchronises its stream). */
+#define RSB_NOALLOC_SCRATCH_BYTES (256ll << 20)
+#define RSB_NOALLOC_MAX_ELEMS 65536
+#define RSB_NOALLOC_MAX_PARTS 1024
+int rsb_partition_noalloc(int64_t nelem, int32_t nv_per_elem, const int64_t *elem_vertex_ids,
+                          int32_t nparts, const rsb_opts *opts, int32_t *part_out,
+                          rsb_stats *stats_out);
+
 /* Message for a return code (static string). */
 const char *rsb_strerror(int code);
 /* Message of the last failing call on this thread ("" if none). */

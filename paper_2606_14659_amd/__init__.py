@@ -24,6 +24,8 @@ PRECOND = {"none": 0, "amg": 1}
 
 OK, WARN_NOT_CONVERGED, WARN_DISCONNECTED = 0, 1, 2
 EINVAL, ENOMEM, EDEVICE, EBUFFER, EINTERNAL = -1, -2, -3, -4, -5
+# rsb_partition_noalloc limits (RSB_NOALLOC_* in rsb.h)
+NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_ELEMS, NOALLOC_MAX_PARTS = 256 << 20, 65536, 1024
 
 
 class Opts(C.Structure):
@@ -84,6 +86,8 @@ _SIGNATURES = {
     "rsb_split": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "rsb_partition": ([C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                        C.c_void_p], C.c_int),
+    "rsb_partition_noalloc": ([C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                               C.c_void_p, C.c_void_p], C.c_int),
     "rsb_partition_batch": ([C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "rsb_amg_level": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
@@ -330,6 +334,20 @@ def partition(ids, nparts: int, device: bool = False, **kw):
     st.struct_size = C.sizeof(Stats)
     code = _check(lib().rsb_partition(n, nv, a.ptr, int(nparts), C.byref(o), pp, C.byref(st)),
                   "rsb_partition")
+    return code, part, st.as_dict()
+
+
+def partition_noalloc(ids, nparts: int, device: bool = False, **kw):
+    """(status, part, stats): rsb_partition with its device scratch in the
+    library's fixed region (no device allocation by the library)."""
+    n, nv = _ids_shape(ids)
+    o = make_opts(device, **kw)
+    a = _Arr(ids, np.int64, device)
+    part, pp = _out(n, np.int32, device)
+    st = Stats()
+    st.struct_size = C.sizeof(Stats)
+    code = _check(lib().rsb_partition_noalloc(n, nv, a.ptr, int(nparts), C.byref(o), pp,
+                                              C.byref(st)), "rsb_partition_noalloc")
     return code, part, st.as_dict()
 
 

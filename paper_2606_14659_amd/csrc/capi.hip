@@ -113,14 +113,14 @@ void check_opts(const rsb_opts *o) {
     fail(RSB_EINVAL, "warm_start needs Lanczos (RSB_LANCZOS or RSB_AUTO) with lanczos_keep >= 2");
 }
 
-void setup_ctx(Ctx &ctx, const rsb_opts &o) {
+void setup_ctx(Ctx &ctx, const rsb_opts &o, bool private_stream = true) {
   int ndev = 0;
   RSB_HIP(hipGetDeviceCount(&ndev));
   if (o.device < 0 || o.device >= ndev) fail(RSB_EINVAL, "device ordinal out of range");
   RSB_HIP(hipSetDevice(o.device));
   ctx.device = o.device;
   ctx.stream = (hipStream_t)o.stream;
-  if (!ctx.stream) {
+  if (!ctx.stream && private_stream) {
     // graph capture needs a real stream: use a private one for this call
     RSB_HIP(hipStreamCreateWithFlags(&ctx.stream, hipStreamNonBlocking));
     ctx.own_stream = true;
@@ -1040,6 +1040,55 @@ int rsb_partition(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts,
     }
     std::vector<MeshIn> meshes{{nelem, in.p, nparts}};
     RunOut r = run_rsb(meshes, nv, *opts, ctx, dpart, stats_out, nullptr);
+    if (!dev) copy_out(ctx, part_out, (const int32_t *)dpart, nelem, false);
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    return r.status;
+  });
+}
+
+int rsb_partition_noalloc(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts,
+                          const rsb_opts *opts, int32_t *part_out, rsb_stats *stats_out) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    check_mesh(nelem, nv, ids);
+    check_stats(stats_out);
+    if (nparts < 1 || nparts > nelem) fail(RSB_EINVAL, "nparts must be in [1, nelem]");
+    if (!part_out) fail(RSB_EINVAL, "part_out is NULL");
+    if (nelem > RSB_NOALLOC_MAX_ELEMS || nparts > RSB_NOALLOC_MAX_PARTS)
+      fail(RSB_EINVAL, "rsb_partition_noalloc takes at most " +
+                           std::to_string(RSB_NOALLOC_MAX_ELEMS) + " elements and " +
+                           std::to_string(RSB_NOALLOC_MAX_PARTS) + " parts (got " +
+                           std::to_string(nelem) + " and " + std::to_string(nparts) + ")");
+    // graph replay, profiling events and tile trials allocate: all off
+    rsb_opts o = *opts;
+    o.use_hipgraph = 0;
+    o.profile = 0;
+    o.autotune = 0;
+    NoallocRegion &reg = noalloc_region(o.device);
+    std::lock_guard<std::mutex> lock(reg.mu);
+    Ctx ctx;
+    setup_ctx(ctx, o, false);
+    // (the last MiB is never handed out: a streaming kernel's unconditional
+    // reads just past its buffer stay inside the array)
+    reg.arena.reset(reg.ptr, reg.bytes - ((size_t)1 << 20));
+    ctx.arena = &reg.arena;
+    // whatever happens, the call's work on the region ends before the next
+    // call may use it
+    struct Drain {
+      hipStream_t s;
+      ~Drain() { (void)hipStreamSynchronize(s); }
+    } drain{ctx.stream};
+    const bool dev = o.device_pointers != 0;
+    InArr<int64_t> in;
+    in.init(ctx, ids, nelem * nv, dev);
+    DevBuf<int32_t> own;
+    int32_t *dpart = part_out;
+    if (!dev) {
+      own.alloc(ctx, nelem);
+      dpart = own.get();
+    }
+    std::vector<MeshIn> meshes{{nelem, in.p, nparts}};
+    RunOut r = run_rsb(meshes, nv, o, ctx, dpart, stats_out, nullptr);
     if (!dev) copy_out(ctx, part_out, (const int32_t *)dpart, nelem, false);
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     return r.status;

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -78,6 +79,58 @@ inline void fault_point(bool alloc) {
     fail(RSB_EDEVICE, "injected launch failure (RSB_FAULT_INJECT)");
 }
 
+// Device scratch carved from one fixed region instead of the allocator (the
+// entry point for callers that cannot allocate).  First fit over a free list
+// with coalescing; offsets are aligned to 256 bytes.  Every buffer of a call
+// lives on the call's one stream, so a region freed by the host may be handed
+// out again at once: later work on the stream runs after the earlier work.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0;
+  size_t in_use = 0, peak = 0;
+  std::map<size_t, size_t> free_list;  // offset -> bytes
+  void reset(void *b, size_t bytes) {
+    base = (char *)b;
+    cap = bytes;
+    in_use = peak = 0;
+    free_list.clear();
+    free_list[0] = bytes;
+  }
+  static size_t rounded(size_t bytes) { return (std::max<size_t>(bytes, 1) + 255) & ~size_t(255); }
+  void *take(size_t bytes) {
+    const size_t need = rounded(bytes);
+    for (auto it = free_list.begin(); it != free_list.end(); ++it) {
+      if (it->second < need) continue;
+      const size_t off = it->first, len = it->second;
+      free_list.erase(it);
+      if (len > need) free_list[off + need] = len - need;
+      in_use += need;
+      peak = std::max(peak, in_use);
+      return base + off;
+    }
+    return nullptr;
+  }
+  void give(void *p, size_t bytes) {
+    const size_t len = rounded(bytes);
+    size_t off = (size_t)((char *)p - base);
+    size_t end = off + len;
+    in_use -= len;
+    auto next = free_list.lower_bound(off);
+    if (next != free_list.end() && next->first == end) {
+      end += next->second;
+      next = free_list.erase(next);
+    }
+    if (next != free_list.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        off = prev->first;
+        free_list.erase(prev);
+      }
+    }
+    free_list[off] = end - off;
+  }
+};
+
 struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;  // created for a call that passed the null stream
@@ -88,6 +141,7 @@ struct Ctx {
   int verbose = 0;
   std::vector<std::string> tuned;  // tile classes timed during this call
   int64_t fp64_level_steps = 0;    // mixed precision: level steps continued with FP64 directions
+  Arena *arena = nullptr;          // non-null: device scratch comes from this region only
   FaultPlan fault;
   Ctx() = default;
   Ctx(const Ctx &) = delete;
@@ -128,6 +182,17 @@ struct DevBuf {
     if (c.limit > 0 && c.in_use + (int64_t)bytes > c.limit)
       fail(RSB_ENOMEM, "device_mem_limit exceeded: need " + std::to_string(c.in_use + bytes) +
                            " bytes, limit " + std::to_string(c.limit));
+    if (c.arena) {
+      p = (T *)c.arena->take(bytes);
+      if (!p)
+        fail(RSB_ENOMEM, "the problem needs more device scratch than the fixed region of " +
+                             std::to_string(c.arena->cap) + " bytes (" +
+                             std::to_string(c.arena->in_use) + " in use, " +
+                             std::to_string(bytes) + " more asked for)");
+      c.in_use += bytes;
+      c.peak = std::max(c.peak, c.in_use);
+      return;
+    }
     hipError_t e = hipMallocAsync((void **)&p, bytes, c.stream);
     if (e != hipSuccess) {
       p = nullptr;
@@ -139,7 +204,8 @@ struct DevBuf {
   }
   void release() {
     if (p) {
-      (void)hipFreeAsync(p, ctx->stream);
+      if (ctx->arena) ctx->arena->give(p, std::max<size_t>(n, 1) * sizeof(T));
+      else (void)hipFreeAsync(p, ctx->stream);
       ctx->in_use -= std::max<size_t>(n, 1) * sizeof(T);
       p = nullptr;
     }

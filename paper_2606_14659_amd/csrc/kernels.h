@@ -1,8 +1,23 @@
 // kernels.h -- internal interfaces between the library's translation units.
 #pragma once
+#include <mutex>
+
 #include "common.h"
 
 namespace rsb {
+
+// The fixed device region of rsb_partition_noalloc on one GPU: its device
+// address (looked up once per device), size, and the lock and free list of
+// the calls that use it.
+struct NoallocRegion {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  hipError_t err = hipSuccess;
+  std::mutex mu;
+  Arena arena;
+};
+// Makes `device` current and returns its region (RSB_EDEVICE if the lookup fails).
+NoallocRegion &noalloc_region(int device);
 
 // ---------------------------------------------------------------------------
 // Plain CSR on the device (output of the dual-graph builder).

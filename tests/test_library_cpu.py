@@ -153,3 +153,23 @@ def test_batch_bad_arguments_rejected_before_any_device_call():
         assert code == rsb.EINVAL and why in L.rsb_last_error()
     assert L.rsb_partition_batch(2, nelem, 4, idp, parts_ok, C.byref(o), None, None) == rsb.EINVAL
     assert L.rsb_partition_batch(2, None, 4, idp, parts_ok, C.byref(o), out_ok, None) == rsb.EINVAL
+
+
+def test_noalloc_limits_rejected_before_any_device_call():
+    # the entry point for callers that cannot allocate: sizes beyond its
+    # documented maximum are refused on the host, with the limits named
+    hdr = open(os.path.join(ROOT, "include", "rsb.h")).read()
+    assert f"#define RSB_NOALLOC_MAX_ELEMS {rsb.NOALLOC_MAX_ELEMS}" in hdr
+    assert f"#define RSB_NOALLOC_MAX_PARTS {rsb.NOALLOC_MAX_PARTS}" in hdr
+    assert "#define RSB_NOALLOC_SCRATCH_BYTES (256ll << 20)" in hdr
+    assert rsb.NOALLOC_SCRATCH_BYTES == 256 << 20
+    L = rsb.lib()
+    o = rsb.make_opts()
+    n = rsb.NOALLOC_MAX_ELEMS + 1
+    ids = np.arange(4 * n, dtype=np.int64).reshape(n, 4)
+    part = np.zeros(n, dtype=np.int32)
+    P = lambda a: a.ctypes.data_as(C.c_void_p)
+    assert L.rsb_partition_noalloc(n, 4, P(ids), 2, C.byref(o), P(part), None) == rsb.EINVAL
+    assert b"at most 65536 elements and 1024 parts" in L.rsb_last_error()
+    assert L.rsb_partition_noalloc(2000, 4, P(ids), 1025, C.byref(o), P(part), None) == rsb.EINVAL
+    assert L.rsb_partition_noalloc(2, 4, None, 2, C.byref(o), P(part), None) == rsb.EINVAL
