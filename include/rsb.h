@@ -226,6 +226,10 @@ typedef struct rsb_stats {
   int32_t reserved;
   double ms_reorder;         /* opts->reorder = 1: locality order of the rows (host wall
                                 clock, included in ms_total) */
+  /* opts->profile = 1 (Lanczos, sliced ELL): y = L x alone on the level-0
+   * matrix in the directions' precision, 20 launches timed with HIP events */
+  double spmv_alone_us;      /* average launch time */
+  double spmv_alone_bytes;   /* algorithmic bytes per launch: 4 (n + 1) + 4 nnz + 2 s n */
 } rsb_stats;
 
 /* Fills *o with the defaults listed above.  Returns RSB_OK or RSB_EINVAL (o NULL). */
@@ -373,6 +377,16 @@ int rsb_partition_batch(int32_t nmesh, const int64_t *nelem, int32_t nv_per_elem
 int rsb_partition_noalloc(int64_t nelem, int32_t nv_per_elem, const int64_t *elem_vertex_ids,
                           int32_t nparts, const rsb_opts *opts, int32_t *part_out,
                           rsb_stats *stats_out);
+
+/* Reference for the roofline of the streaming kernels (not a step of the
+ * method): *gbs_out = GB/s of a plain HBM stream over `bytes` on
+ * opts->device and opts->stream, the average of `reps` launches after a
+ * warm-up.  kind 0: read (16-byte non-temporal loads, summed); 1: copy
+ * (bytes read plus bytes written); 2: write.  Allocates its buffers.
+ * Errors: RSB_EINVAL for a bad kind, bytes < 4096, reps < 1 or a NULL
+ * pointer; RSB_ENOMEM; RSB_EDEVICE. */
+int rsb_hbm_probe(int32_t kind, int64_t bytes, int32_t reps, const rsb_opts *opts,
+                  double *gbs_out);
 
 /* Message for a return code (static string). */
 const char *rsb_strerror(int code);

@@ -55,7 +55,8 @@ class Stats(C.Structure):
         ("nnz", C.c_int64), ("kernel_bytes", C.c_double), ("kernel_ms", C.c_double),
         ("kernel_launches", C.c_int64), ("tile_rows", C.c_int32), ("amg_levels", C.c_int32),
         ("sweeps", C.c_int32), ("sweep_moved", C.c_int32), ("fallbacks", C.c_int32),
-        ("reserved", C.c_int32), ("ms_reorder", C.c_double),
+        ("reserved", C.c_int32), ("ms_reorder", C.c_double), ("spmv_alone_us", C.c_double),
+        ("spmv_alone_bytes", C.c_double),
     ]
 
     def as_dict(self):
@@ -95,6 +96,8 @@ _SIGNATURES = {
                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "rsb_amg_vcycle": ([C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                         C.c_void_p], C.c_int),
+    "rsb_hbm_probe": ([C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.POINTER(C.c_double)],
+                      C.c_int),
     "rsb_strerror": ([C.c_int], C.c_char_p),
     "rsb_last_error": ([], C.c_char_p),
 }
@@ -349,6 +352,15 @@ def partition_noalloc(ids, nparts: int, device: bool = False, **kw):
     code = _check(lib().rsb_partition_noalloc(n, nv, a.ptr, int(nparts), C.byref(o), pp,
                                               C.byref(st)), "rsb_partition_noalloc")
     return code, part, st.as_dict()
+
+
+def hbm_probe(kind: str, nbytes: int, reps: int = 10, **kw) -> float:
+    """GB/s of a plain HBM stream: kind 'read', 'copy' (read + write bytes) or 'write'."""
+    o = make_opts(False, **kw)
+    gbs = C.c_double(0)
+    _check(lib().rsb_hbm_probe({"read": 0, "copy": 1, "write": 2}[kind], int(nbytes), int(reps),
+                               C.byref(o), C.byref(gbs)), "rsb_hbm_probe")
+    return gbs.value
 
 
 def partition_batch(ids_list, nparts_list, device: bool = False, **kw):

@@ -416,6 +416,15 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     if (o.gather_scatter) gs_level_build(gsb, *L, total, L->gs, ctx);
     choose_tile(*L, o, work.get(), ctx);
     if (level == 0) st.tile_rows = kBlock * L->rpt;
+    if (level == 0 && o.profile && o.method != RSB_INVERSE_CG && !o.gather_scatter) {
+      // the level-0 Laplacian SpMV on its own, in the Lanczos directions'
+      // precision, with its algorithmic bytes: row pointers, the nonzeros'
+      // packed words, one read of x and one write of y
+      const bool f32 = o.precision == RSB_MIXED;
+      const double sv = f32 ? 4.0 : 8.0, n = (double)L->nrows;
+      st.spmv_alone_us = spmv_alone_us(view_of(*L), f32, 20, ctx);
+      st.spmv_alone_bytes = 4.0 * (n + 1.0) + 4.0 * (double)L->nnz + 2.0 * sv * n;
+    }
     solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
     components_and_targets(*L, C, S, ctx);
     phase_to(lv + " solve");
@@ -1092,6 +1101,20 @@ int rsb_partition_noalloc(int64_t nelem, int32_t nv, const int64_t *ids, int32_t
     if (!dev) copy_out(ctx, part_out, (const int32_t *)dpart, nelem, false);
     RSB_HIP(hipStreamSynchronize(ctx.stream));
     return r.status;
+  });
+}
+
+int rsb_hbm_probe(int32_t kind, int64_t bytes, int32_t reps, const rsb_opts *opts,
+                  double *gbs_out) {
+  return guarded([&]() -> int {
+    check_opts(opts);
+    if (kind < 0 || kind > 2 || bytes < 4096 || reps < 1 || !gbs_out)
+      fail(RSB_EINVAL, "rsb_hbm_probe: kind 0, 1 or 2, bytes >= 4096, reps >= 1, gbs_out "
+                       "non-NULL");
+    Ctx ctx;
+    setup_ctx(ctx, *opts);
+    *gbs_out = hbm_probe_gbs(kind, bytes, reps, opts->device, ctx);
+    return RSB_OK;
   });
 }
 

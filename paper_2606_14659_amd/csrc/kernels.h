@@ -19,6 +19,15 @@ struct NoallocRegion {
 // Makes `device` current and returns its region (RSB_EDEVICE if the lookup fails).
 NoallocRegion &noalloc_region(int device);
 
+// Reference measurements (probe.hip).  hbm_probe_gbs: GB/s of a plain
+// stream over `bytes` (kind 0 read, 1 copy counting both directions, 2
+// write), average of `reps` launches after a warm-up.  spmv_alone_us:
+// average time of y = L x alone on a level's sliced ELL (0 for the
+// gather-scatter operator).
+struct LevelView;
+double hbm_probe_gbs(int kind, int64_t bytes, int reps, int device, Ctx &ctx);
+double spmv_alone_us(const LevelView &L, bool fp32, int reps, Ctx &ctx);
+
 // ---------------------------------------------------------------------------
 // Plain CSR on the device (output of the dual-graph builder).
 // ---------------------------------------------------------------------------

@@ -44,8 +44,8 @@ def test_traffic_summary_scales_counters_by_the_copy(tmp_path):
     _counter_csv(tmp_path / "kw.csv", [(1, kern, "WRITE_SIZE", 40.0), (2, kern, "WRITE_SIZE", 40.0),
                                        (3, other, "WRITE_SIZE", 9e9)])
     # a 1 GiB copy whose reads the counter sees at half size and writes at full size
-    _counter_csv(tmp_path / "cf.csv", [(7, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0)])
-    _counter_csv(tmp_path / "cw.csv", [(7, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1048576.0)])
+    _counter_csv(tmp_path / "cf.csv", [(7, "rsb::(anonymous namespace)::k_hbm_copy(float __vector(4) const*, float __vector(4)*, long)", "FETCH_SIZE", 524288.0)])
+    _counter_csv(tmp_path / "cw.csv", [(7, "rsb::(anonymous namespace)::k_hbm_copy(float __vector(4) const*, float __vector(4)*, long)", "WRITE_SIZE", 1048576.0)])
     out = tmp_path / "traffic.txt"
     r = subprocess.run([sys.executable, BENCH, "--traffic-summary",
                         "--workload", "box128x128x64-holes5-2", "--kernel-name", kern, "--fetch-csv", str(tmp_path / "kf.csv"),
