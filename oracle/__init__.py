@@ -29,7 +29,8 @@ class Opts(C.Structure):
                 ("lanczos_keep", C.c_int32), ("inv_precond", C.c_int32),
                 ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double),
                 ("fiedler_sweep", C.c_int32), ("sweep_gap", C.c_double),
-                ("warm_start", C.c_int32), ("second_solve", C.c_int32)]
+                ("warm_start", C.c_int32), ("second_solve", C.c_int32),
+                ("lanczos_s", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -424,6 +424,78 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
     double last_b = 0.0;
     bool breakdown = false;
     for (int j = nk; j < m; ++j) {
+      if (o.lanczos_s == 2 && j >= 2 && j + 1 < m) {
+        // Two steps from one block (step j+1 and j+2 in the paper's
+        // numbering): K = [L q_j, L^2 q_j], two classical Gram-Schmidt
+        // passes of both columns against [u0, Q[0..j]], then Cholesky QR of
+        // the remainder W = [w1, w2] = [q_{j+1}, q_{j+2}] [[R00, R01], [0, R11]].
+        // Projected matrix: alpha_j = q_j^T L q_j (coefficient of L q_j on
+        // q_j), beta_{j+1} = R00, and, since L q_{j+1} = (L^2 q_j - L V h1) / R00
+        // and only q_j of the old basis couples to q_{j+1},
+        // alpha_{j+1} = q_{j+1}^T L q_{j+1} = R01 / R00 - alpha_j,
+        // beta_{j+2} = q_{j+2}^T L q_{j+1} = R11 / R00.
+        Vec w2(n);
+        apply_laplacian(g, Q[j], w);
+        apply_laplacian(g, w, w2);
+        info.matvecs += 2;
+        double a = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+          for (Vec *col : {&w, &w2}) {
+            const double *pw = col->data();
+            const double h0 = fixed_sum(n, [=](int64_t i) { return u0 * pw[i]; });
+            std::vector<double> h(j + 1);
+            for (int k2 = 0; k2 <= j; ++k2) h[k2] = dot(Q[k2], *col);
+            Vec &c = *col;
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
+            for (int64_t i = 0; i < n; ++i) {
+              double s = h0 * u0;
+              for (int k2 = 0; k2 <= j; ++k2) s += h[k2] * Q[k2][i];
+              c[i] -= s;
+            }
+            if (col == &w) a += h[j];
+          }
+        }
+        const double g00 = dot(w, w), g01 = dot(w, w2), g11 = dot(w2, w2);
+        const double r00 = std::sqrt(g00);
+        alpha.push_back(a);
+        H[(size_t)j * m + j] = a;
+        tnorm = std::max(tnorm, std::fabs(a) + r00 + (j == nk ? 0.0 : beta[j]));
+        if (r00 <= 1e-12 * tnorm) {  // breakdown after step j+1
+          last_b = r00;
+          breakdown = true;
+          break;
+        }
+        const double r01 = g01 / r00;
+        const double r11 = std::sqrt(std::max(g11 - r01 * r01, 0.0));
+        const double a1 = r01 / r00 - a, b1 = r00, b2 = r11 / r00;
+        beta.push_back(b1);
+        H[(size_t)j * m + j + 1] = H[(size_t)(j + 1) * m + j] = b1;
+        Vec qa(n);
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
+        for (int64_t i = 0; i < n; ++i) qa[i] = w[i] / r00;
+        Q.push_back(qa);
+        alpha.push_back(a1);
+        H[(size_t)(j + 1) * m + j + 1] = a1;
+        tnorm = std::max(tnorm, std::fabs(a1) + b2 + b1);
+        // the next direction, unnormalised with norm beta_{j+2}:
+        // (w2 - R01 q_{j+1}) / R00
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
+        for (int64_t i = 0; i < n; ++i) w[i] = (w2[i] - r01 * qa[i]) / r00;
+        last_b = b2;
+        ++j;
+        if (j == m - 1) break;
+        if (b2 <= 1e-12 * tnorm) {
+          breakdown = true;
+          break;
+        }
+        beta.push_back(b2);
+        H[(size_t)j * m + j + 1] = H[(size_t)(j + 1) * m + j] = b2;
+        Vec qb(n);
+#pragma omp parallel for schedule(static) if (n >= kThreadMin)
+        for (int64_t i = 0; i < n; ++i) qb[i] = w[i] / b2;
+        Q.push_back(qb);
+        continue;
+      }
       apply_laplacian(g, Q[j], w);
       ++info.matvecs;
       double a = dot(Q[j], w);
@@ -1175,6 +1247,7 @@ void orc_opts_default(orc_opts *o) {
   o->sweep_gap = 0.1;
   o->warm_start = 0;
   o->second_solve = 0;
+  o->lanczos_s = 1;
 }
 
 double orc_start_value(uint64_t seed, int64_t gid) { return start_value(seed, gid); }

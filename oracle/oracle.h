@@ -65,6 +65,10 @@ typedef struct orc_opts {
                                 pair comes from a second Lanczos solve from
                                 another random start (seed ^ ORC_SECOND_SEED),
                                 so that an exactly degenerate pair is swept */
+  int32_t lanczos_s;         /* 1: one Lanczos step at a time; 2: from step 3 on,
+                                steps j+1 and j+2 from one block [L q_j, L^2 q_j]
+                                (two-step Lanczos; the same Krylov space and
+                                projected matrix in exact arithmetic) */
 } orc_opts;
 
 #define ORC_SECOND_SEED 0x9E3779B97F4A7C15ull
