@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Lanczos iters/s + SpMV HBM GB/s; time to 4096-way RSB at matched edge cut"
 HBM_PEAK_GBS = 8000.0
-KERNEL_LABEL = "k_lz_project (SpMV + projection, Lanczos steps j>=3)"
+KERNEL_LABEL = "k_lz_pb (SpMV of L q + projection of the two-step block, Lanczos steps j>=3)"
 
 WORKLOADS = {
     "box256x256x128-clustered10-renum-4096": dict(nparts=4096),
@@ -149,7 +149,7 @@ def oracle_comparison(workload, lambda2, residual, cut):
 
 KERNEL_SOURCES = ("lanczos.hip", "solver_dev.h", "common.h", "kernels.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles",
-                            "k_lz_project_box256x256x128-clustered10-renum-4096_traffic.txt")
+                            "k_lz_pb_box256x256x128-clustered10-renum-4096_traffic.txt")
 
 
 def kernel_source_hash():
@@ -270,6 +270,9 @@ def main():
     ap.add_argument("--keep", type=int, default=8,
                     help="thick restart keeping this many Ritz pairs (0: explicit restart)")
     ap.add_argument("--max-restarts", type=int, default=50)
+    ap.add_argument("--lanczos-s", type=int, default=2, choices=[1, 2],
+                    help="thick restart: 2 = two Lanczos steps from one block (one basis "
+                         "read per step), 1 = one step at a time")
     ap.add_argument("--method", default="lanczos", choices=["lanczos", "inverse_cg", "auto"],
                     help="eigen-solver; inverse_cg runs report CG steps, not Lanczos steps")
     ap.add_argument("--sweep", type=int, default=0,
@@ -302,7 +305,7 @@ def main():
     ap.add_argument("--write-csv")
     ap.add_argument("--copy-fetch-csv")
     ap.add_argument("--copy-write-csv")
-    ap.add_argument("--kernel-name", default="k_lz_project<float, 4, 0, 3>")
+    ap.add_argument("--kernel-name", default="k_lz_pb<float, 4>")
     ap.add_argument("--kernel-label", default=KERNEL_LABEL)
     ap.add_argument("--commands", default="")
     ap.add_argument("--out", default=TRAFFIC_FILE)
@@ -339,8 +342,9 @@ def main():
                 max_restarts=args.max_restarts, verbose=args.verbose, lanczos_keep=args.keep,
                 method=args.method, inv_precond=args.precond, cg_tol=1e-8, inv_max_outer=100,
                 fiedler_sweep=args.sweep, warm_start=args.warm_start, reorder=args.reorder,
-                gather_scatter=args.gather_scatter, second_solve=args.second_solve, batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
-                autotune=args.autotune)
+                gather_scatter=args.gather_scatter, second_solve=args.second_solve,
+                batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
+                autotune=args.autotune, lanczos_s=args.lanczos_s)
     if args.autotune_cache:
         opts["autotune_cache"] = args.autotune_cache
 
@@ -406,6 +410,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "elements": mesh.nelem, "nparts": wl["nparts"],
                    "precision": args.precision, "lanczos_m": args.m, "lanczos_keep": args.keep,
+                   "lanczos_s": args.lanczos_s,
                    "tol": args.tol,
                    "max_restarts": args.max_restarts, "graph": "weighted vertex-shared",
                    "method": args.method, "precond": args.precond, "fiedler_sweep": args.sweep,
@@ -454,10 +459,11 @@ def main():
                        if pst and pst["spmv_alone_us"] > 0 else None),
     }
     if args.compare_per_subgraph:
-        # the plain per-subgraph FP64 GPU path: the same solver settings,
-        # FP64, every subgraph of a level solved on its own (one run)
+        # the plain per-subgraph FP64 GPU path: the same restart settings,
+        # FP64, one Lanczos step at a time, every subgraph of a level solved
+        # on its own (one run)
         t0 = time.perf_counter()
-        o = rsb.make_opts(True, **dict(opts, precision="fp64", batched=0))
+        o = rsb.make_opts(True, **dict(opts, precision="fp64", batched=0, lanczos_s=1))
         pst = rsb.Stats()
         pst.struct_size = rsb.C.sizeof(rsb.Stats)
         pcode = rsb.lib().rsb_partition(mesh.nelem, mesh.nv, rsb.C.c_void_p(ids.data_ptr()),

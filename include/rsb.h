@@ -180,6 +180,14 @@ typedef struct rsb_opts {
                                vector.  One Krylov space holds a single direction
                                of an exactly degenerate pair (Sec. 9), two solves
                                hold two.  Doubles the solve time.  0 (default). */
+  int32_t lanczos_s;        /* thick restart (lanczos_keep > 0) with the sliced-ELL
+                               operator: 2 = from step 3 on, steps j and j+1 come
+                               from one block [L q_j, L^2 q_j] (two-step Lanczos:
+                               the same Krylov space and projected matrix as one
+                               step at a time in exact arithmetic; the basis is
+                               read twice per two steps instead of twice per
+                               step); 1 (default) = one step at a time.  Ignored
+                               for explicit restart and gather_scatter. */
 } rsb_opts;
 
 typedef struct rsb_stats {

@@ -41,6 +41,7 @@ class Opts(C.Structure):
         ("inv_precond", C.c_int32), ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double),
         ("fiedler_sweep", C.c_int32), ("warm_start", C.c_int32), ("sweep_gap", C.c_double),
         ("reorder", C.c_int32), ("gather_scatter", C.c_int32), ("second_solve", C.c_int32),
+        ("lanczos_s", C.c_int32),
     ]
 
 

@@ -105,6 +105,7 @@ void check_opts(const rsb_opts *o) {
   if (o->second_solve != 0 && o->second_solve != 1) fail(RSB_EINVAL, "second_solve must be 0 or 1");
   if (o->second_solve && o->fiedler_sweep < 1)
     fail(RSB_EINVAL, "second_solve needs fiedler_sweep > 0");
+  if (o->lanczos_s != 1 && o->lanczos_s != 2) fail(RSB_EINVAL, "lanczos_s must be 1 or 2");
   if (o->gather_scatter != 0 && o->gather_scatter != 1)
     fail(RSB_EINVAL, "gather_scatter must be 0 or 1");
   if (o->gather_scatter && (o->graph != RSB_GRAPH_WEIGHTED || o->method == RSB_INVERSE_CG))
@@ -226,7 +227,8 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
       return inverse_level(v, C, SS, ip, work, y64, graph, ctx);
     }
     LanczosParams lp{o.lanczos_m, o.lanczos_keep, o.max_restarts, o.tol, graph ? 1 : 0,
-                     o.seed,      prof,           v.nnz,          y2, warm};
+                     o.seed,      prof,           v.nnz,          y2, warm,
+                     o.lanczos_s == 2 ? 1 : 0};
     return mixed ? lanczos_level<float>(v, C, SS, lp, work, y64, ctx)
                  : lanczos_level<double>(v, C, SS, lp, work, y64, ctx);
   };
@@ -744,6 +746,7 @@ int rsb_opts_init(rsb_opts *o) {
   o->amg_sigma = 2.0 / 3.0;
   o->fiedler_sweep = 0;
   o->sweep_gap = 0.1;
+  o->lanczos_s = 1;
   return RSB_OK;
 }
 

@@ -125,7 +125,11 @@ struct SegState {
   int32_t refine;       // mixed precision: 1 = stopped where FP32 directions stall with
                         // the tolerance not met, 2 = continued with FP64 directions
   int32_t stall;        // consecutive cycles whose residual changed by <= 5%
-  int32_t pad2;
+  int32_t pair;         // two-step Lanczos: 0 none pending; 1 the last pair's block
+                        // (W1, W2, factor R) awaits normalisation; 2 a one-column
+                        // pair ended the cycle (W1 is the continuation); 3 the
+                        // cycle's last vector awaits its second pass
+  double r00, r01, r11; // two-step Lanczos: Cholesky factor of the last pair's block
 };
 
 // The Laplacian in gather-scatter form (Sec. 5: A_w = P^T Q Q^T P,
@@ -306,6 +310,7 @@ struct LanczosParams {
   int64_t nnz;           // off-diagonal nonzeros of the level (for the byte count)
   double *y2_out;        // non-null (thick restart): the second Ritz vector, FP64
   const double *warm;    // non-null: warm start by element index (NaN: none)
+  int pairs = 0;         // 1: thick restart runs steps j >= 3 two at a time
 };
 // work: lanczos_workspace_bytes(L.nrows, m, T is float, keep) bytes of device
 // memory (FP64 u0, q_1, restart and work vectors; type-T directions q_2..q_m

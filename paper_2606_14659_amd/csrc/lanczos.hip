@@ -85,6 +85,9 @@ struct LzArgs {
                  // K + (k - 2) * vs, FP64 (the basis slots themselves when T = double)
   int64_t vs;
   T *Wt0, *Wt1;  // ping-pong work vectors of steps >= 2
+  double *Z1, *Z2;  // two-step Lanczos: L q~_j and L^2 q~_j of the current pair (FP64)
+  double *Pa, *Pb;  // two-step Lanczos: the pair's block after projection, W1 and W2 (FP64)
+  int pairs;     // 1: steps j >= 3 run two at a time (thick restart, sliced ELL)
   int m;
   double tol;
   int fp32_stall;     // T = float, thick restart: park a segment whose residual
@@ -132,6 +135,19 @@ template <typename T, int STEP>
 __device__ inline typename StepTypes<T, STEP>::Tw *step_out(const LzArgs<T> &a, int j) {
   if constexpr (STEP == 1) return a.Wd;
   else return (j & 1) ? a.Wt1 : a.Wt0;
+}
+
+// Does segment S run step j with the one-step launches?  With two-step
+// Lanczos only steps 1 and 2, and a first step j0 >= 4 that is even, do
+// (pairs start at odd steps j >= 3).
+template <typename T>
+__device__ inline bool single_step(const LzArgs<T> &a, const SegState &S, int j) {
+  return !a.pairs || j < 3 || (j == S.j0 && (j & 1) == 0);
+}
+
+// Does segment S run the pair of steps j, j + 1 (j odd, j >= 3)?
+__device__ inline bool pair_step(const SegState &S, int j) {
+  return S.active && !S.cycle_done && j >= S.j0 && j >= 3 && (j & 1);
 }
 
 // v_k^T z over one tile for a wavefront: slices of 64 rows, NSL of them
@@ -349,7 +365,7 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
-  if (!S.active || S.cycle_done || j < S.j0) return;
+  if (!S.active || S.cycle_done || j < S.j0 || !single_step(a, S, j)) return;
   if (MODE == 1 && !S.need2) return;
   const Tin *Win = step_in<T, STEP>(a, j);
   Tw *Wout = step_out<T, STEP>(a, j);
@@ -443,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_update(LzArgs<T> a, int j) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
-  if (!S.active || S.cycle_done || j < S.j0) return;
+  if (!S.active || S.cycle_done || j < S.j0 || !single_step(a, S, j)) return;
   if (PASS == 2 && !S.need2) return;
   const bool delayed = (PASS == 1) && a.keep > 0;
   const double *hg = a.h + (int64_t)b.seg * a.ps;
@@ -597,6 +613,18 @@ __global__ __launch_bounds__(kBlock) void k_lz_ritz_thick(LzArgs<T> a) {
     ts[c][l] = (c < nv && l >= 1 && l <= k) ? tg[(int64_t)c * a.ps + l - 1] : 0.0;
   }
   __syncthreads();
+  if (S.pair == 3) {
+    // two-step Lanczos: the last basis vector is stored before its second
+    // Gram-Schmidt pass, q_k = q~_k - sum_{l<k} d_l v_l (slot 0: u0); the
+    // Ritz vectors take the pass in their coefficients instead:
+    // t_l q_l summed = sum_{l<k} (t_l - t_k d_l) v_l + t_k q~_k
+    const double *dg = a.cdel + (int64_t)b.seg * a.ps;
+    for (int i = threadIdx.x; i < NKB * k; i += kBlock) {
+      const int c = i / k, l = i % k;
+      ts[c][l] -= ts[c][k] * dg[l];
+    }
+    __syncthreads();
+  }
   const bool cont = (k == a.m && k >= 2 && nv >= 1);
   const T *csrc = (k & 1) ? a.Wt1 : a.Wt0;          // output of step k >= 2
   T *cdst = (nv & 1) ? a.Wt1 : a.Wt0;               // input of step nv + 1 >= 3
@@ -606,9 +634,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_ritz_thick(LzArgs<T> a) {
   for (int r = 0; r < RPT; ++r) {
     const int64_t row = tr.row[r];
     double acc[NKB];
-    const double q1 = a.Q1[row];
+    const double q1 = a.Q1[row], u0 = a.U0[row];
 #pragma unroll
-    for (int c = 0; c < NKB; ++c) acc[c] = q1 * ts[c][1];
+    for (int c = 0; c < NKB; ++c) acc[c] = q1 * ts[c][1] + u0 * ts[c][0];
     // kept FP64 slots 2..nk, then type-T slots (coefficients past k are 0)
     const int kk = min(nkc, k);
     for (int l = 2; l <= kk; l += 4) {
@@ -651,6 +679,308 @@ __global__ __launch_bounds__(kBlock) void k_lz_ritz_thick(LzArgs<T> a) {
 }
 
 // ----------------------------------------------------------------------------
+// Two-step Lanczos (thick restart, steps j >= 3).  Steps j and j + 1 come
+// from one block [L q~_j, L^2 q~_j] (the same Krylov space and projected
+// matrix as one step at a time, in exact arithmetic).  Per pair:
+//   A: the step input q~_j (after a pair also that pair's first vector
+//      q~_{j-1}) is formed and stored; z1 = L q~_j;
+//   B: z2 = L z1; per block, the dot products of every basis vector with
+//      z1, z2 and with the vectors still waiting for their second
+//      Gram-Schmidt pass (q~_j, and after a pair q~_{j-1});
+//   reduce: the second-pass coefficients and the projections of z1 and z2
+//      on the corrected basis, written on the stored vectors; alpha_j;
+//   C: W = [z1, z2] - V H and the second pass of the waiting vectors from
+//      one read of the basis; partial sums of the Gram matrix of W;
+//   reduce: Cholesky QR W = [q~_{j+1}, q~_{j+2}] R: beta_{j+1} = R00,
+//      alpha_{j+1} = R01 / R00 - alpha_j (only q_j of the old basis couples
+//      to q_{j+1}), beta_{j+2} = R11 / R00.
+// The next pair's A forms q~_{j+1} = W1 / R00 and q~_{j+2} = (W2 - R01
+// q~_{j+1}) / R11; after the cycle's last pair the closing launches store
+// q~_k, give it its second pass and write the continuation direction.  When
+// j = m the pair has one column (step m alone).  The basis is read twice per
+// two steps instead of twice per step.
+// ----------------------------------------------------------------------------
+template <typename T, int RPT>
+__global__ __launch_bounds__(proj_threads<RPT>()) void k_lz_pa(LzArgs<T> a, int j) {
+  constexpr int NT = proj_threads<RPT>();
+  constexpr int TILE = kBlock * RPT;
+  constexpr int RT = TILE / NT;
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!pair_step(S, j)) return;
+  const bool from_pair = S.pair == 1;
+  const T *Win = ((j - 1) & 1) ? a.Wt1 : a.Wt0;
+  const double s1 = from_pair ? 1.0 / S.r00 : 0.0;
+  const double s2 = from_pair ? 1.0 / S.r11 : 0.0;
+  const double s3 = from_pair ? -S.r01 / (S.r00 * S.r11) : 0.0;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int lr = r * NT + (int)threadIdx.x;
+    const bool ok = lr < b.nrows;
+    const int64_t row = b.row0 + (ok ? lr : 0);
+    if (from_pair) {
+      const double w1 = a.Pa[row], w2 = a.Pb[row];
+      double l1, l2;
+      lap_row2<double>(a.chunk_ptr, a.cols, a.Pa, a.Pb, row, w1, w2, l1, l2);
+      const double qa = w1 * s1;
+      const double qb = w2 * s2 + w1 * s3;
+      if (ok) {
+        a.V[(int64_t)(j - 1) * a.vs + row] = (T)qa;
+        a.V[(int64_t)j * a.vs + row] = (T)qb;
+        a.Z1[row] = l2 * s2 + l1 * s3;
+      }
+    } else {
+      // (the one-step input: its SpMV in the directions' precision, as the
+      // one-step launches take it)
+      const T wi = Win[row];
+      const double qd = ((double)wi - S.c * a.U0[row]) * S.s;
+      const T lw = lap_row<T>(a.chunk_ptr, a.cols, Win, row, wi);
+      if (ok) {
+        a.V[(int64_t)j * a.vs + row] = (T)qd;
+        a.Z1[row] = S.s * (double)lw;
+      }
+    }
+  }
+}
+
+// v_k^T of four staged vectors over one tile (wavefront), one read of v_k.
+template <int NSL, typename P, typename SZ, typename SQ>
+__device__ inline void wave_dot4(const P *__restrict__ v, const SZ *z1, const SZ *z2,
+                                 const SQ *q1, const SQ *q2, int lane, int nsl, double (&acc)[4]) {
+  constexpr int NB = NSL < 8 ? NSL : 8;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = 0.0;
+  for (int t0 = 0; t0 < nsl; t0 += NB) {
+    P x[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) x[t] = (t0 + t < nsl) ? ld_stream(v + (t0 + t) * kWave) : (P)0;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const int o = (t0 + t) * kWave + lane;
+      if (t0 + t < nsl) {
+        const double xv = (double)x[t];
+        acc[0] += xv * (double)z1[o];
+        acc[1] += xv * (double)z2[o];
+        acc[2] += xv * (double)q1[o];
+        acc[3] += xv * (double)q2[o];
+      }
+    }
+  }
+}
+
+template <typename T, int RPT>
+__global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_per_eu(RPT <= 4 ? 6 : 4))) void k_lz_pb(LzArgs<T> a, int j) {
+  constexpr int NT = proj_threads<RPT>();
+  constexpr int TILE = kBlock * RPT;
+  constexpr int RT = TILE / NT;
+  constexpr int NW = NT / kWave;
+  constexpr int NSL = TILE / kWave;
+  __shared__ double z1s[TILE], z2s[TILE];
+  __shared__ T qjs[TILE], qis[TILE];
+  __shared__ double vals[4 * kMaxM + 8];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!pair_step(S, j)) return;
+  const bool two = j < a.m;
+  const bool pend2 = S.pair == 1;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int lr = r * NT + (int)threadIdx.x;
+    const bool ok = lr < b.nrows;
+    const int64_t row = b.row0 + (ok ? lr : 0);
+    const double z1 = a.Z1[row];
+    double z2 = 0.0;
+    if (two) {
+      z2 = lap_row<double>(a.chunk_ptr, a.cols, a.Z1, row, z1);
+      if (ok) a.Z2[row] = z2;
+    }
+    z1s[lr] = ok ? z1 : 0.0;
+    z2s[lr] = ok ? z2 : 0.0;
+    qjs[lr] = ok ? a.V[(int64_t)j * a.vs + row] : (T)0;
+    qis[lr] = (ok && pend2) ? a.V[(int64_t)(j - 1) * a.vs + row] : (T)0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int nsl = b.nrows / kWave;
+  // vals: [0, j] v_k^T z1 | [j+1, 2j+1] v_k^T z2 | [2j+2, 3j+1] v_k^T q~_j (k < j) |
+  //       [3j+2, 4j] v_k^T q~_{j-1} (k < j - 1)
+  for (int k = wave; k <= j; k += NW) {
+    double acc[4];
+    if (k <= 1) {
+      const double *v = (k == 0 ? a.U0 : a.Q1) + b.row0 + lane;
+      wave_dot4<NSL>(v, z1s, z2s, qjs, qis, lane, nsl, acc);
+    } else if (k <= S.nk) {
+      const double *v = a.K + (int64_t)(k - 2) * a.vs + b.row0 + lane;
+      wave_dot4<NSL>(v, z1s, z2s, qjs, qis, lane, nsl, acc);
+    } else {
+      const T *v = a.V + (int64_t)k * a.vs + b.row0 + lane;
+      wave_dot4<NSL>(v, z1s, z2s, qjs, qis, lane, nsl, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = wave_sum(acc[i]);
+    if (lane == 0) {
+      vals[k] = acc[0];
+      vals[j + 1 + k] = acc[1];
+      if (k < j) vals[2 * j + 2 + k] = acc[2];
+      if (k < j - 1) vals[3 * j + 2 + k] = acc[3];
+    }
+  }
+  __syncthreads();
+  const int nval = 4 * j + 1;
+  for (int i = threadIdx.x; i < nval; i += NT) a.part[(int64_t)lb * a.ps + i] = vals[i];
+}
+
+// acc_c[r] += sum_k coef_c[k] B[k - kb][row_r] for four coefficient vectors.
+template <typename P, int RPT>
+__device__ inline void accumulate_slots4(const P *__restrict__ B, int kb, int64_t vs,
+                                         const TileRows<RPT> &tr, const double *const *coef,
+                                         int k0, int k1, double (&acc)[4][RPT]) {
+  for (int k = k0; k <= k1; k += 4) {
+    P v[4][RPT];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        v[kk][r] = ld_stream(B + (int64_t)(min(k + kk, k1) - kb) * vs + tr.row[r]);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      if (k + kk > k1) break;
+      double cf[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cf[c] = coef[c][k + kk];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const double x = (double)v[kk][r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c][r] += x * cf[c];
+      }
+    }
+  }
+}
+
+template <typename T, int RPT>
+__global__ __launch_bounds__(kBlock) void k_lz_pc(LzArgs<T> a, int j) {
+  __shared__ double cs[4][kMaxM + 4];
+  __shared__ double red[4 * 3];
+  __shared__ double vals[3];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!pair_step(S, j)) return;
+  const bool two = j < a.m;
+  const bool pend2 = S.pair == 1;
+  // coefficient vectors over slots 0..j: g1, g2 (W = z - V g), e (second
+  // pass of q~_j), ei (second pass of q~_{j-1}); zero past their ranges
+  const double *hg = a.h + (int64_t)b.seg * a.ps;
+  const double *cg = a.cdel + (int64_t)b.seg * a.ps;
+  for (int k = threadIdx.x; k <= j + 3; k += kBlock) {
+    cs[0][k] = (k <= j) ? hg[k] : 0.0;
+    cs[1][k] = (two && k <= j) ? hg[j + 1 + k] : 0.0;
+    cs[2][k] = (k < j) ? cg[k] : 0.0;
+    cs[3][k] = (pend2 && k < j - 1) ? cg[j + k] : 0.0;
+  }
+  __syncthreads();
+  const TileRows<RPT> tr(b);
+  double acc[4][RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const double u = a.U0[tr.row[r]], q1 = a.Q1[tr.row[r]];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c][r] = u * cs[c][0] + q1 * cs[c][1];
+  }
+  const double *coef[4] = {cs[0], cs[1], cs[2], cs[3]};
+  const int kk = min(S.nk, j);
+  if (kk >= 2) accumulate_slots4<double, RPT>(a.K, 2, a.vs, tr, coef, 2, kk, acc);
+  if (j >= max(2, kk + 1)) accumulate_slots4<T, RPT>(a.V, 0, a.vs, tr, coef, max(2, kk + 1), j, acc);
+  double p[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int64_t row = tr.row[r];
+    const double w1 = a.Z1[row] - acc[0][r];
+    const double w2 = two ? a.Z2[row] - acc[1][r] : 0.0;
+    if (!tr.ok[r]) continue;
+    T *qj = a.V + (int64_t)j * a.vs + row;
+    *qj = (T)((double)*qj - acc[2][r]);
+    if (pend2) {
+      T *qi = a.V + (int64_t)(j - 1) * a.vs + row;
+      *qi = (T)((double)*qi - acc[3][r]);
+    }
+    a.Pa[row] = w1;
+    if (two) a.Pb[row] = w2;
+    p[0] += w1 * w1;
+    p[1] += w1 * w2;
+    p[2] += w2 * w2;
+  }
+  block_reduce_into<3>(p, red, vals, 3);
+  write_partials(a, lb, vals, 3);
+}
+
+// Closing launch of a cycle that ended in a pair (S.pair 1) or in a
+// one-column pair (S.pair 2).  With S.pair 1 the last basis vector
+// q~_k = W1 / R00 is stored and its dot products with the basis before it
+// are summed (its second pass, applied by the Ritz launch through its
+// coefficients); the continuation direction (unnormalised, norm
+// beta_{k+1}) is written where the Ritz launch expects the output of step k.
+template <typename T, int RPT>
+__global__ __launch_bounds__(proj_threads<RPT>()) void k_lz_px1(LzArgs<T> a) {
+  constexpr int NT = proj_threads<RPT>();
+  constexpr int TILE = kBlock * RPT;
+  constexpr int RT = TILE / NT;
+  constexpr int NW = NT / kWave;
+  constexpr int NSL = TILE / kWave;
+  __shared__ T qs[TILE];
+  __shared__ double vals[kMaxM + 4];
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const BlkDev b = a.blk[lb];
+  const SegState S = a.st[b.seg];
+  if (!S.active || (S.pair != 1 && S.pair != 2)) return;
+  const int k = S.k;
+  T *cont = (k & 1) ? a.Wt1 : a.Wt0;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int lr = r * NT + (int)threadIdx.x;
+    const bool ok = lr < b.nrows;
+    const int64_t row = b.row0 + (ok ? lr : 0);
+    T q = (T)0;
+    if (S.pair == 1) {
+      const double w1 = (double)a.Pa[row], w2 = (double)a.Pb[row];
+      const double qk = w1 / S.r00;
+      q = (T)qk;
+      if (ok) {
+        a.V[(int64_t)k * a.vs + row] = q;
+        cont[row] = (T)((w2 - S.r01 * qk) / S.r00);
+      }
+    } else if (ok) {
+      cont[row] = (T)a.Pa[row];
+    }
+    qs[lr] = ok ? q : (T)0;
+  }
+  if (S.pair != 1) return;
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int nsl = b.nrows / kWave;
+  for (int kb = wave; kb < k; kb += NW) {
+    double acc[4];
+    if (kb <= 1) {
+      const double *v = (kb == 0 ? a.U0 : a.Q1) + b.row0 + lane;
+      wave_dot4<NSL>(v, qs, qs, qs, qs, lane, nsl, acc);
+    } else if (kb <= S.nk) {
+      const double *v = a.K + (int64_t)(kb - 2) * a.vs + b.row0 + lane;
+      wave_dot4<NSL>(v, qs, qs, qs, qs, lane, nsl, acc);
+    } else {
+      const T *v = a.V + (int64_t)kb * a.vs + b.row0 + lane;
+      wave_dot4<NSL>(v, qs, qs, qs, qs, lane, nsl, acc);
+    }
+    acc[0] = wave_sum(acc[0]);
+    if (lane == 0) vals[kb] = acc[0];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += NT) a.part[(int64_t)lb * a.ps + i] = vals[i];
+}
+
+// ----------------------------------------------------------------------------
 // Gather-scatter operator: the group sums of the vector that the next launch
 // multiplies (the step's input, or the Ritz vector for the residual), for
 // the groups of the segments that launch works on.
@@ -689,11 +1019,12 @@ inline unsigned gs_grid(const GsView &g) { return (unsigned)((g.ngroups + kBlock
 // ----------------------------------------------------------------------------
 // Reductions and the per-segment logic that finishes each launch above.
 // ----------------------------------------------------------------------------
-enum LzOp { OP_BEGIN, OP_PROJ0, OP_PROJ1, OP_UPD1, OP_UPD2, OP_RITZ, OP_RESID };
+enum LzOp { OP_BEGIN, OP_PROJ0, OP_PROJ1, OP_UPD1, OP_UPD2, OP_RITZ, OP_RESID, OP_PB, OP_PC,
+            OP_PX };
 
 template <typename T, int OP>
 __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
-  __shared__ double vals[2 * kMaxM + 8];
+  __shared__ double vals[4 * kMaxM + 8];
   const int g = blockIdx.x;
   const GrpDev G = a.grp[g];
   const int s = G.seg;
@@ -706,6 +1037,8 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
                    : (OP == OP_PROJ0) ? (a.keep > 0 ? 2 * j + 2 : j + 2)
                    : (OP == OP_PROJ1) ? j + 2
                    : (OP == OP_UPD1 || OP == OP_UPD2) ? 1
+                   : (OP == OP_PB) ? 4 * j + 1
+                   : (OP == OP_PX) ? max(S.k, 1)
                    : 3;
   group_sums(a, G, vals, nval);
   bool take;
@@ -715,11 +1048,18 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
       break;
     case OP_PROJ0:
     case OP_UPD1:
-      take = S.active && !S.cycle_done && j >= S.j0;
+      take = S.active && !S.cycle_done && j >= S.j0 && single_step(a, S, j);
       break;
     case OP_PROJ1:
     case OP_UPD2:
-      take = S.active && !S.cycle_done && j >= S.j0 && S.need2;
+      take = S.active && !S.cycle_done && j >= S.j0 && S.need2 && single_step(a, S, j);
+      break;
+    case OP_PB:
+    case OP_PC:
+      take = pair_step(S, j);
+      break;
+    case OP_PX:
+      take = S.active && S.pair == 1;
       break;
     default:
       take = S.active != 0;
@@ -728,6 +1068,71 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
   if (!take) return;
   if (!group_finish(a, g, G, sg, vals, nval)) return;
   double *hs = a.h + (int64_t)s * a.ps;
+  if (OP == OP_PB) {
+    // Two-step Lanczos, after B.  q~_{j-1} (waiting when the input came from
+    // a pair) and q~_j get their second Gram-Schmidt pass:
+    //   q_{j-1} = q~_{j-1} - sum_{k<j-1} ci_k v_k,   ci_k = v_k^T q~_{j-1},
+    //   q_j = q~_j - sum_{k<j-1} c_k v_k - c_{j-1} q_{j-1},
+    // with c_k = v_k^T q~_j and c_{j-1} = q_{j-1}^T q~_j.  z1, z2 are
+    // projected on the corrected basis (h) and the combinations are
+    // written on the stored vectors (g; e and ei for the corrections).
+    __shared__ double sc[5];
+    const double *a1 = vals, *a2 = vals + j + 1, *d = vals + 2 * j + 2, *dd = vals + 3 * j + 2;
+    const bool pend2 = S.pair == 1;
+    if (threadIdx.x == 0) {
+      double cjm1 = d[j - 1], h1m = a1[j - 1], h2m = a2[j - 1];
+      if (pend2)
+        for (int k = 0; k < j - 1; ++k) {
+          cjm1 -= dd[k] * d[k];
+          h1m -= dd[k] * a1[k];
+          h2m -= dd[k] * a2[k];
+        }
+      double h1j = a1[j], h2j = a2[j];
+      for (int k = 0; k < j - 1; ++k) {
+        h1j -= d[k] * a1[k];
+        h2j -= d[k] * a2[k];
+      }
+      h1j -= cjm1 * h1m;
+      h2j -= cjm1 * h2m;
+      sc[0] = cjm1;
+      sc[1] = h1m;
+      sc[2] = h2m;
+      sc[3] = h1j;
+      sc[4] = h2j;
+    }
+    __syncthreads();
+    const double cjm1 = sc[0], h1j = sc[3], h2j = sc[4];
+    const double g1m = sc[1] - h1j * cjm1, g2m = sc[2] - h2j * cjm1;
+    double *cd = a.cdel + (int64_t)s * a.ps;
+    for (int k = threadIdx.x; k <= j; k += kBlock) {
+      double g1, g2;
+      if (k == j) {
+        g1 = h1j;
+        g2 = h2j;
+      } else if (k == j - 1) {
+        g1 = g1m;
+        g2 = g2m;
+        cd[k] = cjm1;
+      } else {
+        const double ci = pend2 ? dd[k] : 0.0;
+        g1 = a1[k] - h1j * d[k] - g1m * ci;
+        g2 = a2[k] - h2j * d[k] - g2m * ci;
+        cd[k] = d[k] - cjm1 * ci;
+        cd[j + k] = ci;
+      }
+      hs[k] = g1;
+      hs[j + 1 + k] = g2;
+    }
+    if (threadIdx.x == 0) a.alpha[(int64_t)s * a.ps + j - 1] = h1j;
+    return;
+  }
+  if (OP == OP_PX) {
+    // closing second pass of the cycle's last vector q~_k
+    double *cd = a.cdel + (int64_t)s * a.ps;
+    for (int i = threadIdx.x; i < S.k; i += kBlock) cd[i] = vals[i];
+    if (threadIdx.x == 0) a.st[s].pair = 3;
+    return;
+  }
   if (OP == OP_PROJ0 || OP == OP_PROJ1) {
     if (OP == OP_PROJ0 && a.keep > 0) {
       // delayed second pass: q_j = q~_j - sum_{k<j} c_k b_k.  The step must
@@ -764,6 +1169,40 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
   }
   if (threadIdx.x != 0) return;
   SegState &W = a.st[s];
+  if (OP == OP_PC) {
+    // Two-step Lanczos, after C: Cholesky QR of W = [W1, W2]
+    const double g00 = vals[0], g01 = vals[1], g11 = vals[2];
+    double *al = a.alpha + (int64_t)s * a.ps;
+    double *be = a.beta + (int64_t)s * a.ps;
+    const double alj = al[j - 1];
+    const double r00 = sqrt(fmax(g00, 0.0));
+    W.tnorm = fmax(W.tnorm, fabs(alj) + r00 + be[j - 1]);
+    be[j] = r00;
+    W.k = j;
+    W.r00 = r00;
+    if (j >= a.m) {  // one column (step m alone): W1 continues the next cycle
+      W.cycle_done = 1;
+      W.pair = 2;
+      return;
+    }
+    if (r00 <= a.brk * W.tnorm) {
+      W.cycle_done = 1;
+      W.pair = 0;
+      return;
+    }
+    const double r01 = g01 / r00;
+    const double r11 = sqrt(fmax(g11 - r01 * r01, 0.0));
+    const double al1 = r01 / r00 - alj, b2 = r11 / r00;
+    al[j] = al1;
+    be[j + 1] = b2;
+    W.tnorm = fmax(W.tnorm, fabs(al1) + b2 + r00);
+    W.k = j + 1;
+    W.r01 = r01;
+    W.r11 = r11;
+    W.pair = 1;
+    if (j + 1 >= a.m || b2 <= a.brk * W.tnorm) W.cycle_done = 1;
+    return;
+  }
   if (OP == OP_BEGIN || OP == OP_RITZ) {
     const double c = vals[0];
     W.c = c;
@@ -779,6 +1218,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
       W.converged = 0;
       W.refine = 0;
       W.stall = 0;
+      W.pair = 0;
       W.restarts = 0;
       W.tnorm = 0.0;
       W.res = 0.0;
@@ -829,6 +1269,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
     W.restarts += 1;
     W.cycle_done = 0;
     W.need2 = 0;
+    W.pair = 0;
     const double *be = a.beta + (int64_t)s * a.ps;
     const int kc = W.k;
     if (a.keep > 0 && kc == a.m && W.nnext >= 1 && be[kc] > 0.0 && !to_fp64) {
@@ -854,6 +1295,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
       W.tnorm = tn;
       W.c = 0.0;
       W.s = 1.0 / bl;
+      // two-step Lanczos: a cycle starting at an even step >= 4 needs the
+      // one-step launches of even steps
+      if (a.pairs && !to_fp64 && W.j0 >= 4 && !(W.j0 & 1)) atomicAdd(&a.flags[4], 1);
     } else {
       // explicit restart from the Ritz vector (c, s stay the transform of Y)
       W.nk = 0;
@@ -1372,6 +1816,7 @@ __global__ void k_flags_reset(int32_t *flags) {
   flags[0] = 0;
   flags[1] = 0;
   flags[2] = 0;
+  flags[4] = 0;
 }
 
 template <int MB, int KB, typename T>
@@ -1415,15 +1860,39 @@ struct LzLaunch {
     k_lz_update<T, RPT, 2, STEP><<<nblk, kBlock, 0, s>>>(a, j);
     k_lz_reduce<T, OP_UPD2><<<ngrp, kBlock, 0, s>>>(a, j);
   }
+  // two-step Lanczos: steps j and j + 1 (j odd, j >= 3)
+  static void pair(const LzArgs<T> &a, int nblk, int ngrp, int j, hipStream_t s,
+                   hipEvent_t *ev) {
+    k_lz_pa<T, RPT><<<nblk, proj_threads<RPT>(), 0, s>>>(a, j);
+    if (ev) (void)hipEventRecord(ev[0], s);
+    k_lz_pb<T, RPT><<<nblk, proj_threads<RPT>(), 0, s>>>(a, j);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    k_lz_reduce<T, OP_PB><<<ngrp, kBlock, 0, s>>>(a, j);
+    k_lz_pc<T, RPT><<<nblk, kBlock, 0, s>>>(a, j);
+    k_lz_reduce<T, OP_PC><<<ngrp, kBlock, 0, s>>>(a, j);
+  }
   // ev: null, or 2*(m+1) events; ev[2j], ev[2j+1] bracket the first-pass
-  // project launch of every step j >= 3.
+  // project launch of every step j >= 3 (two-step Lanczos: the B launch of
+  // the pair starting at odd j).
+  // even_singles (two-step Lanczos): also the one-step launches of even
+  // steps >= 4, for segments whose cycle starts at such a step
   static void cycle(const LzArgs<T> &a, int nblk, int ngrp, int nseg, hipStream_t s,
-                    hipEvent_t *ev = nullptr) {
+                    hipEvent_t *ev = nullptr, bool even_singles = true) {
     k_flags_reset<<<1, 1, 0, s>>>(a.flags);
     for (int j = 1; j <= a.m; ++j) {
+      if (a.pairs && j >= 3 && (j & 1)) {
+        pair(a, nblk, ngrp, j, s, ev ? ev + 2 * j : nullptr);
+        continue;
+      }
+      if (a.pairs && j >= 4 && !even_singles) continue;
       if (j == 1) step<1>(a, nblk, ngrp, j, s, nullptr);
       else if (j == 2) step<2>(a, nblk, ngrp, j, s, nullptr);
-      else step<3>(a, nblk, ngrp, j, s, ev ? ev + 2 * j : nullptr);
+      else step<3>(a, nblk, ngrp, j, s, (ev && !a.pairs) ? ev + 2 * j : nullptr);
+    }
+    if (a.pairs) {
+      // (the second pass of the last vector is applied by the Ritz launch)
+      k_lz_px1<T, RPT><<<nblk, proj_threads<RPT>(), 0, s>>>(a);
+      k_lz_reduce<T, OP_PX><<<ngrp, kBlock, 0, s>>>(a, 0);
     }
     if (a.keep > 0) {
       trieig_arrow_launch(a, nseg, s);
@@ -1461,9 +1930,10 @@ void dispatch_rpt(int rpt, F &&f) {
 
 void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx &ctx) {
   S.m = m;
-  // partial sums of 2 j + 2 values (delayed second pass), or of the kept
-  // directions' coefficients of CG with full projection
-  S.pstride = std::max(2 * m + 8, kMaxFullProj);
+  // partial sums of 2 j + 2 values (delayed second pass), 4 j + 1 (two-step
+  // Lanczos), or of the kept directions' coefficients of CG with full
+  // projection
+  S.pstride = std::max(4 * m + 8, kMaxFullProj);
   S.nkcap = std::max(1, keep);
   const size_t ns = std::max(nseg, 1), nb = std::max(nblk, 1), ng = std::max(ngrp, 1);
   if (!S.st.p || S.st.n < ns) S.st.alloc(ctx, ns);
@@ -1478,7 +1948,7 @@ void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx
   S.gpart.alloc(ctx, ng * S.pstride);
   S.gcnt.alloc(ctx, ng);
   S.scnt.alloc(ctx, ns);
-  S.n_active.alloc(ctx, 4);
+  S.n_active.alloc(ctx, 8);
   S.counters.alloc(ctx, 4);
   RSB_HIP(hipMemsetAsync(S.gcnt.get(), 0, S.gcnt.bytes(), ctx.stream));
   RSB_HIP(hipMemsetAsync(S.scnt.get(), 0, S.scnt.bytes(), ctx.stream));
@@ -1489,7 +1959,9 @@ void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx
 size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32, int keep) {
   const size_t t = fp32 ? 4 : 8;
   const size_t kept = (fp32 && keep > 1) ? (size_t)(keep - 1) * 8 : 0;
-  return (size_t)rows * (5 * 8 + (size_t)(m + 3) * t + kept);
+  // FP64 u0, q1, Y, Wd (+1 spare); type-T basis (m + 1) and work vectors (2);
+  // FP64 kept Ritz vectors; the four vectors of a two-step pair
+  return (size_t)rows * (5 * 8 + (size_t)(m + 3) * t + kept + 4 * 8);
 }
 
 namespace {
@@ -1502,12 +1974,14 @@ int64_t run_cycles(const LzArgs<T> &a, const LevelView &L, const LanczosParams &
   const int nblk = L.nblk, nseg = L.nseg, ngrp = L.ngrp;
   int64_t level_steps = 0;
   struct Res {
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr, exec_lean = nullptr;
+    hipGraph_t graph = nullptr, graph_lean = nullptr;
     std::vector<hipEvent_t> ev;
     ~Res() {
       if (exec) (void)hipGraphExecDestroy(exec);
       if (graph) (void)hipGraphDestroy(graph);
+      if (exec_lean) (void)hipGraphExecDestroy(exec_lean);
+      if (graph_lean) (void)hipGraphDestroy(graph_lean);
       for (auto e : ev) (void)hipEventDestroy(e);
     }
   } res;
@@ -1524,6 +1998,13 @@ int64_t run_cycles(const LzArgs<T> &a, const LevelView &L, const LanczosParams &
     hipError_t e = hipStreamEndCapture(ctx.stream, &res.graph);
     if (e != hipSuccess) fail(RSB_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
     RSB_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
+    if (a.pairs) {
+      RSB_HIP(hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal));
+      Lz::cycle(a, nblk, ngrp, nseg, ctx.stream, nullptr, false);
+      e = hipStreamEndCapture(ctx.stream, &res.graph_lean);
+      if (e != hipSuccess) fail(RSB_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+      RSB_HIP(hipGraphInstantiate(&res.exec_lean, res.graph_lean, nullptr, nullptr, 0));
+    }
   }
   // profiled byte count: per segment active in the cycle, its rows for
   // every step it ran (its nonzeros taken in proportion to its rows)
@@ -1546,8 +2027,10 @@ int64_t run_cycles(const LzArgs<T> &a, const LevelView &L, const LanczosParams &
     steps0.resize(nseg);
     j00.resize(nseg);
   }
-  int32_t flags[3] = {0, 0, 0};
+  int32_t flags[5] = {0, 0, 0, 0, 0};
   for (int cyc = 0; cyc <= p.max_restarts; ++cyc) {
+    // (the first cycle of a solve starts at step 1 everywhere)
+    const bool even_singles = flags[4] > 0;
     if (prof) {
       read_state();
       for (int i = 0; i < nseg; ++i) {
@@ -1557,9 +2040,10 @@ int64_t run_cycles(const LzArgs<T> &a, const LevelView &L, const LanczosParams &
       }
     }
     if (res.exec) {
-      RSB_HIP(hipGraphLaunch(res.exec, ctx.stream));
+      RSB_HIP(hipGraphLaunch((res.exec_lean && !even_singles) ? res.exec_lean : res.exec,
+                             ctx.stream));
     } else {
-      Lz::cycle(a, nblk, ngrp, nseg, ctx.stream, prof ? res.ev.data() : nullptr);
+      Lz::cycle(a, nblk, ngrp, nseg, ctx.stream, prof ? res.ev.data() : nullptr, even_singles);
       RSB_LAUNCHED();
     }
     RSB_HIP(hipMemcpyAsync(flags, a.flags, sizeof(flags), hipMemcpyDeviceToHost, ctx.stream));
@@ -1587,7 +2071,8 @@ int64_t run_cycles(const LzArgs<T> &a, const LevelView &L, const LanczosParams &
       const double op_row = L.gs.nv ? 4.0 * L.gs.nv + 4.0 +
                                           8.0 * (double)L.gs.ngroups / (double)std::max<int64_t>(L.nrows, 1)
                                     : 4.0 * nnz_per_row;
-      for (int j = 3; j <= flags[1]; ++j) {
+      for (int j = 3; j <= flags[1]; j += a.pairs ? 2 : 1) {
+        if (a.pairs && !(j & 1)) continue;
         float ms = 0.f;
         RSB_HIP(hipEventElapsedTime(&ms, res.ev[2 * j], res.ev[2 * j + 1]));
         double rows = 0.0, kept_rows = 0.0;
@@ -1598,8 +2083,12 @@ int64_t run_cycles(const LzArgs<T> &a, const LevelView &L, const LanczosParams &
           }
         profp->ms += ms;
         profp->launches += 1;
+        // one-step: x, q_j and L q_j, u0 and q_1 (FP64), slots 2..j-1;
+        // two-step B: z1 and z2, u0 and q_1, slots 2..j
         profp->bytes += (L.gs.nv ? 0.0 : 4.0 * (rows + 1)) + op_row * rows +
-                        rows * (st + st + st + 16.0 + (j - 2) * st) + kept_rows * (8.0 - st);
+                        (a.pairs ? rows * (st + st + 16.0 + (j - 1) * st)
+                                 : rows * (st + st + st + 16.0 + (j - 2) * st)) +
+                        kept_rows * (8.0 - st);
       }
     }
     if (flags[0] == 0) break;
@@ -1647,8 +2136,17 @@ LzArgs<T> level_args(const LevelView &L, CompDev &C, SolveDev &S, const LanczosP
   a.Wt0 = wt + (int64_t)(p.m + 1) * L.nrows;
   a.Wt1 = a.Wt0 + L.nrows;
   // kept Ritz vectors (FP64): after the work vectors when the directions are
-  // FP32, else the basis slots themselves
+  // FP32, else the basis slots themselves; then the four vectors of a pair
   a.K = sizeof(T) == 8 ? (double *)(a.V + 2 * L.nrows) : (double *)(a.Wt1 + L.nrows);
+  // (FP64 whatever T is: the second vector of a pair is formed from the
+  // block with a cancellation, W2 - R01 q_{j+1}, that magnifies rounding)
+  double *pb = sizeof(T) == 8 ? (double *)(a.Wt1 + L.nrows)
+                              : a.K + (int64_t)std::max(p.keep - 1, 0) * L.nrows;
+  a.Z1 = pb;
+  a.Z2 = pb + L.nrows;
+  a.Pa = pb + 2 * L.nrows;
+  a.Pb = pb + 3 * L.nrows;
+  a.pairs = (p.pairs && p.keep > 0 && L.gs.nv == 0) ? 1 : 0;
   a.m = p.m;
   a.tol = p.tol;
   a.fp32_stall = 0;
@@ -1701,7 +2199,7 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
       // FP64 directions for the parked segments: u0, q_1, the Ritz vector
       // and the step-1 work vector stay where they are; the basis, the kept
       // Ritz vectors and the work vectors get an FP64 layout of their own
-      DevBuf<double> ws2(ctx, (size_t)(p.m + 3) * (size_t)L.nrows);
+      DevBuf<double> ws2(ctx, (size_t)(p.m + 3 + 4) * (size_t)L.nrows);
       LzArgs<double> d = level_args<double>(L, C, S, p, work);
       d.U0 = a.U0;
       d.Q1 = a.Q1;
@@ -1711,6 +2209,10 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
       d.Wt0 = d.V + (int64_t)(p.m + 1) * L.nrows;
       d.Wt1 = d.Wt0 + L.nrows;
       d.K = d.V + 2 * L.nrows;
+      d.Z1 = d.Wt1 + L.nrows;  // (T = double)
+      d.Z2 = d.Z1 + L.nrows;
+      d.Pa = d.Z2 + L.nrows;
+      d.Pb = d.Pa + L.nrows;
       dispatch_rpt<double>(L.rpt, [&](auto launcher) {
         using Lz = decltype(launcher);
         k_lz_refine_on<<<(L.nseg + kBlock - 1) / kBlock, kBlock, 0, ctx.stream>>>(d.st, L.nseg);

@@ -192,6 +192,47 @@ __device__ inline X lap_row(const int64_t *__restrict__ chunk_ptr, const uint32_
   return acc;
 }
 
+// The same row of L applied to two vectors from one read of the column words.
+template <int G, typename X>
+__device__ inline void lap_slots2(const uint32_t *__restrict__ cp, const X *__restrict__ x,
+                                  const X *__restrict__ y, int k0, int width, X xi, X yi,
+                                  X &ax, X &ay) {
+  uint32_t w[G];
+#pragma unroll
+  for (int u = 0; u < G; ++u) w[u] = ld_stream(cp + (int64_t)(k0 + u) * 64);
+#pragma unroll
+  for (int u = 0; u < G; ++u) w[u] = (k0 + u < width) ? w[u] : 0u;
+  X xv[G], yv[G];
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+    xv[u] = x[colw_col(w[u])];
+    yv[u] = y[colw_col(w[u])];
+  }
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+    const X wt = (X)colw_wt(w[u]);
+    ax += colw_wt(w[u]) ? wt * (xi - xv[u]) : (X)0;
+    ay += colw_wt(w[u]) ? wt * (yi - yv[u]) : (X)0;
+  }
+}
+
+template <typename X>
+__device__ inline void lap_row2(const int64_t *__restrict__ chunk_ptr,
+                                const uint32_t *__restrict__ cols, const X *__restrict__ x,
+                                const X *__restrict__ y, int64_t row, X xi, X yi, X &ax, X &ay) {
+  constexpr int G = sizeof(X) == 8 ? kSlotGroup / 4 : kSlotGroup / 2;
+  const int64_t c = row >> 6;
+  const int lane = (int)(row & 63);
+  const int64_t p = chunk_ptr[c];
+  const int width = (int)((chunk_ptr[c + 1] - p) >> 6);
+  const uint32_t *cp = cols + p + lane;
+  ax = 0;
+  ay = 0;
+  int k0 = 0;
+  for (; k0 + 4 < width; k0 += G) lap_slots2<G>(cp, x, y, k0, width, xi, yi, ax, ay);
+  if (k0 < width) lap_slots2<4>(cp, x, y, k0, width, xi, yi, ax, ay);
+}
+
 // Gather-scatter row (Sec. 5): (L x)_e = deg_e x_e - sum of U over the row's
 // vertex groups, U already holding the group sums of x.  Slots are read four
 // at a time (loads in flight together); a slot without a group adds 0.
