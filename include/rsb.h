@@ -217,13 +217,17 @@ typedef struct rsb_stats {
                                 (-1 when the total number of parts > 16384) */
   double avg_neighbors;      /* rsb_partition: mean neighbour parts of a part */
   int64_t nnz;               /* off-diagonal nonzeros of the level-0 Laplacian */
-  /* opts->profile = 1: the SpMV-and-projection kernel of Lanczos steps j >= 3 */
+  /* opts->profile = 1: the SpMV-and-projection kernel of Lanczos steps j >= 3
+   * (lanczos_s = 2: the B launch of the pair starting at step j) */
   double kernel_bytes;       /* algorithmic bytes of all its launches: per launch at
                                 step j over n rows with nnz off-diagonal entries,
                                 4 (n + 1) + 4 nnz + n (s_x + s_Lq + s_q + 16 +
                                 (j - 2) s_q + (k - 1)(8 - s_q)), s_ = bytes per
                                 value, k = Ritz pairs kept by a thick restart
-                                (FP64 basis slots 2..k; no term for k <= 1) */
+                                (FP64 basis slots 2..k; no term for k <= 1);
+                                lanczos_s = 2: 4 (n + 1) + 4 nnz + n (8 + 8 + 16 +
+                                (j - 1) s_q + (k - 1)(8 - s_q)) (z1 read, z2
+                                written, both FP64; basis slots 0..j) */
   double kernel_ms;          /* summed device time of its launches (HIP events) */
   int64_t kernel_launches;   /* its launches */
   int32_t tile_rows;         /* rows per workgroup of the streaming kernels at level 0 */

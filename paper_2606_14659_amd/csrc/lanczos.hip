@@ -2084,9 +2084,9 @@ int64_t run_cycles(const LzArgs<T> &a, const LevelView &L, const LanczosParams &
         profp->ms += ms;
         profp->launches += 1;
         // one-step: x, q_j and L q_j, u0 and q_1 (FP64), slots 2..j-1;
-        // two-step B: z1 and z2, u0 and q_1, slots 2..j
+        // two-step B: z1 read and z2 written (FP64), u0 and q_1, slots 2..j
         profp->bytes += (L.gs.nv ? 0.0 : 4.0 * (rows + 1)) + op_row * rows +
-                        (a.pairs ? rows * (st + st + 16.0 + (j - 1) * st)
+                        (a.pairs ? rows * (8.0 + 8.0 + 16.0 + (j - 1) * st)
                                  : rows * (st + st + st + 16.0 + (j - 2) * st)) +
                         kept_rows * (8.0 - st);
       }

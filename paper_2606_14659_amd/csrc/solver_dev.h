@@ -220,7 +220,8 @@ template <typename X>
 __device__ inline void lap_row2(const int64_t *__restrict__ chunk_ptr,
                                 const uint32_t *__restrict__ cols, const X *__restrict__ x,
                                 const X *__restrict__ y, int64_t row, X xi, X yi, X &ax, X &ay) {
-  constexpr int G = sizeof(X) == 8 ? kSlotGroup / 4 : kSlotGroup / 2;
+  // 8 slots at a time: 8 words and 16 gathers in flight
+  constexpr int G = kSlotGroup / 2;
   const int64_t c = row >> 6;
   const int lane = (int)(row & 63);
   const int64_t p = chunk_ptr[c];
