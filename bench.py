@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Lanczos iters/s + SpMV HBM GB/s; time to 4096-way RSB at matched edge cut"
 HBM_PEAK_GBS = 8000.0
 KERNEL_LABEL = "k_lz_pb (SpMV of L q + projection of the two-step block, Lanczos steps j>=3)"
+KERNEL_LABEL_S1 = "k_lz_project (SpMV of q_j + projection, Lanczos steps j>=3)"
 
 WORKLOADS = {
     "box256x256x128-clustered10-renum-4096": dict(nparts=4096),
@@ -390,6 +391,7 @@ def main():
             raise SystemExit("profiled partition differs from the timed ones")
         print(f"[bench] profiled run: {pst['ms_total']:.0f} ms", file=sys.stderr, flush=True)
     achieved = kern_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
+    klabel = KERNEL_LABEL if args.lanczos_s == 2 else KERNEL_LABEL_S1
     probe = {}
     if not args.no_profile:
         for kind in ("read", "copy", "write"):
@@ -438,10 +440,10 @@ def main():
                                     st["edge_cut"]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": stored_traffic(args.workload, KERNEL_LABEL)
+                     "traffic": stored_traffic(args.workload, klabel)
                      if st["tile_rows"] == 1024 and not args.gather_scatter and not args.reorder
                      else None,
-                     "kernel": KERNEL_LABEL,
+                     "kernel": klabel,
                      "tile_rows_level0": st["tile_rows"],
                      "algorithmic_bytes_per_launch": kern_bytes / max(kern_launches, 1),
                      "launches": kern_launches,

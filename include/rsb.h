@@ -188,6 +188,14 @@ typedef struct rsb_opts {
                                read twice per two steps instead of twice per
                                step); 1 (default) = one step at a time.  Ignored
                                for explicit restart and gather_scatter. */
+  int32_t pack_matrix;      /* 1 (default) = each level also keeps a packed copy of
+                               the sliced-ELL slices whose column offsets from the
+                               row (column - row) fit in at most 4 windows of 1024:
+                               16-bit entries (weight, window, offset) instead of
+                               32-bit words, read by the Lanczos and CG SpMVs; the
+                               other slices are read as 32-bit words.  The same
+                               entries in the same order, so results are bitwise
+                               those of 0 = 32-bit words only. */
 } rsb_opts;
 
 typedef struct rsb_stats {
@@ -220,14 +228,14 @@ typedef struct rsb_stats {
   /* opts->profile = 1: the SpMV-and-projection kernel of Lanczos steps j >= 3
    * (lanczos_s = 2: the B launch of the pair starting at step j) */
   double kernel_bytes;       /* algorithmic bytes of all its launches: per launch at
-                                step j over n rows with nnz off-diagonal entries,
-                                4 (n + 1) + 4 nnz + n (s_x + s_Lq + s_q + 16 +
-                                (j - 2) s_q + (k - 1)(8 - s_q)), s_ = bytes per
-                                value, k = Ritz pairs kept by a thick restart
-                                (FP64 basis slots 2..k; no term for k <= 1);
-                                lanczos_s = 2: 4 (n + 1) + 4 nnz + n (8 + 8 + 16 +
-                                (j - 1) s_q + (k - 1)(8 - s_q)) (z1 read, z2
-                                written, both FP64; basis slots 0..j) */
+                                step j over n rows, 4 (n + 1) + M + n (s_x + s_Lq +
+                                s_q + 16 + (j - 2) s_q + (k - 1)(8 - s_q)), M = the
+                                rows' share of matrix_bytes (below; 4 nnz without
+                                packing), s_ = bytes per value, k = Ritz pairs kept
+                                by a thick restart (FP64 basis slots 2..k; no term
+                                for k <= 1); lanczos_s = 2: 4 (n + 1) + M + n (8 +
+                                8 + 16 + (j - 1) s_q + (k - 1)(8 - s_q)) (z1 read,
+                                z2 written, both FP64; basis slots 0..j) */
   double kernel_ms;          /* summed device time of its launches (HIP events) */
   int64_t kernel_launches;   /* its launches */
   int32_t tile_rows;         /* rows per workgroup of the streaming kernels at level 0 */
@@ -241,7 +249,13 @@ typedef struct rsb_stats {
   /* opts->profile = 1 (Lanczos, sliced ELL): y = L x alone on the level-0
    * matrix in the directions' precision, 20 launches timed with HIP events */
   double spmv_alone_us;      /* average launch time */
-  double spmv_alone_bytes;   /* algorithmic bytes per launch: 4 (n + 1) + 4 nnz + 2 s n */
+  double spmv_alone_bytes;   /* algorithmic bytes per launch: 4 (n + 1) + matrix_bytes
+                                + 2 s n */
+  /* level 0 (first mesh's level of rsb_partition_batch: the whole level) */
+  double packed_fraction;    /* nonzeros in packed slices / nnz */
+  double matrix_bytes;       /* the matrix as the SpMV reads it: 4 per nonzero of a
+                                32-bit slice, 2 per nonzero of a packed slice plus 16
+                                per packed slice (window bases) */
 } rsb_stats;
 
 /* Fills *o with the defaults listed above.  Returns RSB_OK or RSB_EINVAL (o NULL). */

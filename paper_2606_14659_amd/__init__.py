@@ -42,6 +42,7 @@ class Opts(C.Structure):
         ("fiedler_sweep", C.c_int32), ("warm_start", C.c_int32), ("sweep_gap", C.c_double),
         ("reorder", C.c_int32), ("gather_scatter", C.c_int32), ("second_solve", C.c_int32),
         ("lanczos_s", C.c_int32),
+        ("pack_matrix", C.c_int32),
     ]
 
 
@@ -57,7 +58,8 @@ class Stats(C.Structure):
         ("kernel_launches", C.c_int64), ("tile_rows", C.c_int32), ("amg_levels", C.c_int32),
         ("sweeps", C.c_int32), ("sweep_moved", C.c_int32), ("fallbacks", C.c_int32),
         ("reserved", C.c_int32), ("ms_reorder", C.c_double), ("spmv_alone_us", C.c_double),
-        ("spmv_alone_bytes", C.c_double),
+        ("spmv_alone_bytes", C.c_double), ("packed_fraction", C.c_double),
+        ("matrix_bytes", C.c_double),
     ]
 
     def as_dict(self):

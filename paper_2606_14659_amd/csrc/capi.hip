@@ -106,6 +106,7 @@ void check_opts(const rsb_opts *o) {
   if (o->second_solve && o->fiedler_sweep < 1)
     fail(RSB_EINVAL, "second_solve needs fiedler_sweep > 0");
   if (o->lanczos_s != 1 && o->lanczos_s != 2) fail(RSB_EINVAL, "lanczos_s must be 1 or 2");
+  if (o->pack_matrix != 0 && o->pack_matrix != 1) fail(RSB_EINVAL, "pack_matrix must be 0 or 1");
   if (o->gather_scatter != 0 && o->gather_scatter != 1)
     fail(RSB_EINVAL, "gather_scatter must be 0 or 1");
   if (o->gather_scatter && (o->graph != RSB_GRAPH_WEIGHTED || o->method == RSB_INVERSE_CG))
@@ -130,6 +131,7 @@ void setup_ctx(Ctx &ctx, const rsb_opts &o, bool private_stream = true) {
   }
   ctx.limit = o.device_mem_limit;
   ctx.verbose = o.verbose;
+  ctx.pack = o.pack_matrix != 0;
   if (const char *env = std::getenv("RSB_LOG"))
     if (std::string(env) == "level") ctx.verbose = std::max(ctx.verbose, 1);
   if (const char *env = std::getenv("RSB_FAULT_INJECT")) {
@@ -247,7 +249,10 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     v.seg = os.seg.get();
     v.blk = os.blk.get();
     v.grp = os.grp.get();
-    v.nnz = (int64_t)((double)L.nnz * L.seg[s].npad / std::max<int64_t>(L.nrows, 1));
+    const double frac = (double)L.seg[s].npad / (double)std::max<int64_t>(L.nrows, 1);
+    v.nnz = (int64_t)((double)L.nnz * frac);
+    v.packed_nnz = (int64_t)((double)L.packed_nnz * frac);
+    v.packed_slices = (int64_t)((double)L.packed_slices * frac);
     v.gs.only_seg = s;
     const int64_t steps = run(v, S1, false, inverse);
     RSB_HIP(hipMemcpyAsync(S.st.get() + s, S1.st.get(), sizeof(SegState),
@@ -417,15 +422,20 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     CompDev C;
     if (o.gather_scatter) gs_level_build(gsb, *L, total, L->gs, ctx);
     choose_tile(*L, o, work.get(), ctx);
-    if (level == 0) st.tile_rows = kBlock * L->rpt;
+    if (level == 0) {
+      st.tile_rows = kBlock * L->rpt;
+      st.packed_fraction = L->nnz > 0 ? (double)L->packed_nnz / (double)L->nnz : 0.0;
+      st.matrix_bytes = matrix_bytes(view_of(*L));
+    }
     if (level == 0 && o.profile && o.method != RSB_INVERSE_CG && !o.gather_scatter) {
       // the level-0 Laplacian SpMV on its own, in the Lanczos directions'
-      // precision, with its algorithmic bytes: row pointers, the nonzeros'
-      // packed words, one read of x and one write of y
+      // precision, with its algorithmic bytes: row pointers, the matrix as
+      // read (32-bit words, or packed entries and their window bases), one
+      // read of x and one write of y
       const bool f32 = o.precision == RSB_MIXED;
       const double sv = f32 ? 4.0 : 8.0, n = (double)L->nrows;
       st.spmv_alone_us = spmv_alone_us(view_of(*L), f32, 20, ctx);
-      st.spmv_alone_bytes = 4.0 * (n + 1.0) + 4.0 * (double)L->nnz + 2.0 * sv * n;
+      st.spmv_alone_bytes = 4.0 * (n + 1.0) + matrix_bytes(view_of(*L)) + 2.0 * sv * n;
     }
     solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
     components_and_targets(*L, C, S, ctx);
@@ -747,6 +757,7 @@ int rsb_opts_init(rsb_opts *o) {
   o->fiedler_sweep = 0;
   o->sweep_gap = 0.1;
   o->lanczos_s = 1;
+  o->pack_matrix = 1;
   return RSB_OK;
 }
 

@@ -141,6 +141,7 @@ struct Ctx {
   int verbose = 0;
   std::vector<std::string> tuned;  // tile classes timed during this call
   int64_t fp64_level_steps = 0;    // mixed precision: level steps continued with FP64 directions
+  bool pack = true;                // levels keep a packed copy of the slices that fit
   Arena *arena = nullptr;          // non-null: device scratch comes from this region only
   FaultPlan fault;
   Ctx() = default;
@@ -229,6 +230,24 @@ __host__ __device__ inline uint32_t pack_colw(uint32_t col, uint32_t w) {
 }
 __host__ __device__ inline uint32_t colw_col(uint32_t word) { return word >> kColShift; }
 __host__ __device__ inline uint32_t colw_wt(uint32_t word) { return word & kWeightMask; }
+
+// ---------------------------------------------------------------------------
+// Packed copy of a slice (16-bit slot entries, two per word: slot 2p in the
+// low half of word p, slot 2p + 1 in the high half).  A slice's deltas
+// (column - row) are covered by at most kPackClusters windows of
+// 2^kPackOffBits, window b starting at base b (ascending); an entry holds
+// (weight << 12) | (b << 10) | (delta - base b), 0 for a padding slot.  Slice
+// c starts at word (chunk_ptr[c] + 64 c) / 2 (room for ceil(width / 2) words
+// per row).  A slice whose deltas need more windows keeps only its 32-bit
+// words; its meta.x is kPlainSlice.
+// ---------------------------------------------------------------------------
+constexpr int kPackOffBits = 10;
+constexpr int kPackClusters = 4;
+constexpr int32_t kPlainSlice = INT32_MIN;
+
+__host__ __device__ inline int64_t packed_slice_word(int64_t chunk_word, int64_t chunk) {
+  return (chunk_word + 64 * chunk) >> 1;
+}
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

@@ -41,6 +41,8 @@ struct InvArgs {
   int ps;
   const int64_t *chunk_ptr;
   const uint32_t *cols;
+  const uint32_t *pk;  // packed slices (see SellRef)
+  const int4 *meta;
   const int32_t *root;
   const int32_t *gid;
   double *U0, *B, *X, *R, *P0, *P1, *LP;
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_inv_res(InvArgs a) {
     const int64_t row = tr.row[r];
     const double xi = a.X[row];
     const double y = (xi - c * a.U0[row]) * sc;
-    const double ly = sc * lap_row<double>(a.chunk_ptr, a.cols, a.X, row, xi);
+    const double ly = sc * lap_row<double>(SellRef{a.chunk_ptr, a.cols, a.pk, a.meta}, a.X, row, xi);
     const double rr = ly - th * y;
     if (tr.ok[r]) {
       p[0] += rr * rr;
@@ -500,6 +502,8 @@ int64_t inverse_impl(const LevelView &L, CompDev &C, SolveDev &S, const InverseP
   a.ps = S.pstride;
   a.chunk_ptr = L.chunk_ptr;
   a.cols = L.cols;
+  a.pk = L.pk;
+  a.meta = L.pmeta;
   a.root = C.root.get();
   a.gid = L.gid;
   double *w = (double *)work;

@@ -188,6 +188,10 @@ struct Level {
   DevBuf<int32_t> gid;         // row -> element id within its mesh
   int64_t words = 0;
   int64_t nnz = 0;             // off-diagonal nonzeros (non-padding words)
+  DevBuf<uint32_t> pk;         // packed copy of the slices that fit (16-bit entries)
+  DevBuf<int4> pmeta;          // [nchunks] window bases, or kPlainSlice
+  int64_t packed_slices = 0;   // slices read in the packed form
+  int64_t packed_nnz = 0;      // nonzeros in those slices
   GsLevel gs;                  // gather-scatter operator, when selected
 };
 
@@ -201,11 +205,26 @@ struct LevelView {
   const GrpDev *grp = nullptr;
   const int64_t *chunk_ptr = nullptr;
   const uint32_t *cols = nullptr;
+  const uint32_t *pk = nullptr;
+  const int4 *pmeta = nullptr;
   const int32_t *gid = nullptr;
   const int32_t *orig = nullptr;
   int64_t nnz = 0;
+  int64_t nchunks = 0, packed_slices = 0, packed_nnz = 0;
   GsView gs;
 };
+
+// Algorithmic bytes of a level's matrix as the row kernels read it: 4 per
+// nonzero of a slice kept in 32-bit words, 2 per nonzero of a packed slice
+// plus its 16 bytes of window bases.
+inline double matrix_bytes(const LevelView &v) {
+  const double pn = (double)v.packed_nnz;
+  return 4.0 * ((double)v.nnz - pn) + 2.0 * pn + 16.0 * (double)v.packed_slices;
+}
+
+// Packed copy of a level's slices (or every slice marked kPlainSlice when
+// packing is off): Level::pk, pmeta, packed_slices, packed_nnz.
+void pack_level(Level &L, Ctx &ctx);
 
 inline LevelView view_of(const Level &L) {
   LevelView v;
@@ -219,6 +238,11 @@ inline LevelView view_of(const Level &L) {
   v.grp = L.d_grp.get();
   v.chunk_ptr = L.chunk_ptr.get();
   v.cols = L.cols.get();
+  v.pk = L.pk.get();
+  v.pmeta = L.pmeta.get();
+  v.nchunks = L.nchunks;
+  v.packed_slices = L.packed_slices;
+  v.packed_nnz = L.packed_nnz;
   v.gid = L.gid.get();
   v.orig = L.orig.get();
   v.nnz = L.nnz;

@@ -74,6 +74,8 @@ struct LzArgs {
   int ps;
   const int64_t *chunk_ptr;
   const uint32_t *cols;
+  const uint32_t *pk;  // packed slices (see SellRef)
+  const int4 *meta;
   const int32_t *root;
   const int32_t *gid;
   double *U0;    // u0 (ones vector of the cut component, normalised)
@@ -102,6 +104,7 @@ struct LzArgs {
   const int32_t *orig;     // row -> element index of the whole call (-1: padding)
   const double *warm;      // warm start by element (NaN: none), or null
   GsView gs;               // gather-scatter operator (gs.nv > 0) instead of the sliced ELL
+  __device__ SellRef sell() const { return {chunk_ptr, cols, pk, meta}; }
 };
 
 // Vector types of step j: STEP 1 reads Y and works in FP64; STEP 2 reads the
@@ -387,7 +390,7 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
     if (MODE == 0) {
       const Tin wi = Win[row];
       const double qd = ((double)wi - c * a.U0[row]) * sc;
-      const Tin lw = a.gs.nv ? gs_row<Tin>(a.gs, row, wi) : lap_row<Tin>(a.chunk_ptr, a.cols, Win, row, wi);
+      const Tin lw = a.gs.nv ? gs_row<Tin>(a.gs, row, wi) : lap_row<Tin>(a.sell(), Win, row, wi);
       const Tw lq = (Tw)(sc * (double)lw);
       if (STEP == 1) {
         q = qd;
@@ -569,7 +572,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_residual(LzArgs<T> a) {
     const double wi = a.Y[row];
     const double y = (wi - c * a.U0[row]) * sc;
     const double ly =
-        sc * (a.gs.nv ? gs_row<double>(a.gs, row, wi) : lap_row<double>(a.chunk_ptr, a.cols, a.Y, row, wi));
+        sc * (a.gs.nv ? gs_row<double>(a.gs, row, wi) : lap_row<double>(a.sell(), a.Y, row, wi));
     const double rr = ly - th * y;
     if (tr.ok[r]) {
       // the normalised Ritz vector is q_1 of a thick-restarted next cycle
@@ -722,7 +725,7 @@ __global__ __launch_bounds__(proj_threads<RPT>()) void k_lz_pa(LzArgs<T> a, int 
     if (from_pair) {
       const double w1 = a.Pa[row], w2 = a.Pb[row];
       double l1, l2;
-      lap_row2<double>(a.chunk_ptr, a.cols, a.Pa, a.Pb, row, w1, w2, l1, l2);
+      lap_row2<double>(a.sell(), a.Pa, a.Pb, row, w1, w2, l1, l2);
       const double qa = w1 * s1;
       const double qb = w2 * s2 + w1 * s3;
       if (ok) {
@@ -735,7 +738,7 @@ __global__ __launch_bounds__(proj_threads<RPT>()) void k_lz_pa(LzArgs<T> a, int 
       // one-step launches take it)
       const T wi = Win[row];
       const double qd = ((double)wi - S.c * a.U0[row]) * S.s;
-      const T lw = lap_row<T>(a.chunk_ptr, a.cols, Win, row, wi);
+      const T lw = lap_row<T>(a.sell(), Win, row, wi);
       if (ok) {
         a.V[(int64_t)j * a.vs + row] = (T)qd;
         a.Z1[row] = S.s * (double)lw;
@@ -793,7 +796,7 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
     const double z1 = a.Z1[row];
     double z2 = 0.0;
     if (two) {
-      z2 = lap_row<double>(a.chunk_ptr, a.cols, a.Z1, row, z1);
+      z2 = lap_row<double>(a.sell(), a.Z1, row, z1);
       if (ok) a.Z2[row] = z2;
     }
     z1s[lr] = ok ? z1 : 0.0;
@@ -2065,12 +2068,12 @@ int64_t run_cycles(const LzArgs<T> &a, const LevelView &L, const LanczosParams &
       // vectors in basis slots 2..nk, stored in FP64 whatever T is.
       read_state();
       const double st = (double)sizeof(T);
-      const double nnz_per_row = (double)p.nnz / (double)std::max<int64_t>(L.nrows, 1);
-      // operator bytes per row: sliced ELL words, or the gather-scatter
-      // slot words, degree and group sums (each group read once)
+      // operator bytes per row: the sliced-ELL matrix as read (32-bit
+      // words or packed entries), or the gather-scatter slot words, degree
+      // and group sums (each group read once)
       const double op_row = L.gs.nv ? 4.0 * L.gs.nv + 4.0 +
                                           8.0 * (double)L.gs.ngroups / (double)std::max<int64_t>(L.nrows, 1)
-                                    : 4.0 * nnz_per_row;
+                                    : matrix_bytes(L) / (double)std::max<int64_t>(L.nrows, 1);
       for (int j = 3; j <= flags[1]; j += a.pairs ? 2 : 1) {
         if (a.pairs && !(j & 1)) continue;
         float ms = 0.f;
@@ -2119,6 +2122,8 @@ LzArgs<T> level_args(const LevelView &L, CompDev &C, SolveDev &S, const LanczosP
   a.ps = S.pstride;
   a.chunk_ptr = L.chunk_ptr;
   a.cols = L.cols;
+  a.pk = L.pk;
+  a.meta = L.pmeta;
   a.root = C.root.get();
   a.gid = L.gid;
   a.orig = L.orig;
@@ -2281,6 +2286,8 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
   a.ps = S.pstride;
   a.chunk_ptr = L.chunk_ptr;
   a.cols = L.cols;
+  a.pk = L.pk;
+  a.meta = L.pmeta;
   a.gs = L.gs;
   double *wd = (double *)work;
   a.U0 = wd;

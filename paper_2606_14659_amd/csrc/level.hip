@@ -742,11 +742,114 @@ __global__ void k_row_part_offset(const int32_t *__restrict__ orig, const SegDev
   poff[i] = mesh_off[seg[s].mesh];
 }
 
+// Packed copy of the slices (the layout is described with kPackOffBits):
+// one wavefront per slice.  The window bases cover the slice's deltas
+// (column - row) greedily from the least one (each base is the least delta
+// the windows before it leave uncovered), which needs the fewest windows; a
+// slice that needs more than kPackClusters keeps only its 32-bit words.
+__device__ inline int32_t wave_min_i32(int32_t v) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_slices(const int64_t *__restrict__ chunk_ptr,
+                                                       const uint32_t *__restrict__ cols,
+                                                       int64_t nchunks, uint32_t *__restrict__ pk,
+                                                       int4 *__restrict__ meta,
+                                                       unsigned long long *__restrict__ cnt) {
+  const int64_t c = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (c >= nchunks) return;  // the whole wavefront
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t p = chunk_ptr[c];
+  const int width = (int)((chunk_ptr[c + 1] - p) >> 6);
+  const int32_t row = (int32_t)(c * kWave + lane);
+  const uint32_t *cp = cols + p + lane;
+  int32_t b[kPackClusters] = {0, 0, 0, 0};
+  int nb = 0;
+  bool fits = true;
+  int32_t covered = INT32_MIN;  // deltas <= covered lie in a window
+  for (;;) {
+    int32_t mn = INT32_MAX;
+    for (int k = 0; k < width; ++k) {
+      const uint32_t w = cp[(int64_t)k * kWave];
+      const int32_t d = (int32_t)colw_col(w) - row;
+      if (colw_wt(w) && d > covered && d < mn) mn = d;
+    }
+    mn = wave_min_i32(mn);
+    if (mn == INT32_MAX) break;
+    if (nb == kPackClusters) {
+      fits = false;
+      break;
+    }
+#pragma unroll
+    for (int i = 0; i < kPackClusters; ++i) b[i] = (i == nb) ? mn : b[i];
+    ++nb;
+    covered = mn + ((1 << kPackOffBits) - 1);
+  }
+  if (!fits) {
+    if (lane == 0) meta[c] = make_int4(kPlainSlice, 0, 0, 0);
+    return;
+  }
+  uint32_t *out = pk + packed_slice_word(p, c) + lane;
+  int nz = 0;
+  for (int q = 0; 2 * q < width; ++q) {
+    uint32_t h[2] = {0u, 0u};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int k = 2 * q + t;
+      const uint32_t w = k < width ? cp[(int64_t)k * kWave] : 0u;
+      if (colw_wt(w)) {
+        const int32_t d = (int32_t)colw_col(w) - row;
+        // window: the last base <= d (bases ascending, unused ones never match)
+        const int i = (nb > 1 && d >= b[1]) + (nb > 2 && d >= b[2]) + (nb > 3 && d >= b[3]);
+        const int32_t base = i == 0 ? b[0] : i == 1 ? b[1] : i == 2 ? b[2] : b[3];
+        h[t] = (colw_wt(w) << 12) | ((uint32_t)i << kPackOffBits) | (uint32_t)(d - base);
+        ++nz;
+      }
+    }
+    out[(int64_t)q * kWave] = h[0] | (h[1] << 16);
+  }
+  nz = wave_sum_i(nz);
+  if (lane == 0) {
+    meta[c] = make_int4(b[0], b[1], b[2], b[3]);
+    atomicAdd(&cnt[0], (unsigned long long)nz);
+    atomicAdd(&cnt[1], 1ull);
+  }
+}
+
+__global__ void k_meta_plain(int4 *meta, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) meta[i] = make_int4(kPlainSlice, 0, 0, 0);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+void pack_level(Level &L, Ctx &ctx) {
+  L.pmeta.alloc(ctx, std::max<int64_t>(L.nchunks, 1));
+  L.packed_slices = L.packed_nnz = 0;
+  if (L.nchunks == 0) return;
+  if (!ctx.pack) {
+    k_meta_plain<<<grid_for(L.nchunks, kBlock), kBlock, 0, ctx.stream>>>(L.pmeta.get(), L.nchunks);
+    RSB_LAUNCHED();
+    return;
+  }
+  L.pk.alloc(ctx, std::max<int64_t>(packed_slice_word(L.words, L.nchunks), 1));
+  DevBuf<unsigned long long> cnt(ctx, 2);
+  RSB_HIP(hipMemsetAsync(cnt.get(), 0, 2 * sizeof(unsigned long long), ctx.stream));
+  const int64_t per = kBlock / kWave;
+  k_pack_slices<<<(unsigned)((L.nchunks + per - 1) / per), kBlock, 0, ctx.stream>>>(
+      L.chunk_ptr.get(), L.cols.get(), L.nchunks, L.pk.get(), L.pmeta.get(), cnt.get());
+  RSB_LAUNCHED();
+  unsigned long long h[2] = {0, 0};
+  RSB_HIP(hipMemcpyAsync(h, cnt.get(), sizeof(h), hipMemcpyDeviceToHost, ctx.stream));
+  RSB_HIP(hipStreamSynchronize(ctx.stream));
+  L.packed_nnz = (int64_t)h[0];
+  L.packed_slices = (int64_t)h[1];
+}
+
 void level_tables(Level &L, int rpt, Ctx &ctx) {
   L.rpt = rpt;
   L.blk.clear();
@@ -830,6 +933,7 @@ void level0_from_csr(Level &L, const std::vector<const DevCsr *> &g,
   L.orig.alloc(ctx, std::max<int64_t>(L.nrows, 1));
   L.gid.alloc(ctx, std::max<int64_t>(L.nrows, 1));
   if (L.nseg == 0) {
+    pack_level(L, ctx);
     level_tables(L, rpt, ctx);
     return;
   }
@@ -860,6 +964,7 @@ void level0_from_csr(Level &L, const std::vector<const DevCsr *> &g,
         orig_base[mesh_seg[s]], perm ? (*perm)[mesh_seg[s]] : nullptr);
     RSB_LAUNCHED();
   }
+  pack_level(L, ctx);
   level_tables(L, rpt, ctx);
 }
 
@@ -1132,6 +1237,7 @@ void compact_level(Level &L, const uint8_t *side, int32_t *d_part_out, Level &ne
   next.gid.alloc(ctx, std::max<int64_t>(next.nrows, 1));
   if (next.nseg == 0) {
     RSB_HIP(hipStreamSynchronize(ctx.stream));
+    pack_level(next, ctx);
     level_tables(next, rpt, ctx);
     return;
   }
@@ -1167,6 +1273,7 @@ void compact_level(Level &L, const uint8_t *side, int32_t *d_part_out, Level &ne
                                            next.cols.get(), next.orig.get(), next.gid.get(),
                                            L.nrows);
   RSB_LAUNCHED();
+  pack_level(next, ctx);
   level_tables(next, rpt, ctx);
 }
 

@@ -74,12 +74,11 @@ __global__ void k_fill_f32(float *p, int64_t n, float v) {
     p[i] = v;
 }
 
-// y = L x on the level's sliced ELL (difference form), one row per thread
-// slot, tiles and block order as the Lanczos kernels use them.
+// y = L x on the level's sliced ELL (difference form; packed slices where
+// the level has them), one row per thread slot, tiles and block order as the
+// Lanczos kernels use them.
 template <typename T, int RPT>
-__global__ __launch_bounds__(kBlock) void k_spmv_alone(const BlkDev *__restrict__ blk,
-                                                       const int64_t *__restrict__ chunk_ptr,
-                                                       const uint32_t *__restrict__ cols,
+__global__ __launch_bounds__(kBlock) void k_spmv_alone(const BlkDev *__restrict__ blk, SellRef m,
                                                        const T *__restrict__ x,
                                                        T *__restrict__ y) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -87,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_alone(const BlkDev *__restrict_
   const TileRows<RPT> tr(b);
   T v[RPT];
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) v[r] = lap_row<T>(chunk_ptr, cols, x, tr.row[r], x[tr.row[r]]);
+  for (int r = 0; r < RPT; ++r) v[r] = lap_row<T>(m, x, tr.row[r], x[tr.row[r]]);
 #pragma unroll
   for (int r = 0; r < RPT; ++r)
     if (tr.ok[r]) y[tr.row[r]] = v[r];
@@ -128,8 +127,8 @@ double spmv_alone_typed(const LevelView &L, int reps, Ctx &ctx) {
   double total = 0.0;
   auto launch = [&](auto rpt_tag) {
     constexpr int RPT = decltype(rpt_tag)::value;
-    k_spmv_alone<T, RPT><<<L.nblk, kBlock, 0, ctx.stream>>>(L.blk, L.chunk_ptr, L.cols, x.get(),
-                                                            y.get());
+    k_spmv_alone<T, RPT><<<L.nblk, kBlock, 0, ctx.stream>>>(
+        L.blk, SellRef{L.chunk_ptr, L.cols, L.pk, L.pmeta}, x.get(), y.get());
   };
   auto run = [&]() {
     switch (L.rpt) {

@@ -152,86 +152,165 @@ __device__ inline P ld_stream(const P *p) {
   return __builtin_nontemporal_load(p);
 }
 
+// The level's Laplacian as the row kernels read it: the sliced-ELL words and
+// their packed copy (per-slice meta; kPlainSlice: words only).
+struct SellRef {
+  const int64_t *chunk_ptr;
+  const uint32_t *cols;
+  const uint32_t *pk;
+  const int4 *meta;
+};
+
 // Sliced-ELL Laplacian row in difference form: sum_j w_ij (x_i - x_j),
-// accumulated in the vector type (paper Sec. 5: the action of L on x).
-template <int G, typename X>
-__device__ inline void lap_slots(const uint32_t *__restrict__ cp, const X *__restrict__ x, int k0,
-                                 int width, X xi, X &acc) {
-  uint32_t w[G];
+// accumulated in the vector type in slot order (paper Sec. 5: the action of L
+// on x); a padding slot leaves the sum as it is.  The words are read in groups
+// of G slots, exactly the row's width (loads past it masked off); the next
+// group's words are issued before the current group's gathers are consumed,
+// so words and gathers are in flight together.
+template <int G>
+__device__ inline void lap_words(const uint32_t *__restrict__ cp, int k0, int width,
+                                 uint32_t (&w)[G]) {
 #pragma unroll
-  for (int u = 0; u < G; ++u) w[u] = ld_stream(cp + (int64_t)(k0 + u) * 64);
-#pragma unroll
-  for (int u = 0; u < G; ++u) w[u] = (k0 + u < width) ? w[u] : 0u;
-  X xv[G];
-#pragma unroll
-  for (int u = 0; u < G; ++u) xv[u] = x[colw_col(w[u])];
-#pragma unroll
-  for (int u = 0; u < G; ++u) acc += colw_wt(w[u]) ? (X)colw_wt(w[u]) * (xi - xv[u]) : (X)0;
+  for (int u = 0; u < G; ++u) w[u] = (k0 + u < width) ? ld_stream(cp + (int64_t)(k0 + u) * 64) : 0u;
 }
 
-template <typename X>
-__device__ inline X lap_row(const int64_t *__restrict__ chunk_ptr, const uint32_t *__restrict__ cols,
-                            const X *__restrict__ x, int64_t row, X xi) {
-  // slots read at once: 16 for 4-byte values, 8 for 8-byte values (register
-  // budget), and a group of 4 for a short remainder; never more than the
-  // zero slack after the last slice
-  constexpr int G = sizeof(X) == 8 ? kSlotGroup / 2 : kSlotGroup;
-  const int64_t c = row >> 6;
-  const int lane = (int)(row & 63);
-  const int64_t p = chunk_ptr[c];
-  const int width = (int)((chunk_ptr[c + 1] - p) >> 6);
-  const uint32_t *cp = cols + p + lane;
+// w (x_i - x_j) added to the row's sum as one fused multiply-add, so that the
+// 32-bit and the packed reading of a slice give the same bits.
+__device__ inline float lap_fma(float w, float d, float acc) { return __builtin_fmaf(w, d, acc); }
+__device__ inline double lap_fma(double w, double d, double acc) { return __builtin_fma(w, d, acc); }
+
+// One slot entry of a packed slice: weight, and the column as an offset from
+// the row (the slice's window base for its cluster added).
+struct PkEntry {
+  uint32_t wt;
+  int32_t col;
+};
+
+__device__ inline PkEntry pk_entry(uint32_t half, int32_t row, const int4 &mb) {
+  const uint32_t cid = (half >> kPackOffBits) & (kPackClusters - 1);
+  const int32_t base = cid == 0 ? mb.x : cid == 1 ? mb.y : cid == 2 ? mb.z : mb.w;
+  return {half >> 12, row + base + (int32_t)(half & ((1u << kPackOffBits) - 1))};
+}
+
+template <typename X, int G>
+__device__ inline X lap_row_plain(const uint32_t *__restrict__ cp, int width,
+                                  const X *__restrict__ x, X xi) {
   X acc = 0;
-  // Groups of slots with unconditional loads (all column words, then all
-  // gathers, so they are in flight together).  Slots past the row's width
-  // read the next slice or the zero slack after the last one and are masked
-  // to weight 0; a weight-0 slot contributes exactly 0 whatever it gathered.
-  int k0 = 0;
-  for (; k0 + 4 < width; k0 += G) lap_slots<G>(cp, x, k0, width, xi, acc);
-  if (k0 < width) lap_slots<4>(cp, x, k0, width, xi, acc);
+  uint32_t w[G];
+  lap_words<G>(cp, 0, width, w);
+  for (int k0 = 0; k0 < width; k0 += G) {
+    X xv[G];
+    uint32_t wc[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      wc[u] = w[u];
+      xv[u] = colw_wt(wc[u]) ? x[colw_col(wc[u])] : (X)0;
+    }
+    lap_words<G>(cp, k0 + G, width, w);
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+      acc = colw_wt(wc[u]) ? lap_fma((X)colw_wt(wc[u]), xi - xv[u], acc) : acc;
+  }
   return acc;
 }
 
-// The same row of L applied to two vectors from one read of the column words.
-template <int G, typename X>
-__device__ inline void lap_slots2(const uint32_t *__restrict__ cp, const X *__restrict__ x,
-                                  const X *__restrict__ y, int k0, int width, X xi, X yi,
-                                  X &ax, X &ay) {
-  uint32_t w[G];
+// Packed slice: GW words (2 GW slots) per group.
+template <typename X, int GW>
+__device__ inline X lap_row_packed(const uint32_t *__restrict__ cp, int nw, const int4 &mb,
+                                   int32_t row, const X *__restrict__ x, X xi) {
+  X acc = 0;
+  uint32_t w[GW];
+  lap_words<GW>(cp, 0, nw, w);
+  for (int k0 = 0; k0 < nw; k0 += GW) {
+    X xv[2 * GW];
+    PkEntry e[2 * GW];
 #pragma unroll
-  for (int u = 0; u < G; ++u) w[u] = ld_stream(cp + (int64_t)(k0 + u) * 64);
+    for (int u = 0; u < GW; ++u) {
+      e[2 * u] = pk_entry(w[u] & 0xffffu, row, mb);
+      e[2 * u + 1] = pk_entry(w[u] >> 16, row, mb);
+    }
 #pragma unroll
-  for (int u = 0; u < G; ++u) w[u] = (k0 + u < width) ? w[u] : 0u;
-  X xv[G], yv[G];
+    for (int u = 0; u < 2 * GW; ++u) xv[u] = e[u].wt ? x[e[u].col] : (X)0;
+    lap_words<GW>(cp, k0 + GW, nw, w);
 #pragma unroll
-  for (int u = 0; u < G; ++u) {
-    xv[u] = x[colw_col(w[u])];
-    yv[u] = y[colw_col(w[u])];
+    for (int u = 0; u < 2 * GW; ++u) acc = e[u].wt ? lap_fma((X)e[u].wt, xi - xv[u], acc) : acc;
   }
-#pragma unroll
-  for (int u = 0; u < G; ++u) {
-    const X wt = (X)colw_wt(w[u]);
-    ax += colw_wt(w[u]) ? wt * (xi - xv[u]) : (X)0;
-    ay += colw_wt(w[u]) ? wt * (yi - yv[u]) : (X)0;
-  }
+  return acc;
 }
 
 template <typename X>
-__device__ inline void lap_row2(const int64_t *__restrict__ chunk_ptr,
-                                const uint32_t *__restrict__ cols, const X *__restrict__ x,
+__device__ inline X lap_row(const SellRef &m, const X *__restrict__ x, int64_t row, X xi) {
+  constexpr int G = sizeof(X) == 8 ? kSlotGroup / 2 : kSlotGroup;
+  const int64_t c = row >> 6;
+  const int lane = (int)(row & 63);
+  const int64_t p = m.chunk_ptr[c];
+  const int width = (int)((m.chunk_ptr[c + 1] - p) >> 6);
+  const int4 mb = m.meta[c];
+  if (mb.x != kPlainSlice)
+    return lap_row_packed<X, G / 2>(m.pk + packed_slice_word(p, c) + lane, (width + 1) >> 1, mb,
+                                    (int32_t)row, x, xi);
+  return lap_row_plain<X, G>(m.cols + p + lane, width, x, xi);
+}
+
+// The same row of L applied to two vectors from one read of the matrix.
+template <typename X>
+__device__ inline void lap_acc2(uint32_t wt, X xv, X yv, X xi, X yi, X &ax, X &ay) {
+  ax = wt ? lap_fma((X)wt, xi - xv, ax) : ax;
+  ay = wt ? lap_fma((X)wt, yi - yv, ay) : ay;
+}
+
+template <typename X>
+__device__ inline void lap_row2(const SellRef &m, const X *__restrict__ x,
                                 const X *__restrict__ y, int64_t row, X xi, X yi, X &ax, X &ay) {
-  // 8 slots at a time: 8 words and 16 gathers in flight
   constexpr int G = kSlotGroup / 2;
   const int64_t c = row >> 6;
   const int lane = (int)(row & 63);
-  const int64_t p = chunk_ptr[c];
-  const int width = (int)((chunk_ptr[c + 1] - p) >> 6);
-  const uint32_t *cp = cols + p + lane;
+  const int64_t p = m.chunk_ptr[c];
+  const int width = (int)((m.chunk_ptr[c + 1] - p) >> 6);
+  const int4 mb = m.meta[c];
   ax = 0;
   ay = 0;
-  int k0 = 0;
-  for (; k0 + 4 < width; k0 += G) lap_slots2<G>(cp, x, y, k0, width, xi, yi, ax, ay);
-  if (k0 < width) lap_slots2<4>(cp, x, y, k0, width, xi, yi, ax, ay);
+  if (mb.x != kPlainSlice) {
+    constexpr int GW = G / 2;
+    const uint32_t *cp = m.pk + packed_slice_word(p, c) + lane;
+    const int nw = (width + 1) >> 1;
+    uint32_t w[GW];
+    lap_words<GW>(cp, 0, nw, w);
+    for (int k0 = 0; k0 < nw; k0 += GW) {
+      X xv[2 * GW], yv[2 * GW];
+      PkEntry e[2 * GW];
+#pragma unroll
+      for (int u = 0; u < GW; ++u) {
+        e[2 * u] = pk_entry(w[u] & 0xffffu, (int32_t)row, mb);
+        e[2 * u + 1] = pk_entry(w[u] >> 16, (int32_t)row, mb);
+      }
+#pragma unroll
+      for (int u = 0; u < 2 * GW; ++u) {
+        xv[u] = e[u].wt ? x[e[u].col] : (X)0;
+        yv[u] = e[u].wt ? y[e[u].col] : (X)0;
+      }
+      lap_words<GW>(cp, k0 + GW, nw, w);
+#pragma unroll
+      for (int u = 0; u < 2 * GW; ++u) lap_acc2(e[u].wt, xv[u], yv[u], xi, yi, ax, ay);
+    }
+    return;
+  }
+  const uint32_t *cp = m.cols + p + lane;
+  uint32_t w[G];
+  lap_words<G>(cp, 0, width, w);
+  for (int k0 = 0; k0 < width; k0 += G) {
+    X xv[G], yv[G];
+    uint32_t wc[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      wc[u] = w[u];
+      xv[u] = colw_wt(wc[u]) ? x[colw_col(wc[u])] : (X)0;
+      yv[u] = colw_wt(wc[u]) ? y[colw_col(wc[u])] : (X)0;
+    }
+    lap_words<G>(cp, k0 + G, width, w);
+#pragma unroll
+    for (int u = 0; u < G; ++u) lap_acc2(colw_wt(wc[u]), xv[u], yv[u], xi, yi, ax, ay);
+  }
 }
 
 // Gather-scatter row (Sec. 5): (L x)_e = deg_e x_e - sum of U over the row's
