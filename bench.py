@@ -286,6 +286,9 @@ def main():
                     help="store rows in Cuthill-McKee order before the first level")
     ap.add_argument("--gather-scatter", type=int, default=0, choices=[0, 1],
                     help="Lanczos SpMV in the gather-scatter form instead of the sliced ELL")
+    ap.add_argument("--pack-matrix", type=int, default=1, choices=[0, 1, 2],
+                    help="0: sliced-ELL words; 1: packed slices; 2: packed slices and "
+                         "LDS-staged gathers")
     ap.add_argument("--precond", default="none", choices=["none", "amg"],
                     help="inverse_cg: plain CG or aggregation-multigrid preconditioned CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -345,7 +348,8 @@ def main():
                 fiedler_sweep=args.sweep, warm_start=args.warm_start, reorder=args.reorder,
                 gather_scatter=args.gather_scatter, second_solve=args.second_solve,
                 batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
-                autotune=args.autotune, lanczos_s=args.lanczos_s)
+                autotune=args.autotune, lanczos_s=args.lanczos_s,
+                pack_matrix=args.pack_matrix)
     if args.autotune_cache:
         opts["autotune_cache"] = args.autotune_cache
 
@@ -418,6 +422,7 @@ def main():
                    "method": args.method, "precond": args.precond, "fiedler_sweep": args.sweep,
                    "warm_start": bool(args.warm_start), "reorder": bool(args.reorder),
                    "gather_scatter": bool(args.gather_scatter),
+                   "pack_matrix": args.pack_matrix,
                    "second_solve": bool(args.second_solve),
                    "batched": not args.unbatched},
         "time_to_partition_ms": dt * 1e3 / args.steps,

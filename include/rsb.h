@@ -193,9 +193,13 @@ typedef struct rsb_opts {
                                row (column - row) fit in at most 4 windows of 1024:
                                16-bit entries (weight, window, offset) instead of
                                32-bit words, read by the Lanczos and CG SpMVs; the
-                               other slices are read as 32-bit words.  The same
-                               entries in the same order, so results are bitwise
-                               those of 0 = 32-bit words only. */
+                               other slices are read as 32-bit words.  2 = also, per
+                               workgroup tile of the Lanczos SpMVs, the intervals of
+                               the vector that its packed slices reach (up to 6
+                               intervals, 4864 values) are copied into LDS first and
+                               the neighbours gathered there.  The same entries in
+                               the same order and the same values, so results are
+                               bitwise those of 0 = 32-bit words only. */
 } rsb_opts;
 
 typedef struct rsb_stats {
@@ -256,6 +260,8 @@ typedef struct rsb_stats {
   double matrix_bytes;       /* the matrix as the SpMV reads it: 4 per nonzero of a
                                 32-bit slice, 2 per nonzero of a packed slice plus 16
                                 per packed slice (window bases) */
+  double staged_fraction;    /* tiles (workgroups of the streaming kernels) whose
+                                gathers are staged in LDS / tiles */
 } rsb_stats;
 
 /* Fills *o with the defaults listed above.  Returns RSB_OK or RSB_EINVAL (o NULL). */

@@ -59,7 +59,7 @@ class Stats(C.Structure):
         ("sweeps", C.c_int32), ("sweep_moved", C.c_int32), ("fallbacks", C.c_int32),
         ("reserved", C.c_int32), ("ms_reorder", C.c_double), ("spmv_alone_us", C.c_double),
         ("spmv_alone_bytes", C.c_double), ("packed_fraction", C.c_double),
-        ("matrix_bytes", C.c_double),
+        ("matrix_bytes", C.c_double), ("staged_fraction", C.c_double),
     ]
 
     def as_dict(self):

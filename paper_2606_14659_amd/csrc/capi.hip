@@ -106,7 +106,7 @@ void check_opts(const rsb_opts *o) {
   if (o->second_solve && o->fiedler_sweep < 1)
     fail(RSB_EINVAL, "second_solve needs fiedler_sweep > 0");
   if (o->lanczos_s != 1 && o->lanczos_s != 2) fail(RSB_EINVAL, "lanczos_s must be 1 or 2");
-  if (o->pack_matrix != 0 && o->pack_matrix != 1) fail(RSB_EINVAL, "pack_matrix must be 0 or 1");
+  if (o->pack_matrix < 0 || o->pack_matrix > 2) fail(RSB_EINVAL, "pack_matrix must be 0, 1 or 2");
   if (o->gather_scatter != 0 && o->gather_scatter != 1)
     fail(RSB_EINVAL, "gather_scatter must be 0 or 1");
   if (o->gather_scatter && (o->graph != RSB_GRAPH_WEIGHTED || o->method == RSB_INVERSE_CG))
@@ -131,7 +131,7 @@ void setup_ctx(Ctx &ctx, const rsb_opts &o, bool private_stream = true) {
   }
   ctx.limit = o.device_mem_limit;
   ctx.verbose = o.verbose;
-  ctx.pack = o.pack_matrix != 0;
+  ctx.pack = o.pack_matrix;
   if (const char *env = std::getenv("RSB_LOG"))
     if (std::string(env) == "level") ctx.verbose = std::max(ctx.verbose, 1);
   if (const char *env = std::getenv("RSB_FAULT_INJECT")) {
@@ -426,6 +426,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
       st.tile_rows = kBlock * L->rpt;
       st.packed_fraction = L->nnz > 0 ? (double)L->packed_nnz / (double)L->nnz : 0.0;
       st.matrix_bytes = matrix_bytes(view_of(*L));
+      st.staged_fraction = L->nblk > 0 ? (double)L->staged_tiles / (double)L->nblk : 0.0;
     }
     if (level == 0 && o.profile && o.method != RSB_INVERSE_CG && !o.gather_scatter) {
       // the level-0 Laplacian SpMV on its own, in the Lanczos directions'

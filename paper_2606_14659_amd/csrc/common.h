@@ -141,7 +141,8 @@ struct Ctx {
   int verbose = 0;
   std::vector<std::string> tuned;  // tile classes timed during this call
   int64_t fp64_level_steps = 0;    // mixed precision: level steps continued with FP64 directions
-  bool pack = true;                // levels keep a packed copy of the slices that fit
+  int pack = 1;  // 0: 32-bit words only; 1: packed copy of the slices that fit; 2: and
+                 // their tiles' gathers staged in LDS
   Arena *arena = nullptr;          // non-null: device scratch comes from this region only
   FaultPlan fault;
   Ctx() = default;
@@ -248,6 +249,20 @@ constexpr int32_t kPlainSlice = INT32_MIN;
 __host__ __device__ inline int64_t packed_slice_word(int64_t chunk_word, int64_t chunk) {
   return (chunk_word + 64 * chunk) >> 1;
 }
+
+// Gathers staged in LDS: a tile's launch first copies the intervals of the
+// gathered vector that its packed slices reach (at most kStageMaxInt of them,
+// kStageCap values together) into LDS; the rows then read their neighbours
+// there.  Filled per tile layout (rows per thread) at its first slice.
+constexpr int kStageMaxInt = 6;
+constexpr int kStageCap = 4864;
+constexpr int kStageGap = 64;  // ranges closer than this share an interval
+
+struct TileStage {
+  int32_t nint;   // intervals; 0 = the tile reads its neighbours from global memory
+  int32_t total;  // values staged
+  int32_t lo[kStageMaxInt], len[kStageMaxInt], off[kStageMaxInt];
+};
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

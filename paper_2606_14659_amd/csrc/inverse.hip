@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_inv_res(InvArgs a) {
     const int64_t row = tr.row[r];
     const double xi = a.X[row];
     const double y = (xi - c * a.U0[row]) * sc;
-    const double ly = sc * lap_row<double>(SellRef{a.chunk_ptr, a.cols, a.pk, a.meta}, a.X, row, xi);
+    const double ly = sc * lap_row<double>(SellRef{a.chunk_ptr, a.cols, a.pk, a.meta, nullptr, nullptr}, a.X, row, xi);
     const double rr = ly - th * y;
     if (tr.ok[r]) {
       p[0] += rr * rr;

@@ -190,8 +190,12 @@ struct Level {
   int64_t nnz = 0;             // off-diagonal nonzeros (non-padding words)
   DevBuf<uint32_t> pk;         // packed copy of the slices that fit (16-bit entries)
   DevBuf<int4> pmeta;          // [nchunks] window bases, or kPlainSlice
+  DevBuf<int4> crlo, crhi;     // [nchunks] least / greatest column of each window
+  DevBuf<TileStage> stage;     // [nchunks] at each tile's first slice (current tiles)
+  DevBuf<int4> lmeta;          // [nchunks] LDS bases of the windows (current tiles)
   int64_t packed_slices = 0;   // slices read in the packed form
   int64_t packed_nnz = 0;      // nonzeros in those slices
+  int64_t staged_tiles = 0;    // current tiles whose gathers are staged in LDS
   GsLevel gs;                  // gather-scatter operator, when selected
 };
 
@@ -207,6 +211,8 @@ struct LevelView {
   const uint32_t *cols = nullptr;
   const uint32_t *pk = nullptr;
   const int4 *pmeta = nullptr;
+  const TileStage *stage = nullptr;
+  const int4 *lmeta = nullptr;
   const int32_t *gid = nullptr;
   const int32_t *orig = nullptr;
   int64_t nnz = 0;
@@ -240,6 +246,8 @@ inline LevelView view_of(const Level &L) {
   v.cols = L.cols.get();
   v.pk = L.pk.get();
   v.pmeta = L.pmeta.get();
+  v.stage = L.stage.get();
+  v.lmeta = L.lmeta.get();
   v.nchunks = L.nchunks;
   v.packed_slices = L.packed_slices;
   v.packed_nnz = L.packed_nnz;

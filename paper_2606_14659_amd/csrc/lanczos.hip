@@ -76,6 +76,8 @@ struct LzArgs {
   const uint32_t *cols;
   const uint32_t *pk;  // packed slices (see SellRef)
   const int4 *meta;
+  const TileStage *stage;  // LDS staging of the current tiles (null: none)
+  const int4 *lmeta;
   const int32_t *root;
   const int32_t *gid;
   double *U0;    // u0 (ones vector of the cut component, normalised)
@@ -104,7 +106,7 @@ struct LzArgs {
   const int32_t *orig;     // row -> element index of the whole call (-1: padding)
   const double *warm;      // warm start by element (NaN: none), or null
   GsView gs;               // gather-scatter operator (gs.nv > 0) instead of the sliced ELL
-  __device__ SellRef sell() const { return {chunk_ptr, cols, pk, meta}; }
+  __device__ SellRef sell() const { return {chunk_ptr, cols, pk, meta, stage, lmeta}; }
 };
 
 // Vector types of step j: STEP 1 reads Y and works in FP64; STEP 2 reads the
@@ -361,6 +363,10 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
   constexpr int RT = TILE / NT;  // rows per thread
   constexpr int NW = NT / kWave;
   constexpr int NSL = TILE / kWave;
+  // LDS: the step input staged for the SpMV (FP32 steps j >= 3 of a staged
+  // tile), L q_j, q_j and the partial sums of the projection
+  constexpr int kStageN = (STEP == 3 && MODE == 0 && sizeof(Tin) == 4) ? kStageCap : 1;
+  __shared__ Tin xs[kStageN];
   __shared__ double zs[TILE];
   __shared__ double qs[MODE == 0 ? TILE : 1];
   __shared__ double vals[2 * kMaxM + 8];
@@ -374,6 +380,12 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
   Tw *Wout = step_out<T, STEP>(a, j);
   const double c = S.c, sc = S.s;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const SellRef m = a.sell();
+  const bool staged = kStageN > 1 && a.gs.nv == 0 && tile_staged(m, b.row0);
+  if (staged) {
+    stage_copy(m, b.row0, Win, xs, (int)threadIdx.x, NT);
+    __syncthreads();
+  }
   int64_t rows[RT];
   bool oks[RT];
 #pragma unroll
@@ -390,7 +402,9 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
     if (MODE == 0) {
       const Tin wi = Win[row];
       const double qd = ((double)wi - c * a.U0[row]) * sc;
-      const Tin lw = a.gs.nv ? gs_row<Tin>(a.gs, row, wi) : lap_row<Tin>(a.sell(), Win, row, wi);
+      const Tin lw = a.gs.nv ? gs_row<Tin>(a.gs, row, wi)
+                     : staged ? lap_row<Tin, true>(m, Win, xs, row, wi)
+                              : lap_row<Tin, false>(m, Win, nullptr, row, wi);
       const Tw lq = (Tw)(sc * (double)lw);
       if (STEP == 1) {
         q = qd;
@@ -772,6 +786,16 @@ __device__ inline void wave_dot4(const P *__restrict__ v, const SZ *z1, const SZ
   }
 }
 
+// LDS of the B launch: z1 staged for the SpMV (a staged tile), then the four
+// vectors of the projection and its partial sums.
+template <typename T, int TILE>
+constexpr size_t pb_lds_bytes() {
+  constexpr size_t stage = (size_t)kStageCap * sizeof(double);
+  constexpr size_t proj = (size_t)TILE * (2 * sizeof(double) + 2 * sizeof(T)) +
+                          (4 * kMaxM + 8) * sizeof(double);
+  return stage > proj ? stage : proj;
+}
+
 template <typename T, int RPT>
 __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_per_eu(RPT <= 4 ? 6 : 4))) void k_lz_pb(LzArgs<T> a, int j) {
   constexpr int NT = proj_threads<RPT>();
@@ -779,15 +803,26 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
   constexpr int RT = TILE / NT;
   constexpr int NW = NT / kWave;
   constexpr int NSL = TILE / kWave;
-  __shared__ double z1s[TILE], z2s[TILE];
-  __shared__ T qjs[TILE], qis[TILE];
-  __shared__ double vals[4 * kMaxM + 8];
+  __shared__ __align__(16) char smem[pb_lds_bytes<T, TILE>()];
+  double *xs = reinterpret_cast<double *>(smem);
+  double *z1s = reinterpret_cast<double *>(smem);
+  double *z2s = z1s + TILE;
+  T *qjs = reinterpret_cast<T *>(z2s + TILE);
+  T *qis = qjs + TILE;
+  double *vals = reinterpret_cast<double *>(qis + TILE);
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
   if (!pair_step(S, j)) return;
   const bool two = j < a.m;
   const bool pend2 = S.pair == 1;
+  const SellRef m = a.sell();
+  const bool staged = two && tile_staged(m, b.row0);
+  if (staged) {
+    stage_copy(m, b.row0, a.Z1, xs, (int)threadIdx.x, NT);
+    __syncthreads();
+  }
+  double z1v[RT], z2v[RT];
 #pragma unroll
   for (int r = 0; r < RT; ++r) {
     const int lr = r * NT + (int)threadIdx.x;
@@ -796,11 +831,21 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
     const double z1 = a.Z1[row];
     double z2 = 0.0;
     if (two) {
-      z2 = lap_row<double>(a.sell(), a.Z1, row, z1);
+      z2 = staged ? lap_row<double, true>(m, a.Z1, xs, row, z1)
+                  : lap_row<double, false>(m, a.Z1, nullptr, row, z1);
       if (ok) a.Z2[row] = z2;
     }
-    z1s[lr] = ok ? z1 : 0.0;
-    z2s[lr] = ok ? z2 : 0.0;
+    z1v[r] = ok ? z1 : 0.0;
+    z2v[r] = ok ? z2 : 0.0;
+  }
+  if (staged) __syncthreads();  // the staged z1 is overwritten below
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int lr = r * NT + (int)threadIdx.x;
+    const bool ok = lr < b.nrows;
+    const int64_t row = b.row0 + (ok ? lr : 0);
+    z1s[lr] = z1v[r];
+    z2s[lr] = z2v[r];
     qjs[lr] = ok ? a.V[(int64_t)j * a.vs + row] : (T)0;
     qis[lr] = (ok && pend2) ? a.V[(int64_t)(j - 1) * a.vs + row] : (T)0;
   }
@@ -2124,6 +2169,8 @@ LzArgs<T> level_args(const LevelView &L, CompDev &C, SolveDev &S, const LanczosP
   a.cols = L.cols;
   a.pk = L.pk;
   a.meta = L.pmeta;
+  a.stage = L.stage;
+  a.lmeta = L.lmeta;
   a.root = C.root.get();
   a.gid = L.gid;
   a.orig = L.orig;
@@ -2288,6 +2335,8 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
   a.cols = L.cols;
   a.pk = L.pk;
   a.meta = L.pmeta;
+  a.stage = L.stage;
+  a.lmeta = L.lmeta;
   a.gs = L.gs;
   double *wd = (double *)work;
   a.U0 = wd;

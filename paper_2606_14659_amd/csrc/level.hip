@@ -746,24 +746,38 @@ __global__ void k_row_part_offset(const int32_t *__restrict__ orig, const SegDev
 // one wavefront per slice.  The window bases cover the slice's deltas
 // (column - row) greedily from the least one (each base is the least delta
 // the windows before it leave uncovered), which needs the fewest windows; a
-// slice that needs more than kPackClusters keeps only its 32-bit words.
+// slice that needs more than kPackClusters keeps only its 32-bit words.  The
+// exact column range of each window (least and greatest column, over the
+// slice's rows) goes to crlo / crhi for the staging of tiles.
 __device__ inline int32_t wave_min_i32(int32_t v) {
   for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
   return v;
 }
+__device__ inline int32_t wave_max_i32(int32_t v) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+  return v;
+}
 
-__global__ __launch_bounds__(kBlock) void k_pack_slices(const int64_t *__restrict__ chunk_ptr,
-                                                       const uint32_t *__restrict__ cols,
-                                                       int64_t nchunks, uint32_t *__restrict__ pk,
-                                                       int4 *__restrict__ meta,
-                                                       unsigned long long *__restrict__ cnt) {
-  const int64_t c = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  if (c >= nchunks) return;  // the whole wavefront
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t p = chunk_ptr[c];
-  const int width = (int)((chunk_ptr[c + 1] - p) >> 6);
-  const int32_t row = (int32_t)(c * kWave + lane);
-  const uint32_t *cp = cols + p + lane;
+constexpr int kPackRegSlots = 32;  // slots a row keeps in registers while packing
+
+template <bool REG>
+__device__ inline uint32_t pack_word(const uint32_t *cp, const uint32_t (&wr)[kPackRegSlots], int k) {
+  if (REG) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int u = 0; u < kPackRegSlots; ++u) w = (u == k) ? wr[u] : w;
+    return w;
+  }
+  return cp[(int64_t)k * kWave];
+}
+
+// Returns the slice's nonzeros when it is packed, -1 when it stays in words.
+template <bool REG>
+__device__ int pack_one_slice(const uint32_t *cp, int width, int32_t row, int lane,
+                              uint32_t *out, int4 *meta, int4 *crlo, int4 *crhi, int64_t c) {
+  uint32_t wr[kPackRegSlots];
+#pragma unroll
+  for (int u = 0; u < kPackRegSlots; ++u) wr[u] = (REG && u < width) ? cp[(int64_t)u * kWave] : 0u;
   int32_t b[kPackClusters] = {0, 0, 0, 0};
   int nb = 0;
   bool fits = true;
@@ -771,7 +785,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_slices(const int64_t *__restric
   for (;;) {
     int32_t mn = INT32_MAX;
     for (int k = 0; k < width; ++k) {
-      const uint32_t w = cp[(int64_t)k * kWave];
+      const uint32_t w = pack_word<REG>(cp, wr, k);
       const int32_t d = (int32_t)colw_col(w) - row;
       if (colw_wt(w) && d > covered && d < mn) mn = d;
     }
@@ -787,39 +801,201 @@ __global__ __launch_bounds__(kBlock) void k_pack_slices(const int64_t *__restric
     covered = mn + ((1 << kPackOffBits) - 1);
   }
   if (!fits) {
-    if (lane == 0) meta[c] = make_int4(kPlainSlice, 0, 0, 0);
-    return;
+    if (lane == 0) {
+      meta[c] = make_int4(kPlainSlice, 0, 0, 0);
+      crlo[c] = make_int4(INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX);
+      crhi[c] = make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
+    }
+    return -1;
   }
-  uint32_t *out = pk + packed_slice_word(p, c) + lane;
+  int32_t lo[kPackClusters] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+  int32_t hi[kPackClusters] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
   int nz = 0;
   for (int q = 0; 2 * q < width; ++q) {
     uint32_t h[2] = {0u, 0u};
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int k = 2 * q + t;
-      const uint32_t w = k < width ? cp[(int64_t)k * kWave] : 0u;
+      const uint32_t w = k < width ? pack_word<REG>(cp, wr, k) : 0u;
       if (colw_wt(w)) {
-        const int32_t d = (int32_t)colw_col(w) - row;
+        const int32_t col = (int32_t)colw_col(w);
+        const int32_t d = col - row;
         // window: the last base <= d (bases ascending, unused ones never match)
         const int i = (nb > 1 && d >= b[1]) + (nb > 2 && d >= b[2]) + (nb > 3 && d >= b[3]);
         const int32_t base = i == 0 ? b[0] : i == 1 ? b[1] : i == 2 ? b[2] : b[3];
         h[t] = (colw_wt(w) << 12) | ((uint32_t)i << kPackOffBits) | (uint32_t)(d - base);
+#pragma unroll
+        for (int u = 0; u < kPackClusters; ++u) {
+          lo[u] = (u == i) ? min(lo[u], col) : lo[u];
+          hi[u] = (u == i) ? max(hi[u], col) : hi[u];
+        }
         ++nz;
       }
     }
     out[(int64_t)q * kWave] = h[0] | (h[1] << 16);
   }
+#pragma unroll
+  for (int u = 0; u < kPackClusters; ++u) {
+    lo[u] = wave_min_i32(lo[u]);
+    hi[u] = wave_max_i32(hi[u]);
+  }
   nz = wave_sum_i(nz);
   if (lane == 0) {
     meta[c] = make_int4(b[0], b[1], b[2], b[3]);
-    atomicAdd(&cnt[0], (unsigned long long)nz);
-    atomicAdd(&cnt[1], 1ull);
+    crlo[c] = make_int4(lo[0], lo[1], lo[2], lo[3]);
+    crhi[c] = make_int4(hi[0], hi[1], hi[2], hi[3]);
+  }
+  return nz;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_slices(const int64_t *__restrict__ chunk_ptr,
+                                                       const uint32_t *__restrict__ cols,
+                                                       int64_t nchunks, uint32_t *__restrict__ pk,
+                                                       int4 *__restrict__ meta,
+                                                       int4 *__restrict__ crlo,
+                                                       int4 *__restrict__ crhi,
+                                                       unsigned long long *__restrict__ cnt) {
+  // slices strided over the grid's wavefronts; the counts summed per block
+  // (one pair of atomics per block)
+  __shared__ unsigned long long red[2][kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+  unsigned long long nz = 0, ns = 0;
+  for (int64_t c = (int64_t)blockIdx.x * (kBlock / kWave) + wave; c < nchunks; c += nwaves) {
+    const int64_t p = chunk_ptr[c];
+    const int width = (int)((chunk_ptr[c + 1] - p) >> 6);
+    const int32_t row = (int32_t)(c * kWave + lane);
+    const uint32_t *cp = cols + p + lane;
+    uint32_t *out = pk + packed_slice_word(p, c) + lane;
+    const int r = width <= kPackRegSlots
+                      ? pack_one_slice<true>(cp, width, row, lane, out, meta, crlo, crhi, c)
+                      : pack_one_slice<false>(cp, width, row, lane, out, meta, crlo, crhi, c);
+    if (r >= 0) {
+      nz += (unsigned long long)r;
+      ns += 1;
+    }
+  }
+  if (lane == 0) {
+    red[0][wave] = nz;
+    red[1][wave] = ns;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) {
+      nz += red[0][w];
+      ns += red[1][w];
+    }
+    atomicAdd(&cnt[0], nz);
+    atomicAdd(&cnt[1], ns);
   }
 }
 
 __global__ void k_meta_plain(int4 *meta, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) meta[i] = make_int4(kPlainSlice, 0, 0, 0);
+}
+
+// Staging of a tile's gathers (one wavefront per tile): the column ranges of
+// the windows of its packed slices, merged where they overlap or lie within
+// kStageGap of each other, become at most kStageMaxInt intervals of the
+// vector that the tile's launch copies into LDS (at most kStageCap values
+// together); lmeta then holds, per slice and window, the base that turns a
+// packed entry into an LDS index (interval offset - interval start + window
+// base).  A tile whose ranges need more is not staged (nint = 0).
+__global__ __launch_bounds__(kBlock) void k_stage_tiles(const BlkDev *__restrict__ blk, int nblk,
+                                                       const int4 *__restrict__ meta,
+                                                       const int4 *__restrict__ crlo,
+                                                       const int4 *__restrict__ crhi,
+                                                       TileStage *__restrict__ stage,
+                                                       int4 *__restrict__ lmeta,
+                                                       unsigned *__restrict__ nstaged) {
+  const int t = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (t >= nblk) return;  // the whole wavefront
+  const int lane = threadIdx.x & (kWave - 1);
+  const BlkDev bk = blk[t];
+  const int64_t c0 = bk.row0 >> 6;
+  const int ns = bk.nrows >> 6;
+  // range r = 4 (slice) + window; a lane holds ranges lane + 64 i
+  constexpr int kR = 4;  // ranges per lane: tiles of up to 64 slices
+  int32_t rlo[kR], rhi[kR], rk[kR];
+#pragma unroll
+  for (int i = 0; i < kR; ++i) {
+    const int r = lane + kWave * i;
+    rlo[i] = INT32_MAX;
+    rhi[i] = INT32_MIN;
+    rk[i] = -1;
+    if (r < 4 * ns) {
+      const int64_t c = c0 + (r >> 2);
+      const int4 lo = crlo[c], hi = crhi[c];
+      const int u = r & 3;
+      rlo[i] = u == 0 ? lo.x : u == 1 ? lo.y : u == 2 ? lo.z : lo.w;
+      rhi[i] = u == 0 ? hi.x : u == 1 ? hi.y : u == 2 ? hi.z : hi.w;
+      if (rlo[i] > rhi[i]) rk[i] = kStageMaxInt;  // empty (or a slice in words)
+    } else {
+      rk[i] = kStageMaxInt;
+    }
+  }
+  TileStage ts{};
+  int32_t off = 0;
+  bool ok = ns <= kR * kWave / 4;
+  for (int k = 0; ok; ++k) {
+    int32_t lo = INT32_MAX;
+#pragma unroll
+    for (int i = 0; i < kR; ++i) lo = (rk[i] < 0) ? min(lo, rlo[i]) : lo;
+    lo = wave_min_i32(lo);
+    if (lo == INT32_MAX) break;  // every range placed
+    if (k == kStageMaxInt) {
+      ok = false;
+      break;
+    }
+    int32_t hi = lo;
+    for (;;) {
+      int32_t h = hi;
+#pragma unroll
+      for (int i = 0; i < kR; ++i)
+        h = (rk[i] < 0 && rlo[i] <= hi + kStageGap) ? max(h, rhi[i]) : h;
+      h = wave_max_i32(h);
+      if (h == hi) break;
+      hi = h;
+    }
+#pragma unroll
+    for (int i = 0; i < kR; ++i) rk[i] = (rk[i] < 0 && rlo[i] <= hi + kStageGap) ? k : rk[i];
+    ts.lo[k] = lo;
+    ts.len[k] = hi - lo + 1;
+    ts.off[k] = off;
+    off += hi - lo + 1;
+    ts.nint = k + 1;
+    if (off > kStageCap) ok = false;
+  }
+  ts.total = off;
+  if (!ok) ts.nint = 0;
+  if (lane == 0) {
+    stage[c0] = ts;
+    if (ts.nint > 0) atomicAdd(nstaged, 1u);
+  }
+  // the LDS bases of the tile's packed slices
+#pragma unroll
+  for (int i = 0; i < kR; ++i) {
+    const int r = lane + kWave * i;
+    if (r < 4 * ns) {
+      const int64_t c = c0 + (r >> 2);
+      const int u = r & 3;
+      const int4 mb = meta[c];
+      const int32_t base = u == 0 ? mb.x : u == 1 ? mb.y : u == 2 ? mb.z : mb.w;
+      int32_t v = 0;
+      if (ts.nint > 0 && rk[i] >= 0 && rk[i] < kStageMaxInt) {
+        int32_t klo = 0, koff = 0;
+#pragma unroll
+        for (int k = 0; k < kStageMaxInt; ++k)
+          if (k == rk[i]) {
+            klo = ts.lo[k];
+            koff = ts.off[k];
+          }
+        v = base + koff - klo;
+      }
+      reinterpret_cast<int32_t *>(lmeta)[4 * c + u] = v;
+    }
+  }
 }
 
 }  // namespace
@@ -831,23 +1007,49 @@ void pack_level(Level &L, Ctx &ctx) {
   L.pmeta.alloc(ctx, std::max<int64_t>(L.nchunks, 1));
   L.packed_slices = L.packed_nnz = 0;
   if (L.nchunks == 0) return;
-  if (!ctx.pack) {
+  if (ctx.pack == 0) {
     k_meta_plain<<<grid_for(L.nchunks, kBlock), kBlock, 0, ctx.stream>>>(L.pmeta.get(), L.nchunks);
     RSB_LAUNCHED();
     return;
   }
   L.pk.alloc(ctx, std::max<int64_t>(packed_slice_word(L.words, L.nchunks), 1));
+  L.crlo.alloc(ctx, L.nchunks);
+  L.crhi.alloc(ctx, L.nchunks);
   DevBuf<unsigned long long> cnt(ctx, 2);
   RSB_HIP(hipMemsetAsync(cnt.get(), 0, 2 * sizeof(unsigned long long), ctx.stream));
   const int64_t per = kBlock / kWave;
-  k_pack_slices<<<(unsigned)((L.nchunks + per - 1) / per), kBlock, 0, ctx.stream>>>(
-      L.chunk_ptr.get(), L.cols.get(), L.nchunks, L.pk.get(), L.pmeta.get(), cnt.get());
+  const unsigned grid = (unsigned)std::min<int64_t>((L.nchunks + per - 1) / per, 2048);
+  k_pack_slices<<<grid, kBlock, 0, ctx.stream>>>(
+      L.chunk_ptr.get(), L.cols.get(), L.nchunks, L.pk.get(), L.pmeta.get(), L.crlo.get(),
+      L.crhi.get(), cnt.get());
   RSB_LAUNCHED();
   unsigned long long h[2] = {0, 0};
   RSB_HIP(hipMemcpyAsync(h, cnt.get(), sizeof(h), hipMemcpyDeviceToHost, ctx.stream));
   RSB_HIP(hipStreamSynchronize(ctx.stream));
   L.packed_nnz = (int64_t)h[0];
   L.packed_slices = (int64_t)h[1];
+}
+
+// The staging tables of the level's current tiles (levels with a packed
+// copy only; other tiles are never staged).
+void stage_tiles(Level &L, Ctx &ctx) {
+  if (L.nchunks == 0 || L.crlo.get() == nullptr || L.blk.empty()) return;
+  L.stage.alloc(ctx, L.nchunks);
+  L.lmeta.alloc(ctx, L.nchunks);
+  RSB_HIP(hipMemsetAsync(L.stage.get(), 0, L.nchunks * sizeof(TileStage), ctx.stream));
+  L.staged_tiles = 0;
+  if (ctx.pack < 2) return;
+  DevBuf<unsigned> cnt(ctx, 1);
+  RSB_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(unsigned), ctx.stream));
+  const int per = kBlock / kWave;
+  k_stage_tiles<<<(unsigned)((L.nblk + per - 1) / per), kBlock, 0, ctx.stream>>>(
+      L.d_blk.get(), L.nblk, L.pmeta.get(), L.crlo.get(), L.crhi.get(), L.stage.get(),
+      L.lmeta.get(), cnt.get());
+  RSB_LAUNCHED();
+  unsigned h = 0;
+  RSB_HIP(hipMemcpyAsync(&h, cnt.get(), sizeof(unsigned), hipMemcpyDeviceToHost, ctx.stream));
+  RSB_HIP(hipStreamSynchronize(ctx.stream));
+  L.staged_tiles = (int64_t)h;
 }
 
 void level_tables(Level &L, int rpt, Ctx &ctx) {
@@ -894,6 +1096,7 @@ void level_tables(Level &L, int rpt, Ctx &ctx) {
                          hipMemcpyHostToDevice, ctx.stream));
   RSB_HIP(hipMemcpyAsync(L.d_grp.get(), L.grp.data(), L.grp.size() * sizeof(GrpDev),
                          hipMemcpyHostToDevice, ctx.stream));
+  stage_tiles(L, ctx);
   // the host vectors must stay alive until the copies ran
   RSB_HIP(hipStreamSynchronize(ctx.stream));
 }

@@ -74,19 +74,27 @@ __global__ void k_fill_f32(float *p, int64_t n, float v) {
     p[i] = v;
 }
 
-// y = L x on the level's sliced ELL (difference form; packed slices where
-// the level has them), one row per thread slot, tiles and block order as the
-// Lanczos kernels use them.
+// y = L x on the level's sliced ELL (difference form; packed slices and
+// their tiles' staged gathers where the level has them), one row per thread
+// slot, tiles and block order as the Lanczos kernels use them.
 template <typename T, int RPT>
 __global__ __launch_bounds__(kBlock) void k_spmv_alone(const BlkDev *__restrict__ blk, SellRef m,
                                                        const T *__restrict__ x,
                                                        T *__restrict__ y) {
+  __shared__ T xs[kStageCap];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = blk[lb];
+  const bool staged = tile_staged(m, b.row0);
+  if (staged) {
+    stage_copy(m, b.row0, x, xs, (int)threadIdx.x, kBlock);
+    __syncthreads();
+  }
   const TileRows<RPT> tr(b);
   T v[RPT];
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) v[r] = lap_row<T>(m, x, tr.row[r], x[tr.row[r]]);
+  for (int r = 0; r < RPT; ++r)
+    v[r] = staged ? lap_row<T, true>(m, x, xs, tr.row[r], x[tr.row[r]])
+                  : lap_row<T, false>(m, x, nullptr, tr.row[r], x[tr.row[r]]);
 #pragma unroll
   for (int r = 0; r < RPT; ++r)
     if (tr.ok[r]) y[tr.row[r]] = v[r];
@@ -128,7 +136,7 @@ double spmv_alone_typed(const LevelView &L, int reps, Ctx &ctx) {
   auto launch = [&](auto rpt_tag) {
     constexpr int RPT = decltype(rpt_tag)::value;
     k_spmv_alone<T, RPT><<<L.nblk, kBlock, 0, ctx.stream>>>(
-        L.blk, SellRef{L.chunk_ptr, L.cols, L.pk, L.pmeta}, x.get(), y.get());
+        L.blk, SellRef{L.chunk_ptr, L.cols, L.pk, L.pmeta, L.stage, L.lmeta}, x.get(), y.get());
   };
   auto run = [&]() {
     switch (L.rpt) {

@@ -159,7 +159,28 @@ struct SellRef {
   const uint32_t *cols;
   const uint32_t *pk;
   const int4 *meta;
+  const TileStage *stage;  // null: no tile is staged
+  const int4 *lmeta;
 };
+
+// The staging of the tile starting at row0, if it has one.
+__device__ inline bool tile_staged(const SellRef &m, int64_t row0) {
+  return m.stage != nullptr && m.stage[row0 >> 6].nint > 0;
+}
+
+// Copies the tile's intervals of x into xs (LDS); the caller synchronises.
+template <typename X>
+__device__ inline void stage_copy(const SellRef &m, int64_t row0, const X *__restrict__ x, X *xs,
+                                  int tid, int nt) {
+  const TileStage &ts = m.stage[row0 >> 6];
+  const int nint = ts.nint;
+  for (int k = 0; k < nint; ++k) {
+    const X *src = x + ts.lo[k];
+    X *dst = xs + ts.off[k];
+    const int len = ts.len[k];
+    for (int i = tid; i < len; i += nt) dst[i] = src[i];
+  }
+}
 
 // Sliced-ELL Laplacian row in difference form: sum_j w_ij (x_i - x_j),
 // accumulated in the vector type in slot order (paper Sec. 5: the action of L
@@ -238,18 +259,28 @@ __device__ inline X lap_row_packed(const uint32_t *__restrict__ cp, int nw, cons
   return acc;
 }
 
-template <typename X>
-__device__ inline X lap_row(const SellRef &m, const X *__restrict__ x, int64_t row, X xi) {
+// STAGED: the row's tile has its intervals of x in xs (LDS); a packed slice
+// then gathers there through its LDS bases, a slice in words from x.
+template <typename X, bool STAGED = false>
+__device__ inline X lap_row(const SellRef &m, const X *__restrict__ x, const X *xs, int64_t row,
+                            X xi) {
   constexpr int G = sizeof(X) == 8 ? kSlotGroup / 2 : kSlotGroup;
   const int64_t c = row >> 6;
   const int lane = (int)(row & 63);
   const int64_t p = m.chunk_ptr[c];
   const int width = (int)((m.chunk_ptr[c + 1] - p) >> 6);
   const int4 mb = m.meta[c];
-  if (mb.x != kPlainSlice)
-    return lap_row_packed<X, G / 2>(m.pk + packed_slice_word(p, c) + lane, (width + 1) >> 1, mb,
-                                    (int32_t)row, x, xi);
+  if (mb.x != kPlainSlice) {
+    const uint32_t *cp = m.pk + packed_slice_word(p, c) + lane;
+    if (STAGED) return lap_row_packed<X, G / 2>(cp, (width + 1) >> 1, m.lmeta[c], (int32_t)row, xs, xi);
+    return lap_row_packed<X, G / 2>(cp, (width + 1) >> 1, mb, (int32_t)row, x, xi);
+  }
   return lap_row_plain<X, G>(m.cols + p + lane, width, x, xi);
+}
+
+template <typename X>
+__device__ inline X lap_row(const SellRef &m, const X *__restrict__ x, int64_t row, X xi) {
+  return lap_row<X, false>(m, x, nullptr, row, xi);
 }
 
 // The same row of L applied to two vectors from one read of the matrix.
