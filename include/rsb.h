@@ -192,8 +192,9 @@ typedef struct rsb_opts {
                                the sliced-ELL slices whose column offsets from the
                                row (column - row) fit in at most 4 windows of 1024:
                                16-bit entries (weight, window, offset) instead of
-                               32-bit words, read by the Lanczos and CG SpMVs; the
-                               other slices are read as 32-bit words.  2 = also, per
+                               32-bit words, read by the Lanczos SpMVs and the
+                               inverse iteration's residual (its CG steps read the
+                               words); the other slices are read as 32-bit words.  2 = also, per
                                workgroup tile of the Lanczos SpMVs, the intervals of
                                the vector that its packed slices reach (up to 6
                                intervals, 4864 values) are copied into LDS first and
