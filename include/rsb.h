@@ -263,6 +263,10 @@ typedef struct rsb_stats {
                                 per packed slice (window bases) */
   double staged_fraction;    /* tiles (workgroups of the streaming kernels) whose
                                 gathers are staged in LDS / tiles */
+  /* opts->profile = 1: the level-0 SpMV alone as above with every slice read from
+   * its 32-bit words */
+  double spmv_words_us;      /* average launch time */
+  double spmv_words_bytes;   /* algorithmic bytes per launch: 4 (n + 1) + 4 nnz + 2 s n */
 } rsb_stats;
 
 /* Fills *o with the defaults listed above.  Returns RSB_OK or RSB_EINVAL (o NULL). */

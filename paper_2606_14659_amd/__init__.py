@@ -60,6 +60,7 @@ class Stats(C.Structure):
         ("reserved", C.c_int32), ("ms_reorder", C.c_double), ("spmv_alone_us", C.c_double),
         ("spmv_alone_bytes", C.c_double), ("packed_fraction", C.c_double),
         ("matrix_bytes", C.c_double), ("staged_fraction", C.c_double),
+        ("spmv_words_us", C.c_double), ("spmv_words_bytes", C.c_double),
     ]
 
     def as_dict(self):

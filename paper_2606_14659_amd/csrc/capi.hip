@@ -437,6 +437,8 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
       const double sv = f32 ? 4.0 : 8.0, n = (double)L->nrows;
       st.spmv_alone_us = spmv_alone_us(view_of(*L), f32, 20, ctx);
       st.spmv_alone_bytes = 4.0 * (n + 1.0) + matrix_bytes(view_of(*L)) + 2.0 * sv * n;
+      st.spmv_words_us = spmv_words_us(view_of(*L), f32, 20, ctx);
+      st.spmv_words_bytes = 4.0 * (n + 1.0) + 4.0 * (double)L->nnz + 2.0 * sv * n;
     }
     solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
     components_and_targets(*L, C, S, ctx);

@@ -27,6 +27,8 @@ NoallocRegion &noalloc_region(int device);
 struct LevelView;
 double hbm_probe_gbs(int kind, int64_t bytes, int reps, int device, Ctx &ctx);
 double spmv_alone_us(const LevelView &L, bool fp32, int reps, Ctx &ctx);
+// The same with every slice read from its 32-bit words.
+double spmv_words_us(const LevelView &L, bool fp32, int reps, Ctx &ctx);
 
 // ---------------------------------------------------------------------------
 // Plain CSR on the device (output of the dual-graph builder).

@@ -90,7 +90,8 @@ struct LzArgs {
   int64_t vs;
   T *Wt0, *Wt1;  // ping-pong work vectors of steps >= 2
   double *Z1, *Z2;  // two-step Lanczos: L q~_j and L^2 q~_j of the current pair (FP64)
-  double *Pa, *Pb;  // two-step Lanczos: the pair's block after projection, W1 and W2 (FP64)
+  double2 *Pw;      // two-step Lanczos: the pair's block after projection, (W1, W2) per
+                    // row (FP64, interleaved: the next launch gathers both at once)
   int pairs;     // 1: steps j >= 3 run two at a time (thick restart, sliced ELL)
   int m;
   double tol;
@@ -737,9 +738,10 @@ __global__ __launch_bounds__(proj_threads<RPT>()) void k_lz_pa(LzArgs<T> a, int 
     const bool ok = lr < b.nrows;
     const int64_t row = b.row0 + (ok ? lr : 0);
     if (from_pair) {
-      const double w1 = a.Pa[row], w2 = a.Pb[row];
+      const double2 wp = a.Pw[row];
+      const double w1 = wp.x, w2 = wp.y;
       double l1, l2;
-      lap_row2<double>(a.sell(), a.Pa, a.Pb, row, w1, w2, l1, l2);
+      lap_row2i(a.sell(), a.Pw, row, w1, w2, l1, l2);
       const double qa = w1 * s1;
       const double qb = w2 * s2 + w1 * s3;
       if (ok) {
@@ -955,8 +957,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_pc(LzArgs<T> a, int j) {
       T *qi = a.V + (int64_t)(j - 1) * a.vs + row;
       *qi = (T)((double)*qi - acc[3][r]);
     }
-    a.Pa[row] = w1;
-    if (two) a.Pb[row] = w2;
+    a.Pw[row] = make_double2(w1, w2);
     p[0] += w1 * w1;
     p[1] += w1 * w2;
     p[2] += w2 * w2;
@@ -993,7 +994,8 @@ __global__ __launch_bounds__(proj_threads<RPT>()) void k_lz_px1(LzArgs<T> a) {
     const int64_t row = b.row0 + (ok ? lr : 0);
     T q = (T)0;
     if (S.pair == 1) {
-      const double w1 = (double)a.Pa[row], w2 = (double)a.Pb[row];
+      const double2 wp = a.Pw[row];
+      const double w1 = wp.x, w2 = wp.y;
       const double qk = w1 / S.r00;
       q = (T)qk;
       if (ok) {
@@ -1001,7 +1003,7 @@ __global__ __launch_bounds__(proj_threads<RPT>()) void k_lz_px1(LzArgs<T> a) {
         cont[row] = (T)((w2 - S.r01 * qk) / S.r00);
       }
     } else if (ok) {
-      cont[row] = (T)a.Pa[row];
+      cont[row] = (T)a.Pw[row].x;
     }
     qs[lr] = ok ? q : (T)0;
   }
@@ -2196,8 +2198,7 @@ LzArgs<T> level_args(const LevelView &L, CompDev &C, SolveDev &S, const LanczosP
                               : a.K + (int64_t)std::max(p.keep - 1, 0) * L.nrows;
   a.Z1 = pb;
   a.Z2 = pb + L.nrows;
-  a.Pa = pb + 2 * L.nrows;
-  a.Pb = pb + 3 * L.nrows;
+  a.Pw = reinterpret_cast<double2 *>(pb + 2 * L.nrows);
   a.pairs = (p.pairs && p.keep > 0 && L.gs.nv == 0) ? 1 : 0;
   a.m = p.m;
   a.tol = p.tol;
@@ -2263,8 +2264,7 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
       d.K = d.V + 2 * L.nrows;
       d.Z1 = d.Wt1 + L.nrows;  // (T = double)
       d.Z2 = d.Z1 + L.nrows;
-      d.Pa = d.Z2 + L.nrows;
-      d.Pb = d.Pa + L.nrows;
+      d.Pw = reinterpret_cast<double2 *>(d.Z2 + L.nrows);
       dispatch_rpt<double>(L.rpt, [&](auto launcher) {
         using Lz = decltype(launcher);
         k_lz_refine_on<<<(L.nseg + kBlock - 1) / kBlock, kBlock, 0, ctx.stream>>>(d.st, L.nseg);

@@ -163,6 +163,24 @@ double spmv_alone_us(const LevelView &L, bool fp32, int reps, Ctx &ctx) {
   return fp32 ? spmv_alone_typed<float>(L, reps, ctx) : spmv_alone_typed<double>(L, reps, ctx);
 }
 
+__global__ void k_meta_words(int4 *meta, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) meta[i] = make_int4(kPlainSlice, 0, 0, 0);
+}
+
+double spmv_words_us(const LevelView &L, bool fp32, int reps, Ctx &ctx) {
+  if (L.nrows == 0 || L.nblk == 0 || L.gs.nv > 0 || L.nchunks == 0) return 0.0;
+  // every slice marked as kept in words, no staging
+  DevBuf<int4> meta(ctx, (size_t)L.nchunks);
+  k_meta_words<<<(unsigned)((L.nchunks + 255) / 256), 256, 0, ctx.stream>>>(meta.get(), L.nchunks);
+  RSB_LAUNCHED();
+  LevelView w = L;
+  w.pmeta = meta.get();
+  w.stage = nullptr;
+  w.lmeta = nullptr;
+  return spmv_alone_us(w, fp32, reps, ctx);
+}
+
 double hbm_probe_gbs(int kind, int64_t bytes, int reps, int device, Ctx &ctx) {
   const int64_t n4 = bytes / 16;
   DevBuf<f32x4> src(ctx, (size_t)n4);

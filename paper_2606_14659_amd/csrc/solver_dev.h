@@ -290,9 +290,10 @@ __device__ inline void lap_acc2(uint32_t wt, X xv, X yv, X xi, X yi, X &ax, X &a
   ay = wt ? lap_fma((X)wt, yi - yv, ay) : ay;
 }
 
-template <typename X>
-__device__ inline void lap_row2(const SellRef &m, const X *__restrict__ x,
-                                const X *__restrict__ y, int64_t row, X xi, X yi, X &ax, X &ay) {
+// Two FP64 vectors stored interleaved (x in .x, y in .y): one 16-byte gather
+// per slot for both.
+__device__ inline void lap_row2i(const SellRef &m, const double2 *__restrict__ xy, int64_t row,
+                                 double xi, double yi, double &ax, double &ay) {
   constexpr int G = kSlotGroup / 2;
   const int64_t c = row >> 6;
   const int lane = (int)(row & 63);
@@ -308,7 +309,7 @@ __device__ inline void lap_row2(const SellRef &m, const X *__restrict__ x,
     uint32_t w[GW];
     lap_words<GW>(cp, 0, nw, w);
     for (int k0 = 0; k0 < nw; k0 += GW) {
-      X xv[2 * GW], yv[2 * GW];
+      double2 v[2 * GW];
       PkEntry e[2 * GW];
 #pragma unroll
       for (int u = 0; u < GW; ++u) {
@@ -316,13 +317,10 @@ __device__ inline void lap_row2(const SellRef &m, const X *__restrict__ x,
         e[2 * u + 1] = pk_entry(w[u] >> 16, (int32_t)row, mb);
       }
 #pragma unroll
-      for (int u = 0; u < 2 * GW; ++u) {
-        xv[u] = e[u].wt ? x[e[u].col] : (X)0;
-        yv[u] = e[u].wt ? y[e[u].col] : (X)0;
-      }
+      for (int u = 0; u < 2 * GW; ++u) v[u] = e[u].wt ? xy[e[u].col] : make_double2(0.0, 0.0);
       lap_words<GW>(cp, k0 + GW, nw, w);
 #pragma unroll
-      for (int u = 0; u < 2 * GW; ++u) lap_acc2(e[u].wt, xv[u], yv[u], xi, yi, ax, ay);
+      for (int u = 0; u < 2 * GW; ++u) lap_acc2(e[u].wt, v[u].x, v[u].y, xi, yi, ax, ay);
     }
     return;
   }
@@ -330,17 +328,16 @@ __device__ inline void lap_row2(const SellRef &m, const X *__restrict__ x,
   uint32_t w[G];
   lap_words<G>(cp, 0, width, w);
   for (int k0 = 0; k0 < width; k0 += G) {
-    X xv[G], yv[G];
+    double2 v[G];
     uint32_t wc[G];
 #pragma unroll
     for (int u = 0; u < G; ++u) {
       wc[u] = w[u];
-      xv[u] = colw_wt(wc[u]) ? x[colw_col(wc[u])] : (X)0;
-      yv[u] = colw_wt(wc[u]) ? y[colw_col(wc[u])] : (X)0;
+      v[u] = colw_wt(wc[u]) ? xy[colw_col(wc[u])] : make_double2(0.0, 0.0);
     }
     lap_words<G>(cp, k0 + G, width, w);
 #pragma unroll
-    for (int u = 0; u < G; ++u) lap_acc2(colw_wt(wc[u]), xv[u], yv[u], xi, yi, ax, ay);
+    for (int u = 0; u < G; ++u) lap_acc2(colw_wt(wc[u]), v[u].x, v[u].y, xi, yi, ax, ay);
   }
 }
 
