@@ -66,7 +66,7 @@ def cpu_model():
     return platform.processor() or platform.machine()
 
 
-def cpu_baseline(mesh, nparts, m, keep, tol, warm_start, max_restarts):
+def cpu_baseline(mesh, nparts, m, keep, tol, warm_start, max_restarts, bfs_start=0):
     """The CPU oracle (FP64, built here with -O3 -march=native) on a bounded
     sample of the workload, with the GPU run's solver settings.
 
@@ -106,7 +106,7 @@ def cpu_baseline(mesh, nparts, m, keep, tol, warm_start, max_restarts):
     t0 = time.perf_counter()
     pst, part, pinfo = oracle.partition(mesh.ids[:n_part], p_part, lanczos_m=m, lanczos_keep=keep,
                                         tol=tol, warm_start=int(warm_start),
-                                        max_restarts=max_restarts)
+                                        bfs_start=int(bfs_start), max_restarts=max_restarts)
     t_part = time.perf_counter() - t0
     v1, s1, d1 = rates[1]
     vn, sn, dn = rates[nthreads]
@@ -121,7 +121,8 @@ def cpu_baseline(mesh, nparts, m, keep, tol, warm_start, max_restarts):
             "partition_sample": {"elements": n_part, "nparts": p_part, "seconds": t_part,
                                  "threads": nthreads, "status": pst,
                                  "settings": f"m={m}, keep={keep}, tol={tol}, "
-                                             f"warm_start={int(warm_start)}"}}
+                                             f"warm_start={int(warm_start)}, "
+                                             f"bfs_start={int(bfs_start)}"}}
 
 
 GOLDENS = os.path.join(ROOT, "tests", "golden", "config_goldens.json")
@@ -286,6 +287,9 @@ def main():
                     help="store rows in Cuthill-McKee order before the first level")
     ap.add_argument("--gather-scatter", type=int, default=0, choices=[0, 1],
                     help="Lanczos SpMV in the gather-scatter form instead of the sliced ELL")
+    ap.add_argument("--bfs-start", type=int, default=1, choices=[0, 1],
+                    help="first solve of the mesh starts from the BFS distance to a "
+                         "pseudo-peripheral element")
     ap.add_argument("--pack-matrix", type=int, default=1, choices=[0, 1, 2],
                     help="0: sliced-ELL words; 1: packed slices; 2: packed slices and "
                          "LDS-staged gathers")
@@ -349,7 +353,7 @@ def main():
                 gather_scatter=args.gather_scatter, second_solve=args.second_solve,
                 batched=0 if args.unbatched else 1, rows_per_thread=args.rows_per_thread,
                 autotune=args.autotune, lanczos_s=args.lanczos_s,
-                pack_matrix=args.pack_matrix)
+                pack_matrix=args.pack_matrix, bfs_start=args.bfs_start)
     if args.autotune_cache:
         opts["autotune_cache"] = args.autotune_cache
 
@@ -423,6 +427,7 @@ def main():
                    "warm_start": bool(args.warm_start), "reorder": bool(args.reorder),
                    "gather_scatter": bool(args.gather_scatter),
                    "pack_matrix": args.pack_matrix,
+                   "bfs_start": bool(args.bfs_start),
                    "second_solve": bool(args.second_solve),
                    "batched": not args.unbatched},
         "time_to_partition_ms": dt * 1e3 / args.steps,
@@ -498,7 +503,7 @@ def main():
               flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, wl["nparts"], args.m, args.keep, args.tol,
-                                           args.warm_start, args.max_restarts)
+                                           args.warm_start, args.max_restarts, args.bfs_start)
     print(json.dumps(out), flush=True)
 
 

@@ -201,6 +201,16 @@ typedef struct rsb_opts {
                                the neighbours gathered there.  The same entries in
                                the same order and the same values, so results are
                                bitwise those of 0 = 32-bit words only. */
+  int32_t bfs_start;        /* 1 = the first Lanczos solve of each mesh (the one
+                               with no parent vector to start from) starts from the
+                               number of edges between each element and a pseudo-
+                               peripheral element (the element farthest from element
+                               0, smallest index among the farthest), centred and
+                               scaled to unit root-mean-square over the elements the
+                               search reaches, plus 0.1 x the random start; other
+                               elements take the random start.  Not in the paper,
+                               which leaves the start vector open.  0 (default): the
+                               random start. */
 } rsb_opts;
 
 typedef struct rsb_stats {

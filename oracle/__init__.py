@@ -30,7 +30,7 @@ class Opts(C.Structure):
                 ("amg_smooth", C.c_int32), ("amg_sigma", C.c_double),
                 ("fiedler_sweep", C.c_int32), ("sweep_gap", C.c_double),
                 ("warm_start", C.c_int32), ("second_solve", C.c_int32),
-                ("lanczos_s", C.c_int32)]
+                ("lanczos_s", C.c_int32), ("bfs_start", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -101,6 +101,7 @@ def load(path: str):
     L.orc_split.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
     L.orc_gs_apply.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_locality_order.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_bfs_start.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_partition.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, P(Opts),
                                 C.c_void_p, P(Info)]
     L.orc_metrics.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
@@ -212,6 +213,19 @@ def locality_order(row_ptr, col, w) -> np.ndarray:
     rc = lib().orc_locality_order(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(out))
     if rc != 0:
         raise RuntimeError(f"orc_locality_order: {rc}")
+    return out
+
+
+def bfs_start(row_ptr, col, w) -> np.ndarray:
+    """Start values of bfs_start on a CSR graph (NaN where not reached)."""
+    n = len(row_ptr) - 1
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    ww = np.ascontiguousarray(w, dtype=np.int32)
+    out = np.zeros(n, dtype=np.float64)
+    rc = lib().orc_bfs_start(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_bfs_start: {rc}")
     return out
 
 

@@ -1149,9 +1149,11 @@ bool valid_mesh(int64_t nelem, int32_t nv, const int64_t *ids) {
 }
 
 // Recursion of Alg. 1 on the vertex list `elems` (ascending global ids),
-// parts [p0, p0 + np).
+// parts [p0, p0 + np).  The first call (root) reads the start values of
+// bfs_start from `warm`; the others read it only with warm_start.
 int rsb_recurse(const Graph &g, const std::vector<int64_t> &elems, int32_t p0, int32_t np,
-                const orc_opts &o, int32_t *part, orc_info &info, int &worst, WarmMap &warm) {
+                const orc_opts &o, int32_t *part, orc_info &info, int &worst, WarmMap &warm,
+                bool root = false) {
   if (np == 1) {
     for (int64_t e : elems) part[e] = p0;
     return 0;
@@ -1163,7 +1165,8 @@ int rsb_recurse(const Graph &g, const std::vector<int64_t> &elems, int32_t p0, i
   Vec y;
   double lam;
   orc_info li{};
-  int st = bisect(sub, elems, n_low, o, side, y, lam, li, o.warm_start ? &warm : nullptr);
+  const bool read_warm = o.warm_start || (root && o.bfs_start);
+  int st = bisect(sub, elems, n_low, o, side, y, lam, li, read_warm ? &warm : nullptr);
   if (st < 0) return st;
   worst = std::max(worst, st);
   info.matvecs += li.matvecs;
@@ -1202,6 +1205,32 @@ std::vector<int32_t> bfs_levels(const Graph &g, int64_t src) {
       }
   }
   return dist;
+}
+
+// Start values of bfs_start (not in the paper, which leaves the start vector
+// open): the number of edges from the pseudo-peripheral row (as for the
+// locality order), centred and scaled to unit root-mean-square over the rows
+// the search reaches (sums of the integer distances taken exactly).
+void bfs_start_values(const Graph &g, const std::vector<int64_t> &gid, WarmMap &warm) {
+  if (g.n < 2) return;
+  const std::vector<int32_t> d0 = bfs_levels(g, 0);
+  int64_t far = 0;
+  for (int64_t i = 0; i < g.n; ++i)
+    if (d0[i] > d0[far]) far = i;
+  const std::vector<int32_t> d = bfs_levels(g, far);
+  int64_t cnt = 0, s1 = 0, s2 = 0;
+  for (int64_t i = 0; i < g.n; ++i)
+    if (d[i] >= 0) {
+      ++cnt;
+      s1 += d[i];
+      s2 += (int64_t)d[i] * d[i];
+    }
+  const double mean = (double)s1 / (double)cnt;
+  const double var = (double)s2 / (double)cnt - mean * mean;
+  if (cnt < 2 || !(var > 0.0)) return;
+  const double sd = std::sqrt(var);
+  for (int64_t i = 0; i < g.n; ++i)
+    if (d[i] >= 0) warm[gid[i]] = ((double)d[i] - mean) / sd;
 }
 
 std::vector<int32_t> cuthill_mckee(Graph g) {
@@ -1248,6 +1277,7 @@ void orc_opts_default(orc_opts *o) {
   o->warm_start = 0;
   o->second_solve = 0;
   o->lanczos_s = 1;
+  o->bfs_start = 0;
 }
 
 double orc_start_value(uint64_t seed, int64_t gid) { return start_value(seed, gid); }
@@ -1360,7 +1390,9 @@ int orc_fiedler(int64_t nelem, int32_t nv, const int64_t *ids, const orc_opts *o
   std::vector<uint8_t> side;
   Vec yv;
   orc_info li{};
-  int st = bisect(g, gv, nelem / 2, *o, side, yv, *lambda, li);
+  WarmMap warm;
+  if (o->bfs_start) bfs_start_values(g, gv, warm);
+  int st = bisect(g, gv, nelem / 2, *o, side, yv, *lambda, li, o->bfs_start ? &warm : nullptr);
   if (info) *info = li;
   if (st < 0) return st;
   std::copy(yv.begin(), yv.end(), y);
@@ -1452,6 +1484,22 @@ int orc_locality_order(int64_t n, const int64_t *row_ptr, const int32_t *col,
   return 0;
 }
 
+int orc_bfs_start(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                  double *out) {
+  if (n < 1 || !row_ptr || !col || !weight || !out) return -1;
+  Graph g;
+  to_graph(n, row_ptr, col, weight, g);
+  std::vector<int64_t> gv(n);
+  for (int64_t i = 0; i < n; ++i) gv[i] = i;
+  WarmMap warm;
+  bfs_start_values(g, gv, warm);
+  for (int64_t i = 0; i < n; ++i) {
+    auto it = warm.find(i);
+    out[i] = it == warm.end() ? std::nan("") : it->second;
+  }
+  return 0;
+}
+
 int orc_amg_vcycle(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
                    const int64_t *gid, double sigma, int32_t nsmooth, const double *f, double *u) {
   if (n < 1 || !row_ptr || !gid || !f || !u || nsmooth < 0) return -1;
@@ -1474,7 +1522,8 @@ int orc_partition(int64_t nelem, int32_t nv, const int64_t *ids, int32_t nparts,
   orc_info li{};
   int worst = 0;
   WarmMap warm;
-  int r = rsb_recurse(g, all, 0, nparts, *o, part, li, worst, warm);
+  if (o->bfs_start) bfs_start_values(g, all, warm);
+  int r = rsb_recurse(g, all, 0, nparts, *o, part, li, worst, warm, true);
   if (info) *info = li;
   if (r < 0) return r;
   return worst;

@@ -69,6 +69,12 @@ typedef struct orc_opts {
                                 steps j+1 and j+2 from one block [L q_j, L^2 q_j]
                                 (two-step Lanczos; the same Krylov space and
                                 projected matrix in exact arithmetic) */
+  int32_t bfs_start;         /* 1: the first bisection's solve (no parent vector)
+                                starts from the graph distance to a pseudo-
+                                peripheral element, centred and scaled to unit
+                                root-mean-square (plus 0.1 x the random start);
+                                elements the search does not reach take the
+                                random start.  0: the random start. */
 } orc_opts;
 
 #define ORC_SECOND_SEED 0x9E3779B97F4A7C15ull
@@ -172,6 +178,11 @@ int orc_gs_apply(int64_t nelem, int32_t nv, const int64_t *ids, const double *x,
  * order[k] = row placed at position k.  Not part of the paper's method (it
  * stands in for the coordinate pre-sort of the elements).  Returns 0, -1 on
  * bad input. */
+/* The start values of bfs_start on a CSR graph (row i = global id i): out[i]
+ * = (d_i - mean) / sd, NaN for rows the search does not reach. */
+int orc_bfs_start(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                  double *out);
+
 int orc_locality_order(int64_t n, const int64_t *row_ptr, const int32_t *col,
                        const int32_t *weight, int32_t *order);
 

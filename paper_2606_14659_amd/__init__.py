@@ -42,7 +42,7 @@ class Opts(C.Structure):
         ("fiedler_sweep", C.c_int32), ("warm_start", C.c_int32), ("sweep_gap", C.c_double),
         ("reorder", C.c_int32), ("gather_scatter", C.c_int32), ("second_solve", C.c_int32),
         ("lanczos_s", C.c_int32),
-        ("pack_matrix", C.c_int32),
+        ("pack_matrix", C.c_int32), ("bfs_start", C.c_int32),
     ]
 
 

@@ -107,6 +107,7 @@ void check_opts(const rsb_opts *o) {
     fail(RSB_EINVAL, "second_solve needs fiedler_sweep > 0");
   if (o->lanczos_s != 1 && o->lanczos_s != 2) fail(RSB_EINVAL, "lanczos_s must be 1 or 2");
   if (o->pack_matrix < 0 || o->pack_matrix > 2) fail(RSB_EINVAL, "pack_matrix must be 0, 1 or 2");
+  if (o->bfs_start != 0 && o->bfs_start != 1) fail(RSB_EINVAL, "bfs_start must be 0 or 1");
   if (o->gather_scatter != 0 && o->gather_scatter != 1)
     fail(RSB_EINVAL, "gather_scatter must be 0 or 1");
   if (o->gather_scatter && (o->graph != RSB_GRAPH_WEIGHTED || o->method == RSB_INVERSE_CG))
@@ -345,6 +346,21 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     parts_total += meshes[b].nparts;
   }
   const int rpt = o.rows_per_thread ? o.rows_per_thread : default_rpt(total);
+  // start values by element: the BFS start of the first solve of each mesh
+  // (taken in element order, before any reordering), then the parents'
+  // second Ritz vectors of the warm start
+  DevBuf<double> warm;
+  if (o.warm_start || o.bfs_start) {
+    warm.alloc(ctx, std::max<int64_t>(total, 1));
+    fill_f64(warm.get(), total, std::nan(""), ctx);
+  }
+  if (o.bfs_start) {
+    int64_t off = 0;
+    for (size_t b = 0; b < meshes.size(); ++b) {
+      if (np[b] >= 2) bfs_start_values(graphs[b], warm.get() + off, ctx);
+      off += meshes[b].nelem;
+    }
+  }
   // locality order of each mesh's rows (not for rsb_fiedler, whose vector
   // is returned row by row)
   std::vector<DevBuf<int32_t>> perms;
@@ -400,12 +416,8 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
                                                  : wlz;
   DevBuf<char> work(ctx, wbytes);
   DevBuf<double> y64(ctx, cap_rows);
-  DevBuf<double> y2, warm;
+  DevBuf<double> y2;
   if (o.fiedler_sweep > 0 || o.warm_start) y2.alloc(ctx, cap_rows);
-  if (o.warm_start) {
-    warm.alloc(ctx, std::max<int64_t>(total, 1));
-    fill_f64(warm.get(), total, std::nan(""), ctx);
-  }
   DevBuf<uint8_t> side(ctx, cap_rows);
   KernelProfile prof;
   Level LA, LB;
@@ -445,7 +457,9 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     phase_to(lv + " solve");
     int amg_levels = 0;
     const int64_t fp64_steps0 = ctx.fp64_level_steps;
-    const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(), y2.get(), warm.get(),
+    const bool read_warm = o.warm_start || (level == 0 && o.bfs_start);
+    const int64_t steps = solve_level(*L, C, S, o, work.get(), y64.get(), y2.get(),
+                                      read_warm ? warm.get() : nullptr,
                                       o.profile ? &prof : nullptr, &amg_levels, &st.fallbacks, ctx);
     if (o.warm_start) warm_update(*L, C, S, y2.get(), warm.get(), ctx);
     st.amg_levels = std::max(st.amg_levels, amg_levels);
@@ -761,6 +775,7 @@ int rsb_opts_init(rsb_opts *o) {
   o->sweep_gap = 0.1;
   o->lanczos_s = 1;
   o->pack_matrix = 1;
+  o->bfs_start = 0;
   return RSB_OK;
 }
 

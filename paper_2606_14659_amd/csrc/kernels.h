@@ -55,6 +55,13 @@ void sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int bits, Ctx &ctx,
 // CSR is rewritten in that order (columns relabelled).
 void locality_order(DevCsr &g, DevBuf<int32_t> &perm, Ctx &ctx);
 
+// Start values of opts->bfs_start for one mesh's dual graph (element order):
+// warm[i] = (d_i - mean) / sd with d the number of edges from the pseudo-
+// peripheral row (the row farthest from row 0, smallest index among the
+// farthest), mean and sd over the rows the search reaches (exact integer
+// sums); other entries are left as they are.
+void bfs_start_values(const DevCsr &g, double *warm, Ctx &ctx);
+
 // Dual graph of nelem elements with nv vertex ids each (device ids).
 void build_dual_graph(const int64_t *d_ids, int64_t nelem, int nv, int graph, DevCsr &out,
                       Ctx &ctx);

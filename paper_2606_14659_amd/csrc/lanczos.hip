@@ -763,10 +763,27 @@ __global__ __launch_bounds__(proj_threads<RPT>()) void k_lz_pa(LzArgs<T> a, int 
   }
 }
 
-// v_k^T of four staged vectors over one tile (wavefront), one read of v_k.
-template <int NSL, typename P, typename SZ, typename SQ>
-__device__ inline void wave_dot4(const P *__restrict__ v, const SZ *z1, const SZ *z2,
-                                 const SQ *q1, const SQ *q2, int lane, int nsl, double (&acc)[4]) {
+// v_k^T q over one tile (wavefront) for a staged q of any type.
+template <int NSL, typename P, typename SQ>
+__device__ inline double wave_dot1(const P *__restrict__ v, const SQ *q, int lane, int nsl) {
+  constexpr int NB = NSL < 8 ? NSL : 8;
+  double acc = 0.0;
+  for (int t0 = 0; t0 < nsl; t0 += NB) {
+    P x[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) x[t] = (t0 + t < nsl) ? ld_stream(v + (t0 + t) * kWave) : (P)0;
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+      if (t0 + t < nsl) acc += (double)x[t] * (double)q[(t0 + t) * kWave + lane];
+  }
+  return acc;
+}
+
+// v_k^T of four staged vectors over one tile (wavefront), one read of v_k;
+// the vectors staged as two interleaved pairs (one LDS read each).
+template <int NSL, typename P, typename SQ2>
+__device__ inline void wave_dot4i(const P *__restrict__ v, const double2 *zz, const SQ2 *qq,
+                                  int lane, int nsl, double (&acc)[4]) {
   constexpr int NB = NSL < 8 ? NSL : 8;
 #pragma unroll
   for (int i = 0; i < 4; ++i) acc[i] = 0.0;
@@ -779,10 +796,12 @@ __device__ inline void wave_dot4(const P *__restrict__ v, const SZ *z1, const SZ
       const int o = (t0 + t) * kWave + lane;
       if (t0 + t < nsl) {
         const double xv = (double)x[t];
-        acc[0] += xv * (double)z1[o];
-        acc[1] += xv * (double)z2[o];
-        acc[2] += xv * (double)q1[o];
-        acc[3] += xv * (double)q2[o];
+        const double2 z = zz[o];
+        const SQ2 q = qq[o];
+        acc[0] += xv * z.x;
+        acc[1] += xv * z.y;
+        acc[2] += xv * (double)q.x;
+        acc[3] += xv * (double)q.y;
       }
     }
   }
@@ -806,12 +825,11 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
   constexpr int NW = NT / kWave;
   constexpr int NSL = TILE / kWave;
   __shared__ __align__(16) char smem[pb_lds_bytes<T, TILE>()];
+  using T2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
   double *xs = reinterpret_cast<double *>(smem);
-  double *z1s = reinterpret_cast<double *>(smem);
-  double *z2s = z1s + TILE;
-  T *qjs = reinterpret_cast<T *>(z2s + TILE);
-  T *qis = qjs + TILE;
-  double *vals = reinterpret_cast<double *>(qis + TILE);
+  double2 *zz = reinterpret_cast<double2 *>(smem);
+  T2 *qq = reinterpret_cast<T2 *>(zz + TILE);
+  double *vals = reinterpret_cast<double *>(qq + TILE);
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const BlkDev b = a.blk[lb];
   const SegState S = a.st[b.seg];
@@ -846,10 +864,11 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
     const int lr = r * NT + (int)threadIdx.x;
     const bool ok = lr < b.nrows;
     const int64_t row = b.row0 + (ok ? lr : 0);
-    z1s[lr] = z1v[r];
-    z2s[lr] = z2v[r];
-    qjs[lr] = ok ? a.V[(int64_t)j * a.vs + row] : (T)0;
-    qis[lr] = (ok && pend2) ? a.V[(int64_t)(j - 1) * a.vs + row] : (T)0;
+    zz[lr] = make_double2(z1v[r], z2v[r]);
+    T2 q;
+    q.x = ok ? a.V[(int64_t)j * a.vs + row] : (T)0;
+    q.y = (ok && pend2) ? a.V[(int64_t)(j - 1) * a.vs + row] : (T)0;
+    qq[lr] = q;
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -860,13 +879,13 @@ __global__ __launch_bounds__(proj_threads<RPT>()) __attribute__((amdgpu_waves_pe
     double acc[4];
     if (k <= 1) {
       const double *v = (k == 0 ? a.U0 : a.Q1) + b.row0 + lane;
-      wave_dot4<NSL>(v, z1s, z2s, qjs, qis, lane, nsl, acc);
+      wave_dot4i<NSL>(v, zz, qq, lane, nsl, acc);
     } else if (k <= S.nk) {
       const double *v = a.K + (int64_t)(k - 2) * a.vs + b.row0 + lane;
-      wave_dot4<NSL>(v, z1s, z2s, qjs, qis, lane, nsl, acc);
+      wave_dot4i<NSL>(v, zz, qq, lane, nsl, acc);
     } else {
       const T *v = a.V + (int64_t)k * a.vs + b.row0 + lane;
-      wave_dot4<NSL>(v, z1s, z2s, qjs, qis, lane, nsl, acc);
+      wave_dot4i<NSL>(v, zz, qq, lane, nsl, acc);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = wave_sum(acc[i]);
@@ -1012,19 +1031,16 @@ __global__ __launch_bounds__(proj_threads<RPT>()) void k_lz_px1(LzArgs<T> a) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int nsl = b.nrows / kWave;
   for (int kb = wave; kb < k; kb += NW) {
-    double acc[4];
+    double acc;
     if (kb <= 1) {
-      const double *v = (kb == 0 ? a.U0 : a.Q1) + b.row0 + lane;
-      wave_dot4<NSL>(v, qs, qs, qs, qs, lane, nsl, acc);
+      acc = wave_dot1<NSL>((kb == 0 ? a.U0 : a.Q1) + b.row0 + lane, qs, lane, nsl);
     } else if (kb <= S.nk) {
-      const double *v = a.K + (int64_t)(kb - 2) * a.vs + b.row0 + lane;
-      wave_dot4<NSL>(v, qs, qs, qs, qs, lane, nsl, acc);
+      acc = wave_dot1<NSL>(a.K + (int64_t)(kb - 2) * a.vs + b.row0 + lane, qs, lane, nsl);
     } else {
-      const T *v = a.V + (int64_t)kb * a.vs + b.row0 + lane;
-      wave_dot4<NSL>(v, qs, qs, qs, qs, lane, nsl, acc);
+      acc = wave_dot1<NSL>(a.V + (int64_t)kb * a.vs + b.row0 + lane, qs, lane, nsl);
     }
-    acc[0] = wave_sum(acc[0]);
-    if (lane == 0) vals[kb] = acc[0];
+    acc = wave_sum(acc);
+    if (lane == 0) vals[kb] = acc;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < k; i += NT) a.part[(int64_t)lb * a.ps + i] = vals[i];

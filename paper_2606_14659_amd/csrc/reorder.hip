@@ -152,7 +152,84 @@ int bfs(const DevCsr &g, int64_t src, int32_t *dist, int32_t *fa, int32_t *fb, i
   return L;
 }
 
+// Row count and the exact integer sums of the reached rows' distances (per
+// block, then one atomic add per block).
+__global__ void k_bfs_sums(const int32_t *__restrict__ dist, int64_t n,
+                           unsigned long long *__restrict__ sums) {
+  __shared__ unsigned long long red[3][kBlock / kWave];
+  unsigned long long c = 0, s1 = 0, s2 = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t d = dist[i];
+    if (d >= 0) {
+      c += 1;
+      s1 += (unsigned long long)d;
+      s2 += (unsigned long long)d * (unsigned long long)d;
+    }
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    c += __shfl_xor(c, off, kWave);
+    s1 += __shfl_xor(s1, off, kWave);
+    s2 += __shfl_xor(s2, off, kWave);
+  }
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    red[0][w] = c;
+    red[1][w] = s1;
+    red[2][w] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kBlock / kWave; ++k) {
+      c += red[0][k];
+      s1 += red[1][k];
+      s2 += red[2][k];
+    }
+    atomicAdd(&sums[0], c);
+    atomicAdd(&sums[1], s1);
+    atomicAdd(&sums[2], s2);
+  }
+}
+
+__global__ void k_bfs_warm(const int32_t *__restrict__ dist, int64_t n, double mean, double sd,
+                           double *__restrict__ warm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && dist[i] >= 0) warm[i] = ((double)dist[i] - mean) / sd;
+}
+
 }  // namespace
+
+void bfs_start_values(const DevCsr &g, double *warm, Ctx &ctx) {
+  const int64_t n = g.n;
+  if (n < 2) return;
+  const unsigned gr = grid_for(n, kBlock);
+  DevBuf<int32_t> dist(ctx, n), fa(ctx, n), fb(ctx, n), cnt1(ctx, 1);
+  DevBuf<unsigned long long> best(ctx, 1), sums(ctx, 3);
+  bfs(g, 0, dist.get(), fa.get(), fb.get(), cnt1.get(), ctx);
+  RSB_HIP(hipMemsetAsync(best.get(), 0, sizeof(unsigned long long), ctx.stream));
+  k_bfs_far<<<gr, kBlock, 0, ctx.stream>>>(dist.get(), n, best.get());
+  RSB_LAUNCHED();
+  unsigned long long hb = 0;
+  RSB_HIP(hipMemcpyAsync(&hb, best.get(), sizeof(hb), hipMemcpyDeviceToHost, ctx.stream));
+  RSB_HIP(hipStreamSynchronize(ctx.stream));
+  const int64_t far = hb ? (int64_t)(0xFFFFFFFFull - (hb & 0xFFFFFFFFull)) : 0;
+  bfs(g, far, dist.get(), fa.get(), fb.get(), cnt1.get(), ctx);
+  RSB_HIP(hipMemsetAsync(sums.get(), 0, 3 * sizeof(unsigned long long), ctx.stream));
+  k_bfs_sums<<<std::min<unsigned>(gr, 1024u), kBlock, 0, ctx.stream>>>(dist.get(), n, sums.get());
+  RSB_LAUNCHED();
+  unsigned long long h[3] = {0, 0, 0};
+  RSB_HIP(hipMemcpyAsync(h, sums.get(), sizeof(h), hipMemcpyDeviceToHost, ctx.stream));
+  RSB_HIP(hipStreamSynchronize(ctx.stream));
+  const int64_t cnt = (int64_t)h[0];
+  if (cnt < 2) return;
+  // the same arithmetic on the exact sums as the reference definition
+  const double mean = (double)(int64_t)h[1] / (double)cnt;
+  const double var = (double)(int64_t)h[2] / (double)cnt - mean * mean;
+  if (!(var > 0.0)) return;
+  k_bfs_warm<<<gr, kBlock, 0, ctx.stream>>>(dist.get(), n, mean, std::sqrt(var), warm);
+  RSB_LAUNCHED();
+  RSB_HIP(hipStreamSynchronize(ctx.stream));
+}
 
 void locality_order(DevCsr &g, DevBuf<int32_t> &perm, Ctx &ctx) {
   const int64_t n = g.n;

@@ -65,7 +65,8 @@ def test_bad_options_rejected_before_any_device_call():
                          ("fiedler_sweep", -1), ("fiedler_sweep", 65), ("sweep_gap", -1.0),
                          ("warm_start", 2), ("warm_start", -1), ("reorder", 2),
                          ("gather_scatter", 2), ("gather_scatter", -1), ("lanczos_s", 3),
-                         ("lanczos_s", 0), ("pack_matrix", 3), ("pack_matrix", -1)):
+                         ("lanczos_s", 0), ("pack_matrix", 3), ("pack_matrix", -1),
+                         ("bfs_start", 2), ("bfs_start", -1)):
         oo = rsb.Opts.from_buffer_copy(o)
         setattr(oo, field, value)
         part = np.zeros(2, dtype=np.int32)
