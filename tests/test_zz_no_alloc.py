@@ -11,7 +11,8 @@ import paper_2606_14659_amd as rsb
 
 pytestmark = pytest.mark.gpu
 
-BENCH = dict(precision="mixed", lanczos_keep=8, lanczos_m=40, tol=1e-2, warm_start=1)
+BENCH = dict(precision="mixed", lanczos_keep=8, lanczos_m=40, tol=1e-2, warm_start=1, lanczos_s=2,
+             bfs_start=1)
 
 
 def _pair(ids, nparts, device=False, **kw):
