@@ -361,7 +361,7 @@ void solve_alloc(SolveDev &S, int nseg, int nblk, int ngrp, int m, int keep, Ctx
 size_t lanczos_workspace_bytes(int64_t rows, int m, bool fp32, int keep);
 // Device time (ms) of one Lanczos step of the level with its current tile.
 template <typename T>
-double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx);
+double lanczos_trial_ms(const LevelView &L, int m, bool pairs, void *work, Ctx &ctx);
 template <typename T>
 int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p,
                       void *work, double *y64_out, Ctx &ctx);

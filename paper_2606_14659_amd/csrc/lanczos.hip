@@ -2312,9 +2312,11 @@ int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const Lanczos
 // selection.  The vectors hold whatever the workspace holds; every segment
 // is marked active and the state is restored before each timed repetition.
 template <typename T>
-double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
+double lanczos_trial_ms(const LevelView &L, int m, bool pairs, void *work, Ctx &ctx) {
   if (L.nseg == 0 || L.nblk == 0 || m < 4 || m > kMaxM) return 0.0;
-  const int j = m / 2 >= 3 ? m / 2 : 3;
+  // a step in the middle of a cycle; the two-step form times the pair that
+  // starts there (odd j)
+  const int j = pairs ? ((m / 2) | 1) : (m / 2 >= 3 ? m / 2 : 3);
   SolveDev S;
   solve_alloc(S, L.nseg, L.nblk, L.ngrp, m, 0, ctx);
   std::vector<SegState> hs(L.nseg);
@@ -2364,6 +2366,14 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
   a.vs = L.nrows;
   a.Wt0 = wt + (int64_t)(m + 1) * L.nrows;
   a.Wt1 = a.Wt0 + L.nrows;
+  // the pair's FP64 vectors where the kept Ritz vectors would start (no
+  // kept vectors here; the workspace of the solve holds both)
+  double *pv = (double *)(a.Wt1 + L.nrows);
+  a.K = pv;
+  a.Z1 = pv;
+  a.Z2 = pv + L.nrows;
+  a.Pw = reinterpret_cast<double2 *>(pv + 2 * L.nrows);
+  a.pairs = pairs ? 1 : 0;
   a.m = m;
   a.tol = 1.0;
   a.brk = 0.0;
@@ -2387,11 +2397,15 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
                            hipMemcpyDeviceToDevice, ctx.stream);
       if (err != hipSuccess) break;
       (void)hipEventRecord(e0, ctx.stream);
-      if (a.gs.nv) k_lz_gsum<T, 3><<<gs_grid(a.gs), kBlock, 0, ctx.stream>>>(a, j);
-      k_lz_project<T, RPT, 0, 3><<<nblk, proj_threads<RPT>(), 0, ctx.stream>>>(a, j);
-      k_lz_reduce<T, OP_PROJ0><<<ngrp, kBlock, 0, ctx.stream>>>(a, j);
-      k_lz_update<T, RPT, 1, 3><<<nblk, kBlock, 0, ctx.stream>>>(a, j);
-      k_lz_reduce<T, OP_UPD1><<<ngrp, kBlock, 0, ctx.stream>>>(a, j);
+      if (pairs) {
+        LzLaunch<T, RPT>::pair(a, nblk, ngrp, j, ctx.stream, nullptr);
+      } else {
+        if (a.gs.nv) k_lz_gsum<T, 3><<<gs_grid(a.gs), kBlock, 0, ctx.stream>>>(a, j);
+        k_lz_project<T, RPT, 0, 3><<<nblk, proj_threads<RPT>(), 0, ctx.stream>>>(a, j);
+        k_lz_reduce<T, OP_PROJ0><<<ngrp, kBlock, 0, ctx.stream>>>(a, j);
+        k_lz_update<T, RPT, 1, 3><<<nblk, kBlock, 0, ctx.stream>>>(a, j);
+        k_lz_reduce<T, OP_UPD1><<<ngrp, kBlock, 0, ctx.stream>>>(a, j);
+      }
       (void)hipEventRecord(e1, ctx.stream);
       err = hipEventSynchronize(e1);
       float ms = 0.f;
@@ -2407,8 +2421,8 @@ double lanczos_trial_ms(const LevelView &L, int m, void *work, Ctx &ctx) {
   return total;
 }
 
-template double lanczos_trial_ms<float>(const LevelView &, int, void *, Ctx &);
-template double lanczos_trial_ms<double>(const LevelView &, int, void *, Ctx &);
+template double lanczos_trial_ms<float>(const LevelView &, int, bool, void *, Ctx &);
+template double lanczos_trial_ms<double>(const LevelView &, int, bool, void *, Ctx &);
 
 template int64_t lanczos_level<float>(const LevelView &, CompDev &, SolveDev &,
                                       const LanczosParams &, void *, double *, Ctx &);

@@ -9,7 +9,8 @@
 // and keeps the fastest; results are kept per process and, when a cache file
 // is named, in that file as one line per problem class:
 //
-//   rsb-tile 1 <gfx arch> <precision> <log2 rows> <nonzeros per row> <log2 segments> <m> <rpt>
+//   rsb-tile 2 <gfx arch> <precision> <log2 rows> <nonzeros per row> <log2 segments> <m>
+//              <steps per launch sequence: 1, or 2 for the two-step form> <rpt>
 //
 // A class is the level's size, density and segment count rounded as above,
 // so one tuned entry serves every level and mesh of similar shape.  The
@@ -31,7 +32,7 @@ namespace {
 
 constexpr int kCandidates[] = {2, 4, 8};
 
-using TileKey = std::string;  // "<arch> <precision> <log2 rows> <nnz/row> <log2 segs> <m>"
+using TileKey = std::string;  // "<arch> <precision> <log2 rows> <nnz/row> <log2 segs> <m> <s>"
 
 std::mutex g_tune_mu;
 std::map<TileKey, int> g_tiles;              // tuned in this process or read from files
@@ -54,9 +55,9 @@ std::string arch_name(int device) {
   return colon == std::string::npos ? a : a.substr(0, colon);
 }
 
-TileKey make_key(const std::string &arch, int prec, int lr, int nz, int ls, int m) {
+TileKey make_key(const std::string &arch, int prec, int lr, int nz, int ls, int m, int s) {
   char b[160];
-  std::snprintf(b, sizeof(b), "%s %d %d %d %d %d", arch.c_str(), prec, lr, nz, ls, m);
+  std::snprintf(b, sizeof(b), "%s %d %d %d %d %d %d", arch.c_str(), prec, lr, nz, ls, m, s);
   return b;
 }
 
@@ -72,13 +73,14 @@ void read_cache(const std::string &path) {
   FILE *f = std::fopen(path.c_str(), "r");
   if (!f) return;  // a missing file is an empty cache
   char arch[64];
-  int ver, prec, lr, nz, ls, m, rpt;
+  int ver, prec, lr, nz, ls, m, st, rpt;
   char line[256];
   while (std::fgets(line, sizeof(line), f)) {
-    if (std::sscanf(line, "rsb-tile %d %63s %d %d %d %d %d %d", &ver, arch, &prec, &lr, &nz, &ls,
-                    &m, &rpt) == 8 &&
-        ver == 1 && valid_rpt(rpt))
-      g_tiles[make_key(arch, prec, lr, nz, ls, m)] = rpt;
+    // (lines of other versions are ignored: version 1 had no step count)
+    if (std::sscanf(line, "rsb-tile %d %63s %d %d %d %d %d %d %d", &ver, arch, &prec, &lr, &nz,
+                    &ls, &m, &st, &rpt) == 9 &&
+        ver == 2 && (st == 1 || st == 2) && valid_rpt(rpt))
+      g_tiles[make_key(arch, prec, lr, nz, ls, m, st)] = rpt;
   }
   std::fclose(f);
 }
@@ -86,15 +88,22 @@ void read_cache(const std::string &path) {
 void append_cache(const std::string &path, const TileKey &k, int rpt) {
   FILE *f = std::fopen(path.c_str(), "a");
   if (!f) fail(RSB_EINVAL, "autotune_cache: cannot open " + path + " for appending");
-  std::fprintf(f, "rsb-tile 1 %s %d\n", k.c_str(), rpt);
+  std::fprintf(f, "rsb-tile 2 %s %d\n", k.c_str(), rpt);
   std::fclose(f);
+}
+
+// The launch sequence the solve will run: two steps at a time with
+// lanczos_s = 2 (thick restart, sliced ELL), else one.
+bool two_step(const rsb_opts &o) {
+  return o.lanczos_s == 2 && o.lanczos_keep > 0 && !o.gather_scatter;
 }
 
 double trial(Level &L, int rpt, const rsb_opts &o, void *work, Ctx &ctx) {
   level_tables(L, rpt, ctx);
   const LevelView v = view_of(L);
-  return o.precision == RSB_MIXED ? lanczos_trial_ms<float>(v, o.lanczos_m, work, ctx)
-                                  : lanczos_trial_ms<double>(v, o.lanczos_m, work, ctx);
+  const bool pairs = two_step(o);
+  return o.precision == RSB_MIXED ? lanczos_trial_ms<float>(v, o.lanczos_m, pairs, work, ctx)
+                                  : lanczos_trial_ms<double>(v, o.lanczos_m, pairs, work, ctx);
 }
 
 }  // namespace
@@ -111,7 +120,7 @@ void choose_tile(Level &L, const rsb_opts &o, void *work, Ctx &ctx) {
     const int64_t nnz_row = L.nrows > 0 ? (L.nnz + L.nrows / 2) / L.nrows : 0;
     const TileKey key = make_key(arch_name(ctx.device), o.precision,
                                  ilog2(std::max<int64_t>(L.nrows, 1)), (int)nnz_row,
-                                 ilog2(std::max(L.nseg, 1)), o.lanczos_m);
+                                 ilog2(std::max(L.nseg, 1)), o.lanczos_m, two_step(o) ? 2 : 1);
     const std::string path = o.autotune_cache ? o.autotune_cache : "";
     std::lock_guard<std::mutex> lock(g_tune_mu);
     if (!path.empty()) read_cache(path);

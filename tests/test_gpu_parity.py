@@ -288,19 +288,24 @@ def test_tile_sizes_identical_partition(orc, rpt):
     assert np.array_equal(part, opart)
 
 
-def test_autotune_cache(tmp_path):
+@pytest.mark.parametrize("steps", [1, 2])
+def test_autotune_cache(tmp_path, steps):
+    # one- and two-step launch sequences are timed and cached as separate
+    # classes (the last key field before the tile)
     ids = MESHES["clustered"]
     path = str(tmp_path / "tiles.txt")
-    st1, p1, _ = rsb.partition(ids, 16, precision="mixed", autotune=2, autotune_cache=path)
+    kw = dict(precision="mixed", lanczos_keep=8, lanczos_m=40, lanczos_s=steps,
+              autotune_cache=path)
+    st1, p1, _ = rsb.partition(ids, 16, autotune=2, **kw)
     lines = open(path).read().splitlines()
     assert lines
     for line in lines:
         f = line.split()
-        assert f[:2] == ["rsb-tile", "1"] and f[2].startswith("gfx") and len(f) == 9
-        assert int(f[-1]) in (2, 4, 8)
-    keys = [" ".join(line.split()[2:8]) for line in lines]
+        assert f[:2] == ["rsb-tile", "2"] and f[2].startswith("gfx") and len(f) == 10
+        assert int(f[-2]) == steps and int(f[-1]) in (2, 4, 8)
+    keys = [" ".join(line.split()[2:9]) for line in lines]
     assert len(keys) == len(set(keys))  # each class timed once per call
-    st2, p2, _ = rsb.partition(ids, 16, precision="mixed", autotune=1, autotune_cache=path)
+    st2, p2, _ = rsb.partition(ids, 16, autotune=1, **kw)
     assert st1 == st2
     assert np.array_equal(p1, p2)
     assert open(path).read().splitlines() == lines  # served from the cache
