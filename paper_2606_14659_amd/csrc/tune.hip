@@ -136,7 +136,8 @@ void choose_tile(Level &L, const rsb_opts &o, void *work, Ctx &ctx) {
       for (int c : kCandidates) {
         const double ms = trial(L, c, o, work, ctx);
         if (ctx.verbose >= 2)
-          fprintf(stderr, "[rsb]   tile %d rows: %.3f ms per step (per pair of steps in the two-step form)\n", kBlock * c, ms);
+          fprintf(stderr, "[rsb]   tile %d rows: %.3f ms per step (two-step form: per pair)\n",
+                  kBlock * c, ms);
         if (ms > 0.0 && (best == 0.0 || ms < best)) {
           best = ms;
           want = c;
