@@ -35,22 +35,29 @@ __global__ void k_bfs_init(int32_t *__restrict__ dist, int64_t n, int64_t src,
   if (i == 0) frontier[0] = (int32_t)src;
 }
 
-// One level of the search from the frontier (rows at level L): unreached
+// One level of the search from the frontier (rows at level L, *nf of them,
+// a count the previous level's launch left on the device): unreached
 // neighbours get level L + 1 (first claim wins; every claimant writes the
 // same level, so the levels do not depend on timing) and join the next
-// frontier, whose order may vary and is not used.
-__global__ void k_bfs_top(const int32_t *__restrict__ frontier, int64_t nf,
+// frontier, whose order may vary and is not used.  A fixed grid strides over
+// the frontier, so levels can be launched back to back without the host
+// reading their sizes.
+__global__ void k_bfs_top(const int32_t *__restrict__ frontier, const int32_t *__restrict__ nf,
                           const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                           int32_t *__restrict__ dist, int32_t L, int32_t *__restrict__ next,
                           int32_t *__restrict__ nnext) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nf) return;
-  const int32_t i = frontier[k];
-  for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
-    const int32_t j = col[p];
-    if (dist[j] == -1 && atomicCAS(&dist[j], -1, L + 1) == -1) next[atomicAdd(nnext, 1)] = j;
+  const int64_t n = *nf;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = frontier[k];
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      const int32_t j = col[p];
+      if (dist[j] == -1 && atomicCAS(&dist[j], -1, L + 1) == -1) next[atomicAdd(nnext, 1)] = j;
+    }
   }
 }
+
+__global__ void k_bfs_count_set(int32_t *__restrict__ c, int32_t v) { c[0] = v; }
 
 // farthest reached row, smallest index among ties: max of (dist, ~row)
 __global__ void k_bfs_far(const int32_t *__restrict__ dist, int64_t n,
@@ -129,27 +136,38 @@ __global__ void k_perm_csr(const int64_t *__restrict__ rp, const int32_t *__rest
   }
 }
 
-// Breadth-first levels from src into dist; returns the number of levels.
-int bfs(const DevCsr &g, int64_t src, int32_t *dist, int32_t *fa, int32_t *fb, int32_t *cnt,
-        Ctx &ctx) {
+// Breadth-first levels from src into dist; returns the number of levels
+// (the largest distance + 1).  Levels go out in batches of kBfsBatch
+// launches; lc[i] holds the frontier size of the batch's level i, and the
+// host reads the batch's sizes once to find where the search ended (the
+// launches after that found an empty frontier and did nothing).
+constexpr int kBfsBatch = 16;
+
+int bfs(const DevCsr &g, int64_t src, int32_t *dist, int32_t *fa, int32_t *fb, Ctx &ctx) {
   const int64_t n = g.n;
   k_bfs_init<<<grid_for(n, kBlock), kBlock, 0, ctx.stream>>>(dist, n, src, fa);
   RSB_LAUNCHED();
-  int64_t nf = 1;
+  DevBuf<int32_t> lc(ctx, kBfsBatch + 1);
+  const unsigned grid = std::min<unsigned>(grid_for(n, kBlock), 1024u);
   int32_t L = 0;
-  while (nf > 0) {
-    RSB_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t), ctx.stream));
-    k_bfs_top<<<grid_for(nf, kBlock), kBlock, 0, ctx.stream>>>(fa, nf, g.row_ptr.get(),
-                                                               g.col.get(), dist, L, fb, cnt);
+  int32_t start = 1;  // frontier size at the batch's first level
+  for (;;) {
+    RSB_HIP(hipMemsetAsync(lc.get(), 0, (kBfsBatch + 1) * sizeof(int32_t), ctx.stream));
+    k_bfs_count_set<<<1, 1, 0, ctx.stream>>>(lc.get(), start);
+    for (int i = 0; i < kBfsBatch; ++i) {
+      k_bfs_top<<<grid, kBlock, 0, ctx.stream>>>(fa, lc.get() + i, g.row_ptr.get(), g.col.get(),
+                                                 dist, L + i, fb, lc.get() + i + 1);
+      std::swap(fa, fb);
+    }
     RSB_LAUNCHED();
-    int32_t h = 0;
-    RSB_HIP(hipMemcpyAsync(&h, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, ctx.stream));
+    int32_t h[kBfsBatch + 1];
+    RSB_HIP(hipMemcpyAsync(h, lc.get(), sizeof(h), hipMemcpyDeviceToHost, ctx.stream));
     RSB_HIP(hipStreamSynchronize(ctx.stream));
-    std::swap(fa, fb);
-    nf = h;
-    ++L;
+    for (int i = 1; i <= kBfsBatch; ++i)
+      if (h[i] == 0) return L + i;
+    L += kBfsBatch;
+    start = h[kBfsBatch];
   }
-  return L;
 }
 
 // Row count and the exact integer sums of the reached rows' distances (per
@@ -203,9 +221,9 @@ void bfs_start_values(const DevCsr &g, double *warm, Ctx &ctx) {
   const int64_t n = g.n;
   if (n < 2) return;
   const unsigned gr = grid_for(n, kBlock);
-  DevBuf<int32_t> dist(ctx, n), fa(ctx, n), fb(ctx, n), cnt1(ctx, 1);
+  DevBuf<int32_t> dist(ctx, n), fa(ctx, n), fb(ctx, n);
   DevBuf<unsigned long long> best(ctx, 1), sums(ctx, 3);
-  bfs(g, 0, dist.get(), fa.get(), fb.get(), cnt1.get(), ctx);
+  bfs(g, 0, dist.get(), fa.get(), fb.get(), ctx);
   RSB_HIP(hipMemsetAsync(best.get(), 0, sizeof(unsigned long long), ctx.stream));
   k_bfs_far<<<gr, kBlock, 0, ctx.stream>>>(dist.get(), n, best.get());
   RSB_LAUNCHED();
@@ -213,7 +231,7 @@ void bfs_start_values(const DevCsr &g, double *warm, Ctx &ctx) {
   RSB_HIP(hipMemcpyAsync(&hb, best.get(), sizeof(hb), hipMemcpyDeviceToHost, ctx.stream));
   RSB_HIP(hipStreamSynchronize(ctx.stream));
   const int64_t far = hb ? (int64_t)(0xFFFFFFFFull - (hb & 0xFFFFFFFFull)) : 0;
-  bfs(g, far, dist.get(), fa.get(), fb.get(), cnt1.get(), ctx);
+  bfs(g, far, dist.get(), fa.get(), fb.get(), ctx);
   RSB_HIP(hipMemsetAsync(sums.get(), 0, 3 * sizeof(unsigned long long), ctx.stream));
   k_bfs_sums<<<std::min<unsigned>(gr, 1024u), kBlock, 0, ctx.stream>>>(dist.get(), n, sums.get());
   RSB_LAUNCHED();
@@ -236,9 +254,9 @@ void locality_order(DevCsr &g, DevBuf<int32_t> &perm, Ctx &ctx) {
   perm.alloc(ctx, std::max<int64_t>(n, 1));
   if (n == 0) return;
   const unsigned gr = grid_for(n, kBlock);
-  DevBuf<int32_t> dist(ctx, n), fa(ctx, n), fb(ctx, n), cnt1(ctx, 1);
+  DevBuf<int32_t> dist(ctx, n), fa(ctx, n), fb(ctx, n);
   DevBuf<unsigned long long> best(ctx, 1);
-  bfs(g, 0, dist.get(), fa.get(), fb.get(), cnt1.get(), ctx);
+  bfs(g, 0, dist.get(), fa.get(), fb.get(), ctx);
   RSB_HIP(hipMemsetAsync(best.get(), 0, sizeof(unsigned long long), ctx.stream));
   k_bfs_far<<<gr, kBlock, 0, ctx.stream>>>(dist.get(), n, best.get());
   RSB_LAUNCHED();
@@ -246,7 +264,7 @@ void locality_order(DevCsr &g, DevBuf<int32_t> &perm, Ctx &ctx) {
   RSB_HIP(hipMemcpyAsync(&hb, best.get(), sizeof(hb), hipMemcpyDeviceToHost, ctx.stream));
   RSB_HIP(hipStreamSynchronize(ctx.stream));
   const int64_t far = hb ? (int64_t)(0xFFFFFFFFull - (hb & 0xFFFFFFFFull)) : 0;
-  const int nlev = bfs(g, far, dist.get(), fa.get(), fb.get(), cnt1.get(), ctx);
+  const int nlev = bfs(g, far, dist.get(), fa.get(), fb.get(), ctx);
   DevBuf<uint64_t> keys(ctx, n);
   DevBuf<uint32_t> vals(ctx, n);
   k_order_keys<<<gr, kBlock, 0, ctx.stream>>>(dist.get(), n, keys.get(), vals.get());
