@@ -287,7 +287,7 @@ def main():
                     help="store rows in Cuthill-McKee order before the first level")
     ap.add_argument("--gather-scatter", type=int, default=0, choices=[0, 1],
                     help="Lanczos SpMV in the gather-scatter form instead of the sliced ELL")
-    ap.add_argument("--bfs-start", type=int, default=1, choices=[0, 1],
+    ap.add_argument("--bfs-start", type=int, default=0, choices=[0, 1],
                     help="first solve of the mesh starts from the BFS distance to a "
                          "pseudo-peripheral element")
     ap.add_argument("--pack-matrix", type=int, default=1, choices=[0, 1, 2],

@@ -53,7 +53,7 @@ def check_lambda_vs_oracle(lam, res, key, label, bound):
     return rel
 
 BENCH = dict(precision="mixed", lanczos_keep=8, tol=1e-2, lanczos_m=40, max_restarts=50,
-             warm_start=1, lanczos_s=2, bfs_start=1)
+             warm_start=1, lanczos_s=2)
 
 
 def _torch_ids(ids):

@@ -11,8 +11,8 @@ import paper_2606_14659_amd as rsb
 
 pytestmark = pytest.mark.gpu
 
-BENCH = dict(precision="mixed", lanczos_keep=8, lanczos_m=40, tol=1e-2, warm_start=1, lanczos_s=2,
-             bfs_start=1)
+BENCH = dict(precision="mixed", lanczos_keep=8, lanczos_m=40, tol=1e-2, warm_start=1, lanczos_s=2)
+BFS = dict(BENCH, bfs_start=1)
 
 
 def _pair(ids, nparts, device=False, **kw):
@@ -26,7 +26,7 @@ def _pair(ids, nparts, device=False, **kw):
     return p1
 
 
-@pytest.mark.parametrize("kw", [{}, BENCH], ids=["default", "bench"])
+@pytest.mark.parametrize("kw", [{}, BENCH, BFS], ids=["default", "bench", "bfs_start"])
 def test_two_calls_second_smaller(kw):
     big = mg.uniform_holes(mg.box_hex(40, 30, 24), 0.05, 31)
     small = mg.clustered_holes(mg.box_hex(23, 17, 11), 0.1, 32)
