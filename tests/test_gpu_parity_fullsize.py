@@ -251,7 +251,7 @@ def test_c3_c4_rsb_1024(c3, precision, tol):
     # C3 (FP64) and C4 (mixed precision) into 1024 parts: the first
     # bisection's eigenvalue and the final cut against the FP64 oracle's
     ids = _torch_ids(c3.ids)
-    kw = dict(lanczos_keep=8, lanczos_m=40, warm_start=1,
+    kw = dict(lanczos_keep=8, lanczos_m=40, warm_start=1, lanczos_s=2,
               max_restarts=50 if tol >= 1e-2 else 400)
     st, part, stats = rsb.partition(ids, 1024, device=True, precision=precision, tol=tol, **kw)
     assert st >= 0  # 1: a segment hit the restart cap, 2: a disconnected subgraph (outputs valid)
