@@ -1764,42 +1764,49 @@ __global__ __launch_bounds__(kWave) void k_trieig_arrow(SegState *__restrict__ s
       G[lane][c2] = g;
     }
   __syncthreads();
-  if (lane == 0) {
-    for (int a1 = 0; a1 < nv; ++a1)
-      for (int b1 = 0; b1 < nv; ++b1) U[a1][b1] = (a1 == b1) ? 1.0 : 0.0;
+  // cyclic Jacobi on G: every rotation's rows and columns are updated by
+  // lane r for entry r (the same arithmetic as one lane taking r in order:
+  // the column pass reads the entries before it, the row pass after it)
+  if (lane < KB)
+    for (int b1 = 0; b1 < KB; ++b1) U[lane][b1] = (lane == b1) ? 1.0 : 0.0;
+  __syncthreads();
+  if (lane == 0)
     for (int a1 = 0; a1 < nv; ++a1)
       for (int b1 = a1 + 1; b1 < nv; ++b1) G[a1][b1] = G[b1][a1] = 0.5 * (G[a1][b1] + G[b1][a1]);
-    for (int sweep = 0; sweep < 30; ++sweep) {
-      double off = 0.0, dia = 0.0;
-      for (int a1 = 0; a1 < nv; ++a1) {
-        dia += G[a1][a1] * G[a1][a1];
-        for (int b1 = a1 + 1; b1 < nv; ++b1) off += G[a1][b1] * G[a1][b1];
-      }
-      if (off <= 1e-32 * dia) break;
-      for (int p1 = 0; p1 < nv; ++p1)
-        for (int q1 = p1 + 1; q1 < nv; ++q1) {
-          const double gpq = G[p1][q1];
-          if (gpq == 0.0) continue;
-          const double tau = (G[q1][q1] - G[p1][p1]) / (2.0 * gpq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
-          for (int r = 0; r < nv; ++r) {
-            const double grp = G[r][p1], grq = G[r][q1];
-            G[r][p1] = cs * grp - sn * grq;
-            G[r][q1] = sn * grp + cs * grq;
-          }
-          for (int r = 0; r < nv; ++r) {
-            const double gpr = G[p1][r], gqr = G[q1][r];
-            G[p1][r] = cs * gpr - sn * gqr;
-            G[q1][r] = sn * gpr + cs * gqr;
-          }
-          for (int r = 0; r < nv; ++r) {
-            const double urp = U[r][p1], urq = U[r][q1];
-            U[r][p1] = cs * urp - sn * urq;
-            U[r][q1] = sn * urp + cs * urq;
-          }
-        }
+  __syncthreads();
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int a1 = 0; a1 < nv; ++a1) {
+      dia += G[a1][a1] * G[a1][a1];
+      for (int b1 = a1 + 1; b1 < nv; ++b1) off += G[a1][b1] * G[a1][b1];
     }
+    if (off <= 1e-32 * dia) break;  // the same decision in every lane
+    for (int p1 = 0; p1 < nv; ++p1)
+      for (int q1 = p1 + 1; q1 < nv; ++q1) {
+        const double gpq = G[p1][q1];
+        if (gpq == 0.0) continue;
+        const double tau = (G[q1][q1] - G[p1][p1]) / (2.0 * gpq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+        __syncthreads();  // every lane has read G[p][q], G[p][p], G[q][q]
+        if (lane < nv) {
+          const double grp = G[lane][p1], grq = G[lane][q1];
+          G[lane][p1] = cs * grp - sn * grq;
+          G[lane][q1] = sn * grp + cs * grq;
+          const double urp = U[lane][p1], urq = U[lane][q1];
+          U[lane][p1] = cs * urp - sn * urq;
+          U[lane][q1] = sn * urp + cs * urq;
+        }
+        __syncthreads();
+        if (lane < nv) {
+          const double gpr = G[p1][lane], gqr = G[q1][lane];
+          G[p1][lane] = cs * gpr - sn * gqr;
+          G[q1][lane] = sn * gpr + cs * gqr;
+        }
+        __syncthreads();
+      }
+  }
+  if (lane == 0) {
     // ascending order of the Ritz values (selection sort of the columns)
     for (int a1 = 0; a1 < nv; ++a1) gev[a1] = G[a1][a1];
     for (int a1 = 0; a1 < nv; ++a1) {
