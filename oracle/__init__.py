@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "oracle.cpp")
 
 GRAPH = {"weighted": 0, "unit": 1, "face": 2}
-METHOD = {"lanczos": 0, "inverse_cg": 1, "auto": 2}
+METHOD = {"lanczos": 0, "inverse_cg": 1, "auto": 2, "block": 3}
 PRECOND = {"none": 0, "amg": 1}
 
 
@@ -114,6 +114,8 @@ def load(path: str):
     L.orc_cg_solve.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                P(Opts), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                P(C.c_int32)]
+    L.orc_block_pair.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 P(Opts), C.c_void_p, C.c_void_p, C.c_void_p, P(Info)]
     L.orc_set_threads.argtypes = [C.c_int32]
     return L
 
@@ -270,6 +272,22 @@ def fiedler_csr(row_ptr, col, w, gid=None, **kw):
     if rc < 0:
         raise RuntimeError(f"orc_fiedler_csr: {rc}")
     return rc, lam.value, y, info.as_dict()
+
+
+def block_pair(row_ptr, col, w, gid=None, **kw):
+    """Block Lanczos pair on a connected CSR graph: (status, y1, y2,
+    (theta1, theta2), info); theta2 = inf when there is no second direction."""
+    n, rp, c, ww, g = _csr_args(row_ptr, col, w, gid)
+    o = opts(**dict(kw, method="block"))
+    y1 = np.zeros(n, dtype=np.float64)
+    y2 = np.zeros(n, dtype=np.float64)
+    th = np.zeros(2, dtype=np.float64)
+    info = Info()
+    rc = lib().orc_block_pair(n, _ptr(rp), _ptr(c), _ptr(ww), _ptr(g), C.byref(o), _ptr(y1),
+                              _ptr(y2), _ptr(th), C.byref(info))
+    if rc < 0:
+        raise RuntimeError(f"orc_block_pair: {rc}")
+    return rc, y1, y2, (float(th[0]), float(th[1])), info.as_dict()
 
 
 def _csr_args(row_ptr, col, w, gid):

@@ -618,6 +618,251 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
 }
 
 // ---------------------------------------------------------------------------
+// Block Lanczos for the Fiedler pair (Sec. 9: a block iteration of two
+// vectors orthogonalised together at every step finds both vectors of an
+// exactly degenerate pair, where a one-vector iteration finds only the
+// combination its start vector holds).  The steps, in the order taken:
+//  * start block: column 0 the usual start (random, or warm), column 1 the
+//    random start of seed ^ ORC_SECOND_SEED; ones component removed; Cholesky
+//    QR twice (below);
+//  * block step j: W = L X_j; two classical Gram-Schmidt passes of both
+//    columns against [u0, Q]; the projected matrix T = Q^T L Q takes the two
+//    passes' summed coefficients as the columns of X_j (rows of the vectors
+//    before it and of X_j itself, the 2 x 2 block on the diagonal
+//    symmetrised); Cholesky QR twice of the remainder gives X_{j+1};
+//  * after m/2 blocks (or when both columns of a remainder vanish): the
+//    eigenpairs of T by cyclic Jacobi; the two smallest give the Ritz pairs
+//    (theta1, y1), (theta2, y2), each tested by ||L y - theta y|| <= tol theta;
+//  * restart: explicit from [y1, y2] (keep = 0), or thick (keep > 0, even):
+//    the keep smallest Ritz vectors head the next cycle's basis, where T is
+//    diag(theta), and the cycle continues from the last remainder block.
+// Readings (the paper gives no algorithmic detail): T from the computed
+// coefficients rather than an assumed block-tridiagonal form (the same in
+// exact arithmetic; it also gives the couplings of the kept vectors);
+// Cholesky QR run twice, the second on the nearly orthonormal first result.
+// Deflation: a column whose part orthogonal to the column before it is at
+// most kBlockDeflRel of its norm, or below kBlockDeflAbs times the largest
+// ||L x|| seen, becomes a zero column; it stays zero in later blocks (the
+// block continues as a one-vector Lanczos) and its diagonal entry of T is
+// set above every eigenvalue of T, so that it never enters the pair.
+// A pair within sweep_gap (when fiedler_sweep > 0) is rotated within its
+// plane so that y1 is the normalised projection of the random start of seed
+// on it: the pair's plane is well defined, a basis of it (for an exactly
+// degenerate pair) is not.
+// ---------------------------------------------------------------------------
+constexpr double kBlockDeflRel = 1e-7;
+constexpr double kBlockDeflAbs = 1e-10;
+
+struct BlockQR {
+  double r00 = 0.0, r01 = 0.0, r11 = 0.0;
+  bool z0 = false, z1 = false;  // dropped (zero) columns
+};
+
+// [w0, w1] = [x0, x1] R by Cholesky QR of the Gram matrix (in place).
+BlockQR block_cholqr(Vec &w0, Vec &w1, double thr_abs) {
+  BlockQR r;
+  const double g00 = dot(w0, w0), g01 = dot(w0, w1), g11 = dot(w1, w1);
+  r.r00 = std::sqrt(g00);
+  r.z0 = !(r.r00 > thr_abs);
+  if (r.z0) {
+    r.r00 = 0.0;
+    r.r01 = 0.0;
+  } else {
+    r.r01 = g01 / r.r00;
+  }
+  r.r11 = std::sqrt(std::max(g11 - r.r01 * r.r01, 0.0));
+  r.z1 = !(r.r11 > std::max(thr_abs, kBlockDeflRel * std::sqrt(g11)));
+  if (r.z1) r.r11 = 0.0;
+  const int64_t n = (int64_t)w0.size();
+  for (int64_t i = 0; i < n; ++i) {
+    const double x0 = r.z0 ? 0.0 : w0[i] / r.r00;
+    const double x1 = r.z1 ? 0.0 : (w1[i] - r.r01 * x0) / r.r11;
+    w0[i] = x0;
+    w1[i] = x1;
+  }
+  return r;
+}
+
+// Both passes; the second keeps the first one's dropped columns dropped.
+void block_cholqr2(Vec &w0, Vec &w1, double thr_abs, bool &z0, bool &z1) {
+  const BlockQR a = block_cholqr(w0, w1, thr_abs);
+  const BlockQR b = block_cholqr(w0, w1, 0.5);
+  z0 = a.z0 || b.z0;
+  z1 = a.z1 || b.z1;
+}
+
+int block_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_opts &o, Vec &y,
+                  double &lambda, orc_info &info, SecondPair &pair,
+                  const WarmMap *warm = nullptr) {
+  const int64_t n = g.n;
+  const double u0 = 1.0 / std::sqrt((double)n);
+  const int nb = std::max(2, o.lanczos_m) / 2;  // blocks per cycle
+  const int keep = std::max(0, o.lanczos_keep);
+  Vec x0(n), x1(n);
+  double raw = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    x0[i] = start_value(o.seed, gid[i]);
+    if (warm) {
+      auto it = warm->find(gid[i]);
+      if (it != warm->end()) x0[i] = it->second + kWarmNoise * x0[i];
+    }
+    x1[i] = start_value(o.seed ^ ORC_SECOND_SEED, gid[i]);
+  }
+  raw = std::sqrt(std::max(dot(x0, x0), dot(x1, x1)));
+  deflate_ones(x0);
+  deflate_ones(x1);
+  bool z0 = false, z1 = false;
+  block_cholqr2(x0, x1, kBlockDeflAbs * raw, z0, z1);
+  std::vector<Vec> Q;          // basis of the cycle
+  std::vector<char> zq;        // zero (dropped) columns of Q
+  Vec tkeep;                   // Ritz values of the kept vectors at its head
+  double tnorm = 0.0;
+  int converged = 0;
+  double th1 = 0.0, th2 = 0.0, res1 = 0.0;
+  bool has2 = false;
+  Vec y1(n, 0.0), y2(n, 0.0);
+  for (int cycle = 0; cycle <= o.max_restarts; ++cycle) {
+    const int nk = (int)Q.size();
+    const int mv = nk + 2 * (nb - nk / 2);     // basis size of a full cycle
+    Vec T((size_t)mv * mv, 0.0);
+    for (int i = 0; i < nk; ++i) T[(size_t)i * mv + i] = tkeep[i];
+    Q.push_back(x0);
+    Q.push_back(x1);
+    zq.push_back(z0);
+    zq.push_back(z1);
+    bool breakdown = false;
+    for (int jb = nk / 2; jb < nb; ++jb) {
+      const int a = 2 * jb;  // first column of X_j in Q
+      Vec w0(n), w1(n);
+      apply_laplacian(g, Q[a], w0);
+      apply_laplacian(g, Q[a + 1], w1);
+      info.matvecs += 2;
+      tnorm = std::max(tnorm, std::max(norm2(w0), norm2(w1)));
+      const int nq = a + 2;
+      Vec hs((size_t)nq * 2, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int c = 0; c < 2; ++c) {
+          Vec &w = c ? w1 : w0;
+          const double *pw = w.data();
+          const double h0 = fixed_sum(n, [=](int64_t i) { return u0 * pw[i]; });
+          std::vector<double> h(nq);
+          for (int k = 0; k < nq; ++k) h[k] = dot(Q[k], w);
+          for (int64_t i = 0; i < n; ++i) {
+            double s = h0 * u0;
+            for (int k = 0; k < nq; ++k) s += h[k] * Q[k][i];
+            w[i] -= s;
+          }
+          for (int k = 0; k < nq; ++k) hs[(size_t)k * 2 + c] += h[k];
+        }
+      }
+      for (int k = 0; k < a; ++k)
+        for (int c = 0; c < 2; ++c)
+          T[(size_t)k * mv + a + c] = T[(size_t)(a + c) * mv + k] = hs[(size_t)k * 2 + c];
+      T[(size_t)a * mv + a] = hs[(size_t)a * 2 + 0];
+      T[(size_t)(a + 1) * mv + a + 1] = hs[(size_t)(a + 1) * 2 + 1];
+      T[(size_t)a * mv + a + 1] = T[(size_t)(a + 1) * mv + a] =
+          0.5 * (hs[(size_t)a * 2 + 1] + hs[(size_t)(a + 1) * 2 + 0]);
+      // the remainder block: the next X (or, after the last block, the
+      // continuation of a thick restart)
+      block_cholqr2(w0, w1, kBlockDeflAbs * tnorm, z0, z1);
+      x0.swap(w0);
+      x1.swap(w1);
+      if (z0 && z1) {
+        breakdown = true;
+        break;
+      }
+      if (jb + 1 < nb) {
+        Q.push_back(x0);
+        Q.push_back(x1);
+        zq.push_back(z0);
+        zq.push_back(z1);
+      }
+    }
+    // Ritz pairs of T (its leading k x k part)
+    const int k = (int)Q.size();
+    double big = 0.0;
+    for (int r = 0; r < k; ++r) {
+      if (zq[r]) continue;
+      double rs = 0.0;
+      for (int c = 0; c < k; ++c) rs += std::fabs(T[(size_t)r * mv + c]);
+      big = std::max(big, rs);
+    }
+    big = 1.0 + 2.0 * big;
+    Vec Tk((size_t)k * k);
+    for (int r = 0; r < k; ++r)
+      for (int c = 0; c < k; ++c) Tk[(size_t)r * k + c] = T[(size_t)r * mv + c];
+    for (int r = 0; r < k; ++r)
+      if (zq[r]) Tk[(size_t)r * k + r] = big;
+    Vec ev, EV;
+    jacobi_eigen(k, Tk, ev, EV);
+    const int nn = std::max(2, keep);
+    std::vector<Vec> R(nn, Vec(n, 0.0));
+    for (int c = 0; c < nn && c < k; ++c)
+      for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int r = 0; r < k; ++r) s += EV[(size_t)r * k + c] * Q[r][i];
+        R[c][i] = s;
+      }
+    th1 = ev[0];
+    th2 = ev[1];
+    has2 = ev[1] < big;
+    y1 = R[0];
+    y2 = R[1];
+    res1 = residual_norm(g, y1, th1, info.matvecs);
+    const double res2 = has2 ? residual_norm(g, y2, th2, info.matvecs) : 0.0;
+    info.cycles = cycle + 1;
+    if (res1 <= o.tol * th1 && (!has2 || res2 <= o.tol * th2)) {
+      converged = 1;
+      break;
+    }
+    if (cycle == o.max_restarts) break;
+    if (keep == 0 || breakdown) {
+      Q.clear();
+      zq.clear();
+      tkeep.clear();
+      x0 = y1;
+      x1 = y2;
+      deflate_ones(x0);
+      deflate_ones(x1);
+      block_cholqr2(x0, x1, kBlockDeflAbs, z0, z1);
+      continue;
+    }
+    // thick restart: x0, x1 hold the last remainder block
+    Q.assign(R.begin(), R.begin() + keep);
+    zq.assign(keep, 0);
+    tkeep.assign(ev.begin(), ev.begin() + keep);
+    for (int c = 0; c < keep; ++c) zq[c] = !(ev[c] < big);
+  }
+  if (o.fiedler_sweep > 0 && has2 && th2 - th1 <= o.sweep_gap * th1) {
+    double c1 = 0.0, c2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double s = start_value(o.seed, gid[i]);
+      c1 += s * y1[i];
+      c2 += s * y2[i];
+    }
+    const double cn = std::sqrt(c1 * c1 + c2 * c2);
+    if (cn > 0.0)
+      for (int64_t i = 0; i < n; ++i) {
+        const double a1 = y1[i], a2 = y2[i];
+        y1[i] = (c1 * a1 + c2 * a2) / cn;
+        y2[i] = (c1 * a2 - c2 * a1) / cn;
+      }
+  }
+  normalize(y1);
+  y = y1;
+  info.theta = th1;
+  info.residual = res1;
+  info.converged = converged;
+  lambda = rayleigh(g, y, info.matvecs);
+  canonical_sign(y, gid);
+  pair.ok = has2;
+  pair.theta1 = th1;
+  pair.theta2 = th2;
+  pair.y2 = y2;
+  return converged ? 0 : 1;
+}
+
+// ---------------------------------------------------------------------------
 // Aggregation multigrid preconditioner for the inverse-iteration solves
 // (Sec. 7, Alg. 3).  Every level is the Laplacian of a graph with integer
 // weights; the next level collapses pairs of rows (piecewise-constant
@@ -1084,6 +1329,8 @@ int bisect(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const
   SecondPair second;
   if (o.method == ORC_INVERSE_CG) {
     st = inverse_fiedler(sub, sub_gid, o, ys, lambda, info);
+  } else if (o.method == ORC_BLOCK) {
+    st = block_fiedler(sub, sub_gid, o, ys, lambda, info, second, warm);
   } else {
     st = lanczos_fiedler(sub, sub_gid, o, ys, lambda, info,
                          (o.fiedler_sweep > 0 || warm) ? &second : nullptr, warm);
@@ -1104,7 +1351,8 @@ int bisect(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const
     for (size_t i = 0; i < sub_gid.size(); ++i) (*warm)[sub_gid[i]] = second.y2[i] * scale;
   }
   std::vector<uint8_t> sub_side;
-  if (o.second_solve && o.fiedler_sweep > 0 && o.method != ORC_INVERSE_CG) {
+  if (o.second_solve && o.fiedler_sweep > 0 && o.method != ORC_INVERSE_CG &&
+      o.method != ORC_BLOCK) {
     // the pair from two solves: Lanczos again from another random start
     // (no warm start); a second vector within sweep_gap of the first and at
     // least 0.1 away from its direction is swept with it, a vector the
@@ -1344,6 +1592,31 @@ int orc_fiedler_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const
   if (info) *info = li;
   if (st < 0) return st;
   std::copy(yv.begin(), yv.end(), y);
+  return st;
+}
+
+int orc_block_pair(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                   const int64_t *gid, const orc_opts *o, double *y1, double *y2, double *theta,
+                   orc_info *info) {
+  if (n < 2 || !row_ptr || !col || !weight || !gid || !o || !y1 || !y2 || !theta) return -1;
+  if (o->lanczos_m < 4 || o->lanczos_m % 2 || o->lanczos_keep < 0 || o->lanczos_keep % 2 ||
+      o->lanczos_keep > o->lanczos_m - 4)
+    return -1;
+  Graph g;
+  to_graph(n, row_ptr, col, weight, g);
+  std::vector<int64_t> gv(gid, gid + n);
+  std::vector<int32_t> comp;
+  if (components(g, gv, comp) != 1) return -2;
+  Vec yv;
+  double lambda = 0.0;
+  orc_info li{};
+  SecondPair pair;
+  const int st = block_fiedler(g, gv, *o, yv, lambda, li, pair);
+  if (info) *info = li;
+  std::copy(yv.begin(), yv.end(), y1);
+  for (int64_t i = 0; i < n; ++i) y2[i] = pair.y2[i];
+  theta[0] = pair.theta1;
+  theta[1] = pair.ok ? pair.theta2 : INFINITY;
   return st;
 }
 

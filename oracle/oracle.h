@@ -33,14 +33,17 @@ extern "C" {
 #endif
 
 enum { ORC_GRAPH_WEIGHTED = 0, ORC_GRAPH_UNIT = 1, ORC_GRAPH_FACE = 2 };
-enum { ORC_LANCZOS = 0, ORC_INVERSE_CG = 1, ORC_AUTO = 2 };
+enum { ORC_LANCZOS = 0, ORC_INVERSE_CG = 1, ORC_AUTO = 2, ORC_BLOCK = 3 };
 enum { ORC_PRECOND_NONE = 0, ORC_PRECOND_AMG = 1 };
 
 typedef struct orc_opts {
   int32_t graph;             /* ORC_GRAPH_* */
-  int32_t method;            /* ORC_LANCZOS, ORC_INVERSE_CG, or ORC_AUTO: Lanczos,
+  int32_t method;            /* ORC_LANCZOS, ORC_INVERSE_CG, ORC_AUTO: Lanczos,
                                 and inverse iteration from a fresh random start
-                                where Lanczos does not converge (Sec. 7) */
+                                where Lanczos does not converge (Sec. 7), or
+                                ORC_BLOCK: block Lanczos of two vectors giving
+                                the Fiedler pair (Sec. 9; lanczos_m even >= 4,
+                                lanczos_keep even <= lanczos_m - 4) */
   int32_t lanczos_m;         /* Lanczos steps per cycle */
   int32_t max_restarts;      /* cycles after the first one */
   double tol;                /* stop when ||L y - rho y|| <= tol * rho, rho = y^T L y */
@@ -131,6 +134,17 @@ int orc_fiedler(int64_t nelem, int32_t nv, const int64_t *ids, const orc_opts *o
 int orc_fiedler_csr(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
                     const int64_t *gid, const orc_opts *o, double *y, double *lambda,
                     orc_info *info);
+
+/* Block Lanczos of two vectors (method ORC_BLOCK's solver) on a connected
+ * CSR graph: y1 (unit norm, canonical sign) and y2 (unit norm, orthogonal to
+ * y1; zero when the graph has no second direction) span the pair's plane;
+ * theta[0] <= theta[1] are the Ritz values of the pair (theta[1] = +inf
+ * without a second direction).  A pair within sweep_gap (fiedler_sweep > 0)
+ * is rotated so that y1 is the projection of the random start on its plane.
+ * Returns 0 converged, 1 not converged, -1 bad input, -2 disconnected. */
+int orc_block_pair(int64_t n, const int64_t *row_ptr, const int32_t *col, const int32_t *weight,
+                   const int64_t *gid, const orc_opts *o, double *y1, double *y2, double *theta,
+                   orc_info *info);
 
 /* One inner solve of inverse iteration (Sec. 7, Alg. 2): CG for L x = b on
  * the ones-complement, from x = 0, with the options' cg_tol, cg_max_iter,
