@@ -61,6 +61,16 @@ extern "C" {
                             again by inverse iteration from the random start
                             (Sec. 7: the paper's fallback where Lanczos did not
                             converge) */
+#define RSB_BLOCK 3      /* block Lanczos of two vectors, orthogonalised together at
+                            every step (Sec. 9: the block iteration that finds both
+                            vectors of an exactly degenerate Fiedler pair): one
+                            solve gives the pair for fiedler_sweep.  FP64 whatever
+                            precision says; lanczos_m (even, 4..48) basis vectors
+                            per cycle, lanczos_keep (even, <= lanczos_m - 4) kept
+                            Ritz vectors of a thick restart (0: explicit restart
+                            from the pair); converged when both Ritz pairs meet
+                            tol (the second when there is one).  lanczos_s,
+                            gather_scatter and second_solve do not apply. */
 
 #define RSB_PRECOND_NONE 0 /* INVERSE_CG: plain CG */
 #define RSB_PRECOND_AMG 1  /* INVERSE_CG: aggregation multigrid V-cycle (Sec. 7, Alg. 3) */
@@ -83,7 +93,7 @@ extern "C" {
 typedef struct rsb_opts {
   int32_t struct_size;      /* sizeof(rsb_opts); set by rsb_opts_init */
   int32_t graph;            /* RSB_GRAPH_* */
-  int32_t method;           /* RSB_LANCZOS, RSB_INVERSE_CG or RSB_AUTO */
+  int32_t method;           /* RSB_LANCZOS, RSB_INVERSE_CG, RSB_AUTO or RSB_BLOCK */
   int32_t precision;        /* RSB_FP64 or RSB_MIXED */
   int32_t lanczos_m;        /* Lanczos steps per cycle (default 100, max 250) */
   int32_t max_restarts;     /* restarts after the first cycle (default 50) */

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librsb.so")
 
 GRAPH = {"weighted": 0, "unit": 1, "face": 2}
-METHOD = {"lanczos": 0, "inverse_cg": 1, "auto": 2}
+METHOD = {"lanczos": 0, "inverse_cg": 1, "auto": 2, "block": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 PRECOND = {"none": 0, "amg": 1}
 

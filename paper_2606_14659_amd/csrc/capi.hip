@@ -76,7 +76,7 @@ void check_opts(const rsb_opts *o) {
   if (o->struct_size != (int32_t)sizeof(rsb_opts))
     fail(RSB_EINVAL, "opts->struct_size mismatch (call rsb_opts_init)");
   if (o->graph < 0 || o->graph > 2) fail(RSB_EINVAL, "graph kind");
-  if (o->method < 0 || o->method > 2) fail(RSB_EINVAL, "method");
+  if (o->method < 0 || o->method > 3) fail(RSB_EINVAL, "method");
   if (o->precision < 0 || o->precision > 1) fail(RSB_EINVAL, "precision");
   if (o->lanczos_m < 1 || o->lanczos_m > kMaxM) fail(RSB_EINVAL, "lanczos_m must be in [1, 250]");
   if (o->max_restarts < 0) fail(RSB_EINVAL, "negative max_restarts");
@@ -88,6 +88,14 @@ void check_opts(const rsb_opts *o) {
   if (o->lanczos_keep < 0 || o->lanczos_keep > kMaxKeep ||
       (o->lanczos_keep > 0 && o->lanczos_keep >= o->lanczos_m))
     fail(RSB_EINVAL, "lanczos_keep must be 0 or in [1, min(16, lanczos_m - 1)]");
+  if (o->method == RSB_BLOCK) {
+    if (o->lanczos_m < 4 || o->lanczos_m > kBkMaxM || o->lanczos_m % 2)
+      fail(RSB_EINVAL, "RSB_BLOCK: lanczos_m must be even and in [4, 48]");
+    if (o->lanczos_keep % 2 || o->lanczos_keep > o->lanczos_m - 4)
+      fail(RSB_EINVAL, "RSB_BLOCK: lanczos_keep must be even and at most lanczos_m - 4");
+    if (o->gather_scatter) fail(RSB_EINVAL, "RSB_BLOCK does not take gather_scatter");
+    if (o->second_solve) fail(RSB_EINVAL, "RSB_BLOCK gives the pair itself: no second_solve");
+  }
   if (o->rows_per_thread != 0 && o->rows_per_thread != 2 && o->rows_per_thread != 4 &&
       o->rows_per_thread != 8)
     fail(RSB_EINVAL, "rows_per_thread must be 0, 2, 4 or 8");
@@ -97,8 +105,9 @@ void check_opts(const rsb_opts *o) {
   if (!(o->amg_sigma > 0.0 && o->amg_sigma < 2.0)) fail(RSB_EINVAL, "amg_sigma must be in (0, 2)");
   if (o->fiedler_sweep < 0 || o->fiedler_sweep > 64)
     fail(RSB_EINVAL, "fiedler_sweep must be in [0, 64]");
-  if (o->fiedler_sweep > 0 && (o->method == RSB_INVERSE_CG || o->lanczos_keep < 2))
-    fail(RSB_EINVAL, "fiedler_sweep needs Lanczos (RSB_LANCZOS or RSB_AUTO) with lanczos_keep >= 2");
+  if (o->fiedler_sweep > 0 && o->method != RSB_BLOCK &&
+      (o->method == RSB_INVERSE_CG || o->lanczos_keep < 2))
+    fail(RSB_EINVAL, "fiedler_sweep needs RSB_BLOCK, or Lanczos (RSB_LANCZOS or RSB_AUTO) with lanczos_keep >= 2");
   if (!(o->sweep_gap >= 0.0)) fail(RSB_EINVAL, "sweep_gap must be >= 0");
   if (o->warm_start != 0 && o->warm_start != 1) fail(RSB_EINVAL, "warm_start must be 0 or 1");
   if (o->reorder != 0 && o->reorder != 1) fail(RSB_EINVAL, "reorder must be 0 or 1");
@@ -112,8 +121,9 @@ void check_opts(const rsb_opts *o) {
     fail(RSB_EINVAL, "gather_scatter must be 0 or 1");
   if (o->gather_scatter && (o->graph != RSB_GRAPH_WEIGHTED || o->method == RSB_INVERSE_CG))
     fail(RSB_EINVAL, "gather_scatter needs graph RSB_GRAPH_WEIGHTED and Lanczos (RSB_LANCZOS or RSB_AUTO)");
-  if (o->warm_start && (o->method == RSB_INVERSE_CG || o->lanczos_keep < 2))
-    fail(RSB_EINVAL, "warm_start needs Lanczos (RSB_LANCZOS or RSB_AUTO) with lanczos_keep >= 2");
+  if (o->warm_start && o->method != RSB_BLOCK &&
+      (o->method == RSB_INVERSE_CG || o->lanczos_keep < 2))
+    fail(RSB_EINVAL, "warm_start needs RSB_BLOCK, or Lanczos (RSB_LANCZOS or RSB_AUTO) with lanczos_keep >= 2");
 }
 
 void setup_ctx(Ctx &ctx, const rsb_opts &o, bool private_stream = true) {
@@ -214,6 +224,11 @@ void one_segment_tables(const Level &L, int s, OneSeg &o, Ctx &ctx) {
   o.ngrp = tmp.ngrp;
 }
 
+// Ritz buffers per segment: the kept count, or the pair of the block solver.
+int solve_keep(const rsb_opts &o) {
+  return o.method == RSB_BLOCK ? std::max(o.lanczos_keep, 2) : o.lanczos_keep;
+}
+
 // Eigen-solve of one level: all segments batched, or one segment at a time.
 // RSB_AUTO runs Lanczos and then, for every segment Lanczos left
 // unconverged, inverse iteration from the random start (Sec. 7: the paper
@@ -223,6 +238,11 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
                     int *amg_levels, int *fallbacks, Ctx &ctx) {
   const bool mixed = o.precision == RSB_MIXED;
   auto run = [&](const LevelView &v, SolveDev &SS, bool graph, bool inverse) -> int64_t {
+    if (o.method == RSB_BLOCK) {
+      BlockParams bp{o.lanczos_m, o.lanczos_keep, o.max_restarts, o.tol,
+                     o.seed,      warm,           o.fiedler_sweep, o.sweep_gap};
+      return block_level(v, C, SS, bp, y64, y2, ctx);
+    }
     if (inverse) {
       InverseParams ip{o.inv_max_outer, o.cg_max_iter, o.cg_tol,     o.tol,
                        o.seed,          o.inv_precond, o.amg_sigma,  o.amg_smooth,
@@ -240,7 +260,7 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     OneSeg os;
     one_segment_tables(L, s, os, ctx);
     SolveDev S1;
-    solve_alloc(S1, 1, os.nblk, os.ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
+    solve_alloc(S1, 1, os.nblk, os.ngrp, std::max(o.lanczos_m, 1), solve_keep(o), ctx);
     RSB_HIP(hipMemcpyAsync(S1.st.get(), S.st.get() + s, sizeof(SegState),
                            hipMemcpyDeviceToDevice, ctx.stream));
     LevelView v = view_of(L);
@@ -452,7 +472,7 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
       st.spmv_words_us = spmv_words_us(view_of(*L), f32, 20, ctx);
       st.spmv_words_bytes = 4.0 * (n + 1.0) + 4.0 * (double)L->nnz + 2.0 * sv * n;
     }
-    solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), o.lanczos_keep, ctx);
+    solve_alloc(S, L->nseg, L->nblk, L->ngrp, std::max(o.lanczos_m, 1), solve_keep(o), ctx);
     components_and_targets(*L, C, S, ctx);
     phase_to(lv + " solve");
     int amg_levels = 0;

@@ -366,6 +366,26 @@ template <typename T>
 int64_t lanczos_level(const LevelView &L, CompDev &C, SolveDev &S, const LanczosParams &p,
                       void *work, double *y64_out, Ctx &ctx);
 
+// Block Lanczos of two vectors (method RSB_BLOCK, FP64): the Fiedler pair of
+// every segment with a component to cut.  y64 receives y1, y2 (if non-null)
+// y2 (zero without a second direction); S.tvals holds the pair's Ritz values
+// (second: 1e300 without a second direction), S.st the Fiedler vector's
+// Rayleigh quotient, residual, cycles and convergence.  Returns the block
+// steps launched.
+constexpr int kBkMaxM = 48;  // largest basis of a block Lanczos cycle
+struct BlockParams {
+  int m;                 // basis vectors per cycle (even): m / 2 blocks
+  int keep;              // 0: explicit restart from the pair; k > 0 (even): thick restart
+  int max_restarts;
+  double tol;
+  uint64_t seed;
+  const double *warm;    // non-null: warm start of column 0 by element index (NaN: none)
+  int sweep;             // > 0: a pair within sweep_gap is rotated to the start's projection
+  double sweep_gap;
+};
+int64_t block_level(const LevelView &L, CompDev &C, SolveDev &S, const BlockParams &p,
+                    double *y64, double *y2, Ctx &ctx);
+
 // Aggregation multigrid hierarchy of a bisection level (preconditioner of
 // the inverse-iteration solves).  Level 0 aliases the level's packed sliced
 // ELL; coarse levels own sliced-ELL column and weight words.

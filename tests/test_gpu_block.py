@@ -1,0 +1,157 @@
+"""GPU parity of the block Lanczos of two vectors (method "block", the
+paper's Sec. 9 proposal), against the oracle's block Lanczos on the same
+seeded inputs: Ritz values after a fixed number of cycles (explicit and thick
+restart, which depend on every step of a cycle), converged Fiedler pairs
+element by element, partitions identical on unique-axis boxes and on an
+exactly degenerate box swept with the pair (whose cut a one-vector solve
+cannot reach), cuts within 1% on holed meshes, tiny components that exhaust
+the block Krylov space, and batched = one subgraph at a time = batch call.
+"""
+import numpy as np
+import pytest
+
+import meshgen as mg
+import paper_2606_14659_amd as rsb
+from spectral_util import assert_fiedler_close, lambda23
+
+pytestmark = pytest.mark.gpu
+
+MESHES = {
+    "holes": lambda: mg.uniform_holes(mg.box_hex(23, 17, 9), 0.07, 3).ids,
+    "clustered": lambda: mg.clustered_holes(mg.box_hex(30, 26, 22), 0.1, 9).ids,
+    "quad": lambda: mg.uniform_holes(mg.box_quad(150, 97), 0.05, 4).ids,
+}
+
+
+@pytest.mark.parametrize("restarts", [0, 2])
+@pytest.mark.parametrize("m,keep", [(20, 0), (40, 8), (24, 4)])
+@pytest.mark.parametrize("name", list(MESHES))
+def test_cycles_match_oracle(orc, name, m, keep, restarts):
+    ids = MESHES[name]()
+    kw = dict(method="block", lanczos_m=m, lanczos_keep=keep, tol=1e-15,
+              max_restarts=restarts)
+    print(f"[block] cycles {name} m {m} keep {keep} restarts {restarts}", flush=True)
+    st, lam, y, stats = rsb.fiedler(ids, **kw)
+    ost, olam, oy, oinfo = orc.fiedler(ids, **kw)
+    assert stats["cycles"] == oinfo["cycles"] == restarts + 1
+    assert abs(lam - olam) <= 1e-10 * olam
+    # the Ritz vector after these cycles, element by element
+    assert np.abs(y - oy).max() <= 1e-7 * np.abs(oy).max()
+
+
+@pytest.mark.parametrize("name,m,keep,tol", [
+    ("holes", 40, 8, 1e-8), ("clustered", 40, 8, 1e-8), ("quad", 40, 8, 1e-8),
+    ("holes", 40, 0, 1e-7), ("clustered", 40, 0, 1e-7)])
+def test_fiedler_converged(orc, name, m, keep, tol):
+    ids = MESHES[name]()
+    kw = dict(method="block", lanczos_m=m, lanczos_keep=keep, max_restarts=2000)
+    print(f"[block] converged {name} m {m} keep {keep}", flush=True)
+    st, lam, y, stats = rsb.fiedler(ids, tol=tol, **kw)
+    ost, olam, oy, oinfo = orc.fiedler(ids, tol=1e-10, **dict(kw, lanczos_keep=8))
+    assert st == 0 and ost == 0
+    assert abs(lam - olam) <= max(tol, 1e-9) * olam
+    l2, l3 = lambda23(orc, ids)
+    assert_fiedler_close(y, oy, stats["residual"], oinfo["residual"], l3 - l2)
+
+
+@pytest.mark.parametrize("dims,nparts", [((16, 16, 4), 2), ((16, 16, 4), 4), ((20, 20, 6), 8)])
+def test_degenerate_box_swept_like_oracle(orc, dims, nparts):
+    # lambda_2 = lambda_3 exactly: the block finds the plane, the sweep picks
+    # the axis-aligned cut; the one-vector solve with the sweep cannot
+    ids = mg.box_hex(*dims).ids
+    kw = dict(graph="face", lanczos_m=40, lanczos_keep=8, tol=1e-8, fiedler_sweep=16)
+    print(f"[block] degenerate {dims} {nparts}", flush=True)
+    st, part, s = rsb.partition(ids, nparts, method="block", **kw)
+    ost, opart, oinfo = orc.partition(ids, nparts, method="block", **kw)
+    assert st == ost == 0 and np.array_equal(part, opart)
+    assert s["sweeps"] == oinfo["sweeps"] >= 1
+    st1, p1, s1 = rsb.partition(ids, nparts, **kw)
+    cut = orc.metrics(ids, part, nparts)["weighted_cut"]
+    cut1 = orc.metrics(ids, p1, nparts)["weighted_cut"]
+    assert s1["sweeps"] == 0 and cut < cut1
+
+
+@pytest.mark.parametrize("keep", [0, 8])
+def test_partition_identical_on_unique_axis_box(orc, keep):
+    ids = mg.box_hex(24, 20, 18).ids
+    kw = dict(graph="face", method="block", lanczos_m=40, lanczos_keep=keep, tol=1e-8,
+              warm_start=1)
+    st, part, _ = rsb.partition(ids, 8, **kw)
+    ost, opart, _ = orc.partition(ids, 8, **kw)
+    # (explicit restart leaves a bisection at the restart cap: status 1 on both)
+    assert st == ost and np.array_equal(part, opart)
+
+
+@pytest.mark.parametrize("sweep", [0, 8])
+@pytest.mark.parametrize("name,nparts", [("holes", 16), ("clustered", 32), ("quad", 12)])
+def test_partition_cut_within_one_percent(orc, name, nparts, sweep):
+    ids = MESHES[name]()
+    kw = dict(method="block", lanczos_m=40, lanczos_keep=8, tol=1e-6, warm_start=1,
+              fiedler_sweep=sweep)
+    print(f"[block] partition {name} {nparts} sweep {sweep}", flush=True)
+    st, part, s = rsb.partition(ids, nparts, **kw)
+    ost, opart, oinfo = orc.partition(ids, nparts, **kw)
+    assert st >= 0 and ost >= 0
+    sizes = np.bincount(part, minlength=nparts)
+    assert sizes.min() >= len(ids) // nparts and sizes.max() <= -(-len(ids) // nparts)
+    cut = orc.metrics(ids, part, nparts)["weighted_cut"]
+    ocut = orc.metrics(ids, opart, nparts)["weighted_cut"]
+    assert abs(cut - ocut) <= 0.01 * ocut
+
+
+SMALL = [lambda: mg.box_quad(2, 1), lambda: mg.box_quad(3, 1), lambda: mg.box_quad(2, 2),
+         lambda: mg.box_quad(4, 2), lambda: mg.box_quad(4, 3), lambda: mg.box_hex(2, 2, 2),
+         lambda: mg.box_hex(3, 2, 2)]
+
+
+@pytest.mark.parametrize("keep", [0, 4])
+@pytest.mark.parametrize("k", range(len(SMALL)))
+def test_small_graph_exact_after_one_cycle(orc, k, keep):
+    # the whole space fits one cycle (20 basis vectors): exact pair after it,
+    # exhausted columns dropped; no second vector on two elements
+    ids = SMALL[k]().ids
+    rp, col, w = orc.dual_graph(ids)
+    from test_oracle_pins import dense_laplacian
+    ev = np.linalg.eigvalsh(dense_laplacian(rp, col, w))
+    st, lam, y, s = rsb.fiedler(ids, method="block", lanczos_m=20, lanczos_keep=keep, tol=1e-10,
+                                max_restarts=0)
+    assert st == 0 and s["cycles"] == 1
+    assert abs(lam - ev[1]) <= 1e-12 * ev[-1]
+    assert abs(np.linalg.norm(y) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("keep", [0, 4])
+def test_tiny_components_partition(orc, keep):
+    # small pieces next to a larger box; symmetric pieces split through
+    # elements of equal value in exact arithmetic (either side is correct),
+    # so sizes, status and the cut are compared, not the labels
+    pieces = [p() for p in SMALL[:5]] + [mg.box_quad(20, 14)]
+    ids, off = [], 0
+    for p in pieces:
+        ids.append(p.ids + off)
+        off = int(p.ids.max()) + 1 + off
+    ids = np.concatenate(ids)
+    for nparts in (2, 5, 17, 40):
+        kw = dict(method="block", lanczos_m=20, lanczos_keep=keep, tol=1e-8, max_restarts=300,
+                  fiedler_sweep=8)
+        print(f"[block] tiny keep {keep} nparts {nparts}", flush=True)
+        st, part, s = rsb.partition(ids, nparts, **kw)
+        ost, opart, _ = orc.partition(ids, nparts, **kw)
+        assert st == ost
+        sizes = np.bincount(part, minlength=nparts)
+        assert sizes.min() >= len(ids) // nparts and sizes.max() <= -(-len(ids) // nparts)
+        cut = orc.metrics(ids, part, nparts)["weighted_cut"]
+        ocut = orc.metrics(ids, opart, nparts)["weighted_cut"]
+        assert cut <= 1.02 * ocut + 2
+
+
+def test_batched_unbatched_and_batch_call():
+    meshes = [MESHES["holes"](), mg.box_hex(16, 16, 4).ids, MESHES["clustered"]()]
+    nparts = [8, 4, 6]
+    kw = dict(method="block", lanczos_m=40, lanczos_keep=8, tol=1e-6, warm_start=1,
+              fiedler_sweep=8)
+    st, parts, _ = rsb.partition_batch(meshes, nparts, **kw)
+    for b, ids in enumerate(meshes):
+        s1, p1, _ = rsb.partition(ids, nparts[b], **kw)
+        s2, p2, _ = rsb.partition(ids, nparts[b], batched=0, **kw)
+        assert np.array_equal(p1, parts[b]) and np.array_equal(p1, p2)

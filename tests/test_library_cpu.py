@@ -54,7 +54,7 @@ def test_bad_options_rejected_before_any_device_call():
     o = rsb.Opts()
     rsb.lib().rsb_opts_init(C.byref(o))
     bad = []
-    for field, value in (("struct_size", 4), ("graph", 7), ("method", 3), ("method", -1),
+    for field, value in (("struct_size", 4), ("graph", 7), ("method", 4), ("method", -1),
                          ("lanczos_m", 0), ("lanczos_m", 251),
                          ("tol", 0.0), ("cg_full_projection", 33), ("cg_full_projection", -1),
                          ("precision", 5),
@@ -86,6 +86,17 @@ def test_bad_options_rejected_before_any_device_call():
         part = np.zeros(2, dtype=np.int32)
         assert rsb.lib().rsb_partition(2, 4, ids.ctypes.data_as(C.c_void_p), 2, C.byref(oo),
                                        part.ctypes.data_as(C.c_void_p), None) == rsb.EINVAL
+    # the block solver: an even basis of 4..48 vectors, an even kept count
+    # leaving two blocks, no gather-scatter operator, no second solve
+    for m, keep, gs, second in ((41, 8, 0, 0), (50, 8, 0, 0), (2, 0, 0, 0), (40, 7, 0, 0),
+                                (40, 38, 0, 0), (40, 8, 1, 0), (40, 8, 0, 1)):
+        oo = rsb.Opts.from_buffer_copy(o)
+        oo.method, oo.lanczos_m, oo.lanczos_keep = 3, m, keep
+        oo.gather_scatter, oo.second_solve, oo.fiedler_sweep = gs, second, 8 * second
+        part = np.zeros(2, dtype=np.int32)
+        assert rsb.lib().rsb_partition(2, 4, ids.ctypes.data_as(C.c_void_p), 2, C.byref(oo),
+                                       part.ctypes.data_as(C.c_void_p), None) == rsb.EINVAL, \
+            (m, keep, gs, second)
     # the gather-scatter operator is the weighted Laplacian, applied by Lanczos
     for graph, method in ((1, 0), (2, 0), (0, 1)):
         oo = rsb.Opts.from_buffer_copy(o)
