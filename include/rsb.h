@@ -146,17 +146,22 @@ typedef struct rsb_opts {
                                coarse Laplacians, per subgraph. */
   int32_t amg_smooth;       /* AMG: damped-Jacobi steps per smoothing phase (1) */
   double amg_sigma;         /* AMG: Jacobi damping weight (2/3) */
-  int32_t fiedler_sweep;    /* Lanczos (RSB_LANCZOS or RSB_AUTO) with lanczos_keep >= 2:
-                               S > 0 sweeps the
+  int32_t fiedler_sweep;    /* RSB_BLOCK, or Lanczos (RSB_LANCZOS or RSB_AUTO) with
+                               lanczos_keep >= 2: S > 0 sweeps the
                                Fiedler pair (Sec. 9: search the combinations of a
                                near-degenerate pair for the smallest cut).  When
                                the second Ritz value is within sweep_gap of the
                                first, S combinations cos(a) y1 + sin(a) y2,
                                a = k pi / S, are split and the one that cuts the
                                least weight is used (ties: smallest k).  0: off
-                               (default); at most 64.  An exactly degenerate pair
-                               shows a single Ritz vector and is not swept. */
-  int32_t warm_start;       /* Lanczos (LANCZOS or AUTO), lanczos_keep >= 2: 1 = the solve of a
+                               (default); at most 64.  With one-vector Lanczos an
+                               exactly degenerate pair shows a single Ritz vector
+                               and is not swept; RSB_BLOCK finds both and, for a
+                               pair within sweep_gap, first rotates it within its
+                               plane so that y1 is the projection of the random
+                               start (a well-defined basis). */
+  int32_t warm_start;       /* RSB_BLOCK, or Lanczos (LANCZOS or AUTO) with lanczos_keep
+                               >= 2: 1 = the solve of a
                                subgraph starts from its parent's second Ritz
                                vector (unit root-mean-square on the parent's cut
                                component) plus 0.1 x the random start; elements
