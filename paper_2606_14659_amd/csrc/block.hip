@@ -430,78 +430,111 @@ __global__ __launch_bounds__(kBlock) void k_bk_output(BkArgs a, double *__restri
 }
 
 // ----------------------------------------------------------------------------
-// Eigenpairs of the cycle's projected matrix, one wave per segment: cyclic
-// Jacobi (Golub & Van Loan, Sec. 8.5) in the (p, q) order p < q, rotations
-// applied to the columns, then the rows, of A and to the columns of V; the
-// eigenvalues sorted ascending (stable).  Output: the first max(2, keep)
-// Ritz values and coefficient vectors.
+// Eigenpairs of the cycle's projected matrix, one wave per segment: Jacobi
+// rotations (Golub & Van Loan, Sec. 8.5) in round-robin order -- in each of
+// the k - 1 rounds of a sweep the k / 2 pairs (p, q) of the circle method are
+// disjoint, so their rotations commute and are applied together: angles from
+// the current matrix, then the columns of A and V (one row per lane), then
+// the rows of A (one column per lane).  Sweeps until the off-diagonal part
+// is at rounding level; eigenvalues sorted ascending (stable).  Output: the
+// first max(2, keep) Ritz values and coefficient vectors.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(kWave) void k_bk_eig(BkArgs a) {
-  __shared__ double A[kBkMaxM * kBkMaxM];
-  __shared__ double V[kBkMaxM * kBkMaxM];
+  // rows padded to an odd number of doubles: the lanes' row accesses of a
+  // column spread over the LDS banks
+  __shared__ double A[kBkMaxM * (kBkMaxM + 1)];
+  __shared__ double V[kBkMaxM * (kBkMaxM + 1)];
+  __shared__ double rc[kBkMaxM / 2], rs_[kBkMaxM / 2];
+  __shared__ int32_t rp[kBkMaxM / 2], rq[kBkMaxM / 2];
   __shared__ int32_t ord[kBkMaxM];
   const int s = blockIdx.x;
   const BkState B = a.bs[s];
   if (!B.active) return;
-  const int k = B.nv;
+  const int k = B.nv;  // even
+  const int h = k / 2;
+  const int ld = k + 1;
   const int lane = threadIdx.x;
   const double *T = a.Tm + (int64_t)s * a.m * a.m;
   const int32_t *zq = a.Zq + (int64_t)s * a.m;
   for (int i = lane; i < k * k; i += kWave) {
-    A[i] = T[(int64_t)(i / k) * a.m + i % k];
-    V[i] = (i / k == i % k) ? 1.0 : 0.0;
+    const int r = i / k, c = i % k;
+    A[r * ld + c] = T[(int64_t)r * a.m + c];
+    V[r * ld + c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
   // diagonal of the dropped columns: above every eigenvalue (row-sum bound)
   double rs = 0.0;
   if (lane < k && !zq[lane])
-    for (int c = 0; c < k; ++c) rs += fabs(A[lane * k + c]);
+    for (int c = 0; c < k; ++c) rs += fabs(A[lane * ld + c]);
   for (int off = kWave / 2; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off, kWave));
   const double big = 1.0 + 2.0 * rs;
   __syncthreads();
-  if (lane < k && zq[lane]) A[lane * k + lane] = big;
+  if (lane < k && zq[lane]) A[lane * ld + lane] = big;
   __syncthreads();
   double f = 0.0;
-  for (int i = lane; i < k * k; i += kWave) f += A[i] * A[i];
+  for (int i = lane; i < k * k; i += kWave) {
+    const double v = A[(i / k) * ld + i % k];
+    f += v * v;
+  }
   const double fro = sqrt(wave_sum(f));
   for (int sweep = 0; sweep < 100; ++sweep) {
     double off = 0.0;
     for (int i = lane; i < k * k; i += kWave) {
       const int p = i / k, q = i % k;
-      if (p < q) off += 2.0 * A[i] * A[i];
+      if (p < q) off += 2.0 * A[p * ld + q] * A[p * ld + q];
     }
     off = wave_sum(off);
     if (sqrt(off) <= 1e-15 * fro || fro == 0.0) break;
-    for (int p = 0; p < k; ++p) {
-      for (int q = p + 1; q < k; ++q) {
-        const double apq = A[p * k + q];
-        if (apq == 0.0) continue;
-        const double tau = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
-        if (lane < k) {
-          const double arp = A[lane * k + p], arq = A[lane * k + q];
-          A[lane * k + p] = c * arp - sn * arq;
-          A[lane * k + q] = sn * arp + c * arq;
-          const double vrp = V[lane * k + p], vrq = V[lane * k + q];
-          V[lane * k + p] = c * vrp - sn * vrq;
-          V[lane * k + q] = sn * vrp + c * vrq;
+    for (int rnd = 0; rnd < k - 1; ++rnd) {
+      if (lane < h) {
+        // circle method: player 0 fixed, players 1..k-1 rotate by one each round
+        const int pa = lane == 0 ? 0 : 1 + (lane - 1 + rnd) % (k - 1);
+        const int pb = 1 + (k - 2 - lane + rnd) % (k - 1);
+        const int p = min(pa, pb), q = max(pa, pb);
+        const double apq = A[p * ld + q];
+        double c = 1.0, sn = 0.0;
+        if (apq != 0.0) {
+          const double tau = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = t * c;
         }
-        __syncthreads();
-        if (lane < k) {
-          const double apr = A[p * k + lane], aqr = A[q * k + lane];
-          A[p * k + lane] = c * apr - sn * aqr;
-          A[q * k + lane] = sn * apr + c * aqr;
-        }
-        __syncthreads();
+        rc[lane] = c;
+        rs_[lane] = sn;
+        rp[lane] = p;
+        rq[lane] = q;
       }
+      __syncthreads();
+      if (lane < k) {
+        for (int i = 0; i < h; ++i) {
+          const int p = rp[i], q = rq[i];
+          const double c = rc[i], sn = rs_[i];
+          const double arp = A[lane * ld + p], arq = A[lane * ld + q];
+          A[lane * ld + p] = c * arp - sn * arq;
+          A[lane * ld + q] = sn * arp + c * arq;
+          const double vrp = V[lane * ld + p], vrq = V[lane * ld + q];
+          V[lane * ld + p] = c * vrp - sn * vrq;
+          V[lane * ld + q] = sn * vrp + c * vrq;
+        }
+      }
+      __syncthreads();
+      if (lane < k) {
+        for (int i = 0; i < h; ++i) {
+          const int p = rp[i], q = rq[i];
+          const double c = rc[i], sn = rs_[i];
+          const double apr = A[p * ld + lane], aqr = A[q * ld + lane];
+          A[p * ld + lane] = c * apr - sn * aqr;
+          A[q * ld + lane] = sn * apr + c * aqr;
+        }
+      }
+      __syncthreads();
     }
   }
   if (lane < k) {
-    const double d = A[lane * k + lane];
+    const double d = A[lane * ld + lane];
     int rank = 0;
     for (int j = 0; j < k; ++j) {
-      const double e = A[j * k + j];
+      const double e = A[j * ld + j];
       rank += (e < d || (e == d && j < lane)) ? 1 : 0;
     }
     ord[rank] = lane;
@@ -512,14 +545,14 @@ __global__ __launch_bounds__(kWave) void k_bk_eig(BkArgs a) {
   double *tl = a.tvals + (int64_t)s * a.nkcap;
   for (int c = 0; c < nn; ++c) {
     const int o = ord[c];
-    if (lane == 0) tl[c] = A[o * k + o];
-    for (int r = lane; r < k; r += kWave) tv[(int64_t)c * a.ps + r] = V[r * k + o];
+    if (lane == 0) tl[c] = A[o * ld + o];
+    for (int r = lane; r < k; r += kWave) tv[(int64_t)c * a.ps + r] = V[r * ld + o];
   }
   if (lane == 0) {
     BkState &Bo = a.bs[s];
     Bo.big = big;
-    Bo.th1 = A[ord[0] * k + ord[0]];
-    Bo.th2 = A[ord[1] * k + ord[1]];
+    Bo.th1 = A[ord[0] * ld + ord[0]];
+    Bo.th2 = A[ord[1] * ld + ord[1]];
     Bo.has2 = Bo.th2 < big;
   }
 }
