@@ -15,7 +15,7 @@
 //   orth 2  W -= [u0 Q] H2; Gram matrix of W;
 //   reduce  first Cholesky QR factor of W, the next raw block.
 // After m/2 blocks (or a block with both columns dropped): the eigenpairs of
-// T by cyclic Jacobi (one wave per segment), the Ritz vectors, their
+// T by Jacobi rotations (one wave per segment), the Ritz vectors, their
 // residuals, and an explicit or thick restart.
 //
 // Deflation: a column whose part orthogonal to the column before it is at

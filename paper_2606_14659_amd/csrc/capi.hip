@@ -509,7 +509,8 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
     // FP64 SpMV launches: all of them in FP64 mode; with FP32 directions,
     // steps 1-2 and the residual of every cycle, and every step of the
     // cycles continued with FP64 directions
-    st.spmv_fp64 += (o.precision == RSB_MIXED && o.method != RSB_INVERSE_CG)
+    st.spmv_fp64 += (o.precision == RSB_MIXED && o.method != RSB_INVERSE_CG &&
+                     o.method != RSB_BLOCK)
                         ? 3 * (int64_t)cyc + (ctx.fp64_level_steps - fp64_steps0)
                         : steps + cyc;
     st.disconnected += disc;
