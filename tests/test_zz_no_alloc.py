@@ -2,7 +2,7 @@
 through the C ABI its partitions equal rsb_partition's on the same inputs,
 on two calls in a row (the second with a smaller mesh, so the region holds
 the first call's contents), with host and device arrays, default and
-benchmark solver settings, and at the documented maximum size."""
+benchmark solver settings, the block Lanczos, and at the documented maximum size."""
 import numpy as np
 import pytest
 
@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 
 BENCH = dict(precision="mixed", lanczos_keep=8, lanczos_m=40, tol=1e-2, warm_start=1, lanczos_s=2)
 BFS = dict(BENCH, bfs_start=1)
+BLOCK = dict(method="block", lanczos_m=40, lanczos_keep=8, tol=1e-6, warm_start=1, fiedler_sweep=8)
 
 
 def _pair(ids, nparts, device=False, **kw):
@@ -26,7 +27,7 @@ def _pair(ids, nparts, device=False, **kw):
     return p1
 
 
-@pytest.mark.parametrize("kw", [{}, BENCH, BFS], ids=["default", "bench", "bfs_start"])
+@pytest.mark.parametrize("kw", [{}, BENCH, BFS, BLOCK], ids=["default", "bench", "bfs_start", "block"])
 def test_two_calls_second_smaller(kw):
     big = mg.uniform_holes(mg.box_hex(40, 30, 24), 0.05, 31)
     small = mg.clustered_holes(mg.box_hex(23, 17, 11), 0.1, 32)
@@ -52,6 +53,7 @@ def test_maximum_size():
     print("[noalloc] maximum size, 65536 elements -> 1024 parts", flush=True)
     _pair(mesh.ids, 1024)
     _pair(mesh.ids, 1024, **BENCH)
+    _pair(mesh.ids, 1024, **BLOCK)
     # and a smaller call after it
     _pair(mg.box_hex(9, 7, 5).ids, 4)
 
