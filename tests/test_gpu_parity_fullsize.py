@@ -6,7 +6,8 @@ properties that hold at any size.
 
 C1 16^3 cube, face graph: one 100-step Lanczos cycle and RSB to 8.
 C2 128x128x64, 5% holes: dual graph bit-exact; Fiedler pair by Lanczos
-   (FP64) and by inverse iteration (plain CG and AMG-preconditioned CG),
+   (FP64), by the block Lanczos and by inverse iteration (plain CG and
+   AMG-preconditioned CG),
    residual checked in FP64 on the CPU; the AMG hierarchy's first coarse
    level against its definition on sampled rows.
 C3/C4 256x256x64, 3% holes: RSB to 1024 in FP64 and mixed precision.
@@ -235,6 +236,23 @@ def test_c2_lambda2_vs_oracle(c2, precision):
         st, lam, y, stats = rsb.fiedler(c2.ids, precision=precision, tol=1e-4, **kw)
         assert st == 0
         check_lambda_vs_oracle(lam, stats["residual"], "c2", "C2 mixed tol 1e-4", 1e-5)
+
+
+def test_c2_block_lambda2_vs_oracle(orc, c2):
+    # the block Lanczos of two vectors on the whole C2 mesh to 1e-8 (both
+    # Ritz pairs): its Fiedler value against the oracle's, the returned
+    # vector's FP64 residual recomputed on the CPU
+    kw = dict(method="block", lanczos_m=48, lanczos_keep=12, max_restarts=800, tol=1e-8)
+    print("[fullsize] C2 block", flush=True)
+    st, lam, y, stats = rsb.fiedler(c2.ids, **kw)
+    print(f"[fullsize] C2 block: {stats['cycles']} cycles, {stats['ms_total']:.0f} ms", flush=True)
+    assert st == 0 and stats["residual"] <= 1.01e-8 * lam
+    check_lambda_vs_oracle(lam, stats["residual"], "c2", "C2 block tol 1e-8", 1e-8)
+    rp, col, w = orc.dual_graph(c2.ids)
+    ly = orc.laplacian_apply(rp, col, w, y)
+    rho = float(y @ ly)
+    assert abs(np.linalg.norm(y) - 1.0) < 1e-12 and abs(lam - rho) <= 1e-12 * rho
+    assert np.linalg.norm(ly - rho * y) <= 1.02e-8 * rho
 
 
 @pytest.fixture(scope="module")
