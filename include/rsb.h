@@ -235,9 +235,10 @@ typedef struct rsb_opts {
 typedef struct rsb_stats {
   int32_t struct_size;       /* sizeof(rsb_stats), set by the caller */
   int32_t levels;            /* bisection levels run */
-  int64_t level_steps;       /* Lanczos (or CG) steps, one per launch over all
-                                segments of a level */
-  int64_t segment_steps;     /* the same counted per segment */
+  int64_t level_steps;       /* Lanczos (or CG, or RSB_BLOCK's block) steps, one
+                                per launch over all segments of a level */
+  int64_t segment_steps;     /* the same counted per segment (a block step
+                                applies L to two vectors) */
   int64_t cycles;            /* Lanczos cycles summed over levels */
   int64_t spmv_fp64;         /* SpMVs run with FP64 vectors (level launches) */
   int32_t not_converged;     /* segments that hit the iteration caps */
