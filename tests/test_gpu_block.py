@@ -155,3 +155,19 @@ def test_batched_unbatched_and_batch_call():
         s1, p1, _ = rsb.partition(ids, nparts[b], **kw)
         s2, p2, _ = rsb.partition(ids, nparts[b], batched=0, **kw)
         assert np.array_equal(p1, parts[b]) and np.array_equal(p1, p2)
+
+
+@pytest.mark.parametrize("name", ["holes", "clustered"])
+def test_matrix_reading_and_row_order_do_not_change_it(name):
+    # the packed slices give the 32-bit words' bits; the Cuthill-McKee row
+    # order changes only where rows are stored
+    ids = MESHES[name]()
+    kw = dict(method="block", lanczos_m=40, lanczos_keep=8, tol=1e-6, warm_start=1,
+              fiedler_sweep=8)
+    st0, lam0, y0, _ = rsb.fiedler(ids, pack_matrix=0, **kw)
+    st1, lam1, y1, _ = rsb.fiedler(ids, pack_matrix=1, **kw)
+    assert st0 == st1 and lam0 == lam1
+    assert np.array_equal(y0.view(np.uint64), y1.view(np.uint64))
+    s0, p0, _ = rsb.partition(ids, 12, **kw)
+    s1, p1, _ = rsb.partition(ids, 12, reorder=1, **kw)
+    assert s0 == s1 and np.array_equal(p0, p1)
