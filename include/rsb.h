@@ -192,9 +192,11 @@ typedef struct rsb_opts {
                                thick restart's second Ritz vector; it is swept when
                                its Rayleigh quotient is within sweep_gap of the
                                first and at least 0.1 of it lies off the first
-                               vector.  One Krylov space holds a single direction
-                               of an exactly degenerate pair (Sec. 9), two solves
-                               hold two.  Doubles the solve time.  0 (default). */
+                               vector; where it is not, the thick restart's own
+                               pair is swept as without the option.  One Krylov
+                               space holds a single direction of an exactly
+                               degenerate pair (Sec. 9), two solves hold two.
+                               Doubles the solve time.  0 (default). */
   int32_t lanczos_s;        /* thick restart (lanczos_keep > 0) with the sliced-ELL
                                operator: 2 = from step 3 on, steps j and j+1 come
                                from one block [L q_j, L^2 q_j] (two-step Lanczos:

@@ -1250,16 +1250,16 @@ int64_t bisection_cut(const Graph &g, const std::vector<uint8_t> &side) {
 // each with the canonical sign, are combined as cos(a) y1 + sin(a) y2 for
 // a = k pi / S, k = 0..S-1; every combination (canonical sign) is split by
 // the usual rule and the one of smallest cut replaces y (ties: smallest k).
-void sweep_pair(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const orc_opts &o,
+bool sweep_pair(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const orc_opts &o,
                 const SecondPair &sp, Vec &y, orc_info &info, double min_perp = 1e-6) {
-  if (!(sp.theta2 - sp.theta1 <= o.sweep_gap * sp.theta1)) return;
+  if (!(sp.theta2 - sp.theta1 <= o.sweep_gap * sp.theta1)) return false;
   const int64_t n = g.n;
   Vec y2 = sp.y2;
   deflate_ones(y2);
   const double b = dot(y, y2);
   for (int64_t i = 0; i < n; ++i) y2[i] -= b * y[i];
   const double nn = norm2(y2);
-  if (!(nn > min_perp)) return;
+  if (!(nn > min_perp)) return false;
   for (double &v : y2) v /= nn;
   canonical_sign(y2, gid);
   info.sweeps += 1;
@@ -1283,6 +1283,7 @@ void sweep_pair(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, 
   }
   if (best != 0) info.sweep_moved += 1;
   y = best_y;
+  return true;
 }
 
 // One bisection of graph g (vertices in ascending gid order) into a low side
@@ -1368,7 +1369,10 @@ int bisect(const Graph &g, const std::vector<int64_t> &gid, int64_t n_low, const
     two.ok = true;
     two.theta1 = lambda;
     two.theta2 = lam2;
-    sweep_pair(sub, sub_gid, n_low - strad_before, o, two, ys, info, 0.1);
+    // a second solve that did not give a pair to sweep leaves the thick
+    // restart's own pair (its Ritz values, its second Ritz vector)
+    if (!sweep_pair(sub, sub_gid, n_low - strad_before, o, two, ys, info, 0.1) && second.ok)
+      sweep_pair(sub, sub_gid, n_low - strad_before, o, second, ys, info);
   } else if (second.ok && o.fiedler_sweep > 0) {
     sweep_pair(sub, sub_gid, n_low - strad_before, o, second, ys, info);
   }

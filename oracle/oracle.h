@@ -67,7 +67,9 @@ typedef struct orc_opts {
   int32_t second_solve;      /* fiedler_sweep > 0: the second vector of the swept
                                 pair comes from a second Lanczos solve from
                                 another random start (seed ^ ORC_SECOND_SEED),
-                                so that an exactly degenerate pair is swept */
+                                so that an exactly degenerate pair is swept;
+                                where that pair is not swept, the thick
+                                restart's own pair is (as without the option) */
   int32_t lanczos_s;         /* 1: one Lanczos step at a time; 2: from step 3 on,
                                 steps j+1 and j+2 from one block [L q_j, L^2 q_j]
                                 (two-step Lanczos; the same Krylov space and

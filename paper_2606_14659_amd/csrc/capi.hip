@@ -525,11 +525,21 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
                 i, L->seg[i].n, L->seg[i].P, hs[i].ncomp, hs[i].solve, hs[i].converged,
                 hs[i].cycles, (long long)hs[i].steps, hs[i].res, hs[i].rho, hs[i].theta);
     double min_perp2 = 1e-12;
+    // second_solve: the thick restart's own pair (second Ritz vector and
+    // Ritz values), swept where the second solve's pair is not
+    DevBuf<double> y2_thick;
+    std::vector<double> tv_thick;
     if (o.second_solve) {
       // the pair from two solves: Lanczos again from another random start;
       // its vector becomes y2 and its Rayleigh quotient the second value of
       // the gap test, then the first solve's vector and state come back
       const int64_t nr = L->nrows;
+      y2_thick.alloc(ctx, std::max<int64_t>(nr, 1));
+      RSB_HIP(hipMemcpyAsync(y2_thick.get(), y2.get(), nr * sizeof(double),
+                             hipMemcpyDeviceToDevice, ctx.stream));
+      tv_thick.assign((size_t)L->nseg * S.nkcap, 0.0);
+      RSB_HIP(hipMemcpyAsync(tv_thick.data(), S.tvals.get(), tv_thick.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx.stream));
       DevBuf<double> y1(ctx, std::max<int64_t>(nr, 1));
       DevBuf<SegState> st1(ctx, L->nseg);
       RSB_HIP(hipMemcpyAsync(y1.get(), y64.get(), nr * sizeof(double), hipMemcpyDeviceToDevice,
@@ -562,9 +572,28 @@ RunOut run_rsb(const std::vector<MeshIn> &meshes, int nv, const rsb_opts &o, Ctx
       RSB_HIP(hipStreamSynchronize(ctx.stream));
       min_perp2 = 0.01;
     }
-    if (o.fiedler_sweep > 0)
+    if (o.fiedler_sweep > 0) {
+      std::vector<int32_t> on;
       fiedler_sweep(*L, C, S, y64.get(), y2.get(), o.fiedler_sweep, o.sweep_gap, &st.sweeps,
-                    &st.sweep_moved, ctx, min_perp2);
+                    &st.sweep_moved, ctx, min_perp2, &on);
+      if (o.second_solve && S.nkcap >= 2) {
+        // segments the second solve's pair left unswept: the thick
+        // restart's pair, with its gap and the usual perpendicular part
+        std::vector<double> tv = tv_thick;
+        bool any = false;
+        for (int i = 0; i < L->nseg; ++i) {
+          if (on[i]) tv[(size_t)i * S.nkcap + 1] = 1e300;
+          else any = true;
+        }
+        if (any) {
+          RSB_HIP(hipMemcpyAsync(S.tvals.get(), tv.data(), tv.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, ctx.stream));
+          RSB_HIP(hipStreamSynchronize(ctx.stream));
+          fiedler_sweep(*L, C, S, y64.get(), y2_thick.get(), o.fiedler_sweep, o.sweep_gap,
+                        &st.sweeps, &st.sweep_moved, ctx);
+        }
+      }
+    }
     if (fiedler_y) {
       const SegState &s = hs[0];
       RSB_HIP(hipMemcpyAsync(fiedler_y, y64.get(), meshes[0].nelem * sizeof(double),

@@ -455,10 +455,10 @@ int64_t inverse_level(const LevelView &L, CompDev &C, SolveDev &S, const Inverse
 // u0 and y1, both with the canonical sign; a = k pi / nangles) whose split
 // cuts the least weight.  Counts swept segments and those that moved.  A
 // segment is swept only if the part of y2 off u0 and y1 has squared norm
-// above min_perp2 (y2 of unit norm).
+// above min_perp2 (y2 of unit norm).  on_out (optional): 1 per swept segment.
 void fiedler_sweep(Level &L, CompDev &C, SolveDev &S, double *y64, const double *y2, int nangles,
                    double sweep_gap, int *swept, int *moved, Ctx &ctx,
-                   double min_perp2 = 1e-12);
+                   double min_perp2 = 1e-12, std::vector<int32_t> *on_out = nullptr);
 
 // Warm start for the next level: warm[orig[row]] = the second Ritz vector y2
 // at unit root-mean-square on each segment's cut component (segments whose

@@ -256,8 +256,10 @@ void warm_update(Level &L, CompDev &C, SolveDev &S, const double *y2, double *wa
 }
 
 void fiedler_sweep(Level &L, CompDev &C, SolveDev &S, double *y64, const double *y2, int nangles,
-                   double sweep_gap, int *swept, int *moved, Ctx &ctx, double min_perp2) {
+                   double sweep_gap, int *swept, int *moved, Ctx &ctx, double min_perp2,
+                   std::vector<int32_t> *on_out) {
   const int64_t n = L.nrows;
+  if (on_out) on_out->assign(L.nseg, 0);
   if (n == 0 || L.nseg == 0 || nangles < 1) return;
   hipStream_t st = ctx.stream;
   DevBuf<SweepSeg> sw(ctx, L.nseg);
@@ -289,6 +291,8 @@ void fiedler_sweep(Level &L, CompDev &C, SolveDev &S, double *y64, const double 
   int on = 0;
   for (auto &w : hs) on += w.on;
   if (swept) *swept += on;
+  if (on_out)
+    for (int i = 0; i < L.nseg; ++i) (*on_out)[i] = hs[i].on;
   if (on == 0) return;
   const unsigned g = grid_for(n, kBlock), gs = grid_for(L.nseg, 64);
   DevBuf<double> y2h(ctx, n), yk(ctx, n);

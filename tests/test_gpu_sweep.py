@@ -177,3 +177,17 @@ def test_second_solve_partition_degenerate_box(orc):
     cut = orc.metrics(ids, part, 4)["weighted_cut"]
     ocut = orc.metrics(ids, opart, 4)["weighted_cut"]
     assert abs(cut - ocut) <= 0.01 * ocut
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("seed", range(3))
+def test_second_solve_falls_back_to_thick_pair(orc, seed, precision):
+    # the second solve comes back to y1 on these near-degenerate pairs: the
+    # thick restart's own pair is swept, exactly as without the option
+    ids = mg.uniform_holes(mg.box_hex(10, 10, 4), 0.06, seed).ids
+    kw = dict(KW, precision=precision, fiedler_sweep=16)
+    st0, lam0, y0, s0 = rsb.fiedler(ids, **kw)
+    st1, lam1, y1, s1 = rsb.fiedler(ids, second_solve=1, **kw)
+    assert s0["sweeps"] == s1["sweeps"] == 1 and np.array_equal(y0, y1)
+    ost, olam, oy, oinfo = orc.fiedler(ids, second_solve=1, **dict(KW, fiedler_sweep=16))
+    assert oinfo["sweeps"] == 1 and half_cut(orc, ids, y1) == half_cut(orc, ids, oy)

@@ -109,3 +109,15 @@ def test_second_solve_leaves_a_simple_pair_alone(orc):
     st1, p1, info = orc.partition(ids, 8, fiedler_sweep=8, second_solve=1, **KW)
     assert st0 == st1 == 0 and info["sweeps"] == 0
     assert np.array_equal(p0, p1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_second_solve_falls_back_to_the_thick_restart_pair(orc, seed):
+    # a near-degenerate pair whose second solve comes back to y1 (not 0.1
+    # off it): the thick restart's own pair is swept, exactly as without the
+    # option
+    mesh = mg.uniform_holes(mg.box_hex(10, 10, 4), 0.06, seed)
+    st0, lam0, y0, i0 = orc.fiedler(mesh.ids, fiedler_sweep=16, **KW)
+    st1, lam1, y1, i1 = orc.fiedler(mesh.ids, fiedler_sweep=16, second_solve=1, **KW)
+    assert i0["sweeps"] == i1["sweeps"] == 1
+    assert np.array_equal(y0, y1)
