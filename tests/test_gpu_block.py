@@ -171,3 +171,23 @@ def test_matrix_reading_and_row_order_do_not_change_it(name):
     s0, p0, _ = rsb.partition(ids, 12, **kw)
     s1, p1, _ = rsb.partition(ids, 12, reorder=1, **kw)
     assert s0 == s1 and np.array_equal(p0, p1)
+
+
+@pytest.mark.parametrize("graph", ["unit", "face"])
+@pytest.mark.parametrize("keep", [0, 8])
+def test_other_graph_kinds(orc, graph, keep):
+    # the unit-weight and the face graph: cuts within 1% of the oracle's,
+    # and the unique-axis box identical
+    ids = MESHES["holes"]()
+    kw = dict(graph=graph, method="block", lanczos_m=40, lanczos_keep=keep, tol=1e-6,
+              max_restarts=300)
+    st, part, _ = rsb.partition(ids, 10, **kw)
+    ost, opart, _ = orc.partition(ids, 10, **kw)
+    assert st == ost
+    cut = orc.metrics(ids, part, 10)["weighted_cut"]
+    ocut = orc.metrics(ids, opart, 10)["weighted_cut"]
+    assert abs(cut - ocut) <= 0.01 * ocut
+    box = mg.box_hex(20, 14, 9).ids
+    st, part, _ = rsb.partition(box, 4, **kw)
+    ost, opart, _ = orc.partition(box, 4, **kw)
+    assert st == ost and np.array_equal(part, opart)
