@@ -444,8 +444,8 @@ __global__ __launch_bounds__(kWave) void k_bk_eig(BkArgs a) {
   // column spread over the LDS banks
   __shared__ double A[kBkMaxM * (kBkMaxM + 1)];
   __shared__ double V[kBkMaxM * (kBkMaxM + 1)];
-  __shared__ double rc[kBkMaxM / 2], rs_[kBkMaxM / 2];
-  __shared__ int32_t rp[kBkMaxM / 2], rq[kBkMaxM / 2];
+  __shared__ double rot_c[kBkMaxM / 2], rot_s[kBkMaxM / 2];  // this round's rotations
+  __shared__ int32_t rot_p[kBkMaxM / 2], rot_q[kBkMaxM / 2];
   __shared__ int32_t ord[kBkMaxM];
   const int s = blockIdx.x;
   const BkState B = a.bs[s];
@@ -499,16 +499,16 @@ __global__ __launch_bounds__(kWave) void k_bk_eig(BkArgs a) {
           c = 1.0 / sqrt(1.0 + t * t);
           sn = t * c;
         }
-        rc[lane] = c;
-        rs_[lane] = sn;
-        rp[lane] = p;
-        rq[lane] = q;
+        rot_c[lane] = c;
+        rot_s[lane] = sn;
+        rot_p[lane] = p;
+        rot_q[lane] = q;
       }
       __syncthreads();
       if (lane < k) {
         for (int i = 0; i < h; ++i) {
-          const int p = rp[i], q = rq[i];
-          const double c = rc[i], sn = rs_[i];
+          const int p = rot_p[i], q = rot_q[i];
+          const double c = rot_c[i], sn = rot_s[i];
           const double arp = A[lane * ld + p], arq = A[lane * ld + q];
           A[lane * ld + p] = c * arp - sn * arq;
           A[lane * ld + q] = sn * arp + c * arq;
@@ -520,8 +520,8 @@ __global__ __launch_bounds__(kWave) void k_bk_eig(BkArgs a) {
       __syncthreads();
       if (lane < k) {
         for (int i = 0; i < h; ++i) {
-          const int p = rp[i], q = rq[i];
-          const double c = rc[i], sn = rs_[i];
+          const int p = rot_p[i], q = rot_q[i];
+          const double c = rot_c[i], sn = rot_s[i];
           const double apr = A[p * ld + lane], aqr = A[q * ld + lane];
           A[p * ld + lane] = c * apr - sn * aqr;
           A[q * ld + lane] = sn * apr + c * aqr;
