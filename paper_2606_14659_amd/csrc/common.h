@@ -145,11 +145,21 @@ struct Ctx {
                  // their tiles' gathers staged in LDS
   Arena *arena = nullptr;          // non-null: device scratch comes from this region only
   FaultPlan fault;
+  // device blocks released during the call, by size: a later allocation on
+  // the same stream takes one (stream order makes that safe), and the rest
+  // are returned to the pool once the call's work has ended (returning memory
+  // that captured graphs used can hold the host while the queue runs dry)
+  std::multimap<size_t, void *> spare;
   Ctx() = default;
   Ctx(const Ctx &) = delete;
   Ctx &operator=(const Ctx &) = delete;
   ~Ctx() {
     if (fault_plan() == &fault) fault_plan() = nullptr;
+    if (!spare.empty()) {
+      (void)hipStreamSynchronize(stream);
+      for (auto &kv : spare) (void)hipFreeAsync(kv.second, stream);
+      spare.clear();
+    }
     if (own_stream && stream) {
       (void)hipStreamSynchronize(stream);
       (void)hipStreamDestroy(stream);
@@ -161,17 +171,20 @@ template <typename T>
 struct DevBuf {
   T *p = nullptr;
   size_t n = 0;
+  size_t cap = 0;  // bytes of the block held
   Ctx *ctx = nullptr;
   DevBuf() = default;
   DevBuf(Ctx &c, size_t count) { alloc(c, count); }
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
-  DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), ctx(o.ctx) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), cap(o.cap), ctx(o.ctx) {
+    o.p = nullptr; o.n = 0; o.cap = 0;
+  }
   DevBuf &operator=(DevBuf &&o) noexcept {
     if (this != &o) {
       release();
-      p = o.p; n = o.n; ctx = o.ctx;
-      o.p = nullptr; o.n = 0;
+      p = o.p; n = o.n; cap = o.cap; ctx = o.ctx;
+      o.p = nullptr; o.n = 0; o.cap = 0;
     }
     return *this;
   }
@@ -185,6 +198,7 @@ struct DevBuf {
       fail(RSB_ENOMEM, "device_mem_limit exceeded: need " + std::to_string(c.in_use + bytes) +
                            " bytes, limit " + std::to_string(c.limit));
     if (c.arena) {
+      cap = bytes;
       p = (T *)c.arena->take(bytes);
       if (!p)
         fail(RSB_ENOMEM, "the problem needs more device scratch than the fixed region of " +
@@ -195,7 +209,27 @@ struct DevBuf {
       c.peak = std::max(c.peak, c.in_use);
       return;
     }
+    // a block released earlier in the call, at least this size and at most twice it
+    auto it = c.spare.lower_bound(bytes);
+    if (it != c.spare.end() && it->first <= 2 * bytes) {
+      p = (T *)it->second;
+      cap = it->first;
+      c.spare.erase(it);
+      c.in_use += bytes;
+      c.peak = std::max(c.peak, c.in_use);
+      return;
+    }
+    cap = bytes;
     hipError_t e = hipMallocAsync((void **)&p, bytes, c.stream);
+    if (e == hipErrorOutOfMemory && !c.spare.empty()) {
+      // the kept blocks go back to the pool and the allocation is tried again
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(c.stream);
+      for (auto &kv : c.spare) (void)hipFreeAsync(kv.second, c.stream);
+      c.spare.clear();
+      (void)hipStreamSynchronize(c.stream);
+      e = hipMallocAsync((void **)&p, bytes, c.stream);
+    }
     if (e != hipSuccess) {
       p = nullptr;
       fail(e == hipErrorOutOfMemory ? RSB_ENOMEM : RSB_EDEVICE,
@@ -206,12 +240,13 @@ struct DevBuf {
   }
   void release() {
     if (p) {
-      if (ctx->arena) ctx->arena->give(p, std::max<size_t>(n, 1) * sizeof(T));
-      else (void)hipFreeAsync(p, ctx->stream);
+      if (ctx->arena) ctx->arena->give(p, cap);
+      else ctx->spare.emplace(cap, p);
       ctx->in_use -= std::max<size_t>(n, 1) * sizeof(T);
       p = nullptr;
     }
     n = 0;
+    cap = 0;
   }
   ~DevBuf() { release(); }
   T *get() const { return p; }
