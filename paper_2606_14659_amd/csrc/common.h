@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -131,6 +132,34 @@ struct Arena {
   }
 };
 
+// Idle device blocks of calls that have ended, per device.  A call takes
+// from here before it asks the pool: each hipMallocAsync and hipFreeAsync
+// holds the host for about 0.1 ms, and a partition makes hundreds of them.
+// Blocks only enter after their call has synchronised its stream, so any
+// later call, on any stream, may use them.  Beyond kBlockCacheMax bytes the
+// largest go back to the pool.
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<size_t, void *> blocks;
+  size_t bytes = 0;
+};
+constexpr size_t kBlockCacheMax = size_t(32) << 30;
+inline BlockCache &block_cache(int device) {
+  static BlockCache caches[64];
+  return caches[(unsigned)device % 64u];
+}
+
+// Takes a block of at least `bytes` and at most twice that from `m`, or
+// returns null; *cap receives its size.
+inline void *take_block(std::multimap<size_t, void *> &m, size_t bytes, size_t *cap) {
+  auto it = m.lower_bound(bytes);
+  if (it == m.end() || it->first > 2 * bytes) return nullptr;
+  void *q = it->second;
+  *cap = it->first;
+  m.erase(it);
+  return q;
+}
+
 struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;  // created for a call that passed the null stream
@@ -146,9 +175,10 @@ struct Ctx {
   Arena *arena = nullptr;          // non-null: device scratch comes from this region only
   FaultPlan fault;
   // device blocks released during the call, by size: a later allocation on
-  // the same stream takes one (stream order makes that safe), and the rest
-  // are returned to the pool once the call's work has ended (returning memory
-  // that captured graphs used can hold the host while the queue runs dry)
+  // the same stream takes one (stream order makes that safe); at the end of
+  // the call, with its work done, they join the device's block cache
+  // (returning memory that captured graphs used can hold the host while the
+  // queue runs dry)
   std::multimap<size_t, void *> spare;
   Ctx() = default;
   Ctx(const Ctx &) = delete;
@@ -157,8 +187,20 @@ struct Ctx {
     if (fault_plan() == &fault) fault_plan() = nullptr;
     if (!spare.empty()) {
       (void)hipStreamSynchronize(stream);
-      for (auto &kv : spare) (void)hipFreeAsync(kv.second, stream);
+      BlockCache &bc = block_cache(device);
+      std::lock_guard<std::mutex> lock(bc.mu);
+      for (auto &kv : spare) {
+        bc.blocks.emplace(kv.first, kv.second);
+        bc.bytes += kv.first;
+      }
       spare.clear();
+      while (bc.bytes > kBlockCacheMax && !bc.blocks.empty()) {
+        auto it = std::prev(bc.blocks.end());
+        (void)hipFreeAsync(it->second, stream);
+        bc.bytes -= it->first;
+        bc.blocks.erase(it);
+      }
+      (void)hipStreamSynchronize(stream);
     }
     if (own_stream && stream) {
       (void)hipStreamSynchronize(stream);
@@ -209,24 +251,35 @@ struct DevBuf {
       c.peak = std::max(c.peak, c.in_use);
       return;
     }
-    // a block released earlier in the call, at least this size and at most twice it
-    auto it = c.spare.lower_bound(bytes);
-    if (it != c.spare.end() && it->first <= 2 * bytes) {
-      p = (T *)it->second;
-      cap = it->first;
-      c.spare.erase(it);
+    // a block released earlier in the call, or by a call that has ended, at
+    // least this size and at most twice it
+    p = (T *)take_block(c.spare, bytes, &cap);
+    if (!p) {
+      BlockCache &bc = block_cache(c.device);
+      std::lock_guard<std::mutex> lock(bc.mu);
+      p = (T *)take_block(bc.blocks, bytes, &cap);
+      if (p) bc.bytes -= cap;
+    }
+    if (p) {
       c.in_use += bytes;
       c.peak = std::max(c.peak, c.in_use);
       return;
     }
     cap = bytes;
     hipError_t e = hipMallocAsync((void **)&p, bytes, c.stream);
-    if (e == hipErrorOutOfMemory && !c.spare.empty()) {
+    if (e == hipErrorOutOfMemory) {
       // the kept blocks go back to the pool and the allocation is tried again
       (void)hipGetLastError();
       (void)hipStreamSynchronize(c.stream);
       for (auto &kv : c.spare) (void)hipFreeAsync(kv.second, c.stream);
       c.spare.clear();
+      {
+        BlockCache &bc = block_cache(c.device);
+        std::lock_guard<std::mutex> lock(bc.mu);
+        for (auto &kv : bc.blocks) (void)hipFreeAsync(kv.second, c.stream);
+        bc.blocks.clear();
+        bc.bytes = 0;
+      }
       (void)hipStreamSynchronize(c.stream);
       e = hipMallocAsync((void **)&p, bytes, c.stream);
     }
