@@ -22,7 +22,12 @@
  *    Work is queued on opts->stream (a hipStream_t; NULL = the null stream).
  *    Calls on distinct streams may run from distinct host threads.
  *  - Scratch device memory comes from the stream-ordered allocator of the
- *    device and is returned to its pool before the call returns.
+ *    device.  Blocks a call releases are reused by its later allocations;
+ *    when the call ends they are kept, idle, in a per-device cache of at most
+ *    32 GiB that later calls draw from before asking the allocator (each
+ *    allocation and free of the allocator holds the host for about 0.1 ms).
+ *    The cache is emptied back into the allocator's pool whenever an
+ *    allocation finds the device out of memory.
  *  - Limits: nelem < 2^28 elements per call (all meshes of a batch
  *    together), edge weights <= 15 (shared-vertex counts), at most 1024
  *    candidate neighbour entries per element when building the graph
