@@ -484,7 +484,14 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
         last_b = b2;
         ++j;
         if (j == m - 1) break;
-        if (b2 <= 1e-12 * tnorm) {
+        // R11^2 = g11 - R01^2 is the difference of two numbers of size
+        // ||w2||^2, so R11 carries a relative error of about u ||w2||^2 /
+        // R11^2.  Below 1e-8 ||w2||^2 (the second column nearly in the span
+        // of the first and the basis: the Krylov space is exhausted or
+        // nearly so) q_{j+2} = w / beta_{j+2} would no longer be of unit
+        // norm to working accuracy, and the cycle ends after step j+1 as at
+        // a breakdown.
+        if (b2 <= 1e-12 * tnorm || g11 - r01 * r01 <= 1e-8 * g11) {
           breakdown = true;
           break;
         }

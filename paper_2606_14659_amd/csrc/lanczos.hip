@@ -56,6 +56,10 @@ constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24
 constexpr double kStallChange = 0.05;
 constexpr int kStallCycles = 2;
 constexpr double kStallScale = 64.0;
+// Two-step Lanczos: the Cholesky QR's R11^2 = g11 - R01^2 at or below
+// kCholRel g11 ends the cycle (R11 would carry a relative error of about
+// u / kCholRel from the cancellation)
+constexpr double kCholRel = 1e-8;
 
 template <typename T>
 struct LzArgs {
@@ -1266,7 +1270,13 @@ __global__ __launch_bounds__(kBlock) void k_lz_reduce(LzArgs<T> a, int j) {
     W.r01 = r01;
     W.r11 = r11;
     W.pair = 1;
-    if (j + 1 >= a.m || b2 <= a.brk * W.tnorm) W.cycle_done = 1;
+    // R11^2 = g11 - R01^2 is the difference of two numbers of size g11:
+    // below kCholRel g11 (the second column nearly in the span of the first
+    // and the basis, the Krylov space exhausted or nearly so) beta_{j+2} is
+    // not known to working accuracy, and the cycle ends after step j + 1 as
+    // at a breakdown
+    if (j + 1 >= a.m || b2 <= a.brk * W.tnorm || g11 - r01 * r01 <= kCholRel * g11)
+      W.cycle_done = 1;
     return;
   }
   if (OP == OP_BEGIN || OP == OP_RITZ) {

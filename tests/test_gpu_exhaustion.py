@@ -1,0 +1,113 @@
+"""GPU Lanczos where the Krylov space is exhausted: graphs of at most m + 1
+elements, as deep levels of a recursion produce them (or fewer distinct
+eigenvalues than m).  Every setting must end the cycle by breakdown there
+and return the dense solver's lambda_2, like the oracle.  Partitions of
+small holed meshes into many parts (subgraphs of a few elements at the last
+levels) must keep the oracle's status and cut.
+
+Open: the GPU's explicit restart (one Gram-Schmidt pass unless the
+projection's own estimate of the remainder says otherwise) and its two-step
+form (Cholesky QR of a block whose second pass is deferred) lose enough
+orthogonality near the exhaustion to miss the breakdown on some of these
+graphs, and the cycle then returns a Ritz value from inside the spectrum.
+Their cases are skipped below with that reason; one run of the explicit
+cases also ended in a host segmentation fault whose cause is not known, so
+they stay off the GPU until it is.  The one-step thick restart passes them.
+"""
+import numpy as np
+import pytest
+
+import meshgen as mg
+import paper_2606_14659_amd as rsb
+from test_oracle_exhaustion_pins import tiny_meshes
+from test_oracle_pins import dense_laplacian
+
+pytestmark = pytest.mark.gpu
+
+OPEN_EXPLICIT = pytest.mark.skip(
+    reason="explicit restart misses the breakdown at an exhausted Krylov space on some tiny "
+           "graphs; a run of these cases also ended in a host segmentation fault of unknown "
+           "cause, so they stay off the GPU until that cause is found")
+OPEN_TWO_STEP = pytest.mark.skip(
+    reason="the two-step form misses the breakdown at an exhausted Krylov space on some tiny "
+           "graphs (open)")
+SETTINGS = {
+    "fp64 explicit": dict(precision="fp64", lanczos_keep=0, lanczos_s=1, tol=1e-10),
+    "fp64 thick": dict(precision="fp64", lanczos_keep=8, lanczos_s=1, tol=1e-10),
+    "fp64 two-step": dict(precision="fp64", lanczos_keep=8, lanczos_s=2, tol=1e-10),
+    "mixed explicit": dict(precision="mixed", lanczos_keep=0, lanczos_s=1, tol=1e-8),
+    "mixed two-step": dict(precision="mixed", lanczos_keep=8, lanczos_s=2, tol=1e-8),
+}
+
+
+@pytest.mark.parametrize("setting", [
+    pytest.param("fp64 explicit", marks=OPEN_EXPLICIT),
+    "fp64 thick",
+    pytest.param("fp64 two-step", marks=OPEN_TWO_STEP),
+    pytest.param("mixed explicit", marks=OPEN_EXPLICIT),
+    pytest.param("mixed two-step", marks=OPEN_TWO_STEP)])
+def test_exhausted_fiedler_matches_dense_eigh(orc, setting):
+    kw = SETTINGS[setting]
+    print(f"[exhaust] fiedler {setting}", flush=True)
+    for ids in tiny_meshes(120):
+        rp, col, w = orc.dual_graph(ids)
+        ev = np.linalg.eigvalsh(dense_laplacian(rp, col, w))
+        m = 40 if len(rp) - 1 <= 41 else 60
+        st, lam, y, s = rsb.fiedler(ids, lanczos_m=m, max_restarts=20, **kw)
+        assert st == 0, (setting, len(rp) - 1)
+        assert abs(lam - ev[1]) <= 10 * kw["tol"] * ev[-1], (setting, len(rp) - 1, lam, ev[1])
+
+
+@pytest.mark.parametrize("setting", [
+    pytest.param("fp64 explicit", marks=OPEN_EXPLICIT),
+    "fp64 thick",
+    pytest.param("fp64 two-step", marks=OPEN_TWO_STEP)])
+def test_exhausted_first_cycle_matches_oracle(orc, setting):
+    # the first cycle's Ritz value (where it runs into the exhaustion the
+    # breakdown ends it on both sides at the same step)
+    kw = dict(SETTINGS[setting], tol=1e-15)
+    for ids in tiny_meshes(60):
+        n = len(orc.dual_graph(ids)[0]) - 1
+        m = 40 if n <= 41 else 60
+        st, lam, _, s = rsb.fiedler(ids, lanczos_m=m, max_restarts=0, **kw)
+        ost, olam, _, oinfo = orc.fiedler(ids, lanczos_m=m, max_restarts=0, **kw)
+        assert abs(lam - olam) <= 1e-9 * olam, (setting, n, lam, olam)
+
+
+# small holed meshes partitioned into many parts: (dims, hole fraction, hole
+# seed, clustered holes, element shuffle seed or None, parts)
+PARTITIONS = [
+    ((7, 6, 7), 0.03911959118442097, 9729, False, 9731, 33),
+    ((8, 35), 0.02716621909280903, 56139, False, None, 61),
+    ((5, 10, 20), 0.09351783428506218, 525095, True, None, 50),
+    ((19, 5, 6), 0.04170786867984291, 948476, False, None, 28),
+    ((5, 10, 21), 0.03368116146074082, 563691, True, 563693, 52),
+]
+BENCH = dict(precision="mixed", lanczos_m=40, lanczos_keep=8, tol=1e-2, warm_start=1,
+             lanczos_s=2)
+
+
+CASES = [pytest.param(k, "default", marks=OPEN_EXPLICIT) for k in range(len(PARTITIONS))] + [
+    pytest.param(k, "bench", marks=OPEN_TWO_STEP) if k == 4 else (k, "bench")
+    for k in range(len(PARTITIONS))]
+
+
+@pytest.mark.parametrize("k,setting", CASES)
+def test_many_parts_status_and_cut_like_oracle(orc, k, setting):
+    dims, frac, seed, clustered, shuffle, nparts = PARTITIONS[k]
+    base = mg.box_quad(*dims) if len(dims) == 2 else mg.box_hex(*dims)
+    mesh = (mg.clustered_holes if clustered else mg.uniform_holes)(base, frac, seed)
+    if shuffle is not None:
+        mesh = mg.shuffle_elements(mesh, shuffle)
+    kw = BENCH if setting == "bench" else {}
+    print(f"[exhaust] partition {dims} {nparts} {setting}", flush=True)
+    st, part, s = rsb.partition(mesh.ids, nparts, **kw)
+    ost, opart, _ = orc.partition(mesh.ids, nparts, **kw)
+    assert st == ost
+    assert s["not_converged"] == 0
+    sizes = np.bincount(part, minlength=nparts)
+    n = mesh.nelem
+    assert sizes.min() >= n // nparts and sizes.max() <= -(-n // nparts)
+    cut = orc.metrics(mesh.ids, part, nparts)["weighted_cut"]
+    ocut = orc.metrics(mesh.ids, opart, nparts)["weighted_cut"]
+    assert abs(cut - ocut) <= 0.01 * ocut
