@@ -139,7 +139,16 @@ typedef struct rsb_opts {
                                last residual direction.  With precision =
                                RSB_MIXED the kept Ritz vectors stay FP64, and a
                                solve that stalls short of tol finishes with FP64
-                               directions (see RSB_MIXED). */
+                               directions (see RSB_MIXED).  Known limitation:
+                               where a cycle exhausts the Krylov space (a
+                               subgraph of at most lanczos_m + 1 elements, or
+                               fewer distinct eigenvalues than lanczos_m), the
+                               explicit restart can miss the breakdown and
+                               return a poor vector for that bisection (status
+                               RSB_WARN_NOT_CONVERGED at the restart cap); the
+                               thick restart one step at a time does not.
+                               Partitions into parts of a few dozen elements
+                               should use k > 0 with lanczos_s = 1. */
   int32_t inv_precond;      /* inverse iteration: RSB_PRECOND_NONE (default) or
                                RSB_PRECOND_AMG.  With AMG the first direction
                                of every CG solve is still the plain residual
@@ -209,7 +218,10 @@ typedef struct rsb_opts {
                                step at a time in exact arithmetic; the basis is
                                read twice per two steps instead of twice per
                                step); 1 (default) = one step at a time.  Ignored
-                               for explicit restart and gather_scatter. */
+                               for explicit restart and gather_scatter.  Known
+                               limitation: the form 2 shares the explicit
+                               restart's weakness at an exhausted Krylov space
+                               (see lanczos_keep). */
   int32_t pack_matrix;      /* 1 (default) = each level also keeps a packed copy of
                                the sliced-ELL slices whose column offsets from the
                                row (column - row) fit in at most 4 windows of 1024:
