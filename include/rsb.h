@@ -144,8 +144,9 @@ typedef struct rsb_opts {
                                subgraph of at most lanczos_m + 1 elements, or
                                fewer distinct eigenvalues than lanczos_m), the
                                explicit restart can miss the breakdown and
-                               return a poor vector for that bisection (status
-                               RSB_WARN_NOT_CONVERGED at the restart cap); the
+                               return a poor vector for that bisection (most
+                               often reported as RSB_WARN_NOT_CONVERGED at the
+                               restart cap, but a loose tol can pass it); the
                                thick restart one step at a time does not.
                                Partitions into parts of a few dozen elements
                                should use k > 0 with lanczos_s = 1. */
