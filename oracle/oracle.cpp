@@ -403,6 +403,11 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
   normalize(q);
   const int m = std::max(1, o.lanczos_m);
   const int keep = std::max(0, o.lanczos_keep);
+  // two steps at a time only on graphs of more than 4 m elements: a cycle
+  // can exhaust the Krylov space of a smaller one (at most m + 1 elements,
+  // or fewer distinct eigenvalues than m), and one step at a time meets the
+  // breakdown there with both Gram-Schmidt passes behind it
+  const bool pairs = o.lanczos_s == 2 && n > 4 * (int64_t)m;
   int converged = 0;
   double theta = 0.0, res = 0.0;
   y = q;
@@ -424,7 +429,7 @@ int lanczos_fiedler(const Graph &g, const std::vector<int64_t> &gid, const orc_o
     double last_b = 0.0;
     bool breakdown = false;
     for (int j = nk; j < m; ++j) {
-      if (o.lanczos_s == 2 && j >= 2 && j + 1 < m) {
+      if (pairs && j >= 2 && j + 1 < m) {
         // Two steps from one block (step j+1 and j+2 in the paper's
         // numbering): K = [L q_j, L^2 q_j], two classical Gram-Schmidt
         // passes of both columns against [u0, Q[0..j]], then Cholesky QR of

@@ -225,6 +225,8 @@ void one_segment_tables(const Level &L, int s, OneSeg &o, Ctx &ctx) {
 }
 
 // Ritz buffers per segment: the kept count, or the pair of the block solver.
+constexpr int kPairMinPerStep = 4;
+
 int solve_keep(const rsb_opts &o) {
   return o.method == RSB_BLOCK ? std::max(o.lanczos_keep, 2) : o.lanczos_keep;
 }
@@ -237,6 +239,22 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
                     double *y64, double *y2, const double *warm, KernelProfile *prof,
                     int *amg_levels, int *fallbacks, Ctx &ctx) {
   const bool mixed = o.precision == RSB_MIXED;
+  // two steps at a time only where every component this level solves has
+  // more than kPairMinPerStep * lanczos_m elements: a cycle can exhaust the
+  // Krylov space of a smaller graph (at most m + 1 elements, or fewer
+  // distinct eigenvalues than m), and the block's single Gram-Schmidt pass
+  // before its Cholesky QR can then miss the breakdown
+  bool pairs = o.lanczos_s == 2 && o.method != RSB_BLOCK;
+  if (pairs) {
+    std::vector<SegState> hs(L.nseg);
+    RSB_HIP(hipMemcpyAsync(hs.data(), S.st.get(), L.nseg * sizeof(SegState),
+                           hipMemcpyDeviceToHost, ctx.stream));
+    RSB_HIP(hipStreamSynchronize(ctx.stream));
+    for (const SegState &h : hs)
+      if (h.solve && h.invsqrt_nc > 0.0 &&
+          1.0 / (h.invsqrt_nc * h.invsqrt_nc) <= kPairMinPerStep * o.lanczos_m + 0.5)
+        pairs = false;
+  }
   auto run = [&](const LevelView &v, SolveDev &SS, bool graph, bool inverse) -> int64_t {
     if (o.method == RSB_BLOCK) {
       BlockParams bp{o.lanczos_m, o.lanczos_keep, o.max_restarts, o.tol,
@@ -251,7 +269,7 @@ int64_t solve_level(const Level &L, CompDev &C, SolveDev &S, const rsb_opts &o, 
     }
     LanczosParams lp{o.lanczos_m, o.lanczos_keep, o.max_restarts, o.tol, graph ? 1 : 0,
                      o.seed,      prof,           v.nnz,          y2, warm,
-                     o.lanczos_s == 2 ? 1 : 0};
+                     pairs ? 1 : 0};
     return mixed ? lanczos_level<float>(v, C, SS, lp, work, y64, ctx)
                  : lanczos_level<double>(v, C, SS, lp, work, y64, ctx);
   };

@@ -5,14 +5,17 @@ and return the dense solver's lambda_2, like the oracle.  Partitions of
 small holed meshes into many parts (subgraphs of a few elements at the last
 levels) must keep the oracle's status and cut.
 
+The two-step form runs one step at a time on levels that solve a component
+of at most 4 m elements (its block's single Gram-Schmidt pass before the
+Cholesky QR missed the breakdown there), as the oracle does on such graphs.
+
 Open: the GPU's explicit restart (one Gram-Schmidt pass unless the
-projection's own estimate of the remainder says otherwise) and its two-step
-form (Cholesky QR of a block whose second pass is deferred) lose enough
+projection's own estimate of the remainder says otherwise) loses enough
 orthogonality near the exhaustion to miss the breakdown on some of these
 graphs, and the cycle then returns a Ritz value from inside the spectrum.
-Their cases are skipped below with that reason; one run of the explicit
-cases also ended in a host segmentation fault whose cause is not known, so
-they stay off the GPU until it is.  The one-step thick restart passes them.
+Its cases are skipped below with that reason; one run of them also ended in
+a host segmentation fault whose cause is not known, so they stay off the GPU
+until it is.  The one-step thick restart passes them.
 """
 import numpy as np
 import pytest
@@ -28,9 +31,7 @@ OPEN_EXPLICIT = pytest.mark.skip(
     reason="explicit restart misses the breakdown at an exhausted Krylov space on some tiny "
            "graphs; a run of these cases also ended in a host segmentation fault of unknown "
            "cause, so they stay off the GPU until that cause is found")
-OPEN_TWO_STEP = pytest.mark.skip(
-    reason="the two-step form misses the breakdown at an exhausted Krylov space on some tiny "
-           "graphs (open)")
+
 SETTINGS = {
     "fp64 explicit": dict(precision="fp64", lanczos_keep=0, lanczos_s=1, tol=1e-10),
     "fp64 thick": dict(precision="fp64", lanczos_keep=8, lanczos_s=1, tol=1e-10),
@@ -43,9 +44,9 @@ SETTINGS = {
 @pytest.mark.parametrize("setting", [
     pytest.param("fp64 explicit", marks=OPEN_EXPLICIT),
     "fp64 thick",
-    pytest.param("fp64 two-step", marks=OPEN_TWO_STEP),
+    "fp64 two-step",
     pytest.param("mixed explicit", marks=OPEN_EXPLICIT),
-    pytest.param("mixed two-step", marks=OPEN_TWO_STEP)])
+    "mixed two-step"])
 def test_exhausted_fiedler_matches_dense_eigh(orc, setting):
     kw = SETTINGS[setting]
     print(f"[exhaust] fiedler {setting}", flush=True)
@@ -61,7 +62,7 @@ def test_exhausted_fiedler_matches_dense_eigh(orc, setting):
 @pytest.mark.parametrize("setting", [
     pytest.param("fp64 explicit", marks=OPEN_EXPLICIT),
     "fp64 thick",
-    pytest.param("fp64 two-step", marks=OPEN_TWO_STEP)])
+    "fp64 two-step"])
 def test_exhausted_first_cycle_matches_oracle(orc, setting):
     # the first cycle's Ritz value (where it runs into the exhaustion the
     # breakdown ends it on both sides at the same step)
@@ -88,8 +89,7 @@ BENCH = dict(precision="mixed", lanczos_m=40, lanczos_keep=8, tol=1e-2, warm_sta
 
 
 CASES = [pytest.param(k, "default", marks=OPEN_EXPLICIT) for k in range(len(PARTITIONS))] + [
-    pytest.param(k, "bench", marks=OPEN_TWO_STEP) if k == 4 else (k, "bench")
-    for k in range(len(PARTITIONS))]
+    (k, "bench") for k in range(len(PARTITIONS))]
 
 
 @pytest.mark.parametrize("k,setting", CASES)
@@ -111,3 +111,18 @@ def test_many_parts_status_and_cut_like_oracle(orc, k, setting):
     cut = orc.metrics(mesh.ids, part, nparts)["weighted_cut"]
     ocut = orc.metrics(mesh.ids, opart, nparts)["weighted_cut"]
     assert abs(cut - ocut) <= 0.01 * ocut
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_two_step_runs_one_step_on_small_components(precision):
+    # at most 4 m elements: bit for bit the one-step solve; above, the
+    # two-step recurrence (equal to rounding)
+    kw = dict(precision=precision, lanczos_m=20, lanczos_keep=8, tol=1e-8, max_restarts=100)
+    small = mg.uniform_holes(mg.box_hex(5, 4, 4), 0.05, 3).ids
+    big = mg.uniform_holes(mg.box_hex(9, 7, 5), 0.05, 3).ids
+    _, l1, y1, _ = rsb.fiedler(small, lanczos_s=1, **kw)
+    _, l2, y2, _ = rsb.fiedler(small, lanczos_s=2, **kw)
+    assert l1 == l2 and np.array_equal(y1, y2)
+    _, l1, y1, _ = rsb.fiedler(big, lanczos_s=1, **kw)
+    _, l2, y2, _ = rsb.fiedler(big, lanczos_s=2, **kw)
+    assert abs(l1 - l2) <= 1e-7 * l1 and not np.array_equal(y1, y2)

@@ -92,3 +92,19 @@ def test_two_step_box_with_repeated_eigenvalues(orc):
     st, lam, _, _ = orc.fiedler(ids, lanczos_m=40, lanczos_keep=8, lanczos_s=2, tol=1e-10,
                                 max_restarts=5)
     assert st == 0 and abs(lam - ev[1]) <= 1e-12 * ev[-1]
+
+
+def test_two_step_only_above_four_m_elements(orc):
+    # at most 4 m elements: one step at a time (bit for bit the one-step
+    # result, whose breakdown the pins above check); above: the two-step
+    # recurrence (the same values to rounding, not bit for bit)
+    kw = dict(lanczos_m=20, lanczos_keep=8, tol=1e-10, max_restarts=50)
+    small = mg.uniform_holes(mg.box_hex(5, 4, 4), 0.05, 3).ids  # 76 elements <= 80
+    big = mg.uniform_holes(mg.box_hex(9, 7, 5), 0.05, 3).ids    # 299 elements
+    assert len(small) <= 80 < len(big)
+    _, l1, y1, _ = orc.fiedler(small, lanczos_s=1, **kw)
+    _, l2, y2, _ = orc.fiedler(small, lanczos_s=2, **kw)
+    assert l1 == l2 and np.array_equal(y1, y2)
+    _, l1, y1, _ = orc.fiedler(big, lanczos_s=1, **kw)
+    _, l2, y2, _ = orc.fiedler(big, lanczos_s=2, **kw)
+    assert abs(l1 - l2) <= 1e-9 * l1 and not np.array_equal(y1, y2)
