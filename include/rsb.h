@@ -219,10 +219,12 @@ typedef struct rsb_opts {
                                step at a time in exact arithmetic; the basis is
                                read twice per two steps instead of twice per
                                step); 1 (default) = one step at a time.  Ignored
-                               for explicit restart and gather_scatter.  Known
-                               limitation: the form 2 shares the explicit
-                               restart's weakness at an exhausted Krylov space
-                               (see lanczos_keep). */
+                               for explicit restart and gather_scatter.  A level
+                               that solves a component of at most
+                               4 * lanczos_m elements runs one step at a time
+                               (a cycle can exhaust the Krylov space of such a
+                               graph, and the block's single Gram-Schmidt pass
+                               before its Cholesky QR can miss that breakdown). */
   int32_t pack_matrix;      /* 1 (default) = each level also keeps a packed copy of
                                the sliced-ELL slices whose column offsets from the
                                row (column - row) fit in at most 4 windows of 1024:
